@@ -1,0 +1,113 @@
+"""Independent explicit-matrix constructions used to pin the oracle.
+
+Nothing here calls the oracle: matrices are assembled entry by entry from the
+SG-DIA arrays and from the written definitions of the interpolation weights,
+so a mistake in the oracle's index arithmetic shows up as a mismatch.
+"""
+import numpy as np
+
+
+def lin(shape, x, y, z):
+    return (x * shape[1] + y) * shape[2] + z
+
+
+def dense_from_sgdia(A, off, shape, bs=1):
+    """Explicit (N*bs) x (N*bs) matrix of an SG-DIA operator."""
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    M = np.zeros((N * bs, N * bs))
+    for s, (dx, dy, dz) in enumerate(off):
+        for x in range(nx):
+            for y in range(ny):
+                for z in range(nz):
+                    a, b, c = x + dx, y + dy, z + dz
+                    if not (0 <= a < nx and 0 <= b < ny and 0 <= c < nz):
+                        continue
+                    i = lin(shape, x, y, z)
+                    j = lin(shape, a, b, c)
+                    for r in range(bs):
+                        for cc in range(bs):
+                            M[i * bs + r, j * bs + cc] = A[s * bs * bs + r * bs + cc, i]
+    return M
+
+
+def interp_matrix(shape, cmask):
+    """Explicit trilinear vertex-centred interpolation P (Nf x Nc): coarse X
+    sits at fine 2X+1 on coarsened axes; weight prod_a w(f_a - (2X_a+1)) with
+    w(0)=1, w(+-1)=1/2; identity on axes that are not coarsened."""
+    cs = tuple(n // 2 if (cmask >> a) & 1 else n for a, n in enumerate(shape))
+    Nf = int(np.prod(shape))
+    Nc = int(np.prod(cs))
+    P = np.zeros((Nf, Nc))
+    for X in range(cs[0]):
+        for Y in range(cs[1]):
+            for Z in range(cs[2]):
+                J = (X, Y, Z)
+                base = [2 * J[a] + 1 if (cmask >> a) & 1 else J[a] for a in range(3)]
+                rng = [(-1, 0, 1) if (cmask >> a) & 1 else (0,) for a in range(3)]
+                for dx in rng[0]:
+                    for dy in rng[1]:
+                        for dz in rng[2]:
+                            f = (base[0] + dx, base[1] + dy, base[2] + dz)
+                            if not all(0 <= f[a] < shape[a] for a in range(3)):
+                                continue
+                            w = 1.0
+                            for d in (dx, dy, dz):
+                                if d != 0:
+                                    w *= 0.5
+                            P[lin(shape, *f), lin(cs, *J)] = w
+    return P, cs
+
+
+def sgdia_from_dense27(M, shape, bs=1, tol=0.0):
+    """Reads a dense coarse operator back into 27-point SG-DIA form and checks
+    that no entry lies outside the offsets {-1,0,1}^3."""
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    out = np.zeros((27 * bs * bs, N))
+    seen = np.zeros_like(M, dtype=bool)
+    for s in range(27):
+        dx, dy, dz = s // 9 - 1, (s // 3) % 3 - 1, s % 3 - 1
+        for x in range(nx):
+            for y in range(ny):
+                for z in range(nz):
+                    a, b, c = x + dx, y + dy, z + dz
+                    if not (0 <= a < nx and 0 <= b < ny and 0 <= c < nz):
+                        continue
+                    i = lin(shape, x, y, z)
+                    j = lin(shape, a, b, c)
+                    for r in range(bs):
+                        for cc in range(bs):
+                            out[s * bs * bs + r * bs + cc, i] = M[i * bs + r, j * bs + cc]
+                            seen[i * bs + r, j * bs + cc] = True
+    outside = np.abs(M[~seen]).max() if (~seen).any() else 0.0
+    assert outside <= tol, "coarse operator has entries outside the 27-point pattern"
+    return out
+
+
+def csr_gs(M, b, u, direction, zero_guess):
+    """Sequential point GS on an explicit matrix, rows in ascending
+    (direction=+1) or descending order.  Row update: t = b_i, then the
+    columns holding values from before the sweep, then the columns already
+    updated in this sweep, each group in ascending column order,
+    t = fma(-a_ij, u_j, t); u_i = t * (1/a_ii)."""
+    n = len(b)
+    u = u.copy()
+    rows = range(n) if direction > 0 else range(n - 1, -1, -1)
+    for i in rows:
+        t = b[i]
+        cols = np.nonzero(M[i])[0]
+        old = [j for j in cols if (j > i if direction > 0 else j < i)]
+        new = [j for j in cols if (j < i if direction > 0 else j > i)]
+        groups = [new] if zero_guess else [old, new]
+        for grp in groups:
+            for j in grp:
+                t = float(np.fma(-M[i, j], u[j], t)) if hasattr(np, "fma") else _fma(-M[i, j], u[j], t)
+        u[i] = t * (1.0 / M[i, i])
+    return u
+
+
+def _fma(a, b, c):
+    """Correctly rounded a*b+c via exact rational arithmetic."""
+    from fractions import Fraction
+    return float(Fraction(a) * Fraction(b) + Fraction(c))
