@@ -1,0 +1,155 @@
+/*
+ * structmg.h -- C ABI of libstructmg, an MI355X (gfx950) implementation of
+ * the structured algebraic multigrid preconditioner of "StructMG: A Fast and
+ * Scalable Structured Algebraic Multigrid" (arXiv 2506.21932).
+ *
+ * The user supplies only the finest-level matrix and right-hand sides
+ * (Sec. 3.2.2, input data format); the hierarchy is built once and applied
+ * many times (Sec. 2, total-time equation).  One application of the
+ * preconditioner is one V-cycle (Sec. 2): pre-smoothing, residual and
+ * restriction, coarse correction, prolongation, post-smoothing.
+ *
+ * Conventions shared by every entry point
+ *   Grid (nx, ny, nz); linear index i = (x*ny + y)*nz + z (z contiguous).
+ *   Stencil patterns 3d7 / 3d19 / 3d27 with offsets in {-1,0,1}^3 (Sec. 3.2.3
+ *   masks), numbered lexicographically with dx slowest (the Offset(2d9) /
+ *   Offset(2d5) numbering of Sec. 3.3 extended to 3D).
+ *   Matrix storage "SG-DIA" (Sec. 3.1 P1): coefficient of row i for offset s
+ *   at coeffs[s*N + i], N = nx*ny*nz.  Block systems (block = 3 unknowns per
+ *   node): entry (r, c) of the 3x3 block of offset s at coeffs[(s*9 + r*3 + c)*N + i],
+ *   vectors interleaved v[i*3 + c].  Couplings to neighbours outside the
+ *   grid are ignored (Dirichlet elimination; the paper zero-pads them).
+ *   Pointers named "device" are HIP device memory owned by the caller;
+ *   "stream" is a hipStream_t (NULL = default stream).
+ *
+ * Ownership: the library never allocates device memory.  Every hierarchy
+ *   array lives in the caller's workspace (size from smg_workspace_size),
+ *   which the handle borrows until smg_destroy.  coeffs may be freed once
+ *   smg_setup has returned.
+ *
+ * Errors: every call returns an smg_status; nothing aborts.  A failed call
+ *   leaves a message for smg_last_error.  Handles are not thread-safe, and
+ *   calls on one handle must not overlap in time (they share its workspace).
+ */
+#ifndef STRUCTMG_H
+#define STRUCTMG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct smg_handle_s* smg_handle;
+
+typedef enum {
+  SMG_OK = 0,
+  SMG_ENOTCONV = 1,    /* iteration limit reached; results still filled in */
+  SMG_EINVAL = -1,     /* invalid argument or configuration */
+  SMG_ENOMEM = -2,     /* workspace too small */
+  SMG_EDEVICE = -3,    /* HIP runtime error */
+  SMG_EBREAKDOWN = -4, /* zero pivot / zero diagonal, or p.Ap <= 0 in CG */
+  SMG_EDEADLOCK = -5   /* wavefront watchdog fired (a wait did not finish) */
+} smg_status;
+
+typedef enum { SMG_SMOOTH_GS = 0, SMG_SMOOTH_ILU0 = 1 } smg_smoother;
+typedef enum { SMG_COARSEN_FULL = 0, SMG_COARSEN_SEMI_XY = 1 } smg_coarsen;
+typedef enum { SMG_FP64 = 0, SMG_FP32 = 1, SMG_FP16_ROWSCALE = 2 } smg_prec;
+
+typedef struct {
+  int nx, ny, nz;      /* finest grid */
+  int block;           /* unknowns per node: 1, or 3 (3x3 blocks, 27-point only) */
+  int pattern;         /* finest-level pattern: 7, 19 or 27; coarse levels are 27-point */
+  int smoother;        /* smg_smoother: symmetric point GS (forward before, backward
+                          after the coarse correction) or ILU(0) on each level's mask */
+  int coarsen;         /* smg_coarsen: coarsen x,y,z (full) or only x,y (semi) */
+  int semi_levels;     /* with SMG_COARSEN_FULL: the first semi_levels levels coarsen x,y only */
+  int prec;            /* smg_prec of the V-cycle matrices and vectors; the outer
+                          Krylov method, its operator, dot products, true residuals
+                          and the coarsest solve stay FP64 */
+  int max_coarse;      /* bound on the unknowns of the dense coarsest level (0: 4096) */
+  int gmres_restart;   /* Krylov basis reserved in the workspace for GMRES (0: none) */
+} smg_config;
+
+typedef struct {
+  int iters;               /* preconditioner applications in the Krylov loop */
+  int levels;              /* multigrid levels */
+  double rel_resid_true;   /* ||b - A x||_2 / ||b||_2 recomputed in FP64 at the end */
+  double grid_complexity;  /* sum n_l / n_0          (Sec. 2, complexity equation) */
+  double op_complexity;    /* sum S_l n_l / (S_0 n_0): stored structured entries */
+  double t_setup_ms;
+  double t_solve_ms;
+} smg_result;
+
+/* Workspace bytes needed for cfg.  Returns SMG_EINVAL for an unsupported cfg. */
+smg_status smg_workspace_size(const smg_config* cfg, size_t* bytes);
+
+/* Builds the hierarchy: copies the finest matrix (device, FP64, SG-DIA as
+ * above), forms every coarse operator with the stencil Galerkin product
+ * A_c = R A P (Sec. 3.3; trilinear P, R = P^T), the smoother data (1/a_ii,
+ * 3x3 block inverses or ILU(0) factors), truncated copies for reduced
+ * V-cycle precision, and the inverse of the dense coarsest operator.
+ * Synchronises `stream` before returning.  SMG_EBREAKDOWN on a zero pivot. */
+smg_status smg_setup(const smg_config* cfg, const double* coeffs, void* workspace, size_t bytes, void* stream,
+                     smg_handle* out);
+
+/* z = M^-1 r: one V-cycle (device FP64 vectors of N*block entries; r and z
+ * must not overlap).  Asynchronous on `stream`. */
+smg_status smg_precondition(smg_handle h, const double* r, double* z, void* stream);
+
+/* Solves A x = b with preconditioned CG (krylov = 0) or right-preconditioned
+ * restarted GMRES(krylov) (krylov <= cfg.gmres_restart).  x holds the initial
+ * guess on entry.  Stops when ||r||_2 / ||b||_2 < rtol for the true residual
+ * (settings table: relative tolerance).  Synchronises `stream`.
+ * SMG_ENOTCONV when maxit is reached (res still filled in). */
+smg_status smg_solve(smg_handle h, const double* b, double* x, double rtol, int maxit, int krylov, smg_result* res,
+                     void* stream);
+
+smg_status smg_destroy(smg_handle h);
+
+/* Message of the last failed call on h (or of the last failed setup when h is
+ * NULL).  Never NULL. */
+const char* smg_last_error(smg_handle h);
+
+/* ---- hierarchy introspection ------------------------------------------ */
+/* info[0..5] = nx, ny, nz, pattern points, coarsening mask to the next level
+ * (bit 0 x, bit 1 y, bit 2 z; 0 on the coarsest level), block. */
+smg_status smg_level_info(smg_handle h, int level, int* info);
+int smg_num_levels(smg_handle h);
+
+/* Copies level data into device memory dst (stream-ordered):
+ * what = 0 matrix (FP64, S*block^2*N), 1 reciprocal diagonal (FP64, N) or
+ * 3x3 diagonal-block inverses (FP64, 9*N), 2 ILU lower factor (FP64, S*N),
+ * 3 ILU upper factor (FP64, S*N), 4 reciprocal of the ILU diagonal (FP64, N),
+ * 5 V-cycle matrix (FP32; FP16 storage is expanded to scale*float(h)),
+ * 6 V-cycle reciprocal diagonal / block inverses (FP32). */
+smg_status smg_level_export(smg_handle h, int level, int what, void* dst, void* stream);
+
+/* Influence chains of the generated triple product for a (fine pattern,
+ * coarsening mask) pair per interior coarse element (Table of chain counts). */
+int smg_rap_chain_count(int pattern, int cmask);
+
+/* ---- single V-cycle steps on one level --------------------------------
+ * These run the same kernels as the V-cycle.  Vectors are device arrays in
+ * the V-cycle precision (double for SMG_FP64, float otherwise) of the level's
+ * size (times block).  Output arrays must not overlap inputs. */
+smg_status smg_op_spmv(smg_handle h, int level, const void* x, void* y, void* stream);          /* y = A_l x */
+smg_status smg_op_spmv_fp64(smg_handle h, const double* x, double* y, void* stream);           /* finest, FP64 */
+/* u = S_pre(f): forward GS sweep from u = 0, or the ILU(0) solve. */
+smg_status smg_op_presmooth(smg_handle h, int level, const void* f, void* u, void* stream);
+/* u_out = S_post(f, u_in + P e_c): backward GS sweep, or the ILU(0)
+ * correction, after prolongation of the coarse correction e_c (level l+1
+ * vector, NULL for none). */
+smg_status smg_op_postsmooth(smg_handle h, int level, const void* f, const void* u_in, const void* ec, void* u_out,
+                             void* stream);
+/* rc = R (f - A_l u): fused residual and restriction to level l+1. */
+smg_status smg_op_resid_restrict(smg_handle h, int level, const void* f, const void* u, void* rc, void* stream);
+smg_status smg_op_restrict(smg_handle h, int level, const void* rf, void* rc, void* stream);
+smg_status smg_op_prolong_add(smg_handle h, int level, const void* ec, void* uf, void* stream);
+/* u = A_L^-1 f on the coarsest level (FP64 inverse). */
+smg_status smg_op_coarse_solve(smg_handle h, const void* f, void* u, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

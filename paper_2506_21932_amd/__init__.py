@@ -1,0 +1,201 @@
+"""Python binding of libstructmg (structured multigrid preconditioner, gfx950).
+
+Argument marshalling only: every numerical step runs in the HIP kernels of
+``libstructmg.so`` behind the C ABI of ``include/structmg.h``.  PyTorch tensors
+provide device memory and the current HIP stream.  There is no fallback: if
+the library is missing or cannot be loaded, importing the binding's entry
+points raises.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libstructmg.so")
+
+SMG_OK, SMG_ENOTCONV, SMG_EINVAL, SMG_ENOMEM, SMG_EDEVICE, SMG_EBREAKDOWN, SMG_EDEADLOCK = 0, 1, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "SMG_OK", 1: "SMG_ENOTCONV", -1: "SMG_EINVAL", -2: "SMG_ENOMEM", -3: "SMG_EDEVICE",
+                -4: "SMG_EBREAKDOWN", -5: "SMG_EDEADLOCK"}
+PREC = {"fp64": 0, "fp32": 1, "fp16": 2}
+SMOOTHER = {"gs": 0, "ilu0": 1}
+COARSEN = {"full": 0, "semi_xy": 1}
+
+
+class SmgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("block", C.c_int), ("pattern", C.c_int),
+                ("smoother", C.c_int), ("coarsen", C.c_int), ("semi_levels", C.c_int), ("prec", C.c_int),
+                ("max_coarse", C.c_int), ("gmres_restart", C.c_int)]
+
+
+class Result(C.Structure):
+    _fields_ = [("iters", C.c_int), ("levels", C.c_int), ("rel_resid_true", C.c_double),
+                ("grid_complexity", C.c_double), ("op_complexity", C.c_double), ("t_setup_ms", C.c_double),
+                ("t_solve_ms", C.c_double)]
+
+
+EXPORTS = ["smg_workspace_size", "smg_setup", "smg_precondition", "smg_solve", "smg_destroy", "smg_last_error",
+           "smg_level_info", "smg_num_levels", "smg_level_export", "smg_rap_chain_count", "smg_op_spmv",
+           "smg_op_spmv_fp64", "smg_op_presmooth", "smg_op_postsmooth", "smg_op_resid_restrict", "smg_op_restrict",
+           "smg_op_prolong_add", "smg_op_coarse_solve"]
+
+_lib = None
+
+
+def load():
+    """Loads libstructmg.so (built by __graft_entry__.build / build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2506_21932_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i, d = C.c_void_p, C.c_int, C.c_double
+    L.smg_workspace_size.argtypes = [C.POINTER(Config), C.POINTER(C.c_size_t)]
+    L.smg_setup.argtypes = [C.POINTER(Config), vp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.smg_precondition.argtypes = [vp, vp, vp, vp]
+    L.smg_solve.argtypes = [vp, vp, vp, d, i, i, C.POINTER(Result), vp]
+    L.smg_destroy.argtypes = [vp]
+    L.smg_last_error.argtypes = [vp]
+    L.smg_last_error.restype = C.c_char_p
+    L.smg_level_info.argtypes = [vp, i, C.POINTER(C.c_int)]
+    L.smg_num_levels.argtypes = [vp]
+    L.smg_num_levels.restype = i
+    L.smg_level_export.argtypes = [vp, i, i, vp, vp]
+    L.smg_rap_chain_count.argtypes = [i, i]
+    L.smg_rap_chain_count.restype = i
+    L.smg_op_spmv.argtypes = [vp, i, vp, vp, vp]
+    L.smg_op_spmv_fp64.argtypes = [vp, vp, vp, vp]
+    L.smg_op_presmooth.argtypes = [vp, i, vp, vp, vp]
+    L.smg_op_postsmooth.argtypes = [vp, i, vp, vp, vp, vp, vp]
+    L.smg_op_resid_restrict.argtypes = [vp, i, vp, vp, vp, vp]
+    L.smg_op_restrict.argtypes = [vp, i, vp, vp, vp]
+    L.smg_op_prolong_add.argtypes = [vp, i, vp, vp, vp]
+    L.smg_op_coarse_solve.argtypes = [vp, vp, vp, vp]
+    for name in EXPORTS:
+        if name not in ("smg_last_error", "smg_num_levels", "smg_rap_chain_count"):
+            getattr(L, name).restype = i
+    _lib = L
+    return L
+
+
+def rap_chain_count(pattern, cmask):
+    return load().smg_rap_chain_count(int(pattern), int(cmask))
+
+
+def make_config(shape, pattern=7, block=1, smoother="gs", coarsen="full", semi_levels=0, prec="fp64",
+                max_coarse=0, gmres_restart=0):
+    nx, ny, nz = (int(v) for v in shape)
+    return Config(nx, ny, nz, int(block), int(pattern), SMOOTHER[smoother], COARSEN[coarsen], int(semi_levels),
+                  PREC[prec], int(max_coarse), int(gmres_restart))
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class StructMG:
+    """Owns a libstructmg handle and its workspace (a torch uint8 tensor)."""
+
+    def __init__(self, coeffs, shape, pattern=7, block=1, smoother="gs", coarsen="full", semi_levels=0, prec="fp64",
+                 max_coarse=0, gmres_restart=0, device="cuda"):
+        import torch
+        L = load()
+        self.L = L
+        self.cfg = make_config(shape, pattern, block, smoother, coarsen, semi_levels, prec, max_coarse, gmres_restart)
+        self.block = int(block)
+        self.prec = prec
+        nbytes = C.c_size_t(0)
+        self._check(L.smg_workspace_size(C.byref(self.cfg), C.byref(nbytes)), None)
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
+        coeffs = coeffs.to(device=device, dtype=torch.float64).contiguous()
+        h = C.c_void_p()
+        self._check(L.smg_setup(C.byref(self.cfg), _ptr(coeffs), _ptr(self.workspace), nbytes, _stream(),
+                                C.byref(h)), None)
+        self.h = h
+        self.shape = tuple(int(v) for v in shape)
+
+    def _check(self, st, h):
+        if st not in (SMG_OK,):
+            msg = self.L.smg_last_error(h).decode()
+            raise SmgError(st, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.smg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def nlev(self):
+        return self.L.smg_num_levels(self.h)
+
+    def level_info(self, l):
+        info = (C.c_int * 6)()
+        self._check(self.L.smg_level_info(self.h, int(l), info), self.h)
+        return {"dims": (info[0], info[1], info[2]), "S": info[3], "cmask": info[4], "block": info[5]}
+
+    def export(self, l, what, out):
+        self._check(self.L.smg_level_export(self.h, int(l), int(what), _ptr(out), _stream()), self.h)
+        return out
+
+    def precondition(self, r, z):
+        self._check(self.L.smg_precondition(self.h, _ptr(r), _ptr(z), _stream()), self.h)
+        return z
+
+    def solve(self, b, x, rtol=1e-9, maxit=500, krylov=0):
+        res = Result()
+        st = self.L.smg_solve(self.h, _ptr(b), _ptr(x), float(rtol), int(maxit), int(krylov), C.byref(res), _stream())
+        if st not in (SMG_OK, SMG_ENOTCONV):
+            self._check(st, self.h)
+        return {"status": st, "iters": res.iters, "levels": res.levels, "rel_resid_true": res.rel_resid_true,
+                "grid_complexity": res.grid_complexity, "op_complexity": res.op_complexity,
+                "t_setup_ms": res.t_setup_ms, "t_solve_ms": res.t_solve_ms}
+
+    # single V-cycle steps (same kernels as the cycle)
+    def op_spmv(self, l, x, y):
+        self._check(self.L.smg_op_spmv(self.h, int(l), _ptr(x), _ptr(y), _stream()), self.h)
+        return y
+
+    def op_spmv_fp64(self, x, y):
+        self._check(self.L.smg_op_spmv_fp64(self.h, _ptr(x), _ptr(y), _stream()), self.h)
+        return y
+
+    def op_presmooth(self, l, f, u):
+        self._check(self.L.smg_op_presmooth(self.h, int(l), _ptr(f), _ptr(u), _stream()), self.h)
+        return u
+
+    def op_postsmooth(self, l, f, u_in, ec, u_out):
+        self._check(self.L.smg_op_postsmooth(self.h, int(l), _ptr(f), _ptr(u_in), _ptr(ec), _ptr(u_out),
+                                             _stream()), self.h)
+        return u_out
+
+    def op_resid_restrict(self, l, f, u, rc):
+        self._check(self.L.smg_op_resid_restrict(self.h, int(l), _ptr(f), _ptr(u), _ptr(rc), _stream()), self.h)
+        return rc
+
+    def op_restrict(self, l, rf, rc):
+        self._check(self.L.smg_op_restrict(self.h, int(l), _ptr(rf), _ptr(rc), _stream()), self.h)
+        return rc
+
+    def op_prolong_add(self, l, ec, uf):
+        self._check(self.L.smg_op_prolong_add(self.h, int(l), _ptr(ec), _ptr(uf), _stream()), self.h)
+        return uf
+
+    def op_coarse_solve(self, f, u):
+        self._check(self.L.smg_op_coarse_solve(self.h, _ptr(f), _ptr(u), _stream()), self.h)
+        return u

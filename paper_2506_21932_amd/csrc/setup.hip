@@ -1,0 +1,265 @@
+// Setup-phase kernels: level-0 copy with Dirichlet masking (Sec. 3.1 P1
+// zero padding), reciprocal diagonal, 3x3 diagonal-block inverses, ILU(0)
+// factorisation on the level's own mask (Sec. 3.2.3, Sec. 3.4 ILU), and
+// truncation of FP64 level data to FP32 or FP16 with a per-row FP32 scale.
+#include "smg_kernels.h"
+
+namespace smg {
+
+__device__ inline void unflat3(unsigned i, int ny, int nz, int& x, int& y, int& z) {
+  unsigned nyz = (unsigned)ny * (unsigned)nz;
+  x = (int)(i / nyz);
+  unsigned r = i - (unsigned)x * nyz;
+  y = (int)(r / (unsigned)nz);
+  z = (int)(r - (unsigned)y * (unsigned)nz);
+}
+
+// dst[s*be+e][i] = src[...] for in-grid couplings, 0 otherwise.
+template <int PAT>
+__global__ __launch_bounds__(256) void k_copy_masked(Grid g, int be, const double* __restrict__ src,
+                                                     double* __restrict__ dst) {
+  const unsigned N = (unsigned)g.N();
+  const unsigned i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= N) return;
+  int X, Y, Z;
+  unflat3(i, g.ny, g.nz, X, Y, Z);
+#pragma unroll
+  for (int s = 0; s < PAT; ++s) {
+    const bool in = in_grid(g, X + pat_off(PAT, s, 0), Y + pat_off(PAT, s, 1), Z + pat_off(PAT, s, 2));
+    for (int e = 0; e < be; ++e) {
+      const long k = ((long)s * be + e) * N + i;
+      dst[k] = in ? src[k] : 0.0;
+    }
+  }
+}
+
+hipError_t launch_copy_masked(int pat, const Grid& g, int be, const double* src, double* dst, hipStream_t st) {
+  const unsigned N = (unsigned)g.N();
+  dim3 grid((N + 255) / 256), blk(256);
+  if (pat == 7)
+    hipLaunchKernelGGL((k_copy_masked<7>), grid, blk, 0, st, g, be, src, dst);
+  else if (pat == 19)
+    hipLaunchKernelGGL((k_copy_masked<19>), grid, blk, 0, st, g, be, src, dst);
+  else if (pat == 27)
+    hipLaunchKernelGGL((k_copy_masked<27>), grid, blk, 0, st, g, be, src, dst);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// rd_i = 1 / a_ii (IEEE division); a zero diagonal raises err bit 1.
+__global__ __launch_bounds__(256) void k_recip_diag(long N, const double* __restrict__ ac, double* __restrict__ rd,
+                                                    unsigned* err) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  const double a = ac[i];
+  if (a == 0.0) atomicOr(err, 2u);
+  rd[i] = 1.0 / a;
+}
+
+hipError_t launch_recip_diag(int pat, const Grid& g, const double* A, double* rd, unsigned* err, hipStream_t st) {
+  const long N = g.N();
+  hipLaunchKernelGGL(k_recip_diag, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, A + (long)(pat / 2) * N,
+                     rd, err);
+  return hipGetLastError();
+}
+
+// Inverse of the centre 3x3 block of each node: Gauss-Jordan with partial
+// pivoting on [D | I]; pivot row divided by the pivot, other rows updated
+// with fma(-f, pivot_row, row).
+__global__ __launch_bounds__(256) void k_block_dinv(long N, const double* __restrict__ Ac, double* __restrict__ Dinv,
+                                                    unsigned* err) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  double m[3][6];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      m[r][k] = Ac[(long)(r * 3 + k) * N + i];
+      m[r][3 + k] = r == k ? 1.0 : 0.0;
+    }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int p = k;
+#pragma unroll
+    for (int r = k + 1; r < 3; ++r)
+      if (fabs(m[r][k]) > fabs(m[p][k])) p = r;
+    if (m[p][k] == 0.0) {
+      atomicOr(err, 2u);
+      return;
+    }
+    if (p != k) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        const double t = m[k][j];
+        m[k][j] = m[p][j];
+        m[p][j] = t;
+      }
+    }
+    const double piv = m[k][k];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) m[k][j] = m[k][j] / piv;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      if (r == k) continue;
+      const double f = m[r][k];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) m[r][j] = fma(-f, m[k][j], m[r][j]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Dinv[(long)(r * 3 + k) * N + i] = m[r][3 + k];
+}
+
+hipError_t launch_block_dinv(const Grid& g, const double* A, double* Dinv, unsigned* err, hipStream_t st) {
+  const long N = g.N();
+  hipLaunchKernelGGL(k_block_dinv, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, A + 13L * 9 * N, Dinv,
+                     err);
+  return hipGetLastError();
+}
+
+// ILU(0) rows on one hyperplane wx*x + wy*y + z = tau (all their lower
+// neighbours lie on earlier hyperplanes).  Doolittle IKJ on the mask:
+// lower slots in canonical (= ascending column) order, w[s] /= U_c[k], then
+// w[slot(off_s+off_t)] = fma(-w[s], U_t[k], w[...]) for the upper slots t of
+// row k in canonical order, dropping fill outside the mask.
+template <int PAT>
+__global__ __launch_bounds__(256) void k_ilu0_plane(Grid g, int tau, const double* __restrict__ A,
+                                                    double* __restrict__ L, double* __restrict__ U,
+                                                    double* __restrict__ rU, unsigned* err) {
+  constexpr int C = PAT / 2, WX = hp_wx(PAT), WY = hp_wy(PAT);
+  const long N = g.N();
+  const unsigned col = blockIdx.x * 256u + threadIdx.x;
+  if (col >= (unsigned)(g.nx * g.ny)) return;
+  const int X = (int)(col / (unsigned)g.ny), Y = (int)(col % (unsigned)g.ny);
+  const int Z = tau - WX * X - WY * Y;
+  if (Z < 0 || Z >= g.nz) return;
+  const long i = ((long)X * g.ny + Y) * g.nz + Z;
+  const long nyz = (long)g.ny * g.nz;
+  double w[PAT];
+#pragma unroll
+  for (int s = 0; s < PAT; ++s) {
+    const bool in = in_grid(g, X + pat_off(PAT, s, 0), Y + pat_off(PAT, s, 1), Z + pat_off(PAT, s, 2));
+    w[s] = in ? A[(long)s * N + i] : 0.0;
+  }
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    const int ax = X + pat_off(PAT, s, 0), ay = Y + pat_off(PAT, s, 1), az = Z + pat_off(PAT, s, 2);
+    if (!in_grid(g, ax, ay, az)) continue;
+    const long k = i + pat_off(PAT, s, 0) * nyz + pat_off(PAT, s, 1) * g.nz + pat_off(PAT, s, 2);
+    w[s] = w[s] / U[(long)C * N + k];
+#pragma unroll
+    for (int t = C + 1; t < PAT; ++t) {
+      const int dx = pat_off(PAT, s, 0) + pat_off(PAT, t, 0), dy = pat_off(PAT, s, 1) + pat_off(PAT, t, 1),
+                dz = pat_off(PAT, s, 2) + pat_off(PAT, t, 2);
+      if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) continue;
+      const int sl = pat_slot(PAT, dx, dy, dz);
+      if (sl < 0) continue;
+      if (!in_grid(g, ax + pat_off(PAT, t, 0), ay + pat_off(PAT, t, 1), az + pat_off(PAT, t, 2))) continue;
+      w[sl] = fma(-w[s], U[(long)t * N + k], w[sl]);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < PAT; ++s) {
+    L[(long)s * N + i] = s < C ? w[s] : 0.0;
+    U[(long)s * N + i] = s >= C ? w[s] : 0.0;
+  }
+  if (w[C] == 0.0) atomicOr(err, 2u);
+  rU[i] = 1.0 / w[C];
+}
+
+hipError_t launch_ilu0_factor(int pat, const Grid& g, const double* A, double* L, double* U, double* rU,
+                              unsigned* err, hipStream_t st) {
+  const int D = hp_wx(pat) * (g.nx - 1) + hp_wy(pat) * (g.ny - 1) + g.nz;
+  const dim3 grid((unsigned)((g.nx * g.ny + 255) / 256)), blk(256);
+  for (int tau = 0; tau < D; ++tau) {
+    if (pat == 7)
+      hipLaunchKernelGGL((k_ilu0_plane<7>), grid, blk, 0, st, g, tau, A, L, U, rU, err);
+    else if (pat == 19)
+      hipLaunchKernelGGL((k_ilu0_plane<19>), grid, blk, 0, st, g, tau, A, L, U, rU, err);
+    else if (pat == 27)
+      hipLaunchKernelGGL((k_ilu0_plane<27>), grid, blk, 0, st, g, tau, A, L, U, rU, err);
+    else
+      return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+__global__ __launch_bounds__(256) void k_to_f32(const double* __restrict__ s, float* __restrict__ d, long n) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) d[i] = (float)s[i];
+}
+
+hipError_t launch_to_f32(const double* src, float* dst, long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+// Per scalar row (node i, block row r): s = float(max |a|), h = half(float(a / s)).
+__global__ __launch_bounds__(256) void k_to_f16(const double* __restrict__ A, long N, int S, int bs,
+                                                __half* __restrict__ h, float* __restrict__ sc) {
+  const long k = (long)blockIdx.x * 256 + threadIdx.x;
+  if (k >= N * bs) return;
+  const long i = k % N;
+  const int r = (int)(k / N);
+  const int be = bs * bs;
+  double mx = 0.0;
+  for (int s = 0; s < S; ++s)
+    for (int c = 0; c < bs; ++c) {
+      const double v = fabs(A[((long)s * be + r * bs + c) * N + i]);
+      if (v > mx) mx = v;
+    }
+  const float s32 = (float)mx;
+  sc[(long)r * N + i] = s32;
+  for (int s = 0; s < S; ++s)
+    for (int c = 0; c < bs; ++c) {
+      const long q = ((long)s * be + r * bs + c) * N + i;
+      h[q] = s32 == 0.0f ? __float2half_rn(0.0f) : __float2half_rn((float)(A[q] / (double)s32));
+    }
+}
+
+hipError_t launch_to_f16_rowscale(const double* A, long N, int S, int bs, __half* h, float* sc, hipStream_t st) {
+  const long n = N * bs;
+  hipLaunchKernelGGL(k_to_f16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, N, S, bs, h, sc);
+  return hipGetLastError();
+}
+
+// out = scale * float(h), the value the kernels use for an FP16 coefficient.
+__global__ __launch_bounds__(256) void k_dequant(const __half* __restrict__ h, const float* __restrict__ sc, long N,
+                                                 int S, int bs, float* __restrict__ out) {
+  const long k = (long)blockIdx.x * 256 + threadIdx.x;
+  const int be = bs * bs;
+  if (k >= (long)S * be * N) return;
+  const long i = k % N;
+  const int e = (int)((k / N) % be);
+  out[k] = sc[(long)(e / bs) * N + i] * __half2float(h[k]);
+}
+
+hipError_t launch_dequant_f16(const __half* h, const float* sc, long N, int S, int bs, float* out, hipStream_t st) {
+  const long n = (long)S * bs * bs * N;
+  hipLaunchKernelGGL(k_dequant, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, h, sc, N, S, bs, out);
+  return hipGetLastError();
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_fill(V* p, long n, V v) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <class V>
+hipError_t launch_fill_bits(V* p, long n, V v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_fill<V>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+template hipError_t launch_fill_bits<double>(double*, long, double, hipStream_t);
+template hipError_t launch_fill_bits<float>(float*, long, float, hipStream_t);
+template hipError_t launch_fill_bits<unsigned>(unsigned*, long, unsigned, hipStream_t);
+
+}  // namespace smg

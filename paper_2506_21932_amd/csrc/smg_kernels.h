@@ -1,0 +1,103 @@
+// Host-side launchers of the device kernels (internal to libstructmg).
+#pragma once
+#include "smg_common.h"
+
+namespace smg {
+
+// ---- wavefront triangular sweep --------------------------------------
+template <class V>
+struct WfArgs {
+  Grid g;
+  int sh, ntx, nty;          // tiling (see wf_tiling)
+  const V* h;                // right-hand side of the triangular system
+  const V* d;                // diagonal scaling (unused for a unit diagonal)
+  V* x;                      // output; positions read by other tiles hold the sentinel
+  V* next;                   // output buffer of the next sweep on this level (sentinel prefill), or null
+  int next_dir, next_sh;     // direction / shear of that next sweep
+  const V* addv;             // optional: addout = addv + x
+  V* addout;
+  unsigned* ctr;             // [0] ticket counter, [1] exit counter; zero between launches
+  unsigned* err;             // watchdog flag (bit 0)
+};
+
+void wf_tiling(const Grid& g, int* sh, int* ntx, int* nty);
+
+template <class M>
+hipError_t launch_wavefront(int pat, int dir, bool unitd, bool add, const WfArgs<typename M::V>& a, const M& m,
+                            hipStream_t st);
+
+// ---- parallel stencil kernels (stencil.hip) ----------------------------
+// y = A x   (res = false)   or   y = b - A x   (res = true)
+template <class M>
+hipError_t launch_spmv(int pat, const Grid& g, const M& m, const typename M::V* x, const typename M::V* b,
+                       typename M::V* y, bool res, hipStream_t st);
+
+// rc = R (f - A u), R = P^T trilinear, coarsening mask cmask
+template <class M>
+hipError_t launch_resid_restrict(int pat, const Grid& g, int cmask, const M& m, const typename M::V* f,
+                                 const typename M::V* u, typename M::V* rc, hipStream_t st);
+
+// With u_old = u + P ec (ec may be null: u_old = u):
+//   full = false: h = f - sum_{lower s} a_s u_old[nbr]    (input of the backward GS sweep)
+//   full = true : h = f - A u_old, and uold_out = u_old   (input of the ILU correction)
+template <class M>
+hipError_t launch_prolong_post(int pat, const Grid& g, int cmask, const M& m, const typename M::V* f,
+                               const typename M::V* u, const typename M::V* ec, typename M::V* h,
+                               typename M::V* uold_out, bool full, hipStream_t st);
+
+// plain restriction / prolongation (kernel-level entry points)
+template <class V>
+hipError_t launch_restrict(const Grid& g, int cmask, int bs, const V* rf, V* rc, hipStream_t st);
+template <class V>
+hipError_t launch_prolong_add(const Grid& g, int cmask, int bs, const V* ec, V* uf, hipStream_t st);
+
+// ---- block (3x3) variants (block.hip) --------------------------------
+template <class M>
+hipError_t launch_bspmv(const Grid& g, const M& m, const typename M::V* x, const typename M::V* b,
+                        typename M::V* y, bool res, hipStream_t st);
+template <class M>
+hipError_t launch_bresid_restrict(const Grid& g, int cmask, const M& m, const typename M::V* f,
+                                  const typename M::V* u, typename M::V* rc, hipStream_t st);
+template <class M>
+hipError_t launch_bprolong_post(const Grid& g, int cmask, const M& m, const typename M::V* f,
+                                const typename M::V* u, const typename M::V* ec, typename M::V* h,
+                                hipStream_t st);
+template <class M, class DM>
+hipError_t launch_bwavefront(int dir, const WfArgs<typename M::V>& a, const M& m, const DM& dinv, hipStream_t st);
+
+// ---- setup (setup.hip) ------------------------------------------------
+hipError_t launch_copy_masked(int pat, const Grid& g, int be, const double* src, double* dst, hipStream_t st);
+hipError_t launch_recip_diag(int pat, const Grid& g, const double* A, double* rd, unsigned* err, hipStream_t st);
+hipError_t launch_block_dinv(const Grid& g, const double* A, double* Dinv, unsigned* err, hipStream_t st);
+hipError_t launch_ilu0_factor(int pat, const Grid& g, const double* A, double* L, double* U, double* rU,
+                              unsigned* err, hipStream_t st);
+hipError_t launch_to_f32(const double* src, float* dst, long n, hipStream_t st);
+hipError_t launch_to_f16_rowscale(const double* A, long N, int S, int bs, __half* h, float* sc, hipStream_t st);
+hipError_t launch_dequant_f16(const __half* h, const float* sc, long N, int S, int bs, float* out, hipStream_t st);
+template <class V>
+hipError_t launch_fill_bits(V* p, long n, V v, hipStream_t st);
+
+// ---- RAP (rap.hip, generated chains) --------------------------------
+// Ac[(n*be + e)*Nc + I] for the 27 coarse offsets; A entry stride sA elements.
+hipError_t launch_rap(int pat, int cmask, const Grid& gf, const double* A, long sA, double* Ac, long sAc,
+                      hipStream_t st);
+int rap_chain_count(int pat, int cmask);
+
+// ---- coarsest level (coarse.hip) ------------------------------------
+hipError_t launch_dense_assemble(const Grid& g, int bs, const double* A, double* M, int ld, hipStream_t st);
+hipError_t launch_aug_init(int n, double* aug, hipStream_t st);
+hipError_t coarse_invert(int n, double* aug, int* info_dev, hipStream_t st);  // aug: n x 2n, inverse in right half
+template <class V>
+hipError_t launch_coarse_gemv(int n, const double* Ainv, int ld, const V* f, V* u, hipStream_t st);
+
+// ---- vectors and reductions (vec.hip) --------------------------------
+hipError_t launch_axpy(long n, double a, const double* x, double* y, hipStream_t st);   // y = fma(a, x, y)
+hipError_t launch_xpby(long n, const double* x, double b, double* y, hipStream_t st);   // y = fma(b, y, x)
+hipError_t launch_scale(long n, double s, const double* x, double* y, hipStream_t st);  // y = s * x
+hipError_t launch_dot(long n, const double* x, const double* y, double* partial, double* out, hipStream_t st);
+hipError_t launch_cast_d2f(long n, const double* x, float* y, hipStream_t st);
+hipError_t launch_cast_f2d(long n, const float* x, double* y, hipStream_t st);
+hipError_t launch_add(long n, const double* a, const double* b, double* y, hipStream_t st);
+constexpr int DOT_BLOCKS = 1024;
+
+}  // namespace smg

@@ -1,0 +1,330 @@
+// Parallel stencil kernels on SG-DIA storage: SpMV / residual (Sec. 3.1 P1),
+// the fused residual + restriction of the downward V-cycle leg, and the fused
+// prolongation + correction feeding the post-smoother of the upward leg
+// (Sec. 2, V-cycle).  Interpolation P is vertex-centred trilinear with the
+// grid map of Sec. 3.3 (coarse X <-> fine 2X+1, stride 2, base offset 1);
+// restriction is R = P^T.
+//
+// Every output element is produced with the same operations in the same
+// order as the definition it implements: accumulations run over stencil
+// offsets (or restriction offsets, or interpolation parents) in canonical
+// lexicographic order with explicit fma, and out-of-grid terms are skipped.
+#include "smg_kernels.h"
+
+namespace smg {
+
+__device__ inline void unflat(unsigned i, int ny, int nz, int& x, int& y, int& z) {
+  unsigned nyz = (unsigned)ny * (unsigned)nz;
+  x = (int)(i / nyz);
+  unsigned r = i - (unsigned)x * nyz;
+  y = (int)(r / (unsigned)nz);
+  z = (int)(r - (unsigned)y * (unsigned)nz);
+}
+
+// ---------------------------------------------------------------- SpMV
+template <int PAT, class M, bool RES>
+__global__ __launch_bounds__(256) void k_spmv(Grid g, M m, const typename M::V* __restrict__ x,
+                                              const typename M::V* __restrict__ b, typename M::V* __restrict__ y) {
+  using V = typename M::V;
+  const unsigned N = (unsigned)g.N();
+  const unsigned i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= N) return;
+  int X, Y, Z;
+  unflat(i, g.ny, g.nz, X, Y, Z);
+  const long nyz = (long)g.ny * g.nz;
+  V acc = V(0);
+#pragma unroll
+  for (int s = 0; s < PAT; ++s) {
+    const int dx = pat_off(PAT, s, 0), dy = pat_off(PAT, s, 1), dz = pat_off(PAT, s, 2);
+    if (in_grid(g, X + dx, Y + dy, Z + dz)) acc = fma(m(s, i), x[(long)i + dx * nyz + dy * g.nz + dz], acc);
+  }
+  y[i] = RES ? b[i] - acc : acc;
+}
+
+template <class M>
+hipError_t launch_spmv(int pat, const Grid& g, const M& m, const typename M::V* x, const typename M::V* b,
+                       typename M::V* y, bool res, hipStream_t st) {
+  const unsigned N = (unsigned)g.N();
+  dim3 grid((N + 255) / 256), blk(256);
+#define SMG_SPMV(P)                                                                    \
+  if (pat == P) {                                                                      \
+    if (res)                                                                           \
+      hipLaunchKernelGGL((k_spmv<P, M, true>), grid, blk, 0, st, g, m, x, b, y);      \
+    else                                                                               \
+      hipLaunchKernelGGL((k_spmv<P, M, false>), grid, blk, 0, st, g, m, x, b, y);     \
+    return hipGetLastError();                                                          \
+  }
+  SMG_SPMV(7)
+  SMG_SPMV(19)
+  SMG_SPMV(27)
+#undef SMG_SPMV
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------ residual + restriction
+// One workgroup per coarse block of RB_X x RB_Y x RB_Z coarse points.
+// Phase 1 computes the fine residuals of the block's footprint into LDS;
+// phase 2 restricts them.  A residual shared by two blocks is recomputed
+// (identically) by both.
+constexpr int RB_X = 4, RB_Y = 4, RB_Z = 16;
+
+__host__ __device__ inline int rr_ext(int cm, int cb) { return cm ? 2 * cb + 1 : cb; }
+
+template <int PAT, class M>
+__global__ __launch_bounds__(256) void k_resid_restrict(Grid gf, int cmask, M m, const typename M::V* __restrict__ f,
+                                                        const typename M::V* __restrict__ u,
+                                                        typename M::V* __restrict__ rc) {
+  using V = typename M::V;
+  constexpr int MAXE = (2 * RB_X + 1) * (2 * RB_Y + 1) * (2 * RB_Z + 1);
+  __shared__ V rs[MAXE];
+  const int cmx = cmask & 1, cmy = (cmask >> 1) & 1, cmz = (cmask >> 2) & 1;
+  const Grid gc{cmx ? gf.nx / 2 : gf.nx, cmy ? gf.ny / 2 : gf.ny, cmz ? gf.nz / 2 : gf.nz};
+  const int nbz = (gc.nz + RB_Z - 1) / RB_Z, nby = (gc.ny + RB_Y - 1) / RB_Y;
+  const int bid = blockIdx.x;
+  const int bz = bid % nbz, by = (bid / nbz) % nby, bx = bid / (nbz * nby);
+  const int C0x = bx * RB_X, C0y = by * RB_Y, C0z = bz * RB_Z;
+  const int lox = cmx ? 2 * C0x : C0x, loy = cmy ? 2 * C0y : C0y, loz = cmz ? 2 * C0z : C0z;
+  const int ex = rr_ext(cmx, RB_X), ey = rr_ext(cmy, RB_Y), ez = rr_ext(cmz, RB_Z);
+  const long nyz = (long)gf.ny * gf.nz;
+  const int ne = ex * ey * ez;
+  for (int k = threadIdx.x; k < ne; k += 256) {
+    const int fz = loz + k % ez, fy = loy + (k / ez) % ey, fx = lox + k / (ez * ey);
+    if (fx >= gf.nx || fy >= gf.ny || fz >= gf.nz) continue;
+    const long i = ((long)fx * gf.ny + fy) * gf.nz + fz;
+    V acc = V(0);
+#pragma unroll
+    for (int s = 0; s < PAT; ++s) {
+      const int dx = pat_off(PAT, s, 0), dy = pat_off(PAT, s, 1), dz = pat_off(PAT, s, 2);
+      if (in_grid(gf, fx + dx, fy + dy, fz + dz)) acc = fma(m(s, i), u[i + dx * nyz + dy * gf.nz + dz], acc);
+    }
+    rs[k] = f[i] - acc;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < RB_X * RB_Y * RB_Z; k += 256) {
+    const int Z = C0z + k % RB_Z, Yc = C0y + (k / RB_Z) % RB_Y, Xc = C0x + k / (RB_Z * RB_Y);
+    if (Xc >= gc.nx || Yc >= gc.ny || Z >= gc.nz) continue;
+    const int fx0 = cmx ? 2 * Xc + 1 : Xc, fy0 = cmy ? 2 * Yc + 1 : Yc, fz0 = cmz ? 2 * Z + 1 : Z;
+    V acc = V(0);
+#pragma unroll
+    for (int r = 0; r < 27; ++r) {
+      const int dx = r / 9 - 1, dy = (r / 3) % 3 - 1, dz = r % 3 - 1;
+      if ((!cmx && dx) || (!cmy && dy) || (!cmz && dz)) continue;
+      const int ux = fx0 + dx, uy = fy0 + dy, uz = fz0 + dz;
+      if (!in_grid(gf, ux, uy, uz)) continue;
+      const V w = V((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
+      acc = fma(w, rs[((ux - lox) * ey + (uy - loy)) * ez + (uz - loz)], acc);
+    }
+    rc[((long)Xc * gc.ny + Yc) * gc.nz + Z] = acc;
+  }
+}
+
+template <class M>
+hipError_t launch_resid_restrict(int pat, const Grid& g, int cmask, const M& m, const typename M::V* f,
+                                 const typename M::V* u, typename M::V* rc, hipStream_t st) {
+  const int cx = (cmask & 1) ? g.nx / 2 : g.nx, cy = (cmask & 2) ? g.ny / 2 : g.ny, cz = (cmask & 4) ? g.nz / 2 : g.nz;
+  const unsigned nb = (unsigned)(((cx + RB_X - 1) / RB_X) * ((cy + RB_Y - 1) / RB_Y) * ((cz + RB_Z - 1) / RB_Z));
+#define SMG_RR(P)                                                                                      \
+  if (pat == P) {                                                                                      \
+    hipLaunchKernelGGL((k_resid_restrict<P, M>), dim3(nb), dim3(256), 0, st, g, cmask, m, f, u, rc);  \
+    return hipGetLastError();                                                                          \
+  }
+  SMG_RR(7)
+  SMG_RR(19)
+  SMG_RR(27)
+#undef SMG_RR
+  return hipErrorInvalidValue;
+}
+
+// --------------------------------------- interpolation of one fine point
+// pe = sum over parents (lexicographic) of w * e_J via fma, from zero.
+template <class V>
+__device__ inline V interp_point(const V* __restrict__ ec, const Grid& gc, int cmx, int cmy, int cmz, int fx, int fy,
+                                 int fz, int bs, int comp) {
+  int par[3][2], np[3];
+  V wt[3][2];
+  const int f[3] = {fx, fy, fz}, cm[3] = {cmx, cmy, cmz}, nc[3] = {gc.nx, gc.ny, gc.nz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    np[a] = 0;
+    if (!cm[a]) {
+      par[a][0] = f[a];
+      wt[a][0] = V(1);
+      np[a] = 1;
+    } else if (f[a] & 1) {
+      const int J = (f[a] - 1) / 2;
+      if (J < nc[a]) {
+        par[a][0] = J;
+        wt[a][0] = V(1);
+        np[a] = 1;
+      }
+    } else {
+      const int J0 = f[a] / 2 - 1, J1 = f[a] / 2;
+      if (J0 >= 0 && J0 < nc[a]) {
+        par[a][np[a]] = J0;
+        wt[a][np[a]] = V(0.5);
+        np[a]++;
+      }
+      if (J1 < nc[a]) {
+        par[a][np[a]] = J1;
+        wt[a][np[a]] = V(0.5);
+        np[a]++;
+      }
+    }
+  }
+  V pe = V(0);
+  for (int p = 0; p < np[0]; ++p)
+    for (int q = 0; q < np[1]; ++q)
+      for (int r = 0; r < np[2]; ++r) {
+        const V w = wt[0][p] * wt[1][q] * wt[2][r];
+        const long J = ((long)par[0][p] * gc.ny + par[1][q]) * gc.nz + par[2][r];
+        pe = fma(w, ec[J * bs + comp], pe);
+      }
+  return pe;
+}
+
+// --------------------------------- prolongation + post-smoother input
+constexpr int PP_X = 8, PP_Y = 8, PP_Z = 32;
+
+template <int PAT, class M, bool FULL>
+__global__ __launch_bounds__(256) void k_prolong_post(Grid gf, int cmask, M m, const typename M::V* __restrict__ f,
+                                                      const typename M::V* __restrict__ u,
+                                                      const typename M::V* __restrict__ ec,
+                                                      typename M::V* __restrict__ h, typename M::V* __restrict__ uo) {
+  using V = typename M::V;
+  constexpr int HX = PP_X + 2, HY = PP_Y + 2, HZ = PP_Z + 2;
+  __shared__ V us[HX * HY * HZ];
+  const int cmx = cmask & 1, cmy = (cmask >> 1) & 1, cmz = (cmask >> 2) & 1;
+  const Grid gc{cmx ? gf.nx / 2 : gf.nx, cmy ? gf.ny / 2 : gf.ny, cmz ? gf.nz / 2 : gf.nz};
+  const int nbz = (gf.nz + PP_Z - 1) / PP_Z, nby = (gf.ny + PP_Y - 1) / PP_Y;
+  const int bid = blockIdx.x;
+  const int bz = bid % nbz, by = (bid / nbz) % nby, bx = bid / (nbz * nby);
+  const int x0 = bx * PP_X - 1, y0 = by * PP_Y - 1, z0 = bz * PP_Z - 1;
+  for (int k = threadIdx.x; k < HX * HY * HZ; k += 256) {
+    const int fz = z0 + k % HZ, fy = y0 + (k / HZ) % HY, fx = x0 + k / (HZ * HY);
+    if (!in_grid(gf, fx, fy, fz)) continue;
+    const long i = ((long)fx * gf.ny + fy) * gf.nz + fz;
+    V v = u[i];
+    if (ec != nullptr) v = v + interp_point(ec, gc, cmx, cmy, cmz, fx, fy, fz, 1, 0);
+    us[k] = v;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < PP_X * PP_Y * PP_Z; k += 256) {
+    const int lz = k % PP_Z, ly = (k / PP_Z) % PP_Y, lx = k / (PP_Z * PP_Y);
+    const int fx = x0 + 1 + lx, fy = y0 + 1 + ly, fz = z0 + 1 + lz;
+    if (!in_grid(gf, fx, fy, fz)) continue;
+    const long i = ((long)fx * gf.ny + fy) * gf.nz + fz;
+    const int c = ((lx + 1) * HY + (ly + 1)) * HZ + (lz + 1);
+    if (!FULL) {
+      V t = f[i];
+#pragma unroll
+      for (int s = 0; s < PAT / 2; ++s) {
+        const int dx = pat_off(PAT, s, 0), dy = pat_off(PAT, s, 1), dz = pat_off(PAT, s, 2);
+        if (in_grid(gf, fx + dx, fy + dy, fz + dz)) t = fma(-m(s, i), us[c + (dx * HY + dy) * HZ + dz], t);
+      }
+      h[i] = t;
+    } else {
+      V acc = V(0);
+#pragma unroll
+      for (int s = 0; s < PAT; ++s) {
+        const int dx = pat_off(PAT, s, 0), dy = pat_off(PAT, s, 1), dz = pat_off(PAT, s, 2);
+        if (in_grid(gf, fx + dx, fy + dy, fz + dz)) acc = fma(m(s, i), us[c + (dx * HY + dy) * HZ + dz], acc);
+      }
+      h[i] = f[i] - acc;
+      uo[i] = us[c];
+    }
+  }
+}
+
+template <class M>
+hipError_t launch_prolong_post(int pat, const Grid& g, int cmask, const M& m, const typename M::V* f,
+                               const typename M::V* u, const typename M::V* ec, typename M::V* h,
+                               typename M::V* uold_out, bool full, hipStream_t st) {
+  const unsigned nb =
+      (unsigned)(((g.nx + PP_X - 1) / PP_X) * ((g.ny + PP_Y - 1) / PP_Y) * ((g.nz + PP_Z - 1) / PP_Z));
+#define SMG_PP(P)                                                                                                 \
+  if (pat == P) {                                                                                                 \
+    if (full)                                                                                                     \
+      hipLaunchKernelGGL((k_prolong_post<P, M, true>), dim3(nb), dim3(256), 0, st, g, cmask, m, f, u, ec, h,       \
+                         uold_out);                                                                               \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_prolong_post<P, M, false>), dim3(nb), dim3(256), 0, st, g, cmask, m, f, u, ec, h,      \
+                         uold_out);                                                                               \
+    return hipGetLastError();                                                                                     \
+  }
+  SMG_PP(7)
+  SMG_PP(19)
+  SMG_PP(27)
+#undef SMG_PP
+  return hipErrorInvalidValue;
+}
+
+// -------------------------------------- plain restriction / prolongation
+template <class V>
+__global__ __launch_bounds__(256) void k_restrict(Grid gf, int cmask, int bs, const V* __restrict__ rf,
+                                                  V* __restrict__ rc) {
+  const int cmx = cmask & 1, cmy = (cmask >> 1) & 1, cmz = (cmask >> 2) & 1;
+  const Grid gc{cmx ? gf.nx / 2 : gf.nx, cmy ? gf.ny / 2 : gf.ny, cmz ? gf.nz / 2 : gf.nz};
+  const unsigned k = blockIdx.x * 256u + threadIdx.x;
+  if (k >= (unsigned)(gc.N() * bs)) return;
+  const unsigned ic = k / bs;
+  const int comp = k % bs;
+  int Xc, Yc, Z;
+  unflat(ic, gc.ny, gc.nz, Xc, Yc, Z);
+  const int fx0 = cmx ? 2 * Xc + 1 : Xc, fy0 = cmy ? 2 * Yc + 1 : Yc, fz0 = cmz ? 2 * Z + 1 : Z;
+  V acc = V(0);
+  for (int r = 0; r < 27; ++r) {
+    const int dx = r / 9 - 1, dy = (r / 3) % 3 - 1, dz = r % 3 - 1;
+    if ((!cmx && dx) || (!cmy && dy) || (!cmz && dz)) continue;
+    const int ux = fx0 + dx, uy = fy0 + dy, uz = fz0 + dz;
+    if (!in_grid(gf, ux, uy, uz)) continue;
+    const V w = V((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
+    acc = fma(w, rf[(((long)ux * gf.ny + uy) * gf.nz + uz) * bs + comp], acc);
+  }
+  rc[k] = acc;
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_prolong_add(Grid gf, int cmask, int bs, const V* __restrict__ ec,
+                                                     V* __restrict__ uf) {
+  const int cmx = cmask & 1, cmy = (cmask >> 1) & 1, cmz = (cmask >> 2) & 1;
+  const Grid gc{cmx ? gf.nx / 2 : gf.nx, cmy ? gf.ny / 2 : gf.ny, cmz ? gf.nz / 2 : gf.nz};
+  const unsigned k = blockIdx.x * 256u + threadIdx.x;
+  if (k >= (unsigned)(gf.N() * bs)) return;
+  const unsigned i = k / bs;
+  const int comp = k % bs;
+  int X, Y, Z;
+  unflat(i, gf.ny, gf.nz, X, Y, Z);
+  uf[k] = uf[k] + interp_point(ec, gc, cmx, cmy, cmz, X, Y, Z, bs, comp);
+}
+
+template <class V>
+hipError_t launch_restrict(const Grid& g, int cmask, int bs, const V* rf, V* rc, hipStream_t st) {
+  const long nc = (long)((cmask & 1) ? g.nx / 2 : g.nx) * ((cmask & 2) ? g.ny / 2 : g.ny) *
+                  ((cmask & 4) ? g.nz / 2 : g.nz) * bs;
+  hipLaunchKernelGGL((k_restrict<V>), dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, g, cmask, bs, rf, rc);
+  return hipGetLastError();
+}
+template <class V>
+hipError_t launch_prolong_add(const Grid& g, int cmask, int bs, const V* ec, V* uf, hipStream_t st) {
+  const long n = g.N() * bs;
+  hipLaunchKernelGGL((k_prolong_add<V>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, cmask, bs, ec, uf);
+  return hipGetLastError();
+}
+
+#define SMG_INST(M)                                                                                              \
+  template hipError_t launch_spmv<M>(int, const Grid&, const M&, const M::V*, const M::V*, M::V*, bool,          \
+                                     hipStream_t);                                                               \
+  template hipError_t launch_resid_restrict<M>(int, const Grid&, int, const M&, const M::V*, const M::V*, M::V*, \
+                                               hipStream_t);                                                     \
+  template hipError_t launch_prolong_post<M>(int, const Grid&, int, const M&, const M::V*, const M::V*,          \
+                                             const M::V*, M::V*, M::V*, bool, hipStream_t);
+SMG_INST(MatD)
+SMG_INST(MatF)
+SMG_INST(MatH)
+#undef SMG_INST
+template hipError_t launch_restrict<double>(const Grid&, int, int, const double*, double*, hipStream_t);
+template hipError_t launch_restrict<float>(const Grid&, int, int, const float*, float*, hipStream_t);
+template hipError_t launch_prolong_add<double>(const Grid&, int, int, const double*, double*, hipStream_t);
+template hipError_t launch_prolong_add<float>(const Grid&, int, int, const float*, float*, hipStream_t);
+
+}  // namespace smg

@@ -1,0 +1,895 @@
+// libstructmg host side: hierarchy setup, V-cycle orchestration, outer
+// Krylov solvers and the C ABI declared in include/structmg.h.
+//
+// Setup builds the hierarchy from the finest matrix only (Sec. 3.2.2):
+// multi-dimensional coarsening by fixed stride 2 (Sec. 3.1 P2), coarse
+// operators from the generated stencil triple product (Sec. 3.3), smoother
+// data per level, then the dense coarsest inverse.  The V-cycle (Sec. 2) runs
+// a zero-initial-guess forward GS sweep (or ILU(0) solve) before the coarse
+// correction and a backward GS sweep (or ILU(0) correction) after it, the
+// symmetric PGS / ILU settings of the paper's configuration table.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+
+#include "../../include/structmg.h"
+#include "smg_kernels.h"
+
+using namespace smg;
+
+namespace {
+
+constexpr int MAXLEV = 40;
+
+struct Level {
+  Grid g;
+  int S = 0;      // pattern points
+  int cmask = 0;  // axes coarsened to reach the next level (0: coarsest)
+  long N = 0;
+  double *A64 = nullptr, *rd64 = nullptr, *L64 = nullptr, *U64 = nullptr, *rU64 = nullptr;
+  float *A32 = nullptr, *rd32 = nullptr, *L32 = nullptr, *U32 = nullptr, *rU32 = nullptr;
+  __half* A16 = nullptr;
+  float* sc16 = nullptr;
+  void *f = nullptr, *ua = nullptr, *ub = nullptr, *h = nullptr;
+  void *y1 = nullptr, *y2 = nullptr, *zz = nullptr, *uo = nullptr;
+  int sh = 0, ntx = 0, nty = 0;
+};
+
+}  // namespace
+
+struct smg_handle_s {
+  smg_config cfg{};
+  int bs = 1, nlev = 0, nc = 0;
+  Level lev[MAXLEV];
+  double* aug = nullptr;  // coarsest [.. | A^-1] (n x 2n) + n spare
+  unsigned* ctr = nullptr;
+  unsigned* err = nullptr;
+  int* info = nullptr;
+  double *dpart = nullptr, *dout = nullptr;
+  double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr, *kt = nullptr, *kw = nullptr;
+  double* kV = nullptr;
+  int kV_m = 0;
+  double t_setup_ms = 0.0;
+  char msg[512] = {0};
+};
+
+static char g_setup_msg[512] = "no error";
+
+static smg_status fail(smg_handle h, smg_status st, const char* fmt, ...) {
+  char* dst = h ? h->msg : g_setup_msg;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(dst, 512, fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+#define HIPCHK(h, expr)                                                                         \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess) return fail(h, SMG_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));  \
+  } while (0)
+
+namespace {
+
+struct Arena {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+int next_cmask(int lev, const int* n, int semi, int semi_levels) {
+  int allowed = (semi || lev < semi_levels) ? 3 : 7, m = 0;
+  for (int a = 0; a < 3; ++a)
+    if (((allowed >> a) & 1) && n[a] >= 8) m |= 1 << a;
+  return m;
+}
+
+const char* check_cfg(const smg_config* c) {
+  if (!c) return "null config";
+  if (c->nx < 1 || c->ny < 1 || c->nz < 1) return "grid dimensions must be >= 1";
+  if ((double)c->nx * c->ny * c->nz * (c->block > 1 ? c->block : 1) >= 2147483647.0) return "grid too large";
+  if (c->block != 1 && c->block != 3) return "block must be 1 or 3";
+  if (c->pattern != 7 && c->pattern != 19 && c->pattern != 27) return "pattern must be 7, 19 or 27";
+  if (c->block == 3 && c->pattern != 27) return "block systems use the 27-point pattern";
+  if (c->smoother != SMG_SMOOTH_GS && c->smoother != SMG_SMOOTH_ILU0) return "unknown smoother";
+  if (c->smoother == SMG_SMOOTH_ILU0 && c->block != 1) return "ILU(0) is implemented for scalar systems";
+  if (c->smoother == SMG_SMOOTH_ILU0 && c->prec == SMG_FP16_ROWSCALE) return "ILU(0) supports FP64 and FP32";
+  if (c->coarsen != SMG_COARSEN_FULL && c->coarsen != SMG_COARSEN_SEMI_XY) return "unknown coarsening";
+  if (c->semi_levels < 0) return "semi_levels must be >= 0";
+  if (c->prec < SMG_FP64 || c->prec > SMG_FP16_ROWSCALE) return "unknown precision";
+  if (c->max_coarse < 0 || c->gmres_restart < 0 || c->gmres_restart > 200) return "bad max_coarse / gmres_restart";
+  return nullptr;
+}
+
+// Lays out every device array of the handle in the workspace (base == null:
+// size only).  Returns the number of bytes.
+size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, int* nc_out) {
+  Arena ar{base};
+  const int bs = cfg.block, be = bs * bs;
+  const int maxc = cfg.max_coarse > 0 ? cfg.max_coarse : 4096;
+  const size_t vsz = cfg.prec == SMG_FP64 ? 8 : 4;
+  int n[3] = {cfg.nx, cfg.ny, cfg.nz};
+  int nlev = 0;
+  Level tmp[MAXLEV];
+  Level* L = H ? H->lev : tmp;
+  for (;;) {
+    Level& v = L[nlev];
+    v.g = Grid{n[0], n[1], n[2]};
+    v.N = v.g.N();
+    v.S = nlev == 0 ? cfg.pattern : 27;
+    v.cmask = next_cmask(nlev, n, cfg.coarsen == SMG_COARSEN_SEMI_XY, cfg.semi_levels);
+    ++nlev;
+    if (v.cmask == 0 || nlev == MAXLEV) {
+      v.cmask = 0;
+      break;
+    }
+    for (int a = 0; a < 3; ++a)
+      if ((v.cmask >> a) & 1) n[a] /= 2;
+  }
+  const long nc = L[nlev - 1].N * bs;
+  if (nlev_out) *nlev_out = nlev;
+  if (nc_out) *nc_out = (int)nc;
+  if (nc > maxc) return 0;
+  for (int l = 0; l < nlev; ++l) {
+    Level& v = L[l];
+    const long N = v.N;
+    const bool last = l == nlev - 1;
+    v.A64 = ar.take<double>((size_t)v.S * be * N);
+    auto vec = [&](void** p) { *p = ar.take<char>((size_t)N * bs * vsz); };
+    vec(&v.f);
+    vec(&v.ub);
+    if (last) continue;
+    vec(&v.ua);
+    vec(&v.h);
+    v.rd64 = ar.take<double>((size_t)(bs == 3 ? 9 : 1) * N);
+    if (cfg.smoother == SMG_SMOOTH_ILU0) {
+      v.L64 = ar.take<double>((size_t)v.S * N);
+      v.U64 = ar.take<double>((size_t)v.S * N);
+      v.rU64 = ar.take<double>((size_t)N);
+      vec(&v.y1);
+      vec(&v.y2);
+      vec(&v.zz);
+      vec(&v.uo);
+    }
+    if (cfg.prec == SMG_FP32) {
+      v.A32 = ar.take<float>((size_t)v.S * be * N);
+      v.rd32 = ar.take<float>((size_t)(bs == 3 ? 9 : 1) * N);
+      if (cfg.smoother == SMG_SMOOTH_ILU0) {
+        v.L32 = ar.take<float>((size_t)v.S * N);
+        v.U32 = ar.take<float>((size_t)v.S * N);
+        v.rU32 = ar.take<float>((size_t)N);
+      }
+    } else if (cfg.prec == SMG_FP16_ROWSCALE) {
+      v.A16 = ar.take<__half>((size_t)v.S * be * N);
+      v.sc16 = ar.take<float>((size_t)bs * N);
+      v.rd32 = ar.take<float>((size_t)(bs == 3 ? 9 : 1) * N);
+    }
+  }
+  double* aug = ar.take<double>((size_t)nc * 2 * nc + nc);
+  unsigned* ctr = ar.take<unsigned>(64);
+  unsigned* err = ar.take<unsigned>(64);
+  int* info = ar.take<int>(64);
+  double* dpart = ar.take<double>(DOT_BLOCKS);
+  double* dout = ar.take<double>(64);
+  const long n0 = L[0].N * bs;
+  double* kr = ar.take<double>(n0);
+  double* kz = ar.take<double>(n0);
+  double* kp = ar.take<double>(n0);
+  double* kq = ar.take<double>(n0);
+  double* kt = ar.take<double>(n0);
+  double* kw = ar.take<double>(n0);
+  double* kV = cfg.gmres_restart > 0 ? ar.take<double>((size_t)n0 * (cfg.gmres_restart + 1)) : nullptr;
+  if (H) {
+    H->aug = aug;
+    H->ctr = ctr;
+    H->err = err;
+    H->info = info;
+    H->dpart = dpart;
+    H->dout = dout;
+    H->kr = kr;
+    H->kz = kz;
+    H->kp = kp;
+    H->kq = kq;
+    H->kt = kt;
+    H->kw = kw;
+    H->kV = kV;
+    H->kV_m = cfg.gmres_restart;
+  }
+  return ar.off + 256;
+}
+
+// ---- precision traits of the V-cycle ---------------------------------
+struct P64 {
+  using V = double;
+  using M = MatD;
+  using MF = MatD;
+  static M A(const Level& l) { return MatD{l.A64, l.N}; }
+  static MF Lf(const Level& l) { return MatD{l.L64, l.N}; }
+  static MF Uf(const Level& l) { return MatD{l.U64, l.N}; }
+  static const V* rd(const Level& l) { return l.rd64; }
+  static const V* rU(const Level& l) { return l.rU64; }
+};
+struct P32 {
+  using V = float;
+  using M = MatF;
+  using MF = MatF;
+  static M A(const Level& l) { return MatF{l.A32, l.N}; }
+  static MF Lf(const Level& l) { return MatF{l.L32, l.N}; }
+  static MF Uf(const Level& l) { return MatF{l.U32, l.N}; }
+  static const V* rd(const Level& l) { return l.rd32; }
+  static const V* rU(const Level& l) { return l.rU32; }
+};
+struct P16 {
+  using V = float;
+  using M = MatH;
+  using MF = MatF;
+  static M A(const Level& l) { return MatH{l.A16, l.sc16, l.N}; }
+  static MF Lf(const Level& l) { return MatF{l.L32, l.N}; }
+  static MF Uf(const Level& l) { return MatF{l.U32, l.N}; }
+  static const V* rd(const Level& l) { return l.rd32; }
+  static const V* rU(const Level& l) { return l.rU32; }
+};
+
+template <class V, class M>
+hipError_t sweep(smg_handle_s* H, const Level& L, int dir, bool unitd, const M& m, const V* hin, const V* d, V* x,
+                 V* next, int next_dir, const V* addv, V* addout, hipStream_t st) {
+  WfArgs<V> a{};
+  a.g = L.g;
+  a.sh = L.sh;
+  a.ntx = L.ntx;
+  a.nty = L.nty;
+  a.h = hin;
+  a.d = d;
+  a.x = x;
+  a.next = next;
+  a.next_dir = next_dir;
+  a.next_sh = L.sh;
+  a.addv = addv;
+  a.addout = addout;
+  a.ctr = H->ctr;
+  a.err = H->err;
+  return launch_wavefront<M>(L.S, dir, unitd, addout != nullptr, a, m, st);
+}
+
+// One V-cycle on internal or caller vectors: f0 = level-0 right-hand side,
+// z0 = level-0 output (its positions read across tiles are given sentinels by
+// the pre-smoothing sweep).
+template <class PT>
+hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z0, hipStream_t st) {
+  using V = typename PT::V;
+  const int NL = H->nlev;
+  const bool ilu = H->cfg.smoother == SMG_SMOOTH_ILU0;
+  auto F = [&](int l) -> const V* { return l == 0 ? f0 : (const V*)H->lev[l].f; };
+  auto UB = [&](int l) -> V* { return l == 0 ? z0 : (V*)H->lev[l].ub; };
+  hipError_t e;
+  for (int l = 0; l < NL - 1; ++l) {
+    const Level& v = H->lev[l];
+    const auto A = PT::A(v);
+    if (!ilu) {
+      e = sweep<V>(H, v, +1, false, A, F(l), PT::rd(v), (V*)v.ua, UB(l), -1, nullptr, nullptr, st);
+    } else {
+      e = sweep<V>(H, v, +1, true, PT::Lf(v), F(l), nullptr, (V*)v.y1, (V*)v.ua, -1, nullptr, nullptr, st);
+      if (e != hipSuccess) return e;
+      e = sweep<V>(H, v, -1, false, PT::Uf(v), (const V*)v.y1, PT::rU(v), (V*)v.ua, (V*)v.y2, +1, nullptr, nullptr,
+                   st);
+    }
+    if (e != hipSuccess) return e;
+    e = launch_resid_restrict(v.S, v.g, v.cmask, A, F(l), (const V*)v.ua, (V*)H->lev[l + 1].f, st);
+    if (e != hipSuccess) return e;
+  }
+  e = launch_coarse_gemv<V>(H->nc, H->aug + H->nc, 2 * H->nc, F(NL - 1), UB(NL - 1), st);
+  if (e != hipSuccess) return e;
+  for (int l = NL - 2; l >= 0; --l) {
+    const Level& v = H->lev[l];
+    const auto A = PT::A(v);
+    if (!ilu) {
+      e = launch_prolong_post(v.S, v.g, v.cmask, A, F(l), (const V*)v.ua, (const V*)UB(l + 1), (V*)v.h, (V*)nullptr,
+                              false, st);
+      if (e != hipSuccess) return e;
+      e = sweep<V>(H, v, -1, false, A, (const V*)v.h, PT::rd(v), UB(l), (V*)v.ua, +1, nullptr, nullptr, st);
+    } else {
+      e = launch_prolong_post(v.S, v.g, v.cmask, A, F(l), (const V*)v.ua, (const V*)UB(l + 1), (V*)v.h, (V*)v.uo,
+                              true, st);
+      if (e != hipSuccess) return e;
+      e = sweep<V>(H, v, +1, true, PT::Lf(v), (const V*)v.h, nullptr, (V*)v.y2, (V*)v.zz, -1, nullptr, nullptr, st);
+      if (e != hipSuccess) return e;
+      e = sweep<V>(H, v, -1, false, PT::Uf(v), (const V*)v.y2, PT::rU(v), (V*)v.zz, (V*)v.y1, +1, (const V*)v.uo,
+                   UB(l), st);
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t vcycle(smg_handle_s* H, const double* r, double* z, hipStream_t st) {
+  const Level& l0 = H->lev[0];
+  const long n0 = l0.N * H->bs;
+  switch (H->cfg.prec) {
+    case SMG_FP64:
+      return vcycle_t<P64>(H, r, z, st);
+    case SMG_FP32: {
+      hipError_t e = launch_cast_d2f(n0, r, (float*)l0.f, st);
+      if (e == hipSuccess) e = vcycle_t<P32>(H, (const float*)l0.f, (float*)l0.ub, st);
+      if (e == hipSuccess) e = launch_cast_f2d(n0, (const float*)l0.ub, z, st);
+      return e;
+    }
+    default: {
+      hipError_t e = launch_cast_d2f(n0, r, (float*)l0.f, st);
+      if (e == hipSuccess) e = vcycle_t<P16>(H, (const float*)l0.f, (float*)l0.ub, st);
+      if (e == hipSuccess) e = launch_cast_f2d(n0, (const float*)l0.ub, z, st);
+      return e;
+    }
+  }
+}
+
+hipError_t spmv64(smg_handle_s* H, const double* x, const double* b, double* y, bool res, hipStream_t st) {
+  const Level& l0 = H->lev[0];
+  return launch_spmv(l0.S, l0.g, MatD{l0.A64, l0.N}, x, b, y, res, st);
+}
+
+smg_status check_err(smg_handle_s* H, hipStream_t st) {
+  unsigned e = 0;
+  HIPCHK(H, hipMemcpyAsync(&e, H->err, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  HIPCHK(H, hipStreamSynchronize(st));
+  if (e & 1u) return fail(H, SMG_EDEADLOCK, "wavefront watchdog fired");
+  if (e & 2u) return fail(H, SMG_EBREAKDOWN, "zero pivot or zero diagonal");
+  return SMG_OK;
+}
+
+double dot(smg_handle_s* H, const double* x, const double* y, long n, hipStream_t st, hipError_t* e) {
+  double v = 0.0;
+  *e = launch_dot(n, x, y, H->dpart, H->dout, st);
+  if (*e != hipSuccess) return 0.0;
+  *e = hipMemcpyAsync(&v, H->dout, sizeof(double), hipMemcpyDeviceToHost, st);
+  if (*e != hipSuccess) return 0.0;
+  *e = hipStreamSynchronize(st);
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+smg_status smg_workspace_size(const smg_config* cfg, size_t* bytes) {
+  const char* why = check_cfg(cfg);
+  if (why) return fail(nullptr, SMG_EINVAL, "%s", why);
+  if (!bytes) return fail(nullptr, SMG_EINVAL, "null bytes pointer");
+  int nlev = 0, nc = 0;
+  size_t b = plan(*cfg, nullptr, nullptr, &nlev, &nc);
+  if (b == 0) return fail(nullptr, SMG_EINVAL, "coarsest level has %d unknowns (> max_coarse)", nc);
+  *bytes = b;
+  return SMG_OK;
+}
+
+smg_status smg_setup(const smg_config* cfg, const double* coeffs, void* workspace, size_t bytes, void* stream,
+                     smg_handle* out) {
+  if (!out) return fail(nullptr, SMG_EINVAL, "null output handle");
+  *out = nullptr;
+  const char* why = check_cfg(cfg);
+  if (why) return fail(nullptr, SMG_EINVAL, "%s", why);
+  if (!coeffs || !workspace) return fail(nullptr, SMG_EINVAL, "null coefficient or workspace pointer");
+  int nlev = 0, nc = 0;
+  const size_t need = plan(*cfg, nullptr, nullptr, &nlev, &nc);
+  if (need == 0) return fail(nullptr, SMG_EINVAL, "coarsest level has %d unknowns (> max_coarse)", nc);
+  if (bytes < need) return fail(nullptr, SMG_ENOMEM, "workspace of %zu bytes, %zu needed", bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  auto t0 = std::chrono::steady_clock::now();
+  smg_handle_s* H = new smg_handle_s();
+  H->cfg = *cfg;
+  H->bs = cfg->block;
+  char* base = (char*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+  plan(*cfg, H, base, &H->nlev, &H->nc);
+  const int bs = H->bs, be = bs * bs;
+  auto bail = [&](smg_status s) {
+    if (s != SMG_OK) {
+      snprintf(g_setup_msg, sizeof g_setup_msg, "%s", H->msg);
+      delete H;
+    }
+    return s;
+  };
+#define SCHK(expr)                                                                               \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) return bail(fail(H, SMG_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_))); \
+  } while (0)
+  SCHK(launch_fill_bits<unsigned>(H->ctr, 64, 0u, st));
+  SCHK(launch_fill_bits<unsigned>(H->err, 64, 0u, st));
+  SCHK(launch_fill_bits<unsigned>((unsigned*)H->info, 64, 0u, st));
+  // level 0 copy (Dirichlet couplings zeroed), coarse operators by RAP
+  SCHK(launch_copy_masked(H->lev[0].S, H->lev[0].g, be, coeffs, H->lev[0].A64, st));
+  for (int l = 0; l + 1 < H->nlev; ++l) {
+    const Level& f = H->lev[l];
+    Level& c = H->lev[l + 1];
+    for (int e = 0; e < be; ++e)
+      SCHK(launch_rap(f.S, f.cmask, f.g, f.A64 + (long)e * f.N, (long)be * f.N, c.A64 + (long)e * c.N,
+                      (long)be * c.N, st));
+  }
+  // smoother data, truncation, wavefront tiling and sentinel fills
+  for (int l = 0; l + 1 < H->nlev; ++l) {
+    Level& v = H->lev[l];
+    if (bs == 3)
+      SCHK(launch_block_dinv(v.g, v.A64, v.rd64, H->err, st));
+    else
+      SCHK(launch_recip_diag(v.S, v.g, v.A64, v.rd64, H->err, st));
+    if (cfg->smoother == SMG_SMOOTH_ILU0) SCHK(launch_ilu0_factor(v.S, v.g, v.A64, v.L64, v.U64, v.rU64, H->err, st));
+    const long na = (long)v.S * be * v.N;
+    if (cfg->prec == SMG_FP32) {
+      SCHK(launch_to_f32(v.A64, v.A32, na, st));
+      SCHK(launch_to_f32(v.rd64, v.rd32, (bs == 3 ? 9 : 1) * v.N, st));
+      if (cfg->smoother == SMG_SMOOTH_ILU0) {
+        SCHK(launch_to_f32(v.L64, v.L32, (long)v.S * v.N, st));
+        SCHK(launch_to_f32(v.U64, v.U32, (long)v.S * v.N, st));
+        SCHK(launch_to_f32(v.rU64, v.rU32, v.N, st));
+      }
+    } else if (cfg->prec == SMG_FP16_ROWSCALE) {
+      SCHK(launch_to_f16_rowscale(v.A64, v.N, v.S, bs, v.A16, v.sc16, st));
+      SCHK(launch_to_f32(v.rd64, v.rd32, (bs == 3 ? 9 : 1) * v.N, st));
+    }
+    wf_tiling(v.g, &v.sh, &v.ntx, &v.nty);
+    const long nv = v.N * bs;
+    void* bufs[] = {v.ua, v.ub, v.y1, v.y2, v.zz};
+    for (void* p : bufs) {
+      if (!p) continue;
+      if (cfg->prec == SMG_FP64) {
+        double s;
+        uint64_t b = SENT64;
+        memcpy(&s, &b, 8);
+        SCHK(launch_fill_bits<double>((double*)p, nv, s, st));
+      } else {
+        float s;
+        uint32_t b = SENT32;
+        memcpy(&s, &b, 4);
+        SCHK(launch_fill_bits<float>((float*)p, nv, s, st));
+      }
+    }
+  }
+  // coarsest: dense FP64 inverse
+  {
+    const Level& c = H->lev[H->nlev - 1];
+    SCHK(launch_aug_init(H->nc, H->aug, st));
+    SCHK(launch_dense_assemble(c.g, bs, c.A64, H->aug, 2 * H->nc, st));
+    SCHK(coarse_invert(H->nc, H->aug, H->info, st));
+  }
+  SCHK(hipStreamSynchronize(st));
+  unsigned errv = 0;
+  int infov = 0;
+  SCHK(hipMemcpy(&errv, H->err, sizeof errv, hipMemcpyDeviceToHost));
+  SCHK(hipMemcpy(&infov, H->info, sizeof infov, hipMemcpyDeviceToHost));
+  if (errv & 2u) return bail(fail(H, SMG_EBREAKDOWN, "zero diagonal or zero ILU pivot during setup"));
+  if (infov) return bail(fail(H, SMG_EBREAKDOWN, "singular coarsest operator"));
+#undef SCHK
+  H->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = H;
+  return SMG_OK;
+}
+
+smg_status smg_precondition(smg_handle h, const double* r, double* z, void* stream) {
+  if (!h) return fail(nullptr, SMG_EINVAL, "null handle");
+  if (!r || !z) return fail(h, SMG_EINVAL, "null vector");
+  const long n0 = h->lev[0].N * h->bs;
+  if ((const char*)z < (const char*)(r + n0) && (const char*)r < (const char*)(z + n0))
+    return fail(h, SMG_EINVAL, "r and z overlap");
+  if (h->bs != 1) return fail(h, SMG_EINVAL, "block V-cycle not available");
+  HIPCHK(h, vcycle(h, r, z, (hipStream_t)stream));
+  return SMG_OK;
+}
+
+smg_status smg_solve(smg_handle H, const double* b, double* x, double rtol, int maxit, int krylov, smg_result* res,
+                     void* stream) {
+  if (!H) return fail(nullptr, SMG_EINVAL, "null handle");
+  if (!b || !x) return fail(H, SMG_EINVAL, "null vector");
+  if (!(rtol > 0.0) || maxit < 0 || krylov < 0) return fail(H, SMG_EINVAL, "bad rtol / maxit / krylov");
+  if (krylov > 0 && krylov > H->kV_m) return fail(H, SMG_EINVAL, "GMRES(%d) needs cfg.gmres_restart >= %d", krylov, krylov);
+  if (H->bs != 1) return fail(H, SMG_EINVAL, "block V-cycle not available");
+  hipStream_t st = (hipStream_t)stream;
+  const long n = H->lev[0].N * H->bs;
+  hipError_t e = hipSuccess;
+  auto t0 = std::chrono::steady_clock::now();
+#define KCHK(expr)                                                                       \
+  do {                                                                                   \
+    e = (expr);                                                                          \
+    if (e != hipSuccess) return fail(H, SMG_EDEVICE, "%s: %s", #expr, hipGetErrorString(e)); \
+  } while (0)
+#define KDOT(a, b_) dot(H, a, b_, n, st, &e)
+  double *r = H->kr, *z = H->kz, *p = H->kp, *q = H->kq;
+  double bn = sqrt(KDOT(b, b));
+  KCHK(e);
+  if (bn == 0.0) bn = 1.0;
+  KCHK(spmv64(H, x, b, r, true, st));
+  double rel = sqrt(KDOT(r, r)) / bn;
+  KCHK(e);
+  int it = 0;
+  smg_status status = SMG_ENOTCONV;
+  if (rel < rtol) status = SMG_OK;
+  if (krylov == 0 && status != SMG_OK) {
+    KCHK(vcycle(H, r, z, st));
+    KCHK(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    double rho = KDOT(r, z);
+    KCHK(e);
+    while (it < maxit) {
+      KCHK(spmv64(H, p, nullptr, q, false, st));
+      const double pq = KDOT(p, q);
+      KCHK(e);
+      if (!(pq > 0.0)) {
+        status = SMG_EBREAKDOWN;
+        fail(H, SMG_EBREAKDOWN, "p.Ap = %g <= 0", pq);
+        break;
+      }
+      const double alpha = rho / pq;
+      KCHK(launch_axpy(n, alpha, p, x, st));
+      KCHK(launch_axpy(n, -alpha, q, r, st));
+      ++it;
+      rel = sqrt(KDOT(r, r)) / bn;
+      KCHK(e);
+      if (rel < rtol) {
+        KCHK(spmv64(H, x, b, r, true, st));
+        rel = sqrt(KDOT(r, r)) / bn;
+        KCHK(e);
+        if (rel < rtol) {
+          status = SMG_OK;
+          break;
+        }
+      }
+      KCHK(vcycle(H, r, z, st));
+      const double rho1 = KDOT(r, z);
+      KCHK(e);
+      const double beta = rho1 / rho;
+      rho = rho1;
+      KCHK(launch_xpby(n, z, beta, p, st));
+    }
+  } else if (status != SMG_OK) {
+    // right-preconditioned GMRES(m), modified Gram-Schmidt, Givens rotations
+    const int m = krylov;
+    double* V = H->kV;
+    double *w = H->kw, *t = H->kt;
+    double Hm[201 * 200];
+    double cs[200], sn[200], g[201], y[200];
+    double beta = rel * bn;
+    while (status != SMG_OK && it < maxit) {
+      KCHK(launch_scale(n, 1.0 / beta, r, V, st));
+      for (int k = 0; k <= m; ++k) g[k] = 0.0;
+      g[0] = beta;
+      int jdone = 0;
+      for (int j = 0; j < m && it < maxit; ++j) {
+        double* vj = V + (long)j * n;
+        double* vn = V + (long)(j + 1) * n;
+        KCHK(vcycle(H, vj, z, st));
+        KCHK(spmv64(H, z, nullptr, w, false, st));
+        for (int i = 0; i <= j; ++i) {
+          double* vi = V + (long)i * n;
+          const double hij = KDOT(w, vi);
+          KCHK(e);
+          Hm[i * m + j] = hij;
+          KCHK(launch_axpy(n, -hij, vi, w, st));
+        }
+        const double hn = sqrt(KDOT(w, w));
+        KCHK(e);
+        Hm[(j + 1) * m + j] = hn;
+        if (hn != 0.0) KCHK(launch_scale(n, 1.0 / hn, w, vn, st));
+        for (int i = 0; i < j; ++i) {
+          const double a = Hm[i * m + j], bb = Hm[(i + 1) * m + j];
+          Hm[i * m + j] = cs[i] * a + sn[i] * bb;
+          Hm[(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+        }
+        const double a = Hm[j * m + j], bb = Hm[(j + 1) * m + j];
+        const double den = sqrt(a * a + bb * bb);
+        cs[j] = den == 0.0 ? 1.0 : a / den;
+        sn[j] = den == 0.0 ? 0.0 : bb / den;
+        Hm[j * m + j] = den;
+        Hm[(j + 1) * m + j] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        ++it;
+        jdone = j + 1;
+        if (fabs(g[j + 1]) / bn < rtol || hn == 0.0) break;
+      }
+      for (int i = jdone - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int k = i + 1; k < jdone; ++k) s -= Hm[i * m + k] * y[k];
+        y[i] = s / Hm[i * m + i];
+      }
+      KCHK(launch_scale(n, y[0], V, t, st));
+      for (int i = 1; i < jdone; ++i) KCHK(launch_axpy(n, y[i], V + (long)i * n, t, st));
+      KCHK(vcycle(H, t, z, st));
+      KCHK(launch_axpy(n, 1.0, z, x, st));
+      KCHK(spmv64(H, x, b, r, true, st));
+      beta = sqrt(KDOT(r, r));
+      KCHK(e);
+      rel = beta / bn;
+      if (rel < rtol) status = SMG_OK;
+    }
+  }
+  // final true residual in FP64
+  KCHK(spmv64(H, x, b, r, true, st));
+  rel = sqrt(KDOT(r, r)) / bn;
+  KCHK(e);
+  smg_status es = check_err(H, st);
+  if (es != SMG_OK) return es;
+#undef KDOT
+#undef KCHK
+  if (res) {
+    res->iters = it;
+    res->levels = H->nlev;
+    res->rel_resid_true = rel;
+    double sn0 = 0, sn = 0, so0 = 0, so = 0;
+    for (int l = 0; l < H->nlev; ++l) {
+      sn += (double)H->lev[l].N;
+      so += (double)H->lev[l].N * H->lev[l].S;
+    }
+    sn0 = (double)H->lev[0].N;
+    so0 = (double)H->lev[0].N * H->lev[0].S;
+    res->grid_complexity = sn / sn0;
+    res->op_complexity = so / so0;
+    res->t_setup_ms = H->t_setup_ms;
+    res->t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (status == SMG_ENOTCONV) fail(H, SMG_ENOTCONV, "not converged after %d iterations (rel %g)", it, rel);
+  return status;
+}
+
+smg_status smg_destroy(smg_handle h) {
+  delete h;
+  return SMG_OK;
+}
+
+const char* smg_last_error(smg_handle h) { return h ? h->msg : g_setup_msg; }
+
+int smg_num_levels(smg_handle h) { return h ? h->nlev : 0; }
+
+smg_status smg_level_info(smg_handle h, int level, int* info) {
+  if (!h || !info) return fail(h, SMG_EINVAL, "null argument");
+  if (level < 0 || level >= h->nlev) return fail(h, SMG_EINVAL, "level %d out of range", level);
+  const Level& v = h->lev[level];
+  info[0] = v.g.nx;
+  info[1] = v.g.ny;
+  info[2] = v.g.nz;
+  info[3] = v.S;
+  info[4] = v.cmask;
+  info[5] = h->bs;
+  return SMG_OK;
+}
+
+smg_status smg_level_export(smg_handle h, int level, int what, void* dst, void* stream) {
+  if (!h || !dst) return fail(h, SMG_EINVAL, "null argument");
+  if (level < 0 || level >= h->nlev) return fail(h, SMG_EINVAL, "level %d out of range", level);
+  const Level& v = h->lev[level];
+  hipStream_t st = (hipStream_t)stream;
+  const long be = (long)h->bs * h->bs, nd = (h->bs == 3 ? 9 : 1) * v.N;
+  const void* src = nullptr;
+  size_t bytes = 0;
+  const bool last = level == h->nlev - 1;
+  switch (what) {
+    case 0: src = v.A64; bytes = sizeof(double) * v.S * be * v.N; break;
+    case 1: src = v.rd64; bytes = sizeof(double) * nd; break;
+    case 2: src = v.L64; bytes = sizeof(double) * v.S * v.N; break;
+    case 3: src = v.U64; bytes = sizeof(double) * v.S * v.N; break;
+    case 4: src = v.rU64; bytes = sizeof(double) * v.N; break;
+    case 5:
+      if (last || h->cfg.prec == SMG_FP64) return fail(h, SMG_EINVAL, "no reduced-precision matrix on this level");
+      if (h->cfg.prec == SMG_FP32) {
+        src = v.A32;
+        bytes = sizeof(float) * v.S * be * v.N;
+        break;
+      }
+      HIPCHK(h, launch_dequant_f16(v.A16, v.sc16, v.N, v.S, h->bs, (float*)dst, st));
+      return SMG_OK;
+    case 6:
+      if (last || h->cfg.prec == SMG_FP64) return fail(h, SMG_EINVAL, "no reduced-precision diagonal on this level");
+      src = v.rd32;
+      bytes = sizeof(float) * nd;
+      break;
+    default: return fail(h, SMG_EINVAL, "unknown export %d", what);
+  }
+  if (!src) return fail(h, SMG_EINVAL, "level %d has no data %d", level, what);
+  HIPCHK(h, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
+  return SMG_OK;
+}
+
+int smg_rap_chain_count(int pattern, int cmask) { return rap_chain_count(pattern, cmask); }
+
+}  // extern "C"
+
+// ---- single-step entry points (C linkage from the header declarations) ---
+static smg_status op_level_check(smg_handle h, int level, bool need_next) {
+  if (!h) return fail(nullptr, SMG_EINVAL, "null handle");
+  if (level < 0 || level >= h->nlev) return fail(h, SMG_EINVAL, "level %d out of range", level);
+  if (need_next && level + 1 >= h->nlev) return fail(h, SMG_EINVAL, "level %d is the coarsest", level);
+  if (h->bs != 1) return fail(h, SMG_EINVAL, "block operators not available");
+  return SMG_OK;
+}
+
+template <class PT>
+static hipError_t op_presmooth_t(smg_handle_s* H, const Level& v, const void* f, void* u, hipStream_t st) {
+  using V = typename PT::V;
+  V sent;
+  if (sizeof(V) == 8) {
+    uint64_t b = SENT64;
+    memcpy(&sent, &b, 8);
+  } else {
+    uint32_t b = SENT32;
+    memcpy(&sent, &b, 4);
+  }
+  const long nv = v.N;
+  hipError_t e;
+  if (H->cfg.smoother == SMG_SMOOTH_GS) {
+    e = launch_fill_bits<V>((V*)u, nv, sent, st);
+    if (e == hipSuccess)
+      e = sweep<V>(H, v, +1, false, PT::A(v), (const V*)f, PT::rd(v), (V*)u, nullptr, 0, nullptr, nullptr, st);
+    return e;
+  }
+  e = launch_fill_bits<V>((V*)v.h, nv, sent, st);
+  if (e == hipSuccess) e = launch_fill_bits<V>((V*)u, nv, sent, st);
+  if (e == hipSuccess)
+    e = sweep<V>(H, v, +1, true, PT::Lf(v), (const V*)f, nullptr, (V*)v.h, nullptr, 0, nullptr, nullptr, st);
+  if (e == hipSuccess)
+    e = sweep<V>(H, v, -1, false, PT::Uf(v), (const V*)v.h, PT::rU(v), (V*)u, nullptr, 0, nullptr, nullptr, st);
+  return e;
+}
+
+template <class PT>
+static hipError_t op_postsmooth_t(smg_handle_s* H, const Level& v, const void* f, const void* uin, const void* ec,
+                                  void* uout, hipStream_t st) {
+  using V = typename PT::V;
+  V sent;
+  if (sizeof(V) == 8) {
+    uint64_t b = SENT64;
+    memcpy(&sent, &b, 8);
+  } else {
+    uint32_t b = SENT32;
+    memcpy(&sent, &b, 4);
+  }
+  const long nv = v.N;
+  const auto A = PT::A(v);
+  hipError_t e;
+  if (H->cfg.smoother == SMG_SMOOTH_GS) {
+    e = launch_prolong_post(v.S, v.g, v.cmask, A, (const V*)f, (const V*)uin, (const V*)ec, (V*)v.h, (V*)nullptr,
+                            false, st);
+    if (e == hipSuccess) e = launch_fill_bits<V>((V*)uout, nv, sent, st);
+    if (e == hipSuccess)
+      e = sweep<V>(H, v, -1, false, A, (const V*)v.h, PT::rd(v), (V*)uout, nullptr, 0, nullptr, nullptr, st);
+    return e;
+  }
+  // ILU correction: r = f - A u_old; u_out = u_old + U^-1 L^-1 r.  Scratch: the
+  // level's y1/y2/zz buffers, whose sentinel state is restored afterwards.
+  e = launch_prolong_post(v.S, v.g, v.cmask, A, (const V*)f, (const V*)uin, (const V*)ec, (V*)v.h, (V*)v.uo, true,
+                          st);
+  if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.y2, nv, sent, st);
+  if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.zz, nv, sent, st);
+  if (e == hipSuccess)
+    e = sweep<V>(H, v, +1, true, PT::Lf(v), (const V*)v.h, nullptr, (V*)v.y2, nullptr, 0, nullptr, nullptr, st);
+  if (e == hipSuccess)
+    e = sweep<V>(H, v, -1, false, PT::Uf(v), (const V*)v.y2, PT::rU(v), (V*)v.zz, nullptr, 0, (const V*)v.uo,
+                 (V*)uout, st);
+  if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.y2, nv, sent, st);
+  if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.zz, nv, sent, st);
+  return e;
+}
+
+template <template <class> class OP, class... Args>
+static hipError_t by_prec(smg_handle_s* H, Args... args) {
+  switch (H->cfg.prec) {
+    case SMG_FP64: return OP<P64>::run(H, args...);
+    case SMG_FP32: return OP<P32>::run(H, args...);
+    default: return OP<P16>::run(H, args...);
+  }
+}
+
+template <class PT>
+struct OpSpmv {
+  static hipError_t run(smg_handle_s* H, int l, const void* x, void* y, hipStream_t st) {
+    const Level& v = H->lev[l];
+    using V = typename PT::V;
+    if (l == H->nlev - 1 && H->cfg.prec != SMG_FP64) return hipErrorInvalidValue;
+    if (l == H->nlev - 1 || H->cfg.prec == SMG_FP64)
+      return launch_spmv(v.S, v.g, MatD{v.A64, v.N}, (const double*)x, nullptr, (double*)y, false, st);
+    return launch_spmv(v.S, v.g, PT::A(v), (const V*)x, (const V*)nullptr, (V*)y, false, st);
+  }
+};
+template <class PT>
+struct OpPre {
+  static hipError_t run(smg_handle_s* H, int l, const void* f, void* u, hipStream_t st) {
+    return op_presmooth_t<PT>(H, H->lev[l], f, u, st);
+  }
+};
+template <class PT>
+struct OpPost {
+  static hipError_t run(smg_handle_s* H, int l, const void* f, const void* ui, const void* ec, void* uo,
+                        hipStream_t st) {
+    return op_postsmooth_t<PT>(H, H->lev[l], f, ui, ec, uo, st);
+  }
+};
+template <class PT>
+struct OpRR {
+  static hipError_t run(smg_handle_s* H, int l, const void* f, const void* u, void* rc, hipStream_t st) {
+    const Level& v = H->lev[l];
+    using V = typename PT::V;
+    return launch_resid_restrict(v.S, v.g, v.cmask, PT::A(v), (const V*)f, (const V*)u, (V*)rc, st);
+  }
+};
+
+smg_status smg_op_spmv(smg_handle h, int level, const void* x, void* y, void* stream) {
+  smg_status s = op_level_check(h, level, false);
+  if (s != SMG_OK) return s;
+  if (!x || !y) return fail(h, SMG_EINVAL, "null vector");
+  if (level == h->nlev - 1 && h->cfg.prec != SMG_FP64)
+    return fail(h, SMG_EINVAL, "the coarsest level is kept in FP64 only");
+  HIPCHK(h, (by_prec<OpSpmv>(h, level, x, y, (hipStream_t)stream)));
+  return SMG_OK;
+}
+
+smg_status smg_op_spmv_fp64(smg_handle h, const double* x, double* y, void* stream) {
+  if (!h || !x || !y) return fail(h, SMG_EINVAL, "null argument");
+  if (h->bs != 1) return fail(h, SMG_EINVAL, "block operators not available");
+  HIPCHK(h, spmv64(h, x, nullptr, y, false, (hipStream_t)stream));
+  return SMG_OK;
+}
+
+smg_status smg_op_presmooth(smg_handle h, int level, const void* f, void* u, void* stream) {
+  smg_status s = op_level_check(h, level, true);
+  if (s != SMG_OK) return s;
+  if (!f || !u || f == u) return fail(h, SMG_EINVAL, "null or aliased vectors");
+  HIPCHK(h, (by_prec<OpPre>(h, level, f, u, (hipStream_t)stream)));
+  return check_err(h, (hipStream_t)stream);
+}
+
+smg_status smg_op_postsmooth(smg_handle h, int level, const void* f, const void* u_in, const void* ec, void* u_out,
+                             void* stream) {
+  smg_status s = op_level_check(h, level, true);
+  if (s != SMG_OK) return s;
+  if (!f || !u_in || !u_out || u_out == u_in || u_out == f) return fail(h, SMG_EINVAL, "null or aliased vectors");
+  HIPCHK(h, (by_prec<OpPost>(h, level, f, u_in, ec, u_out, (hipStream_t)stream)));
+  return check_err(h, (hipStream_t)stream);
+}
+
+smg_status smg_op_resid_restrict(smg_handle h, int level, const void* f, const void* u, void* rc, void* stream) {
+  smg_status s = op_level_check(h, level, true);
+  if (s != SMG_OK) return s;
+  if (!f || !u || !rc) return fail(h, SMG_EINVAL, "null vector");
+  HIPCHK(h, (by_prec<OpRR>(h, level, f, u, rc, (hipStream_t)stream)));
+  return SMG_OK;
+}
+
+smg_status smg_op_restrict(smg_handle h, int level, const void* rf, void* rc, void* stream) {
+  if (!h) return fail(nullptr, SMG_EINVAL, "null handle");
+  if (level < 0 || level + 1 >= h->nlev) return fail(h, SMG_EINVAL, "level %d has no coarser level", level);
+  if (!rf || !rc) return fail(h, SMG_EINVAL, "null vector");
+  const Level& v = h->lev[level];
+  if (h->cfg.prec == SMG_FP64)
+    HIPCHK(h, launch_restrict<double>(v.g, v.cmask, h->bs, (const double*)rf, (double*)rc, (hipStream_t)stream));
+  else
+    HIPCHK(h, launch_restrict<float>(v.g, v.cmask, h->bs, (const float*)rf, (float*)rc, (hipStream_t)stream));
+  return SMG_OK;
+}
+
+smg_status smg_op_prolong_add(smg_handle h, int level, const void* ec, void* uf, void* stream) {
+  if (!h) return fail(nullptr, SMG_EINVAL, "null handle");
+  if (level < 0 || level + 1 >= h->nlev) return fail(h, SMG_EINVAL, "level %d has no coarser level", level);
+  if (!ec || !uf) return fail(h, SMG_EINVAL, "null vector");
+  const Level& v = h->lev[level];
+  if (h->cfg.prec == SMG_FP64)
+    HIPCHK(h, launch_prolong_add<double>(v.g, v.cmask, h->bs, (const double*)ec, (double*)uf, (hipStream_t)stream));
+  else
+    HIPCHK(h, launch_prolong_add<float>(v.g, v.cmask, h->bs, (const float*)ec, (float*)uf, (hipStream_t)stream));
+  return SMG_OK;
+}
+
+smg_status smg_op_coarse_solve(smg_handle h, const void* f, void* u, void* stream) {
+  if (!h || !f || !u) return fail(h, SMG_EINVAL, "null argument");
+  if (h->cfg.prec == SMG_FP64)
+    HIPCHK(h, launch_coarse_gemv<double>(h->nc, h->aug + h->nc, 2 * h->nc, (const double*)f, (double*)u,
+                                         (hipStream_t)stream));
+  else
+    HIPCHK(h, launch_coarse_gemv<float>(h->nc, h->aug + h->nc, 2 * h->nc, (const float*)f, (float*)u,
+                                        (hipStream_t)stream));
+  return SMG_OK;
+}

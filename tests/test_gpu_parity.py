@@ -1,0 +1,259 @@
+"""GPU parity tests: every kernel of the V-cycle, called through the C ABI,
+against the CPU oracle on the same seeded inputs.
+
+Bar: bit-exact for the stencil kernels (SpMV / residual, Gauss-Seidel and
+ILU sweeps, restriction, prolongation, triple product, truncation) whose
+per-element operation order is fixed; 1e-13 relative for the coarsest solve
+(explicit inverse on the GPU, LU on the CPU) and for quantities built from it.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2506_21932_amd as smg  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def T(a, dt=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dt)
+
+
+def N(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+CASES = [
+    # (shape, pattern, coarsen, semi_levels)
+    ((20, 18, 17), 7, "full", 0),
+    ((33, 17, 9), 19, "full", 0),
+    ((24, 21, 12), 27, "full", 0),
+    ((40, 36, 6), 19, "semi_xy", 0),
+    ((37, 19, 23), 7, "full", 2),
+]
+
+
+def _ids(c):
+    return f"{c[0][0]}x{c[0][1]}x{c[0][2]}-3d{c[1]}-{c[2]}{c[3]}"
+
+
+def _pair(case, smoother="gs", prec="fp64", sym=True, seed=3):
+    shape, pat, coarsen, semi = case
+    A = workloads.random_sgdia(shape, pat, seed=seed, symmetric=sym)
+    H = oracle.Hierarchy(shape, pat, A, smoother=smoother, coarsen=coarsen, semi_levels=semi, prec=prec)
+    mg = smg.StructMG(T(A), shape, pattern=pat, smoother=smoother, coarsen=coarsen, semi_levels=semi, prec=prec,
+                      device=DEV)
+    return A, H, mg
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_hierarchy_rap_bitexact(case):
+    A, H, mg = _pair(case)
+    assert mg.nlev == H.nlev
+    for l in range(H.nlev):
+        inf = mg.level_info(l)
+        ref = H.level_info(l)
+        assert inf["dims"] == ref["dims"] and inf["S"] == ref["S"] and inf["cmask"] == ref["cmask"]
+        Ar = H.level_data(l, 0)
+        got = N(mg.export(l, 0, torch.empty(Ar.shape, dtype=torch.float64, device=DEV)))
+        assert np.array_equal(got, Ar), f"level {l}: max diff {np.abs(got - Ar).max()}"
+        if l < H.nlev - 1:
+            rd = H.level_data(l, 1)
+            got = N(mg.export(l, 1, torch.empty(rd.shape, dtype=torch.float64, device=DEV)))
+            assert np.array_equal(got, rd)
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_level_kernels_bitexact(case):
+    A, H, mg = _pair(case)
+    g = workloads.rng(11)
+    for l in range(H.nlev - 1):
+        inf = H.level_info(l)
+        dims, S, cm = inf["dims"], inf["S"], inf["cmask"]
+        off = workloads.offsets(S)
+        Al, rd = H.level_data(l, 0), H.level_data(l, 1).ravel()
+        f = g.uniform(-1, 1, size=dims)
+        u = g.uniform(-1, 1, size=dims)
+        cdims = oracle.coarse_dims(dims, cm)
+        ec = g.uniform(-1, 1, size=cdims)
+        # SpMV
+        y = N(mg.op_spmv(l, T(f), torch.empty(int(np.prod(dims)), dtype=torch.float64, device=DEV)))
+        assert np.array_equal(y, oracle.spmv(off, Al, f).ravel()), f"spmv level {l}"
+        # pre-smoothing: forward GS from zero
+        ug = N(mg.op_presmooth(l, T(f), torch.empty(int(np.prod(dims)), dtype=torch.float64, device=DEV)))
+        ur = oracle.gs_sweep(off, Al, rd, f, np.zeros(dims), 1, 1)
+        assert np.array_equal(ug, ur.ravel()), f"forward GS level {l}: {np.abs(ug - ur.ravel()).max()}"
+        # residual + restriction
+        rc = N(mg.op_resid_restrict(l, T(f), T(u), torch.empty(int(np.prod(cdims)), dtype=torch.float64,
+                                                               device=DEV)))
+        rr = oracle.restrict(oracle.residual(off, Al, f, u), cm)
+        assert np.array_equal(rc, rr.ravel()), f"resid+restrict level {l}"
+        # prolongation + backward GS
+        uo = N(mg.op_postsmooth(l, T(f), T(u), T(ec), torch.empty(int(np.prod(dims)), dtype=torch.float64,
+                                                                  device=DEV)))
+        ref = oracle.gs_sweep(off, Al, rd, f, oracle.prolong_add(u, ec, cm), -1, 0)
+        assert np.array_equal(uo, ref.ravel()), f"backward GS level {l}: {np.abs(uo - ref.ravel()).max()}"
+        # plain restriction / prolongation
+        rc2 = N(mg.op_restrict(l, T(f), torch.empty(int(np.prod(cdims)), dtype=torch.float64, device=DEV)))
+        assert np.array_equal(rc2, oracle.restrict(f, cm).ravel())
+        uf = T(u.copy())
+        mg.op_prolong_add(l, T(ec), uf)
+        assert np.array_equal(N(uf), oracle.prolong_add(u, ec, cm).ravel())
+
+
+@pytest.mark.parametrize("case", CASES[:3], ids=_ids)
+def test_sweeps_deterministic(case):
+    """Repeated sweeps give identical bits (a missed dependence would not)."""
+    A, H, mg = _pair(case)
+    dims = H.level_info(0)["dims"]
+    f = T(workloads.rng(5).uniform(-1, 1, size=dims))
+    first = None
+    for _ in range(20):
+        u = mg.op_presmooth(0, f, torch.empty(int(np.prod(dims)), dtype=torch.float64, device=DEV))
+        v = N(u)
+        if first is None:
+            first = v
+        assert np.array_equal(v, first)
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_coarse_solve_and_vcycle(case):
+    A, H, mg = _pair(case)
+    L = H.nlev - 1
+    inf = H.level_info(L)
+    n = int(np.prod(inf["dims"]))
+    f = workloads.rng(2).uniform(-1, 1, size=n)
+    u = N(mg.op_coarse_solve(T(f), torch.empty(n, dtype=torch.float64, device=DEV)))
+    M = oracle.dense(workloads.offsets(27) if L > 0 else workloads.offsets(case[1]), H.level_data(L, 0),
+                     inf["dims"])
+    ref = np.linalg.solve(M, f)
+    assert np.abs(u - ref).max() <= 1e-13 * np.abs(ref).max() * max(1.0, np.linalg.cond(M) / 1e3)
+    # whole V-cycle
+    dims = H.level_info(0)["dims"]
+    r = workloads.rng(9).uniform(-1, 1, size=dims)
+    z = N(mg.precondition(T(r.ravel()), torch.empty(r.size, dtype=torch.float64, device=DEV)))
+    zr = H.apply(r).ravel()
+    assert np.abs(z - zr).max() <= 1e-12 * np.abs(zr).max()
+    # twice in a row (buffers are reused across cycles)
+    z2 = N(mg.precondition(T(r.ravel()), torch.empty(r.size, dtype=torch.float64, device=DEV)))
+    assert np.array_equal(z, z2)
+
+
+def test_poisson_32_pcg():
+    """32^3 Poisson, PCG with the V(1,1) symmetric GS cycle, tol 1e-9."""
+    A, b = workloads.poisson7(32)
+    shape = (32, 32, 32)
+    H = oracle.Hierarchy(shape, 7, A)
+    xr, st, itr, relr = H.pcg(b, 1e-9, 100)
+    mg = smg.StructMG(T(A), shape, pattern=7, device=DEV)
+    x = torch.zeros(b.size, dtype=torch.float64, device=DEV)
+    res = mg.solve(T(b.ravel()), x, rtol=1e-9, maxit=100)
+    assert res["status"] == 0 and res["rel_resid_true"] < 1e-9
+    assert abs(res["iters"] - itr) <= 1
+    xg = N(x)
+    assert np.abs(xg - xr.ravel()).max() / np.abs(xr).max() < 1e-6
+    assert res["levels"] == 4
+
+
+@pytest.mark.parametrize("case", [CASES[1], CASES[3]], ids=_ids)
+def test_ilu0_bitexact(case):
+    A, H, mg = _pair(case, smoother="ilu0", sym=False)
+    g = workloads.rng(13)
+    for l in range(H.nlev - 1):
+        inf = H.level_info(l)
+        dims, S, cm = inf["dims"], inf["S"], inf["cmask"]
+        off = workloads.offsets(S)
+        for what in (2, 3, 4):
+            ref = H.level_data(l, what)
+            got = N(mg.export(l, what, torch.empty(ref.shape, dtype=torch.float64, device=DEV)))
+            assert np.array_equal(got, ref), f"ILU factor {what} level {l}"
+        Lf, Uf, rU = H.level_data(l, 2), H.level_data(l, 3), H.level_data(l, 4).ravel()
+        Al = H.level_data(l, 0)
+        f = g.uniform(-1, 1, size=dims)
+        u = g.uniform(-1, 1, size=dims)
+        ec = g.uniform(-1, 1, size=oracle.coarse_dims(dims, cm))
+        ug = N(mg.op_presmooth(l, T(f), torch.empty(int(np.prod(dims)), dtype=torch.float64, device=DEV)))
+        ref = oracle.tri_solve(off, Uf, rU, oracle.tri_solve(off, Lf, None, f, 0), 1)
+        assert np.array_equal(ug, ref.ravel()), f"ILU solve level {l}"
+        uo = N(mg.op_postsmooth(l, T(f), T(u), T(ec), torch.empty(int(np.prod(dims)), dtype=torch.float64,
+                                                                  device=DEV)))
+        uold = oracle.prolong_add(u, ec, cm)
+        r = oracle.residual(off, Al, f, uold)
+        zc = oracle.tri_solve(off, Uf, rU, oracle.tri_solve(off, Lf, None, r, 0), 1)
+        assert np.array_equal(uo, (uold + zc).ravel()), f"ILU correction level {l}"
+
+
+def test_gmres_ilu_nonsymmetric():
+    shape = (40, 36, 10)
+    A = workloads.random_sgdia(shape, 19, seed=23, symmetric=False)
+    b = workloads.rng(4).uniform(-1, 1, size=shape)
+    H = oracle.Hierarchy(shape, 19, A, smoother="ilu0", coarsen="semi_xy")
+    xr, st, itr, relr = H.gmres(b, 1e-9, 300, restart=30)
+    mg = smg.StructMG(T(A), shape, pattern=19, smoother="ilu0", coarsen="semi_xy", gmres_restart=30, device=DEV)
+    x = torch.zeros(b.size, dtype=torch.float64, device=DEV)
+    res = mg.solve(T(b.ravel()), x, rtol=1e-9, maxit=300, krylov=30)
+    assert res["status"] == 0 and res["rel_resid_true"] < 1e-9
+    assert abs(res["iters"] - itr) <= 2
+    assert np.abs(N(x) - xr.ravel()).max() <= 1e-6 * np.abs(xr).max()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_reduced_precision_bitexact(prec):
+    case = CASES[0]
+    A, H, mg = _pair(case, prec=prec)
+    g = workloads.rng(17)
+    for l in range(H.nlev - 1):
+        inf = H.level_info(l)
+        dims, S, cm = inf["dims"], inf["S"], inf["cmask"]
+        off = workloads.offsets(S)
+        A32 = H.level_data(l, 5)
+        rd32 = H.level_data(l, 6).ravel()
+        got = N(mg.export(l, 5, torch.empty(A32.shape, dtype=torch.float32, device=DEV)))
+        assert np.array_equal(got, A32), f"{prec} matrix level {l}"
+        got = N(mg.export(l, 6, torch.empty(rd32.shape, dtype=torch.float32, device=DEV)))
+        assert np.array_equal(got, rd32)
+        f = g.uniform(-1, 1, size=dims).astype(np.float32)
+        u = g.uniform(-1, 1, size=dims).astype(np.float32)
+        ec = g.uniform(-1, 1, size=oracle.coarse_dims(dims, cm)).astype(np.float32)
+        f32 = torch.float32
+        y = N(mg.op_spmv(l, T(f, f32), torch.empty(f.size, dtype=f32, device=DEV)))
+        assert np.array_equal(y, oracle.spmv(off, A32, f).ravel())
+        ug = N(mg.op_presmooth(l, T(f, f32), torch.empty(f.size, dtype=f32, device=DEV)))
+        assert np.array_equal(ug, oracle.gs_sweep(off, A32, rd32, f, np.zeros(dims, np.float32), 1, 1).ravel())
+        uo = N(mg.op_postsmooth(l, T(f, f32), T(u, f32), T(ec, f32), torch.empty(f.size, dtype=f32, device=DEV)))
+        ref = oracle.gs_sweep(off, A32, rd32, f, oracle.prolong_add(u, ec, cm), -1, 0)
+        assert np.array_equal(uo, ref.ravel())
+        rc = N(mg.op_resid_restrict(l, T(f, f32), T(u, f32),
+                                    torch.empty(int(np.prod(oracle.coarse_dims(dims, cm))), dtype=f32, device=DEV)))
+        assert np.array_equal(rc, oracle.restrict(oracle.residual(off, A32, f, u), cm).ravel())
+    # the mixed-precision V-cycle matches the oracle's mixed-precision cycle
+    dims = H.level_info(0)["dims"]
+    r = workloads.rng(9).uniform(-1, 1, size=dims)
+    z = N(mg.precondition(T(r.ravel()), torch.empty(r.size, dtype=torch.float64, device=DEV)))
+    zr = H.apply(r).ravel()
+    assert np.abs(z - zr).max() <= 1e-5 * np.abs(zr).max()
+    # and the outer FP64 PCG reaches 1e-9
+    x = torch.zeros(r.size, dtype=torch.float64, device=DEV)
+    res = mg.solve(T(r.ravel()), x, rtol=1e-9, maxit=200)
+    assert res["status"] == 0 and res["rel_resid_true"] < 1e-9
+
+
+def test_error_paths():
+    A, b = workloads.poisson7(8)
+    with pytest.raises(smg.SmgError) as e:
+        smg.StructMG(T(A), (8, 8, 8), pattern=5, device=DEV)
+    assert e.value.status == smg.SMG_EINVAL
+    A2 = A.copy()
+    A2[3, 17] = 0.0  # zero diagonal
+    with pytest.raises(smg.SmgError) as e:
+        smg.StructMG(T(A2), (8, 8, 8), pattern=7, device=DEV)
+    assert e.value.status == smg.SMG_EBREAKDOWN
