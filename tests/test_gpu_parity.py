@@ -107,7 +107,7 @@ def test_level_kernels_bitexact(case):
         assert np.array_equal(rc2, oracle.restrict(f, cm).ravel())
         uf = T(u.copy())
         mg.op_prolong_add(l, T(ec), uf)
-        assert np.array_equal(N(uf), oracle.prolong_add(u, ec, cm).ravel())
+        assert np.array_equal(N(uf).ravel(), oracle.prolong_add(u, ec, cm).ravel())
 
 
 @pytest.mark.parametrize("case", CASES[:3], ids=_ids)
