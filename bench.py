@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Time-to-solution benchmark of the structured-AMG preconditioned CG on one
+MI355X.
+
+Workload (default): 3D variable-coefficient diffusion on a 256^3 grid,
+7-point finite-volume stencil, cell coefficients log-normal (sigma = 2) with
+32 random spherical inclusions of contrast 10^U[-3,3], harmonic-mean faces,
+seed 2, RHS uniform[-1,1]; FP64 PCG preconditioned by one V-cycle (forward GS
+before, backward GS after the coarse correction), full coarsening to 4^3,
+stencil Galerkin triple products, exact coarsest solve; stop at ||r||/||b|| <
+1e-9 (true residual).
+
+One step = the whole method on that input: hierarchy setup (triple products,
+smoother data, coarsest inverse) followed by the PCG solve, inputs resident
+in HBM.  The JSON line reports the mean step time (time-to-solution), the HBM
+roofline of the kernel with the largest share of the solve, and the CPU oracle
+timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-solution @1e-9 rel resid + V-cycle HBM GB/s; mixed/batched vs FP64"
+HBM_PEAK_GBS = 8000.0
+KIND_NAMES = ["pre_sweep", "pre_sweep_u", "resid_restrict", "coarse_solve", "prolong_post", "post_sweep",
+              "post_sweep_u", "spmv_fp64"]
+KERNEL_OF_KIND = {"pre_sweep": "k_wavefront (forward)", "pre_sweep_u": "k_wavefront (ILU upper)",
+                  "resid_restrict": "k_resid_restrict", "coarse_solve": "k_coarse_gemv",
+                  "prolong_post": "k_prolong_post", "post_sweep": "k_wavefront (backward)",
+                  "post_sweep_u": "k_wavefront (ILU upper, add)", "spmv_fp64": "k_spmv"}
+
+
+def kernel_bytes(kind, S, N, Nc, w, smoother="gs", ncoarse=0):
+    """Algorithmic HBM bytes of one launch: every stored coefficient and vector
+    entry the kernel needs is read once, every output written once."""
+    SL = S // 2
+    if kind == "pre_sweep":
+        return (SL + 3) * w * N if smoother == "gs" else (SL + 2) * w * N
+    if kind == "pre_sweep_u":
+        return (SL + 3) * w * N
+    if kind == "resid_restrict":
+        return (S + 2) * w * N + w * Nc
+    if kind == "coarse_solve":
+        return 8 * ncoarse * ncoarse + 2 * w * ncoarse
+    if kind == "prolong_post":
+        return ((SL + 3) * w * N + w * Nc) if smoother == "gs" else ((S + 4) * w * N + w * Nc)
+    if kind == "post_sweep":
+        return (SL + 3) * w * N if smoother == "gs" else (SL + 2) * w * N
+    if kind == "post_sweep_u":
+        return (SL + 5) * w * N
+    if kind == "spmv_fp64":
+        return (S + 2) * 8 * N
+    raise ValueError(kind)
+
+
+def wavefront_src_hash():
+    h = hashlib.sha256()
+    for f in ("wavefront.hip", "stencil.hip", "smg_common.h"):
+        with open(os.path.join(ROOT, "paper_2506_21932_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_key):
+    """HBM bytes per launch measured with rocprofv3 counters (profiles/), only
+    while the kernel sources are unchanged since the measurement."""
+    p = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        with open(p) as f:
+            d = json.load(f)
+        if d.get("src_hash") != wavefront_src_hash():
+            return None
+        e = d["kernels"].get(kernel_key)
+        return None if e is None else float(e["hbm_bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def make_workload(name):
+    import workloads
+    if name == "diffusion256":
+        shape = (256, 256, 256)
+        A, b = workloads.diffusion7(shape, seed=2)
+        return dict(shape=shape, A=A, b=b, pattern=7, smoother="gs", coarsen="full", semi_levels=0, krylov=0,
+                    desc="3D diffusion 256^3, 7-pt, log-normal sigma=2 + 32 inclusions, FP64 PCG + V(1,1) sym GS")
+    if name == "poisson32":
+        shape = (32, 32, 32)
+        A, b = workloads.poisson7(32)
+        return dict(shape=shape, A=A, b=b, pattern=7, smoother="gs", coarsen="full", semi_levels=0, krylov=0,
+                    desc="3D Poisson 32^3, 7-pt, FP64 PCG + V(1,1) sym GS")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(name, budget_s=30.0):
+    """The oracle (single-threaded C, as committed) on a bounded sample: the
+    same recipe at 1/8 of the unknowns (128^3 for the 256^3 workload), full
+    setup + PCG to 1e-9, scaled by the unknown-count ratio."""
+    import oracle
+    import workloads
+    if name == "diffusion256":
+        shape = (128, 128, 128)
+        A, b = workloads.diffusion7(shape, seed=2, nspheres=4, rmin=4.0, rmax=16.0)
+        scale = 8.0
+        sample = "same recipe at 128^3 (4 inclusions, radii 4-16), oracle setup + PCG to 1e-9, x8 unknowns"
+    else:
+        shape = (32, 32, 32)
+        A, b = workloads.poisson7(32)
+        scale = 1.0
+        sample = "full workload"
+    t0 = time.perf_counter()
+    H = oracle.Hierarchy(shape, 7, A)
+    x, st, it, rel = H.pcg(b, 1e-9, 200)
+    t = time.perf_counter() - t0
+    return {"value": round(t * 1e3 * scale, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": f"{sample}; measured {t:.1f}s, {it} iterations, rel resid {rel:.2e}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="diffusion256")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--breakdown", action="store_true", help="print per-kernel table to stderr")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2506_21932_amd as smg
+
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    W = make_workload(args.workload)
+    t_gen = time.perf_counter() - t_gen
+    print(f"[bench] workload {args.workload} generated in {t_gen:.1f}s", file=sys.stderr, flush=True)
+    shape = W["shape"]
+    n = int(np.prod(shape))
+    A = torch.from_numpy(W["A"]).to(dev)
+    b = torch.from_numpy(W["b"].ravel().copy()).to(dev)
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    kw = dict(pattern=W["pattern"], smoother=W["smoother"], coarsen=W["coarsen"], semi_levels=W["semi_levels"])
+    mg = smg.StructMG(A, shape, device=dev, **kw)
+    levels = [mg.level_info(l) for l in range(mg.nlev)]
+
+    # pre-run (untimed): find the kernel with the largest share of the solve
+    mg.set_timing(True)
+    x.zero_()
+    mg.solve(b, x, rtol=1e-9, maxit=300, krylov=W["krylov"])
+    rep, _ = mg.timing_report(mg.nlev)
+    dom = max(rep.items(), key=lambda kv: kv[1][0])[0]
+
+    def bytes_of(lk):
+        l, kind = lk
+        inf = levels[l]
+        N = int(np.prod(inf["dims"]))
+        Nc = int(np.prod(levels[l + 1]["dims"])) if l + 1 < len(levels) else 0
+        ncoarse = int(np.prod(levels[-1]["dims"]))
+        return kernel_bytes(kind, inf["S"], N, Nc, 8, W["smoother"], ncoarse)
+
+    ncycles = sum(c for (l, k), (ms, c) in rep.items() if l == 0 and k == "pre_sweep")
+    vc_ms = sum(ms for (l, k), (ms, c) in rep.items() if k != "spmv_fp64")
+    vc_bytes = sum(bytes_of(lk) * c for lk, (ms, c) in rep.items() if lk[1] != "spmv_fp64")
+    breakdown = {f"L{l}:{k}": {"ms_per_launch": round(ms / c, 4), "launches": c,
+                               "GBps": round(bytes_of((l, k)) / (ms / c) / 1e6, 1)}
+                 for (l, k), (ms, c) in sorted(rep.items())}
+    if args.breakdown:
+        for k, v in breakdown.items():
+            print(f"[bench] {k:24s} {v}", file=sys.stderr)
+    mg.set_timing(True, level=dom[0], kinds=[dom[1]])
+
+    for _ in range(args.warmup):
+        mg.resetup(A)
+        x.zero_()
+        mg.solve(b, x, rtol=1e-9, maxit=300, krylov=W["krylov"])
+    mg.timing_report(mg.nlev)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        mg.resetup(A)
+        x.zero_()
+        r = mg.solve(b, x, rtol=1e-9, maxit=300, krylov=W["krylov"])
+        torch.cuda.synchronize()
+        r["step_ms"] = (time.perf_counter() - ts) * 1e3
+        results.append(r)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    rep_t, _ = mg.timing_report(mg.nlev)
+    d_ms, d_cnt = rep_t[dom]
+    d_avg = d_ms / d_cnt
+    d_bytes = bytes_of(dom)
+    achieved = d_bytes / (d_avg * 1e-3) / 1e9
+    kernel_key = f"L{dom[0]}:{dom[1]}"
+    traffic = load_traffic(kernel_key)
+    ok = all(r["status"] == 0 and r["rel_resid_true"] < 1e-9 for r in results)
+    line = {
+        "metric": METRIC,
+        "value": round(ms_per_step, 2),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded)",
+        "config": {"workload": W["desc"], "grid": list(shape), "unknowns": n, "tol": 1e-9, "solver": "PCG",
+                   "levels": mg.nlev},
+        "roofline": {"bound": "hbm", "kernel": f"{KERNEL_OF_KIND[dom[1]]} level {dom[0]}",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "algorithmic_bytes_per_launch": d_bytes, "avg_launch_ms": round(d_avg, 4),
+                     "launches": d_cnt},
+        "converged": ok,
+        "iters": results[-1]["iters"],
+        "rel_resid_true": results[-1]["rel_resid_true"],
+        "t_setup_ms": round(float(np.mean([r["t_setup_ms"] for r in results])), 2),
+        "t_solve_ms": round(float(np.mean([r["t_solve_ms"] for r in results])), 2),
+        "vcycle": {"ms": round(vc_ms / max(ncycles, 1), 4), "algorithmic_GBps": round(vc_bytes / vc_ms / 1e6, 1)},
+        "complexity": {"grid": round(results[-1]["grid_complexity"], 4),
+                       "operator": round(results[-1]["op_complexity"], 4)},
+        "kernels": breakdown,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

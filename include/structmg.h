@@ -93,6 +93,12 @@ smg_status smg_workspace_size(const smg_config* cfg, size_t* bytes);
 smg_status smg_setup(const smg_config* cfg, const double* coeffs, void* workspace, size_t bytes, void* stream,
                      smg_handle* out);
 
+/* Rebuilds the hierarchy of an existing handle for new finest-level
+ * coefficients with the same grid, pattern and settings (same workspace).
+ * Synchronises `stream`.  A failure leaves the handle unusable until the next
+ * successful smg_resetup. */
+smg_status smg_resetup(smg_handle h, const double* coeffs, void* stream);
+
 /* z = M^-1 r: one V-cycle (device FP64 vectors of N*block entries; r and z
  * must not overlap).  Asynchronous on `stream`. */
 smg_status smg_precondition(smg_handle h, const double* r, double* z, void* stream);
@@ -148,6 +154,20 @@ smg_status smg_op_restrict(smg_handle h, int level, const void* rf, void* rc, vo
 smg_status smg_op_prolong_add(smg_handle h, int level, const void* ec, void* uf, void* stream);
 /* u = A_L^-1 f on the coarsest level (FP64 inverse). */
 smg_status smg_op_coarse_solve(smg_handle h, const void* f, void* u, void* stream);
+
+/* ---- kernel timing (profiling aid) --------------------------------------
+ * When enabled, each kernel of the V-cycle and the outer FP64 SpMV on the
+ * selected level and of the selected kinds (bit k of `kinds` for kind k) is
+ * bracketed by HIP events on its launch stream (at most 16384 launches are
+ * recorded between reports).  smg_timing_report synchronises on the events,
+ * then fills ms[level*8 + kind] (milliseconds summed over launches) and
+ * counts[...] (number of launches) for levels < max_levels, and clears the
+ * record.  Kinds: 0 pre-smoothing sweep (GS forward / ILU lower), 1 ILU upper
+ * pre-smoothing sweep, 2 residual + restriction, 3 coarsest solve,
+ * 4 prolongation + post-smoother input, 5 post-smoothing sweep (GS backward /
+ * ILU lower), 6 ILU upper post-smoothing sweep, 7 outer FP64 SpMV. */
+smg_status smg_set_timing(smg_handle h, int enable, int level /* -1: all */, unsigned kinds /* bit mask */);
+smg_status smg_timing_report(smg_handle h, double* ms, int* counts, int max_levels, int* dropped);
 
 #ifdef __cplusplus
 }

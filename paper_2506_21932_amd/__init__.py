@@ -41,7 +41,10 @@ class Result(C.Structure):
 EXPORTS = ["smg_workspace_size", "smg_setup", "smg_precondition", "smg_solve", "smg_destroy", "smg_last_error",
            "smg_level_info", "smg_num_levels", "smg_level_export", "smg_rap_chain_count", "smg_op_spmv",
            "smg_op_spmv_fp64", "smg_op_presmooth", "smg_op_postsmooth", "smg_op_resid_restrict", "smg_op_restrict",
-           "smg_op_prolong_add", "smg_op_coarse_solve"]
+           "smg_op_prolong_add", "smg_op_coarse_solve", "smg_set_timing", "smg_timing_report", "smg_resetup"]
+
+TIMING_KINDS = ["pre_sweep", "pre_sweep_u", "resid_restrict", "coarse_solve", "prolong_post", "post_sweep",
+                "post_sweep_u", "spmv_fp64"]
 
 _lib = None
 
@@ -76,6 +79,9 @@ def load():
     L.smg_op_restrict.argtypes = [vp, i, vp, vp, vp]
     L.smg_op_prolong_add.argtypes = [vp, i, vp, vp, vp]
     L.smg_op_coarse_solve.argtypes = [vp, vp, vp, vp]
+    L.smg_set_timing.argtypes = [vp, i, i, C.c_uint]
+    L.smg_resetup.argtypes = [vp, vp, vp]
+    L.smg_timing_report.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int), i, C.POINTER(C.c_int)]
     for name in EXPORTS:
         if name not in ("smg_last_error", "smg_num_levels", "smg_rap_chain_count"):
             getattr(L, name).restype = i
@@ -107,7 +113,7 @@ class StructMG:
     """Owns a libstructmg handle and its workspace (a torch uint8 tensor)."""
 
     def __init__(self, coeffs, shape, pattern=7, block=1, smoother="gs", coarsen="full", semi_levels=0, prec="fp64",
-                 max_coarse=0, gmres_restart=0, device="cuda"):
+                 max_coarse=0, gmres_restart=0, device="cuda", workspace=None):
         import torch
         L = load()
         self.L = L
@@ -116,7 +122,10 @@ class StructMG:
         self.prec = prec
         nbytes = C.c_size_t(0)
         self._check(L.smg_workspace_size(C.byref(self.cfg), C.byref(nbytes)), None)
-        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
+        if workspace is not None and workspace.numel() >= nbytes.value:
+            self.workspace = workspace
+        else:
+            self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
         coeffs = coeffs.to(device=device, dtype=torch.float64).contiguous()
         h = C.c_void_p()
         self._check(L.smg_setup(C.byref(self.cfg), _ptr(coeffs), _ptr(self.workspace), nbytes, _stream(),
@@ -195,6 +204,35 @@ class StructMG:
     def op_prolong_add(self, l, ec, uf):
         self._check(self.L.smg_op_prolong_add(self.h, int(l), _ptr(ec), _ptr(uf), _stream()), self.h)
         return uf
+
+    def set_timing(self, enable, level=-1, kinds=None):
+        mask = 0xFF if kinds is None else sum(1 << TIMING_KINDS.index(k) for k in kinds)
+        self._check(self.L.smg_set_timing(self.h, int(bool(enable)), int(level), mask), self.h)
+
+    def resetup(self, coeffs):
+        self._check(self.L.smg_resetup(self.h, _ptr(coeffs), _stream()), self.h)
+
+    def timing_report(self, max_levels=40):
+        """{(level, kind): (ms, launches)} of the launches recorded since the last report."""
+        n = max_levels * len(TIMING_KINDS)
+        ms = (C.c_double * n)()
+        cnt = (C.c_int * n)()
+        dropped = C.c_int(0)
+        self._check(self.L.smg_timing_report(self.h, ms, cnt, int(max_levels), C.byref(dropped)), self.h)
+        out = {}
+        for k in range(n):
+            if cnt[k]:
+                out[(k // len(TIMING_KINDS), TIMING_KINDS[k % len(TIMING_KINDS)])] = (ms[k], cnt[k])
+        return out, bool(dropped.value)
+
+    @staticmethod
+    def workspace_bytes(shape, **kw):
+        cfg = make_config(shape, **kw)
+        n = C.c_size_t(0)
+        st = load().smg_workspace_size(C.byref(cfg), C.byref(n))
+        if st != SMG_OK:
+            raise SmgError(st, load().smg_last_error(None).decode())
+        return int(n.value)
 
     def op_coarse_solve(self, f, u):
         self._check(self.L.smg_op_coarse_solve(self.h, _ptr(f), _ptr(u), _stream()), self.h)

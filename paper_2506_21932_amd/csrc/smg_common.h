@@ -95,6 +95,40 @@ struct MatH {
   __device__ float operator()(int s, long i) const { return sc[i] * __half2float(a[(long)s * n + i]); }
 };
 
+// Sweep data stored in wavefront schedule order (see wavefront.hip): slot s
+// of the pattern at sk[s*stride + q] for schedule position q; the centre slot
+// holds the diagonal scaling of the sweep (1/a_ii, or 1/U_ii for ILU).
+struct SkD {
+  const double* a;
+  long stride;
+  using V = double;
+  __device__ double operator()(int s, long q) const { return a[(long)s * stride + q]; }
+};
+struct SkF {
+  const float* a;
+  long stride;
+  using V = float;
+  __device__ float operator()(int s, long q) const { return a[(long)s * stride + q]; }
+};
+struct SkH {
+  const __half* a;
+  const float* sc;
+  const float* dg;
+  long stride;
+  int centre;
+  using V = float;
+  __device__ float operator()(int s, long q) const {
+    return s == centre ? dg[q] : sc[q] * __half2float(a[(long)s * stride + q]);
+  }
+};
+
+constexpr int WF_TX = 16, WF_TY = 16;  // columns per wavefront tile (256 lanes)
+
+struct WfTiling {
+  int sh, ntx, nty, ns;  // shear, tiles in x / y, steps per tile
+  long nsk;              // schedule-ordered entries per slot (tiles * steps * lanes)
+};
+
 struct Grid {
   int nx, ny, nz;
   __host__ __device__ long N() const { return (long)nx * ny * nz; }

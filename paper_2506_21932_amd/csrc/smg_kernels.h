@@ -8,23 +8,28 @@ namespace smg {
 template <class V>
 struct WfArgs {
   Grid g;
-  int sh, ntx, nty;          // tiling (see wf_tiling)
+  WfTiling t;                // tiling of the level (wf_tiling)
   const V* h;                // right-hand side of the triangular system
-  const V* d;                // diagonal scaling (unused for a unit diagonal)
   V* x;                      // output; positions read by other tiles hold the sentinel
   V* next;                   // output buffer of the next sweep on this level (sentinel prefill), or null
-  int next_dir, next_sh;     // direction / shear of that next sweep
+  int next_dir;              // direction of that next sweep
   const V* addv;             // optional: addout = addv + x
   V* addout;
   unsigned* ctr;             // [0] ticket counter, [1] exit counter; zero between launches
   unsigned* err;             // watchdog flag (bit 0)
+  V* dump;                   // 4 * 256 elements of scratch for stores of inactive lanes
 };
 
-void wf_tiling(const Grid& g, int* sh, int* ntx, int* nty);
+void wf_tiling(const Grid& g, int pat, WfTiling* t);
 
-template <class M>
-hipError_t launch_wavefront(int pat, int dir, bool unitd, bool add, const WfArgs<typename M::V>& a, const M& m,
+template <class SK>
+hipError_t launch_wavefront(int pat, int dir, bool unitd, bool add, const WfArgs<typename SK::V>& a, const SK& m,
                             hipStream_t st);
+template <class T>
+hipError_t launch_skew_pack(int pat, const Grid& g, const WfTiling& tl, const double* lo, const double* dg,
+                            const double* up, T* out, hipStream_t st);
+hipError_t launch_skew_pack_h(int pat, const Grid& g, const WfTiling& tl, const __half* a16, const float* sc,
+                              const float* rd, __half* o16, float* osc, float* ord, hipStream_t st);
 
 // ---- parallel stencil kernels (stencil.hip) ----------------------------
 // y = A x   (res = false)   or   y = b - A x   (res = true)

@@ -20,6 +20,9 @@
 
 using namespace smg;
 
+#define SMG_TIMING_CAP 16384
+#define SMG_TIMING_KINDS 8
+
 namespace {
 
 constexpr int MAXLEV = 40;
@@ -35,7 +38,10 @@ struct Level {
   float* sc16 = nullptr;
   void *f = nullptr, *ua = nullptr, *ub = nullptr, *h = nullptr;
   void *y1 = nullptr, *y2 = nullptr, *zz = nullptr, *uo = nullptr;
-  int sh = 0, ntx = 0, nty = 0;
+  WfTiling tl{};          // wavefront tiling
+  void* sk = nullptr;     // sweep data in schedule order (V-cycle precision; FP16: halves)
+  float* sksc = nullptr;  // FP16: row scales in schedule order
+  float* skdg = nullptr;  // FP16: diagonal scaling in schedule order
 };
 
 }  // namespace
@@ -49,14 +55,41 @@ struct smg_handle_s {
   unsigned* err = nullptr;
   int* info = nullptr;
   double *dpart = nullptr, *dout = nullptr;
+  double* dump = nullptr;  // wavefront scratch (4 * 256 doubles)
   double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr, *kt = nullptr, *kw = nullptr;
   double* kV = nullptr;
   int kV_m = 0;
   double t_setup_ms = 0.0;
   char msg[512] = {0};
+  // kernel timing (profiling aid): event pairs per (level, kind)
+  bool timing = false;
+  int tm_level = -1;      // record only this level (-1: all)
+  unsigned tm_kinds = ~0u;  // bit mask of recorded kinds
+  int ev_used = 0;
+  int ev_tag[SMG_TIMING_CAP];
+  hipEvent_t ev0[SMG_TIMING_CAP], ev1[SMG_TIMING_CAP];
 };
 
 static char g_setup_msg[512] = "no error";
+
+// Brackets the launches of one (level, kind) with events on `st` when timing
+// is enabled.
+struct Timed {
+  smg_handle_s* H;
+  int slot;
+  hipStream_t st;
+  Timed(smg_handle_s* h, int level, int kind, hipStream_t s) : H(h), slot(-1), st(s) {
+    if (H->timing && H->ev_used < SMG_TIMING_CAP && (H->tm_level < 0 || H->tm_level == level) &&
+        ((H->tm_kinds >> kind) & 1u)) {
+      slot = H->ev_used++;
+      H->ev_tag[slot] = level * SMG_TIMING_KINDS + kind;
+      (void)hipEventRecord(H->ev0[slot], st);
+    }
+  }
+  ~Timed() {
+    if (slot >= 0) (void)hipEventRecord(H->ev1[slot], st);
+  }
+};
 
 static smg_status fail(smg_handle h, smg_status st, const char* fmt, ...) {
   char* dst = h ? h->msg : g_setup_msg;
@@ -161,6 +194,16 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
       vec(&v.zz);
       vec(&v.uo);
     }
+    wf_tiling(v.g, v.S, &v.tl);
+    if (bs == 1) {
+      if (cfg.prec == SMG_FP16_ROWSCALE) {
+        v.sk = ar.take<__half>((size_t)v.S * v.tl.nsk);
+        v.sksc = ar.take<float>((size_t)v.tl.nsk);
+        v.skdg = ar.take<float>((size_t)v.tl.nsk);
+      } else {
+        v.sk = ar.take<char>((size_t)v.S * v.tl.nsk * vsz);
+      }
+    }
     if (cfg.prec == SMG_FP32) {
       v.A32 = ar.take<float>((size_t)v.S * be * N);
       v.rd32 = ar.take<float>((size_t)(bs == 3 ? 9 : 1) * N);
@@ -181,6 +224,7 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
   int* info = ar.take<int>(64);
   double* dpart = ar.take<double>(DOT_BLOCKS);
   double* dout = ar.take<double>(64);
+  double* dump = ar.take<double>(1024);
   const long n0 = L[0].N * bs;
   double* kr = ar.take<double>(n0);
   double* kz = ar.take<double>(n0);
@@ -196,6 +240,7 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
     H->info = info;
     H->dpart = dpart;
     H->dout = dout;
+    H->dump = dump;
     H->kr = kr;
     H->kz = kz;
     H->kp = kp;
@@ -213,6 +258,8 @@ struct P64 {
   using V = double;
   using M = MatD;
   using MF = MatD;
+  using SK = SkD;
+  static SK sk(const Level& l) { return SkD{(const double*)l.sk, l.tl.nsk}; }
   static M A(const Level& l) { return MatD{l.A64, l.N}; }
   static MF Lf(const Level& l) { return MatD{l.L64, l.N}; }
   static MF Uf(const Level& l) { return MatD{l.U64, l.N}; }
@@ -223,6 +270,8 @@ struct P32 {
   using V = float;
   using M = MatF;
   using MF = MatF;
+  using SK = SkF;
+  static SK sk(const Level& l) { return SkF{(const float*)l.sk, l.tl.nsk}; }
   static M A(const Level& l) { return MatF{l.A32, l.N}; }
   static MF Lf(const Level& l) { return MatF{l.L32, l.N}; }
   static MF Uf(const Level& l) { return MatF{l.U32, l.N}; }
@@ -233,6 +282,8 @@ struct P16 {
   using V = float;
   using M = MatH;
   using MF = MatF;
+  using SK = SkH;
+  static SK sk(const Level& l) { return SkH{(const __half*)l.sk, l.sksc, l.skdg, l.tl.nsk, l.S / 2}; }
   static M A(const Level& l) { return MatH{l.A16, l.sc16, l.N}; }
   static MF Lf(const Level& l) { return MatF{l.L32, l.N}; }
   static MF Uf(const Level& l) { return MatF{l.U32, l.N}; }
@@ -240,25 +291,22 @@ struct P16 {
   static const V* rU(const Level& l) { return l.rU32; }
 };
 
-template <class V, class M>
-hipError_t sweep(smg_handle_s* H, const Level& L, int dir, bool unitd, const M& m, const V* hin, const V* d, V* x,
-                 V* next, int next_dir, const V* addv, V* addout, hipStream_t st) {
+template <class V, class SK>
+hipError_t sweep(smg_handle_s* H, const Level& L, int dir, bool unitd, const SK& sk, const V* hin, V* x, V* next,
+                 int next_dir, const V* addv, V* addout, hipStream_t st) {
   WfArgs<V> a{};
   a.g = L.g;
-  a.sh = L.sh;
-  a.ntx = L.ntx;
-  a.nty = L.nty;
+  a.t = L.tl;
   a.h = hin;
-  a.d = d;
   a.x = x;
   a.next = next;
   a.next_dir = next_dir;
-  a.next_sh = L.sh;
   a.addv = addv;
   a.addout = addout;
   a.ctr = H->ctr;
   a.err = H->err;
-  return launch_wavefront<M>(L.S, dir, unitd, addout != nullptr, a, m, st);
+  a.dump = reinterpret_cast<V*>(H->dump);
+  return launch_wavefront<SK>(L.S, dir, unitd, addout != nullptr, a, sk, st);
 }
 
 // One V-cycle on internal or caller vectors: f0 = level-0 right-hand side,
@@ -276,35 +324,55 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
     const Level& v = H->lev[l];
     const auto A = PT::A(v);
     if (!ilu) {
-      e = sweep<V>(H, v, +1, false, A, F(l), PT::rd(v), (V*)v.ua, UB(l), -1, nullptr, nullptr, st);
+      Timed t(H, l, 0, st);
+      e = sweep<V>(H, v, +1, false, PT::sk(v), F(l), (V*)v.ua, UB(l), -1, nullptr, nullptr, st);
     } else {
-      e = sweep<V>(H, v, +1, true, PT::Lf(v), F(l), nullptr, (V*)v.y1, (V*)v.ua, -1, nullptr, nullptr, st);
+      {
+        Timed t(H, l, 0, st);
+        e = sweep<V>(H, v, +1, true, PT::sk(v), F(l), (V*)v.y1, (V*)v.ua, -1, nullptr, nullptr, st);
+      }
       if (e != hipSuccess) return e;
-      e = sweep<V>(H, v, -1, false, PT::Uf(v), (const V*)v.y1, PT::rU(v), (V*)v.ua, (V*)v.y2, +1, nullptr, nullptr,
-                   st);
+      Timed t(H, l, 1, st);
+      e = sweep<V>(H, v, -1, false, PT::sk(v), (const V*)v.y1, (V*)v.ua, (V*)v.y2, +1, nullptr, nullptr, st);
     }
     if (e != hipSuccess) return e;
-    e = launch_resid_restrict(v.S, v.g, v.cmask, A, F(l), (const V*)v.ua, (V*)H->lev[l + 1].f, st);
+    {
+      Timed t(H, l, 2, st);
+      e = launch_resid_restrict(v.S, v.g, v.cmask, A, F(l), (const V*)v.ua, (V*)H->lev[l + 1].f, st);
+    }
     if (e != hipSuccess) return e;
   }
-  e = launch_coarse_gemv<V>(H->nc, H->aug + H->nc, 2 * H->nc, F(NL - 1), UB(NL - 1), st);
+  {
+    Timed t(H, NL - 1, 3, st);
+    e = launch_coarse_gemv<V>(H->nc, H->aug + H->nc, 2 * H->nc, F(NL - 1), UB(NL - 1), st);
+  }
   if (e != hipSuccess) return e;
   for (int l = NL - 2; l >= 0; --l) {
     const Level& v = H->lev[l];
     const auto A = PT::A(v);
     if (!ilu) {
-      e = launch_prolong_post(v.S, v.g, v.cmask, A, F(l), (const V*)v.ua, (const V*)UB(l + 1), (V*)v.h, (V*)nullptr,
-                              false, st);
+      {
+        Timed t(H, l, 4, st);
+        e = launch_prolong_post(v.S, v.g, v.cmask, A, F(l), (const V*)v.ua, (const V*)UB(l + 1), (V*)v.h,
+                                (V*)nullptr, false, st);
+      }
       if (e != hipSuccess) return e;
-      e = sweep<V>(H, v, -1, false, A, (const V*)v.h, PT::rd(v), UB(l), (V*)v.ua, +1, nullptr, nullptr, st);
+      Timed t(H, l, 5, st);
+      e = sweep<V>(H, v, -1, false, PT::sk(v), (const V*)v.h, UB(l), (V*)v.ua, +1, nullptr, nullptr, st);
     } else {
-      e = launch_prolong_post(v.S, v.g, v.cmask, A, F(l), (const V*)v.ua, (const V*)UB(l + 1), (V*)v.h, (V*)v.uo,
-                              true, st);
+      {
+        Timed t(H, l, 4, st);
+        e = launch_prolong_post(v.S, v.g, v.cmask, A, F(l), (const V*)v.ua, (const V*)UB(l + 1), (V*)v.h,
+                                (V*)v.uo, true, st);
+      }
       if (e != hipSuccess) return e;
-      e = sweep<V>(H, v, +1, true, PT::Lf(v), (const V*)v.h, nullptr, (V*)v.y2, (V*)v.zz, -1, nullptr, nullptr, st);
+      {
+        Timed t(H, l, 5, st);
+        e = sweep<V>(H, v, +1, true, PT::sk(v), (const V*)v.h, (V*)v.y2, (V*)v.zz, -1, nullptr, nullptr, st);
+      }
       if (e != hipSuccess) return e;
-      e = sweep<V>(H, v, -1, false, PT::Uf(v), (const V*)v.y2, PT::rU(v), (V*)v.zz, (V*)v.y1, +1, (const V*)v.uo,
-                   UB(l), st);
+      Timed t(H, l, 6, st);
+      e = sweep<V>(H, v, -1, false, PT::sk(v), (const V*)v.y2, (V*)v.zz, (V*)v.y1, +1, (const V*)v.uo, UB(l), st);
     }
     if (e != hipSuccess) return e;
   }
@@ -334,6 +402,7 @@ hipError_t vcycle(smg_handle_s* H, const double* r, double* z, hipStream_t st) {
 
 hipError_t spmv64(smg_handle_s* H, const double* x, const double* b, double* y, bool res, hipStream_t st) {
   const Level& l0 = H->lev[0];
+  Timed t(H, 0, 7, st);
   return launch_spmv(l0.S, l0.g, MatD{l0.A64, l0.N}, x, b, y, res, st);
 }
 
@@ -354,6 +423,99 @@ double dot(smg_handle_s* H, const double* x, const double* y, long n, hipStream_
   if (*e != hipSuccess) return 0.0;
   *e = hipStreamSynchronize(st);
   return v;
+}
+
+
+// Setup pipeline on an already planned handle (used by smg_setup and
+// smg_resetup): level-0 copy, triple products, smoother data, truncation,
+// sentinel fills, coarsest inverse.
+smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st) {
+  const smg_config* cfg = &H->cfg;
+  const int bs = H->bs, be = bs * bs;
+#define SCHK(expr)                                                                            \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(H, SMG_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+  SCHK(launch_fill_bits<unsigned>(H->ctr, 64, 0u, st));
+  SCHK(launch_fill_bits<unsigned>(H->err, 64, 0u, st));
+  SCHK(launch_fill_bits<unsigned>((unsigned*)H->info, 64, 0u, st));
+  // level 0 copy (Dirichlet couplings zeroed), coarse operators by RAP
+  SCHK(launch_copy_masked(H->lev[0].S, H->lev[0].g, be, coeffs, H->lev[0].A64, st));
+  for (int l = 0; l + 1 < H->nlev; ++l) {
+    const Level& f = H->lev[l];
+    Level& c = H->lev[l + 1];
+    for (int e = 0; e < be; ++e)
+      SCHK(launch_rap(f.S, f.cmask, f.g, f.A64 + (long)e * f.N, (long)be * f.N, c.A64 + (long)e * c.N,
+                      (long)be * c.N, st));
+  }
+  // smoother data, truncation, wavefront tiling and sentinel fills
+  for (int l = 0; l + 1 < H->nlev; ++l) {
+    Level& v = H->lev[l];
+    if (bs == 3)
+      SCHK(launch_block_dinv(v.g, v.A64, v.rd64, H->err, st));
+    else
+      SCHK(launch_recip_diag(v.S, v.g, v.A64, v.rd64, H->err, st));
+    if (cfg->smoother == SMG_SMOOTH_ILU0) SCHK(launch_ilu0_factor(v.S, v.g, v.A64, v.L64, v.U64, v.rU64, H->err, st));
+    const long na = (long)v.S * be * v.N;
+    if (cfg->prec == SMG_FP32) {
+      SCHK(launch_to_f32(v.A64, v.A32, na, st));
+      SCHK(launch_to_f32(v.rd64, v.rd32, (bs == 3 ? 9 : 1) * v.N, st));
+      if (cfg->smoother == SMG_SMOOTH_ILU0) {
+        SCHK(launch_to_f32(v.L64, v.L32, (long)v.S * v.N, st));
+        SCHK(launch_to_f32(v.U64, v.U32, (long)v.S * v.N, st));
+        SCHK(launch_to_f32(v.rU64, v.rU32, v.N, st));
+      }
+    } else if (cfg->prec == SMG_FP16_ROWSCALE) {
+      SCHK(launch_to_f16_rowscale(v.A64, v.N, v.S, bs, v.A16, v.sc16, st));
+      SCHK(launch_to_f32(v.rd64, v.rd32, (bs == 3 ? 9 : 1) * v.N, st));
+    }
+    // sweep data in wavefront schedule order
+    if (bs == 1) {
+      const bool ilu = cfg->smoother == SMG_SMOOTH_ILU0;
+      const double* lo = ilu ? v.L64 : v.A64;
+      const double* up = ilu ? v.U64 : v.A64;
+      const double* dg = ilu ? v.rU64 : v.rd64;
+      if (cfg->prec == SMG_FP64)
+        SCHK(launch_skew_pack<double>(v.S, v.g, v.tl, lo, dg, up, (double*)v.sk, st));
+      else if (cfg->prec == SMG_FP32)
+        SCHK(launch_skew_pack<float>(v.S, v.g, v.tl, lo, dg, up, (float*)v.sk, st));
+      else
+        SCHK(launch_skew_pack_h(v.S, v.g, v.tl, v.A16, v.sc16, v.rd32, (__half*)v.sk, v.sksc, v.skdg, st));
+    }
+    const long nv = v.N * bs;
+    void* bufs[] = {v.ua, v.ub, v.y1, v.y2, v.zz};
+    for (void* p : bufs) {
+      if (!p) continue;
+      if (cfg->prec == SMG_FP64) {
+        double s;
+        uint64_t b = SENT64;
+        memcpy(&s, &b, 8);
+        SCHK(launch_fill_bits<double>((double*)p, nv, s, st));
+      } else {
+        float s;
+        uint32_t b = SENT32;
+        memcpy(&s, &b, 4);
+        SCHK(launch_fill_bits<float>((float*)p, nv, s, st));
+      }
+    }
+  }
+  // coarsest: dense FP64 inverse
+  {
+    const Level& c = H->lev[H->nlev - 1];
+    SCHK(launch_aug_init(H->nc, H->aug, st));
+    SCHK(launch_dense_assemble(c.g, bs, c.A64, H->aug, 2 * H->nc, st));
+    SCHK(coarse_invert(H->nc, H->aug, H->info, st));
+  }
+  SCHK(hipStreamSynchronize(st));
+  unsigned errv = 0;
+  int infov = 0;
+  SCHK(hipMemcpy(&errv, H->err, sizeof errv, hipMemcpyDeviceToHost));
+  SCHK(hipMemcpy(&infov, H->info, sizeof infov, hipMemcpyDeviceToHost));
+  if (errv & 2u) return fail(H, SMG_EBREAKDOWN, "zero diagonal or zero ILU pivot during setup");
+  if (infov) return fail(H, SMG_EBREAKDOWN, "singular coarsest operator");
+#undef SCHK
+  return SMG_OK;
 }
 
 }  // namespace
@@ -389,7 +551,6 @@ smg_status smg_setup(const smg_config* cfg, const double* coeffs, void* workspac
   H->bs = cfg->block;
   char* base = (char*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
   plan(*cfg, H, base, &H->nlev, &H->nc);
-  const int bs = H->bs, be = bs * bs;
   auto bail = [&](smg_status s) {
     if (s != SMG_OK) {
       snprintf(g_setup_msg, sizeof g_setup_msg, "%s", H->msg);
@@ -397,79 +558,22 @@ smg_status smg_setup(const smg_config* cfg, const double* coeffs, void* workspac
     }
     return s;
   };
-#define SCHK(expr)                                                                               \
-  do {                                                                                           \
-    hipError_t e_ = (expr);                                                                      \
-    if (e_ != hipSuccess) return bail(fail(H, SMG_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_))); \
-  } while (0)
-  SCHK(launch_fill_bits<unsigned>(H->ctr, 64, 0u, st));
-  SCHK(launch_fill_bits<unsigned>(H->err, 64, 0u, st));
-  SCHK(launch_fill_bits<unsigned>((unsigned*)H->info, 64, 0u, st));
-  // level 0 copy (Dirichlet couplings zeroed), coarse operators by RAP
-  SCHK(launch_copy_masked(H->lev[0].S, H->lev[0].g, be, coeffs, H->lev[0].A64, st));
-  for (int l = 0; l + 1 < H->nlev; ++l) {
-    const Level& f = H->lev[l];
-    Level& c = H->lev[l + 1];
-    for (int e = 0; e < be; ++e)
-      SCHK(launch_rap(f.S, f.cmask, f.g, f.A64 + (long)e * f.N, (long)be * f.N, c.A64 + (long)e * c.N,
-                      (long)be * c.N, st));
-  }
-  // smoother data, truncation, wavefront tiling and sentinel fills
-  for (int l = 0; l + 1 < H->nlev; ++l) {
-    Level& v = H->lev[l];
-    if (bs == 3)
-      SCHK(launch_block_dinv(v.g, v.A64, v.rd64, H->err, st));
-    else
-      SCHK(launch_recip_diag(v.S, v.g, v.A64, v.rd64, H->err, st));
-    if (cfg->smoother == SMG_SMOOTH_ILU0) SCHK(launch_ilu0_factor(v.S, v.g, v.A64, v.L64, v.U64, v.rU64, H->err, st));
-    const long na = (long)v.S * be * v.N;
-    if (cfg->prec == SMG_FP32) {
-      SCHK(launch_to_f32(v.A64, v.A32, na, st));
-      SCHK(launch_to_f32(v.rd64, v.rd32, (bs == 3 ? 9 : 1) * v.N, st));
-      if (cfg->smoother == SMG_SMOOTH_ILU0) {
-        SCHK(launch_to_f32(v.L64, v.L32, (long)v.S * v.N, st));
-        SCHK(launch_to_f32(v.U64, v.U32, (long)v.S * v.N, st));
-        SCHK(launch_to_f32(v.rU64, v.rU32, v.N, st));
-      }
-    } else if (cfg->prec == SMG_FP16_ROWSCALE) {
-      SCHK(launch_to_f16_rowscale(v.A64, v.N, v.S, bs, v.A16, v.sc16, st));
-      SCHK(launch_to_f32(v.rd64, v.rd32, (bs == 3 ? 9 : 1) * v.N, st));
-    }
-    wf_tiling(v.g, &v.sh, &v.ntx, &v.nty);
-    const long nv = v.N * bs;
-    void* bufs[] = {v.ua, v.ub, v.y1, v.y2, v.zz};
-    for (void* p : bufs) {
-      if (!p) continue;
-      if (cfg->prec == SMG_FP64) {
-        double s;
-        uint64_t b = SENT64;
-        memcpy(&s, &b, 8);
-        SCHK(launch_fill_bits<double>((double*)p, nv, s, st));
-      } else {
-        float s;
-        uint32_t b = SENT32;
-        memcpy(&s, &b, 4);
-        SCHK(launch_fill_bits<float>((float*)p, nv, s, st));
-      }
-    }
-  }
-  // coarsest: dense FP64 inverse
   {
-    const Level& c = H->lev[H->nlev - 1];
-    SCHK(launch_aug_init(H->nc, H->aug, st));
-    SCHK(launch_dense_assemble(c.g, bs, c.A64, H->aug, 2 * H->nc, st));
-    SCHK(coarse_invert(H->nc, H->aug, H->info, st));
+    smg_status bs_ = build_hierarchy(H, coeffs, st);
+    if (bs_ != SMG_OK) return bail(bs_);
   }
-  SCHK(hipStreamSynchronize(st));
-  unsigned errv = 0;
-  int infov = 0;
-  SCHK(hipMemcpy(&errv, H->err, sizeof errv, hipMemcpyDeviceToHost));
-  SCHK(hipMemcpy(&infov, H->info, sizeof infov, hipMemcpyDeviceToHost));
-  if (errv & 2u) return bail(fail(H, SMG_EBREAKDOWN, "zero diagonal or zero ILU pivot during setup"));
-  if (infov) return bail(fail(H, SMG_EBREAKDOWN, "singular coarsest operator"));
-#undef SCHK
   H->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = H;
+  return SMG_OK;
+}
+
+smg_status smg_resetup(smg_handle h, const double* coeffs, void* stream) {
+  if (!h) return fail(nullptr, SMG_EINVAL, "null handle");
+  if (!coeffs) return fail(h, SMG_EINVAL, "null coefficient pointer");
+  auto t0 = std::chrono::steady_clock::now();
+  smg_status s = build_hierarchy(h, coeffs, (hipStream_t)stream);
+  if (s != SMG_OK) return s;
+  h->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return SMG_OK;
 }
 
@@ -637,7 +741,10 @@ smg_status smg_solve(smg_handle H, const double* b, double* x, double rtol, int 
   return status;
 }
 
+smg_status smg_set_timing(smg_handle h, int enable, int level, unsigned kinds);
+
 smg_status smg_destroy(smg_handle h) {
+  if (h && h->timing) smg_set_timing(h, 0, -1, 0);
   delete h;
   return SMG_OK;
 }
@@ -724,15 +831,15 @@ static hipError_t op_presmooth_t(smg_handle_s* H, const Level& v, const void* f,
   if (H->cfg.smoother == SMG_SMOOTH_GS) {
     e = launch_fill_bits<V>((V*)u, nv, sent, st);
     if (e == hipSuccess)
-      e = sweep<V>(H, v, +1, false, PT::A(v), (const V*)f, PT::rd(v), (V*)u, nullptr, 0, nullptr, nullptr, st);
+      e = sweep<V>(H, v, +1, false, PT::sk(v), (const V*)f, (V*)u, nullptr, 0, nullptr, nullptr, st);
     return e;
   }
   e = launch_fill_bits<V>((V*)v.h, nv, sent, st);
   if (e == hipSuccess) e = launch_fill_bits<V>((V*)u, nv, sent, st);
   if (e == hipSuccess)
-    e = sweep<V>(H, v, +1, true, PT::Lf(v), (const V*)f, nullptr, (V*)v.h, nullptr, 0, nullptr, nullptr, st);
+    e = sweep<V>(H, v, +1, true, PT::sk(v), (const V*)f, (V*)v.h, nullptr, 0, nullptr, nullptr, st);
   if (e == hipSuccess)
-    e = sweep<V>(H, v, -1, false, PT::Uf(v), (const V*)v.h, PT::rU(v), (V*)u, nullptr, 0, nullptr, nullptr, st);
+    e = sweep<V>(H, v, -1, false, PT::sk(v), (const V*)v.h, (V*)u, nullptr, 0, nullptr, nullptr, st);
   return e;
 }
 
@@ -756,7 +863,7 @@ static hipError_t op_postsmooth_t(smg_handle_s* H, const Level& v, const void* f
                             false, st);
     if (e == hipSuccess) e = launch_fill_bits<V>((V*)uout, nv, sent, st);
     if (e == hipSuccess)
-      e = sweep<V>(H, v, -1, false, A, (const V*)v.h, PT::rd(v), (V*)uout, nullptr, 0, nullptr, nullptr, st);
+      e = sweep<V>(H, v, -1, false, PT::sk(v), (const V*)v.h, (V*)uout, nullptr, 0, nullptr, nullptr, st);
     return e;
   }
   // ILU correction: r = f - A u_old; u_out = u_old + U^-1 L^-1 r.  Scratch: the
@@ -766,10 +873,9 @@ static hipError_t op_postsmooth_t(smg_handle_s* H, const Level& v, const void* f
   if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.y2, nv, sent, st);
   if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.zz, nv, sent, st);
   if (e == hipSuccess)
-    e = sweep<V>(H, v, +1, true, PT::Lf(v), (const V*)v.h, nullptr, (V*)v.y2, nullptr, 0, nullptr, nullptr, st);
+    e = sweep<V>(H, v, +1, true, PT::sk(v), (const V*)v.h, (V*)v.y2, nullptr, 0, nullptr, nullptr, st);
   if (e == hipSuccess)
-    e = sweep<V>(H, v, -1, false, PT::Uf(v), (const V*)v.y2, PT::rU(v), (V*)v.zz, nullptr, 0, (const V*)v.uo,
-                 (V*)uout, st);
+    e = sweep<V>(H, v, -1, false, PT::sk(v), (const V*)v.y2, (V*)v.zz, nullptr, 0, (const V*)v.uo, (V*)uout, st);
   if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.y2, nv, sent, st);
   if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.zz, nv, sent, st);
   return e;
@@ -891,5 +997,48 @@ smg_status smg_op_coarse_solve(smg_handle h, const void* f, void* u, void* strea
   else
     HIPCHK(h, launch_coarse_gemv<float>(h->nc, h->aug + h->nc, 2 * h->nc, (const float*)f, (float*)u,
                                         (hipStream_t)stream));
+  return SMG_OK;
+}
+
+smg_status smg_set_timing(smg_handle h, int enable, int level, unsigned kinds) {
+  if (!h) return fail(nullptr, SMG_EINVAL, "null handle");
+  h->tm_level = level;
+  h->tm_kinds = kinds;
+  if (enable && !h->timing) {
+    for (int k = 0; k < SMG_TIMING_CAP; ++k) {
+      HIPCHK(h, hipEventCreate(&h->ev0[k]));
+      HIPCHK(h, hipEventCreate(&h->ev1[k]));
+    }
+  }
+  if (!enable && h->timing) {
+    for (int k = 0; k < SMG_TIMING_CAP; ++k) {
+      (void)hipEventDestroy(h->ev0[k]);
+      (void)hipEventDestroy(h->ev1[k]);
+    }
+  }
+  h->timing = enable != 0;
+  h->ev_used = 0;
+  return SMG_OK;
+}
+
+smg_status smg_timing_report(smg_handle h, double* ms, int* counts, int max_levels, int* dropped) {
+  if (!h || !ms || !counts || max_levels < 1) return fail(h, SMG_EINVAL, "bad arguments");
+  const int nk = SMG_TIMING_KINDS;
+  for (int k = 0; k < max_levels * nk; ++k) {
+    ms[k] = 0.0;
+    counts[k] = 0;
+  }
+  for (int k = 0; k < h->ev_used; ++k) {
+    HIPCHK(h, hipEventSynchronize(h->ev1[k]));
+    float t = 0.0f;
+    HIPCHK(h, hipEventElapsedTime(&t, h->ev0[k], h->ev1[k]));
+    const int tag = h->ev_tag[k];
+    if (tag / nk < max_levels) {
+      ms[tag] += t;
+      counts[tag] += 1;
+    }
+  }
+  if (dropped) *dropped = h->ev_used >= SMG_TIMING_CAP;
+  h->ev_used = 0;
   return SMG_OK;
 }

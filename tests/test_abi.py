@@ -50,7 +50,10 @@ def test_workspace_size_and_validation():
     st, n = _ws(shape=(32, 32, 32), pattern=7)
     assert st == smg.SMG_OK and n > 7 * 32 ** 3 * 8
     st2, n2 = _ws(shape=(32, 32, 32), pattern=7, prec="fp32")
-    assert st2 == smg.SMG_OK and n2 > n  # FP32 copies come on top of the FP64 hierarchy
+    # the FP32 V-cycle keeps the FP64 finest matrix (for the Galerkin products) plus its FP32 copy
+    assert st2 == smg.SMG_OK and n2 > 7 * 32 ** 3 * (8 + 4)
+    st3, n3 = _ws(shape=(32, 32, 32), pattern=7, prec="fp16")
+    assert st3 == smg.SMG_OK and n3 < n2  # half-precision coefficients with one FP32 scale per row
     assert _ws(shape=(32, 32, 32), pattern=5)[0] == smg.SMG_EINVAL
     assert _ws(shape=(0, 32, 32), pattern=7)[0] == smg.SMG_EINVAL
     assert _ws(shape=(8, 8, 8), pattern=7, block=3)[0] == smg.SMG_EINVAL

@@ -47,11 +47,14 @@ def hp(pat):
     return {7: (1, 1), 19: (3, 2), 27: (4, 2)}[pat]
 
 
-def exported(pat, lx, ly, sh):
+def exported(pat, lx, ly, sh, direction):
+    """Is lane (lx, ly)'s column read by a lane of another tile in a sweep of
+    the given direction?"""
     for c in range(4):
         if not col_used(pat, c):
             continue
         cx, cy = col_d(c)
+        cx, cy = direction * cx, direction * cy
         qx, qy = lx - cx, ly - cy - sh * cx
         if qx < 0 or qx >= TX or qy < 0 or qy >= TY:
             return True
@@ -67,9 +70,11 @@ def tiling(g):
 
 
 def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf):
-    """Replays one kernel launch.  x_init: output buffer contents at launch
-    (sentinel = nan marker array `sent`).  Returns the output buffer and the
-    prefill mask written into the next buffer."""
+    """Replays one kernel launch in the kernel's tile order.  Both directions
+    share one tile geometry (forward frame); the backward sweep visits tiles
+    and steps in reverse and reads upper neighbours.  x_init: output buffer
+    at launch (nan marks a sentinel).  Returns (x, prefill mask, skewed-index
+    map used for the coefficient reads)."""
     nx, ny, nz = g
     N = nx * ny * nz
     WX, WY = hp(pat)
@@ -77,49 +82,44 @@ def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf):
     C = pat // 2
     T = list(range(C)) if direction > 0 else list(range(C + 1, pat))
     sh, ntx, nty = tiling(g)
+    PRE = max(col_maxdz(pat, c) for c in range(4) if col_used(pat, c))
     x = x_init.copy()
     sent_at_start = np.isnan(x_init)
     pref = np.zeros(N, bool)
     coherent = np.zeros(N, bool)
     lanes = np.arange(TX * TY)
     lx, ly = lanes // TY, lanes % TY
-    PRE = max(col_maxdz(pat, c) for c in range(4) if col_used(pat, c))
     skew = (WX - sh * WY) * lx + WY * ly + PRE
-    maxskew = (WX - sh * WY) * (TX - 1) + WY * (TY - 1) + PRE
-    exp_lane = np.array([exported(pat, a, b, sh) for a, b in zip(lx, ly)])
-    for t in range(ntx * nty):
+    NS = nz + (WX - sh * WY) * (TX - 1) + WY * (TY - 1) + 2 * PRE  # pre-roll at both ends
+    exp_lane = np.array([exported(pat, a, b, sh, direction) for a, b in zip(lx, ly)])
+    exp_next = np.array([exported(pat, a, b, sh, nxt_dir) for a, b in zip(lx, ly)]) if nxt_buf is not None \
+        else np.zeros(TX * TY, bool)
+    skidx = np.full(N, -1, np.int64)
+    ntiles = ntx * nty
+    for ticket in range(ntiles):
+        t = ticket if direction > 0 else ntiles - 1 - ticket
         X, Y = divmod(t, nty)
         ring = np.full((HIST, TX * TY), np.nan)
         ring_pt = -np.ones((HIST, TX * TY), np.int64)
         xt = X * TX + lx
         yt = Y * TY + ly - sh * lx
         colv = (xt < nx) & (yt >= 0) & (yt < ny)
-        xo = np.where(direction > 0, xt, nx - 1 - xt)
-        yo = np.where(direction > 0, yt, ny - 1 - yt)
-        cb = (xo * ny + yo) * nz
+        cb = (xt * ny + yt) * nz
         nl, nsk, rem, cin, ncb = {}, {}, {}, {}, {}
         for c in range(4):
             cx, cy = col_d(c)
-            qx, qy = lx + cx, ly + cy + sh * cx
+            cxo, cyo = direction * cx, direction * cy
+            qx, qy = lx + cxo, ly + cyo + sh * cxo
             rem[c] = (qx < 0) | (qx >= TX) | (qy < 0) | (qy >= TY)
             nl[c] = np.where(rem[c], 0, qx * TY + qy)
             nsk[c] = (WX - sh * WY) * qx + WY * qy + PRE
-            qxx, qyy = xt + cx, yt + cy
+            qxx, qyy = xt + cxo, yt + cyo
             cin[c] = colv & (qxx >= 0) & (qxx < nx) & (qyy >= 0) & (qyy < ny)
-            qxo = np.where(direction > 0, qxx, nx - 1 - qxx)
-            qyo = np.where(direction > 0, qyy, ny - 1 - qyy)
-            ncb[c] = (qxo * ny + qyo) * nz
-        if nxt_buf is not None:
-            x2 = np.where(nxt_dir > 0, xo, nx - 1 - xo)
-            y2 = np.where(nxt_dir > 0, yo, ny - 1 - yo)
-            lx2 = x2 % TX
-            ly2 = (y2 + sh * lx2) % TY
-            prefl = colv & np.array([exported(pat, a, b, sh) for a, b in zip(lx2, ly2)])
-        else:
-            prefl = np.zeros(TX * TY, bool)
+            ncb[c] = (qxx * ny + qyy) * nz
         win = np.zeros((4, 3, TX * TY))
         own_prev = np.zeros(TX * TY)
-        for s in range(nz + maxskew):
+        for k in range(NS):
+            s = k if direction > 0 else NS - 1 - k
             z = s - skew
             for c in range(4):
                 if not col_used(pat, c):
@@ -127,11 +127,11 @@ def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf):
                 md = col_maxdz(pat, c)
                 win[c][0] = win[c][1]
                 win[c][1] = win[c][2]
-                zn = z + md
+                zn = z + direction * md
                 ok = cin[c] & (zn >= 0) & (zn < nz)
                 v = np.zeros(TX * TY)
                 for l in np.nonzero(ok)[0]:
-                    gi = ncb[c][l] + (zn[l] if direction > 0 else nz - 1 - zn[l])
+                    gi = ncb[c][l] + zn[l]
                     if not rem[c][l]:
                         slot = (zn[l] + nsk[c][l]) % HIST
                         assert ring_pt[slot, nl[c][l]] == gi, "LDS ring slot does not hold the point"
@@ -143,18 +143,19 @@ def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf):
                 win[c][md + 1] = v
             act = colv & (z >= 0) & (z < nz)
             for l in np.nonzero(act)[0]:
-                i = cb[l] + (z[l] if direction > 0 else nz - 1 - z[l])
+                i = cb[l] + z[l]
+                skidx[i] = (t * NS + s) * TX * TY + l
                 tv = h[i]
-                for k, so in enumerate(T):
-                    dx, dy, dz = (direction * v for v in off[so])
+                for so in T:
+                    dx, dy, dz = (int(v) for v in off[so])
                     if dx == 0 and dy == 0:
-                        val, ok = own_prev[l], z[l] >= 1
+                        val, ok = own_prev[l], 0 <= z[l] - direction < nz
                     else:
-                        c = dy + 1 if dx == -1 else 3
-                        val = win[c][dz + 1][l]
+                        c = col_of(direction * dx, direction * dy)
+                        val = win[c][direction * dz + 1][l]
                         ok = cin[c][l] and 0 <= z[l] + dz < nz
                     if ok:
-                        tv = np.fma(-A[so, i], val, tv) if hasattr(np, "fma") else _fma(-A[so, i], val, tv)
+                        tv = _fma(-A[so, i], val, tv)
                 xv = tv * rd[i]
                 own_prev[l] = xv
                 ring[s % HIST, l] = xv
@@ -162,9 +163,13 @@ def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf):
                 x[i] = xv
                 if exp_lane[l]:
                     coherent[i] = True
-                if prefl[l]:
+                if exp_next[l]:
                     pref[i] = True
-    return x, pref
+    return x, pref, skidx
+
+
+def col_of(dx, dy):
+    return dy + 1 if dx == -1 else (3 if dy == -1 else -1)
 
 
 def _fma(a, b, c):
@@ -182,7 +187,7 @@ def test_wavefront_schedule_matches_sequential(pat, g):
     b = workloads.rng(1).uniform(-1, 1, size=N)
     # forward sweep with zero initial guess; every output position starts as sentinel
     x0 = np.full(N, np.nan)
-    u_f, pref_f = run_sweep(g, pat, +1, A, rd, b, x0, -1, True)
+    u_f, pref_f, sk_f = run_sweep(g, pat, +1, A, rd, b, x0, -1, True)
     ref_f = oracle.gs_sweep(off, A, rd, b.reshape(g), np.zeros(g), 1, 1).ravel()
     assert np.array_equal(u_f, ref_f)
     # backward sweep: input h = f - L u_old (old values first), output starts
@@ -197,10 +202,14 @@ def test_wavefront_schedule_matches_sequential(pat, g):
             if 0 <= a < g[0] and 0 <= bb < g[1] and 0 <= c < g[2]:
                 hb[i] = _fma(-A[s, i], u_old[(a * g[1] + bb) * g[2] + c], hb[i])
     xb0 = np.where(pref_f, np.nan, 0.0)
-    u_b, pref_b = run_sweep(g, pat, -1, A, rd, hb, xb0, +1, True)
+    u_b, pref_b, sk_b = run_sweep(g, pat, -1, A, rd, hb, xb0, +1, True)
     ref_b = oracle.gs_sweep(off, A, rd, b.reshape(g), u_old.reshape(g), -1, 0).ravel()
     assert np.array_equal(u_b, ref_b)
+    # both directions read the coefficients at the same skewed positions,
+    # every point exactly once, each position belonging to one point
+    assert np.array_equal(sk_f, sk_b) and (sk_f >= 0).all()
+    assert len(np.unique(sk_f)) == N
     # and the next forward sweep reads only positions the backward sweep prefilled
     xf1 = np.where(pref_b, np.nan, 0.0)
-    u_f2, _ = run_sweep(g, pat, +1, A, rd, b, xf1, -1, None)
+    u_f2, _, _ = run_sweep(g, pat, +1, A, rd, b, xf1, -1, None)
     assert np.array_equal(u_f2, ref_f)

@@ -55,14 +55,17 @@ def fv7_from_cells(kx, ky=None, kz=None):
     """Cell-centred finite-volume 7-point operator (h = 1) from cell
     coefficients: face transmissibility is the harmonic mean 2 ka kb/(ka+kb);
     a Dirichlet boundary face (ghost value at h/2) contributes 2k to the
-    diagonal.  Returns A with shape (7, N)."""
+    diagonal.  Returns A with shape (7, N).  (Written with in-place numpy
+    operations so that large grids need few temporary arrays.)"""
     ky = kx if ky is None else ky
     kz = kx if kz is None else kz
     shape = kx.shape
     off = offsets(7)
     A = np.zeros((7,) + shape)
-    diag = np.zeros(shape)
+    diag = A[3]
     kk = {0: kx, 1: ky, 2: kz}
+    buf1 = np.empty(int(np.prod(shape)))
+    buf2 = np.empty(int(np.prod(shape)))
     for s, d in enumerate(off):
         d = tuple(int(v) for v in d)
         if d == (0, 0, 0):
@@ -71,14 +74,19 @@ def fv7_from_cells(kx, ky=None, kz=None):
         k = kk[ax]
         dst, src = _shift_valid(shape, d)
         ka, kb = k[dst], k[src]
-        T = 2.0 * ka * kb / (ka + kb)
-        A[s][dst] = -T
+        n = ka.size
+        T = buf1[:n].reshape(ka.shape)
+        den = buf2[:n].reshape(ka.shape)
+        np.multiply(ka, kb, out=T)
+        T *= 2.0
+        np.add(ka, kb, out=den)
+        T /= den
+        np.negative(T, out=A[s][dst])
         diag[dst] += T
         # boundary faces in direction d: cells whose neighbour i+d is outside
         bnd = [slice(None)] * 3
         bnd[ax] = slice(shape[ax] - 1, shape[ax]) if d[ax] > 0 else slice(0, 1)
         diag[tuple(bnd)] += 2.0 * k[tuple(bnd)]
-    A[3] = diag
     return A.reshape(7, -1)
 
 
@@ -105,7 +113,9 @@ def diffusion7(shape=(256, 256, 256), seed=2, sigma=2.0, nspheres=32, rmin=8.0, 
     U[rmin, rmax] cells); 7-point FV with harmonic-mean faces."""
     shape = tuple(shape)
     g = rng(seed)
-    k = np.exp(sigma * g.standard_normal(shape))
+    k = g.standard_normal(shape)
+    k *= sigma
+    np.exp(k, out=k)
     cen = g.uniform(0.0, 1.0, size=(nspheres, 3)) * np.array(shape)
     rad = g.uniform(rmin, rmax, size=nspheres)
     con = 10.0 ** g.uniform(-3.0, 3.0, size=nspheres)
