@@ -4,17 +4,17 @@
  * Scalable Structured Algebraic Multigrid" (arXiv 2506.21932).
  *
  * The user supplies only the finest-level matrix and right-hand sides
- * (Sec. 3.2.2, input data format); the hierarchy is built once and applied
+ * (Sec. 4.2.2, input data format); the hierarchy is built once and applied
  * many times (Sec. 2, total-time equation).  One application of the
  * preconditioner is one V-cycle (Sec. 2): pre-smoothing, residual and
  * restriction, coarse correction, prolongation, post-smoothing.
  *
  * Conventions shared by every entry point
  *   Grid (nx, ny, nz); linear index i = (x*ny + y)*nz + z (z contiguous).
- *   Stencil patterns 3d7 / 3d19 / 3d27 with offsets in {-1,0,1}^3 (Sec. 3.2.3
+ *   Stencil patterns 3d7 / 3d19 / 3d27 with offsets in {-1,0,1}^3 (Sec. 4.2.3
  *   masks), numbered lexicographically with dx slowest (the Offset(2d9) /
- *   Offset(2d5) numbering of Sec. 3.3 extended to 3D).
- *   Matrix storage "SG-DIA" (Sec. 3.1 P1): coefficient of row i for offset s
+ *   Offset(2d5) numbering of Sec. 4.3 extended to 3D).
+ *   Matrix storage "SG-DIA" (Sec. 4.1 P1): coefficient of row i for offset s
  *   at coeffs[s*N + i], N = nx*ny*nz.  Block systems (block = 3 unknowns per
  *   node): entry (r, c) of the 3x3 block of offset s at coeffs[(s*9 + r*3 + c)*N + i],
  *   vectors interleaved v[i*3 + c].  Couplings to neighbours outside the
@@ -86,7 +86,7 @@ smg_status smg_workspace_size(const smg_config* cfg, size_t* bytes);
 
 /* Builds the hierarchy: copies the finest matrix (device, FP64, SG-DIA as
  * above), forms every coarse operator with the stencil Galerkin product
- * A_c = R A P (Sec. 3.3; trilinear P, R = P^T), the smoother data (1/a_ii,
+ * A_c = R A P (Sec. 4.3; trilinear P, R = P^T), the smoother data (1/a_ii,
  * 3x3 block inverses or ILU(0) factors), truncated copies for reduced
  * V-cycle precision, and the inverse of the dense coarsest operator.
  * Synchronises `stream` before returning.  SMG_EBREAKDOWN on a zero pivot. */

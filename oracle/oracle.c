@@ -4,11 +4,11 @@
  * A plain, slow, sequential FP64 implementation of the structured multigrid
  * preconditioner of "StructMG: A Fast and Scalable Structured Algebraic
  * Multigrid" (arXiv 2506.21932): SG-DIA stencil SpMV and residual
- * (Sec. 3.1 P1), lexicographic Gauss-Seidel and ILU(0) (Sec. 3.4 formulas),
+ * (Sec. 4.1 P1), lexicographic Gauss-Seidel and ILU(0) (Sec. 4.4 formulas),
  * vertex-centred trilinear restriction / prolongation with the grid map of
- * Sec. 3.3, the stencil Galerkin triple product A^C = R A^F P in its
- * influence-chain form (Sec. 3.3, Eq. for A^C(i,j) as a sum over chains),
- * the V-cycle (Sec. 2), and the outer CG and GMRES iterations (Sec. 4.2).
+ * Sec. 4.3, the stencil Galerkin triple product A^C = R A^F P in its
+ * influence-chain form (Sec. 4.3, Eq. for A^C(i,j) as a sum over chains),
+ * the V-cycle (Sec. 2), and the outer CG and GMRES iterations (Sec. 5.2).
  *
  * Only tests, the smoke check and the CPU-baseline leg of the benchmark load
  * this library.  It shares no code, header or table with the GPU library;
@@ -121,7 +121,7 @@ static int rap_chain_ok(const int* rho, const int* a, const int* n, int cmask, d
 }
 
 /*
- * A^C = R A^F P, stencil form (Sec. 3.3): for each coarse element I and each
+ * A^C = R A^F P, stencil form (Sec. 4.3): for each coarse element I and each
  * of the 27 coarse offsets n (canonical order), the entry A^C(I, I+n) is the
  * sum over influence chains I <- u <- v <- I+n of R(I,u) A^F(u,v) P(v,I+n),
  * grouped per fine element u as
@@ -218,7 +218,7 @@ int orc_rap_chains(int S, const int* off, int cmask, int n_index, int* out, int 
   return cnt;
 }
 
-/* ---- ILU(0) factorisation (Sec. 3.2.3 mask flexibility; Sec. 3.4 ILU) ---
+/* ---- ILU(0) factorisation (Sec. 4.2.3 mask flexibility; Sec. 4.4 ILU) ---
  * Doolittle (unit lower factor), IKJ order, restricted to the pattern mask.
  * Row i: w = row i of A on the mask; for each lower slot s in canonical
  * order (= ascending column k = i+off_s): w[s] = w[s] / U_c[k]; then for
@@ -427,7 +427,7 @@ static float* to_f16_rowscaled(const double* A, long N, int S, int bs) {
 void orc_mg_destroy(omg* mg);
 
 /*
- * Builds the hierarchy from the finest matrix only (Sec. 3.2.2 input).
+ * Builds the hierarchy from the finest matrix only (Sec. 4.2.2 input).
  * pattern: 7/19/27 (level 0); coarse levels are 27-point.  bs: 1 or 3.
  * smoother: 0 = symmetric GS, 1 = ILU(0).  prec: 0 FP64, 1 FP32,
  * 2 FP16 row-scaled.  A0 is copied; out-of-grid couplings are zeroed.
@@ -636,7 +636,7 @@ static double dot(const double* a, const double* b, long n) {
 }
 
 /*
- * Preconditioned CG (Sec. 4.2; stopping rule ||r||_2/||b||_2 < tol from the
+ * Preconditioned CG (Sec. 5.2; stopping rule ||r||_2/||b||_2 < tol from the
  * settings table).  x holds x0 on entry.  When the recursive residual meets
  * the tolerance the true residual b - A x is formed; the iteration stops only
  * if the true residual also meets it, otherwise continues from it.
@@ -685,7 +685,7 @@ int orc_pcg(omg* mg, const double* b, double* x, double tol, int maxit, double* 
 
 /*
  * Right-preconditioned restarted GMRES(m) with modified Gram-Schmidt and
- * Givens rotations (Sec. 4.2).  Converges when the Givens residual estimate
+ * Givens rotations (Sec. 5.2).  Converges when the Givens residual estimate
  * over ||b|| is below tol and the true residual confirms it; restarts from
  * the true residual.  out as for orc_pcg.
  */

@@ -1,7 +1,7 @@
 """Build-time symbolic derivation of the stencil Galerkin triple product.
 
 For each (fine pattern, coarsening mask) this script enumerates the influence
-chains I <- u <- v <- J of the coarse operator entry A^C(I, J) (Sec. 3.3:
+chains I <- u <- v <- J of the coarse operator entry A^C(I, J) (Sec. 4.3:
 A^C(i,j) as the sum over fine elements u, v of R(C_i,F_u) A^F(u,v) P(F_v,C_j)),
 with vertex-centred trilinear P, R = P^T, coarse X <-> fine 2X+1 on coarsened
 axes and identity on the others.  It then emits one fused HIP kernel per

@@ -1,4 +1,4 @@
-// Stencil Galerkin triple product A^C = R A^F P (Sec. 3.3), one fused kernel
+// Stencil Galerkin triple product A^C = R A^F P (Sec. 4.3), one fused kernel
 // per (fine pattern, coarsening mask) generated at build time by gen_rap.py
 // from the enumerated influence chains.  R = P^T with vertex-centred
 // trilinear interpolation; coarse operators are 27-point.  Block systems run

@@ -1,6 +1,6 @@
-// Setup-phase kernels: level-0 copy with Dirichlet masking (Sec. 3.1 P1
+// Setup-phase kernels: level-0 copy with Dirichlet masking (Sec. 4.1 P1
 // zero padding), reciprocal diagonal, 3x3 diagonal-block inverses, ILU(0)
-// factorisation on the level's own mask (Sec. 3.2.3, Sec. 3.4 ILU), and
+// factorisation on the level's own mask (Sec. 4.2.3, Sec. 4.4 ILU), and
 // truncation of FP64 level data to FP32 or FP16 with a per-row FP32 scale.
 #include "smg_kernels.h"
 

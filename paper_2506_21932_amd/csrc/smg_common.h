@@ -3,8 +3,8 @@
 // Grid (nx, ny, nz), linear index i = (x*ny + y)*nz + z (z contiguous).
 // Stencil offsets are enumerated in lexicographic order (dx slowest), which
 // is the numbering of the paper's Offset(2d9) / Offset(2d5) lists extended to
-// 3D (Sec. 3.3).  A level matrix is stored diagonal-major ("SG-DIA",
-// Sec. 3.1 P1): coefficient of row i for offset s at A[s*N + i]; couplings to
+// 3D (Sec. 4.3).  A level matrix is stored diagonal-major ("SG-DIA",
+// Sec. 4.1 P1): coefficient of row i for offset s at A[s*N + i]; couplings to
 // neighbours outside the grid are stored as zero.
 #pragma once
 #include <hip/hip_fp16.h>
@@ -95,38 +95,11 @@ struct MatH {
   __device__ float operator()(int s, long i) const { return sc[i] * __half2float(a[(long)s * n + i]); }
 };
 
-// Sweep data stored in wavefront schedule order (see wavefront.hip): slot s
-// of the pattern at sk[s*stride + q] for schedule position q; the centre slot
-// holds the diagonal scaling of the sweep (1/a_ii, or 1/U_ii for ILU).
-struct SkD {
-  const double* a;
-  long stride;
-  using V = double;
-  __device__ double operator()(int s, long q) const { return a[(long)s * stride + q]; }
-};
-struct SkF {
-  const float* a;
-  long stride;
-  using V = float;
-  __device__ float operator()(int s, long q) const { return a[(long)s * stride + q]; }
-};
-struct SkH {
-  const __half* a;
-  const float* sc;
-  const float* dg;
-  long stride;
-  int centre;
-  using V = float;
-  __device__ float operator()(int s, long q) const {
-    return s == centre ? dg[q] : sc[q] * __half2float(a[(long)s * stride + q]);
-  }
-};
-
 constexpr int WF_TX = 16, WF_TY = 16;  // columns per wavefront tile (256 lanes)
 
 struct WfTiling {
   int sh, ntx, nty, ns;  // shear, tiles in x / y, steps per tile
-  long nsk;              // schedule-ordered entries per slot (tiles * steps * lanes)
+  long nsk;              // schedule positions (tiles * steps * lanes)
 };
 
 struct Grid {

@@ -5,10 +5,25 @@
 namespace smg {
 
 // ---- wavefront triangular sweep --------------------------------------
+// Persistent grid of at most WF_MAX_GRID workgroups (256 CUs, up to three
+// resident sweep workgroups each).
+constexpr int WF_MAX_GRID = 768;
+
+template <class E>
+struct WfVal {
+  using V = E;  // arithmetic type of storage element E
+};
+template <>
+struct WfVal<__half> {
+  using V = float;
+};
+
 template <class V>
 struct WfArgs {
   Grid g;
   WfTiling t;                // tiling of the level (wf_tiling)
+  const void* pk;            // packed sweep data of this direction (launch_wf_pack)
+  const float* sd;           // FP16 storage: {row scale, diagonal scaling} per position
   const V* h;                // right-hand side of the triangular system
   V* x;                      // output; positions read by other tiles hold the sentinel
   V* next;                   // output buffer of the next sweep on this level (sentinel prefill), or null
@@ -17,19 +32,27 @@ struct WfArgs {
   V* addout;
   unsigned* ctr;             // [0] ticket counter, [1] exit counter; zero between launches
   unsigned* err;             // watchdog flag (bit 0)
-  V* dump;                   // 4 * 256 elements of scratch for stores of inactive lanes
 };
 
 void wf_tiling(const Grid& g, int pat, WfTiling* t);
+// 16-byte packs per schedule position and direction for storage elements of
+// ebytes bytes; offsets within a tile must stay below 2^31 bytes.
+int wf_pack_count(int pat, int ebytes);
+bool wf_ranges_ok(const Grid& g, const WfTiling& t, int pat, int vbytes, int ebytes);
 
-template <class SK>
-hipError_t launch_wavefront(int pat, int dir, bool unitd, bool add, const WfArgs<typename SK::V>& a, const SK& m,
+// E = double / float / __half (FP16 storage, FP32 arithmetic)
+template <class E>
+hipError_t launch_wavefront(int pat, int dir, bool unitd, bool add, const WfArgs<typename WfVal<E>::V>& a,
                             hipStream_t st);
-template <class T>
-hipError_t launch_skew_pack(int pat, const Grid& g, const WfTiling& tl, const double* lo, const double* dg,
-                            const double* up, T* out, hipStream_t st);
-hipError_t launch_skew_pack_h(int pat, const Grid& g, const WfTiling& tl, const __half* a16, const float* sc,
-                              const float* rd, __half* o16, float* osc, float* ord, hipStream_t st);
+// Packed sweep data of direction dir from natural SG-DIA arrays: lower
+// (dir > 0) or upper (dir < 0) triangle of lo / up, then the diagonal scaling dg.
+template <class E>
+hipError_t launch_wf_pack(int pat, const Grid& g, const WfTiling& tl, int dir, const double* lo, const double* dg,
+                          const double* up, E* out, hipStream_t st);
+// FP16: halves of a16 per direction; sd (written by the dir > 0 call) holds
+// {row scale, diagonal scaling} per position.
+hipError_t launch_wf_pack_h(int pat, const Grid& g, const WfTiling& tl, int dir, const __half* a16, const float* sc,
+                            const float* rd, __half* out, float* sd, hipStream_t st);
 
 // ---- parallel stencil kernels (stencil.hip) ----------------------------
 // y = A x   (res = false)   or   y = b - A x   (res = true)

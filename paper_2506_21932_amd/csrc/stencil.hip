@@ -1,8 +1,8 @@
-// Parallel stencil kernels on SG-DIA storage: SpMV / residual (Sec. 3.1 P1),
+// Parallel stencil kernels on SG-DIA storage: SpMV / residual (Sec. 4.1 P1),
 // the fused residual + restriction of the downward V-cycle leg, and the fused
 // prolongation + correction feeding the post-smoother of the upward leg
 // (Sec. 2, V-cycle).  Interpolation P is vertex-centred trilinear with the
-// grid map of Sec. 3.3 (coarse X <-> fine 2X+1, stride 2, base offset 1);
+// grid map of Sec. 4.3 (coarse X <-> fine 2X+1, stride 2, base offset 1);
 // restriction is R = P^T.
 //
 // Every output element is produced with the same operations in the same

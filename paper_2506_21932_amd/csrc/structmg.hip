@@ -1,9 +1,9 @@
 // libstructmg host side: hierarchy setup, V-cycle orchestration, outer
 // Krylov solvers and the C ABI declared in include/structmg.h.
 //
-// Setup builds the hierarchy from the finest matrix only (Sec. 3.2.2):
-// multi-dimensional coarsening by fixed stride 2 (Sec. 3.1 P2), coarse
-// operators from the generated stencil triple product (Sec. 3.3), smoother
+// Setup builds the hierarchy from the finest matrix only (Sec. 4.2.2):
+// multi-dimensional coarsening by fixed stride 2 (Sec. 4.1 P2), coarse
+// operators from the generated stencil triple product (Sec. 4.3), smoother
 // data per level, then the dense coarsest inverse.  The V-cycle (Sec. 2) runs
 // a zero-initial-guess forward GS sweep (or ILU(0) solve) before the coarse
 // correction and a backward GS sweep (or ILU(0) correction) after it, the
@@ -38,10 +38,9 @@ struct Level {
   float* sc16 = nullptr;
   void *f = nullptr, *ua = nullptr, *ub = nullptr, *h = nullptr;
   void *y1 = nullptr, *y2 = nullptr, *zz = nullptr, *uo = nullptr;
-  WfTiling tl{};          // wavefront tiling
-  void* sk = nullptr;     // sweep data in schedule order (V-cycle precision; FP16: halves)
-  float* sksc = nullptr;  // FP16: row scales in schedule order
-  float* skdg = nullptr;  // FP16: diagonal scaling in schedule order
+  WfTiling tl{};                    // wavefront tiling
+  void* pk[2] = {nullptr, nullptr};  // packed sweep data, forward / backward (V-cycle precision; FP16: halves)
+  float* psd = nullptr;             // FP16: {row scale, diagonal scaling} per schedule position
 };
 
 }  // namespace
@@ -55,7 +54,6 @@ struct smg_handle_s {
   unsigned* err = nullptr;
   int* info = nullptr;
   double *dpart = nullptr, *dout = nullptr;
-  double* dump = nullptr;  // wavefront scratch (4 * 256 doubles)
   double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr, *kt = nullptr, *kw = nullptr;
   double* kV = nullptr;
   int kV_m = 0;
@@ -131,6 +129,9 @@ const char* check_cfg(const smg_config* c) {
   if (!c) return "null config";
   if (c->nx < 1 || c->ny < 1 || c->nz < 1) return "grid dimensions must be >= 1";
   if ((double)c->nx * c->ny * c->nz * (c->block > 1 ? c->block : 1) >= 2147483647.0) return "grid too large";
+  // sweep buffers address 18 x-planes and one tile's steps with 31-bit byte offsets
+  if ((double)(WF_TX + 2) * c->ny * c->nz * 8 >= 2147483647.0) return "ny * nz too large (limit 14.9e6)";
+  if (c->nz > 65536) return "nz too large (limit 65536)";
   if (c->block != 1 && c->block != 3) return "block must be 1 or 3";
   if (c->pattern != 7 && c->pattern != 19 && c->pattern != 27) return "pattern must be 7, 19 or 27";
   if (c->block == 3 && c->pattern != 27) return "block systems use the 27-point pattern";
@@ -196,13 +197,11 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
     }
     wf_tiling(v.g, v.S, &v.tl);
     if (bs == 1) {
-      if (cfg.prec == SMG_FP16_ROWSCALE) {
-        v.sk = ar.take<__half>((size_t)v.S * v.tl.nsk);
-        v.sksc = ar.take<float>((size_t)v.tl.nsk);
-        v.skdg = ar.take<float>((size_t)v.tl.nsk);
-      } else {
-        v.sk = ar.take<char>((size_t)v.S * v.tl.nsk * vsz);
-      }
+      const int eb = cfg.prec == SMG_FP16_ROWSCALE ? 2 : (int)vsz;
+      const size_t pbytes = (size_t)wf_pack_count(v.S, eb) * 16 * v.tl.nsk;
+      v.pk[0] = ar.take<char>(pbytes);
+      v.pk[1] = ar.take<char>(pbytes);
+      if (cfg.prec == SMG_FP16_ROWSCALE) v.psd = ar.take<float>((size_t)2 * v.tl.nsk);
     }
     if (cfg.prec == SMG_FP32) {
       v.A32 = ar.take<float>((size_t)v.S * be * N);
@@ -224,7 +223,6 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
   int* info = ar.take<int>(64);
   double* dpart = ar.take<double>(DOT_BLOCKS);
   double* dout = ar.take<double>(64);
-  double* dump = ar.take<double>(1024);
   const long n0 = L[0].N * bs;
   double* kr = ar.take<double>(n0);
   double* kz = ar.take<double>(n0);
@@ -240,7 +238,6 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
     H->info = info;
     H->dpart = dpart;
     H->dout = dout;
-    H->dump = dump;
     H->kr = kr;
     H->kz = kz;
     H->kp = kp;
@@ -258,8 +255,7 @@ struct P64 {
   using V = double;
   using M = MatD;
   using MF = MatD;
-  using SK = SkD;
-  static SK sk(const Level& l) { return SkD{(const double*)l.sk, l.tl.nsk}; }
+  using E = double;
   static M A(const Level& l) { return MatD{l.A64, l.N}; }
   static MF Lf(const Level& l) { return MatD{l.L64, l.N}; }
   static MF Uf(const Level& l) { return MatD{l.U64, l.N}; }
@@ -270,8 +266,7 @@ struct P32 {
   using V = float;
   using M = MatF;
   using MF = MatF;
-  using SK = SkF;
-  static SK sk(const Level& l) { return SkF{(const float*)l.sk, l.tl.nsk}; }
+  using E = float;
   static M A(const Level& l) { return MatF{l.A32, l.N}; }
   static MF Lf(const Level& l) { return MatF{l.L32, l.N}; }
   static MF Uf(const Level& l) { return MatF{l.U32, l.N}; }
@@ -282,8 +277,7 @@ struct P16 {
   using V = float;
   using M = MatH;
   using MF = MatF;
-  using SK = SkH;
-  static SK sk(const Level& l) { return SkH{(const __half*)l.sk, l.sksc, l.skdg, l.tl.nsk, l.S / 2}; }
+  using E = __half;
   static M A(const Level& l) { return MatH{l.A16, l.sc16, l.N}; }
   static MF Lf(const Level& l) { return MatF{l.L32, l.N}; }
   static MF Uf(const Level& l) { return MatF{l.U32, l.N}; }
@@ -291,12 +285,14 @@ struct P16 {
   static const V* rU(const Level& l) { return l.rU32; }
 };
 
-template <class V, class SK>
-hipError_t sweep(smg_handle_s* H, const Level& L, int dir, bool unitd, const SK& sk, const V* hin, V* x, V* next,
-                 int next_dir, const V* addv, V* addout, hipStream_t st) {
+template <class E, class V>
+hipError_t sweep(smg_handle_s* H, const Level& L, int dir, bool unitd, const V* hin, V* x, V* next, int next_dir,
+                 const V* addv, V* addout, hipStream_t st) {
   WfArgs<V> a{};
   a.g = L.g;
   a.t = L.tl;
+  a.pk = L.pk[dir > 0 ? 0 : 1];
+  a.sd = L.psd;
   a.h = hin;
   a.x = x;
   a.next = next;
@@ -305,8 +301,7 @@ hipError_t sweep(smg_handle_s* H, const Level& L, int dir, bool unitd, const SK&
   a.addout = addout;
   a.ctr = H->ctr;
   a.err = H->err;
-  a.dump = reinterpret_cast<V*>(H->dump);
-  return launch_wavefront<SK>(L.S, dir, unitd, addout != nullptr, a, sk, st);
+  return launch_wavefront<E>(L.S, dir, unitd, addout != nullptr, a, st);
 }
 
 // One V-cycle on internal or caller vectors: f0 = level-0 right-hand side,
@@ -325,15 +320,15 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
     const auto A = PT::A(v);
     if (!ilu) {
       Timed t(H, l, 0, st);
-      e = sweep<V>(H, v, +1, false, PT::sk(v), F(l), (V*)v.ua, UB(l), -1, nullptr, nullptr, st);
+      e = sweep<typename PT::E, V>(H, v, +1, false, F(l), (V*)v.ua, UB(l), -1, nullptr, nullptr, st);
     } else {
       {
         Timed t(H, l, 0, st);
-        e = sweep<V>(H, v, +1, true, PT::sk(v), F(l), (V*)v.y1, (V*)v.ua, -1, nullptr, nullptr, st);
+        e = sweep<typename PT::E, V>(H, v, +1, true, F(l), (V*)v.y1, (V*)v.ua, -1, nullptr, nullptr, st);
       }
       if (e != hipSuccess) return e;
       Timed t(H, l, 1, st);
-      e = sweep<V>(H, v, -1, false, PT::sk(v), (const V*)v.y1, (V*)v.ua, (V*)v.y2, +1, nullptr, nullptr, st);
+      e = sweep<typename PT::E, V>(H, v, -1, false, (const V*)v.y1, (V*)v.ua, (V*)v.y2, +1, nullptr, nullptr, st);
     }
     if (e != hipSuccess) return e;
     {
@@ -358,7 +353,7 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
       }
       if (e != hipSuccess) return e;
       Timed t(H, l, 5, st);
-      e = sweep<V>(H, v, -1, false, PT::sk(v), (const V*)v.h, UB(l), (V*)v.ua, +1, nullptr, nullptr, st);
+      e = sweep<typename PT::E, V>(H, v, -1, false, (const V*)v.h, UB(l), (V*)v.ua, +1, nullptr, nullptr, st);
     } else {
       {
         Timed t(H, l, 4, st);
@@ -368,11 +363,11 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
       if (e != hipSuccess) return e;
       {
         Timed t(H, l, 5, st);
-        e = sweep<V>(H, v, +1, true, PT::sk(v), (const V*)v.h, (V*)v.y2, (V*)v.zz, -1, nullptr, nullptr, st);
+        e = sweep<typename PT::E, V>(H, v, +1, true, (const V*)v.h, (V*)v.y2, (V*)v.zz, -1, nullptr, nullptr, st);
       }
       if (e != hipSuccess) return e;
       Timed t(H, l, 6, st);
-      e = sweep<V>(H, v, -1, false, PT::sk(v), (const V*)v.y2, (V*)v.zz, (V*)v.y1, +1, (const V*)v.uo, UB(l), st);
+      e = sweep<typename PT::E, V>(H, v, -1, false, (const V*)v.y2, (V*)v.zz, (V*)v.y1, +1, (const V*)v.uo, UB(l), st);
     }
     if (e != hipSuccess) return e;
   }
@@ -476,12 +471,15 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
       const double* lo = ilu ? v.L64 : v.A64;
       const double* up = ilu ? v.U64 : v.A64;
       const double* dg = ilu ? v.rU64 : v.rd64;
-      if (cfg->prec == SMG_FP64)
-        SCHK(launch_skew_pack<double>(v.S, v.g, v.tl, lo, dg, up, (double*)v.sk, st));
-      else if (cfg->prec == SMG_FP32)
-        SCHK(launch_skew_pack<float>(v.S, v.g, v.tl, lo, dg, up, (float*)v.sk, st));
-      else
-        SCHK(launch_skew_pack_h(v.S, v.g, v.tl, v.A16, v.sc16, v.rd32, (__half*)v.sk, v.sksc, v.skdg, st));
+      for (int d = 0; d < 2; ++d) {
+        const int dir = d == 0 ? 1 : -1;
+        if (cfg->prec == SMG_FP64)
+          SCHK(launch_wf_pack<double>(v.S, v.g, v.tl, dir, lo, dg, up, (double*)v.pk[d], st));
+        else if (cfg->prec == SMG_FP32)
+          SCHK(launch_wf_pack<float>(v.S, v.g, v.tl, dir, lo, dg, up, (float*)v.pk[d], st));
+        else
+          SCHK(launch_wf_pack_h(v.S, v.g, v.tl, dir, v.A16, v.sc16, v.rd32, (__half*)v.pk[d], v.psd, st));
+      }
     }
     const long nv = v.N * bs;
     void* bufs[] = {v.ua, v.ub, v.y1, v.y2, v.zz};
@@ -831,15 +829,15 @@ static hipError_t op_presmooth_t(smg_handle_s* H, const Level& v, const void* f,
   if (H->cfg.smoother == SMG_SMOOTH_GS) {
     e = launch_fill_bits<V>((V*)u, nv, sent, st);
     if (e == hipSuccess)
-      e = sweep<V>(H, v, +1, false, PT::sk(v), (const V*)f, (V*)u, nullptr, 0, nullptr, nullptr, st);
+      e = sweep<typename PT::E, V>(H, v, +1, false, (const V*)f, (V*)u, nullptr, 0, nullptr, nullptr, st);
     return e;
   }
   e = launch_fill_bits<V>((V*)v.h, nv, sent, st);
   if (e == hipSuccess) e = launch_fill_bits<V>((V*)u, nv, sent, st);
   if (e == hipSuccess)
-    e = sweep<V>(H, v, +1, true, PT::sk(v), (const V*)f, (V*)v.h, nullptr, 0, nullptr, nullptr, st);
+    e = sweep<typename PT::E, V>(H, v, +1, true, (const V*)f, (V*)v.h, nullptr, 0, nullptr, nullptr, st);
   if (e == hipSuccess)
-    e = sweep<V>(H, v, -1, false, PT::sk(v), (const V*)v.h, (V*)u, nullptr, 0, nullptr, nullptr, st);
+    e = sweep<typename PT::E, V>(H, v, -1, false, (const V*)v.h, (V*)u, nullptr, 0, nullptr, nullptr, st);
   return e;
 }
 
@@ -863,7 +861,7 @@ static hipError_t op_postsmooth_t(smg_handle_s* H, const Level& v, const void* f
                             false, st);
     if (e == hipSuccess) e = launch_fill_bits<V>((V*)uout, nv, sent, st);
     if (e == hipSuccess)
-      e = sweep<V>(H, v, -1, false, PT::sk(v), (const V*)v.h, (V*)uout, nullptr, 0, nullptr, nullptr, st);
+      e = sweep<typename PT::E, V>(H, v, -1, false, (const V*)v.h, (V*)uout, nullptr, 0, nullptr, nullptr, st);
     return e;
   }
   // ILU correction: r = f - A u_old; u_out = u_old + U^-1 L^-1 r.  Scratch: the
@@ -873,9 +871,9 @@ static hipError_t op_postsmooth_t(smg_handle_s* H, const Level& v, const void* f
   if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.y2, nv, sent, st);
   if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.zz, nv, sent, st);
   if (e == hipSuccess)
-    e = sweep<V>(H, v, +1, true, PT::sk(v), (const V*)v.h, (V*)v.y2, nullptr, 0, nullptr, nullptr, st);
+    e = sweep<typename PT::E, V>(H, v, +1, true, (const V*)v.h, (V*)v.y2, nullptr, 0, nullptr, nullptr, st);
   if (e == hipSuccess)
-    e = sweep<V>(H, v, -1, false, PT::sk(v), (const V*)v.y2, (V*)v.zz, nullptr, 0, (const V*)v.uo, (V*)uout, st);
+    e = sweep<typename PT::E, V>(H, v, -1, false, (const V*)v.y2, (V*)v.zz, nullptr, 0, (const V*)v.uo, (V*)uout, st);
   if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.y2, nv, sent, st);
   if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.zz, nv, sent, st);
   return e;

@@ -1,18 +1,29 @@
-"""CPU model of the wavefront sweep kernel's schedule (csrc/wavefront.hip).
+"""CPU model of the wavefront sweep kernel (csrc/wavefront.hip).
 
 The GPU kernel runs tiles concurrently; any order in which each tile runs
 after every tile it depends on is one of its possible executions.  This model
 replays the kernel's exact index arithmetic -- lane -> column mapping with
-shear, per-lane skew, LDS ring slots, register windows, the set of columns
-read from other tiles, the sentinel prefill for the next sweep -- with the
+shear, per-lane skew with the KB padding, the LDS ring rows and halo slots,
+the halo loader lanes, the buffer windows of the vectors, the sentinel
+prefill for the next sweep, the packed coefficient positions -- with the
 tiles run one after another in ticket order, and checks that
 
   * the result equals the sequential lexicographic sweep of the oracle,
-  * every value read from another tile lies in a column that the producer
-    writes with a coherent store and that held the sentinel when the sweep
-    started (so a concurrent reader would have waited for it),
-  * every LDS ring read finds the value written for that point,
-  * the prefill of a sweep marks every position the next sweep reads remotely.
+  * every LDS ring read of a lane that has a point finds the value written
+    for exactly that neighbour point in the same tile (or zero where the
+    neighbour lies outside the grid),
+  * every value fetched from another tile's column held the sentinel when the
+    sweep started (so a concurrent reader would have waited for it),
+  * the right-hand side reaches each lane through the LDS chunk buffer
+    (loaded as column runs) and results leave through the ring as column
+    runs every 16 steps; only columns read by other tiles are written at
+    once, so a fetch of any other position would find the sentinel,
+  * every buffer offset stays inside the planes the kernel's buffer covers,
+    every halo slot index is inside the frame and every used slot has a
+    loader lane,
+  * the prefill of a sweep marks every position the next sweep fetches, and
+  * the packed-data position of every point is unique and inverted by the
+    setup kernel's mapping.
 """
 import numpy as np
 import pytest
@@ -21,7 +32,9 @@ import oracle
 import workloads
 
 TX = TY = 16
-HIST = 8
+NL = TX * TY
+NH = 104
+HIST = 16
 
 
 def pat_has(pat, d):
@@ -38,18 +51,51 @@ def col_used(pat, c):
     return any(pat_has(pat, (cx, cy, dz)) for dz in (-1, 0, 1))
 
 
-def col_maxdz(pat, c):
-    cx, cy = col_d(c)
-    return 1 if pat_has(pat, (cx, cy, 1)) else 0
+def col_of(dx, dy):
+    return dy + 1 if dx == -1 else (3 if dy == -1 else -1)
 
 
 def hp(pat):
     return {7: (1, 1), 19: (3, 2), 27: (4, 2)}[pat]
 
 
+def kb_of(pat):
+    WX, WY = hp(pat)
+    off = workloads.offsets(pat)
+    return max(-(WX * int(d[0]) + WY * int(d[1]) + int(d[2])) for d in off[:pat // 2])
+
+
+def halo_slot(qx, qy):
+    if qx == -1:
+        return qy + 2
+    if qx == TX:
+        return 22 + qy
+    return 40 + 2 * qx + (qy + 2) if qy < 0 else 72 + 2 * qx + (qy - TY)
+
+
+def halo_pos(hs):
+    if hs < 20:
+        return -1, hs - 2
+    if hs < 40:
+        return TX, hs - 22
+    if hs < 72:
+        return (hs - 40) // 2, (hs - 40) % 2 - 2
+    return (hs - 72) // 2, TY + (hs - 72) % 2
+
+
+def halo_used(pat, direction, sh, qx, qy):
+    for c in range(4):
+        if not col_used(pat, c):
+            continue
+        cx, cy = col_d(c)
+        cx, cy = direction * cx, direction * cy
+        lx, ly = qx - cx, qy - cy - sh * cx
+        if 0 <= lx < TX and 0 <= ly < TY:
+            return True
+    return False
+
+
 def exported(pat, lx, ly, sh, direction):
-    """Is lane (lx, ly)'s column read by a lane of another tile in a sweep of
-    the given direction?"""
     for c in range(4):
         if not col_used(pat, c):
             continue
@@ -61,115 +107,211 @@ def exported(pat, lx, ly, sh, direction):
     return False
 
 
-def tiling(g):
+def tiling(g, pat):
     nx, ny, nz = g
+    WX, WY = hp(pat)
     sh = 0 if ny <= TY else 1
     ntx = (nx + TX - 1) // TX
     nty = (ny + sh * (TX - 1) + TY - 1) // TY
-    return sh, ntx, nty
+    ns = nz + (WX - sh * WY) * (TX - 1) + WY * (TY - 1) + 2 * kb_of(pat)
+    return sh, ntx, nty, ns
+
+
+def wf_point(g, pat, q):
+    """The setup kernel's map from a packed position to its point (or -1)."""
+    nx, ny, nz = g
+    WX, WY = hp(pat)
+    sh, ntx, nty, ns = tiling(g, pat)
+    l, r = q % NL, q // NL
+    s, tile = r % ns, r // ns
+    X, Y = divmod(tile, nty)
+    lx, ly = divmod(l, TY)
+    x, y = X * TX + lx, Y * TY + ly - sh * lx
+    z = s - ((WX - sh * WY) * lx + WY * ly + kb_of(pat))
+    ok = x < nx and 0 <= y < ny and 0 <= z < nz
+    return (x * ny + y) * nz + z if ok else -1
 
 
 def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf):
-    """Replays one kernel launch in the kernel's tile order.  Both directions
-    share one tile geometry (forward frame); the backward sweep visits tiles
-    and steps in reverse and reads upper neighbours.  x_init: output buffer
-    at launch (nan marks a sentinel).  Returns (x, prefill mask, skewed-index
-    map used for the coefficient reads)."""
+    """Replays one kernel launch in ticket order.  x_init: output buffer at
+    launch (nan marks a sentinel).  Returns (x, prefill mask, packed index of
+    every point)."""
     nx, ny, nz = g
     N = nx * ny * nz
     WX, WY = hp(pat)
+    KB = kb_of(pat)
     off = workloads.offsets(pat)
     C = pat // 2
     T = list(range(C)) if direction > 0 else list(range(C + 1, pat))
-    sh, ntx, nty = tiling(g)
-    PRE = max(col_maxdz(pat, c) for c in range(4) if col_used(pat, c))
+    sh, ntx, nty, NS = tiling(g, pat)
+    nsteps = -(-NS // HIST) * HIST
+    RW = NL + NH + 1
+    HRW = NL + 1
     x = x_init.copy()
+    done = np.full(N, np.nan)   # every value as soon as it is computed (model bookkeeping only)
     sent_at_start = np.isnan(x_init)
     pref = np.zeros(N, bool)
-    coherent = np.zeros(N, bool)
-    lanes = np.arange(TX * TY)
+    lanes = np.arange(NL)
     lx, ly = lanes // TY, lanes % TY
-    skew = (WX - sh * WY) * lx + WY * ly + PRE
-    NS = nz + (WX - sh * WY) * (TX - 1) + WY * (TY - 1) + 2 * PRE  # pre-roll at both ends
-    exp_lane = np.array([exported(pat, a, b, sh, direction) for a, b in zip(lx, ly)])
+    skew = (WX - sh * WY) * lx + WY * ly + KB
+    exp_now = np.array([exported(pat, a, b, sh, direction) for a, b in zip(lx, ly)])
     exp_next = np.array([exported(pat, a, b, sh, nxt_dir) for a, b in zip(lx, ly)]) if nxt_buf is not None \
-        else np.zeros(TX * TY, bool)
-    skidx = np.full(N, -1, np.int64)
+        else np.zeros(NL, bool)
+    run_y, run_r = lanes // HIST, lanes % HIST   # column-run roles of the threads
+    # neighbour column LDS indices
+    nidx = {}
+    for c in range(4):
+        if not col_used(pat, c):
+            continue
+        cx, cy = col_d(c)
+        cx, cy = direction * cx, direction * cy
+        qx, qy = lx + cx, ly + cy + sh * cx
+        idx = np.empty(NL, np.int64)
+        for l in range(NL):
+            if 0 <= qx[l] < TX and 0 <= qy[l] < TY:
+                idx[l] = qx[l] * TY + qy[l]
+            else:
+                hs = halo_slot(int(qx[l]), int(qy[l]))
+                assert 0 <= hs < NH and halo_pos(hs) == (qx[l], qy[l])
+                idx[l] = NL + hs
+        nidx[c] = idx
+    # halo loader lanes
+    hs_of = (lanes % 64) * 4 + lanes // 64
+    loaders = {}
+    for l in range(NL):
+        hs = int(hs_of[l])
+        if hs < NH:
+            assert halo_slot(*halo_pos(hs)) == hs
+            if halo_used(pat, direction, sh, *halo_pos(hs)):
+                loaders[hs] = l
+    used_slots = {int(v) - NL for c in nidx for v in nidx[c] if v >= NL}
+    assert used_slots <= set(loaders), "a used halo slot has no loader lane"
+    pkidx = np.full(N, -1, np.int64)
     ntiles = ntx * nty
+    pl = ny * nz
     for ticket in range(ntiles):
         t = ticket if direction > 0 else ntiles - 1 - ticket
         X, Y = divmod(t, nty)
-        ring = np.full((HIST, TX * TY), np.nan)
-        ring_pt = -np.ones((HIST, TX * TY), np.int64)
+        p0 = max(X * TX - 1, 0)
+        p1 = min(X * TX + TX + 1, nx)
+        lo_i, hi_i = p0 * pl, p1 * pl
         xt = X * TX + lx
         yt = Y * TY + ly - sh * lx
         colv = (xt < nx) & (yt >= 0) & (yt < ny)
         cb = (xt * ny + yt) * nz
-        nl, nsk, rem, cin, ncb = {}, {}, {}, {}, {}
-        for c in range(4):
-            cx, cy = col_d(c)
-            cxo, cyo = direction * cx, direction * cy
-            qx, qy = lx + cxo, ly + cyo + sh * cxo
-            rem[c] = (qx < 0) | (qx >= TX) | (qy < 0) | (qy >= TY)
-            nl[c] = np.where(rem[c], 0, qx * TY + qy)
-            nsk[c] = (WX - sh * WY) * qx + WY * qy + PRE
-            qxx, qyy = xt + cxo, yt + cyo
-            cin[c] = colv & (qxx >= 0) & (qxx < nx) & (qyy >= 0) & (qyy < ny)
-            ncb[c] = (qxx * ny + qyy) * nz
-        win = np.zeros((4, 3, TX * TY))
-        own_prev = np.zeros(TX * TY)
-        for k in range(NS):
-            s = k if direction > 0 else NS - 1 - k
-            z = s - skew
-            for c in range(4):
-                if not col_used(pat, c):
-                    continue
-                md = col_maxdz(pat, c)
-                win[c][0] = win[c][1]
-                win[c][1] = win[c][2]
-                zn = z + direction * md
-                ok = cin[c] & (zn >= 0) & (zn < nz)
-                v = np.zeros(TX * TY)
-                for l in np.nonzero(ok)[0]:
-                    gi = ncb[c][l] + zn[l]
-                    if not rem[c][l]:
-                        slot = (zn[l] + nsk[c][l]) % HIST
-                        assert ring_pt[slot, nl[c][l]] == gi, "LDS ring slot does not hold the point"
-                        v[l] = ring[slot, nl[c][l]]
+        ring = np.full((HIST, RW), np.nan)
+        ring_pt = np.full((HIST, RW), -2, np.int64)    # point index, or -1 for "zero"
+        ring_it = np.full((HIST, RW), -10 ** 9, np.int64)
+        hbuf = np.full(2 * HIST * HRW, np.nan)
+        own_prev = np.zeros(NL)
+
+        def step_of(k):
+            return k if direction > 0 else NS - 1 - k
+
+        def run_off(i, cyy, s):
+            xx, yy = X * TX + i, Y * TY + cyy - sh * i
+            z = s - ((WX - sh * WY) * i + WY * cyy + KB)
+            if xx < nx and 0 <= yy < ny and 0 <= z < nz:
+                gi = (xx * ny + yy) * nz + z
+                assert lo_i <= gi < hi_i, "column-run offset outside the buffer window"
+                return gi
+            return -1
+
+        def hchunk(c):
+            for t in range(NL):
+                s = step_of(c * HIST + run_r[t])
+                for i in range(TX):
+                    gi = run_off(i, run_y[t], s)
+                    li = ((c & 1) * HIST + run_r[t]) * HRW + i * TY + run_y[t]
+                    assert 0 <= li < 2 * HIST * HRW
+                    hbuf[li] = h[gi] if gi >= 0 else 0.0
+
+        def xchunk_out(c):
+            for t in range(NL):
+                s = step_of(c * HIST + run_r[t])
+                for i in range(TX):
+                    gi = run_off(i, run_y[t], s)
+                    lane = i * TY + run_y[t]
+                    if gi < 0:
+                        continue
+                    assert ring_it[run_r[t], lane] == c * HIST + run_r[t] and ring_pt[run_r[t], lane] == gi
+                    if not exp_now[lane]:
+                        assert np.isnan(x[gi]) or x[gi] == 0.0 or not sent_at_start[gi]
+                        x[gi] = ring[run_r[t], lane]
                     else:
-                        assert sent_at_start[gi], "remote read of a position that was not a sentinel"
-                        assert coherent[gi], "remote read of a value not written coherently"
-                        v[l] = x[gi]
-                win[c][md + 1] = v
+                        assert x[gi] == ring[run_r[t], lane]
+                    if exported(pat, i, run_y[t], sh, nxt_dir) and nxt_buf is not None:
+                        pref[gi] = True
+
+        def halo_put(k):
+            s = step_of(k)
+            for hs, l in loaders.items():
+                qx, qy = halo_pos(hs)
+                hskew = (WX - sh * WY) * qx + WY * qy + KB
+                gx, gy = X * TX + qx, Y * TY + qy - sh * qx
+                hz = s - hskew
+                ok = 0 <= s < NS and 0 <= gx < nx and 0 <= gy < ny and 0 <= hz < nz
+                r = k % HIST
+                if ok:
+                    gi = (gx * ny + gy) * nz + hz
+                    assert lo_i <= gi < hi_i, "halo offset outside the buffer window"
+                    assert sent_at_start[gi], "fetched a position that was not a sentinel at launch"
+                    assert not np.isnan(x[gi]), "fetched a value its producer has not written"
+                    ring[r, NL + hs], ring_pt[r, NL + hs] = x[gi], gi
+                else:
+                    ring[r, NL + hs], ring_pt[r, NL + hs] = 0.0, -1
+                ring_it[r, NL + hs] = k
+
+        hchunk(0)
+        halo_put(0)
+        for k in range(nsteps):
+            j = k % HIST
+            if j == 0:
+                hchunk(k // HIST + 1)
+            s = step_of(k)
+            z = s - skew
             act = colv & (z >= 0) & (z < nz)
+            xr = np.zeros(NL)
             for l in np.nonzero(act)[0]:
                 i = cb[l] + z[l]
-                skidx[i] = (t * NS + s) * TX * TY + l
-                tv = h[i]
+                assert lo_i <= i < hi_i, "point offset outside the buffer window"
+                pkidx[i] = (t * NS + s) * NL + l
+                tv = hbuf[((k // HIST) & 1) * HIST * HRW + j * HRW + l]
+                assert tv == h[i], "right-hand side chunk holds another point"
+                
                 for so in T:
                     dx, dy, dz = (int(v) for v in off[so])
+                    xn, yn, zn = xt[l] + dx, yt[l] + dy, z[l] + dz
+                    inb = 0 <= xn < nx and 0 <= yn < ny and 0 <= zn < nz
+                    gi = (xn * ny + yn) * nz + zn
                     if dx == 0 and dy == 0:
-                        val, ok = own_prev[l], 0 <= z[l] - direction < nz
+                        val = own_prev[l]
+                        assert (val == done[gi]) if inb else val == 0.0
                     else:
                         c = col_of(direction * dx, direction * dy)
-                        val = win[c][direction * dz + 1][l]
-                        ok = cin[c][l] and 0 <= z[l] + dz < nz
-                    if ok:
-                        tv = _fma(-A[so, i], val, tv)
-                xv = tv * rd[i]
-                own_prev[l] = xv
-                ring[s % HIST, l] = xv
-                ring_pt[s % HIST, l] = i
-                x[i] = xv
-                if exp_lane[l]:
-                    coherent[i] = True
-                if exp_next[l]:
-                    pref[i] = True
-    return x, pref, skidx
-
-
-def col_of(dx, dy):
-    return dy + 1 if dx == -1 else (3 if dy == -1 else -1)
+                        back = direction * (WX * dx + WY * dy + dz)
+                        assert -KB <= back <= -1
+                        r = (j + back) % HIST
+                        idx = nidx[c][l]
+                        assert ring_it[r, idx] == k + back, "ring row not written in this tile at that step"
+                        val = ring[r, idx]
+                        if inb:
+                            assert ring_pt[r, idx] == gi, "ring slot holds another point"
+                        else:
+                            assert val == 0.0
+                    tv = _fma(-A[so, i], val, tv)
+                xr[l] = tv * rd[i]
+                done[i] = xr[l]
+                if exp_now[l]:
+                    x[i] = xr[l]   # read by other tiles: written at once
+            own_prev = xr
+            ring[j, :NL] = xr
+            ring_pt[j, :NL] = np.where(act, cb + z, -1)
+            ring_it[j, :NL] = k
+            halo_put(k + 1)
+            if j == HIST - 1:
+                xchunk_out(k // HIST)
+    return x, pref, pkidx
 
 
 def _fma(a, b, c):
@@ -187,7 +329,7 @@ def test_wavefront_schedule_matches_sequential(pat, g):
     b = workloads.rng(1).uniform(-1, 1, size=N)
     # forward sweep with zero initial guess; every output position starts as sentinel
     x0 = np.full(N, np.nan)
-    u_f, pref_f, sk_f = run_sweep(g, pat, +1, A, rd, b, x0, -1, True)
+    u_f, pref_f, pk_f = run_sweep(g, pat, +1, A, rd, b, x0, -1, True)
     ref_f = oracle.gs_sweep(off, A, rd, b.reshape(g), np.zeros(g), 1, 1).ravel()
     assert np.array_equal(u_f, ref_f)
     # backward sweep: input h = f - L u_old (old values first), output starts
@@ -202,14 +344,29 @@ def test_wavefront_schedule_matches_sequential(pat, g):
             if 0 <= a < g[0] and 0 <= bb < g[1] and 0 <= c < g[2]:
                 hb[i] = _fma(-A[s, i], u_old[(a * g[1] + bb) * g[2] + c], hb[i])
     xb0 = np.where(pref_f, np.nan, 0.0)
-    u_b, pref_b, sk_b = run_sweep(g, pat, -1, A, rd, hb, xb0, +1, True)
+    u_b, pref_b, pk_b = run_sweep(g, pat, -1, A, rd, hb, xb0, +1, True)
     ref_b = oracle.gs_sweep(off, A, rd, b.reshape(g), u_old.reshape(g), -1, 0).ravel()
     assert np.array_equal(u_b, ref_b)
-    # both directions read the coefficients at the same skewed positions,
-    # every point exactly once, each position belonging to one point
-    assert np.array_equal(sk_f, sk_b) and (sk_f >= 0).all()
-    assert len(np.unique(sk_f)) == N
-    # and the next forward sweep reads only positions the backward sweep prefilled
+    # both directions use the same packed position per point, every point
+    # exactly once, and the setup kernel maps each position back to its point
+    assert np.array_equal(pk_f, pk_b) and (pk_f >= 0).all()
+    assert len(np.unique(pk_f)) == N
+    assert all(wf_point(g, pat, int(pk_f[i])) == i for i in range(N))
+    # and the next forward sweep fetches only positions the backward sweep prefilled
     xf1 = np.where(pref_b, np.nan, 0.0)
     u_f2, _, _ = run_sweep(g, pat, +1, A, rd, b, xf1, -1, None)
     assert np.array_equal(u_f2, ref_f)
+
+
+def test_out_of_grid_couplings_are_zero():
+    # the kernel applies every coupling unconditionally; the generator (like
+    # every operator the library builds) stores couplings leaving the grid as 0
+    g = (6, 5, 4)
+    for pat in (7, 19, 27):
+        A = workloads.random_sgdia(g, pat, seed=5)
+        off = workloads.offsets(pat)
+        for s, d in enumerate(off):
+            for i in range(int(np.prod(g))):
+                xx, yy, zz = i // (g[1] * g[2]), (i // g[2]) % g[1], i % g[2]
+                if not (0 <= xx + d[0] < g[0] and 0 <= yy + d[1] < g[1] and 0 <= zz + d[2] < g[2]):
+                    assert A[s, i] == 0.0
