@@ -37,20 +37,26 @@
 //    the sentinel.  These accesses are device-coherent (agent scope), so no
 //    fences or flag counters are needed.  The sentinels for the next sweep on
 //    the same level are written by this sweep into that sweep's output.
-//  * Halo values are prefetched only PH = P/2 steps ahead (a tile must run
-//    that far behind its producer for the prefetch to find them written).
+//  * Halo values are prefetched PH = 4 steps ahead: enough to cover a
+//    device-coherent load (about a microsecond), while a tile must run only
+//    that far behind its producer for the prefetch to find them written.
 //    A loader lane that finds a value not yet written first waits for the
 //    value WF_AHEAD steps further along the same column and then refetches
 //    its other prefetched halo values: the tile then runs far enough behind
 //    its producer that later prefetches find their values written, instead
 //    of paying one coherent round trip per step.
 //  * The right-hand side is staged through LDS in chunks of 16 steps, loaded
-//    one chunk ahead as runs of 16 consecutive z per column; results leave
-//    through the LDS ring the same way, every 16 steps, together with the
-//    sentinels for the next sweep.  Per-step accesses to the natural-order
-//    vectors would touch one element of a different cache line per lane and
-//    keep hundreds of lines per tile alive in the L2 cache.  Only columns
-//    read by other tiles are also stored at once, device-coherently.
+//    one chunk ahead as runs of 16 consecutive z per column (two runs per
+//    step in the first half of a chunk, each placed in LDS four steps after
+//    its load); each lane writes its result over the right-hand-side slot it
+//    has just used, and the chunk's results leave the same way, two runs per
+//    step in the first half of the following chunk (before their slots are
+//    refilled), together with the sentinels for the next sweep.  Per-step accesses to the natural-order vectors would touch one
+//    element of a different cache line per lane and keep hundreds of lines
+//    per tile alive in the L2 cache; spreading the runs over the steps keeps
+//    them from holding up the in-order completion of the coefficient loads.
+//    Only columns read by other tiles are also stored at once,
+//    device-coherently.
 //  * Tiles are handed out by an atomic ticket in dependence order, so a
 //    persistent grid of any size always makes progress.  Waits are bounded
 //    by a watchdog that raises an error flag instead of hanging.
@@ -63,11 +69,15 @@
 namespace smg {
 
 constexpr int WF_HIST = 16;                // LDS ring rows (steps)
+constexpr int WF_CH = 16;                  // steps per chunk of right-hand side / results
 constexpr int WF_NL = WF_TX * WF_TY;       // lanes (columns) per tile
 constexpr int WF_NH = 104;                 // halo slots around a tile
 constexpr unsigned WF_SPIN_LIMIT = 1u << 21;
 #ifndef WF_LAG_EXTRA
 #define WF_LAG_EXTRA 2
+#endif
+#ifndef WF_PH
+#define WF_PH 4
 #endif
 constexpr unsigned WF_OOB = 0x80000000u;   // buffer offset outside every range
 constexpr int WF_SC1 = 16;                 // cache policy of device-coherent accesses
@@ -246,11 +256,11 @@ __global__ __launch_bounds__(WF_NL) void k_wavefront(WfArgs<typename WfVal<E>::V
   constexpr int RW = WF_NL + WF_NH + 1;  // ring row length (padded: column runs hit distinct banks)
   constexpr int HRW = WF_NL + 1;         // right-hand-side chunk row length (padded likewise)
   constexpr unsigned PACKB = WF_NL * 16u;
-  constexpr int PH = P / 2;                    // prefetch distance of halo values
+  constexpr int PH = WF_PH;                    // prefetch distance of halo values
   constexpr int WF_AHEAD = PH + WF_LAG_EXTRA;  // steps a stalled tile falls back behind its producer
-  static_assert(WF_HIST % P == 0 && PH >= 2 && WF_HIST > KB + 1, "ring too short");
+  static_assert(WF_HIST % P == 0 && WF_HIST % PH == 0 && PH >= 2 && WF_HIST > KB + 1, "ring too short");
   __shared__ V ring[WF_HIST * RW];
-  __shared__ V hbuf[2 * WF_HIST * HRW];  // right-hand side, two chunks of 16 steps
+  __shared__ V hbuf[2 * WF_CH * HRW];  // right-hand side then results, two chunks of 16 steps
   __shared__ unsigned s_ticket;
 
   const int tid = threadIdx.x;
@@ -283,8 +293,8 @@ __global__ __launch_bounds__(WF_NL) void k_wavefront(WfArgs<typename WfVal<E>::V
   const int hskew = (WX - sh * WY) * hqx + WY * hqy + KB;
   // column runs: in chunk transfers this thread moves step (tid % 16) of the
   // columns of lanes (lx = i, ly = tid / 16), i = 0..15
-  const int cy = tid / WF_HIST;
-  const int cr = tid % WF_HIST;
+  const int cy = tid / WF_CH;
+  const int cr = tid % WF_CH;
   unsigned cexp = 0, cnext = 0;  // bit i: that column is read by other tiles in this / the next sweep
 #pragma unroll
   for (int i = 0; i < WF_TX; ++i) {
@@ -327,7 +337,7 @@ __global__ __launch_bounds__(WF_NL) void k_wavefront(WfArgs<typename WfVal<E>::V
     const int nsteps = (NS + WF_HIST - 1) / WF_HIST * WF_HIST;
     u32x4 cf[P][NPK];
     u32x2 sdv[P];
-    V hb[PH], hc[WF_TX];
+    V hb[PH], hc[WF_TX / 2];
     V own_prev = V(0);
 
     auto step_of = [&](int k) { return DIR > 0 ? k : NS - 1 - k; };
@@ -341,43 +351,46 @@ __global__ __launch_bounds__(WF_NL) void k_wavefront(WfArgs<typename WfVal<E>::V
       if (T::HALF)
         sdv[j] = __builtin_amdgcn_raw_buffer_load_b64(rs, tid * 8u, sin ? (unsigned)s * (WF_NL * 8u) : WF_OOB, 0);
     };
-    // byte offset of step s of the column of lane (i, cy), or WF_OOB
-    auto run_off = [&](int i, int s) {
+    // byte offset of step s of the column of lane (i, cy), or WF_OOB.  The
+    // column's element offset and skew are linear in i; which columns lie in
+    // the grid is fixed per tile (bit i of rmask).
+    const unsigned rb0 = (unsigned)(((X * WF_TX - p0) * (long)ny + (Y * WF_TY + cy)) * nz);
+    const unsigned rdi = (unsigned)((long)ny * nz - (long)sh * nz);
+    const int rsk0 = WY * cy + KB;
+    unsigned rmask = 0;
+#pragma unroll
+    for (int i = 0; i < WF_TX; ++i) {
       const int xx = X * WF_TX + i, yy = Y * WF_TY + cy - sh * i;
-      const int z = s - ((WX - sh * WY) * i + WY * cy + KB);
-      const bool ok = xx < nx && yy >= 0 && yy < ny && z >= 0 && z < nz;
-      return ok ? (unsigned)((((xx - p0) * (long)ny + yy) * nz + z) * (long)sizeof(V)) : WF_OOB;
+      rmask |= (xx < nx && yy >= 0 && yy < ny) ? 1u << i : 0u;
+    }
+    auto run_off = [&](int i, int s) {
+      const int z = s - rsk0 - (WX - sh * WY) * i;
+      const bool ok = ((rmask >> i) & 1u) && (unsigned)z < (unsigned)nz;
+      return ok ? (rb0 + (unsigned)i * rdi + (unsigned)z) * (unsigned)sizeof(V) : WF_OOB;
     };
-    // right-hand side of chunk c: load as column runs, then place in LDS
-    auto hchunk_load = [&](int c) {
-      const int s = step_of(c * WF_HIST + cr);
-#pragma unroll
-      for (int i = 0; i < WF_TX; ++i) hc[i] = bld<V, 0>(rh, run_off(i, s));
+    // right-hand side of chunk c: column runs i loaded into hc[i], then
+    // placed in LDS
+    auto hrun_load = [&](int c, int i) { hc[i % (WF_TX / 2)] = bld<V, 0>(rh, run_off(i, step_of(c * WF_CH + cr))); };
+    auto hrun_put = [&](int c, int i) { hbuf[((c & 1) * WF_CH + cr) * HRW + i * WF_TY + cy] = hc[i % (WF_TX / 2)]; };
+    // results of chunk c (in its hbuf half): column run i out, with the
+    // sentinels of the next sweep
+    auto xrun_out = [&](int c, int i) {
+      const unsigned off = run_off(i, step_of(c * WF_CH + cr));
+      const V xo = hbuf[((c & 1) * WF_CH + cr) * HRW + i * WF_TY + cy];
+      bst<0>(xo, rx, (cexp >> i) & 1u ? WF_OOB : off);
+      bst<0>(B::val(B::sent), rn, (cnext >> i) & 1u ? off : WF_OOB);
     };
-    auto hchunk_put = [&](int c) {
-#pragma unroll
-      for (int i = 0; i < WF_TX; ++i) hbuf[((c & 1) * WF_HIST + cr) * HRW + i * WF_TY + cy] = hc[i];
-    };
-    // results of chunk c (in the ring) out as column runs, with the sentinels
-    // of the next sweep and, with ADD, addout = addv + x
-    auto xchunk_out = [&](int c) {
-      const int s = step_of(c * WF_HIST + cr);
-      V xo[WF_TX];
+    // ADD: addout = addv + x for all runs of chunk c
+    auto add_out = [&](int c) {
+      V av[WF_TX];
       unsigned off[WF_TX];
 #pragma unroll
       for (int i = 0; i < WF_TX; ++i) {
-        off[i] = run_off(i, s);
-        xo[i] = ring[cr * RW + i * WF_TY + cy];
-        bst<0>(xo[i], rx, (cexp >> i) & 1u ? WF_OOB : off[i]);
-        bst<0>(B::val(B::sent), rn, (cnext >> i) & 1u ? off[i] : WF_OOB);
+        off[i] = run_off(i, step_of(c * WF_CH + cr));
+        av[i] = bld<V, 0>(rav, off[i]);
       }
-      if (ADD) {
-        V av[WF_TX];
 #pragma unroll
-        for (int i = 0; i < WF_TX; ++i) av[i] = bld<V, 0>(rav, off[i]);
-#pragma unroll
-        for (int i = 0; i < WF_TX; ++i) bst<0>(av[i] + xo[i], rao, off[i]);
-      }
+      for (int i = 0; i < WF_TX; ++i) bst<0>(av[i] + hbuf[((c & 1) * WF_CH + cr) * HRW + i * WF_TY + cy], rao, off[i]);
     };
     auto halo_fetch = [&](int k, int j) {
       const int s = step_of(k);
@@ -427,54 +440,85 @@ __global__ __launch_bounds__(WF_NL) void k_wavefront(WfArgs<typename WfVal<E>::V
     for (int j = 0; j < P; ++j) prefetch(j, j);
 #pragma unroll
     for (int j = 0; j < PH; ++j) halo_fetch(j, j);
-    hchunk_load(0);
-    hchunk_put(0);
+#pragma unroll
+    for (int i = 0; i < WF_TX; ++i) {
+      hrun_load(0, i);
+      hrun_put(0, i);
+    }
     halo_put(0, 0);
     __syncthreads();
 
     for (int k0 = 0; k0 < nsteps; k0 += WF_HIST) {
-      const int ch = k0 / WF_HIST;
-      hchunk_load(ch + 1);
 #pragma unroll
       for (int j = 0; j < WF_HIST; ++j) {
         const int k = k0 + j;
         const int jp = j % P;
+        const int jj = j % WF_CH;
+        const int ch = k / WF_CH;
+        // the previous chunk's results, runs 2jj and 2jj+1 (a chunk before the
+        // first maps every run outside the buffers), out before their slots
+        // are refilled below
+        if (jj < WF_CH / 2) {
+          if (ADD && jj == 0) add_out(ch - 1);
+          xrun_out(ch - 1, 2 * jj);
+          xrun_out(ch - 1, 2 * jj + 1);
+        }
+        // the next chunk's right-hand side: runs 2(jj-4), 2(jj-4)+1 into LDS,
+        // then runs 2jj, 2jj+1 from HBM (their registers were just freed)
+        if (jj >= 4 && jj < WF_CH / 2 + 4) {
+          hrun_put(ch + 1, 2 * (jj - 4));
+          hrun_put(ch + 1, 2 * (jj - 4) + 1);
+        }
+        if (jj < WF_CH / 2) {
+          hrun_load(ch + 1, 2 * jj);
+          hrun_load(ch + 1, 2 * jj + 1);
+        }
         const int s = step_of(k);
         const int z = s - skew;
         const bool act = colv && z >= 0 && z < nz;
         // the row update, in canonical order of the triangle's offsets
         const V sc = T::HALF ? __uint_as_float(sdv[jp].x) : V(1);
-        V t = hbuf[((ch & 1) * WF_HIST + j) * HRW + tid];
+        V& hslot = hbuf[((ch & 1) * WF_CH + jj) * HRW + tid];
+        V t = hslot;
+        // all neighbour values first (one wait), then the chain of fmas
+        V val[NT];
 #pragma unroll
         for (int m = 0; m < NT; ++m) {
           const int so = DIR > 0 ? m : C + 1 + m;
           const int dx = pat_off(PAT, so, 0), dy = pat_off(PAT, so, 1), dz = pat_off(PAT, so, 2);
-          V val;
           if (dx == 0 && dy == 0) {
-            val = own_prev;
+            val[m] = own_prev;
           } else {
             const int c = col_of(DIR * dx, DIR * dy);
             const int back = DIR * (WX * dx + WY * dy + dz);  // in [-KB, -1]
-            val = ring[((j + back + WF_HIST) % WF_HIST) * RW + nidx[c]];
+            val[m] = ring[((j + back + WF_HIST) % WF_HIST) * RW + nidx[c]];
           }
+        }
+#pragma unroll
+        for (int m = 0; m < NT; ++m) {
           const V cm = T::HALF ? sc * T::get(cf[jp], m) : T::get(cf[jp], m);
-          t = fma(-cm, val, t);
+          t = fma(-cm, val[m], t);
         }
         const V dv = T::HALF ? __uint_as_float(sdv[jp].y) : T::get(cf[jp], NT);
         const V xv = UNITD ? t : t * dv;
         const V xr = act ? xv : V(0);
         own_prev = xr;
         ring[j * RW + tid] = xr;
+        hslot = xr;
         // columns read by other tiles leave at once, device-coherently
         bst<WF_SC1>(xv, rx, exported && act ? (vo + (unsigned)z) * (unsigned)sizeof(V) : WF_OOB);
-        if (j == WF_HIST / 2) hchunk_put(ch + 1);
         halo_put(k + 1, (j + 1) % PH);
         halo_fetch(k + PH, j % PH);
         prefetch(k + P, jp);
         __syncthreads();
       }
-      xchunk_out(ch);
-      __syncthreads();
+    }
+    // the last chunk's results
+    {
+      const int cl = nsteps / WF_CH - 1;
+#pragma unroll
+      for (int i = 0; i < WF_TX; ++i) xrun_out(cl, i);
+      if (ADD) add_out(cl);
     }
   }
   if (tid == 0) {

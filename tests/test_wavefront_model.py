@@ -34,7 +34,8 @@ import workloads
 TX = TY = 16
 NL = TX * TY
 NH = 104
-HIST = 16
+HIST = 16    # LDS ring rows
+CH = 16      # steps per chunk of right-hand side / results
 
 
 def pat_has(pat, d):
@@ -157,7 +158,7 @@ def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf):
     exp_now = np.array([exported(pat, a, b, sh, direction) for a, b in zip(lx, ly)])
     exp_next = np.array([exported(pat, a, b, sh, nxt_dir) for a, b in zip(lx, ly)]) if nxt_buf is not None \
         else np.zeros(NL, bool)
-    run_y, run_r = lanes // HIST, lanes % HIST   # column-run roles of the threads
+    run_y, run_r = lanes // CH, lanes % CH   # column-run roles of the threads
     # neighbour column LDS indices
     nidx = {}
     for c in range(4):
@@ -202,7 +203,8 @@ def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf):
         ring = np.full((HIST, RW), np.nan)
         ring_pt = np.full((HIST, RW), -2, np.int64)    # point index, or -1 for "zero"
         ring_it = np.full((HIST, RW), -10 ** 9, np.int64)
-        hbuf = np.full(2 * HIST * HRW, np.nan)
+        hbuf = np.full(2 * CH * HRW, np.nan)
+        hbuf_pt = np.full(2 * CH * HRW, -2, np.int64)   # point whose result a slot holds (-1: none)
         own_prev = np.zeros(NL)
 
         def step_of(k):
@@ -217,29 +219,32 @@ def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf):
                 return gi
             return -1
 
-        def hchunk(c):
+        def hrun_put(c, i):
             for t in range(NL):
-                s = step_of(c * HIST + run_r[t])
-                for i in range(TX):
-                    gi = run_off(i, run_y[t], s)
-                    li = ((c & 1) * HIST + run_r[t]) * HRW + i * TY + run_y[t]
-                    assert 0 <= li < 2 * HIST * HRW
-                    hbuf[li] = h[gi] if gi >= 0 else 0.0
+                s = step_of(c * CH + run_r[t])
+                gi = run_off(i, run_y[t], s)
+                li = ((c & 1) * CH + run_r[t]) * HRW + i * TY + run_y[t]
+                assert 0 <= li < 2 * CH * HRW
+                hbuf[li] = h[gi] if gi >= 0 else 0.0
+                hbuf_pt[li] = -3   # holds a right-hand side now
 
-        def xchunk_out(c):
+        def xrun_out(c, i):
+            # results of chunk c, run i, from the hbuf slots the lanes wrote
             for t in range(NL):
-                s = step_of(c * HIST + run_r[t])
-                for i in range(TX):
-                    gi = run_off(i, run_y[t], s)
-                    lane = i * TY + run_y[t]
-                    if gi < 0:
-                        continue
-                    assert ring_it[run_r[t], lane] == c * HIST + run_r[t] and ring_pt[run_r[t], lane] == gi
-                    if not exp_now[lane]:
-                        assert np.isnan(x[gi]) or x[gi] == 0.0 or not sent_at_start[gi]
-                        x[gi] = ring[run_r[t], lane]
-                    else:
-                        assert x[gi] == ring[run_r[t], lane]
+                s = step_of(c * CH + run_r[t])
+                li = ((c & 1) * CH + run_r[t]) * HRW + i * TY + run_y[t]
+                gi = run_off(i, run_y[t], s)
+                lane = i * TY + run_y[t]
+                if gi < 0:
+                    continue
+                assert hbuf_pt[li] == gi, "result slot holds another point"
+                if not exp_now[lane]:
+                    assert np.isnan(x[gi]) or x[gi] == 0.0 or not sent_at_start[gi]
+                    x[gi] = hbuf[li]
+                else:
+                    assert x[gi] == hbuf[li]
+                if nxt_buf is not None and exported(pat, i, run_y[t], sh, nxt_dir):
+                    pref[gi] = True
                     if exported(pat, i, run_y[t], sh, nxt_dir) and nxt_buf is not None:
                         pref[gi] = True
 
@@ -262,12 +267,18 @@ def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf):
                     ring[r, NL + hs], ring_pt[r, NL + hs] = 0.0, -1
                 ring_it[r, NL + hs] = k
 
-        hchunk(0)
+        for i in range(TX):
+            hrun_put(0, i)
         halo_put(0)
         for k in range(nsteps):
             j = k % HIST
-            if j == 0:
-                hchunk(k // HIST + 1)
+            jj, ch = k % CH, k // CH
+            if jj < CH // 2:                      # the previous chunk's results, two runs per step
+                xrun_out(ch - 1, 2 * jj)
+                xrun_out(ch - 1, 2 * jj + 1)
+            if 4 <= jj < CH // 2 + 4:             # next chunk's right-hand side, four steps after its load
+                hrun_put(ch + 1, 2 * (jj - 4))
+                hrun_put(ch + 1, 2 * (jj - 4) + 1)
             s = step_of(k)
             z = s - skew
             act = colv & (z >= 0) & (z < nz)
@@ -276,8 +287,9 @@ def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf):
                 i = cb[l] + z[l]
                 assert lo_i <= i < hi_i, "point offset outside the buffer window"
                 pkidx[i] = (t * NS + s) * NL + l
-                tv = hbuf[((k // HIST) & 1) * HIST * HRW + j * HRW + l]
-                assert tv == h[i], "right-hand side chunk holds another point"
+                slot = ((k // CH) & 1) * CH * HRW + (k % CH) * HRW + l
+                tv = hbuf[slot]
+                assert tv == h[i] and hbuf_pt[slot] == -3, "right-hand side chunk holds another point"
                 
                 for so in T:
                     dx, dy, dz = (int(v) for v in off[so])
@@ -306,11 +318,15 @@ def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf):
                     x[i] = xr[l]   # read by other tiles: written at once
             own_prev = xr
             ring[j, :NL] = xr
+            for l in range(NL):   # each lane's result over its right-hand-side slot
+                slot = (ch & 1) * CH * HRW + jj * HRW + l
+                hbuf[slot] = xr[l]
+                hbuf_pt[slot] = (cb[l] + z[l]) if act[l] else -1
             ring_pt[j, :NL] = np.where(act, cb + z, -1)
             ring_it[j, :NL] = k
             halo_put(k + 1)
-            if j == HIST - 1:
-                xchunk_out(k // HIST)
+        for i in range(TX):
+            xrun_out(nsteps // CH - 1, i)
     return x, pref, pkidx
 
 
