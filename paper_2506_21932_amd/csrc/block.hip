@@ -1,0 +1,559 @@
+// 3x3 block systems (vector PDEs, the block operators of Sec. 4.2.3 and the
+// elasticity problem of Sec. 5.1): point-block SpMV and residual, the input
+// of the backward post-smoothing sweep, and the dependence-preserving
+// point-block Gauss-Seidel sweep (Sec. 4.4 with 3x3 blocks).
+//
+// Storage: entry (r, c) of the block of offset s at A[(s*9 + r*3 + c)*N + i];
+// vectors interleaved v[i*3 + c].  Per scalar row r of a block row the
+// accumulation runs over neighbour blocks in canonical order and, inside a
+// block, over columns c in order, with fma.
+//
+// The block sweep follows the scalar wavefront design (csrc/wavefront.hip):
+// z-columns as lanes, sheared tiles in dependence order taken by atomic
+// ticket, per-lane skew with the 3d27 hyperplane weights (4, 2, 1), an LDS
+// ring for neighbour values plus a halo of other tiles' columns fetched
+// device-coherently and checked against a signalling-NaN sentinel.  A node
+// carries 3 values and its row needs 13 coefficient blocks and the inverse
+// diagonal block (126 numbers, ~1 KB in FP64), so a tile is one wavefront of
+// 8 x 8 columns (no workgroup barrier needed) and the coefficients stream
+// through a ring of registers D blocks ahead.
+#include "smg_common.h"
+#include "smg_kernels.h"
+
+namespace smg {
+
+// ------------------------------------------------------------ SpMV / residual
+template <class M, bool RES>
+__global__ __launch_bounds__(256) void k_bspmv(Grid g, M m, const typename M::V* __restrict__ x,
+                                               const typename M::V* __restrict__ b, typename M::V* __restrict__ y) {
+  using V = typename M::V;
+  const long N = g.N();
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  const int X = (int)(i / ((long)g.ny * g.nz)), Y = (int)((i / g.nz) % g.ny), Z = (int)(i % g.nz);
+  const long nyz = (long)g.ny * g.nz;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    V acc = V(0);
+#pragma unroll
+    for (int s = 0; s < 27; ++s) {
+      const int dx = pat_off(27, s, 0), dy = pat_off(27, s, 1), dz = pat_off(27, s, 2);
+      if (!in_grid(g, X + dx, Y + dy, Z + dz)) continue;
+      const long j = i + dx * nyz + dy * g.nz + dz;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc = fma(m(s * 9 + r * 3 + c, r, i), x[j * 3 + c], acc);
+    }
+    y[i * 3 + r] = RES ? b[i * 3 + r] - acc : acc;
+  }
+}
+
+template <class M>
+hipError_t launch_bspmv(const Grid& g, const M& m, const typename M::V* x, const typename M::V* b,
+                        typename M::V* y, bool res, hipStream_t st) {
+  const dim3 grid((unsigned)((g.N() + 255) / 256)), blk(256);
+  if (res)
+    hipLaunchKernelGGL((k_bspmv<M, true>), grid, blk, 0, st, g, m, x, b, y);
+  else
+    hipLaunchKernelGGL((k_bspmv<M, false>), grid, blk, 0, st, g, m, x, b, y);
+  return hipGetLastError();
+}
+
+// h = f - sum over lower neighbour blocks of A_ij u_j (old values): the
+// terms a backward sweep takes from before the sweep, in the order the
+// sequential sweep applies them (first group of the row update).
+template <class M>
+__global__ __launch_bounds__(256) void k_blower(Grid g, M m, const typename M::V* __restrict__ f,
+                                                const typename M::V* __restrict__ u, typename M::V* __restrict__ h) {
+  using V = typename M::V;
+  const long N = g.N();
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  const int X = (int)(i / ((long)g.ny * g.nz)), Y = (int)((i / g.nz) % g.ny), Z = (int)(i % g.nz);
+  const long nyz = (long)g.ny * g.nz;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    V t = f[i * 3 + r];
+#pragma unroll
+    for (int s = 0; s < 13; ++s) {
+      const int dx = pat_off(27, s, 0), dy = pat_off(27, s, 1), dz = pat_off(27, s, 2);
+      if (!in_grid(g, X + dx, Y + dy, Z + dz)) continue;
+      const long j = i + dx * nyz + dy * g.nz + dz;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) t = fma(-m(s * 9 + r * 3 + c, r, i), u[j * 3 + c], t);
+    }
+    h[i * 3 + r] = t;
+  }
+}
+
+template <class M>
+hipError_t launch_blower(const Grid& g, const M& m, const typename M::V* f, const typename M::V* u,
+                         typename M::V* h, hipStream_t st) {
+  hipLaunchKernelGGL((k_blower<M>), dim3((unsigned)((g.N() + 255) / 256)), dim3(256), 0, st, g, m, f, u, h);
+  return hipGetLastError();
+}
+
+#define SMG_BINST(M)                                                                                           \
+  template hipError_t launch_bspmv<M>(const Grid&, const M&, const M::V*, const M::V*, M::V*, bool, hipStream_t); \
+  template hipError_t launch_blower<M>(const Grid&, const M&, const M::V*, const M::V*, M::V*, hipStream_t);
+SMG_BINST(BMatD)
+SMG_BINST(BMatF)
+SMG_BINST(BMatH)
+#undef SMG_BINST
+
+// ------------------------------------------------------------ block sweep
+constexpr int BW_TX = 8, BW_TY = 8, BW_NL = 64;
+constexpr int BW_NH = 56;    // halo slots around an 8 x 8 tile
+constexpr int BW_HIST = 16;  // LDS ring rows (steps)
+constexpr int BW_PH = 4;     // prefetch distance (steps) of right-hand side and halo values
+constexpr int BW_UNROLL = 4;
+constexpr int BW_WX = 4, BW_WY = 2, BW_KB = 7;  // 3d27 hyperplane weights, largest lower step distance
+constexpr unsigned BW_SPIN_LIMIT = 1u << 21;
+constexpr unsigned BW_OOB = 0x80000000u;
+constexpr int BW_SC1 = 16;
+
+typedef unsigned bu32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned bu32x4 __attribute__((ext_vector_type(4)));
+
+void bwf_tiling(const Grid& g, WfTiling* t) {
+  t->sh = g.ny <= BW_TY ? 0 : 1;
+  t->ntx = (g.nx + BW_TX - 1) / BW_TX;
+  t->nty = (g.ny + t->sh * (BW_TX - 1) + BW_TY - 1) / BW_TY;
+  t->ns = g.nz + (BW_WX - t->sh * BW_WY) * (BW_TX - 1) + BW_WY * (BW_TY - 1) + 2 * BW_KB;
+  t->nsk = (long)t->ntx * t->nty * t->ns * BW_NL;
+}
+
+// Packs of the block sweep data: 13 triangle blocks then the inverse
+// diagonal block ("group" 13).  FP64: 5 packs per group (9 of 10 doubles);
+// FP32: 3 (9 of 12 floats); FP16: 2 packs per triangle block (9 halves, then
+// the 3 FP32 row scales at byte 20) and 3 FP32 packs for the inverse.
+__host__ __device__ constexpr int bwf_gpc(int ebytes) { return ebytes == 8 ? 5 : (ebytes == 4 ? 3 : 2); }
+__host__ __device__ constexpr int bwf_gpd(int ebytes) { return ebytes == 8 ? 5 : 3; }
+__host__ __device__ constexpr int bwf_npk(int ebytes) { return 13 * bwf_gpc(ebytes) + bwf_gpd(ebytes); }
+int bwf_pack_count(int ebytes) { return bwf_npk(ebytes); }
+
+__host__ __device__ constexpr int bw_col_dx(int c) { return c == 3 ? 0 : -1; }
+__host__ __device__ constexpr int bw_col_dy(int c) { return c == 3 ? -1 : c - 1; }
+__host__ __device__ constexpr int bw_col_of(int dx, int dy) { return dx == -1 ? dy + 1 : (dy == -1 ? 3 : -1); }
+
+__host__ __device__ constexpr int bwf_halo_slot(int qx, int qy) {
+  return qx == -1 ? qy + 2
+                  : (qx == BW_TX ? 14 + qy
+                                 : (qy < 0 ? 24 + 2 * qx + (qy + 2) : 40 + 2 * qx + (qy - BW_TY)));
+}
+__device__ inline void bwf_halo_pos(int hs, int* qx, int* qy) {
+  if (hs < 12) {
+    *qx = -1;
+    *qy = hs - 2;
+  } else if (hs < 24) {
+    *qx = BW_TX;
+    *qy = hs - 14;
+  } else if (hs < 40) {
+    *qx = (hs - 24) / 2;
+    *qy = (hs - 24) % 2 - 2;
+  } else {
+    *qx = (hs - 40) / 2;
+    *qy = BW_TY + (hs - 40) % 2;
+  }
+}
+__device__ inline bool bwf_halo_used(int dir, int sh, int qx, int qy) {
+  for (int c = 0; c < 4; ++c) {
+    const int cx = dir * bw_col_dx(c), cy = dir * bw_col_dy(c);
+    const int lx = qx - cx, ly = qy - cy - sh * cx;
+    if (lx >= 0 && lx < BW_TX && ly >= 0 && ly < BW_TY) return true;
+  }
+  return false;
+}
+__device__ inline bool bwf_exported(int dir, int lx, int ly, int sh) {
+  for (int c = 0; c < 4; ++c) {
+    const int cx = dir * bw_col_dx(c), cy = dir * bw_col_dy(c);
+    const int qx = lx - cx, qy = ly - cy - sh * cx;
+    if (qx < 0 || qx >= BW_TX || qy < 0 || qy >= BW_TY) return true;
+  }
+  return false;
+}
+
+__device__ inline __amdgpu_buffer_rsrc_t bw_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <class V, int CP>
+__device__ inline V bw_ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  if constexpr (sizeof(V) == 8)
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, CP));
+  else
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, CP));
+}
+template <int CP, class V>
+__device__ inline void bw_st(V v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  if constexpr (sizeof(V) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bu32x2, v), r, off, 0, CP);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, CP);
+}
+
+// element e (0..8, row-major r*3 + c) of a coefficient group held in packs p[]
+template <class E>
+__device__ inline typename WfVal<E>::V bw_coef(const bu32x4* p, int e);
+template <>
+__device__ inline double bw_coef<double>(const bu32x4* p, int e) {
+  const bu32x4 w = p[e / 2];
+  return e % 2 == 0 ? __builtin_bit_cast(double, bu32x2{w.x, w.y}) : __builtin_bit_cast(double, bu32x2{w.z, w.w});
+}
+template <>
+__device__ inline float bw_coef<float>(const bu32x4* p, int e) {
+  return __uint_as_float(p[e / 4][e % 4]);
+}
+template <>
+__device__ inline float bw_coef<__half>(const bu32x4* p, int e) {
+  const unsigned w = p[e / 8][(e % 8) / 2];
+  const float h = __half2float(__ushort_as_half((unsigned short)(e % 2 == 0 ? (w & 0xffffu) : (w >> 16))));
+  const int r = e / 3;  // row scale at byte 20 + 4r of the group
+  const float s = __uint_as_float(p[(20 + 4 * r) / 16][((20 + 4 * r) % 16) / 4]);
+  return s * h;
+}
+// element e of the inverse diagonal block (FP64 for E = double, else FP32)
+template <class E>
+__device__ inline typename WfVal<E>::V bw_dinv(const bu32x4* p, int e) {
+  if constexpr (sizeof(E) == 8)
+    return bw_coef<double>(p, e);
+  else
+    return __uint_as_float(p[e / 4][e % 4]);
+}
+
+template <int DIR, class E>
+__global__ __launch_bounds__(BW_NL) void k_bwavefront(WfArgs<typename WfVal<E>::V> a) {
+  using V = typename WfVal<E>::V;
+  using B = VBits<V>;
+  constexpr int GPC = bwf_gpc(sizeof(E)), GPD = bwf_gpd(sizeof(E)), NPK = bwf_npk(sizeof(E));
+  constexpr int GPM = GPC > GPD ? GPC : GPD;
+  constexpr int D = sizeof(E) == 8 ? 7 : 14;  // coefficient groups fetched ahead (divides 14)
+  constexpr int RW = (BW_NL + BW_NH) * 3 + 1;
+  constexpr unsigned PACKB = BW_NL * 16u;
+  constexpr int VS = (int)sizeof(V);
+  __shared__ V ring[BW_HIST * RW];
+  __shared__ unsigned s_ticket;
+
+  const int tid = threadIdx.x;
+  const int lx = tid / BW_TY, ly = tid % BW_TY;
+  const int sh = a.t.sh;
+  const int skew = (BW_WX - sh * BW_WY) * lx + BW_WY * ly + BW_KB;
+  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  const int NS = a.t.ns;
+  const unsigned ntiles = (unsigned)(a.t.ntx * a.t.nty);
+  const bool exported = bwf_exported(DIR, lx, ly, sh);
+  const bool exp_next = a.next != nullptr && bwf_exported(a.next_dir, lx, ly, sh);
+  int nidx[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int cx = DIR * bw_col_dx(c), cy = DIR * bw_col_dy(c);
+    const int qx = lx + cx, qy = ly + cy + sh * cx;
+    const bool in = qx >= 0 && qx < BW_TX && qy >= 0 && qy < BW_TY;
+    nidx[c] = in ? qx * BW_TY + qy : BW_NL + bwf_halo_slot(qx, qy);
+  }
+  const int hs = tid;
+  int hqx = 0, hqy = 0;
+  bool hrole = false;
+  if (hs < BW_NH) {
+    bwf_halo_pos(hs, &hqx, &hqy);
+    hrole = bwf_halo_used(DIR, sh, hqx, hqy);
+  }
+  const int hskew = (BW_WX - sh * BW_WY) * hqx + BW_WY * hqy + BW_KB;
+
+  for (;;) {
+    if (tid == 0) s_ticket = atomicAdd(&a.ctr[0], 1u);
+    __syncthreads();
+    const unsigned ticket = s_ticket;
+    __syncthreads();
+    if (ticket >= ntiles) break;
+    const unsigned tile = DIR > 0 ? ticket : ntiles - 1u - ticket;
+    const int X = (int)(tile / (unsigned)a.t.nty), Y = (int)(tile % (unsigned)a.t.nty);
+    const int xt = X * BW_TX + lx, yt = Y * BW_TY + ly - sh * lx;
+    const bool colv = xt < nx && yt >= 0 && yt < ny;
+    const int p0 = X * BW_TX > 0 ? X * BW_TX - 1 : 0;
+    const int p1 = X * BW_TX + BW_TX + 1 < nx ? X * BW_TX + BW_TX + 1 : nx;
+    const long pl = (long)ny * nz;
+    const unsigned vbytes = (unsigned)((p1 - p0) * pl * 3 * (long)VS);
+    const long vb = p0 * pl * 3;
+    const auto rh = bw_rsrc(a.h + vb, vbytes);
+    const auto rx = bw_rsrc(a.x + vb, vbytes);
+    const auto rn = bw_rsrc((a.next != nullptr ? a.next : a.x) + vb, a.next != nullptr ? vbytes : 0u);
+    const unsigned vo = colv ? (unsigned)(((xt - p0) * (long)ny + yt) * nz) : 0u;
+    const int gx = X * BW_TX + hqx, gy = Y * BW_TY + hqy - sh * hqx;
+    const bool hcolv = hrole && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    const unsigned hvo = hcolv ? (unsigned)(((gx - p0) * (long)ny + gy) * nz) : 0u;
+    const unsigned tbytes = (unsigned)NS * NPK * PACKB;
+    const auto rp = bw_rsrc((const char*)a.pk + (size_t)tile * tbytes, tbytes);
+    const int nsteps = (NS + BW_UNROLL - 1) / BW_UNROLL * BW_UNROLL;
+
+    auto step_of = [&](int k) { return DIR > 0 ? k : NS - 1 - k; };
+    // byte offset of component 0 of the node of this lane at iteration k
+    auto node_off = [&](int k) {
+      const int z = step_of(k) - skew;
+      return colv && z >= 0 && z < nz ? (vo + (unsigned)z) * 3u * (unsigned)VS : BW_OOB;
+    };
+    auto halo_off = [&](int k) {
+      const int s = step_of(k);
+      const int hz = s - hskew;
+      return s >= 0 && s < NS && hcolv && hz >= 0 && hz < nz ? (hvo + (unsigned)hz) * 3u * (unsigned)VS : BW_OOB;
+    };
+    // coefficient group g of iteration k (sequence k*14 + g) into slot buf[(k*14 + g) % D]
+    bu32x4 buf[D][GPM];
+    auto grp_fetch = [&](int k, int g, int slot) {
+      const int s = step_of(k);
+      const unsigned so = s >= 0 && s < NS ? (unsigned)s * (NPK * PACKB) : BW_OOB;
+      const int np = g < 13 ? GPC : GPD;
+#pragma unroll
+      for (int p = 0; p < np; ++p)
+        buf[slot][p] = __builtin_bit_cast(
+            bu32x4, __builtin_amdgcn_raw_buffer_load_b128(rp, tid * 16u, so + (unsigned)(g * GPC + p) * PACKB, 0));
+    };
+    V hv[BW_PH][3], hb[BW_PH][3];
+    auto h_fetch = [&](int k, int j) {
+      const unsigned off = node_off(k);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) hv[j][r] = bw_ld<V, 0>(rh, off == BW_OOB ? BW_OOB : off + r * VS);
+    };
+    auto halo_fetch = [&](int k, int j) {
+      const unsigned off = halo_off(k);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) hb[j][r] = bw_ld<V, BW_SC1>(rx, off == BW_OOB ? BW_OOB : off + r * VS);
+    };
+    auto halo_put = [&](int k, int j) {
+      const unsigned off = halo_off(k);
+      V v0 = hb[j][0], v1 = hb[j][1], v2 = hb[j][2];
+      if (off != BW_OOB &&
+          (B::bits(v0) == B::sent || B::bits(v1) == B::sent || B::bits(v2) == B::sent)) {
+        unsigned spins = 0;
+        do {
+          __builtin_amdgcn_s_sleep(1);
+          v0 = bw_ld<V, BW_SC1>(rx, off);
+          v1 = bw_ld<V, BW_SC1>(rx, off + VS);
+          v2 = bw_ld<V, BW_SC1>(rx, off + 2 * VS);
+          // once any wait has timed out, stop waiting anywhere
+          if ((spins & 1023u) == 1023u &&
+              (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u))
+            spins = BW_SPIN_LIMIT;
+        } while ((B::bits(v0) == B::sent || B::bits(v1) == B::sent || B::bits(v2) == B::sent) &&
+                 ++spins < BW_SPIN_LIMIT);
+        if (spins >= BW_SPIN_LIMIT) atomicOr(a.err, 1u);
+      }
+      if (hrole) {
+        V* rr = ring + (k % BW_HIST) * RW + (BW_NL + hs) * 3;
+        const bool ok = off != BW_OOB;
+        rr[0] = ok ? v0 : V(0);
+        rr[1] = ok ? v1 : V(0);
+        rr[2] = ok ? v2 : V(0);
+      }
+    };
+
+#pragma unroll
+    for (int g = 0; g < D; ++g) grp_fetch(0, g, g);
+#pragma unroll
+    for (int j = 0; j < BW_PH; ++j) {
+      h_fetch(j, j);
+      halo_fetch(j, j);
+    }
+    halo_put(0, 0);
+    V own0 = V(0), own1 = V(0), own2 = V(0);
+    __syncthreads();
+
+    for (int k0 = 0; k0 < nsteps; k0 += BW_UNROLL) {
+#pragma unroll
+      for (int j = 0; j < BW_UNROLL; ++j) {
+        const int k = k0 + j;
+        const int jp = j % BW_PH;
+        V t0 = hv[jp][0], t1 = hv[jp][1], t2 = hv[jp][2];
+#pragma unroll
+        for (int g = 0; g < 14; ++g) {
+          const int slot = g % D;  // (k*14 + g) % D, 14 being a multiple of D
+          // the group D positions ahead in the sequence
+          const int gn = g + D;
+          if (g < 13) {
+            const int so = DIR > 0 ? g : 14 + g;
+            const int dx = pat_off(27, so, 0), dy = pat_off(27, so, 1), dz = pat_off(27, so, 2);
+            V u0, u1, u2;
+            if (dx == 0 && dy == 0) {
+              u0 = own0;
+              u1 = own1;
+              u2 = own2;
+            } else {
+              const int c = bw_col_of(DIR * dx, DIR * dy);
+              const int back = DIR * (BW_WX * dx + BW_WY * dy + dz);  // in [-KB, -1]
+              const V* rr = ring + ((k + back + BW_HIST) % BW_HIST) * RW + nidx[c] * 3;
+              u0 = rr[0];
+              u1 = rr[1];
+              u2 = rr[2];
+            }
+            t0 = fma(-bw_coef<E>(buf[slot], 0), u0, t0);
+            t0 = fma(-bw_coef<E>(buf[slot], 1), u1, t0);
+            t0 = fma(-bw_coef<E>(buf[slot], 2), u2, t0);
+            t1 = fma(-bw_coef<E>(buf[slot], 3), u0, t1);
+            t1 = fma(-bw_coef<E>(buf[slot], 4), u1, t1);
+            t1 = fma(-bw_coef<E>(buf[slot], 5), u2, t1);
+            t2 = fma(-bw_coef<E>(buf[slot], 6), u0, t2);
+            t2 = fma(-bw_coef<E>(buf[slot], 7), u1, t2);
+            t2 = fma(-bw_coef<E>(buf[slot], 8), u2, t2);
+          } else {
+            const V x0 = fma(bw_dinv<E>(buf[slot], 2), t2, fma(bw_dinv<E>(buf[slot], 1), t1, bw_dinv<E>(buf[slot], 0) * t0));
+            const V x1 = fma(bw_dinv<E>(buf[slot], 5), t2, fma(bw_dinv<E>(buf[slot], 4), t1, bw_dinv<E>(buf[slot], 3) * t0));
+            const V x2 = fma(bw_dinv<E>(buf[slot], 8), t2, fma(bw_dinv<E>(buf[slot], 7), t1, bw_dinv<E>(buf[slot], 6) * t0));
+            t0 = x0;
+            t1 = x1;
+            t2 = x2;
+          }
+          grp_fetch(gn < 14 ? k : k + 1, gn % 14, slot);
+        }
+        const unsigned off = node_off(k);
+        const bool act = off != BW_OOB;
+        own0 = act ? t0 : V(0);
+        own1 = act ? t1 : V(0);
+        own2 = act ? t2 : V(0);
+        V* rw = ring + (k % BW_HIST) * RW + tid * 3;
+        rw[0] = own0;
+        rw[1] = own1;
+        rw[2] = own2;
+        const unsigned oc = exported ? off : BW_OOB, op = exported ? BW_OOB : off;
+        bw_st<BW_SC1>(t0, rx, oc == BW_OOB ? BW_OOB : oc);
+        bw_st<BW_SC1>(t1, rx, oc == BW_OOB ? BW_OOB : oc + VS);
+        bw_st<BW_SC1>(t2, rx, oc == BW_OOB ? BW_OOB : oc + 2 * VS);
+        bw_st<0>(t0, rx, op == BW_OOB ? BW_OOB : op);
+        bw_st<0>(t1, rx, op == BW_OOB ? BW_OOB : op + VS);
+        bw_st<0>(t2, rx, op == BW_OOB ? BW_OOB : op + 2 * VS);
+        if (exp_next && act) {
+          bw_st<0>(B::val(B::sent), rn, off);
+          bw_st<0>(B::val(B::sent), rn, off + VS);
+          bw_st<0>(B::val(B::sent), rn, off + 2 * VS);
+        }
+        halo_put(k + 1, (j + 1) % BW_PH);
+        halo_fetch(k + BW_PH, jp);
+        h_fetch(k + BW_PH, jp);
+        __syncthreads();  // one wavefront: orders the LDS ring accesses of the lanes
+      }
+    }
+  }
+  if (tid == 0) {
+    unsigned o = atomicAdd(&a.ctr[1], 1u);
+    if (o == gridDim.x - 1) {
+      __hip_atomic_store(&a.ctr[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&a.ctr[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+template <class E>
+hipError_t launch_bwavefront(int dir, const WfArgs<typename WfVal<E>::V>& a, hipStream_t st) {
+  const unsigned ntiles = (unsigned)(a.t.ntx * a.t.nty);
+  const unsigned grid = ntiles < 2048u ? ntiles : 2048u;
+  if (dir > 0)
+    hipLaunchKernelGGL((k_bwavefront<1, E>), dim3(grid), dim3(BW_NL), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_bwavefront<-1, E>), dim3(grid), dim3(BW_NL), 0, st, a);
+  return hipGetLastError();
+}
+template hipError_t launch_bwavefront<double>(int, const WfArgs<double>&, hipStream_t);
+template hipError_t launch_bwavefront<float>(int, const WfArgs<float>&, hipStream_t);
+template hipError_t launch_bwavefront<__half>(int, const WfArgs<float>&, hipStream_t);
+
+// ------------------------------------------------------------ packing (setup)
+__device__ inline long bwf_point(const Grid& g, const WfTiling& tl, long q) {
+  const int l = (int)(q % BW_NL);
+  const long r = q / BW_NL;
+  const int s = (int)(r % tl.ns);
+  const int tile = (int)(r / tl.ns);
+  const int X = tile / tl.nty, Y = tile % tl.nty;
+  const int lx = l / BW_TY, ly = l % BW_TY;
+  const int x = X * BW_TX + lx, y = Y * BW_TY + ly - tl.sh * lx;
+  const int z = s - ((BW_WX - tl.sh * BW_WY) * lx + BW_WY * ly + BW_KB);
+  const bool v = x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+  return v ? ((long)x * g.ny + y) * g.nz + z : -1;
+}
+
+// FP64 / FP32: group g < 13 holds block (dir > 0 ? g : 14 + g) row-major,
+// group 13 the inverse diagonal block; padding zero.
+template <class E>
+__global__ __launch_bounds__(256) void k_bwf_pack(Grid g, WfTiling tl, int dir, const double* __restrict__ A,
+                                                  const double* __restrict__ Dinv, E* __restrict__ out) {
+  constexpr int K = 16 / (int)sizeof(E), GPC = bwf_gpc(sizeof(E)), NPK = bwf_npk(sizeof(E));
+  const long q = (long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= tl.nsk) return;
+  const long i = bwf_point(g, tl, q);
+  const long N = g.N();
+  const long row = q / BW_NL;
+  const int lane = (int)(q % BW_NL);
+  for (int grp = 0; grp < 14; ++grp) {
+    const int np = grp < 13 ? GPC : bwf_gpd(sizeof(E));
+    for (int p = 0; p < np; ++p) {
+      E* o = out + ((row * NPK + grp * GPC + p) * BW_NL + lane) * K;
+      for (int e = 0; e < K; ++e) {
+        const int v = p * K + e;
+        double x = 0.0;
+        if (i >= 0 && v < 9)
+          x = grp < 13 ? A[((long)(dir > 0 ? grp : 14 + grp) * 9 + v) * N + i] : Dinv[(long)v * N + i];
+        o[e] = (E)x;
+      }
+    }
+  }
+}
+
+// FP16: per triangle block two packs: 9 halves (bytes 0..17) and the 3 FP32
+// row scales (bytes 20..31); then 3 FP32 packs with the inverse diagonal block.
+__global__ __launch_bounds__(256) void k_bwf_pack_h(Grid g, WfTiling tl, int dir, const __half* __restrict__ a16,
+                                                    const float* __restrict__ sc, const float* __restrict__ rd,
+                                                    unsigned char* __restrict__ out) {
+  constexpr int NPK = bwf_npk(2);
+  const long q = (long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= tl.nsk) return;
+  const long i = bwf_point(g, tl, q);
+  const long N = g.N();
+  const long row = q / BW_NL;
+  const int lane = (int)(q % BW_NL);
+  auto pack = [&](int p) { return out + ((row * NPK + p) * BW_NL + lane) * 16; };
+  for (int grp = 0; grp < 13; ++grp) {
+    unsigned char* o0 = pack(2 * grp);
+    unsigned char* o1 = pack(2 * grp + 1);
+    unsigned char bytes[32];
+    for (int b = 0; b < 32; ++b) bytes[b] = 0;
+    for (int v = 0; v < 9; ++v) {
+      const __half h = i >= 0 ? a16[((long)(dir > 0 ? grp : 14 + grp) * 9 + v) * N + i] : __float2half_rn(0.0f);
+      const unsigned short u = __half_as_ushort(h);
+      bytes[2 * v] = (unsigned char)(u & 0xff);
+      bytes[2 * v + 1] = (unsigned char)(u >> 8);
+    }
+    for (int r = 0; r < 3; ++r) {
+      const unsigned u = __float_as_uint(i >= 0 ? sc[(long)r * N + i] : 0.0f);
+      for (int b = 0; b < 4; ++b) bytes[20 + 4 * r + b] = (unsigned char)(u >> (8 * b));
+    }
+    for (int b = 0; b < 16; ++b) {
+      o0[b] = bytes[b];
+      o1[b] = bytes[16 + b];
+    }
+  }
+  for (int p = 0; p < 3; ++p) {
+    unsigned char* o = pack(26 + p);
+    for (int e = 0; e < 4; ++e) {
+      const int v = p * 4 + e;
+      const unsigned u = __float_as_uint(i >= 0 && v < 9 ? rd[(long)v * N + i] : 0.0f);
+      for (int b = 0; b < 4; ++b) o[4 * e + b] = (unsigned char)(u >> (8 * b));
+    }
+  }
+}
+
+template <class E>
+hipError_t launch_bwf_pack(const Grid& g, const WfTiling& tl, int dir, const double* A, const double* Dinv, E* out,
+                           hipStream_t st) {
+  hipLaunchKernelGGL((k_bwf_pack<E>), dim3((unsigned)((tl.nsk + 255) / 256)), dim3(256), 0, st, g, tl, dir, A, Dinv,
+                     out);
+  return hipGetLastError();
+}
+template hipError_t launch_bwf_pack<double>(const Grid&, const WfTiling&, int, const double*, const double*, double*,
+                                            hipStream_t);
+template hipError_t launch_bwf_pack<float>(const Grid&, const WfTiling&, int, const double*, const double*, float*,
+                                           hipStream_t);
+
+hipError_t launch_bwf_pack_h(const Grid& g, const WfTiling& tl, int dir, const __half* a16, const float* sc,
+                             const float* rd, void* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_bwf_pack_h, dim3((unsigned)((tl.nsk + 255) / 256)), dim3(256), 0, st, g, tl, dir, a16, sc,
+                     rd, (unsigned char*)out);
+  return hipGetLastError();
+}
+
+}  // namespace smg

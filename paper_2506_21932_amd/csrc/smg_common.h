@@ -95,6 +95,30 @@ struct MatH {
   __device__ float operator()(int s, long i) const { return sc[i] * __half2float(a[(long)s * n + i]); }
 };
 
+// 3x3 block matrices: entry e = s*9 + r*3 + c of node i at a[e*N + i]; FP16
+// storage scales scalar row r of node i by sc[r*N + i].
+struct BMatD {
+  const double* a;
+  long n;
+  using V = double;
+  __device__ double operator()(int e, int r, long i) const { return a[(long)e * n + i]; }
+};
+struct BMatF {
+  const float* a;
+  long n;
+  using V = float;
+  __device__ float operator()(int e, int r, long i) const { return a[(long)e * n + i]; }
+};
+struct BMatH {
+  const __half* a;
+  const float* sc;
+  long n;
+  using V = float;
+  __device__ float operator()(int e, int r, long i) const {
+    return sc[(long)r * n + i] * __half2float(a[(long)e * n + i]);
+  }
+};
+
 constexpr int WF_TX = 16, WF_TY = 16;  // columns per wavefront tile (256 lanes)
 
 struct WfTiling {

@@ -80,18 +80,24 @@ template <class V>
 hipError_t launch_prolong_add(const Grid& g, int cmask, int bs, const V* ec, V* uf, hipStream_t st);
 
 // ---- block (3x3) variants (block.hip) --------------------------------
+// y = A x or y = b - A x on 3x3 blocks (27-point pattern)
 template <class M>
 hipError_t launch_bspmv(const Grid& g, const M& m, const typename M::V* x, const typename M::V* b,
                         typename M::V* y, bool res, hipStream_t st);
+// h = f - sum over lower neighbour blocks of A_ij u_j (input of the backward block sweep)
 template <class M>
-hipError_t launch_bresid_restrict(const Grid& g, int cmask, const M& m, const typename M::V* f,
-                                  const typename M::V* u, typename M::V* rc, hipStream_t st);
-template <class M>
-hipError_t launch_bprolong_post(const Grid& g, int cmask, const M& m, const typename M::V* f,
-                                const typename M::V* u, const typename M::V* ec, typename M::V* h,
-                                hipStream_t st);
-template <class M, class DM>
-hipError_t launch_bwavefront(int dir, const WfArgs<typename M::V>& a, const M& m, const DM& dinv, hipStream_t st);
+hipError_t launch_blower(const Grid& g, const M& m, const typename M::V* f, const typename M::V* u,
+                         typename M::V* h, hipStream_t st);
+// point-block Gauss-Seidel sweep on 8 x 8-column tiles (WfArgs.pk: launch_bwf_pack data of this direction)
+void bwf_tiling(const Grid& g, WfTiling* t);
+int bwf_pack_count(int ebytes);
+template <class E>
+hipError_t launch_bwavefront(int dir, const WfArgs<typename WfVal<E>::V>& a, hipStream_t st);
+template <class E>
+hipError_t launch_bwf_pack(const Grid& g, const WfTiling& tl, int dir, const double* A, const double* Dinv, E* out,
+                           hipStream_t st);
+hipError_t launch_bwf_pack_h(const Grid& g, const WfTiling& tl, int dir, const __half* a16, const float* sc,
+                             const float* rd, void* out, hipStream_t st);
 
 // ---- setup (setup.hip) ------------------------------------------------
 hipError_t launch_copy_masked(int pat, const Grid& g, int be, const double* src, double* dst, hipStream_t st);

@@ -132,6 +132,7 @@ const char* check_cfg(const smg_config* c) {
   // sweep buffers address 18 x-planes and one tile's steps with 31-bit byte offsets
   if ((double)(WF_TX + 2) * c->ny * c->nz * 8 >= 2147483647.0) return "ny * nz too large (limit 14.9e6)";
   if (c->nz > 65536) return "nz too large (limit 65536)";
+  if (c->block == 3 && (double)10 * c->ny * c->nz * 3 * 8 >= 2147483647.0) return "ny * nz too large for 3x3 blocks";
   if (c->block != 1 && c->block != 3) return "block must be 1 or 3";
   if (c->pattern != 7 && c->pattern != 19 && c->pattern != 27) return "pattern must be 7, 19 or 27";
   if (c->block == 3 && c->pattern != 27) return "block systems use the 27-point pattern";
@@ -195,13 +196,18 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
       vec(&v.zz);
       vec(&v.uo);
     }
-    wf_tiling(v.g, v.S, &v.tl);
+    const int eb = cfg.prec == SMG_FP16_ROWSCALE ? 2 : (int)vsz;
     if (bs == 1) {
-      const int eb = cfg.prec == SMG_FP16_ROWSCALE ? 2 : (int)vsz;
+      wf_tiling(v.g, v.S, &v.tl);
       const size_t pbytes = (size_t)wf_pack_count(v.S, eb) * 16 * v.tl.nsk;
       v.pk[0] = ar.take<char>(pbytes);
       v.pk[1] = ar.take<char>(pbytes);
       if (cfg.prec == SMG_FP16_ROWSCALE) v.psd = ar.take<float>((size_t)2 * v.tl.nsk);
+    } else {
+      bwf_tiling(v.g, &v.tl);
+      const size_t pbytes = (size_t)bwf_pack_count(eb) * 16 * v.tl.nsk;
+      v.pk[0] = ar.take<char>(pbytes);
+      v.pk[1] = ar.take<char>(pbytes);
     }
     if (cfg.prec == SMG_FP32) {
       v.A32 = ar.take<float>((size_t)v.S * be * N);
@@ -256,6 +262,8 @@ struct P64 {
   using M = MatD;
   using MF = MatD;
   using E = double;
+  using BM = BMatD;
+  static BM BA(const Level& l) { return BMatD{l.A64, l.N}; }
   static M A(const Level& l) { return MatD{l.A64, l.N}; }
   static MF Lf(const Level& l) { return MatD{l.L64, l.N}; }
   static MF Uf(const Level& l) { return MatD{l.U64, l.N}; }
@@ -267,6 +275,8 @@ struct P32 {
   using M = MatF;
   using MF = MatF;
   using E = float;
+  using BM = BMatF;
+  static BM BA(const Level& l) { return BMatF{l.A32, l.N}; }
   static M A(const Level& l) { return MatF{l.A32, l.N}; }
   static MF Lf(const Level& l) { return MatF{l.L32, l.N}; }
   static MF Uf(const Level& l) { return MatF{l.U32, l.N}; }
@@ -278,6 +288,8 @@ struct P16 {
   using M = MatH;
   using MF = MatF;
   using E = __half;
+  using BM = BMatH;
+  static BM BA(const Level& l) { return BMatH{l.A16, l.sc16, l.N}; }
   static M A(const Level& l) { return MatH{l.A16, l.sc16, l.N}; }
   static MF Lf(const Level& l) { return MatF{l.L32, l.N}; }
   static MF Uf(const Level& l) { return MatF{l.U32, l.N}; }
@@ -304,12 +316,71 @@ hipError_t sweep(smg_handle_s* H, const Level& L, int dir, bool unitd, const V* 
   return launch_wavefront<E>(L.S, dir, unitd, addout != nullptr, a, st);
 }
 
+template <class E, class V>
+hipError_t bsweep(smg_handle_s* H, const Level& L, int dir, const V* hin, V* x, V* next, int next_dir,
+                  hipStream_t st) {
+  WfArgs<V> a{};
+  a.g = L.g;
+  a.t = L.tl;
+  a.pk = L.pk[dir > 0 ? 0 : 1];
+  a.h = hin;
+  a.x = x;
+  a.next = next;
+  a.next_dir = next_dir;
+  a.ctr = H->ctr;
+  a.err = H->err;
+  return launch_bwavefront<E>(dir, a, st);
+}
+
+// V-cycle of a 3x3 block system: point-block GS before and after the coarse
+// correction; residual, restriction and prolongation per component.
+template <class PT>
+hipError_t bvcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z0, hipStream_t st) {
+  using V = typename PT::V;
+  using E = typename PT::E;
+  const int NL = H->nlev;
+  auto F = [&](int l) -> const V* { return l == 0 ? f0 : (const V*)H->lev[l].f; };
+  auto UB = [&](int l) -> V* { return l == 0 ? z0 : (V*)H->lev[l].ub; };
+  hipError_t e;
+  for (int l = 0; l < NL - 1; ++l) {
+    const Level& v = H->lev[l];
+    {
+      Timed t(H, l, 0, st);
+      e = bsweep<E, V>(H, v, +1, F(l), (V*)v.ua, UB(l), -1, st);
+    }
+    if (e != hipSuccess) return e;
+    Timed t(H, l, 2, st);
+    e = launch_bspmv(v.g, PT::BA(v), (const V*)v.ua, F(l), (V*)v.h, true, st);
+    if (e == hipSuccess) e = launch_restrict<V>(v.g, v.cmask, 3, (const V*)v.h, (V*)H->lev[l + 1].f, st);
+    if (e != hipSuccess) return e;
+  }
+  {
+    Timed t(H, NL - 1, 3, st);
+    e = launch_coarse_gemv<V>(H->nc, H->aug + H->nc, 2 * H->nc, F(NL - 1), UB(NL - 1), st);
+  }
+  if (e != hipSuccess) return e;
+  for (int l = NL - 2; l >= 0; --l) {
+    const Level& v = H->lev[l];
+    {
+      Timed t(H, l, 4, st);
+      e = launch_prolong_add<V>(v.g, v.cmask, 3, (const V*)UB(l + 1), (V*)v.ua, st);
+      if (e == hipSuccess) e = launch_blower(v.g, PT::BA(v), F(l), (const V*)v.ua, (V*)v.h, st);
+    }
+    if (e != hipSuccess) return e;
+    Timed t(H, l, 5, st);
+    e = bsweep<E, V>(H, v, -1, (const V*)v.h, UB(l), (V*)v.ua, +1, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // One V-cycle on internal or caller vectors: f0 = level-0 right-hand side,
 // z0 = level-0 output (its positions read across tiles are given sentinels by
 // the pre-smoothing sweep).
 template <class PT>
 hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z0, hipStream_t st) {
   using V = typename PT::V;
+  if (H->bs == 3) return bvcycle_t<PT>(H, f0, z0, st);
   const int NL = H->nlev;
   const bool ilu = H->cfg.smoother == SMG_SMOOTH_ILU0;
   auto F = [&](int l) -> const V* { return l == 0 ? f0 : (const V*)H->lev[l].f; };
@@ -398,6 +469,7 @@ hipError_t vcycle(smg_handle_s* H, const double* r, double* z, hipStream_t st) {
 hipError_t spmv64(smg_handle_s* H, const double* x, const double* b, double* y, bool res, hipStream_t st) {
   const Level& l0 = H->lev[0];
   Timed t(H, 0, 7, st);
+  if (H->bs == 3) return launch_bspmv(l0.g, BMatD{l0.A64, l0.N}, x, b, y, res, st);
   return launch_spmv(l0.S, l0.g, MatD{l0.A64, l0.N}, x, b, y, res, st);
 }
 
@@ -466,6 +538,17 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
       SCHK(launch_to_f32(v.rd64, v.rd32, (bs == 3 ? 9 : 1) * v.N, st));
     }
     // sweep data in wavefront schedule order
+    if (bs == 3) {
+      for (int d = 0; d < 2; ++d) {
+        const int dir = d == 0 ? 1 : -1;
+        if (cfg->prec == SMG_FP64)
+          SCHK(launch_bwf_pack<double>(v.g, v.tl, dir, v.A64, v.rd64, (double*)v.pk[d], st));
+        else if (cfg->prec == SMG_FP32)
+          SCHK(launch_bwf_pack<float>(v.g, v.tl, dir, v.A64, v.rd64, (float*)v.pk[d], st));
+        else
+          SCHK(launch_bwf_pack_h(v.g, v.tl, dir, v.A16, v.sc16, v.rd32, v.pk[d], st));
+      }
+    }
     if (bs == 1) {
       const bool ilu = cfg->smoother == SMG_SMOOTH_ILU0;
       const double* lo = ilu ? v.L64 : v.A64;
@@ -581,7 +664,6 @@ smg_status smg_precondition(smg_handle h, const double* r, double* z, void* stre
   const long n0 = h->lev[0].N * h->bs;
   if ((const char*)z < (const char*)(r + n0) && (const char*)r < (const char*)(z + n0))
     return fail(h, SMG_EINVAL, "r and z overlap");
-  if (h->bs != 1) return fail(h, SMG_EINVAL, "block V-cycle not available");
   HIPCHK(h, vcycle(h, r, z, (hipStream_t)stream));
   return SMG_OK;
 }
@@ -592,7 +674,6 @@ smg_status smg_solve(smg_handle H, const double* b, double* x, double rtol, int 
   if (!b || !x) return fail(H, SMG_EINVAL, "null vector");
   if (!(rtol > 0.0) || maxit < 0 || krylov < 0) return fail(H, SMG_EINVAL, "bad rtol / maxit / krylov");
   if (krylov > 0 && krylov > H->kV_m) return fail(H, SMG_EINVAL, "GMRES(%d) needs cfg.gmres_restart >= %d", krylov, krylov);
-  if (H->bs != 1) return fail(H, SMG_EINVAL, "block V-cycle not available");
   hipStream_t st = (hipStream_t)stream;
   const long n = H->lev[0].N * H->bs;
   hipError_t e = hipSuccess;
@@ -809,7 +890,6 @@ static smg_status op_level_check(smg_handle h, int level, bool need_next) {
   if (!h) return fail(nullptr, SMG_EINVAL, "null handle");
   if (level < 0 || level >= h->nlev) return fail(h, SMG_EINVAL, "level %d out of range", level);
   if (need_next && level + 1 >= h->nlev) return fail(h, SMG_EINVAL, "level %d is the coarsest", level);
-  if (h->bs != 1) return fail(h, SMG_EINVAL, "block operators not available");
   return SMG_OK;
 }
 
@@ -824,8 +904,13 @@ static hipError_t op_presmooth_t(smg_handle_s* H, const Level& v, const void* f,
     uint32_t b = SENT32;
     memcpy(&sent, &b, 4);
   }
-  const long nv = v.N;
+  const long nv = v.N * H->bs;
   hipError_t e;
+  if (H->bs == 3) {
+    e = launch_fill_bits<V>((V*)u, nv, sent, st);
+    if (e == hipSuccess) e = bsweep<typename PT::E, V>(H, v, +1, (const V*)f, (V*)u, nullptr, 0, st);
+    return e;
+  }
   if (H->cfg.smoother == SMG_SMOOTH_GS) {
     e = launch_fill_bits<V>((V*)u, nv, sent, st);
     if (e == hipSuccess)
@@ -853,9 +938,19 @@ static hipError_t op_postsmooth_t(smg_handle_s* H, const Level& v, const void* f
     uint32_t b = SENT32;
     memcpy(&sent, &b, 4);
   }
-  const long nv = v.N;
+  const long nv = v.N * H->bs;
   const auto A = PT::A(v);
   hipError_t e;
+  if (H->bs == 3) {
+    // u_old = u_in + P ec in the level's u_a buffer (its sentinels restored after)
+    e = hipMemcpyAsync(v.ua, uin, sizeof(V) * nv, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && ec != nullptr) e = launch_prolong_add<V>(v.g, v.cmask, 3, (const V*)ec, (V*)v.ua, st);
+    if (e == hipSuccess) e = launch_blower(v.g, PT::BA(v), (const V*)f, (const V*)v.ua, (V*)v.h, st);
+    if (e == hipSuccess) e = launch_fill_bits<V>((V*)uout, nv, sent, st);
+    if (e == hipSuccess) e = bsweep<typename PT::E, V>(H, v, -1, (const V*)v.h, (V*)uout, nullptr, 0, st);
+    if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.ua, nv, sent, st);
+    return e;
+  }
   if (H->cfg.smoother == SMG_SMOOTH_GS) {
     e = launch_prolong_post(v.S, v.g, v.cmask, A, (const V*)f, (const V*)uin, (const V*)ec, (V*)v.h, (V*)nullptr,
                             false, st);
@@ -894,6 +989,11 @@ struct OpSpmv {
     const Level& v = H->lev[l];
     using V = typename PT::V;
     if (l == H->nlev - 1 && H->cfg.prec != SMG_FP64) return hipErrorInvalidValue;
+    if (H->bs == 3) {
+      if (l == H->nlev - 1 || H->cfg.prec == SMG_FP64)
+        return launch_bspmv(v.g, BMatD{v.A64, v.N}, (const double*)x, (const double*)nullptr, (double*)y, false, st);
+      return launch_bspmv(v.g, PT::BA(v), (const V*)x, (const V*)nullptr, (V*)y, false, st);
+    }
     if (l == H->nlev - 1 || H->cfg.prec == SMG_FP64)
       return launch_spmv(v.S, v.g, MatD{v.A64, v.N}, (const double*)x, nullptr, (double*)y, false, st);
     return launch_spmv(v.S, v.g, PT::A(v), (const V*)x, (const V*)nullptr, (V*)y, false, st);
@@ -917,6 +1017,11 @@ struct OpRR {
   static hipError_t run(smg_handle_s* H, int l, const void* f, const void* u, void* rc, hipStream_t st) {
     const Level& v = H->lev[l];
     using V = typename PT::V;
+    if (H->bs == 3) {
+      hipError_t e = launch_bspmv(v.g, PT::BA(v), (const V*)u, (const V*)f, (V*)v.h, true, st);
+      if (e == hipSuccess) e = launch_restrict<V>(v.g, v.cmask, 3, (const V*)v.h, (V*)rc, st);
+      return e;
+    }
     return launch_resid_restrict(v.S, v.g, v.cmask, PT::A(v), (const V*)f, (const V*)u, (V*)rc, st);
   }
 };
@@ -933,7 +1038,6 @@ smg_status smg_op_spmv(smg_handle h, int level, const void* x, void* y, void* st
 
 smg_status smg_op_spmv_fp64(smg_handle h, const double* x, double* y, void* stream) {
   if (!h || !x || !y) return fail(h, SMG_EINVAL, "null argument");
-  if (h->bs != 1) return fail(h, SMG_EINVAL, "block operators not available");
   HIPCHK(h, spmv64(h, x, nullptr, y, false, (hipStream_t)stream));
   return SMG_OK;
 }

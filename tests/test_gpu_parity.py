@@ -257,3 +257,105 @@ def test_error_paths():
     with pytest.raises(smg.SmgError) as e:
         smg.StructMG(T(A2), (8, 8, 8), pattern=7, device=DEV)
     assert e.value.status == smg.SMG_EBREAKDOWN
+
+
+# ---------------------------------------------------------------- 3x3 blocks
+BCASES = [(12, 10, 9), (17, 16, 8)]
+OFF27 = workloads.offsets(27)
+
+
+def _bpair(shape, prec="fp64", seed=7):
+    A = workloads.random_sgdia(shape, 27, seed=seed, block=3)
+    H = oracle.Hierarchy(shape, 27, A, block=3, prec=prec)
+    mg = smg.StructMG(T(A), shape, pattern=27, block=3, prec=prec, device=DEV)
+    return A, H, mg
+
+
+@pytest.mark.parametrize("shape", BCASES, ids=lambda s: "x".join(map(str, s)))
+def test_block_kernels_bitexact(shape):
+    A, H, mg = _bpair(shape)
+    assert mg.nlev == H.nlev
+    for l in range(H.nlev):
+        Ar = H.level_data(l, 0)
+        got = N(mg.export(l, 0, torch.empty(Ar.shape, dtype=torch.float64, device=DEV)))
+        assert np.array_equal(got, Ar), f"block triple product level {l}"
+        if l < H.nlev - 1:
+            D = H.level_data(l, 1)
+            got = N(mg.export(l, 1, torch.empty(D.shape, dtype=torch.float64, device=DEV)))
+            assert np.array_equal(got, D), f"block inverses level {l}"
+    g = workloads.rng(21)
+    for l in range(H.nlev - 1):
+        inf = H.level_info(l)
+        dims, cm = inf["dims"], inf["cmask"]
+        cdims = oracle.coarse_dims(dims, cm)
+        Al, D = H.level_data(l, 0), H.level_data(l, 1)
+        f = g.uniform(-1, 1, size=dims + (3,))
+        u = g.uniform(-1, 1, size=dims + (3,))
+        ec = g.uniform(-1, 1, size=cdims + (3,))
+        n3, nc3 = f.size, ec.size
+        y = N(mg.op_spmv(l, T(f.ravel()), torch.empty(n3, dtype=torch.float64, device=DEV)))
+        assert np.array_equal(y, oracle.bspmv(OFF27, Al, f).ravel()), f"block SpMV level {l}"
+        ug = N(mg.op_presmooth(l, T(f.ravel()), torch.empty(n3, dtype=torch.float64, device=DEV)))
+        ur = oracle.bgs_sweep(OFF27, Al, D, f, np.zeros_like(f), 1, 1)
+        assert np.array_equal(ug, ur.ravel()), f"forward block GS level {l}: {np.abs(ug - ur.ravel()).max()}"
+        rc = N(mg.op_resid_restrict(l, T(f.ravel()), T(u.ravel()), torch.empty(nc3, dtype=torch.float64, device=DEV)))
+        rr = oracle.restrict(f - oracle.bspmv(OFF27, Al, u), cm, bs=3)
+        assert np.array_equal(rc, rr.ravel()), f"block resid+restrict level {l}"
+        uo = N(mg.op_postsmooth(l, T(f.ravel()), T(u.ravel()), T(ec.ravel()),
+                                torch.empty(n3, dtype=torch.float64, device=DEV)))
+        ref = oracle.bgs_sweep(OFF27, Al, D, f, oracle.prolong_add(u, ec, cm, bs=3), -1, 0)
+        assert np.array_equal(uo, ref.ravel()), f"backward block GS level {l}: {np.abs(uo - ref.ravel()).max()}"
+    # whole V-cycle, twice (buffers reused)
+    dims = H.level_info(0)["dims"]
+    r = workloads.rng(9).uniform(-1, 1, size=dims + (3,))
+    z = N(mg.precondition(T(r.ravel()), torch.empty(r.size, dtype=torch.float64, device=DEV)))
+    zr = H.apply(r).ravel()
+    assert np.abs(z - zr).max() <= 1e-12 * np.abs(zr).max()
+    z2 = N(mg.precondition(T(r.ravel()), torch.empty(r.size, dtype=torch.float64, device=DEV)))
+    assert np.array_equal(z, z2)
+
+
+def test_block_elasticity_pcg():
+    A, b = workloads.elasticity27(12, seed=4)
+    shape = (12, 12, 12)
+    H = oracle.Hierarchy(shape, 27, A, block=3)
+    xr, st, itr, relr = H.pcg(b, 1e-8, 200)
+    mg = smg.StructMG(T(A), shape, pattern=27, block=3, device=DEV)
+    x = torch.zeros(b.size, dtype=torch.float64, device=DEV)
+    res = mg.solve(T(b.ravel()), x, rtol=1e-8, maxit=200)
+    assert res["status"] == 0 and res["rel_resid_true"] < 1e-8
+    assert abs(res["iters"] - itr) <= 1
+    assert np.abs(N(x) - xr.ravel()).max() <= 1e-5 * np.abs(xr).max()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_block_reduced_precision_bitexact(prec):
+    shape = BCASES[0]
+    A, H, mg = _bpair(shape, prec=prec)
+    f32 = torch.float32
+    g = workloads.rng(23)
+    for l in range(H.nlev - 1):
+        inf = H.level_info(l)
+        dims, cm = inf["dims"], inf["cmask"]
+        A32, D32 = H.level_data(l, 5), H.level_data(l, 6)
+        got = N(mg.export(l, 5, torch.empty(A32.shape, dtype=f32, device=DEV)))
+        assert np.array_equal(got, A32), f"{prec} block matrix level {l}"
+        f = g.uniform(-1, 1, size=dims + (3,)).astype(np.float32)
+        u = g.uniform(-1, 1, size=dims + (3,)).astype(np.float32)
+        ec = g.uniform(-1, 1, size=oracle.coarse_dims(dims, cm) + (3,)).astype(np.float32)
+        y = N(mg.op_spmv(l, T(f.ravel(), f32), torch.empty(f.size, dtype=f32, device=DEV)))
+        assert np.array_equal(y, oracle.bspmv(OFF27, A32, f).ravel())
+        ug = N(mg.op_presmooth(l, T(f.ravel(), f32), torch.empty(f.size, dtype=f32, device=DEV)))
+        assert np.array_equal(ug, oracle.bgs_sweep(OFF27, A32, D32, f, np.zeros_like(f), 1, 1).ravel())
+        uo = N(mg.op_postsmooth(l, T(f.ravel(), f32), T(u.ravel(), f32), T(ec.ravel(), f32),
+                                torch.empty(f.size, dtype=f32, device=DEV)))
+        ref = oracle.bgs_sweep(OFF27, A32, D32, f, oracle.prolong_add(u, ec, cm, bs=3), -1, 0)
+        assert np.array_equal(uo, ref.ravel())
+    dims = H.level_info(0)["dims"]
+    r = workloads.rng(9).uniform(-1, 1, size=dims + (3,))
+    z = N(mg.precondition(T(r.ravel()), torch.empty(r.size, dtype=torch.float64, device=DEV)))
+    zr = H.apply(r).ravel()
+    assert np.abs(z - zr).max() <= 1e-5 * np.abs(zr).max()
+    x = torch.zeros(r.size, dtype=torch.float64, device=DEV)
+    res = mg.solve(T(r.ravel()), x, rtol=1e-8, maxit=300)
+    assert res["status"] == 0 and res["rel_resid_true"] < 1e-8
