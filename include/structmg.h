@@ -169,6 +169,53 @@ smg_status smg_op_coarse_solve(smg_handle h, const void* f, void* u, void* strea
 smg_status smg_set_timing(smg_handle h, int enable, int level /* -1: all */, unsigned kinds /* bit mask */);
 smg_status smg_timing_report(smg_handle h, double* ms, int* counts, int max_levels, int* dropped);
 
+/* ---- batches of independent systems -------------------------------------
+ * Many independent scalar systems (GS smoother; one pattern and one V-cycle
+ * precision for all; grids may differ) solved together: each system has its
+ * own hierarchy, built exactly as by smg_setup, and all systems advance in
+ * lockstep through preconditioned CG, every step being one launch over all
+ * systems; a system stops at its own convergence (per-system tolerance test
+ * as in smg_solve).  One lockstep iteration runs as a captured HIP graph.
+ * Pointer arrays are host arrays of nsys device pointers.  At most 4095
+ * systems. */
+typedef struct smg_batch_s* smg_batch;
+
+/* Workspace bytes for the batch (every cfgs[k] as for smg_workspace_size). */
+smg_status smg_batch_workspace_size(int nsys, const smg_config* cfgs, size_t* bytes);
+
+/* Builds the nsys hierarchies into one workspace (borrowed until
+ * smg_batch_destroy).  Synchronises `stream`. */
+smg_status smg_batch_setup(int nsys, const smg_config* cfgs, const double* const* coeffs, void* workspace,
+                           size_t bytes, void* stream, smg_batch* out);
+
+/* z[k] = M_k^-1 r[k] for every system: one batched V-cycle (each system's
+ * result equals smg_precondition on that system).  Synchronises `stream`. */
+smg_status smg_batch_precondition(smg_batch b, const double* const* r, double* const* z, void* stream);
+
+/* Solves A_k x[k] = bv[k] for all k by lockstep PCG (x[k]: initial guess on
+ * entry).  results / status (optional host arrays of nsys) receive each
+ * system's outcome: SMG_OK, SMG_ENOTCONV or SMG_EBREAKDOWN.  Returns SMG_OK
+ * when all converged, otherwise the worst per-system status.  Synchronises. */
+smg_status smg_batch_solve(smg_batch b, const double* const* bv, double* const* x, double rtol, int maxit,
+                           smg_result* results, int* status, void* stream);
+
+/* Sweep schedule: merge order of the systems' tiles (0: system after system,
+ * 1: round robin) and persistent grid of the batched sweeps (0: default). */
+smg_status smg_batch_set_schedule(smg_batch b, int order, int grid);
+/* Times batched V-cycles for every (order, grid) candidate and keeps the
+ * fastest; returns it and its time per V-cycle (ms).  Overwrites the
+ * internal residual vectors (not the caller's). */
+smg_status smg_batch_tune(smg_batch b, void* stream, int* order, int* grid, double* ms_per_vcycle);
+/* Replays a captured graph per lockstep iteration (1, default) or launches
+ * the iteration's kernels one by one (0). */
+smg_status smg_batch_set_graph(smg_batch b, int enable);
+int smg_batch_num_systems(smg_batch b);
+/* The hierarchy of system k (owned by the batch; for introspection and the
+ * single-system entry points). */
+smg_handle smg_batch_system(smg_batch b, int k);
+smg_status smg_batch_destroy(smg_batch b);
+const char* smg_batch_last_error(smg_batch b);
+
 #ifdef __cplusplus
 }
 #endif

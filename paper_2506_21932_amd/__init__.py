@@ -41,7 +41,10 @@ class Result(C.Structure):
 EXPORTS = ["smg_workspace_size", "smg_setup", "smg_precondition", "smg_solve", "smg_destroy", "smg_last_error",
            "smg_level_info", "smg_num_levels", "smg_level_export", "smg_rap_chain_count", "smg_op_spmv",
            "smg_op_spmv_fp64", "smg_op_presmooth", "smg_op_postsmooth", "smg_op_resid_restrict", "smg_op_restrict",
-           "smg_op_prolong_add", "smg_op_coarse_solve", "smg_set_timing", "smg_timing_report", "smg_resetup"]
+           "smg_op_prolong_add", "smg_op_coarse_solve", "smg_set_timing", "smg_timing_report", "smg_resetup",
+           "smg_batch_workspace_size", "smg_batch_setup", "smg_batch_precondition", "smg_batch_solve",
+           "smg_batch_set_schedule", "smg_batch_tune", "smg_batch_set_graph", "smg_batch_num_systems",
+           "smg_batch_system", "smg_batch_destroy", "smg_batch_last_error"]
 
 TIMING_KINDS = ["pre_sweep", "pre_sweep_u", "resid_restrict", "coarse_solve", "prolong_post", "post_sweep",
                 "post_sweep_u", "spmv_fp64"]
@@ -82,8 +85,22 @@ def load():
     L.smg_set_timing.argtypes = [vp, i, i, C.c_uint]
     L.smg_resetup.argtypes = [vp, vp, vp]
     L.smg_timing_report.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int), i, C.POINTER(C.c_int)]
+    L.smg_batch_workspace_size.argtypes = [i, C.POINTER(Config), C.POINTER(C.c_size_t)]
+    L.smg_batch_setup.argtypes = [i, C.POINTER(Config), C.POINTER(vp), vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.smg_batch_precondition.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
+    L.smg_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), d, i, C.POINTER(Result), C.POINTER(C.c_int), vp]
+    L.smg_batch_set_schedule.argtypes = [vp, i, i]
+    L.smg_batch_tune.argtypes = [vp, vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]
+    L.smg_batch_set_graph.argtypes = [vp, i]
+    L.smg_batch_num_systems.argtypes = [vp]
+    L.smg_batch_system.argtypes = [vp, i]
+    L.smg_batch_system.restype = vp
+    L.smg_batch_destroy.argtypes = [vp]
+    L.smg_batch_last_error.argtypes = [vp]
+    L.smg_batch_last_error.restype = C.c_char_p
     for name in EXPORTS:
-        if name not in ("smg_last_error", "smg_num_levels", "smg_rap_chain_count"):
+        if name not in ("smg_last_error", "smg_num_levels", "smg_rap_chain_count", "smg_batch_system",
+                        "smg_batch_last_error"):
             getattr(L, name).restype = i
     _lib = L
     return L
@@ -237,3 +254,74 @@ class StructMG:
     def op_coarse_solve(self, f, u):
         self._check(self.L.smg_op_coarse_solve(self.h, _ptr(f), _ptr(u), _stream()), self.h)
         return u
+
+
+def _ptr_array(ts):
+    return (C.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+
+class StructMGBatch:
+    """Owns a batch of independent scalar systems solved in lockstep (one
+    workspace tensor holds every hierarchy and the batch's tables)."""
+
+    def __init__(self, coeffs, shapes, pattern=7, smoother="gs", coarsen="full", semi_levels=0, prec="fp64",
+                 max_coarse=0, device="cuda"):
+        import torch
+        L = load()
+        self.L = L
+        self.n = len(shapes)
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.cfgs = (Config * self.n)(*[make_config(s, pattern, 1, smoother, coarsen, semi_levels, prec, max_coarse,
+                                                    0) for s in self.shapes])
+        nbytes = C.c_size_t(0)
+        self._check(L.smg_batch_workspace_size(self.n, self.cfgs, C.byref(nbytes)), None)
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
+        cs = [c.to(device=device, dtype=torch.float64).contiguous() for c in coeffs]
+        b = C.c_void_p()
+        self._check(L.smg_batch_setup(self.n, self.cfgs, _ptr_array(cs), _ptr(self.workspace), nbytes, _stream(),
+                                      C.byref(b)), None)
+        self.b = b
+
+    def _check(self, st, b):
+        if st != SMG_OK:
+            raise SmgError(st, self.L.smg_batch_last_error(b).decode())
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.L.smg_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def levels(self, k):
+        return self.L.smg_num_levels(self.L.smg_batch_system(self.b, int(k)))
+
+    def precondition(self, rs, zs):
+        self._check(self.L.smg_batch_precondition(self.b, _ptr_array(rs), _ptr_array(zs), _stream()), self.b)
+        return zs
+
+    def solve(self, bs, xs, rtol=1e-9, maxit=500):
+        res = (Result * self.n)()
+        stt = (C.c_int * self.n)()
+        st = self.L.smg_batch_solve(self.b, _ptr_array(bs), _ptr_array(xs), float(rtol), int(maxit), res, stt,
+                                    _stream())
+        if st not in (SMG_OK, SMG_ENOTCONV, SMG_EBREAKDOWN):
+            self._check(st, self.b)
+        return st, [{"status": stt[k], "iters": res[k].iters, "levels": res[k].levels,
+                     "rel_resid_true": res[k].rel_resid_true, "t_setup_ms": res[k].t_setup_ms,
+                     "t_solve_ms": res[k].t_solve_ms} for k in range(self.n)]
+
+    def set_schedule(self, order, grid=0):
+        self._check(self.L.smg_batch_set_schedule(self.b, int(order), int(grid)), self.b)
+
+    def set_graph(self, enable):
+        self._check(self.L.smg_batch_set_graph(self.b, int(bool(enable))), self.b)
+
+    def tune(self):
+        o, g, ms = C.c_int(0), C.c_int(0), C.c_double(0)
+        self._check(self.L.smg_batch_tune(self.b, _stream(), C.byref(o), C.byref(g), C.byref(ms)), self.b)
+        return {"order": o.value, "grid": g.value, "ms_per_vcycle": ms.value}

@@ -24,7 +24,7 @@ CXXFLAGS = [
     "-Wno-unused-command-line-argument",
 ]
 SOURCES = ["structmg.hip", "wavefront.hip", "stencil.hip", "rap.hip", "setup.hip", "coarse.hip", "vec.hip",
-           "block.hip"]
+           "block.hip", "batch.hip"]
 
 
 def _compile(src):

@@ -2,32 +2,35 @@
 // level, explicit inverse by Gauss-Jordan elimination with partial pivoting
 // at setup, and an FP64 matrix-vector product per V-cycle (the paper leaves
 // the coarsest solver unspecified; an exact solve is used).
+#include "smg_group.h"
 #include "smg_kernels.h"
 
 namespace smg {
 
-// M (row-major, leading dimension ld) = dense form of a 27-point operator
-// with bs unknowns per node; M must be zeroed beforehand.
-__global__ __launch_bounds__(256) void k_dense_assemble(Grid g, int bs, const double* __restrict__ A,
+// M (row-major, leading dimension ld) = dense form of an operator of pattern
+// pat (the finest pattern when the hierarchy has one level, else 27) with bs
+// unknowns per node; M must be zeroed beforehand.
+__global__ __launch_bounds__(256) void k_dense_assemble(Grid g, int pat, int bs, const double* __restrict__ A,
                                                         double* __restrict__ M, int ld) {
   const long N = g.N();
   const long k = (long)blockIdx.x * 256 + threadIdx.x;
   const int be = bs * bs;
-  if (k >= N * 27 * be) return;
+  if (k >= N * pat * be) return;
   const long i = k % N;
   const int se = (int)(k / N);
   const int s = se / be, e = se % be;
   const int X = (int)(i / ((long)g.ny * g.nz)), Y = (int)((i / g.nz) % g.ny), Z = (int)(i % g.nz);
-  const int ax = X + pat_off(27, s, 0), ay = Y + pat_off(27, s, 1), az = Z + pat_off(27, s, 2);
+  const int ax = X + pat_off(pat, s, 0), ay = Y + pat_off(pat, s, 1), az = Z + pat_off(pat, s, 2);
   if (!in_grid(g, ax, ay, az)) return;
   const long j = ((long)ax * g.ny + ay) * g.nz + az;
   const int r = e / bs, c = e % bs;
   M[(i * bs + r) * ld + j * bs + c] = A[(long)se * N + i];
 }
 
-hipError_t launch_dense_assemble(const Grid& g, int bs, const double* A, double* M, int ld, hipStream_t st) {
-  const long n = g.N() * 27 * bs * bs;
-  hipLaunchKernelGGL(k_dense_assemble, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, bs, A, M, ld);
+hipError_t launch_dense_assemble(const Grid& g, int pat, int bs, const double* A, double* M, int ld,
+                                 hipStream_t st) {
+  const long n = g.N() * pat * bs * bs;
+  hipLaunchKernelGGL(k_dense_assemble, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, pat, bs, A, M, ld);
   return hipGetLastError();
 }
 
@@ -108,22 +111,40 @@ hipError_t coarse_invert(int n, double* aug, int* info_dev, hipStream_t st) {
 // u = Ainv f in FP64 (input/output in the V-cycle precision); one wavefront
 // per row, lanes strided over columns, then a fixed-order lane reduction.
 template <class V>
-__global__ __launch_bounds__(256) void k_coarse_gemv(int n, const double* __restrict__ Ainv, int ld,
-                                                     const V* __restrict__ f, V* __restrict__ u) {
-  const int row = blockIdx.x * 4 + (int)(threadIdx.x / 64);
-  const int lane = threadIdx.x % 64;
-  if (row >= n) return;
-  double acc = 0.0;
-  for (int j = lane; j < n; j += 64) acc = fma(Ainv[(long)row * ld + j], (double)f[j], acc);
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) u[row] = (V)acc;
-}
+struct GemvOp {
+  using Args = GemvArgs<V>;
+  __device__ static void run(const Args& a, unsigned bid) {
+    const int row = (int)bid * 4 + (int)(threadIdx.x / 64);
+    const int lane = threadIdx.x % 64;
+    if (row >= a.n) return;
+    const double* __restrict__ Ainv = a.ainv;
+    const V* __restrict__ f = a.f;
+    double acc = 0.0;
+    for (int j = lane; j < a.n; j += 64) acc = fma(Ainv[(long)row * a.ld + j], (double)f[j], acc);
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (lane == 0) a.u[row] = (V)acc;
+  }
+};
+
+unsigned gemv_blocks(int n) { return (unsigned)((n + 3) / 4); }
 
 template <class V>
 hipError_t launch_coarse_gemv(int n, const double* Ainv, int ld, const V* f, V* u, hipStream_t st) {
-  hipLaunchKernelGGL((k_coarse_gemv<V>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, n, Ainv, ld, f, u);
+  const GemvArgs<V> a{n, ld, Ainv, f, u, 0};
+  hipLaunchKernelGGL((k_one<GemvOp<V>>), dim3(gemv_blocks(n)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
+template <class V>
+hipError_t launch_gemv_group(const GemvArgs<V>* segs, const unsigned* bmap, unsigned nblocks, const int* live,
+                             hipStream_t st) {
+  if (nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_group<GemvOp<V>>), dim3(nblocks), dim3(256), 0, st, segs, bmap, live);
+  return hipGetLastError();
+}
+template hipError_t launch_gemv_group<double>(const GemvArgs<double>*, const unsigned*, unsigned, const int*,
+                                              hipStream_t);
+template hipError_t launch_gemv_group<float>(const GemvArgs<float>*, const unsigned*, unsigned, const int*,
+                                             hipStream_t);
 template hipError_t launch_coarse_gemv<double>(int, const double*, int, const double*, double*, hipStream_t);
 template hipError_t launch_coarse_gemv<float>(int, const double*, int, const float*, float*, hipStream_t);
 

@@ -1,0 +1,107 @@
+// Internal layout of a libstructmg handle and the precision traits of the
+// V-cycle (shared by the single-system and the batched host code).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "../../include/structmg.h"
+#include "smg_kernels.h"
+
+#define SMG_TIMING_CAP 16384
+#define SMG_TIMING_KINDS 8
+
+namespace smg {
+
+constexpr int MAXLEV = 40;
+
+struct Level {
+  Grid g;
+  int S = 0;      // pattern points
+  int cmask = 0;  // axes coarsened to reach the next level (0: coarsest)
+  long N = 0;
+  double *A64 = nullptr, *rd64 = nullptr, *L64 = nullptr, *U64 = nullptr, *rU64 = nullptr;
+  float *A32 = nullptr, *rd32 = nullptr, *L32 = nullptr, *U32 = nullptr, *rU32 = nullptr;
+  __half* A16 = nullptr;
+  float* sc16 = nullptr;
+  void *f = nullptr, *ua = nullptr, *ub = nullptr, *h = nullptr;
+  void *y1 = nullptr, *y2 = nullptr, *zz = nullptr, *uo = nullptr;
+  WfTiling tl{};                    // wavefront tiling
+  void* pk[2] = {nullptr, nullptr};  // packed sweep data, forward / backward (V-cycle precision; FP16: halves)
+  float* psd = nullptr;             // FP16: {row scale, diagonal scaling} per schedule position
+};
+
+}  // namespace smg
+
+struct smg_handle_s {
+  smg_config cfg{};
+  int bs = 1, nlev = 0, nc = 0;
+  smg::Level lev[smg::MAXLEV];
+  double* aug = nullptr;  // coarsest [.. | A^-1] (n x 2n) + n spare
+  unsigned* ctr = nullptr;
+  unsigned* err = nullptr;
+  int* info = nullptr;
+  double *dpart = nullptr, *dout = nullptr;
+  double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr, *kt = nullptr, *kw = nullptr;
+  double* kV = nullptr;
+  int kV_m = 0;
+  double t_setup_ms = 0.0;
+  char msg[512] = {0};
+  // kernel timing (profiling aid): event pairs per (level, kind)
+  bool timing = false;
+  int tm_level = -1;      // record only this level (-1: all)
+  unsigned tm_kinds = ~0u;  // bit mask of recorded kinds
+  int ev_used = 0;
+  int ev_tag[SMG_TIMING_CAP];
+  hipEvent_t ev0[SMG_TIMING_CAP], ev1[SMG_TIMING_CAP];
+};
+
+namespace smg {
+
+// ---- precision traits of the V-cycle ---------------------------------
+struct P64 {
+  using V = double;
+  using M = MatD;
+  using MF = MatD;
+  using E = double;
+  using BM = BMatD;
+  static BM BA(const Level& l) { return BMatD{l.A64, l.N}; }
+  static M A(const Level& l) { return MatD{l.A64, l.N}; }
+  static MF Lf(const Level& l) { return MatD{l.L64, l.N}; }
+  static MF Uf(const Level& l) { return MatD{l.U64, l.N}; }
+  static const V* rd(const Level& l) { return l.rd64; }
+  static const V* rU(const Level& l) { return l.rU64; }
+};
+struct P32 {
+  using V = float;
+  using M = MatF;
+  using MF = MatF;
+  using E = float;
+  using BM = BMatF;
+  static BM BA(const Level& l) { return BMatF{l.A32, l.N}; }
+  static M A(const Level& l) { return MatF{l.A32, l.N}; }
+  static MF Lf(const Level& l) { return MatF{l.L32, l.N}; }
+  static MF Uf(const Level& l) { return MatF{l.U32, l.N}; }
+  static const V* rd(const Level& l) { return l.rd32; }
+  static const V* rU(const Level& l) { return l.rU32; }
+};
+struct P16 {
+  using V = float;
+  using M = MatH;
+  using MF = MatF;
+  using E = __half;
+  using BM = BMatH;
+  static BM BA(const Level& l) { return BMatH{l.A16, l.sc16, l.N}; }
+  static M A(const Level& l) { return MatH{l.A16, l.sc16, l.N}; }
+  static MF Lf(const Level& l) { return MatF{l.L32, l.N}; }
+  static MF Uf(const Level& l) { return MatF{l.U32, l.N}; }
+  static const V* rd(const Level& l) { return l.rd32; }
+  static const V* rU(const Level& l) { return l.rU32; }
+};
+
+// Validation of a configuration (null when supported) and the level shapes
+// (grids, patterns, coarsening masks, sweep tilings; no memory) it leads to.
+// plan_shapes returns the workspace bytes, or 0 when the coarsest level is
+// too large; L holds MAXLEV entries.
+const char* config_error(const smg_config* cfg);
+size_t plan_shapes(const smg_config& cfg, Level* L, int* nlev, int* nc);
+
+}  // namespace smg

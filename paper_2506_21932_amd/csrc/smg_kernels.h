@@ -32,6 +32,7 @@ struct WfArgs {
   V* addout;
   unsigned* ctr;             // [0] ticket counter, [1] exit counter; zero between launches
   unsigned* err;             // watchdog flag (bit 0)
+  int sys;                   // grouped sweeps: system of this grid
 };
 
 void wf_tiling(const Grid& g, int pat, WfTiling* t);
@@ -53,6 +54,78 @@ hipError_t launch_wf_pack(int pat, const Grid& g, const WfTiling& tl, int dir, c
 // {row scale, diagonal scaling} per position.
 hipError_t launch_wf_pack_h(int pat, const Grid& g, const WfTiling& tl, int dir, const __half* a16, const float* sc,
                             const float* rd, __half* out, float* sd, hipStream_t st);
+
+// One sweep over many independent grids of pattern pat in one launch.
+// segs[k]: the arguments of grid k (their ctr / err are not used);
+// tmap[t] = (k << 20) | r: ticket t is the r-th tile of grid k in its own
+// forward dependence order (each grid's tiles appear in increasing r);
+// total tickets; grid workgroups (0: one per tile); ctr / err as in WfArgs;
+// tiles of a grid whose system is finished (live[sys] == 0) are skipped.
+template <class E>
+hipError_t launch_wavefront_group(int pat, int dir, const WfArgs<typename WfVal<E>::V>* segs, const unsigned* tmap,
+                                  unsigned total, unsigned grid, const int* live, unsigned* ctr, unsigned* err,
+                                  hipStream_t st);
+
+// ---- grouped launches ---------------------------------------------------
+// Arguments of one grid of a kernel that can also run grouped (smg_group.h):
+// bmap[b] = (segment << 20) | (block of that segment), live[sys] == 0 skips
+// a segment.  *_blocks give the blocks of one grid.
+template <class M>
+struct SpmvArgs {
+  Grid g;
+  M m;
+  const typename M::V* x;
+  const typename M::V* b;
+  typename M::V* y;
+  int sys;
+};
+template <class M>
+struct RRArgs {
+  Grid g;
+  int cmask;
+  M m;
+  const typename M::V* f;
+  const typename M::V* u;
+  typename M::V* rc;
+  int sys;
+};
+template <class M>
+struct PPArgs {
+  Grid g;
+  int cmask;
+  M m;
+  const typename M::V* f;
+  const typename M::V* u;
+  const typename M::V* ec;
+  typename M::V* h;
+  typename M::V* uo;
+  int sys;
+};
+template <class V>
+struct GemvArgs {
+  int n;
+  int ld;
+  const double* ainv;
+  const V* f;
+  V* u;
+  int sys;
+};
+unsigned spmv_blocks(const Grid& g);
+unsigned rr_blocks(const Grid& g, int cmask);
+unsigned pp_blocks(const Grid& g);
+unsigned gemv_blocks(int n);
+template <class M>
+hipError_t launch_spmv_group(int pat, bool res, const SpmvArgs<M>* segs, const unsigned* bmap, unsigned nblocks,
+                             const int* live, hipStream_t st);
+template <class M>
+hipError_t launch_rr_group(int pat, const RRArgs<M>* segs, const unsigned* bmap, unsigned nblocks, const int* live,
+                           hipStream_t st);
+template <class M>
+hipError_t launch_pp_group(int pat, bool full, const PPArgs<M>* segs, const unsigned* bmap, unsigned nblocks,
+                           const int* live, hipStream_t st);
+template <class V>
+hipError_t launch_gemv_group(const GemvArgs<V>* segs, const unsigned* bmap, unsigned nblocks, const int* live,
+                             hipStream_t st);
 
 // ---- parallel stencil kernels (stencil.hip) ----------------------------
 // y = A x   (res = false)   or   y = b - A x   (res = true)
@@ -118,7 +191,8 @@ hipError_t launch_rap(int pat, int cmask, const Grid& gf, const double* A, long 
 int rap_chain_count(int pat, int cmask);
 
 // ---- coarsest level (coarse.hip) ------------------------------------
-hipError_t launch_dense_assemble(const Grid& g, int bs, const double* A, double* M, int ld, hipStream_t st);
+hipError_t launch_dense_assemble(const Grid& g, int pat, int bs, const double* A, double* M, int ld,
+                                 hipStream_t st);
 hipError_t launch_aug_init(int n, double* aug, hipStream_t st);
 hipError_t coarse_invert(int n, double* aug, int* info_dev, hipStream_t st);  // aug: n x 2n, inverse in right half
 template <class V>

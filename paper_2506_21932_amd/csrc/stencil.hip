@@ -9,6 +9,7 @@
 // order as the definition it implements: accumulations run over stencil
 // offsets (or restriction offsets, or interpolation parents) in canonical
 // lexicographic order with explicit fma, and out-of-grid terms are skipped.
+#include "smg_group.h"
 #include "smg_kernels.h"
 
 namespace smg {
@@ -23,36 +24,63 @@ __device__ inline void unflat(unsigned i, int ny, int nz, int& x, int& y, int& z
 
 // ---------------------------------------------------------------- SpMV
 template <int PAT, class M, bool RES>
-__global__ __launch_bounds__(256) void k_spmv(Grid g, M m, const typename M::V* __restrict__ x,
-                                              const typename M::V* __restrict__ b, typename M::V* __restrict__ y) {
-  using V = typename M::V;
-  const unsigned N = (unsigned)g.N();
-  const unsigned i = blockIdx.x * 256u + threadIdx.x;
-  if (i >= N) return;
-  int X, Y, Z;
-  unflat(i, g.ny, g.nz, X, Y, Z);
-  const long nyz = (long)g.ny * g.nz;
-  V acc = V(0);
+struct SpmvOp {
+  using Args = SpmvArgs<M>;
+  __device__ static void run(const Args& a, unsigned bid) {
+    using V = typename M::V;
+    const Grid g = a.g;
+    const M m = a.m;
+    const V* __restrict__ x = a.x;
+    const unsigned N = (unsigned)g.N();
+    const unsigned i = bid * 256u + threadIdx.x;
+    if (i >= N) return;
+    int X, Y, Z;
+    unflat(i, g.ny, g.nz, X, Y, Z);
+    const long nyz = (long)g.ny * g.nz;
+    V acc = V(0);
 #pragma unroll
-  for (int s = 0; s < PAT; ++s) {
-    const int dx = pat_off(PAT, s, 0), dy = pat_off(PAT, s, 1), dz = pat_off(PAT, s, 2);
-    if (in_grid(g, X + dx, Y + dy, Z + dz)) acc = fma(m(s, i), x[(long)i + dx * nyz + dy * g.nz + dz], acc);
+    for (int s = 0; s < PAT; ++s) {
+      const int dx = pat_off(PAT, s, 0), dy = pat_off(PAT, s, 1), dz = pat_off(PAT, s, 2);
+      if (in_grid(g, X + dx, Y + dy, Z + dz)) acc = fma(m(s, i), x[(long)i + dx * nyz + dy * g.nz + dz], acc);
+    }
+    a.y[i] = RES ? a.b[i] - acc : acc;
   }
-  y[i] = RES ? b[i] - acc : acc;
-}
+};
+
+unsigned spmv_blocks(const Grid& g) { return (unsigned)((g.N() + 255) / 256); }
 
 template <class M>
 hipError_t launch_spmv(int pat, const Grid& g, const M& m, const typename M::V* x, const typename M::V* b,
                        typename M::V* y, bool res, hipStream_t st) {
-  const unsigned N = (unsigned)g.N();
-  dim3 grid((N + 255) / 256), blk(256);
-#define SMG_SPMV(P)                                                                    \
-  if (pat == P) {                                                                      \
-    if (res)                                                                           \
-      hipLaunchKernelGGL((k_spmv<P, M, true>), grid, blk, 0, st, g, m, x, b, y);      \
-    else                                                                               \
-      hipLaunchKernelGGL((k_spmv<P, M, false>), grid, blk, 0, st, g, m, x, b, y);     \
-    return hipGetLastError();                                                          \
+  const SpmvArgs<M> a{g, m, x, b, y, 0};
+  const dim3 grid(spmv_blocks(g)), blk(256);
+#define SMG_SPMV(P)                                                                      \
+  if (pat == P) {                                                                        \
+    if (res)                                                                             \
+      hipLaunchKernelGGL((k_one<SpmvOp<P, M, true>>), grid, blk, 0, st, a);             \
+    else                                                                                 \
+      hipLaunchKernelGGL((k_one<SpmvOp<P, M, false>>), grid, blk, 0, st, a);            \
+    return hipGetLastError();                                                            \
+  }
+  SMG_SPMV(7)
+  SMG_SPMV(19)
+  SMG_SPMV(27)
+#undef SMG_SPMV
+  return hipErrorInvalidValue;
+}
+
+template <class M>
+hipError_t launch_spmv_group(int pat, bool res, const SpmvArgs<M>* segs, const unsigned* bmap, unsigned nblocks,
+                             const int* live, hipStream_t st) {
+  if (nblocks == 0) return hipSuccess;
+  const dim3 grid(nblocks), blk(256);
+#define SMG_SPMV(P)                                                                          \
+  if (pat == P) {                                                                            \
+    if (res)                                                                                 \
+      hipLaunchKernelGGL((k_group<SpmvOp<P, M, true>>), grid, blk, 0, st, segs, bmap, live); \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_group<SpmvOp<P, M, false>>), grid, blk, 0, st, segs, bmap, live);\
+    return hipGetLastError();                                                                \
   }
   SMG_SPMV(7)
   SMG_SPMV(19)
@@ -71,16 +99,22 @@ constexpr int RB_X = 4, RB_Y = 4, RB_Z = 16;
 __host__ __device__ inline int rr_ext(int cm, int cb) { return cm ? 2 * cb + 1 : cb; }
 
 template <int PAT, class M>
-__global__ __launch_bounds__(256) void k_resid_restrict(Grid gf, int cmask, M m, const typename M::V* __restrict__ f,
-                                                        const typename M::V* __restrict__ u,
-                                                        typename M::V* __restrict__ rc) {
+struct RROp {
+  using Args = RRArgs<M>;
+  __device__ static void run(const Args& a, unsigned bid_) {
+  const Grid gf = a.g;
+  const int cmask = a.cmask;
+  const M m = a.m;
+  const typename M::V* __restrict__ f = a.f;
+  const typename M::V* __restrict__ u = a.u;
+  typename M::V* __restrict__ rc = a.rc;
   using V = typename M::V;
   constexpr int MAXE = (2 * RB_X + 1) * (2 * RB_Y + 1) * (2 * RB_Z + 1);
   __shared__ V rs[MAXE];
   const int cmx = cmask & 1, cmy = (cmask >> 1) & 1, cmz = (cmask >> 2) & 1;
   const Grid gc{cmx ? gf.nx / 2 : gf.nx, cmy ? gf.ny / 2 : gf.ny, cmz ? gf.nz / 2 : gf.nz};
   const int nbz = (gc.nz + RB_Z - 1) / RB_Z, nby = (gc.ny + RB_Y - 1) / RB_Y;
-  const int bid = blockIdx.x;
+  const int bid = (int)bid_;
   const int bz = bid % nbz, by = (bid / nbz) % nby, bx = bid / (nbz * nby);
   const int C0x = bx * RB_X, C0y = by * RB_Y, C0z = bz * RB_Z;
   const int lox = cmx ? 2 * C0x : C0x, loy = cmy ? 2 * C0y : C0y, loz = cmz ? 2 * C0z : C0z;
@@ -116,17 +150,39 @@ __global__ __launch_bounds__(256) void k_resid_restrict(Grid gf, int cmask, M m,
     }
     rc[((long)Xc * gc.ny + Yc) * gc.nz + Z] = acc;
   }
+  }
+};
+
+unsigned rr_blocks(const Grid& g, int cmask) {
+  const int cx = (cmask & 1) ? g.nx / 2 : g.nx, cy = (cmask & 2) ? g.ny / 2 : g.ny, cz = (cmask & 4) ? g.nz / 2 : g.nz;
+  return (unsigned)(((cx + RB_X - 1) / RB_X) * ((cy + RB_Y - 1) / RB_Y) * ((cz + RB_Z - 1) / RB_Z));
 }
 
 template <class M>
 hipError_t launch_resid_restrict(int pat, const Grid& g, int cmask, const M& m, const typename M::V* f,
                                  const typename M::V* u, typename M::V* rc, hipStream_t st) {
-  const int cx = (cmask & 1) ? g.nx / 2 : g.nx, cy = (cmask & 2) ? g.ny / 2 : g.ny, cz = (cmask & 4) ? g.nz / 2 : g.nz;
-  const unsigned nb = (unsigned)(((cx + RB_X - 1) / RB_X) * ((cy + RB_Y - 1) / RB_Y) * ((cz + RB_Z - 1) / RB_Z));
-#define SMG_RR(P)                                                                                      \
-  if (pat == P) {                                                                                      \
-    hipLaunchKernelGGL((k_resid_restrict<P, M>), dim3(nb), dim3(256), 0, st, g, cmask, m, f, u, rc);  \
-    return hipGetLastError();                                                                          \
+  const RRArgs<M> a{g, cmask, m, f, u, rc, 0};
+  const unsigned nb = rr_blocks(g, cmask);
+#define SMG_RR(P)                                                                      \
+  if (pat == P) {                                                                      \
+    hipLaunchKernelGGL((k_one<RROp<P, M>>), dim3(nb), dim3(256), 0, st, a);          \
+    return hipGetLastError();                                                          \
+  }
+  SMG_RR(7)
+  SMG_RR(19)
+  SMG_RR(27)
+#undef SMG_RR
+  return hipErrorInvalidValue;
+}
+
+template <class M>
+hipError_t launch_rr_group(int pat, const RRArgs<M>* segs, const unsigned* bmap, unsigned nblocks, const int* live,
+                           hipStream_t st) {
+  if (nblocks == 0) return hipSuccess;
+#define SMG_RR(P)                                                                                       \
+  if (pat == P) {                                                                                       \
+    hipLaunchKernelGGL((k_group<RROp<P, M>>), dim3(nblocks), dim3(256), 0, st, segs, bmap, live);      \
+    return hipGetLastError();                                                                           \
   }
   SMG_RR(7)
   SMG_RR(19)
@@ -186,17 +242,24 @@ __device__ inline V interp_point(const V* __restrict__ ec, const Grid& gc, int c
 constexpr int PP_X = 8, PP_Y = 8, PP_Z = 32;
 
 template <int PAT, class M, bool FULL>
-__global__ __launch_bounds__(256) void k_prolong_post(Grid gf, int cmask, M m, const typename M::V* __restrict__ f,
-                                                      const typename M::V* __restrict__ u,
-                                                      const typename M::V* __restrict__ ec,
-                                                      typename M::V* __restrict__ h, typename M::V* __restrict__ uo) {
+struct PPOp {
+  using Args = PPArgs<M>;
+  __device__ static void run(const Args& a, unsigned bid_) {
+  const Grid gf = a.g;
+  const int cmask = a.cmask;
+  const M m = a.m;
+  const typename M::V* __restrict__ f = a.f;
+  const typename M::V* __restrict__ u = a.u;
+  const typename M::V* __restrict__ ec = a.ec;
+  typename M::V* __restrict__ h = a.h;
+  typename M::V* __restrict__ uo = a.uo;
   using V = typename M::V;
   constexpr int HX = PP_X + 2, HY = PP_Y + 2, HZ = PP_Z + 2;
   __shared__ V us[HX * HY * HZ];
   const int cmx = cmask & 1, cmy = (cmask >> 1) & 1, cmz = (cmask >> 2) & 1;
   const Grid gc{cmx ? gf.nx / 2 : gf.nx, cmy ? gf.ny / 2 : gf.ny, cmz ? gf.nz / 2 : gf.nz};
   const int nbz = (gf.nz + PP_Z - 1) / PP_Z, nby = (gf.ny + PP_Y - 1) / PP_Y;
-  const int bid = blockIdx.x;
+  const int bid = (int)bid_;
   const int bz = bid % nbz, by = (bid / nbz) % nby, bx = bid / (nbz * nby);
   const int x0 = bx * PP_X - 1, y0 = by * PP_Y - 1, z0 = bz * PP_Z - 1;
   for (int k = threadIdx.x; k < HX * HY * HZ; k += 256) {
@@ -233,23 +296,45 @@ __global__ __launch_bounds__(256) void k_prolong_post(Grid gf, int cmask, M m, c
       uo[i] = us[c];
     }
   }
+  }
+};
+
+unsigned pp_blocks(const Grid& g) {
+  return (unsigned)(((g.nx + PP_X - 1) / PP_X) * ((g.ny + PP_Y - 1) / PP_Y) * ((g.nz + PP_Z - 1) / PP_Z));
 }
 
 template <class M>
 hipError_t launch_prolong_post(int pat, const Grid& g, int cmask, const M& m, const typename M::V* f,
                                const typename M::V* u, const typename M::V* ec, typename M::V* h,
                                typename M::V* uold_out, bool full, hipStream_t st) {
-  const unsigned nb =
-      (unsigned)(((g.nx + PP_X - 1) / PP_X) * ((g.ny + PP_Y - 1) / PP_Y) * ((g.nz + PP_Z - 1) / PP_Z));
-#define SMG_PP(P)                                                                                                 \
-  if (pat == P) {                                                                                                 \
-    if (full)                                                                                                     \
-      hipLaunchKernelGGL((k_prolong_post<P, M, true>), dim3(nb), dim3(256), 0, st, g, cmask, m, f, u, ec, h,       \
-                         uold_out);                                                                               \
-    else                                                                                                          \
-      hipLaunchKernelGGL((k_prolong_post<P, M, false>), dim3(nb), dim3(256), 0, st, g, cmask, m, f, u, ec, h,      \
-                         uold_out);                                                                               \
-    return hipGetLastError();                                                                                     \
+  const PPArgs<M> a{g, cmask, m, f, u, ec, h, uold_out, 0};
+  const unsigned nb = pp_blocks(g);
+#define SMG_PP(P)                                                                        \
+  if (pat == P) {                                                                        \
+    if (full)                                                                            \
+      hipLaunchKernelGGL((k_one<PPOp<P, M, true>>), dim3(nb), dim3(256), 0, st, a);     \
+    else                                                                                 \
+      hipLaunchKernelGGL((k_one<PPOp<P, M, false>>), dim3(nb), dim3(256), 0, st, a);    \
+    return hipGetLastError();                                                            \
+  }
+  SMG_PP(7)
+  SMG_PP(19)
+  SMG_PP(27)
+#undef SMG_PP
+  return hipErrorInvalidValue;
+}
+
+template <class M>
+hipError_t launch_pp_group(int pat, bool full, const PPArgs<M>* segs, const unsigned* bmap, unsigned nblocks,
+                           const int* live, hipStream_t st) {
+  if (nblocks == 0) return hipSuccess;
+#define SMG_PP(P)                                                                                           \
+  if (pat == P) {                                                                                           \
+    if (full)                                                                                               \
+      hipLaunchKernelGGL((k_group<PPOp<P, M, true>>), dim3(nblocks), dim3(256), 0, st, segs, bmap, live);  \
+    else                                                                                                    \
+      hipLaunchKernelGGL((k_group<PPOp<P, M, false>>), dim3(nblocks), dim3(256), 0, st, segs, bmap, live); \
+    return hipGetLastError();                                                                               \
   }
   SMG_PP(7)
   SMG_PP(19)
@@ -322,6 +407,17 @@ SMG_INST(MatD)
 SMG_INST(MatF)
 SMG_INST(MatH)
 #undef SMG_INST
+#define SMG_GINST(M)                                                                                           \
+  template hipError_t launch_spmv_group<M>(int, bool, const SpmvArgs<M>*, const unsigned*, unsigned, const int*, \
+                                           hipStream_t);                                                       \
+  template hipError_t launch_rr_group<M>(int, const RRArgs<M>*, const unsigned*, unsigned, const int*,           \
+                                         hipStream_t);                                                         \
+  template hipError_t launch_pp_group<M>(int, bool, const PPArgs<M>*, const unsigned*, unsigned, const int*,     \
+                                         hipStream_t);
+SMG_GINST(MatD)
+SMG_GINST(MatF)
+SMG_GINST(MatH)
+#undef SMG_GINST
 template hipError_t launch_restrict<double>(const Grid&, int, int, const double*, double*, hipStream_t);
 template hipError_t launch_restrict<float>(const Grid&, int, int, const float*, float*, hipStream_t);
 template hipError_t launch_prolong_add<double>(const Grid&, int, int, const double*, double*, hipStream_t);

@@ -15,58 +15,9 @@
 
 #include <chrono>
 
-#include "../../include/structmg.h"
-#include "smg_kernels.h"
+#include "smg_handle.h"
 
 using namespace smg;
-
-#define SMG_TIMING_CAP 16384
-#define SMG_TIMING_KINDS 8
-
-namespace {
-
-constexpr int MAXLEV = 40;
-
-struct Level {
-  Grid g;
-  int S = 0;      // pattern points
-  int cmask = 0;  // axes coarsened to reach the next level (0: coarsest)
-  long N = 0;
-  double *A64 = nullptr, *rd64 = nullptr, *L64 = nullptr, *U64 = nullptr, *rU64 = nullptr;
-  float *A32 = nullptr, *rd32 = nullptr, *L32 = nullptr, *U32 = nullptr, *rU32 = nullptr;
-  __half* A16 = nullptr;
-  float* sc16 = nullptr;
-  void *f = nullptr, *ua = nullptr, *ub = nullptr, *h = nullptr;
-  void *y1 = nullptr, *y2 = nullptr, *zz = nullptr, *uo = nullptr;
-  WfTiling tl{};                    // wavefront tiling
-  void* pk[2] = {nullptr, nullptr};  // packed sweep data, forward / backward (V-cycle precision; FP16: halves)
-  float* psd = nullptr;             // FP16: {row scale, diagonal scaling} per schedule position
-};
-
-}  // namespace
-
-struct smg_handle_s {
-  smg_config cfg{};
-  int bs = 1, nlev = 0, nc = 0;
-  Level lev[MAXLEV];
-  double* aug = nullptr;  // coarsest [.. | A^-1] (n x 2n) + n spare
-  unsigned* ctr = nullptr;
-  unsigned* err = nullptr;
-  int* info = nullptr;
-  double *dpart = nullptr, *dout = nullptr;
-  double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr, *kt = nullptr, *kw = nullptr;
-  double* kV = nullptr;
-  int kV_m = 0;
-  double t_setup_ms = 0.0;
-  char msg[512] = {0};
-  // kernel timing (profiling aid): event pairs per (level, kind)
-  bool timing = false;
-  int tm_level = -1;      // record only this level (-1: all)
-  unsigned tm_kinds = ~0u;  // bit mask of recorded kinds
-  int ev_used = 0;
-  int ev_tag[SMG_TIMING_CAP];
-  hipEvent_t ev0[SMG_TIMING_CAP], ev1[SMG_TIMING_CAP];
-};
 
 static char g_setup_msg[512] = "no error";
 
@@ -148,7 +99,7 @@ const char* check_cfg(const smg_config* c) {
 
 // Lays out every device array of the handle in the workspace (base == null:
 // size only).  Returns the number of bytes.
-size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, int* nc_out) {
+size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, int* nc_out, Level* Lext = nullptr) {
   Arena ar{base};
   const int bs = cfg.block, be = bs * bs;
   const int maxc = cfg.max_coarse > 0 ? cfg.max_coarse : 4096;
@@ -156,7 +107,7 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
   int n[3] = {cfg.nx, cfg.ny, cfg.nz};
   int nlev = 0;
   Level tmp[MAXLEV];
-  Level* L = H ? H->lev : tmp;
+  Level* L = H ? H->lev : (Lext ? Lext : tmp);
   for (;;) {
     Level& v = L[nlev];
     v.g = Grid{n[0], n[1], n[2]};
@@ -255,47 +206,6 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
   }
   return ar.off + 256;
 }
-
-// ---- precision traits of the V-cycle ---------------------------------
-struct P64 {
-  using V = double;
-  using M = MatD;
-  using MF = MatD;
-  using E = double;
-  using BM = BMatD;
-  static BM BA(const Level& l) { return BMatD{l.A64, l.N}; }
-  static M A(const Level& l) { return MatD{l.A64, l.N}; }
-  static MF Lf(const Level& l) { return MatD{l.L64, l.N}; }
-  static MF Uf(const Level& l) { return MatD{l.U64, l.N}; }
-  static const V* rd(const Level& l) { return l.rd64; }
-  static const V* rU(const Level& l) { return l.rU64; }
-};
-struct P32 {
-  using V = float;
-  using M = MatF;
-  using MF = MatF;
-  using E = float;
-  using BM = BMatF;
-  static BM BA(const Level& l) { return BMatF{l.A32, l.N}; }
-  static M A(const Level& l) { return MatF{l.A32, l.N}; }
-  static MF Lf(const Level& l) { return MatF{l.L32, l.N}; }
-  static MF Uf(const Level& l) { return MatF{l.U32, l.N}; }
-  static const V* rd(const Level& l) { return l.rd32; }
-  static const V* rU(const Level& l) { return l.rU32; }
-};
-struct P16 {
-  using V = float;
-  using M = MatH;
-  using MF = MatF;
-  using E = __half;
-  using BM = BMatH;
-  static BM BA(const Level& l) { return BMatH{l.A16, l.sc16, l.N}; }
-  static M A(const Level& l) { return MatH{l.A16, l.sc16, l.N}; }
-  static MF Lf(const Level& l) { return MatF{l.L32, l.N}; }
-  static MF Uf(const Level& l) { return MatF{l.U32, l.N}; }
-  static const V* rd(const Level& l) { return l.rd32; }
-  static const V* rU(const Level& l) { return l.rU32; }
-};
 
 template <class E, class V>
 hipError_t sweep(smg_handle_s* H, const Level& L, int dir, bool unitd, const V* hin, V* x, V* next, int next_dir,
@@ -493,6 +403,17 @@ double dot(smg_handle_s* H, const double* x, const double* y, long n, hipStream_
 }
 
 
+}  // namespace
+
+namespace smg {
+const char* config_error(const smg_config* cfg) { return check_cfg(cfg); }
+size_t plan_shapes(const smg_config& cfg, Level* L, int* nlev, int* nc) {
+  return plan(cfg, nullptr, nullptr, nlev, nc, L);
+}
+}  // namespace smg
+
+namespace {
+
 // Setup pipeline on an already planned handle (used by smg_setup and
 // smg_resetup): level-0 copy, triple products, smoother data, truncation,
 // sentinel fills, coarsest inverse.
@@ -585,7 +506,7 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
   {
     const Level& c = H->lev[H->nlev - 1];
     SCHK(launch_aug_init(H->nc, H->aug, st));
-    SCHK(launch_dense_assemble(c.g, bs, c.A64, H->aug, 2 * H->nc, st));
+    SCHK(launch_dense_assemble(c.g, c.S, bs, c.A64, H->aug, 2 * H->nc, st));
     SCHK(coarse_invert(H->nc, H->aug, H->info, st));
   }
   SCHK(hipStreamSynchronize(st));

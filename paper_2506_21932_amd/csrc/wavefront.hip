@@ -243,8 +243,10 @@ struct WfE<__half> {
   }
 };
 
+// One tile of a sweep (tile numbers in forward dependence order).  err
+// receives the watchdog flag.
 template <int PAT, int DIR, int P, class E, bool UNITD, bool ADD>
-__global__ __launch_bounds__(WF_NL) void k_wavefront(WfArgs<typename WfVal<E>::V> a) {
+__device__ __forceinline__ void wf_tile(const WfArgs<typename WfVal<E>::V>& a, unsigned tile, unsigned* err) {
   using T = WfE<E>;
   using V = typename T::V;
   using B = VBits<V>;
@@ -261,7 +263,6 @@ __global__ __launch_bounds__(WF_NL) void k_wavefront(WfArgs<typename WfVal<E>::V
   static_assert(WF_HIST % P == 0 && WF_HIST % PH == 0 && PH >= 2 && WF_HIST > KB + 1, "ring too short");
   __shared__ V ring[WF_HIST * RW];
   __shared__ V hbuf[2 * WF_CH * HRW];  // right-hand side then results, two chunks of 16 steps
-  __shared__ unsigned s_ticket;
 
   const int tid = threadIdx.x;
   const int lx = tid / WF_TY, ly = tid % WF_TY;
@@ -269,7 +270,6 @@ __global__ __launch_bounds__(WF_NL) void k_wavefront(WfArgs<typename WfVal<E>::V
   const int skew = (WX - sh * WY) * lx + WY * ly + KB;
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
   const int NS = a.t.ns;
-  const unsigned ntiles = (unsigned)(a.t.ntx * a.t.nty);
   const bool exported = wf_exported(PAT, DIR, lx, ly, sh);
 
   // LDS index of each neighbour column (its offsets mirrored for a backward
@@ -302,13 +302,7 @@ __global__ __launch_bounds__(WF_NL) void k_wavefront(WfArgs<typename WfVal<E>::V
     cnext |= (a.next != nullptr && wf_exported(PAT, a.next_dir, i, cy, sh)) ? 1u << i : 0u;
   }
 
-  for (;;) {
-    if (tid == 0) s_ticket = atomicAdd(&a.ctr[0], 1u);
-    __syncthreads();
-    const unsigned ticket = s_ticket;
-    __syncthreads();
-    if (ticket >= ntiles) break;
-    const unsigned tile = DIR > 0 ? ticket : ntiles - 1u - ticket;
+  {
     const int X = (int)(tile / (unsigned)a.t.nty), Y = (int)(tile % (unsigned)a.t.nty);
     const int xt = X * WF_TX + lx;
     const int yt = Y * WF_TY + ly - sh * lx;
@@ -407,10 +401,10 @@ __global__ __launch_bounds__(WF_NL) void k_wavefront(WfArgs<typename WfVal<E>::V
         v = bld<V, WF_SC1>(rx, off);
         ++spins;
         // once any wait has timed out, stop waiting anywhere
-        if ((spins & 1023u) == 1023u && (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u))
+        if ((spins & 1023u) == 1023u && (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u))
           spins = WF_SPIN_LIMIT;
       }
-      if (spins >= WF_SPIN_LIMIT) atomicOr(a.err, 1u);
+      if (spins >= WF_SPIN_LIMIT) atomicOr(err, 1u);
       return v;
     };
     // halo value of iteration k (held in slot j): wait for it if it is still
@@ -521,13 +515,59 @@ __global__ __launch_bounds__(WF_NL) void k_wavefront(WfArgs<typename WfVal<E>::V
       if (ADD) add_out(cl);
     }
   }
-  if (tid == 0) {
-    unsigned o = atomicAdd(&a.ctr[1], 1u);
+}
+
+// The last workgroup to finish resets the ticket counters for the next launch.
+__device__ inline void wf_retire(unsigned* ctr) {
+  if (threadIdx.x == 0) {
+    unsigned o = atomicAdd(&ctr[1], 1u);
     if (o == gridDim.x - 1) {
-      __hip_atomic_store(&a.ctr[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&a.ctr[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctr[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctr[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
+}
+
+__device__ inline unsigned wf_take_ticket(unsigned* ctr) {
+  __shared__ unsigned s_ticket;
+  if (threadIdx.x == 0) s_ticket = atomicAdd(&ctr[0], 1u);
+  __syncthreads();
+  const unsigned t = s_ticket;
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(t);
+}
+
+// One sweep over one grid: persistent workgroups take tiles by ticket.
+template <int PAT, int DIR, int P, class E, bool UNITD, bool ADD>
+__global__ __launch_bounds__(WF_NL) void k_wavefront(WfArgs<typename WfVal<E>::V> a) {
+  const unsigned ntiles = (unsigned)(a.t.ntx * a.t.nty);
+  for (;;) {
+    const unsigned ticket = wf_take_ticket(a.ctr);
+    if (ticket >= ntiles) break;
+    wf_tile<PAT, DIR, P, E, UNITD, ADD>(a, DIR > 0 ? ticket : ntiles - 1u - ticket, a.err);
+  }
+  wf_retire(a.ctr);
+}
+
+// One sweep over many independent grids of the same pattern and precision in
+// one launch.  Ticket k names entry tmap[k] = (segment << 20) | r: the r-th
+// tile of segment seg in that segment's own dependence order, so every
+// tile's producers hold smaller tickets whatever the merge of the segments.
+template <int PAT, int DIR, int P, class E, bool UNITD, bool ADD>
+__global__ __launch_bounds__(WF_NL) void k_wavefront_group(const WfArgs<typename WfVal<E>::V>* __restrict__ segs,
+                                                           const unsigned* __restrict__ tmap, unsigned total,
+                                                           const int* __restrict__ live, unsigned* ctr,
+                                                           unsigned* err) {
+  for (;;) {
+    const unsigned ticket = wf_take_ticket(ctr);
+    if (ticket >= total) break;
+    const unsigned e = __builtin_amdgcn_readfirstlane(tmap[ticket]);
+    const WfArgs<typename WfVal<E>::V> a = segs[e >> 20];
+    if (live != nullptr && live[a.sys] == 0) continue;
+    const unsigned r = e & 0xFFFFFu, nt = (unsigned)(a.t.ntx * a.t.nty);
+    wf_tile<PAT, DIR, P, E, UNITD, ADD>(a, DIR > 0 ? r : nt - 1u - r, err);
+  }
+  wf_retire(ctr);
 }
 
 // ---------------------------------------------------------------------------
@@ -657,6 +697,35 @@ static hipError_t launch_wf_t(const WfArgs<typename WfVal<E>::V>& a, hipStream_t
   hipLaunchKernelGGL((k_wavefront<PAT, DIR, P, E, UNITD, ADD>), dim3(grid), dim3(WF_NL), 0, st, a);
   return hipGetLastError();
 }
+
+template <int PAT, int DIR, int P, class E, bool UNITD, bool ADD>
+static hipError_t launch_wfg_t(const WfArgs<typename WfVal<E>::V>* segs, const unsigned* tmap, unsigned total,
+                               unsigned grid, const int* live, unsigned* ctr, unsigned* err, hipStream_t st) {
+  hipLaunchKernelGGL((k_wavefront_group<PAT, DIR, P, E, UNITD, ADD>), dim3(grid), dim3(WF_NL), 0, st, segs, tmap,
+                     total, live, ctr, err);
+  return hipGetLastError();
+}
+
+template <class E>
+hipError_t launch_wavefront_group(int pat, int dir, const WfArgs<typename WfVal<E>::V>* segs, const unsigned* tmap,
+                                  unsigned total, unsigned grid, const int* live, unsigned* ctr, unsigned* err,
+                                  hipStream_t st) {
+  if (total == 0) return hipSuccess;
+  if (grid == 0 || grid > total) grid = total;
+  if (pat == 7 && dir > 0) return launch_wfg_t<7, 1, 8, E, false, false>(segs, tmap, total, grid, live, ctr, err, st);
+  if (pat == 7 && dir < 0) return launch_wfg_t<7, -1, 8, E, false, false>(segs, tmap, total, grid, live, ctr, err, st);
+  if (pat == 19 && dir > 0) return launch_wfg_t<19, 1, 4, E, false, false>(segs, tmap, total, grid, live, ctr, err, st);
+  if (pat == 19 && dir < 0) return launch_wfg_t<19, -1, 4, E, false, false>(segs, tmap, total, grid, live, ctr, err, st);
+  if (pat == 27 && dir > 0) return launch_wfg_t<27, 1, 4, E, false, false>(segs, tmap, total, grid, live, ctr, err, st);
+  if (pat == 27 && dir < 0) return launch_wfg_t<27, -1, 4, E, false, false>(segs, tmap, total, grid, live, ctr, err, st);
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_wavefront_group<double>(int, int, const WfArgs<double>*, const unsigned*, unsigned,
+                                                   unsigned, const int*, unsigned*, unsigned*, hipStream_t);
+template hipError_t launch_wavefront_group<float>(int, int, const WfArgs<float>*, const unsigned*, unsigned, unsigned,
+                                                  const int*, unsigned*, unsigned*, hipStream_t);
+template hipError_t launch_wavefront_group<__half>(int, int, const WfArgs<float>*, const unsigned*, unsigned,
+                                                   unsigned, const int*, unsigned*, unsigned*, hipStream_t);
 
 template <class E>
 hipError_t launch_wavefront(int pat, int dir, bool unitd, bool add, const WfArgs<typename WfVal<E>::V>& a,

@@ -78,3 +78,26 @@ def test_bad_configs(bad):
     kw = dict(shape=(16, 16, 16), pattern=7)
     kw.update(bad)
     assert _ws(**kw)[0] == smg.SMG_EINVAL
+
+
+def test_batch_validation_host_only():
+    """Batch sizing and configuration checks run on the host (no GPU)."""
+    import ctypes as C
+    import paper_2506_21932_amd as smg
+    L = smg.load()
+    shapes = [(16, 16, 16), (9, 30, 12), (5, 6, 7)]
+    cfgs = (smg.Config * 3)(*[smg.make_config(s, 7, 1, "gs", "full", 3, "fp32", 512, 0) for s in shapes])
+    n = C.c_size_t(0)
+    assert L.smg_batch_workspace_size(3, cfgs, C.byref(n)) == smg.SMG_OK
+    single = sum(smg.StructMG.workspace_bytes(s, pattern=7, semi_levels=3, prec="fp32", max_coarse=512)
+                 for s in shapes)
+    assert n.value > single  # every hierarchy plus the batch tables
+    mixed = (smg.Config * 2)(smg.make_config((8, 8, 8), 7), smg.make_config((8, 8, 8), 19))
+    assert L.smg_batch_workspace_size(2, mixed, C.byref(n)) == smg.SMG_EINVAL
+    assert b"same pattern" in L.smg_batch_last_error(None)
+    ilu = (smg.Config * 1)(smg.make_config((8, 8, 8), 7, smoother="ilu0"))
+    assert L.smg_batch_workspace_size(1, ilu, C.byref(n)) == smg.SMG_EINVAL
+    blk = (smg.Config * 1)(smg.make_config((8, 8, 8), 27, block=3))
+    assert L.smg_batch_workspace_size(1, blk, C.byref(n)) == smg.SMG_EINVAL
+    assert L.smg_batch_workspace_size(0, ilu, C.byref(n)) == smg.SMG_EINVAL
+    assert L.smg_batch_workspace_size(4096, ilu, C.byref(n)) == smg.SMG_EINVAL

@@ -359,3 +359,21 @@ def test_block_reduced_precision_bitexact(prec):
     x = torch.zeros(r.size, dtype=torch.float64, device=DEV)
     res = mg.solve(T(r.ravel()), x, rtol=1e-8, maxit=300)
     assert res["status"] == 0 and res["rel_resid_true"] < 1e-8
+
+
+def test_single_level_hierarchy():
+    """A grid small enough to be its own coarsest level: the dense operator is
+    assembled from the finest (7-point) pattern and solved exactly."""
+    shape = (5, 6, 7)
+    A, b = workloads.reservoir7(shape, seed=56)
+    mg = smg.StructMG(T(A), shape, pattern=7, max_coarse=512, device=DEV)
+    assert mg.nlev == 1
+    f = workloads.rng(8).uniform(-1, 1, size=int(np.prod(shape)))
+    u = N(mg.op_coarse_solve(T(f), torch.empty(f.size, dtype=torch.float64, device=DEV)))
+    ref = np.linalg.solve(oracle.dense(workloads.offsets(7), A, shape), f)
+    assert np.abs(u - ref).max() <= 1e-12 * np.abs(ref).max()
+    H = oracle.Hierarchy(shape, 7, A, max_coarse=512)
+    xr, st, itr, relr = H.pcg(b, 1e-9, 50)
+    x = torch.zeros(b.size, dtype=torch.float64, device=DEV)
+    res = mg.solve(T(b.ravel()), x, rtol=1e-9, maxit=50)
+    assert res["status"] == 0 and res["rel_resid_true"] < 1e-9 and abs(res["iters"] - itr) <= 1
