@@ -61,7 +61,7 @@ def kernel_bytes(kind, S, N, Nc, w, smoother="gs", ncoarse=0):
 
 def wavefront_src_hash():
     h = hashlib.sha256()
-    for f in ("wavefront.hip", "stencil.hip", "smg_common.h"):
+    for f in ("wavefront.hip", "stencil.hip", "smg_common.h", "smg_group.h", "smg_kernels.h"):
         with open(os.path.join(ROOT, "paper_2506_21932_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -123,6 +123,131 @@ def cpu_baseline(name, budget_s=30.0):
             "sample": f"{sample}; measured {t:.1f}s, {it} iterations, rel resid {rel:.2e}"}
 
 
+# ---- supplementary workloads (opt-in; the default line is the 256^3 diffusion)
+def _timed(fn, torch, reps):
+    out, times = None, []
+    for k in range(1 + reps):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        if k > 0:
+            times.append((time.perf_counter() - ts) * 1e3)
+    return out, sum(times) / len(times)
+
+
+def _variants(args, smg, torch, np, dev, W, precs, tol, krylov, **kw):
+    A = torch.from_numpy(W["A"]).to(dev)
+    b = torch.from_numpy(W["b"].ravel().copy()).to(dev)
+    x = torch.zeros_like(b)
+    res = {}
+    for prec in precs:
+        m = smg.StructMG(A, W["shape"], device=dev, prec=prec, **kw)
+
+        def step():
+            m.resetup(A)
+            x.zero_()
+            return m.solve(b, x, rtol=tol, maxit=500, krylov=krylov)
+
+        r, ms = _timed(step, torch, args.steps)
+        res[prec] = {"ms_per_step": round(ms, 2), "iters": r["iters"], "rel_resid_true": r["rel_resid_true"],
+                     "converged": r["status"] == 0 and r["rel_resid_true"] < tol,
+                     "t_setup_ms": round(r["t_setup_ms"], 2), "t_solve_ms": round(r["t_solve_ms"], 2),
+                     "levels": r["levels"]}
+        print(f"[bench] {prec}: {res[prec]}", file=sys.stderr, flush=True)
+        m.close()
+        del m
+    for prec in precs:
+        res[prec]["speedup_vs_fp64"] = round(res["fp64"]["ms_per_step"] / res[prec]["ms_per_step"], 3)
+    return res
+
+
+def extra_weather(args, smg, torch, np, dev):
+    import workloads
+    shape = (512, 512, 64)
+    A, b = workloads.weather19(shape, seed=3)
+    W = dict(shape=shape, A=A, b=b)
+    res = _variants(args, smg, torch, np, dev, W, ("fp64", "fp32"), 1e-9, 30, pattern=19, smoother="ilu0",
+                    coarsen="semi_xy", gmres_restart=30)
+    print(json.dumps({"metric": METRIC, "value": res["fp32"]["ms_per_step"], "unit": "ms", "n_gpus": 1,
+                      "steps": args.steps, "higher_is_better": False, "dtype": "f32 V-cycle / f64 GMRES",
+                      "data": "synthetic (seeded)",
+                      "config": {"workload": "weather-like 512x512x64, 19-pt, vertical 100x, GMRES(30) + ILU(0) "
+                                             "V-cycle, xy-semi coarsening, tol 1e-9"},
+                      "variants": res}), flush=True)
+
+
+def extra_elasticity(args, smg, torch, np, dev):
+    import workloads
+    n = 128
+    A, b = workloads.elasticity27(n, seed=4)
+    W = dict(shape=(n, n, n), A=A, b=b)
+    res = _variants(args, smg, torch, np, dev, W, ("fp64", "fp32", "fp16"), 1e-8, 0, pattern=27, block=3)
+    print(json.dumps({"metric": METRIC, "value": res["fp16"]["ms_per_step"], "unit": "ms", "n_gpus": 1,
+                      "steps": args.steps, "higher_is_better": False, "dtype": "f16 V-cycle / f64 PCG",
+                      "data": "synthetic (seeded)",
+                      "config": {"workload": "elasticity-like 128^3 x 3, 27-pt 3x3 blocks, Q1 FEM, log-normal "
+                                             "moduli (sigma 1), nu 0.3, PCG + block-GS V-cycle, tol 1e-8"},
+                      "variants": res}), flush=True)
+
+
+def extra_batch(args, smg, torch, np, dev):
+    import workloads
+    dims = workloads.reservoir_batch(256, seed=5)
+    t0 = time.perf_counter()
+    systems = [workloads.reservoir7(d, seed=1000 + k) for k, d in enumerate(dims)]
+    print(f"[bench] 256 systems generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    kw = dict(pattern=7, coarsen="full", semi_levels=3, max_coarse=512)
+    As = [torch.from_numpy(A).to(dev) for A, _ in systems]
+    bs = [torch.from_numpy(b.ravel().copy()).to(dev) for _, b in systems]
+    ncells = sum(int(np.prod(d)) for d in dims)
+    out = {}
+    for prec in ("fp32", "fp64"):
+        B = smg.StructMGBatch(As, dims, prec=prec, **kw)
+        tune = B.tune()
+        xs = [torch.zeros_like(b) for b in bs]
+
+        def solve():
+            for x in xs:
+                x.zero_()
+            return B.solve(bs, xs, rtol=1e-9, maxit=300)
+
+        (st, res), ms = _timed(solve, torch, args.steps)
+        out[f"batched_{prec}"] = {"ms": round(ms, 2), "systems_per_s": round(256 / (ms * 1e-3), 2),
+                                  "all_converged": st == 0 and all(r["rel_resid_true"] < 1e-9 for r in res),
+                                  "max_iters": max(r["iters"] for r in res),
+                                  "mean_iters": round(float(np.mean([r["iters"] for r in res])), 2),
+                                  "t_setup_ms": round(res[0]["t_setup_ms"], 1), "schedule": tune}
+        print(f"[bench] batched {prec}: {out[f'batched_{prec}']}", file=sys.stderr, flush=True)
+        B.close()
+        del B
+    # the FP64 path one system after another (single-system solver)
+    hs = [smg.StructMG(A, d, device=dev, prec="fp64", **kw) for A, d in zip(As, dims)]
+    xs = [torch.zeros_like(b) for b in bs]
+
+    def seq():
+        rs = []
+        for m, b, x in zip(hs, bs, xs):
+            x.zero_()
+            rs.append(m.solve(b, x, rtol=1e-9, maxit=300))
+        return rs
+
+    rs, ms = _timed(seq, torch, args.steps)
+    out["sequential_fp64"] = {"ms": round(ms, 2), "systems_per_s": round(256 / (ms * 1e-3), 2),
+                              "all_converged": all(r["status"] == 0 for r in rs)}
+    for k in ("batched_fp32", "batched_fp64"):
+        out[k]["speedup_vs_sequential_fp64"] = round(out["sequential_fp64"]["ms"] / out[k]["ms"], 2)
+    print(json.dumps({"metric": METRIC, "value": out["batched_fp32"]["systems_per_s"], "unit": "systems/s",
+                      "n_gpus": 1, "steps": args.steps, "higher_is_better": True,
+                      "dtype": "f32 V-cycle / f64 PCG", "data": "synthetic (seeded)",
+                      "config": {"workload": f"256 reservoir-like 7-pt systems, dims uniform in [16,96]^3 "
+                                             f"({ncells} cells), kz/kx = 0.01, xy-semi x3 then full, tol 1e-9"},
+                      "variants": out}), flush=True)
+
+
+EXTRA = {"weather512": extra_weather, "elasticity128": extra_elasticity, "reservoir_batch256": extra_batch}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +255,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="diffusion256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 / FP16 V-cycle variants")
     ap.add_argument("--breakdown", action="store_true", help="print per-kernel table to stderr")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -142,6 +268,9 @@ def main():
     import paper_2506_21932_amd as smg
 
     dev = torch.device("cuda:0")
+    if args.workload in EXTRA:
+        EXTRA[args.workload](args, smg, torch, np, dev)
+        return
     t_gen = time.perf_counter()
     W = make_workload(args.workload)
     t_gen = time.perf_counter() - t_gen
@@ -239,6 +368,31 @@ def main():
                        "operator": round(results[-1]["op_complexity"], 4)},
         "kernels": breakdown,
     }
+    if not args.no_mixed:
+        # the same workload with the V-cycle in FP32 and in FP16 (per-row
+        # scaled) storage, inside the FP64 PCG: time-to-solution against FP64
+        mg.set_timing(False)
+        mixed = {}
+        for prec in ("fp32", "fp16"):
+            m2 = smg.StructMG(A, shape, device=dev, prec=prec, **kw)
+            times, r = [], None
+            for k in range(1 + args.steps):
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                m2.resetup(A)
+                x.zero_()
+                r = m2.solve(b, x, rtol=1e-9, maxit=300, krylov=W["krylov"])
+                torch.cuda.synchronize()
+                if k > 0:
+                    times.append((time.perf_counter() - ts) * 1e3)
+            ms = float(np.mean(times))
+            mixed[prec] = {"ms_per_step": round(ms, 2), "iters": r["iters"], "rel_resid_true": r["rel_resid_true"],
+                           "converged": r["status"] == 0 and r["rel_resid_true"] < 1e-9,
+                           "t_setup_ms": round(r["t_setup_ms"], 2), "t_solve_ms": round(r["t_solve_ms"], 2),
+                           "speedup_vs_fp64": round(ms_per_step / ms, 3)}
+            m2.close()
+            del m2
+        line["mixed"] = mixed
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.workload)

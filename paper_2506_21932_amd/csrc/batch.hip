@@ -225,6 +225,7 @@ struct WfGrp {
 // One grouped stencil launch: segments, block map.
 struct Grp {
   int pat = 0;
+  bool small = false;  // small block shape (residual + restriction, prolongation)
   void* segs = nullptr;
   unsigned* bmap = nullptr;
   unsigned nblocks = 0;
@@ -327,9 +328,18 @@ size_t layout(smg_batch_s* B, const std::vector<Shape>& sh, char* base) {
       const Level& v = sh[s].lev[l];
       L.sys.push_back(s);
       tiles += (long)v.tl.ntx * v.tl.nty;
-      rrb += rr_blocks(v.g, v.cmask);
-      ppb += pp_blocks(v.g);
+      rrb += rr_blocks(v.g, v.cmask, false);
+      ppb += pp_blocks(v.g, false);
       L.pre.pat = L.post.pat = L.rr.pat = L.pp.pat = v.S;
+    }
+    // the block shape of a level's grouped launches follows their total size
+    L.rr.small = rr_small((unsigned)rrb);
+    L.pp.small = pp_small((unsigned)ppb);
+    rrb = ppb = 0;
+    for (int s : L.sys) {
+      const Level& v = sh[s].lev[l];
+      rrb += rr_blocks(v.g, v.cmask, L.rr.small);
+      ppb += pp_blocks(v.g, L.pp.small);
     }
     const size_t k = L.sys.size();
     L.pre.segs = ar.take<char>(k * SEGB);
@@ -481,8 +491,8 @@ hipError_t fill_tables(smg_batch_s* B) {
       rr.push_back(RRArgs<M>{v.g, v.cmask, PT::A(v), Fp<PT>(B, s, l), (const V*)v.ua, (V*)H->lev[l + 1].f, s});
       pp.push_back(PPArgs<M>{v.g, v.cmask, PT::A(v), Fp<PT>(B, s, l), (const V*)v.ua, (const V*)UBp<PT>(B, s, l + 1),
                              (V*)v.h, nullptr, s});
-      rrb.push_back(rr_blocks(v.g, v.cmask));
-      ppb.push_back(pp_blocks(v.g));
+      rrb.push_back(rr_blocks(v.g, v.cmask, L.rr.small));
+      ppb.push_back(pp_blocks(v.g, L.pp.small));
     }
     L.post.nt = L.pre.nt;
     if ((e = upload_typed(L.pre.segs, pre)) != hipSuccess) return e;
@@ -534,14 +544,14 @@ hipError_t bvcycle(smg_batch_s* B, const int* gate, hipStream_t st) {
     const LevelPh& L = B->lv[l];
     e = launch_wavefront_group<E>(L.pre.pat, +1, (const WfArgs<V>*)L.pre.segs, L.pre.tmap, L.pre.total, B->grid,
                                   gate, B->ctr, B->err, st);
-    if (e == hipSuccess) e = launch_rr_group<M>(L.rr.pat, (const RRArgs<M>*)L.rr.segs, L.rr.bmap, L.rr.nblocks, gate, st);
+    if (e == hipSuccess) e = launch_rr_group<M>(L.rr.pat, L.rr.small, (const RRArgs<M>*)L.rr.segs, L.rr.bmap, L.rr.nblocks, gate, st);
     if (e != hipSuccess) return e;
   }
   e = launch_gemv_group<V>((const GemvArgs<V>*)B->gemv.segs, B->gemv.bmap, B->gemv.nblocks, gate, st);
   if (e != hipSuccess) return e;
   for (int l = B->maxlev - 2; l >= 0; --l) {
     const LevelPh& L = B->lv[l];
-    e = launch_pp_group<M>(L.pp.pat, false, (const PPArgs<M>*)L.pp.segs, L.pp.bmap, L.pp.nblocks, gate, st);
+    e = launch_pp_group<M>(L.pp.pat, false, L.pp.small, (const PPArgs<M>*)L.pp.segs, L.pp.bmap, L.pp.nblocks, gate, st);
     if (e == hipSuccess)
       e = launch_wavefront_group<E>(L.post.pat, -1, (const WfArgs<V>*)L.post.segs, L.post.tmap, L.post.total, B->grid,
                                     gate, B->ctr, B->err, st);

@@ -111,18 +111,22 @@ struct GemvArgs {
   int sys;
 };
 unsigned spmv_blocks(const Grid& g);
-unsigned rr_blocks(const Grid& g, int cmask);
-unsigned pp_blocks(const Grid& g);
+// residual + restriction and prolongation: large or small blocks (chosen by
+// rr_small / pp_small from the large-block count of one grid or a group)
+unsigned rr_blocks(const Grid& g, int cmask, bool small);
+unsigned pp_blocks(const Grid& g, bool small);
+bool rr_small(unsigned big_blocks);
+bool pp_small(unsigned big_blocks);
 unsigned gemv_blocks(int n);
 template <class M>
 hipError_t launch_spmv_group(int pat, bool res, const SpmvArgs<M>* segs, const unsigned* bmap, unsigned nblocks,
                              const int* live, hipStream_t st);
 template <class M>
-hipError_t launch_rr_group(int pat, const RRArgs<M>* segs, const unsigned* bmap, unsigned nblocks, const int* live,
-                           hipStream_t st);
-template <class M>
-hipError_t launch_pp_group(int pat, bool full, const PPArgs<M>* segs, const unsigned* bmap, unsigned nblocks,
+hipError_t launch_rr_group(int pat, bool small, const RRArgs<M>* segs, const unsigned* bmap, unsigned nblocks,
                            const int* live, hipStream_t st);
+template <class M>
+hipError_t launch_pp_group(int pat, bool full, bool small, const PPArgs<M>* segs, const unsigned* bmap,
+                           unsigned nblocks, const int* live, hipStream_t st);
 template <class V>
 hipError_t launch_gemv_group(const GemvArgs<V>* segs, const unsigned* bmap, unsigned nblocks, const int* live,
                              hipStream_t st);

@@ -94,12 +94,20 @@ hipError_t launch_spmv_group(int pat, bool res, const SpmvArgs<M>* segs, const u
 // Phase 1 computes the fine residuals of the block's footprint into LDS;
 // phase 2 restricts them.  A residual shared by two blocks is recomputed
 // (identically) by both.
-constexpr int RB_X = 4, RB_Y = 4, RB_Z = 16;
+// Coarse block per workgroup: 4 x 4 x 16 on large levels; 2 x 2 x 4 where
+// the large blocks would leave most compute units idle (small levels), so
+// that each thread computes about one residual and the kernel's latency is
+// one round of loads.  Results do not depend on the block shape.
+template <bool SMALL>
+struct RBT {
+  static constexpr int X = SMALL ? 2 : 4, Y = SMALL ? 2 : 4, Z = SMALL ? 4 : 16;
+};
 
 __host__ __device__ inline int rr_ext(int cm, int cb) { return cm ? 2 * cb + 1 : cb; }
 
-template <int PAT, class M>
+template <int PAT, class M, bool SMALL>
 struct RROp {
+  static constexpr int RB_X = RBT<SMALL>::X, RB_Y = RBT<SMALL>::Y, RB_Z = RBT<SMALL>::Z;
   using Args = RRArgs<M>;
   __device__ static void run(const Args& a, unsigned bid_) {
   const Grid gf = a.g;
@@ -153,20 +161,30 @@ struct RROp {
   }
 };
 
-unsigned rr_blocks(const Grid& g, int cmask) {
+template <bool SMALL>
+static unsigned rr_blocks_t(const Grid& g, int cmask) {
+  constexpr int BX = RBT<SMALL>::X, BY = RBT<SMALL>::Y, BZ = RBT<SMALL>::Z;
   const int cx = (cmask & 1) ? g.nx / 2 : g.nx, cy = (cmask & 2) ? g.ny / 2 : g.ny, cz = (cmask & 4) ? g.nz / 2 : g.nz;
-  return (unsigned)(((cx + RB_X - 1) / RB_X) * ((cy + RB_Y - 1) / RB_Y) * ((cz + RB_Z - 1) / RB_Z));
+  return (unsigned)(((cx + BX - 1) / BX) * ((cy + BY - 1) / BY) * ((cz + BZ - 1) / BZ));
 }
+unsigned rr_blocks(const Grid& g, int cmask, bool small) {
+  return small ? rr_blocks_t<true>(g, cmask) : rr_blocks_t<false>(g, cmask);
+}
+bool rr_small(unsigned big_blocks) { return big_blocks < 1024; }
 
 template <class M>
 hipError_t launch_resid_restrict(int pat, const Grid& g, int cmask, const M& m, const typename M::V* f,
                                  const typename M::V* u, typename M::V* rc, hipStream_t st) {
   const RRArgs<M> a{g, cmask, m, f, u, rc, 0};
-  const unsigned nb = rr_blocks(g, cmask);
-#define SMG_RR(P)                                                                      \
-  if (pat == P) {                                                                      \
-    hipLaunchKernelGGL((k_one<RROp<P, M>>), dim3(nb), dim3(256), 0, st, a);          \
-    return hipGetLastError();                                                          \
+  const bool small = rr_small(rr_blocks(g, cmask, false));
+  const unsigned nb = rr_blocks(g, cmask, small);
+#define SMG_RR(P)                                                                          \
+  if (pat == P) {                                                                          \
+    if (small)                                                                             \
+      hipLaunchKernelGGL((k_one<RROp<P, M, true>>), dim3(nb), dim3(256), 0, st, a);       \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_one<RROp<P, M, false>>), dim3(nb), dim3(256), 0, st, a);      \
+    return hipGetLastError();                                                              \
   }
   SMG_RR(7)
   SMG_RR(19)
@@ -176,13 +194,16 @@ hipError_t launch_resid_restrict(int pat, const Grid& g, int cmask, const M& m, 
 }
 
 template <class M>
-hipError_t launch_rr_group(int pat, const RRArgs<M>* segs, const unsigned* bmap, unsigned nblocks, const int* live,
-                           hipStream_t st) {
+hipError_t launch_rr_group(int pat, bool small, const RRArgs<M>* segs, const unsigned* bmap, unsigned nblocks,
+                           const int* live, hipStream_t st) {
   if (nblocks == 0) return hipSuccess;
-#define SMG_RR(P)                                                                                       \
-  if (pat == P) {                                                                                       \
-    hipLaunchKernelGGL((k_group<RROp<P, M>>), dim3(nblocks), dim3(256), 0, st, segs, bmap, live);      \
-    return hipGetLastError();                                                                           \
+#define SMG_RR(P)                                                                                              \
+  if (pat == P) {                                                                                              \
+    if (small)                                                                                                 \
+      hipLaunchKernelGGL((k_group<RROp<P, M, true>>), dim3(nblocks), dim3(256), 0, st, segs, bmap, live);     \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_group<RROp<P, M, false>>), dim3(nblocks), dim3(256), 0, st, segs, bmap, live);    \
+    return hipGetLastError();                                                                                  \
   }
   SMG_RR(7)
   SMG_RR(19)
@@ -239,10 +260,16 @@ __device__ inline V interp_point(const V* __restrict__ ec, const Grid& gc, int c
 }
 
 // --------------------------------- prolongation + post-smoother input
-constexpr int PP_X = 8, PP_Y = 8, PP_Z = 32;
+// Fine block per workgroup: 8 x 8 x 32 on large levels, 4 x 4 x 8 on small
+// ones (as for the restriction).
+template <bool SMALL>
+struct PBT {
+  static constexpr int X = SMALL ? 4 : 8, Y = SMALL ? 4 : 8, Z = SMALL ? 8 : 32;
+};
 
-template <int PAT, class M, bool FULL>
+template <int PAT, class M, bool FULL, bool SMALL>
 struct PPOp {
+  static constexpr int PP_X = PBT<SMALL>::X, PP_Y = PBT<SMALL>::Y, PP_Z = PBT<SMALL>::Z;
   using Args = PPArgs<M>;
   __device__ static void run(const Args& a, unsigned bid_) {
   const Grid gf = a.g;
@@ -299,47 +326,66 @@ struct PPOp {
   }
 };
 
-unsigned pp_blocks(const Grid& g) {
-  return (unsigned)(((g.nx + PP_X - 1) / PP_X) * ((g.ny + PP_Y - 1) / PP_Y) * ((g.nz + PP_Z - 1) / PP_Z));
+template <bool SMALL>
+static unsigned pp_blocks_t(const Grid& g) {
+  constexpr int BX = PBT<SMALL>::X, BY = PBT<SMALL>::Y, BZ = PBT<SMALL>::Z;
+  return (unsigned)(((g.nx + BX - 1) / BX) * ((g.ny + BY - 1) / BY) * ((g.nz + BZ - 1) / BZ));
 }
+unsigned pp_blocks(const Grid& g, bool small) { return small ? pp_blocks_t<true>(g) : pp_blocks_t<false>(g); }
+bool pp_small(unsigned big_blocks) { return big_blocks < 1024; }
 
 template <class M>
 hipError_t launch_prolong_post(int pat, const Grid& g, int cmask, const M& m, const typename M::V* f,
                                const typename M::V* u, const typename M::V* ec, typename M::V* h,
                                typename M::V* uold_out, bool full, hipStream_t st) {
   const PPArgs<M> a{g, cmask, m, f, u, ec, h, uold_out, 0};
-  const unsigned nb = pp_blocks(g);
-#define SMG_PP(P)                                                                        \
-  if (pat == P) {                                                                        \
-    if (full)                                                                            \
-      hipLaunchKernelGGL((k_one<PPOp<P, M, true>>), dim3(nb), dim3(256), 0, st, a);     \
-    else                                                                                 \
-      hipLaunchKernelGGL((k_one<PPOp<P, M, false>>), dim3(nb), dim3(256), 0, st, a);    \
-    return hipGetLastError();                                                            \
+  const bool small = pp_small(pp_blocks(g, false));
+  const unsigned nb = pp_blocks(g, small);
+#define SMG_PP2(P, F)                                                                          \
+  if (small)                                                                                   \
+    hipLaunchKernelGGL((k_one<PPOp<P, M, F, true>>), dim3(nb), dim3(256), 0, st, a);          \
+  else                                                                                         \
+    hipLaunchKernelGGL((k_one<PPOp<P, M, F, false>>), dim3(nb), dim3(256), 0, st, a);
+#define SMG_PP(P)                                                                              \
+  if (pat == P) {                                                                              \
+    if (full) {                                                                                \
+      SMG_PP2(P, true)                                                                         \
+    } else {                                                                                   \
+      SMG_PP2(P, false)                                                                        \
+    }                                                                                          \
+    return hipGetLastError();                                                                  \
   }
   SMG_PP(7)
   SMG_PP(19)
   SMG_PP(27)
 #undef SMG_PP
+#undef SMG_PP2
   return hipErrorInvalidValue;
 }
 
 template <class M>
-hipError_t launch_pp_group(int pat, bool full, const PPArgs<M>* segs, const unsigned* bmap, unsigned nblocks,
-                           const int* live, hipStream_t st) {
+hipError_t launch_pp_group(int pat, bool full, bool small, const PPArgs<M>* segs, const unsigned* bmap,
+                           unsigned nblocks, const int* live, hipStream_t st) {
   if (nblocks == 0) return hipSuccess;
-#define SMG_PP(P)                                                                                           \
-  if (pat == P) {                                                                                           \
-    if (full)                                                                                               \
-      hipLaunchKernelGGL((k_group<PPOp<P, M, true>>), dim3(nblocks), dim3(256), 0, st, segs, bmap, live);  \
-    else                                                                                                    \
-      hipLaunchKernelGGL((k_group<PPOp<P, M, false>>), dim3(nblocks), dim3(256), 0, st, segs, bmap, live); \
-    return hipGetLastError();                                                                               \
+#define SMG_PP2(P, F)                                                                                           \
+  if (small)                                                                                                    \
+    hipLaunchKernelGGL((k_group<PPOp<P, M, F, true>>), dim3(nblocks), dim3(256), 0, st, segs, bmap, live);     \
+  else                                                                                                          \
+    hipLaunchKernelGGL((k_group<PPOp<P, M, F, false>>), dim3(nblocks), dim3(256), 0, st, segs, bmap, live);
+#define SMG_PP(P)                                                                                               \
+  if (pat == P) {                                                                                               \
+    if (full) {                                                                                                 \
+      SMG_PP2(P, true)                                                                                          \
+    } else {                                                                                                    \
+      SMG_PP2(P, false)                                                                                         \
+    }                                                                                                           \
+    return hipGetLastError();                                                                                   \
   }
   SMG_PP(7)
   SMG_PP(19)
   SMG_PP(27)
 #undef SMG_PP
+#undef SMG_PP2
   return hipErrorInvalidValue;
 }
 
@@ -410,10 +456,10 @@ SMG_INST(MatH)
 #define SMG_GINST(M)                                                                                           \
   template hipError_t launch_spmv_group<M>(int, bool, const SpmvArgs<M>*, const unsigned*, unsigned, const int*, \
                                            hipStream_t);                                                       \
-  template hipError_t launch_rr_group<M>(int, const RRArgs<M>*, const unsigned*, unsigned, const int*,           \
+  template hipError_t launch_rr_group<M>(int, bool, const RRArgs<M>*, const unsigned*, unsigned, const int*,     \
                                          hipStream_t);                                                         \
-  template hipError_t launch_pp_group<M>(int, bool, const PPArgs<M>*, const unsigned*, unsigned, const int*,     \
-                                         hipStream_t);
+  template hipError_t launch_pp_group<M>(int, bool, bool, const PPArgs<M>*, const unsigned*, unsigned,           \
+                                         const int*, hipStream_t);
 SMG_GINST(MatD)
 SMG_GINST(MatF)
 SMG_GINST(MatH)
