@@ -386,11 +386,16 @@ typedef struct {
 /* Axes coarsened to go from level `lev` with dims n[] to the next level:
  * every allowed axis whose size is at least 8 (coarse size >= 4).  Allowed
  * axes are x and y on the first `semi_levels` levels (or always, for the
- * semi mode), all three otherwise. */
+ * semi mode), all three otherwise.  A level of the first `semi_levels` whose
+ * x and y can no longer be coarsened takes all three axes instead (the
+ * switch to full coarsening comes early rather than the hierarchy ending). */
 static int orc_next_cmask(int lev, const int* n, int semi_mode, int semi_levels) {
   int allowed = (semi_mode || lev < semi_levels) ? 3 : 7, m = 0;
   for (int a = 0; a < 3; ++a)
     if (((allowed >> a) & 1) && n[a] >= 8) m |= 1 << a;
+  if (m == 0 && !semi_mode && allowed == 3)
+    for (int a = 0; a < 3; ++a)
+      if (n[a] >= 8) m |= 1 << a;
   return m;
 }
 

@@ -69,10 +69,16 @@ struct Arena {
   }
 };
 
+// Axes coarsened from level lev (dims n): the allowed axes with >= 8 points;
+// x,y only on the first semi_levels levels (or always in semi mode), where a
+// level whose x and y cannot be coarsened any more switches to all axes.
 int next_cmask(int lev, const int* n, int semi, int semi_levels) {
   int allowed = (semi || lev < semi_levels) ? 3 : 7, m = 0;
   for (int a = 0; a < 3; ++a)
     if (((allowed >> a) & 1) && n[a] >= 8) m |= 1 << a;
+  if (m == 0 && !semi && allowed == 3)
+    for (int a = 0; a < 3; ++a)
+      if (n[a] >= 8) m |= 1 << a;
   return m;
 }
 

@@ -483,3 +483,21 @@ def test_fp16_truncation_rule():
     H32 = oracle.Hierarchy(shape, 7, A, prec="fp32")
     assert np.array_equal(H32.level_data(0, 5), A.astype(np.float32))
     assert np.array_equal(H32.level_data(0, 6), (1.0 / A[3]).astype(np.float32).reshape(1, -1))
+
+
+def test_coarsening_rule_level_dims():
+    """Level grids of the coarsening rule, worked out by hand: an axis is
+    halved (floor) while allowed and >= 8; x,y only on the first semi_levels
+    levels, switching to all axes early once x and y are both below 8."""
+    A, _ = workloads.reservoir7((16, 19, 56), seed=1)
+    H = oracle.Hierarchy((16, 19, 56), 7, A, semi_levels=3, max_coarse=512)
+    dims = [H.level_info(l)["dims"] for l in range(H.nlev)]
+    assert dims == [(16, 19, 56), (8, 9, 56), (4, 4, 56), (4, 4, 28), (4, 4, 14), (4, 4, 7)]
+    # full coarsening from the start
+    A, _ = workloads.reservoir7((17, 9, 8), seed=2)
+    H = oracle.Hierarchy((17, 9, 8), 7, A)
+    assert [H.level_info(l)["dims"] for l in range(H.nlev)] == [(17, 9, 8), (8, 4, 4), (4, 4, 4)]
+    # semi mode never coarsens z
+    A, _ = workloads.reservoir7((16, 16, 40), seed=3)
+    H = oracle.Hierarchy((16, 16, 40), 7, A, coarsen="semi_xy")
+    assert [H.level_info(l)["dims"] for l in range(H.nlev)] == [(16, 16, 40), (8, 8, 40), (4, 4, 40)]
