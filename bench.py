@@ -368,6 +368,22 @@ def main():
                        "operator": round(results[-1]["op_complexity"], 4)},
         "kernels": breakdown,
     }
+    # the same steps with the V-cycle replayed from a captured graph (kernel
+    # timing off): time-to-solution only
+    mg.set_timing(False)
+    mg.set_graph(True)
+    gtimes = []
+    for k in range(1 + args.steps):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        mg.resetup(A)
+        x.zero_()
+        rg = mg.solve(b, x, rtol=1e-9, maxit=300, krylov=W["krylov"])
+        torch.cuda.synchronize()
+        if k > 0:
+            gtimes.append((time.perf_counter() - ts) * 1e3)
+    line["graph"] = {"ms_per_step": round(float(np.mean(gtimes)), 2), "iters": rg["iters"],
+                     "converged": rg["status"] == 0 and rg["rel_resid_true"] < 1e-9}
     if not args.no_mixed:
         # the same workload with the V-cycle in FP32 and in FP16 (per-row
         # scaled) storage, inside the FP64 PCG: time-to-solution against FP64

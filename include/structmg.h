@@ -113,6 +113,11 @@ smg_status smg_solve(smg_handle h, const double* b, double* x, double rtol, int 
 
 smg_status smg_destroy(smg_handle h);
 
+/* PCG in smg_solve replays one captured HIP graph per V-cycle (1, default;
+ * captured at the first solve, not used while kernel timing is on) or
+ * launches the V-cycle's kernels one by one (0).  Results are identical. */
+smg_status smg_set_graph(smg_handle h, int enable);
+
 /* Message of the last failed call on h (or of the last failed setup when h is
  * NULL).  Never NULL. */
 const char* smg_last_error(smg_handle h);

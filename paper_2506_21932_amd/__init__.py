@@ -44,7 +44,7 @@ EXPORTS = ["smg_workspace_size", "smg_setup", "smg_precondition", "smg_solve", "
            "smg_op_prolong_add", "smg_op_coarse_solve", "smg_set_timing", "smg_timing_report", "smg_resetup",
            "smg_batch_workspace_size", "smg_batch_setup", "smg_batch_precondition", "smg_batch_solve",
            "smg_batch_set_schedule", "smg_batch_tune", "smg_batch_set_graph", "smg_batch_num_systems",
-           "smg_batch_system", "smg_batch_destroy", "smg_batch_last_error"]
+           "smg_batch_system", "smg_batch_destroy", "smg_batch_last_error", "smg_set_graph"]
 
 TIMING_KINDS = ["pre_sweep", "pre_sweep_u", "resid_restrict", "coarse_solve", "prolong_post", "post_sweep",
                 "post_sweep_u", "spmv_fp64"]
@@ -85,6 +85,7 @@ def load():
     L.smg_set_timing.argtypes = [vp, i, i, C.c_uint]
     L.smg_resetup.argtypes = [vp, vp, vp]
     L.smg_timing_report.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int), i, C.POINTER(C.c_int)]
+    L.smg_set_graph.argtypes = [vp, i]
     L.smg_batch_workspace_size.argtypes = [i, C.POINTER(Config), C.POINTER(C.c_size_t)]
     L.smg_batch_setup.argtypes = [i, C.POINTER(Config), C.POINTER(vp), vp, C.c_size_t, vp, C.POINTER(vp)]
     L.smg_batch_precondition.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
@@ -250,6 +251,9 @@ class StructMG:
         if st != SMG_OK:
             raise SmgError(st, load().smg_last_error(None).decode())
         return int(n.value)
+
+    def set_graph(self, enable):
+        self._check(self.L.smg_set_graph(self.h, int(bool(enable))), self.h)
 
     def op_coarse_solve(self, f, u):
         self._check(self.L.smg_op_coarse_solve(self.h, _ptr(f), _ptr(u), _stream()), self.h)

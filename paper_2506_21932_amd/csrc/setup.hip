@@ -126,16 +126,25 @@ hipError_t launch_block_dinv(const Grid& g, const double* A, double* Dinv, unsig
 // lower slots in canonical (= ascending column) order, w[s] /= U_c[k], then
 // w[slot(off_s+off_t)] = fma(-w[s], U_t[k], w[...]) for the upper slots t of
 // row k in canonical order, dropping fill outside the mask.
+// Threads cover only the band of columns that meet the hyperplane: for each
+// x, the kb = nz / wy + 2 largest y with z = tau - wx*x - wy*y >= 0.
+__host__ __device__ constexpr int ilu_band(int nz, int wy) { return nz / wy + 2; }
+
 template <int PAT>
 __global__ __launch_bounds__(256) void k_ilu0_plane(Grid g, int tau, const double* __restrict__ A,
                                                     double* __restrict__ L, double* __restrict__ U,
                                                     double* __restrict__ rU, unsigned* err) {
   constexpr int C = PAT / 2, WX = hp_wx(PAT), WY = hp_wy(PAT);
   const long N = g.N();
-  const unsigned col = blockIdx.x * 256u + threadIdx.x;
-  if (col >= (unsigned)(g.nx * g.ny)) return;
-  const int X = (int)(col / (unsigned)g.ny), Y = (int)(col % (unsigned)g.ny);
-  const int Z = tau - WX * X - WY * Y;
+  const int kb = ilu_band(g.nz, WY);
+  const unsigned t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= (unsigned)(g.nx * kb)) return;
+  const int X = (int)(t / (unsigned)kb);
+  const int rem = tau - WX * X;
+  if (rem < 0) return;
+  const int Y = rem / WY - (int)(t % (unsigned)kb);
+  if (Y < 0 || Y >= g.ny) return;
+  const int Z = rem - WY * Y;
   if (Z < 0 || Z >= g.nz) return;
   const long i = ((long)X * g.ny + Y) * g.nz + Z;
   const long nyz = (long)g.ny * g.nz;
@@ -174,7 +183,7 @@ __global__ __launch_bounds__(256) void k_ilu0_plane(Grid g, int tau, const doubl
 hipError_t launch_ilu0_factor(int pat, const Grid& g, const double* A, double* L, double* U, double* rU,
                               unsigned* err, hipStream_t st) {
   const int D = hp_wx(pat) * (g.nx - 1) + hp_wy(pat) * (g.ny - 1) + g.nz;
-  const dim3 grid((unsigned)((g.nx * g.ny + 255) / 256)), blk(256);
+  const dim3 grid((unsigned)((g.nx * ilu_band(g.nz, hp_wy(pat)) + 255) / 256)), blk(256);
   for (int tau = 0; tau < D; ++tau) {
     if (pat == 7)
       hipLaunchKernelGGL((k_ilu0_plane<7>), grid, blk, 0, st, g, tau, A, L, U, rU, err);

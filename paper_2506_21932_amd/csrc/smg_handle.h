@@ -46,6 +46,11 @@ struct smg_handle_s {
   double t_setup_ms = 0.0;
   char msg[512] = {0};
   // kernel timing (profiling aid): event pairs per (level, kind)
+  // captured graph of the V-cycle on the solver's own vectors (kr -> kz)
+  bool use_graph = true;
+  hipStream_t cap = nullptr;
+  hipGraph_t vgraph = nullptr;
+  hipGraphExec_t vexec = nullptr;
   bool timing = false;
   int tm_level = -1;      // record only this level (-1: all)
   unsigned tm_kinds = ~0u;  // bit mask of recorded kinds

@@ -389,6 +389,39 @@ hipError_t spmv64(smg_handle_s* H, const double* x, const double* b, double* y, 
   return launch_spmv(l0.S, l0.g, MatD{l0.A64, l0.N}, x, b, y, res, st);
 }
 
+void drop_vgraph(smg_handle_s* H) {
+  if (H->vexec) (void)hipGraphExecDestroy(H->vexec);
+  if (H->vgraph) (void)hipGraphDestroy(H->vgraph);
+  H->vexec = nullptr;
+  H->vgraph = nullptr;
+}
+
+// z = M r on the solver's vectors: replays a captured graph of the whole
+// V-cycle (one launch for all its kernels) unless graphs are off or kernel
+// timing is on; the graph is captured at the first use.
+hipError_t vcycle_solver(smg_handle_s* H, hipStream_t st) {
+  if (!H->use_graph || H->timing) return vcycle(H, H->kr, H->kz, st);
+  if (!H->vexec) {
+    hipError_t e = hipSuccess;
+    if (!H->cap) e = hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(H->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t ev = vcycle(H, H->kr, H->kz, H->cap);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(H->cap, &g);
+    if (ev != hipSuccess) e = ev;
+    if (e == hipSuccess) {
+      H->vgraph = g;
+      e = hipGraphInstantiate(&H->vexec, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) drop_vgraph(H);
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipGraphLaunch(H->vexec, st);
+}
+
 smg_status check_err(smg_handle_s* H, hipStream_t st) {
   unsigned e = 0;
   HIPCHK(H, hipMemcpyAsync(&e, H->err, sizeof(unsigned), hipMemcpyDeviceToHost, st));
@@ -622,7 +655,7 @@ smg_status smg_solve(smg_handle H, const double* b, double* x, double rtol, int 
   smg_status status = SMG_ENOTCONV;
   if (rel < rtol) status = SMG_OK;
   if (krylov == 0 && status != SMG_OK) {
-    KCHK(vcycle(H, r, z, st));
+    KCHK(vcycle_solver(H, st));
     KCHK(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     double rho = KDOT(r, z);
     KCHK(e);
@@ -650,7 +683,7 @@ smg_status smg_solve(smg_handle H, const double* b, double* x, double rtol, int 
           break;
         }
       }
-      KCHK(vcycle(H, r, z, st));
+      KCHK(vcycle_solver(H, st));
       const double rho1 = KDOT(r, z);
       KCHK(e);
       const double beta = rho1 / rho;
@@ -751,7 +784,18 @@ smg_status smg_set_timing(smg_handle h, int enable, int level, unsigned kinds);
 
 smg_status smg_destroy(smg_handle h) {
   if (h && h->timing) smg_set_timing(h, 0, -1, 0);
+  if (h) {
+    drop_vgraph(h);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
+  }
   delete h;
+  return SMG_OK;
+}
+
+smg_status smg_set_graph(smg_handle h, int enable) {
+  if (!h) return fail(nullptr, SMG_EINVAL, "null handle");
+  h->use_graph = enable != 0;
+  drop_vgraph(h);
   return SMG_OK;
 }
 
