@@ -226,6 +226,7 @@ struct WfGrp {
 struct Grp {
   int pat = 0;
   bool small = false;  // small block shape (residual + restriction, prolongation)
+  unsigned stage = 0;  // prolongation: LDS-staged coarse values per block
   void* segs = nullptr;
   unsigned* bmap = nullptr;
   unsigned nblocks = 0;
@@ -336,10 +337,12 @@ size_t layout(smg_batch_s* B, const std::vector<Shape>& sh, char* base) {
     L.rr.small = rr_small((unsigned)rrb);
     L.pp.small = pp_small((unsigned)ppb);
     rrb = ppb = 0;
+    L.pp.stage = 0;
     for (int s : L.sys) {
       const Level& v = sh[s].lev[l];
       rrb += rr_blocks(v.g, v.cmask, L.rr.small);
       ppb += pp_blocks(v.g, L.pp.small);
+      L.pp.stage = std::max(L.pp.stage, pp_stage_elems(v.cmask, L.pp.small));
     }
     const size_t k = L.sys.size();
     L.pre.segs = ar.take<char>(k * SEGB);
@@ -551,7 +554,7 @@ hipError_t bvcycle(smg_batch_s* B, const int* gate, hipStream_t st) {
   if (e != hipSuccess) return e;
   for (int l = B->maxlev - 2; l >= 0; --l) {
     const LevelPh& L = B->lv[l];
-    e = launch_pp_group<M>(L.pp.pat, false, L.pp.small, (const PPArgs<M>*)L.pp.segs, L.pp.bmap, L.pp.nblocks, gate, st);
+    e = launch_pp_group<M>(L.pp.pat, false, L.pp.small, L.pp.stage, (const PPArgs<M>*)L.pp.segs, L.pp.bmap, L.pp.nblocks, gate, st);
     if (e == hipSuccess)
       e = launch_wavefront_group<E>(L.post.pat, -1, (const WfArgs<V>*)L.post.segs, L.post.tmap, L.post.total, B->grid,
                                     gate, B->ctr, B->err, st);

@@ -117,6 +117,8 @@ unsigned rr_blocks(const Grid& g, int cmask, bool small);
 unsigned pp_blocks(const Grid& g, bool small);
 bool rr_small(unsigned big_blocks);
 bool pp_small(unsigned big_blocks);
+// coarse values staged in LDS by one prolongation block (grid's mask)
+unsigned pp_stage_elems(int cmask, bool small);
 unsigned gemv_blocks(int n);
 template <class M>
 hipError_t launch_spmv_group(int pat, bool res, const SpmvArgs<M>* segs, const unsigned* bmap, unsigned nblocks,
@@ -124,9 +126,10 @@ hipError_t launch_spmv_group(int pat, bool res, const SpmvArgs<M>* segs, const u
 template <class M>
 hipError_t launch_rr_group(int pat, bool small, const RRArgs<M>* segs, const unsigned* bmap, unsigned nblocks,
                            const int* live, hipStream_t st);
+// stage_elems: the largest pp_stage_elems of the segments (0 when every ec is null)
 template <class M>
-hipError_t launch_pp_group(int pat, bool full, bool small, const PPArgs<M>* segs, const unsigned* bmap,
-                           unsigned nblocks, const int* live, hipStream_t st);
+hipError_t launch_pp_group(int pat, bool full, bool small, unsigned stage_elems, const PPArgs<M>* segs,
+                           const unsigned* bmap, unsigned nblocks, const int* live, hipStream_t st);
 template <class V>
 hipError_t launch_gemv_group(const GemvArgs<V>* segs, const unsigned* bmap, unsigned nblocks, const int* live,
                              hipStream_t st);

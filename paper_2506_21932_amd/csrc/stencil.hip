@@ -181,9 +181,9 @@ hipError_t launch_resid_restrict(int pat, const Grid& g, int cmask, const M& m, 
 #define SMG_RR(P)                                                                          \
   if (pat == P) {                                                                          \
     if (small)                                                                             \
-      hipLaunchKernelGGL((k_one<RROp<P, M, true>>), dim3(nb), dim3(256), 0, st, a);       \
+      hipLaunchKernelGGL((k_one_xcd<RROp<P, M, true>>), dim3(nb), dim3(256), 0, st, a);       \
     else                                                                                   \
-      hipLaunchKernelGGL((k_one<RROp<P, M, false>>), dim3(nb), dim3(256), 0, st, a);      \
+      hipLaunchKernelGGL((k_one_xcd<RROp<P, M, false>>), dim3(nb), dim3(256), 0, st, a);      \
     return hipGetLastError();                                                              \
   }
   SMG_RR(7)
@@ -214,15 +214,17 @@ hipError_t launch_rr_group(int pat, bool small, const RRArgs<M>* segs, const uns
 
 // --------------------------------------- interpolation of one fine point
 // pe = sum over parents (lexicographic) of w * e_J via fma, from zero.
-template <class V>
-__device__ inline V interp_point(const V* __restrict__ ec, const Grid& gc, int cmx, int cmy, int cmz, int fx, int fy,
-                                 int fz, int bs, int comp) {
+template <class V, class EC>
+__device__ inline V interp_point_at(const EC& ec_at, const Grid& gc, int cmx, int cmy, int cmz, int fx, int fy,
+                                    int fz) {
   int par[3][2], np[3];
   V wt[3][2];
   const int f[3] = {fx, fy, fz}, cm[3] = {cmx, cmy, cmz}, nc[3] = {gc.nx, gc.ny, gc.nz};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     np[a] = 0;
+    par[a][0] = par[a][1] = 0;
+    wt[a][0] = wt[a][1] = V(0);
     if (!cm[a]) {
       par[a][0] = f[a];
       wt[a][0] = V(1);
@@ -248,15 +250,28 @@ __device__ inline V interp_point(const V* __restrict__ ec, const Grid& gc, int c
       }
     }
   }
+  // parents in lexicographic order; fixed trip counts, absent parents
+  // predicated off (the same terms in the same order as a loop to np[a])
   V pe = V(0);
-  for (int p = 0; p < np[0]; ++p)
-    for (int q = 0; q < np[1]; ++q)
-      for (int r = 0; r < np[2]; ++r) {
-        const V w = wt[0][p] * wt[1][q] * wt[2][r];
-        const long J = ((long)par[0][p] * gc.ny + par[1][q]) * gc.nz + par[2][r];
-        pe = fma(w, ec[J * bs + comp], pe);
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        if (p < np[0] && q < np[1] && r < np[2]) {
+          const V w = wt[0][p] * wt[1][q] * wt[2][r];
+          pe = fma(w, ec_at(par[0][p], par[1][q], par[2][r]), pe);
+        }
       }
   return pe;
+}
+
+template <class V>
+__device__ inline V interp_point(const V* __restrict__ ec, const Grid& gc, int cmx, int cmy, int cmz, int fx, int fy,
+                                 int fz, int bs, int comp) {
+  auto at = [&](int X, int Y, int Z) { return ec[(((long)X * gc.ny + Y) * gc.nz + Z) * bs + comp]; };
+  return interp_point_at<V>(at, gc, cmx, cmy, cmz, fx, fy, fz);
 }
 
 // --------------------------------- prolongation + post-smoother input
@@ -289,12 +304,30 @@ struct PPOp {
   const int bid = (int)bid_;
   const int bz = bid % nbz, by = (bid / nbz) % nby, bx = bid / (nbz * nby);
   const int x0 = bx * PP_X - 1, y0 = by * PP_Y - 1, z0 = bz * PP_Z - 1;
+  // the coarse values interpolated into this block's fine region, staged in
+  // LDS: parents of fine x in [x0, x0+HX) lie in [floor((x0-1)/2), floor((x0+HX-1)/2)]
+  // staging buffer: dynamic LDS sized by the launch for the coarsening masks
+  // of its grids (pp_stage_elems)
+  extern __shared__ __align__(16) unsigned char pp_dyn[];
+  V* ecs = reinterpret_cast<V*>(pp_dyn);
+  auto fdiv2 = [](int v) { return v >= 0 ? v / 2 : -((1 - v) / 2); };
+  const int c0x = cmx ? fdiv2(x0 - 1) : x0, c0y = cmy ? fdiv2(y0 - 1) : y0, c0z = cmz ? fdiv2(z0 - 1) : z0;
+  const int ecx = cmx ? HX / 2 + 1 : HX, ecy = cmy ? HY / 2 + 1 : HY, ecz = cmz ? HZ / 2 + 1 : HZ;
+  const bool staged = ec != nullptr;
+  if (staged) {
+    for (int k = threadIdx.x; k < ecx * ecy * ecz; k += 256) {
+      const int cz = c0z + k % ecz, cy = c0y + (k / ecz) % ecy, cx = c0x + k / (ecz * ecy);
+      if (in_grid(gc, cx, cy, cz)) ecs[k] = ec[((long)cx * gc.ny + cy) * gc.nz + cz];
+    }
+    __syncthreads();
+  }
+  auto ec_at = [&](int X, int Y, int Z) { return ecs[((X - c0x) * ecy + (Y - c0y)) * ecz + (Z - c0z)]; };
   for (int k = threadIdx.x; k < HX * HY * HZ; k += 256) {
     const int fz = z0 + k % HZ, fy = y0 + (k / HZ) % HY, fx = x0 + k / (HZ * HY);
     if (!in_grid(gf, fx, fy, fz)) continue;
     const long i = ((long)fx * gf.ny + fy) * gf.nz + fz;
     V v = u[i];
-    if (ec != nullptr) v = v + interp_point(ec, gc, cmx, cmy, cmz, fx, fy, fz, 1, 0);
+    if (staged) v = v + interp_point_at<V>(ec_at, gc, cmx, cmy, cmz, fx, fy, fz);
     us[k] = v;
   }
   __syncthreads();
@@ -332,6 +365,12 @@ static unsigned pp_blocks_t(const Grid& g) {
   return (unsigned)(((g.nx + BX - 1) / BX) * ((g.ny + BY - 1) / BY) * ((g.nz + BZ - 1) / BZ));
 }
 unsigned pp_blocks(const Grid& g, bool small) { return small ? pp_blocks_t<true>(g) : pp_blocks_t<false>(g); }
+unsigned pp_stage_elems(int cmask, bool small) {
+  const int hx = (small ? PBT<true>::X : PBT<false>::X) + 2, hy = (small ? PBT<true>::Y : PBT<false>::Y) + 2,
+            hz = (small ? PBT<true>::Z : PBT<false>::Z) + 2;
+  return (unsigned)(((cmask & 1) ? hx / 2 + 1 : hx) * ((cmask & 2) ? hy / 2 + 1 : hy) *
+                    ((cmask & 4) ? hz / 2 + 1 : hz));
+}
 bool pp_small(unsigned big_blocks) { return big_blocks < 1024; }
 
 template <class M>
@@ -341,11 +380,12 @@ hipError_t launch_prolong_post(int pat, const Grid& g, int cmask, const M& m, co
   const PPArgs<M> a{g, cmask, m, f, u, ec, h, uold_out, 0};
   const bool small = pp_small(pp_blocks(g, false));
   const unsigned nb = pp_blocks(g, small);
+  const size_t dyn = ec != nullptr ? pp_stage_elems(cmask, small) * sizeof(typename M::V) : 0;
 #define SMG_PP2(P, F)                                                                          \
   if (small)                                                                                   \
-    hipLaunchKernelGGL((k_one<PPOp<P, M, F, true>>), dim3(nb), dim3(256), 0, st, a);          \
+    hipLaunchKernelGGL((k_one_xcd<PPOp<P, M, F, true>>), dim3(nb), dim3(256), dyn, st, a);    \
   else                                                                                         \
-    hipLaunchKernelGGL((k_one<PPOp<P, M, F, false>>), dim3(nb), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_one_xcd<PPOp<P, M, F, false>>), dim3(nb), dim3(256), dyn, st, a);
 #define SMG_PP(P)                                                                              \
   if (pat == P) {                                                                              \
     if (full) {                                                                                \
@@ -364,14 +404,15 @@ hipError_t launch_prolong_post(int pat, const Grid& g, int cmask, const M& m, co
 }
 
 template <class M>
-hipError_t launch_pp_group(int pat, bool full, bool small, const PPArgs<M>* segs, const unsigned* bmap,
-                           unsigned nblocks, const int* live, hipStream_t st) {
+hipError_t launch_pp_group(int pat, bool full, bool small, unsigned stage_elems, const PPArgs<M>* segs,
+                           const unsigned* bmap, unsigned nblocks, const int* live, hipStream_t st) {
   if (nblocks == 0) return hipSuccess;
-#define SMG_PP2(P, F)                                                                                           \
-  if (small)                                                                                                    \
-    hipLaunchKernelGGL((k_group<PPOp<P, M, F, true>>), dim3(nblocks), dim3(256), 0, st, segs, bmap, live);     \
-  else                                                                                                          \
-    hipLaunchKernelGGL((k_group<PPOp<P, M, F, false>>), dim3(nblocks), dim3(256), 0, st, segs, bmap, live);
+  const size_t dyn = stage_elems * sizeof(typename M::V);
+#define SMG_PP2(P, F)                                                                                             \
+  if (small)                                                                                                      \
+    hipLaunchKernelGGL((k_group<PPOp<P, M, F, true>>), dim3(nblocks), dim3(256), dyn, st, segs, bmap, live);     \
+  else                                                                                                            \
+    hipLaunchKernelGGL((k_group<PPOp<P, M, F, false>>), dim3(nblocks), dim3(256), dyn, st, segs, bmap, live);
 #define SMG_PP(P)                                                                                               \
   if (pat == P) {                                                                                               \
     if (full) {                                                                                                 \
@@ -458,7 +499,7 @@ SMG_INST(MatH)
                                            hipStream_t);                                                       \
   template hipError_t launch_rr_group<M>(int, bool, const RRArgs<M>*, const unsigned*, unsigned, const int*,     \
                                          hipStream_t);                                                         \
-  template hipError_t launch_pp_group<M>(int, bool, bool, const PPArgs<M>*, const unsigned*, unsigned,           \
+  template hipError_t launch_pp_group<M>(int, bool, bool, unsigned, const PPArgs<M>*, const unsigned*, unsigned, \
                                          const int*, hipStream_t);
 SMG_GINST(MatD)
 SMG_GINST(MatF)

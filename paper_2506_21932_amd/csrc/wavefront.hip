@@ -359,7 +359,8 @@ __device__ __forceinline__ void wf_tile(const WfArgs<typename WfVal<E>::V>& a, u
     }
     auto run_off = [&](int i, int s) {
       const int z = s - rsk0 - (WX - sh * WY) * i;
-      const bool ok = ((rmask >> i) & 1u) && (unsigned)z < (unsigned)nz;
+      // branch-free: both tests as bits
+      const unsigned ok = ((rmask >> i) & 1u) & (unsigned)((unsigned)z < (unsigned)nz);
       return ok ? (rb0 + (unsigned)i * rdi + (unsigned)z) * (unsigned)sizeof(V) : WF_OOB;
     };
     // right-hand side of chunk c: column runs i loaded into hc[i], then
