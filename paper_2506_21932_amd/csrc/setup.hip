@@ -2,6 +2,8 @@
 // zero padding), reciprocal diagonal, 3x3 diagonal-block inverses, ILU(0)
 // factorisation on the level's own mask (Sec. 4.2.3, Sec. 4.4 ILU), and
 // truncation of FP64 level data to FP32 or FP16 with a per-row FP32 scale.
+#include <utility>
+
 #include "smg_kernels.h"
 
 namespace smg {
@@ -121,6 +123,49 @@ hipError_t launch_block_dinv(const Grid& g, const double* A, double* Dinv, unsig
   return hipGetLastError();
 }
 
+// Compile-time unrolled elimination of one ILU(0) row (all slot indices are
+// constants): for lower slot S (canonical order) of the row, with the row k
+// of that neighbour: w[S] /= U_C[k], then for each upper slot T of row k in
+// canonical order whose combined offset lies in the mask and in the grid,
+// w[slot] = fma(-w[S], U_T[k], w[slot]).
+// Branch-free: loads use this row's slots when the neighbour row is outside
+// the grid (their values are then not used), and every update is a select,
+// so the loads of all rows can be issued together.
+template <int PAT, int S, int T>
+__device__ __forceinline__ void ilu_fill(double (&w)[PAT], const double* __restrict__ U, long N, long k, bool vs,
+                                         const Grid& g, int ax, int ay, int az) {
+  constexpr int dx = pat_off(PAT, S, 0) + pat_off(PAT, T, 0), dy = pat_off(PAT, S, 1) + pat_off(PAT, T, 1),
+                dz = pat_off(PAT, S, 2) + pat_off(PAT, T, 2);
+  if constexpr (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) {
+    constexpr int sl = pat_slot(PAT, dx, dy, dz);
+    if constexpr (sl >= 0) {
+      const double u = U[(long)T * N + k];
+      const bool in = vs && in_grid(g, ax + pat_off(PAT, T, 0), ay + pat_off(PAT, T, 1), az + pat_off(PAT, T, 2));
+      w[sl] = in ? fma(-w[S], u, w[sl]) : w[sl];
+    }
+  }
+}
+
+template <int PAT, int S, int... T>
+__device__ __forceinline__ void ilu_row(double (&w)[PAT], const Grid& g, int X, int Y, int Z, long i,
+                                        const double* __restrict__ U, std::integer_sequence<int, T...>) {
+  constexpr int C = PAT / 2;
+  const long N = g.N();
+  const int ax = X + pat_off(PAT, S, 0), ay = Y + pat_off(PAT, S, 1), az = Z + pat_off(PAT, S, 2);
+  const bool vs = in_grid(g, ax, ay, az);
+  const long k =
+      vs ? i + pat_off(PAT, S, 0) * ((long)g.ny * g.nz) + pat_off(PAT, S, 1) * (long)g.nz + pat_off(PAT, S, 2) : i;
+  const double ud = U[(long)C * N + k];
+  w[S] = vs ? w[S] / ud : w[S];
+  (ilu_fill<PAT, S, C + 1 + T>(w, U, N, k, vs, g, ax, ay, az), ...);
+}
+
+template <int PAT, int... S>
+__device__ __forceinline__ void ilu_rows(double (&w)[PAT], const Grid& g, int X, int Y, int Z, long i,
+                                         const double* __restrict__ U, std::integer_sequence<int, S...>) {
+  (ilu_row<PAT, S>(w, g, X, Y, Z, i, U, std::make_integer_sequence<int, PAT - PAT / 2 - 1>{}), ...);
+}
+
 // ILU(0) rows on one hyperplane wx*x + wy*y + z = tau (all their lower
 // neighbours lie on earlier hyperplanes).  Doolittle IKJ on the mask:
 // lower slots in canonical (= ascending column) order, w[s] /= U_c[k], then
@@ -152,25 +197,10 @@ __global__ __launch_bounds__(256) void k_ilu0_plane(Grid g, int tau, const doubl
 #pragma unroll
   for (int s = 0; s < PAT; ++s) {
     const bool in = in_grid(g, X + pat_off(PAT, s, 0), Y + pat_off(PAT, s, 1), Z + pat_off(PAT, s, 2));
-    w[s] = in ? A[(long)s * N + i] : 0.0;
+    const double a = A[(long)s * N + i];  // row i's own slot: always in bounds
+    w[s] = in ? a : 0.0;
   }
-#pragma unroll
-  for (int s = 0; s < C; ++s) {
-    const int ax = X + pat_off(PAT, s, 0), ay = Y + pat_off(PAT, s, 1), az = Z + pat_off(PAT, s, 2);
-    if (!in_grid(g, ax, ay, az)) continue;
-    const long k = i + pat_off(PAT, s, 0) * nyz + pat_off(PAT, s, 1) * g.nz + pat_off(PAT, s, 2);
-    w[s] = w[s] / U[(long)C * N + k];
-#pragma unroll
-    for (int t = C + 1; t < PAT; ++t) {
-      const int dx = pat_off(PAT, s, 0) + pat_off(PAT, t, 0), dy = pat_off(PAT, s, 1) + pat_off(PAT, t, 1),
-                dz = pat_off(PAT, s, 2) + pat_off(PAT, t, 2);
-      if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) continue;
-      const int sl = pat_slot(PAT, dx, dy, dz);
-      if (sl < 0) continue;
-      if (!in_grid(g, ax + pat_off(PAT, t, 0), ay + pat_off(PAT, t, 1), az + pat_off(PAT, t, 2))) continue;
-      w[sl] = fma(-w[s], U[(long)t * N + k], w[sl]);
-    }
-  }
+  ilu_rows<PAT>(w, g, X, Y, Z, i, U, std::make_integer_sequence<int, C>{});
 #pragma unroll
   for (int s = 0; s < PAT; ++s) {
     L[(long)s * N + i] = s < C ? w[s] : 0.0;
