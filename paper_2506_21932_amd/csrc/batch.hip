@@ -717,6 +717,9 @@ smg_status smg_batch_setup(int nsys, const smg_config* cfgs, const double* const
       bfail(B, ss, "system %d: %s", s, smg_last_error(nullptr));
       return bail(ss);
     }
+    // the batch's sweeps are tiled on every level; keep the system's own
+    // sweeps on the same data (sentinel protocol) when it is used alone
+    H->hp_on = false;
     B->h.push_back(H);
     off += (b + 255) & ~(size_t)255;
   }

@@ -27,6 +27,9 @@ struct Level {
   WfTiling tl{};                    // wavefront tiling
   void* pk[2] = {nullptr, nullptr};  // packed sweep data, forward / backward (V-cycle precision; FP16: halves)
   float* psd = nullptr;             // FP16: {row scale, diagonal scaling} per schedule position
+  int hp_steps = 0;                 // small level: hyperplanes of the one-workgroup sweep (0: tiled sweep)
+  int* hp_pts = nullptr;            // its point schedule [step][256]
+  void* hp_cf[2] = {nullptr, nullptr};  // its step-ordered coefficients, forward / backward
 };
 
 }  // namespace smg
@@ -48,6 +51,7 @@ struct smg_handle_s {
   // kernel timing (profiling aid): event pairs per (level, kind)
   // captured graph of the V-cycle on the solver's own vectors (kr -> kz)
   bool use_graph = true;
+  bool hp_on = true;  // small levels use the one-workgroup sweep (off inside batches)
   hipStream_t cap = nullptr;
   hipGraph_t vgraph = nullptr;
   hipGraphExec_t vexec = nullptr;

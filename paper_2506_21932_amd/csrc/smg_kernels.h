@@ -1,5 +1,7 @@
 // Host-side launchers of the device kernels (internal to libstructmg).
 #pragma once
+#include <vector>
+
 #include "smg_common.h"
 
 namespace smg {
@@ -65,6 +67,20 @@ template <class E>
 hipError_t launch_wavefront_group(int pat, int dir, const WfArgs<typename WfVal<E>::V>* segs, const unsigned* tmap,
                                   unsigned total, unsigned grid, const int* live, unsigned* ctr, unsigned* err,
                                   hipStream_t st);
+
+// ---- small levels: one-workgroup hyperplane sweep (hpsweep.hip) ---------
+// hp_plan: hyperplanes of the level, or 0 when it does not fit (pts: host
+// schedule [step][256] of box indices, -1 padded).  launch_hp_pack builds the
+// step-ordered coefficients of direction dir (src 0: FP64, 1: FP32 from the
+// FP64 data, 2: FP16 row-scaled storage); launch_hpsweep runs a forward
+// (dir > 0) or backward Gauss-Seidel sweep x = S(h) of the level.
+int hp_plan(const Grid& g, int pat, int vbytes, std::vector<int>* pts);
+hipError_t launch_hp_pack(int pat, int src, const Grid& g, int nsteps, int dir, const int* pts, const double* A,
+                          const double* rd, const __half* a16, const float* sc, const float* rd32, void* out,
+                          hipStream_t st);
+template <class V>
+hipError_t launch_hpsweep(int pat, int dir, const Grid& g, int nsteps, const int* pts, const V* cf, const V* h, V* x,
+                          hipStream_t st);
 
 // ---- grouped launches ---------------------------------------------------
 // Arguments of one grid of a kernel that can also run grouped (smg_group.h):

@@ -160,6 +160,13 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
       v.pk[0] = ar.take<char>(pbytes);
       v.pk[1] = ar.take<char>(pbytes);
       if (cfg.prec == SMG_FP16_ROWSCALE) v.psd = ar.take<float>((size_t)2 * v.tl.nsk);
+      v.hp_steps = cfg.smoother == SMG_SMOOTH_GS ? hp_plan(v.g, v.S, (int)vsz, nullptr) : 0;
+      if (v.hp_steps > 0) {
+        v.hp_pts = ar.take<int>((size_t)v.hp_steps * 256);
+        const size_t kv = 16 / vsz, npk = (v.S / 2 + 1 + kv - 1) / kv;  // 16-byte packs per point
+        v.hp_cf[0] = ar.take<char>((size_t)v.hp_steps * npk * 256 * 16);
+        v.hp_cf[1] = ar.take<char>((size_t)v.hp_steps * npk * 256 * 16);
+      }
     } else {
       bwf_tiling(v.g, &v.tl);
       const size_t pbytes = (size_t)bwf_pack_count(eb) * 16 * v.tl.nsk;
@@ -216,6 +223,9 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
 template <class E, class V>
 hipError_t sweep(smg_handle_s* H, const Level& L, int dir, bool unitd, const V* hin, V* x, V* next, int next_dir,
                  const V* addv, V* addout, hipStream_t st) {
+  // small level: every sweep on it runs in one workgroup (no sentinels used)
+  if (L.hp_steps > 0 && H->hp_on && !unitd && addout == nullptr)
+    return launch_hpsweep<V>(L.S, dir, L.g, L.hp_steps, L.hp_pts, (const V*)L.hp_cf[dir > 0 ? 0 : 1], hin, x, st);
   WfArgs<V> a{};
   a.g = L.g;
   a.t = L.tl;
@@ -522,6 +532,15 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
           SCHK(launch_wf_pack<float>(v.S, v.g, v.tl, dir, lo, dg, up, (float*)v.pk[d], st));
         else
           SCHK(launch_wf_pack_h(v.S, v.g, v.tl, dir, v.A16, v.sc16, v.rd32, (__half*)v.pk[d], v.psd, st));
+      }
+      if (v.hp_steps > 0) {
+        std::vector<int> pts;
+        hp_plan(v.g, v.S, cfg->prec == SMG_FP64 ? 8 : 4, &pts);
+        SCHK(hipMemcpy(v.hp_pts, pts.data(), sizeof(int) * pts.size(), hipMemcpyHostToDevice));
+        const int src = cfg->prec == SMG_FP64 ? 0 : (cfg->prec == SMG_FP32 ? 1 : 2);
+        for (int d = 0; d < 2; ++d)
+          SCHK(launch_hp_pack(v.S, src, v.g, v.hp_steps, d == 0 ? 1 : -1, v.hp_pts, v.A64, v.rd64, v.A16, v.sc16,
+                              v.rd32, v.hp_cf[d], st));
       }
     }
     const long nv = v.N * bs;
