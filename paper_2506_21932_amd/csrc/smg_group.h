@@ -2,8 +2,9 @@
 //
 // OP::run(args, b) does the work of block b of one grid.  k_one runs it over
 // one grid (block b = blockIdx.x).  k_group runs many independent grids in
-// one launch: entry bmap[blockIdx.x] = (segment << 20) | b names the grid
-// (segs[segment]) and its block; a segment whose system is marked finished
+// one launch: entry bmap[w] = (segment << 20) | b names the grid
+// (segs[segment]) and its block, w being the workgroup's position in XCD
+// order (xcd_block); a segment whose system is marked finished
 // (live[args.sys] == 0) is skipped.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -31,7 +32,8 @@ __global__ __launch_bounds__(256) void k_one_xcd(const typename OP::Args a) {
 template <class OP>
 __global__ __launch_bounds__(256) void k_group(const typename OP::Args* __restrict__ segs,
                                                const unsigned* __restrict__ bmap, const int* __restrict__ live) {
-  const unsigned e = bmap[blockIdx.x];
+  // consecutive map entries (neighbouring blocks of one grid) stay on one XCD
+  const unsigned e = bmap[xcd_block(blockIdx.x, gridDim.x)];
   const typename OP::Args& a = segs[e >> 20];
   if (live != nullptr && live[a.sys] == 0) return;
   OP::run(a, e & 0xFFFFFu);
