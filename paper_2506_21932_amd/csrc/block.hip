@@ -13,10 +13,13 @@
 // ticket, per-lane skew with the 3d27 hyperplane weights (4, 2, 1), an LDS
 // ring for neighbour values plus a halo of other tiles' columns fetched
 // device-coherently and checked against a signalling-NaN sentinel.  A node
-// carries 3 values and its row needs 13 coefficient blocks and the inverse
-// diagonal block (126 numbers, ~1 KB in FP64), so a tile is one wavefront of
-// 8 x 8 columns (no workgroup barrier needed) and the coefficients stream
-// through a ring of registers D blocks ahead.
+// carries 3 values and needs 13 coefficient blocks and the inverse diagonal
+// block per step (126 numbers, ~1 KB in FP64): more memory operations than a
+// single wavefront may have in flight (63).  So a tile of 8 x 8 columns has
+// three wavefronts, wavefront r computing scalar row r of every node: it
+// loads only that row of the blocks (42 numbers), accumulates the row's sum
+// in the oracle's order, the three sums meet in LDS, and each wavefront
+// applies its row of the inverse diagonal block.
 #include "smg_common.h"
 #include "smg_kernels.h"
 
@@ -122,13 +125,14 @@ void bwf_tiling(const Grid& g, WfTiling* t) {
   t->nsk = (long)t->ntx * t->nty * t->ns * BW_NL;
 }
 
-// Packs of the block sweep data: 13 triangle blocks then the inverse
-// diagonal block ("group" 13).  FP64: 5 packs per group (9 of 10 doubles);
-// FP32: 3 (9 of 12 floats); FP16: 2 packs per triangle block (9 halves, then
-// the 3 FP32 row scales at byte 20) and 3 FP32 packs for the inverse.
-__host__ __device__ constexpr int bwf_gpc(int ebytes) { return ebytes == 8 ? 5 : (ebytes == 4 ? 3 : 2); }
-__host__ __device__ constexpr int bwf_gpd(int ebytes) { return ebytes == 8 ? 5 : 3; }
-__host__ __device__ constexpr int bwf_npk(int ebytes) { return 13 * bwf_gpc(ebytes) + bwf_gpd(ebytes); }
+// Sweep data per node position and scalar row r (each of the tile's three
+// waves handles one row of every node): the row's 13 triangle blocks (3
+// entries each, canonical order) then row r of the inverse diagonal block.
+// FP64: 42 doubles = 21 packs; FP32: 42 floats in 11 packs; FP16: 39 halves
+// (bytes 0..77), the FP32 row scale (byte 80) and the FP32 inverse row
+// (bytes 84..95) = 6 packs.  Layout [tile][step][row][pack][lane].
+__host__ __device__ constexpr int bwf_npr(int ebytes) { return ebytes == 8 ? 21 : (ebytes == 4 ? 11 : 6); }
+__host__ __device__ constexpr int bwf_npk(int ebytes) { return 3 * bwf_npr(ebytes); }
 int bwf_pack_count(int ebytes) { return bwf_npk(ebytes); }
 
 __host__ __device__ constexpr int bw_col_dx(int c) { return c == 3 ? 0 : -1; }
@@ -190,50 +194,48 @@ __device__ inline void bw_st(V v, __amdgpu_buffer_rsrc_t r, unsigned off) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, CP);
 }
 
-// element e (0..8, row-major r*3 + c) of a coefficient group held in packs p[]
+// entry e (0..41) of a row's sweep data held in packs p[]: e < 39 are the
+// triangle coefficients (block e / 3, column e % 3), e = 39 + c the inverse
+// row's column c
 template <class E>
-__device__ inline typename WfVal<E>::V bw_coef(const bu32x4* p, int e);
+__device__ inline typename WfVal<E>::V bw_row(const bu32x4* p, int e);
 template <>
-__device__ inline double bw_coef<double>(const bu32x4* p, int e) {
+__device__ inline double bw_row<double>(const bu32x4* p, int e) {
   const bu32x4 w = p[e / 2];
   return e % 2 == 0 ? __builtin_bit_cast(double, bu32x2{w.x, w.y}) : __builtin_bit_cast(double, bu32x2{w.z, w.w});
 }
 template <>
-__device__ inline float bw_coef<float>(const bu32x4* p, int e) {
+__device__ inline float bw_row<float>(const bu32x4* p, int e) {
   return __uint_as_float(p[e / 4][e % 4]);
 }
 template <>
-__device__ inline float bw_coef<__half>(const bu32x4* p, int e) {
+__device__ inline float bw_row<__half>(const bu32x4* p, int e) {
+  if (e >= 39) return __uint_as_float(p[(84 + 4 * (e - 39)) / 16][((84 + 4 * (e - 39)) % 16) / 4]);
   const unsigned w = p[e / 8][(e % 8) / 2];
   const float h = __half2float(__ushort_as_half((unsigned short)(e % 2 == 0 ? (w & 0xffffu) : (w >> 16))));
-  const int r = e / 3;  // row scale at byte 20 + 4r of the group
-  const float s = __uint_as_float(p[(20 + 4 * r) / 16][((20 + 4 * r) % 16) / 4]);
-  return s * h;
-}
-// element e of the inverse diagonal block (FP64 for E = double, else FP32)
-template <class E>
-__device__ inline typename WfVal<E>::V bw_dinv(const bu32x4* p, int e) {
-  if constexpr (sizeof(E) == 8)
-    return bw_coef<double>(p, e);
-  else
-    return __uint_as_float(p[e / 4][e % 4]);
+  return __uint_as_float(p[5][0]) * h;  // row scale (byte 80) times the half
 }
 
+constexpr int BW_NT = 3 * BW_NL;  // threads: one wave per scalar row
+
 template <int DIR, class E>
-__global__ __launch_bounds__(BW_NL) void k_bwavefront(WfArgs<typename WfVal<E>::V> a) {
+__global__ __launch_bounds__(BW_NT) void k_bwavefront(WfArgs<typename WfVal<E>::V> a) {
   using V = typename WfVal<E>::V;
   using B = VBits<V>;
-  constexpr int GPC = bwf_gpc(sizeof(E)), GPD = bwf_gpd(sizeof(E)), NPK = bwf_npk(sizeof(E));
-  constexpr int GPM = GPC > GPD ? GPC : GPD;
-  constexpr int D = sizeof(E) == 8 ? 7 : 14;  // coefficient groups fetched ahead (divides 14)
+  constexpr int NPR = bwf_npr(sizeof(E)), NPK = bwf_npk(sizeof(E));
+  constexpr int P = sizeof(E) == 2 ? 4 : 2;  // steps of row data fetched ahead
+  static_assert(BW_UNROLL % P == 0 && BW_UNROLL % BW_PH == 0, "unroll");
   constexpr int RW = (BW_NL + BW_NH) * 3 + 1;
   constexpr unsigned PACKB = BW_NL * 16u;
   constexpr int VS = (int)sizeof(V);
   __shared__ V ring[BW_HIST * RW];
+  __shared__ V tx[3 * BW_NL];  // the three rows' sums of the current step
   __shared__ unsigned s_ticket;
 
   const int tid = threadIdx.x;
-  const int lx = tid / BW_TY, ly = tid % BW_TY;
+  const int r = tid / BW_NL;    // scalar row of this wave
+  const int lane = tid % BW_NL;  // column of the tile
+  const int lx = lane / BW_TY, ly = lane % BW_TY;
   const int sh = a.t.sh;
   const int skew = (BW_WX - sh * BW_WY) * lx + BW_WY * ly + BW_KB;
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
@@ -249,7 +251,8 @@ __global__ __launch_bounds__(BW_NL) void k_bwavefront(WfArgs<typename WfVal<E>::
     const bool in = qx >= 0 && qx < BW_TX && qy >= 0 && qy < BW_TY;
     nidx[c] = in ? qx * BW_TY + qy : BW_NL + bwf_halo_slot(qx, qy);
   }
-  const int hs = tid;
+  // halo loading: lane hs of wave r loads component r of halo slot hs
+  const int hs = lane;
   int hqx = 0, hqy = 0;
   bool hrole = false;
   if (hs < BW_NH) {
@@ -285,148 +288,97 @@ __global__ __launch_bounds__(BW_NL) void k_bwavefront(WfArgs<typename WfVal<E>::
     const int nsteps = (NS + BW_UNROLL - 1) / BW_UNROLL * BW_UNROLL;
 
     auto step_of = [&](int k) { return DIR > 0 ? k : NS - 1 - k; };
-    // byte offset of component 0 of the node of this lane at iteration k
+    // byte offset of component r of the node of this lane at iteration k
     auto node_off = [&](int k) {
       const int z = step_of(k) - skew;
-      return colv && z >= 0 && z < nz ? (vo + (unsigned)z) * 3u * (unsigned)VS : BW_OOB;
+      return colv && z >= 0 && z < nz ? ((vo + (unsigned)z) * 3u + (unsigned)r) * (unsigned)VS : BW_OOB;
     };
     auto halo_off = [&](int k) {
       const int s = step_of(k);
       const int hz = s - hskew;
-      return s >= 0 && s < NS && hcolv && hz >= 0 && hz < nz ? (hvo + (unsigned)hz) * 3u * (unsigned)VS : BW_OOB;
+      return s >= 0 && s < NS && hcolv && hz >= 0 && hz < nz ? ((hvo + (unsigned)hz) * 3u + (unsigned)r) * (unsigned)VS
+                                                             : BW_OOB;
     };
-    // coefficient group g of iteration k (sequence k*14 + g) into slot buf[(k*14 + g) % D]
-    bu32x4 buf[D][GPM];
-    auto grp_fetch = [&](int k, int g, int slot) {
+    // this row's sweep data of iteration k
+    bu32x4 cf[P][NPR];
+    auto row_fetch = [&](int k, int j) {
       const int s = step_of(k);
-      const unsigned so = s >= 0 && s < NS ? (unsigned)s * (NPK * PACKB) : BW_OOB;
-      const int np = g < 13 ? GPC : GPD;
+      const unsigned so = s >= 0 && s < NS ? ((unsigned)s * 3u + (unsigned)r) * (NPR * PACKB) : BW_OOB;
 #pragma unroll
-      for (int p = 0; p < np; ++p)
-        buf[slot][p] = __builtin_bit_cast(
-            bu32x4, __builtin_amdgcn_raw_buffer_load_b128(rp, tid * 16u, so + (unsigned)(g * GPC + p) * PACKB, 0));
+      for (int p = 0; p < NPR; ++p)
+        cf[j][p] =
+            __builtin_bit_cast(bu32x4, __builtin_amdgcn_raw_buffer_load_b128(rp, lane * 16u, so + p * PACKB, 0));
     };
-    V hv[BW_PH][3], hb[BW_PH][3];
-    auto h_fetch = [&](int k, int j) {
-      const unsigned off = node_off(k);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) hv[j][r] = bw_ld<V, 0>(rh, off == BW_OOB ? BW_OOB : off + r * VS);
-    };
-    auto halo_fetch = [&](int k, int j) {
-      const unsigned off = halo_off(k);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) hb[j][r] = bw_ld<V, BW_SC1>(rx, off == BW_OOB ? BW_OOB : off + r * VS);
-    };
+    V hv[BW_PH], hb[BW_PH];
+    auto h_fetch = [&](int k, int j) { hv[j] = bw_ld<V, 0>(rh, node_off(k)); };
+    auto halo_fetch = [&](int k, int j) { hb[j] = bw_ld<V, BW_SC1>(rx, halo_off(k)); };
     auto halo_put = [&](int k, int j) {
       const unsigned off = halo_off(k);
-      V v0 = hb[j][0], v1 = hb[j][1], v2 = hb[j][2];
-      if (off != BW_OOB &&
-          (B::bits(v0) == B::sent || B::bits(v1) == B::sent || B::bits(v2) == B::sent)) {
+      V v = hb[j];
+      if (off != BW_OOB && B::bits(v) == B::sent) {
         unsigned spins = 0;
         do {
           __builtin_amdgcn_s_sleep(1);
-          v0 = bw_ld<V, BW_SC1>(rx, off);
-          v1 = bw_ld<V, BW_SC1>(rx, off + VS);
-          v2 = bw_ld<V, BW_SC1>(rx, off + 2 * VS);
+          v = bw_ld<V, BW_SC1>(rx, off);
           // once any wait has timed out, stop waiting anywhere
-          if ((spins & 1023u) == 1023u &&
-              (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u))
+          if ((spins & 1023u) == 1023u && (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u))
             spins = BW_SPIN_LIMIT;
-        } while ((B::bits(v0) == B::sent || B::bits(v1) == B::sent || B::bits(v2) == B::sent) &&
-                 ++spins < BW_SPIN_LIMIT);
+        } while (B::bits(v) == B::sent && ++spins < BW_SPIN_LIMIT);
         if (spins >= BW_SPIN_LIMIT) atomicOr(a.err, 1u);
       }
-      if (hrole) {
-        V* rr = ring + (k % BW_HIST) * RW + (BW_NL + hs) * 3;
-        const bool ok = off != BW_OOB;
-        rr[0] = ok ? v0 : V(0);
-        rr[1] = ok ? v1 : V(0);
-        rr[2] = ok ? v2 : V(0);
-      }
+      if (hrole) ring[(k % BW_HIST) * RW + (BW_NL + hs) * 3 + r] = off != BW_OOB ? v : V(0);
     };
 
 #pragma unroll
-    for (int g = 0; g < D; ++g) grp_fetch(0, g, g);
+    for (int j = 0; j < P; ++j) row_fetch(j, j);
 #pragma unroll
     for (int j = 0; j < BW_PH; ++j) {
       h_fetch(j, j);
       halo_fetch(j, j);
     }
     halo_put(0, 0);
-    V own0 = V(0), own1 = V(0), own2 = V(0);
     __syncthreads();
 
     for (int k0 = 0; k0 < nsteps; k0 += BW_UNROLL) {
 #pragma unroll
       for (int j = 0; j < BW_UNROLL; ++j) {
         const int k = k0 + j;
-        const int jp = j % BW_PH;
-        V t0 = hv[jp][0], t1 = hv[jp][1], t2 = hv[jp][2];
+        const int jh = j % BW_PH, jc = j % P;
+        // this row's sum over the 13 triangle blocks, canonical order,
+        // columns in order: t = h_r - sum A[m][r][c] u_m[c]
+        V t = hv[jh];
 #pragma unroll
-        for (int g = 0; g < 14; ++g) {
-          const int slot = g % D;  // (k*14 + g) % D, 14 being a multiple of D
-          // the group D positions ahead in the sequence
-          const int gn = g + D;
-          if (g < 13) {
-            const int so = DIR > 0 ? g : 14 + g;
-            const int dx = pat_off(27, so, 0), dy = pat_off(27, so, 1), dz = pat_off(27, so, 2);
-            V u0, u1, u2;
-            if (dx == 0 && dy == 0) {
-              u0 = own0;
-              u1 = own1;
-              u2 = own2;
-            } else {
-              const int c = bw_col_of(DIR * dx, DIR * dy);
-              const int back = DIR * (BW_WX * dx + BW_WY * dy + dz);  // in [-KB, -1]
-              const V* rr = ring + ((k + back + BW_HIST) % BW_HIST) * RW + nidx[c] * 3;
-              u0 = rr[0];
-              u1 = rr[1];
-              u2 = rr[2];
-            }
-            t0 = fma(-bw_coef<E>(buf[slot], 0), u0, t0);
-            t0 = fma(-bw_coef<E>(buf[slot], 1), u1, t0);
-            t0 = fma(-bw_coef<E>(buf[slot], 2), u2, t0);
-            t1 = fma(-bw_coef<E>(buf[slot], 3), u0, t1);
-            t1 = fma(-bw_coef<E>(buf[slot], 4), u1, t1);
-            t1 = fma(-bw_coef<E>(buf[slot], 5), u2, t1);
-            t2 = fma(-bw_coef<E>(buf[slot], 6), u0, t2);
-            t2 = fma(-bw_coef<E>(buf[slot], 7), u1, t2);
-            t2 = fma(-bw_coef<E>(buf[slot], 8), u2, t2);
+        for (int m = 0; m < 13; ++m) {
+          const int so = DIR > 0 ? m : 14 + m;
+          const int dx = pat_off(27, so, 0), dy = pat_off(27, so, 1), dz = pat_off(27, so, 2);
+          const V* rr;
+          if (dx == 0 && dy == 0) {
+            rr = ring + ((k - 1 + BW_HIST) % BW_HIST) * RW + lane * 3;  // this column, previous step
           } else {
-            const V x0 = fma(bw_dinv<E>(buf[slot], 2), t2, fma(bw_dinv<E>(buf[slot], 1), t1, bw_dinv<E>(buf[slot], 0) * t0));
-            const V x1 = fma(bw_dinv<E>(buf[slot], 5), t2, fma(bw_dinv<E>(buf[slot], 4), t1, bw_dinv<E>(buf[slot], 3) * t0));
-            const V x2 = fma(bw_dinv<E>(buf[slot], 8), t2, fma(bw_dinv<E>(buf[slot], 7), t1, bw_dinv<E>(buf[slot], 6) * t0));
-            t0 = x0;
-            t1 = x1;
-            t2 = x2;
+            const int c = bw_col_of(DIR * dx, DIR * dy);
+            const int back = DIR * (BW_WX * dx + BW_WY * dy + dz);  // in [-KB, -1]
+            rr = ring + ((k + back + BW_HIST) % BW_HIST) * RW + nidx[c] * 3;
           }
-          grp_fetch(gn < 14 ? k : k + 1, gn % 14, slot);
+          const V u0 = rr[0], u1 = rr[1], u2 = rr[2];
+          t = fma(-bw_row<E>(cf[jc], 3 * m + 0), u0, t);
+          t = fma(-bw_row<E>(cf[jc], 3 * m + 1), u1, t);
+          t = fma(-bw_row<E>(cf[jc], 3 * m + 2), u2, t);
         }
+        tx[r * BW_NL + lane] = t;
+        __syncthreads();
+        const V t0 = tx[lane], t1 = tx[BW_NL + lane], t2 = tx[2 * BW_NL + lane];
+        const V xv = fma(bw_row<E>(cf[jc], 41), t2, fma(bw_row<E>(cf[jc], 40), t1, bw_row<E>(cf[jc], 39) * t0));
         const unsigned off = node_off(k);
         const bool act = off != BW_OOB;
-        own0 = act ? t0 : V(0);
-        own1 = act ? t1 : V(0);
-        own2 = act ? t2 : V(0);
-        V* rw = ring + (k % BW_HIST) * RW + tid * 3;
-        rw[0] = own0;
-        rw[1] = own1;
-        rw[2] = own2;
-        const unsigned oc = exported ? off : BW_OOB, op = exported ? BW_OOB : off;
-        bw_st<BW_SC1>(t0, rx, oc == BW_OOB ? BW_OOB : oc);
-        bw_st<BW_SC1>(t1, rx, oc == BW_OOB ? BW_OOB : oc + VS);
-        bw_st<BW_SC1>(t2, rx, oc == BW_OOB ? BW_OOB : oc + 2 * VS);
-        bw_st<0>(t0, rx, op == BW_OOB ? BW_OOB : op);
-        bw_st<0>(t1, rx, op == BW_OOB ? BW_OOB : op + VS);
-        bw_st<0>(t2, rx, op == BW_OOB ? BW_OOB : op + 2 * VS);
-        if (exp_next && act) {
-          bw_st<0>(B::val(B::sent), rn, off);
-          bw_st<0>(B::val(B::sent), rn, off + VS);
-          bw_st<0>(B::val(B::sent), rn, off + 2 * VS);
-        }
+        ring[(k % BW_HIST) * RW + lane * 3 + r] = act ? xv : V(0);
+        bw_st<BW_SC1>(xv, rx, exported ? off : BW_OOB);
+        bw_st<0>(xv, rx, exported ? BW_OOB : off);
+        if (exp_next) bw_st<0>(B::val(B::sent), rn, off);
         halo_put(k + 1, (j + 1) % BW_PH);
-        halo_fetch(k + BW_PH, jp);
-        h_fetch(k + BW_PH, jp);
-        __syncthreads();  // one wavefront: orders the LDS ring accesses of the lanes
+        halo_fetch(k + BW_PH, jh);
+        h_fetch(k + BW_PH, jh);
+        row_fetch(k + P, jc);
+        __syncthreads();
       }
     }
   }
@@ -444,9 +396,9 @@ hipError_t launch_bwavefront(int dir, const WfArgs<typename WfVal<E>::V>& a, hip
   const unsigned ntiles = (unsigned)(a.t.ntx * a.t.nty);
   const unsigned grid = ntiles < 2048u ? ntiles : 2048u;
   if (dir > 0)
-    hipLaunchKernelGGL((k_bwavefront<1, E>), dim3(grid), dim3(BW_NL), 0, st, a);
+    hipLaunchKernelGGL((k_bwavefront<1, E>), dim3(grid), dim3(BW_NT), 0, st, a);
   else
-    hipLaunchKernelGGL((k_bwavefront<-1, E>), dim3(grid), dim3(BW_NL), 0, st, a);
+    hipLaunchKernelGGL((k_bwavefront<-1, E>), dim3(grid), dim3(BW_NT), 0, st, a);
   return hipGetLastError();
 }
 template hipError_t launch_bwavefront<double>(int, const WfArgs<double>&, hipStream_t);
@@ -467,72 +419,66 @@ __device__ inline long bwf_point(const Grid& g, const WfTiling& tl, long q) {
   return v ? ((long)x * g.ny + y) * g.nz + z : -1;
 }
 
-// FP64 / FP32: group g < 13 holds block (dir > 0 ? g : 14 + g) row-major,
-// group 13 the inverse diagonal block; padding zero.
+// FP64 / FP32: row r of position q: entries 3m + c = block (dir > 0 ? m :
+// 14 + m) entry (r, c), m < 13; entries 39 + c = inverse diagonal entry
+// (r, c); padding zero.
 template <class E>
 __global__ __launch_bounds__(256) void k_bwf_pack(Grid g, WfTiling tl, int dir, const double* __restrict__ A,
                                                   const double* __restrict__ Dinv, E* __restrict__ out) {
-  constexpr int K = 16 / (int)sizeof(E), GPC = bwf_gpc(sizeof(E)), NPK = bwf_npk(sizeof(E));
+  constexpr int K = 16 / (int)sizeof(E), NPR = bwf_npr(sizeof(E));
   const long q = (long)blockIdx.x * 256 + threadIdx.x;
   if (q >= tl.nsk) return;
   const long i = bwf_point(g, tl, q);
   const long N = g.N();
-  const long row = q / BW_NL;
+  const long pos = q / BW_NL;
   const int lane = (int)(q % BW_NL);
-  for (int grp = 0; grp < 14; ++grp) {
-    const int np = grp < 13 ? GPC : bwf_gpd(sizeof(E));
-    for (int p = 0; p < np; ++p) {
-      E* o = out + ((row * NPK + grp * GPC + p) * BW_NL + lane) * K;
+  for (int r = 0; r < 3; ++r)
+    for (int p = 0; p < NPR; ++p) {
+      E* o = out + (((pos * 3 + r) * NPR + p) * BW_NL + lane) * K;
       for (int e = 0; e < K; ++e) {
         const int v = p * K + e;
         double x = 0.0;
-        if (i >= 0 && v < 9)
-          x = grp < 13 ? A[((long)(dir > 0 ? grp : 14 + grp) * 9 + v) * N + i] : Dinv[(long)v * N + i];
+        if (i >= 0 && v < 39)
+          x = A[((long)(dir > 0 ? v / 3 : 14 + v / 3) * 9 + r * 3 + v % 3) * N + i];
+        else if (i >= 0 && v < 42)
+          x = Dinv[(long)(r * 3 + v - 39) * N + i];
         o[e] = (E)x;
       }
     }
-  }
 }
 
-// FP16: per triangle block two packs: 9 halves (bytes 0..17) and the 3 FP32
-// row scales (bytes 20..31); then 3 FP32 packs with the inverse diagonal block.
+// FP16: row r of position q: the 39 halves of the row's triangle entries
+// (bytes 0..77), the FP32 row scale (bytes 80..83), the FP32 inverse row
+// (bytes 84..95).
 __global__ __launch_bounds__(256) void k_bwf_pack_h(Grid g, WfTiling tl, int dir, const __half* __restrict__ a16,
                                                     const float* __restrict__ sc, const float* __restrict__ rd,
                                                     unsigned char* __restrict__ out) {
-  constexpr int NPK = bwf_npk(2);
+  constexpr int NPR = bwf_npr(2);
   const long q = (long)blockIdx.x * 256 + threadIdx.x;
   if (q >= tl.nsk) return;
   const long i = bwf_point(g, tl, q);
   const long N = g.N();
-  const long row = q / BW_NL;
+  const long pos = q / BW_NL;
   const int lane = (int)(q % BW_NL);
-  auto pack = [&](int p) { return out + ((row * NPK + p) * BW_NL + lane) * 16; };
-  for (int grp = 0; grp < 13; ++grp) {
-    unsigned char* o0 = pack(2 * grp);
-    unsigned char* o1 = pack(2 * grp + 1);
-    unsigned char bytes[32];
-    for (int b = 0; b < 32; ++b) bytes[b] = 0;
-    for (int v = 0; v < 9; ++v) {
-      const __half h = i >= 0 ? a16[((long)(dir > 0 ? grp : 14 + grp) * 9 + v) * N + i] : __float2half_rn(0.0f);
+  for (int r = 0; r < 3; ++r) {
+    unsigned char bytes[16 * NPR];
+    for (int b = 0; b < 16 * NPR; ++b) bytes[b] = 0;
+    for (int v = 0; v < 39; ++v) {
+      const __half h = i >= 0 ? a16[((long)(dir > 0 ? v / 3 : 14 + v / 3) * 9 + r * 3 + v % 3) * N + i]
+                              : __float2half_rn(0.0f);
       const unsigned short u = __half_as_ushort(h);
       bytes[2 * v] = (unsigned char)(u & 0xff);
       bytes[2 * v + 1] = (unsigned char)(u >> 8);
     }
-    for (int r = 0; r < 3; ++r) {
-      const unsigned u = __float_as_uint(i >= 0 ? sc[(long)r * N + i] : 0.0f);
-      for (int b = 0; b < 4; ++b) bytes[20 + 4 * r + b] = (unsigned char)(u >> (8 * b));
+    const unsigned us = __float_as_uint(i >= 0 ? sc[(long)r * N + i] : 0.0f);
+    for (int b = 0; b < 4; ++b) bytes[80 + b] = (unsigned char)(us >> (8 * b));
+    for (int c = 0; c < 3; ++c) {
+      const unsigned u = __float_as_uint(i >= 0 ? rd[(long)(r * 3 + c) * N + i] : 0.0f);
+      for (int b = 0; b < 4; ++b) bytes[84 + 4 * c + b] = (unsigned char)(u >> (8 * b));
     }
-    for (int b = 0; b < 16; ++b) {
-      o0[b] = bytes[b];
-      o1[b] = bytes[16 + b];
-    }
-  }
-  for (int p = 0; p < 3; ++p) {
-    unsigned char* o = pack(26 + p);
-    for (int e = 0; e < 4; ++e) {
-      const int v = p * 4 + e;
-      const unsigned u = __float_as_uint(i >= 0 && v < 9 ? rd[(long)v * N + i] : 0.0f);
-      for (int b = 0; b < 4; ++b) o[4 * e + b] = (unsigned char)(u >> (8 * b));
+    for (int p = 0; p < NPR; ++p) {
+      unsigned char* o = out + (((pos * 3 + r) * NPR + p) * BW_NL + lane) * 16;
+      for (int b = 0; b < 16; ++b) o[b] = bytes[16 * p + b];
     }
   }
 }

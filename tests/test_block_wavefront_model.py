@@ -120,7 +120,6 @@ def run_bsweep(g, direction, A, Dinv, h, x_init, nxt_dir, nxt):
         ring = np.full(HIST * RW, np.nan)
         ring_pt = np.full(HIST * RW, -2, np.int64)
         ring_it = np.full(HIST * RW, -10 ** 9, np.int64)
-        own = np.zeros((NL, 3))
 
         def step_of(k):
             return k if direction > 0 else NS - 1 - k
@@ -163,18 +162,20 @@ def run_bsweep(g, direction, A, Dinv, h, x_init, nxt_dir, nxt):
                     inb = 0 <= xn < nx and 0 <= yn < ny and 0 <= zn < nz
                     gi = (xn * ny + yn) * nz + zn
                     if dx == 0 and dy == 0:
-                        u = own[l]
+                        # the same column one step earlier (this lane's own ring slot)
+                        base = ((k - 1) % HIST) * RW + l * 3
+                        assert ring_it[base] == k - 1, "ring row not written at that step"
                     else:
                         c = col_of(direction * dx, direction * dy)
                         back = direction * (WX * dx + WY * dy + dz)
                         assert -KB <= back <= -1
                         base = ((k + back) % HIST) * RW + nidx[c][l] * 3
                         assert ring_it[base] == k + back, "ring row not written at that step"
-                        u = ring[base:base + 3]
-                        if inb:
-                            assert ring_pt[base] == gi, "ring slot holds another node"
-                        else:
-                            assert (u == 0.0).all()
+                    u = ring[base:base + 3]
+                    if inb:
+                        assert ring_pt[base] == gi, "ring slot holds another node"
+                    else:
+                        assert (u == 0.0).all()
                     for r in range(3):
                         for cc in range(3):
                             tv[r] = _fma(-A[(so * 9 + r * 3 + cc), i], u[cc], tv[r])
@@ -186,7 +187,6 @@ def run_bsweep(g, direction, A, Dinv, h, x_init, nxt_dir, nxt):
                 x[i * 3:i * 3 + 3] = xr[l]
                 if exp_next[l]:
                     pref[i * 3:i * 3 + 3] = True
-            own = xr
             for l in range(NL):
                 base = (k % HIST) * RW + l * 3
                 ring[base:base + 3] = xr[l]
