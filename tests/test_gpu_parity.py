@@ -401,3 +401,39 @@ def test_graph_replay_identical(kind):
         out.append((N(x), res["iters"]))
     for xg, it in out[1:]:
         assert np.array_equal(xg, out[0][0]) and it == out[0][1]
+
+
+# level 0 small enough for the one-workgroup hyperplane sweep (ragged shapes,
+# every pattern, every V-cycle precision); each has a coarser level
+HP_CASES = [((7, 11, 5), 27, "fp64"), ((9, 4, 13), 19, "fp64"), ((16, 16, 16), 7, "fp64"),
+            ((6, 13, 10), 27, "fp32"), ((12, 5, 9), 7, "fp16"), ((10, 9, 8), 19, "fp16")]
+
+
+@pytest.mark.parametrize("shape,pat,prec", HP_CASES, ids=lambda v: str(v))
+def test_small_level_sweeps_bitexact(shape, pat, prec):
+    A = workloads.random_sgdia(shape, pat, seed=19)
+    H = oracle.Hierarchy(shape, pat, A, prec=prec)
+    mg = smg.StructMG(T(A), shape, pattern=pat, prec=prec, device=DEV)
+    assert mg.nlev == H.nlev and H.nlev >= 2
+    inf = H.level_info(0)
+    dims, cm = inf["dims"], inf["cmask"]
+    off = workloads.offsets(pat)
+    if prec == "fp64":
+        Al, rd, dt, npt = H.level_data(0, 0), H.level_data(0, 1).ravel(), torch.float64, np.float64
+    else:
+        Al, rd, dt, npt = H.level_data(0, 5), H.level_data(0, 6).ravel(), torch.float32, np.float32
+    g = workloads.rng(29)
+    for rep in range(2):
+        f = g.uniform(-1, 1, size=dims).astype(npt)
+        u = g.uniform(-1, 1, size=dims).astype(npt)
+        ec = g.uniform(-1, 1, size=oracle.coarse_dims(dims, cm)).astype(npt)
+        ug = N(mg.op_presmooth(0, T(f, dt), torch.empty(f.size, dtype=dt, device=DEV)))
+        assert np.array_equal(ug, oracle.gs_sweep(off, Al, rd, f, np.zeros(dims, npt), 1, 1).ravel())
+        uo = N(mg.op_postsmooth(0, T(f, dt), T(u, dt), T(ec, dt), torch.empty(f.size, dtype=dt, device=DEV)))
+        ref = oracle.gs_sweep(off, Al, rd, f, oracle.prolong_add(u, ec, cm), -1, 0)
+        assert np.array_equal(uo, ref.ravel())
+    # and the whole solve
+    b = workloads.rng(30).uniform(-1, 1, size=dims)
+    x = torch.zeros(b.size, dtype=torch.float64, device=DEV)
+    res = mg.solve(T(b.ravel()), x, rtol=1e-9, maxit=200)
+    assert res["status"] == 0 and res["rel_resid_true"] < 1e-9
