@@ -169,6 +169,12 @@ hipError_t launch_prolong_post(int pat, const Grid& g, int cmask, const M& m, co
                                const typename M::V* u, const typename M::V* ec, typename M::V* h,
                                typename M::V* uold_out, bool full, hipStream_t st);
 
+// h = f - sum_{lower s} a_s u[nbr] (canonical order, fma): the input of a
+// backward Gauss-Seidel sweep from the old values u
+template <class M>
+hipError_t launch_lower(int pat, const Grid& g, const M& m, const typename M::V* f, const typename M::V* u,
+                        typename M::V* h, hipStream_t st);
+
 // plain restriction / prolongation (kernel-level entry points)
 template <class V>
 hipError_t launch_restrict(const Grid& g, int cmask, int bs, const V* rf, V* rc, hipStream_t st);

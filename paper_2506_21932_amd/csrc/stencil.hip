@@ -89,6 +89,47 @@ hipError_t launch_spmv_group(int pat, bool res, const SpmvArgs<M>* segs, const u
   return hipErrorInvalidValue;
 }
 
+// ------------------------------------------ lower-triangle residual
+// h = f - sum over the lower offsets s (canonical order) of a_s u[nbr]: the
+// old-value terms of a backward Gauss-Seidel row (t = f; t = fma(-a, u, t)).
+template <int PAT, class M>
+struct LowerOp {
+  using Args = SpmvArgs<M>;  // x = u, b = f, y = h
+  __device__ static void run(const Args& a, unsigned bid) {
+    using V = typename M::V;
+    const Grid g = a.g;
+    const M m = a.m;
+    const unsigned i = bid * 256u + threadIdx.x;
+    if (i >= (unsigned)g.N()) return;
+    int X, Y, Z;
+    unflat(i, g.ny, g.nz, X, Y, Z);
+    const long nyz = (long)g.ny * g.nz;
+    V t = a.b[i];
+#pragma unroll
+    for (int s = 0; s < PAT / 2; ++s) {
+      const int dx = pat_off(PAT, s, 0), dy = pat_off(PAT, s, 1), dz = pat_off(PAT, s, 2);
+      if (in_grid(g, X + dx, Y + dy, Z + dz)) t = fma(-m(s, i), a.x[(long)i + dx * nyz + dy * g.nz + dz], t);
+    }
+    a.y[i] = t;
+  }
+};
+
+template <class M>
+hipError_t launch_lower(int pat, const Grid& g, const M& m, const typename M::V* f, const typename M::V* u,
+                        typename M::V* h, hipStream_t st) {
+  const SpmvArgs<M> a{g, m, u, f, h, 0};
+  const dim3 grid(spmv_blocks(g)), blk(256);
+  if (pat == 7)
+    hipLaunchKernelGGL((k_one<LowerOp<7, M>>), grid, blk, 0, st, a);
+  else if (pat == 19)
+    hipLaunchKernelGGL((k_one<LowerOp<19, M>>), grid, blk, 0, st, a);
+  else if (pat == 27)
+    hipLaunchKernelGGL((k_one<LowerOp<27, M>>), grid, blk, 0, st, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 // ------------------------------------------------ residual + restriction
 // One workgroup per coarse block of RB_X x RB_Y x RB_Z coarse points.
 // Phase 1 computes the fine residuals of the block's footprint into LDS;
@@ -505,6 +546,10 @@ SMG_GINST(MatD)
 SMG_GINST(MatF)
 SMG_GINST(MatH)
 #undef SMG_GINST
+template hipError_t launch_lower<MatD>(int, const Grid&, const MatD&, const double*, const double*, double*,
+                                       hipStream_t);
+template hipError_t launch_lower<MatF>(int, const Grid&, const MatF&, const float*, const float*, float*, hipStream_t);
+template hipError_t launch_lower<MatH>(int, const Grid&, const MatH&, const float*, const float*, float*, hipStream_t);
 template hipError_t launch_restrict<double>(const Grid&, int, int, const double*, double*, hipStream_t);
 template hipError_t launch_restrict<float>(const Grid&, int, int, const float*, float*, hipStream_t);
 template hipError_t launch_prolong_add<double>(const Grid&, int, int, const double*, double*, hipStream_t);

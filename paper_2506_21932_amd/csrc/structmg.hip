@@ -300,6 +300,14 @@ hipError_t bvcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* 
   return hipSuccess;
 }
 
+// Scalar levels of at least this many points run the residual + restriction
+// and the prolongation + lower-triangle terms as two plain passes each (more
+// workgroups, no halo recomputation); smaller levels use the fused one-launch
+// kernels, whose single launch costs less there.  Both forms give identical
+// bits.
+constexpr long SPLIT_MIN_POINTS = 1L << 17;
+static bool split_rp(const Level& v) { return v.N >= SPLIT_MIN_POINTS; }
+
 // One V-cycle on internal or caller vectors: f0 = level-0 right-hand side,
 // z0 = level-0 output (its positions read across tiles are given sentinels by
 // the pre-smoothing sweep).
@@ -330,7 +338,13 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
     if (e != hipSuccess) return e;
     {
       Timed t(H, l, 2, st);
-      e = launch_resid_restrict(v.S, v.g, v.cmask, A, F(l), (const V*)v.ua, (V*)H->lev[l + 1].f, st);
+      if (split_rp(v)) {
+        // residual into the level's h (free until the upward leg), then R
+        e = launch_spmv(v.S, v.g, A, (const V*)v.ua, F(l), (V*)v.h, true, st);
+        if (e == hipSuccess) e = launch_restrict<V>(v.g, v.cmask, 1, (const V*)v.h, (V*)H->lev[l + 1].f, st);
+      } else {
+        e = launch_resid_restrict(v.S, v.g, v.cmask, A, F(l), (const V*)v.ua, (V*)H->lev[l + 1].f, st);
+      }
     }
     if (e != hipSuccess) return e;
   }
@@ -345,8 +359,15 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
     if (!ilu) {
       {
         Timed t(H, l, 4, st);
-        e = launch_prolong_post(v.S, v.g, v.cmask, A, F(l), (const V*)v.ua, (const V*)UB(l + 1), (V*)v.h,
-                                (V*)nullptr, false, st);
+        if (split_rp(v)) {
+          // u_old = u + P e_c in place (u_a is refilled by the sweep below),
+          // then the backward sweep's old-value terms
+          e = launch_prolong_add<V>(v.g, v.cmask, 1, (const V*)UB(l + 1), (V*)v.ua, st);
+          if (e == hipSuccess) e = launch_lower(v.S, v.g, A, F(l), (const V*)v.ua, (V*)v.h, st);
+        } else {
+          e = launch_prolong_post(v.S, v.g, v.cmask, A, F(l), (const V*)v.ua, (const V*)UB(l + 1), (V*)v.h,
+                                  (V*)nullptr, false, st);
+        }
       }
       if (e != hipSuccess) return e;
       Timed t(H, l, 5, st);
@@ -942,8 +963,18 @@ static hipError_t op_postsmooth_t(smg_handle_s* H, const Level& v, const void* f
     return e;
   }
   if (H->cfg.smoother == SMG_SMOOTH_GS) {
-    e = launch_prolong_post(v.S, v.g, v.cmask, A, (const V*)f, (const V*)uin, (const V*)ec, (V*)v.h, (V*)nullptr,
-                            false, st);
+    // the V-cycle's kernels for this level: h = f - lower(A) u_old with
+    // u_old = u_in + P ec (large levels: formed in u_a, whose sentinels are
+    // restored after)
+    if (split_rp(v)) {
+      e = hipMemcpyAsync(v.ua, uin, sizeof(V) * nv, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess && ec != nullptr) e = launch_prolong_add<V>(v.g, v.cmask, 1, (const V*)ec, (V*)v.ua, st);
+      if (e == hipSuccess) e = launch_lower(v.S, v.g, A, (const V*)f, (const V*)v.ua, (V*)v.h, st);
+      if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.ua, nv, sent, st);
+    } else {
+      e = launch_prolong_post(v.S, v.g, v.cmask, A, (const V*)f, (const V*)uin, (const V*)ec, (V*)v.h,
+                              (V*)nullptr, false, st);
+    }
     if (e == hipSuccess) e = launch_fill_bits<V>((V*)uout, nv, sent, st);
     if (e == hipSuccess)
       e = sweep<typename PT::E, V>(H, v, -1, false, (const V*)v.h, (V*)uout, nullptr, 0, nullptr, nullptr, st);
@@ -1012,7 +1043,10 @@ struct OpRR {
       if (e == hipSuccess) e = launch_restrict<V>(v.g, v.cmask, 3, (const V*)v.h, (V*)rc, st);
       return e;
     }
-    return launch_resid_restrict(v.S, v.g, v.cmask, PT::A(v), (const V*)f, (const V*)u, (V*)rc, st);
+    if (!split_rp(v)) return launch_resid_restrict(v.S, v.g, v.cmask, PT::A(v), (const V*)f, (const V*)u, (V*)rc, st);
+    hipError_t e = launch_spmv(v.S, v.g, PT::A(v), (const V*)u, (const V*)f, (V*)v.h, true, st);
+    if (e == hipSuccess) e = launch_restrict<V>(v.g, v.cmask, 1, (const V*)v.h, (V*)rc, st);
+    return e;
   }
 };
 

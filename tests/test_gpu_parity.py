@@ -39,6 +39,10 @@ CASES = [
     ((24, 21, 12), 27, "full", 0),
     ((40, 36, 6), 19, "semi_xy", 0),
     ((37, 19, 23), 7, "full", 2),
+    # finest levels above the size where residual + restriction and
+    # prolongation + lower terms run as separate passes
+    ((66, 50, 41), 19, "full", 0),
+    ((80, 52, 36), 7, "full", 1),
 ]
 
 
@@ -206,9 +210,9 @@ def test_gmres_ilu_nonsymmetric():
     assert np.abs(N(x) - xr.ravel()).max() <= 1e-6 * np.abs(xr).max()
 
 
+@pytest.mark.parametrize("case", [CASES[0], CASES[6]], ids=_ids)
 @pytest.mark.parametrize("prec", ["fp32", "fp16"])
-def test_reduced_precision_bitexact(prec):
-    case = CASES[0]
+def test_reduced_precision_bitexact(prec, case):
     A, H, mg = _pair(case, prec=prec)
     g = workloads.rng(17)
     for l in range(H.nlev - 1):
