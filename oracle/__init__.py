@@ -62,6 +62,7 @@ def _declare(L):
         getattr(L, "orc_bspmv" + sfx).argtypes = [_i, _i, _i, _i, _ip, p, p, p]
         getattr(L, "orc_bresidual" + sfx).argtypes = [_i, _i, _i, _i, _ip, p, p, p, p]
         getattr(L, "orc_bgs_sweep" + sfx).argtypes = [_i, _i, _i, _i, _ip, p, p, p, p, _i, _i]
+        getattr(L, "orc_lgs_sweep" + sfx).argtypes = [_i, _i, _i, _i, _ip, p, p, p, p, p, _i, _i, p]
     L.orc_pattern.argtypes = [_i, _ip]
     L.orc_pattern.restype = _i
     L.orc_rap.argtypes = [_i, _i, _i, _i, _ip, _i, _dp, _i, _dp]
@@ -69,6 +70,8 @@ def _declare(L):
     L.orc_rap_chains.restype = _i
     L.orc_ilu0.argtypes = [_i, _i, _i, _i, _ip, _dp, _dp, _dp, _dp]
     L.orc_ilu0.restype = _i
+    L.orc_tri_factor.argtypes = [_i, _i, _i, _i, _ip, _dp, _dp, _dp]
+    L.orc_tri_factor.restype = _i
     L.orc_lu_factor.argtypes = [_i, _dp, _ip]
     L.orc_lu_factor.restype = _i
     L.orc_lu_solve.argtypes = [_i, _dp, _ip, _dp]
@@ -138,6 +141,29 @@ def gs_sweep(off, A, rd, b, u, direction, zero_guess):
     getattr(lib(), "orc_gs_sweep" + _sfx(b))(nx, ny, nz, off.shape[0], off.ravel(), _c(A).ravel(), _c(rd).ravel(),
                                             _c(b).ravel(), u.ravel(), int(direction), int(zero_guess))
     return u
+
+
+def lgs_sweep(off, A, rden, cp, b, u, direction, zero_guess):
+    """In-place line GS sweep over z-columns; returns u."""
+    off = _c(off, np.int32)
+    nx, ny, nz = _dims(b.shape)
+    u = _c(u).copy()
+    d = np.zeros(nz, b.dtype)
+    getattr(lib(), "orc_lgs_sweep" + _sfx(b))(nx, ny, nz, off.shape[0], off.ravel(), _c(A).ravel(),
+                                             _c(rden).ravel(), _c(cp).ravel(), _c(b).ravel(), u.ravel(),
+                                             int(direction), int(zero_guess), d)
+    return u
+
+
+def tri_factor(off, A, shape):
+    """Thomas factors (rden, cp) of the z-column tridiagonal blocks of A."""
+    off = _c(off, np.int32)
+    N = int(np.prod(shape))
+    rden = np.zeros(N)
+    cp = np.zeros(N)
+    if lib().orc_tri_factor(*_dims(shape), off.shape[0], off.ravel(), _c(A, np.float64).ravel(), rden, cp):
+        raise ValueError("zero pivot")
+    return rden, cp
 
 
 def tri_solve(off, F, rU, r, upper):
@@ -256,6 +282,7 @@ def f16_bits_to_f32(h):
 
 
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2}
+SMOOTHER = {"gs": 0, "ilu0": 1, "lgs": 2}
 
 
 class Hierarchy:
@@ -267,7 +294,7 @@ class Hierarchy:
         self.bs = int(block)
         self._A0 = _c(A0, np.float64)
         h = lib().orc_mg_create(*self.shape, int(pattern_pts), self.bs, self._A0.ravel(),
-                                1 if smoother == "ilu0" else 0, 1 if coarsen == "semi_xy" else 0, int(semi_levels),
+                                SMOOTHER[smoother], 1 if coarsen == "semi_xy" else 0, int(semi_levels),
                                 PREC[prec], int(max_coarse))
         if not h:
             raise ValueError("oracle hierarchy setup failed")
@@ -295,8 +322,8 @@ class Hierarchy:
         be = self.bs * self.bs
         S = inf["S"]
         sizes = {0: (S * be, N), 1: ((9 if self.bs == 3 else 1), N), 2: (S, N), 3: (S, N), 4: (1, N),
-                 5: (S * be, N), 6: ((9 if self.bs == 3 else 1), N)}
-        dt = np.float32 if what >= 5 else np.float64
+                 5: (S * be, N), 6: ((9 if self.bs == 3 else 1), N), 7: (1, N), 8: (1, N)}
+        dt = np.float32 if what in (5, 6) else np.float64
         out = np.zeros(sizes[what], dt)
         lib().orc_mg_level_data(self.h, l, what, out.ctypes.data_as(C.c_void_p))
         return out

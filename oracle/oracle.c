@@ -362,15 +362,48 @@ int orc_block_dinv(int nx, int ny, int nz, int S, const int* off, const double* 
   return 0;
 }
 
+/* ---- Thomas factorisation of the z-columns (Sec. 4.4, LGS paragraph) ---
+ * For every column (x, y) the tridiagonal block of A on that column: a_z =
+ * coupling to z-1, b_z = centre, c_z = coupling to z+1 (zero at the column
+ * ends).  Pivots of the Thomas algorithm:
+ *   p_0 = b_0,  p_z = fma(-a_z, cp_{z-1}, b_z);  rden_z = 1/p_z;
+ *   cp_z = c_z * rden_z.
+ * Returns 0, or -1 on a zero pivot. */
+int orc_tri_factor(int nx, int ny, int nz, int S, const int* off, const double* A, double* rden, double* cp) {
+  long N = (long)nx * ny * nz;
+  int slo = -1, sc = -1, sup = -1;
+  for (int s = 0; s < S; ++s)
+    if (off[3 * s] == 0 && off[3 * s + 1] == 0) {
+      if (off[3 * s + 2] == -1) slo = s;
+      if (off[3 * s + 2] == 0) sc = s;
+      if (off[3 * s + 2] == 1) sup = s;
+    }
+  for (long col = 0; col < (long)nx * ny; ++col) {
+    long i0 = col * nz;
+    for (int Z = 0; Z < nz; ++Z) {
+      long i = i0 + Z;
+      double az = Z > 0 ? A[slo * N + i] : 0.0;
+      double cz = Z < nz - 1 ? A[sup * N + i] : 0.0;
+      double p = Z == 0 ? A[sc * N + i] : fma(-az, cp[i - 1], A[sc * N + i]);
+      if (p == 0.0) return -1;
+      rden[i] = 1.0 / p;
+      cp[i] = cz * rden[i];
+    }
+  }
+  return 0;
+}
+
 /* ---- multigrid hierarchy ---------------------------------------------- */
 typedef struct {
   int nx, ny, nz, S, cmask;
   long N;
   int off[81];
   double *A, *rd, *L, *U, *rU;           /* FP64 level data */
+  double *tr, *tc;                       /* Thomas factors rden, cp (line GS) */
   float *A32, *rd32, *L32, *U32, *rU32;  /* truncated level data */
-  double *f, *u, *r, *w;                 /* FP64 work vectors */
-  float *f32, *u32, *r32, *w32;          /* reduced-precision work vectors */
+  float *tr32, *tc32;
+  double *f, *u, *r, *w, *d;             /* FP64 work vectors (d: one column) */
+  float *f32, *u32, *r32, *w32, *d32;    /* reduced-precision work vectors */
 } olev;
 
 typedef struct {
@@ -434,12 +467,14 @@ void orc_mg_destroy(omg* mg);
 /*
  * Builds the hierarchy from the finest matrix only (Sec. 4.2.2 input).
  * pattern: 7/19/27 (level 0); coarse levels are 27-point.  bs: 1 or 3.
- * smoother: 0 = symmetric GS, 1 = ILU(0).  prec: 0 FP64, 1 FP32,
+ * smoother: 0 = symmetric GS, 1 = ILU(0), 2 = symmetric line GS over
+ * z-columns (scalar systems; FP64 and FP32).  prec: 0 FP64, 1 FP32,
  * 2 FP16 row-scaled.  A0 is copied; out-of-grid couplings are zeroed.
  * Returns NULL on error (zero pivot, coarsest level too large).
  */
 omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0, int smoother, int semi_mode,
                    int semi_levels, int prec, int max_coarse) {
+  if (smoother == 2 && (bs != 1 || prec == 2)) return NULL;
   omg* mg = (omg*)calloc(1, sizeof(omg));
   mg->bs = bs;
   mg->smoother = smoother;
@@ -474,6 +509,8 @@ omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0
     v->u32 = (float*)calloc(nvec, sizeof(float));
     v->r32 = (float*)calloc(nvec, sizeof(float));
     v->w32 = (float*)calloc(nvec, sizeof(float));
+    v->d = (double*)calloc(n[2], sizeof(double));
+    v->d32 = (float*)calloc(n[2], sizeof(float));
     mg->nlev = l + 1;
     v->cmask = orc_next_cmask(l, n, semi_mode, semi_levels);
     if (v->cmask == 0 || l == 47) {
@@ -500,6 +537,11 @@ omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0
         v->rU = (double*)malloc(sizeof(double) * v->N);
         if (orc_ilu0(v->nx, v->ny, v->nz, v->S, v->off, v->A, v->L, v->U, v->rU)) { orc_mg_destroy(mg); return NULL; }
       }
+      if (smoother == 2) {
+        v->tr = (double*)malloc(sizeof(double) * v->N);
+        v->tc = (double*)malloc(sizeof(double) * v->N);
+        if (orc_tri_factor(v->nx, v->ny, v->nz, v->S, v->off, v->A, v->tr, v->tc)) { orc_mg_destroy(mg); return NULL; }
+      }
     }
     if (prec != 0) {
       long na = (long)v->S * be * v->N;
@@ -509,6 +551,10 @@ omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0
         v->L32 = to_f32(v->L, (long)v->S * v->N);
         v->U32 = to_f32(v->U, (long)v->S * v->N);
         v->rU32 = to_f32(v->rU, v->N);
+      }
+      if (smoother == 2) {
+        v->tr32 = to_f32(v->tr, v->N);
+        v->tc32 = to_f32(v->tc, v->N);
       }
     }
   }
@@ -539,8 +585,9 @@ void orc_mg_destroy(omg* mg) {
     olev* v = &mg->lev[l];
     free(v->A); free(v->rd); free(v->L); free(v->U); free(v->rU);
     free(v->A32); free(v->rd32); free(v->L32); free(v->U32); free(v->rU32);
-    free(v->f); free(v->u); free(v->r); free(v->w);
-    free(v->f32); free(v->u32); free(v->r32); free(v->w32);
+    free(v->tr); free(v->tc); free(v->tr32); free(v->tc32);
+    free(v->f); free(v->u); free(v->r); free(v->w); free(v->d);
+    free(v->f32); free(v->u32); free(v->r32); free(v->w32); free(v->d32);
   }
   free(mg->LU); free(mg->piv); free(mg->cw);
   free(mg->kr); free(mg->kz); free(mg->kp); free(mg->kq); free(mg->kt);
@@ -557,7 +604,7 @@ void orc_mg_level_info(const omg* mg, int l, int* info) {
 }
 
 /* Copies out level data: what = 0 A, 1 rd (or block Dinv), 2 L, 3 U, 4 rU,
- * 5 truncated A (as float), 6 truncated rd. */
+ * 5 truncated A (as float), 6 truncated rd, 7 Thomas rden, 8 Thomas cp. */
 void orc_mg_level_data(const omg* mg, int l, int what, void* out) {
   const olev* v = &mg->lev[l];
   long be = (long)mg->bs * mg->bs;
@@ -569,6 +616,8 @@ void orc_mg_level_data(const omg* mg, int l, int what, void* out) {
     case 4: memcpy(out, v->rU, sizeof(double) * v->N); break;
     case 5: memcpy(out, v->A32, sizeof(float) * v->S * be * v->N); break;
     case 6: memcpy(out, v->rd32, sizeof(float) * (mg->bs == 3 ? 9 : 1) * v->N); break;
+    case 7: memcpy(out, v->tr, sizeof(double) * v->N); break;
+    case 8: memcpy(out, v->tc, sizeof(double) * v->N); break;
   }
 }
 
@@ -581,6 +630,9 @@ void orc_mg_level_data(const omg* mg, int l, int what, void* out) {
 #define FL L
 #define FU U
 #define FRU rU
+#define FTR tr
+#define FTC tc
+#define FD d
 #define REAL double
 #define SFX _f64
 #include "oracle_vcycle.inc"
@@ -595,6 +647,9 @@ void orc_mg_level_data(const omg* mg, int l, int what, void* out) {
 #undef FL
 #undef FU
 #undef FRU
+#undef FTR
+#undef FTC
+#undef FD
 
 #define FF f32
 #define FU_ u32
@@ -605,6 +660,9 @@ void orc_mg_level_data(const omg* mg, int l, int what, void* out) {
 #define FL L32
 #define FU U32
 #define FRU rU32
+#define FTR tr32
+#define FTC tc32
+#define FD d32
 #define REAL float
 #define SFX _f32
 #include "oracle_vcycle.inc"

@@ -111,3 +111,18 @@ def _fma(a, b, c):
     """Correctly rounded a*b+c via exact rational arithmetic."""
     from fractions import Fraction
     return float(Fraction(a) * Fraction(b) + Fraction(c))
+
+
+def line_gs(M, shape, b, u0, direction):
+    """Block Gauss-Seidel over z-columns written with dense blocks: for each
+    column J in lexicographic (x, y) order (reversed for direction -1),
+    u_J = M_JJ^-1 (b_J - sum_{K != J} M_JK u_K) with the current u."""
+    nx, ny, nz = shape
+    u = np.array(u0, dtype=np.float64).ravel().copy()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    cols = range(nx * ny) if direction > 0 else range(nx * ny - 1, -1, -1)
+    for J in cols:
+        r = slice(J * nz, (J + 1) * nz)
+        rhs = b[r] - M[r, :] @ u + M[r, r] @ u[r]
+        u[r] = np.linalg.solve(M[r, r], rhs)
+    return u

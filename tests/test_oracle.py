@@ -95,6 +95,77 @@ def test_gs_zero_guess_equals_zero_start():
 
 
 @pytest.mark.parametrize("npts", [7, 19, 27])
+@pytest.mark.parametrize("shape", [(3, 4, 5), (2, 3, 7), (1, 1, 6), (4, 3, 1)])
+@pytest.mark.parametrize("direction,zero_guess", [(1, 1), (1, 0), (-1, 0)])
+def test_lgs_matches_dense_block_gs(npts, shape, direction, zero_guess):
+    """Line GS = block GS with the z-columns as blocks, solved densely."""
+    off = workloads.offsets(npts)
+    A = workloads.random_sgdia(shape, npts, seed=5, symmetric=False)
+    M = helpers.dense_from_sgdia(A, off, shape)
+    rden, cp = oracle.tri_factor(off, A, shape)
+    g = workloads.rng(9)
+    b = g.uniform(-1, 1, size=shape)
+    u0 = np.zeros(shape) if zero_guess else g.uniform(-1, 1, size=shape)
+    u = oracle.lgs_sweep(off, A, rden, cp, b, u0, direction, zero_guess)
+    ref = helpers.line_gs(M, shape, b, u0, direction)
+    assert np.allclose(u.ravel(), ref, rtol=1e-13, atol=1e-13)
+    # matrix form of the GS formulas with D the column blocks:
+    # u + (D + L)^-1 (b - A u), L the couplings to earlier columns
+    col = np.arange(M.shape[0]) // shape[2]
+    keep = (col[None, :] <= col[:, None]) if direction > 0 else (col[None, :] >= col[:, None])
+    mf = u0.ravel() + np.linalg.solve(np.where(keep, M, 0.0), b.ravel() - M @ u0.ravel())
+    assert np.allclose(u.ravel(), mf, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("npts", [7, 19, 27])
+@pytest.mark.parametrize("direction,zero_guess", [(1, 1), (1, 0), (-1, 0)])
+def test_lgs_one_point_columns_is_point_gs(npts, direction, zero_guess):
+    """With nz = 1 every column is one point: line GS is point GS, bit for bit."""
+    shape = (5, 4, 1)
+    off = workloads.offsets(npts)
+    A = workloads.random_sgdia(shape, npts, seed=8, symmetric=False)
+    rden, cp = oracle.tri_factor(off, A, shape)
+    assert np.array_equal(rden, 1.0 / A[npts // 2]) and not cp.any()
+    g = workloads.rng(3)
+    b = g.uniform(-1, 1, size=shape)
+    u0 = np.zeros(shape) if zero_guess else g.uniform(-1, 1, size=shape)
+    u = oracle.lgs_sweep(off, A, rden, cp, b, u0, direction, zero_guess)
+    ref = oracle.gs_sweep(off, A, 1.0 / A[npts // 2], b, u0, direction, zero_guess)
+    assert np.array_equal(u, ref)
+
+
+def test_thomas_pivots_and_column_solve():
+    """On one column the sweep is the Thomas algorithm: the pivots multiply to
+    the determinant of the tridiagonal matrix and the solve matches a dense
+    solver."""
+    shape = (1, 1, 9)
+    off = workloads.offsets(19)
+    A = workloads.random_sgdia(shape, 19, seed=11, symmetric=False)
+    M = helpers.dense_from_sgdia(A, off, shape)
+    rden, cp = oracle.tri_factor(off, A, shape)
+    assert np.isclose(np.prod(1.0 / rden), np.linalg.det(M), rtol=1e-12)
+    b = workloads.rng(2).uniform(-1, 1, size=shape)
+    u = oracle.lgs_sweep(off, A, rden, cp, b, np.zeros(shape), 1, 1)
+    assert np.allclose(u.ravel(), np.linalg.solve(M, b.ravel()), rtol=1e-14, atol=1e-14)
+
+
+def test_lgs_exact_when_columns_decouple():
+    """Without couplings between columns one sweep solves A u = b."""
+    shape = (3, 4, 6)
+    off = workloads.offsets(27)
+    A = workloads.random_sgdia(shape, 27, seed=6, symmetric=False)
+    for s, (dx, dy, dz) in enumerate(off):
+        if dx or dy:
+            A[s] = 0.0
+    M = helpers.dense_from_sgdia(A, off, shape)
+    rden, cp = oracle.tri_factor(off, A, shape)
+    b = workloads.rng(4).uniform(-1, 1, size=shape)
+    for d in (1, -1):
+        u = oracle.lgs_sweep(off, A, rden, cp, b, np.zeros(shape), d, 1 if d > 0 else 0)
+        assert np.allclose(u.ravel(), np.linalg.solve(M, b.ravel()), rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("npts", [7, 19, 27])
 @pytest.mark.parametrize("shape", [(3, 4, 5), (4, 2, 3)])
 def test_ilu0_property(npts, shape):
     """(L U)_ij = a_ij on the mask (defining property of ILU(0))."""
@@ -350,6 +421,35 @@ def test_vcycle_symmetric(npts):
     a = np.dot(H.apply(x).ravel(), y.ravel())
     b = np.dot(x.ravel(), H.apply(y).ravel())
     assert abs(a - b) <= 1e-12 * max(abs(a), 1.0)
+
+
+def test_vcycle_lgs_symmetric():
+    """Forward line GS before and backward line GS after the coarse
+    correction also give a symmetric preconditioner."""
+    shape = (16, 12, 10)
+    H, _ = _sym_hierarchy(shape, 19, smoother="lgs")
+    assert H.nlev >= 2
+    g = workloads.rng(7)
+    x = g.uniform(-1, 1, size=shape)
+    y = g.uniform(-1, 1, size=shape)
+    a = np.dot(H.apply(x).ravel(), y.ravel())
+    b = np.dot(x.ravel(), H.apply(y).ravel())
+    assert abs(a - b) <= 1e-12 * max(abs(a), 1.0)
+
+
+def test_lgs_beats_point_gs_on_strong_vertical_coupling():
+    """Grid-aligned anisotropy (vertical coupling 100x the horizontal): line
+    GS over z-columns needs far fewer PCG iterations than point GS."""
+    shape = (24, 24, 16)
+    A, b = workloads.weather19(shape, seed=3, skew=0.0)
+    b = b.reshape(shape)
+    its = {}
+    for sm in ("gs", "lgs"):
+        H = oracle.Hierarchy(shape, 19, A, smoother=sm, coarsen="semi_xy")
+        x, st, it, rel = H.pcg(b, 1e-9, 300)
+        assert st == 0 and rel < 1e-9
+        its[sm] = it
+    assert its["lgs"] * 2 <= its["gs"], its
 
 
 def test_vcycle_block_symmetric():
