@@ -92,7 +92,11 @@ __global__ __launch_bounds__(256) void k_gj_elim(int n, double* __restrict__ aug
   if (t >= (long)n * w) return;
   const int r = (int)(t / w), j = k + (int)(t % w);
   if (r == k) return;
-  aug[(long)r * ld + j] = fma(-fac[r], aug[(long)k * ld + j], aug[(long)r * ld + j]);
+  // zero entries of the pivot row (most of the right half while k is small)
+  // leave the column unchanged (up to the sign of a zero): skip their traffic
+  const double pk = aug[(long)k * ld + j];
+  if (pk == 0.0) return;
+  aug[(long)r * ld + j] = fma(-fac[r], pk, aug[(long)r * ld + j]);
 }
 
 hipError_t coarse_invert(int n, double* aug, int* info_dev, hipStream_t st) {

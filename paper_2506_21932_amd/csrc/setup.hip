@@ -128,9 +128,12 @@ hipError_t launch_block_dinv(const Grid& g, const double* A, double* Dinv, unsig
 // of that neighbour: w[S] /= U_C[k], then for each upper slot T of row k in
 // canonical order whose combined offset lies in the mask and in the grid,
 // w[slot] = fma(-w[S], U_T[k], w[slot]).
-// Branch-free: loads use this row's slots when the neighbour row is outside
-// the grid (their values are then not used), and every update is a select,
-// so the loads of all rows can be issued together.
+// Branch-free: every update is performed, with the pivot 1 and the coupling 0
+// where the neighbour row is outside the grid or the fill is out of the mask.
+// Those constants are read from U[PAT*N] = 0 and U[PAT*N+1] = 1 through a
+// selected index, so their values stay unknown to the compiler: it keeps every
+// load of the row unconditional and in flight together instead of splitting
+// the row into branches that each wait for their own load.
 template <int PAT, int S, int T>
 __device__ __forceinline__ void ilu_fill(double (&w)[PAT], const double* __restrict__ U, long N, long k, bool vs,
                                          const Grid& g, int ax, int ay, int az) {
@@ -139,9 +142,11 @@ __device__ __forceinline__ void ilu_fill(double (&w)[PAT], const double* __restr
   if constexpr (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) {
     constexpr int sl = pat_slot(PAT, dx, dy, dz);
     if constexpr (sl >= 0) {
-      const double u = U[(long)T * N + k];
-      const bool in = vs && in_grid(g, ax + pat_off(PAT, T, 0), ay + pat_off(PAT, T, 1), az + pat_off(PAT, T, 2));
-      w[sl] = in ? fma(-w[S], u, w[sl]) : w[sl];
+      const bool in = vs & in_grid(g, ax + pat_off(PAT, T, 0), ay + pat_off(PAT, T, 1), az + pat_off(PAT, T, 2));
+      // unused couplings read the stored zero U[PAT*N]: w + (-w_S * 0) = w
+      // up to the sign of a zero result
+      const double u = U[in ? (long)T * N + k : (long)PAT * N];
+      w[sl] = fma(-w[S], u, w[sl]);
     }
   }
 }
@@ -155,8 +160,9 @@ __device__ __forceinline__ void ilu_row(double (&w)[PAT], const Grid& g, int X, 
   const bool vs = in_grid(g, ax, ay, az);
   const long k =
       vs ? i + pat_off(PAT, S, 0) * ((long)g.ny * g.nz) + pat_off(PAT, S, 1) * (long)g.nz + pat_off(PAT, S, 2) : i;
-  const double ud = U[(long)C * N + k];
-  w[S] = vs ? w[S] / ud : w[S];
+  // the stored 1 outside the grid
+  const double ud = U[vs ? (long)C * N + k : (long)PAT * N + 1];
+  w[S] = w[S] / ud;
   (ilu_fill<PAT, S, C + 1 + T>(w, U, N, k, vs, g, ax, ay, az), ...);
 }
 
@@ -171,28 +177,50 @@ __device__ __forceinline__ void ilu_rows(double (&w)[PAT], const Grid& g, int X,
 // lower slots in canonical (= ascending column) order, w[s] /= U_c[k], then
 // w[slot(off_s+off_t)] = fma(-w[s], U_t[k], w[...]) for the upper slots t of
 // row k in canonical order, dropping fill outside the mask.
-// Threads cover only the band of columns that meet the hyperplane: for each
-// x, the kb = nz / wy + 2 largest y with z = tau - wx*x - wy*y >= 0.
+// Threads cover only the points that can meet the hyperplane: the x range
+// [x0, x0 + nxr) where it crosses the grid, and for each x the kb = nz / wy + 2
+// largest y with z = tau - wx*x - wy*y >= 0.  The rows of one hyperplane are
+// scattered in memory (every load of a wave touches 64 lines), so the launch
+// uses one-wave workgroups to spread them over all compute units.
 __host__ __device__ constexpr int ilu_band(int nz, int wy) { return nz / wy + 2; }
+constexpr int ILU_WG = 64;
+
+// x range [x0, x0 + nxr) of the points on hyperplane tau (nxr <= 0: none)
+__host__ __device__ inline void ilu_xrange(const Grid& g, int wx, int wy, int tau, int* x0, int* nxr) {
+  // wx*x <= tau and wx*x >= tau - wy*(ny-1) - (nz-1)
+  const int lo = tau - wy * (g.ny - 1) - (g.nz - 1);
+  *x0 = lo <= 0 ? 0 : (lo + wx - 1) / wx;
+  const int x1 = tau / wx < g.nx - 1 ? tau / wx : g.nx - 1;
+  *nxr = x1 - *x0 + 1;
+}
+
+// Point of band thread t of hyperplane tau (x range starting at x0, nxr
+// columns); false if the thread has none.
+template <int WX, int WY>
+__device__ __forceinline__ bool ilu_point(const Grid& g, int tau, int x0, int nxr, int kb, int t, int& X, int& Y,
+                                          int& Z) {
+  if (t < 0 || t >= nxr * kb) return false;
+  X = x0 + t / kb;
+  if (X >= g.nx) return false;
+  const int rem = tau - WX * X;
+  if (rem < 0) return false;
+  Y = rem / WY - t % kb;
+  if (Y < 0 || Y >= g.ny) return false;
+  Z = rem - WY * Y;
+  return Z >= 0 && Z < g.nz;
+}
 
 template <int PAT>
-__global__ __launch_bounds__(256) void k_ilu0_plane(Grid g, int tau, const double* __restrict__ A,
-                                                    double* __restrict__ L, double* __restrict__ U,
-                                                    double* __restrict__ rU, unsigned* err) {
+__global__ __launch_bounds__(ILU_WG) void k_ilu0_plane(Grid g, int tau, int x0, int nxr,
+                                                       const double* __restrict__ A, double* __restrict__ L,
+                                                       double* __restrict__ U, double* __restrict__ rU,
+                                                       unsigned* err) {
   constexpr int C = PAT / 2, WX = hp_wx(PAT), WY = hp_wy(PAT);
   const long N = g.N();
   const int kb = ilu_band(g.nz, WY);
-  const unsigned t = blockIdx.x * 256u + threadIdx.x;
-  if (t >= (unsigned)(g.nx * kb)) return;
-  const int X = (int)(t / (unsigned)kb);
-  const int rem = tau - WX * X;
-  if (rem < 0) return;
-  const int Y = rem / WY - (int)(t % (unsigned)kb);
-  if (Y < 0 || Y >= g.ny) return;
-  const int Z = rem - WY * Y;
-  if (Z < 0 || Z >= g.nz) return;
+  int X, Y, Z;
+  if (!ilu_point<WX, WY>(g, tau, x0, nxr, kb, (int)(blockIdx.x * (unsigned)ILU_WG + threadIdx.x), X, Y, Z)) return;
   const long i = ((long)X * g.ny + Y) * g.nz + Z;
-  const long nyz = (long)g.ny * g.nz;
   double w[PAT];
 #pragma unroll
   for (int s = 0; s < PAT; ++s) {
@@ -212,15 +240,25 @@ __global__ __launch_bounds__(256) void k_ilu0_plane(Grid g, int tau, const doubl
 
 hipError_t launch_ilu0_factor(int pat, const Grid& g, const double* A, double* L, double* U, double* rU,
                               unsigned* err, hipStream_t st) {
-  const int D = hp_wx(pat) * (g.nx - 1) + hp_wy(pat) * (g.ny - 1) + g.nz;
-  const dim3 grid((unsigned)((g.nx * ilu_band(g.nz, hp_wy(pat)) + 255) / 256)), blk(256);
+  if (pat != 7 && pat != 19 && pat != 27) return hipErrorInvalidValue;
+  const int wx = hp_wx(pat), wy = hp_wy(pat);
+  const int D = wx * (g.nx - 1) + wy * (g.ny - 1) + g.nz;
+  const long N = g.N();
+  hipError_t e0 = launch_fill_bits<double>(U + (long)pat * N, 1, 0.0, st);
+  if (e0 == hipSuccess) e0 = launch_fill_bits<double>(U + (long)pat * N + 1, 1, 1.0, st);
+  if (e0 != hipSuccess) return e0;
+  const int kb = ilu_band(g.nz, wy);
   for (int tau = 0; tau < D; ++tau) {
+    int x0, nxr;
+    ilu_xrange(g, wx, wy, tau, &x0, &nxr);
+    if (nxr <= 0) continue;
+    const dim3 grid((unsigned)((nxr * kb + ILU_WG - 1) / ILU_WG)), blk(ILU_WG);
     if (pat == 7)
-      hipLaunchKernelGGL((k_ilu0_plane<7>), grid, blk, 0, st, g, tau, A, L, U, rU, err);
+      hipLaunchKernelGGL((k_ilu0_plane<7>), grid, blk, 0, st, g, tau, x0, nxr, A, L, U, rU, err);
     else if (pat == 19)
-      hipLaunchKernelGGL((k_ilu0_plane<19>), grid, blk, 0, st, g, tau, A, L, U, rU, err);
+      hipLaunchKernelGGL((k_ilu0_plane<19>), grid, blk, 0, st, g, tau, x0, nxr, A, L, U, rU, err);
     else if (pat == 27)
-      hipLaunchKernelGGL((k_ilu0_plane<27>), grid, blk, 0, st, g, tau, A, L, U, rU, err);
+      hipLaunchKernelGGL((k_ilu0_plane<27>), grid, blk, 0, st, g, tau, x0, nxr, A, L, U, rU, err);
     else
       return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();

@@ -146,7 +146,7 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
     v.rd64 = ar.take<double>((size_t)(bs == 3 ? 9 : 1) * N);
     if (cfg.smoother == SMG_SMOOTH_ILU0) {
       v.L64 = ar.take<double>((size_t)v.S * N);
-      v.U64 = ar.take<double>((size_t)v.S * N);
+      v.U64 = ar.take<double>((size_t)v.S * N + 2);  // + the factorisation's {0, 1}
       v.rU64 = ar.take<double>((size_t)N);
       vec(&v.y1);
       vec(&v.y2);

@@ -168,7 +168,9 @@ def test_poisson_32_pcg():
     assert res["levels"] == 4
 
 
-@pytest.mark.parametrize("case", [CASES[1], CASES[3]], ids=_ids)
+# the last two cases have hyperplanes of several 64-row chunks and more chunks
+# than the persistent factorisation keeps resident, so its workgroups loop
+@pytest.mark.parametrize("case", [CASES[1], CASES[3], CASES[5], CASES[6]], ids=_ids)
 def test_ilu0_bitexact(case):
     A, H, mg = _pair(case, smoother="ilu0", sym=False)
     g = workloads.rng(13)
