@@ -52,7 +52,7 @@ typedef enum {
   SMG_EDEADLOCK = -5   /* wavefront watchdog fired (a wait did not finish) */
 } smg_status;
 
-typedef enum { SMG_SMOOTH_GS = 0, SMG_SMOOTH_ILU0 = 1 } smg_smoother;
+typedef enum { SMG_SMOOTH_GS = 0, SMG_SMOOTH_ILU0 = 1, SMG_SMOOTH_LGS = 2 } smg_smoother;
 typedef enum { SMG_COARSEN_FULL = 0, SMG_COARSEN_SEMI_XY = 1 } smg_coarsen;
 typedef enum { SMG_FP64 = 0, SMG_FP32 = 1, SMG_FP16_ROWSCALE = 2 } smg_prec;
 
@@ -61,7 +61,10 @@ typedef struct {
   int block;           /* unknowns per node: 1, or 3 (3x3 blocks, 27-point only) */
   int pattern;         /* finest-level pattern: 7, 19 or 27; coarse levels are 27-point */
   int smoother;        /* smg_smoother: symmetric point GS (forward before, backward
-                          after the coarse correction) or ILU(0) on each level's mask */
+                          after the coarse correction), ILU(0) on each level's mask, or
+                          symmetric line GS over z-columns (Sec. 4.4: column right-hand
+                          side from the neighbouring columns, Thomas solve per column;
+                          scalar systems, FP64 or FP32, nz <= 2047) */
   int coarsen;         /* smg_coarsen: coarsen x,y,z (full) or only x,y (semi) */
   int semi_levels;     /* with SMG_COARSEN_FULL: the first semi_levels levels coarsen x,y only */
   int prec;            /* smg_prec of the V-cycle matrices and vectors; the outer
@@ -133,7 +136,8 @@ int smg_num_levels(smg_handle h);
  * 3x3 diagonal-block inverses (FP64, 9*N), 2 ILU lower factor (FP64, S*N),
  * 3 ILU upper factor (FP64, S*N), 4 reciprocal of the ILU diagonal (FP64, N),
  * 5 V-cycle matrix (FP32; FP16 storage is expanded to scale*float(h)),
- * 6 V-cycle reciprocal diagonal / block inverses (FP32). */
+ * 6 V-cycle reciprocal diagonal / block inverses (FP32), 7 line GS Thomas
+ * reciprocal pivots (FP64, N), 8 line GS Thomas c/pivot (FP64, N). */
 smg_status smg_level_export(smg_handle h, int level, int what, void* dst, void* stream);
 
 /* Influence chains of the generated triple product for a (fine pattern,
@@ -146,11 +150,11 @@ int smg_rap_chain_count(int pattern, int cmask);
  * size (times block).  Output arrays must not overlap inputs. */
 smg_status smg_op_spmv(smg_handle h, int level, const void* x, void* y, void* stream);          /* y = A_l x */
 smg_status smg_op_spmv_fp64(smg_handle h, const double* x, double* y, void* stream);           /* finest, FP64 */
-/* u = S_pre(f): forward GS sweep from u = 0, or the ILU(0) solve. */
+/* u = S_pre(f): forward GS or line GS sweep from u = 0, or the ILU(0) solve. */
 smg_status smg_op_presmooth(smg_handle h, int level, const void* f, void* u, void* stream);
-/* u_out = S_post(f, u_in + P e_c): backward GS sweep, or the ILU(0)
- * correction, after prolongation of the coarse correction e_c (level l+1
- * vector, NULL for none). */
+/* u_out = S_post(f, u_in + P e_c): backward GS or line GS sweep, or the
+ * ILU(0) correction, after prolongation of the coarse correction e_c (level
+ * l+1 vector, NULL for none). */
 smg_status smg_op_postsmooth(smg_handle h, int level, const void* f, const void* u_in, const void* ec, void* u_out,
                              void* stream);
 /* rc = R (f - A_l u): fused residual and restriction to level l+1. */

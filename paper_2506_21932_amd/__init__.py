@@ -16,7 +16,7 @@ SMG_OK, SMG_ENOTCONV, SMG_EINVAL, SMG_ENOMEM, SMG_EDEVICE, SMG_EBREAKDOWN, SMG_E
 STATUS_NAMES = {0: "SMG_OK", 1: "SMG_ENOTCONV", -1: "SMG_EINVAL", -2: "SMG_ENOMEM", -3: "SMG_EDEVICE",
                 -4: "SMG_EBREAKDOWN", -5: "SMG_EDEADLOCK"}
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2}
-SMOOTHER = {"gs": 0, "ilu0": 1}
+SMOOTHER = {"gs": 0, "ilu0": 1, "lgs": 2}
 COARSEN = {"full": 0, "semi_xy": 1}
 
 

@@ -1,0 +1,282 @@
+// Line Gauss-Seidel over z-columns (Sec. 4.4, "For LGS" paragraph): the
+// unknowns of one column (x, y) are updated together.  The right-hand side of
+// a column is assembled from the neighbouring columns, then the column's
+// tridiagonal system (couplings (0,0,-1), centre, (0,0,+1)) is solved by the
+// Thomas algorithm.  Columns are visited in lexicographic (x, y) order
+// (forward) or in reverse (backward), as in the GS formulas with the column
+// blocks as D.
+//
+// Setup: k_tri_factor forms the Thomas pivots once per hierarchy (FP64, one
+// thread per column): p_0 = b_0, p_z = fma(-a_z, cp_{z-1}, b_z),
+// rden_z = 1/p_z, cp_z = c_z * rden_z.
+//
+// Sweep (k_lgs): a column depends only on columns whose (x, y) come earlier
+// in the visiting order and are stencil neighbours; in the projected 2D
+// pattern (2d5 for 3d7, 2d9 for 3d19 / 3d27) those lie on earlier
+// hyperplanes cwx*x + y = t with cwx = 1 (3d7) or 2 (3d19, 3d27: the
+// neighbour (x-1, y+1) must come first).  Work unit: a chunk of K columns of
+// one hyperplane (K*nz <= 512 points), numbered hyperplane-major.  Persistent
+// workgroups take chunks by atomic ticket, so every chunk's producers hold
+// smaller tickets and are already running: the grid always makes progress.
+// A workgroup
+//   A. assembles the right-hand side of its K columns, one point per thread:
+//      t = f_i; the terms of columns not yet visited (values from before the
+//      sweep, plain loads); then the terms of columns of this sweep, whose
+//      values are read device-coherently from the output and awaited while
+//      they still hold the sentinel; each group in canonical order with fma.
+//      The Thomas factors of the chunk are staged in LDS with the sums;
+//   B. solves each column in one lane (forward elimination, back
+//      substitution), in the oracle's order of operations;
+//   C. stores the column device-coherently and, if asked, writes the sentinel
+//      into `next` (the buffer the following sweep will fill).  Every reader
+//      of `next` at these points is a column this one waited for, so those
+//      reads are complete.
+// Waits are bounded: after LGS_SPIN_LIMIT polls, bit 0 of err is set and
+// every waiting lane gives up.
+#include <utility>
+
+#include "smg_kernels.h"
+
+namespace smg {
+
+namespace {
+
+constexpr int LGS_NT = 256;                 // threads per workgroup
+constexpr int LGS_PTS = 512;                // points per chunk (K * nz), unless nz is larger
+constexpr unsigned LGS_SPIN_LIMIT = 1u << 21;
+
+__host__ __device__ constexpr int lgs_cwx(int pat) { return pat == 7 ? 1 : 2; }
+
+// does the column at (dx, dy) come later than the current one in the
+// visiting order of direction DIR?
+__host__ __device__ constexpr bool lgs_later(int dir, int dx, int dy) {
+  return dir > 0 ? (dx > 0 || (dx == 0 && dy > 0)) : (dx < 0 || (dx == 0 && dy < 0));
+}
+
+// x range [x0, x0 + nxr) of the columns on hyperplane cwx*x + y = t
+__host__ __device__ inline void lgs_xrange(const Grid& g, int cwx, int t, int* x0, int* nxr) {
+  const int lo = t - (g.ny - 1);
+  *x0 = lo <= 0 ? 0 : (lo + cwx - 1) / cwx;
+  const int x1 = t / cwx < g.nx - 1 ? t / cwx : g.nx - 1;
+  *nxr = x1 - *x0 + 1;
+}
+
+template <class V>
+__device__ inline V cload(const V* p) {
+  using U = typename VBits<V>::U;
+  return VBits<V>::val(__hip_atomic_load(reinterpret_cast<const U*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+template <class V>
+__device__ inline void cstore(V* p, V v) {
+  using U = typename VBits<V>::U;
+  __hip_atomic_store(reinterpret_cast<U*>(p), VBits<V>::bits(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait until *p no longer holds the sentinel.
+template <class V>
+__device__ inline V await_value(const V* p, V v, unsigned* err) {
+  unsigned spins = 0;
+  while (VBits<V>::bits(v) == VBits<V>::sent) {
+    if (++spins >= LGS_SPIN_LIMIT) {
+      atomicOr(err, 1u);
+      break;
+    }
+    if ((spins & 1023u) == 1023u && (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u)) break;
+    __builtin_amdgcn_s_sleep(2);
+    v = cload(p);
+  }
+  return v;
+}
+
+// Terms of one group (columns later in the order: OLD = true; columns of
+// this sweep: OLD = false) for slot S, in canonical order via the fold below.
+template <int PAT, int DIR, bool OLD, int S, class V>
+__device__ __forceinline__ void lgs_term(V& t, const V* __restrict__ A, const V* src, long N, long i, const Grid& g,
+                                         int X, int Y, int Z, unsigned* err) {
+  constexpr int dx = pat_off(PAT, S, 0), dy = pat_off(PAT, S, 1), dz = pat_off(PAT, S, 2);
+  if constexpr (!(dx == 0 && dy == 0) && lgs_later(DIR, dx, dy) == OLD) {
+    if (in_grid(g, X + dx, Y + dy, Z + dz)) {
+      const long j = i + dx * ((long)g.ny * g.nz) + dy * (long)g.nz + dz;
+      V u;
+      if constexpr (OLD) {
+        u = src[j];
+      } else {
+        u = await_value(src + j, cload(src + j), err);
+      }
+      t = fma(-A[(long)S * N + i], u, t);
+    }
+  }
+}
+
+template <int PAT, int DIR, bool OLD, class V, int... S>
+__device__ __forceinline__ void lgs_group(V& t, const V* __restrict__ A, const V* src, long N, long i, const Grid& g,
+                                          int X, int Y, int Z, unsigned* err, std::integer_sequence<int, S...>) {
+  (lgs_term<PAT, DIR, OLD, S, V>(t, A, src, N, i, g, X, Y, Z, err), ...);
+}
+
+__device__ inline unsigned lgs_take_ticket(unsigned* ctr) {
+  __shared__ unsigned s_ticket;
+  if (threadIdx.x == 0) s_ticket = atomicAdd(&ctr[0], 1u);
+  __syncthreads();
+  const unsigned t = s_ticket;
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(t);
+}
+
+// The last workgroup to finish resets the ticket counters for the next launch.
+__device__ inline void lgs_retire(unsigned* ctr) {
+  if (threadIdx.x == 0) {
+    const unsigned o = atomicAdd(&ctr[1], 1u);
+    if (o == gridDim.x - 1) {
+      __hip_atomic_store(&ctr[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctr[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+template <int PAT, int DIR, class V, bool ZG>
+__global__ __launch_bounds__(LGS_NT) void k_lgs(LgsArgs<V> a) {
+  constexpr int CWX = lgs_cwx(PAT);
+  constexpr int SLO = pat_slot(PAT, 0, 0, -1);
+  extern __shared__ __align__(16) unsigned char lgs_smem[];
+  const Grid g = a.g;
+  const long N = g.N();
+  const int nz = g.nz, K = a.K, LD = nz + 1;
+  V* ld = reinterpret_cast<V*>(lgs_smem);  // right-hand side, then d', then x
+  V* la = ld + K * LD;                      // coupling to z-1
+  V* lr = la + K * LD;                      // 1 / pivot
+  V* lc = lr + K * LD;                      // c / pivot
+  const unsigned total = (unsigned)a.T * (unsigned)a.M;
+  for (;;) {
+    const unsigned ticket = lgs_take_ticket(a.ctr);
+    if (ticket >= total) break;
+    const int p = (int)(ticket / (unsigned)a.M), j = (int)(ticket % (unsigned)a.M);
+    const int t = DIR > 0 ? p : a.T - 1 - p;
+    int x0, nxr;
+    lgs_xrange(g, CWX, t, &x0, &nxr);
+    const int ncol = nxr - j * K < K ? nxr - j * K : K;  // columns of this chunk (may be <= 0)
+    // A. right-hand sides and staged factors
+    for (int q = threadIdx.x; q < ncol * nz; q += LGS_NT) {
+      const int c = q / nz, Z = q - c * nz;
+      const int X = x0 + j * K + c, Y = t - CWX * X;
+      const long i = ((long)X * g.ny + Y) * nz + Z;
+      V s = a.f[i];
+      if constexpr (!ZG)
+        lgs_group<PAT, DIR, true, V>(s, a.A, a.uold, N, i, g, X, Y, Z, a.err, std::make_integer_sequence<int, PAT>{});
+      lgs_group<PAT, DIR, false, V>(s, a.A, a.x, N, i, g, X, Y, Z, a.err, std::make_integer_sequence<int, PAT>{});
+      const int o = c * LD + Z;
+      ld[o] = s;
+      la[o] = Z > 0 ? a.A[(long)SLO * N + i] : V(0);
+      lr[o] = a.rden[i];
+      lc[o] = a.cp[i];
+    }
+    __syncthreads();
+    // B. Thomas solve, one lane per column
+    if ((int)threadIdx.x < ncol) {
+      const int b = (int)threadIdx.x * LD;
+      V dp = ld[b] * lr[b];
+      ld[b] = dp;
+      for (int Z = 1; Z < nz; ++Z) {
+        dp = fma(-la[b + Z], dp, ld[b + Z]) * lr[b + Z];
+        ld[b + Z] = dp;
+      }
+      V xv = dp;
+      for (int Z = nz - 2; Z >= 0; --Z) {
+        xv = fma(-lc[b + Z], xv, ld[b + Z]);
+        ld[b + Z] = xv;
+      }
+    }
+    __syncthreads();
+    // C. results out, sentinels for the next sweep
+    for (int q = threadIdx.x; q < ncol * nz; q += LGS_NT) {
+      const int c = q / nz, Z = q - c * nz;
+      const int X = x0 + j * K + c, Y = t - CWX * X;
+      const long i = ((long)X * g.ny + Y) * nz + Z;
+      cstore(a.x + i, ld[c * LD + Z]);
+      if (a.next) a.next[i] = VBits<V>::val(VBits<V>::sent);
+    }
+  }
+  lgs_retire(a.ctr);
+}
+
+// Thomas pivots of every z-column (FP64, one thread per column).
+__global__ __launch_bounds__(256) void k_tri_factor(Grid g, int slo, int sc, int sup, const double* __restrict__ A,
+                                                     double* __restrict__ rden, double* __restrict__ cp,
+                                                     unsigned* err) {
+  const long col = (long)blockIdx.x * 256 + threadIdx.x;
+  if (col >= (long)g.nx * g.ny) return;
+  const long N = g.N();
+  const long i0 = col * g.nz;
+  double cprev = 0.0;
+  for (int Z = 0; Z < g.nz; ++Z) {
+    const long i = i0 + Z;
+    const double az = Z > 0 ? A[(long)slo * N + i] : 0.0;
+    const double cz = Z < g.nz - 1 ? A[(long)sup * N + i] : 0.0;
+    const double piv = Z == 0 ? A[(long)sc * N + i] : fma(-az, cprev, A[(long)sc * N + i]);
+    if (piv == 0.0) atomicOr(err, 2u);
+    const double r = 1.0 / piv;
+    rden[i] = r;
+    cprev = cz * r;
+    cp[i] = cprev;
+  }
+}
+
+template <int PAT, int DIR, class V, bool ZG>
+hipError_t launch_lgs_t(const LgsArgs<V>& a, hipStream_t st) {
+  const unsigned total = (unsigned)a.T * (unsigned)a.M;
+  const unsigned grid = total < (unsigned)LGS_MAX_GRID ? total : (unsigned)LGS_MAX_GRID;
+  const size_t lds = (size_t)4 * a.K * (a.g.nz + 1) * sizeof(V);
+  hipLaunchKernelGGL((k_lgs<PAT, DIR, V, ZG>), dim3(grid), dim3(LGS_NT), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int PAT, class V>
+hipError_t launch_lgs_p(int dir, bool zg, const LgsArgs<V>& a, hipStream_t st) {
+  if (dir > 0) return zg ? launch_lgs_t<PAT, 1, V, true>(a, st) : launch_lgs_t<PAT, 1, V, false>(a, st);
+  if (zg) return hipErrorInvalidValue;  // the zero-guess sweep is the forward pre-smoother
+  return launch_lgs_t<PAT, -1, V, false>(a, st);
+}
+
+}  // namespace
+
+void lgs_plan(const Grid& g, int pat, int* K, int* M, int* T) {
+  const int cwx = lgs_cwx(pat);
+  *K = g.nz >= LGS_PTS ? 1 : (LGS_PTS / g.nz < 64 ? LGS_PTS / g.nz : 64);
+  *T = cwx * (g.nx - 1) + (g.ny - 1) + 1;
+  int mx = 0;
+  for (int t = 0; t < *T; ++t) {
+    int x0, nxr;
+    lgs_xrange(g, cwx, t, &x0, &nxr);
+    mx = nxr > mx ? nxr : mx;
+  }
+  *M = (mx + *K - 1) / *K;
+}
+
+size_t lgs_lds_bytes(const Grid& g, int K, int vbytes) { return (size_t)4 * K * (g.nz + 1) * vbytes; }
+
+hipError_t launch_tri_factor(int pat, const Grid& g, const double* A, double* rden, double* cp, unsigned* err,
+                             hipStream_t st) {
+  const int slo = pat_slot(pat, 0, 0, -1), sc = pat_slot(pat, 0, 0, 0), sup = pat_slot(pat, 0, 0, 1);
+  if (slo < 0 || sc < 0 || sup < 0) return hipErrorInvalidValue;
+  const long ncol = (long)g.nx * g.ny;
+  hipLaunchKernelGGL(k_tri_factor, dim3((unsigned)((ncol + 255) / 256)), dim3(256), 0, st, g, slo, sc, sup, A, rden,
+                     cp, err);
+  return hipGetLastError();
+}
+
+template <class V>
+hipError_t launch_lgs(int pat, int dir, bool zero_guess, const LgsArgs<V>& a, hipStream_t st) {
+  if (a.K < 1 || a.M < 1 || a.T < 1 || a.g.nz > LGS_MAX_NZ || lgs_lds_bytes(a.g, a.K, (int)sizeof(V)) > 65536 ||
+      (!zero_guess && a.uold == nullptr))
+    return hipErrorInvalidValue;
+  if (pat == 7) return launch_lgs_p<7, V>(dir, zero_guess, a, st);
+  if (pat == 19) return launch_lgs_p<19, V>(dir, zero_guess, a, st);
+  if (pat == 27) return launch_lgs_p<27, V>(dir, zero_guess, a, st);
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_lgs<double>(int, int, bool, const LgsArgs<double>&, hipStream_t);
+template hipError_t launch_lgs<float>(int, int, bool, const LgsArgs<float>&, hipStream_t);
+
+}  // namespace smg

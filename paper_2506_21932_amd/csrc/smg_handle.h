@@ -30,6 +30,9 @@ struct Level {
   int hp_steps = 0;                 // small level: hyperplanes of the one-workgroup sweep (0: tiled sweep)
   int* hp_pts = nullptr;            // its point schedule [step][256]
   void* hp_cf[2] = {nullptr, nullptr};  // its step-ordered coefficients, forward / backward
+  double *tr64 = nullptr, *tc64 = nullptr;  // line GS: Thomas 1/pivot and c/pivot per point
+  float *tr32 = nullptr, *tc32 = nullptr;
+  int lg_K = 0, lg_M = 0, lg_T = 0;         // line GS chunking (columns per chunk, chunks, hyperplanes)
 };
 
 }  // namespace smg
@@ -78,6 +81,9 @@ struct P64 {
   static MF Uf(const Level& l) { return MatD{l.U64, l.N}; }
   static const V* rd(const Level& l) { return l.rd64; }
   static const V* rU(const Level& l) { return l.rU64; }
+  static const V* Araw(const Level& l) { return l.A64; }
+  static const V* tr(const Level& l) { return l.tr64; }
+  static const V* tc(const Level& l) { return l.tc64; }
 };
 struct P32 {
   using V = float;
@@ -91,6 +97,9 @@ struct P32 {
   static MF Uf(const Level& l) { return MatF{l.U32, l.N}; }
   static const V* rd(const Level& l) { return l.rd32; }
   static const V* rU(const Level& l) { return l.rU32; }
+  static const V* Araw(const Level& l) { return l.A32; }
+  static const V* tr(const Level& l) { return l.tr32; }
+  static const V* tc(const Level& l) { return l.tc32; }
 };
 struct P16 {
   using V = float;
@@ -104,6 +113,10 @@ struct P16 {
   static MF Uf(const Level& l) { return MatF{l.U32, l.N}; }
   static const V* rd(const Level& l) { return l.rd32; }
   static const V* rU(const Level& l) { return l.rU32; }
+  // line GS keeps no FP16 storage (the configuration is rejected)
+  static const V* Araw(const Level&) { return nullptr; }
+  static const V* tr(const Level&) { return nullptr; }
+  static const V* tc(const Level&) { return nullptr; }
 };
 
 // Validation of a configuration (null when supported) and the level shapes

@@ -209,6 +209,32 @@ hipError_t launch_block_dinv(const Grid& g, const double* A, double* Dinv, unsig
 // and read where a coupling or pivot is unused)
 hipError_t launch_ilu0_factor(int pat, const Grid& g, const double* A, double* L, double* U, double* rU,
                               unsigned* err, hipStream_t st);
+// Line Gauss-Seidel over z-columns (lgs.hip).  Chunks of K columns of one
+// hyperplane are the work units (M chunks per hyperplane, T hyperplanes);
+// x holds the sentinel until written; uold: values before the sweep (null for
+// the zero-guess forward sweep); next: buffer given the sentinel (or null).
+constexpr int LGS_MAX_GRID = 512;
+constexpr int LGS_MAX_NZ = 2047;
+template <class V>
+struct LgsArgs {
+  Grid g;
+  const V* A;
+  const V* rden;
+  const V* cp;
+  const V* f;
+  const V* uold;
+  V* x;
+  V* next;
+  int K, M, T;
+  unsigned* ctr;
+  unsigned* err;
+};
+void lgs_plan(const Grid& g, int pat, int* K, int* M, int* T);
+size_t lgs_lds_bytes(const Grid& g, int K, int vbytes);
+hipError_t launch_tri_factor(int pat, const Grid& g, const double* A, double* rden, double* cp, unsigned* err,
+                             hipStream_t st);
+template <class V>
+hipError_t launch_lgs(int pat, int dir, bool zero_guess, const LgsArgs<V>& a, hipStream_t st);
 hipError_t launch_to_f32(const double* src, float* dst, long n, hipStream_t st);
 hipError_t launch_to_f16_rowscale(const double* A, long N, int S, int bs, __half* h, float* sc, hipStream_t st);
 hipError_t launch_dequant_f16(const __half* h, const float* sc, long N, int S, int bs, float* out, hipStream_t st);

@@ -93,7 +93,11 @@ const char* check_cfg(const smg_config* c) {
   if (c->block != 1 && c->block != 3) return "block must be 1 or 3";
   if (c->pattern != 7 && c->pattern != 19 && c->pattern != 27) return "pattern must be 7, 19 or 27";
   if (c->block == 3 && c->pattern != 27) return "block systems use the 27-point pattern";
-  if (c->smoother != SMG_SMOOTH_GS && c->smoother != SMG_SMOOTH_ILU0) return "unknown smoother";
+  if (c->smoother != SMG_SMOOTH_GS && c->smoother != SMG_SMOOTH_ILU0 && c->smoother != SMG_SMOOTH_LGS)
+    return "unknown smoother";
+  if (c->smoother == SMG_SMOOTH_LGS && c->block != 1) return "line GS is implemented for scalar systems";
+  if (c->smoother == SMG_SMOOTH_LGS && c->prec == SMG_FP16_ROWSCALE) return "line GS supports FP64 and FP32";
+  if (c->smoother == SMG_SMOOTH_LGS && c->nz > LGS_MAX_NZ) return "line GS: nz too large (limit 2047)";
   if (c->smoother == SMG_SMOOTH_ILU0 && c->block != 1) return "ILU(0) is implemented for scalar systems";
   if (c->smoother == SMG_SMOOTH_ILU0 && c->prec == SMG_FP16_ROWSCALE) return "ILU(0) supports FP64 and FP32";
   if (c->coarsen != SMG_COARSEN_FULL && c->coarsen != SMG_COARSEN_SEMI_XY) return "unknown coarsening";
@@ -154,7 +158,15 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
       vec(&v.uo);
     }
     const int eb = cfg.prec == SMG_FP16_ROWSCALE ? 2 : (int)vsz;
-    if (bs == 1) {
+    if (cfg.smoother == SMG_SMOOTH_LGS) {
+      lgs_plan(v.g, v.S, &v.lg_K, &v.lg_M, &v.lg_T);
+      v.tr64 = ar.take<double>((size_t)N);
+      v.tc64 = ar.take<double>((size_t)N);
+      if (cfg.prec == SMG_FP32) {
+        v.tr32 = ar.take<float>((size_t)N);
+        v.tc32 = ar.take<float>((size_t)N);
+      }
+    } else if (bs == 1) {
       wf_tiling(v.g, v.S, &v.tl);
       const size_t pbytes = (size_t)wf_pack_count(v.S, eb) * 16 * v.tl.nsk;
       v.pk[0] = ar.take<char>(pbytes);
@@ -308,6 +320,30 @@ hipError_t bvcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* 
 constexpr long SPLIT_MIN_POINTS = 1L << 17;
 static bool split_rp(const Level& v) { return v.N >= SPLIT_MIN_POINTS; }
 
+// One line GS sweep on level v: x = LGS(f) from the values uold (null: zero
+// initial guess, forward only); next receives the sentinel (or null).
+template <class PT>
+hipError_t lgs_sweep(smg_handle_s* H, const Level& v, int dir, const typename PT::V* f, const typename PT::V* uold,
+                     typename PT::V* x, typename PT::V* next, hipStream_t st) {
+  using V = typename PT::V;
+  LgsArgs<V> a{};
+  a.g = v.g;
+  a.A = PT::Araw(v);
+  a.rden = PT::tr(v);
+  a.cp = PT::tc(v);
+  if (!a.A || !a.rden || !a.cp) return hipErrorInvalidValue;
+  a.f = f;
+  a.uold = uold;
+  a.x = x;
+  a.next = next;
+  a.K = v.lg_K;
+  a.M = v.lg_M;
+  a.T = v.lg_T;
+  a.ctr = H->ctr;
+  a.err = H->err;
+  return launch_lgs<V>(v.S, dir, uold == nullptr, a, st);
+}
+
 // One V-cycle on internal or caller vectors: f0 = level-0 right-hand side,
 // z0 = level-0 output (its positions read across tiles are given sentinels by
 // the pre-smoothing sweep).
@@ -317,13 +353,18 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
   if (H->bs == 3) return bvcycle_t<PT>(H, f0, z0, st);
   const int NL = H->nlev;
   const bool ilu = H->cfg.smoother == SMG_SMOOTH_ILU0;
+  const bool lgs = H->cfg.smoother == SMG_SMOOTH_LGS;
   auto F = [&](int l) -> const V* { return l == 0 ? f0 : (const V*)H->lev[l].f; };
   auto UB = [&](int l) -> V* { return l == 0 ? z0 : (V*)H->lev[l].ub; };
   hipError_t e;
   for (int l = 0; l < NL - 1; ++l) {
     const Level& v = H->lev[l];
     const auto A = PT::A(v);
-    if (!ilu) {
+    if (lgs) {
+      // forward line GS from zero into u_a; the level's output gets sentinels
+      Timed t(H, l, 0, st);
+      e = lgs_sweep<PT>(H, v, +1, F(l), nullptr, (V*)v.ua, UB(l), st);
+    } else if (!ilu) {
       Timed t(H, l, 0, st);
       e = sweep<typename PT::E, V>(H, v, +1, false, F(l), (V*)v.ua, UB(l), -1, nullptr, nullptr, st);
     } else {
@@ -356,7 +397,16 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
   for (int l = NL - 2; l >= 0; --l) {
     const Level& v = H->lev[l];
     const auto A = PT::A(v);
-    if (!ilu) {
+    if (lgs) {
+      {
+        Timed t(H, l, 4, st);
+        e = launch_prolong_add<V>(v.g, v.cmask, 1, (const V*)UB(l + 1), (V*)v.ua, st);
+      }
+      if (e != hipSuccess) return e;
+      // backward line GS from u_a + P e_c; u_a gets its sentinels back
+      Timed t(H, l, 5, st);
+      e = lgs_sweep<PT>(H, v, -1, F(l), (const V*)v.ua, UB(l), (V*)v.ua, st);
+    } else if (!ilu) {
       {
         Timed t(H, l, 4, st);
         if (split_rp(v)) {
@@ -515,6 +565,13 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
     else
       SCHK(launch_recip_diag(v.S, v.g, v.A64, v.rd64, H->err, st));
     if (cfg->smoother == SMG_SMOOTH_ILU0) SCHK(launch_ilu0_factor(v.S, v.g, v.A64, v.L64, v.U64, v.rU64, H->err, st));
+    if (cfg->smoother == SMG_SMOOTH_LGS) {
+      SCHK(launch_tri_factor(v.S, v.g, v.A64, v.tr64, v.tc64, H->err, st));
+      if (cfg->prec == SMG_FP32) {
+        SCHK(launch_to_f32(v.tr64, v.tr32, v.N, st));
+        SCHK(launch_to_f32(v.tc64, v.tc32, v.N, st));
+      }
+    }
     const long na = (long)v.S * be * v.N;
     if (cfg->prec == SMG_FP32) {
       SCHK(launch_to_f32(v.A64, v.A32, na, st));
@@ -540,7 +597,7 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
           SCHK(launch_bwf_pack_h(v.g, v.tl, dir, v.A16, v.sc16, v.rd32, v.pk[d], st));
       }
     }
-    if (bs == 1) {
+    if (bs == 1 && cfg->smoother != SMG_SMOOTH_LGS) {
       const bool ilu = cfg->smoother == SMG_SMOOTH_ILU0;
       const double* lo = ilu ? v.L64 : v.A64;
       const double* up = ilu ? v.U64 : v.A64;
@@ -885,6 +942,8 @@ smg_status smg_level_export(smg_handle h, int level, int what, void* dst, void* 
       src = v.rd32;
       bytes = sizeof(float) * nd;
       break;
+    case 7: src = v.tr64; bytes = sizeof(double) * v.N; break;
+    case 8: src = v.tc64; bytes = sizeof(double) * v.N; break;
     default: return fail(h, SMG_EINVAL, "unknown export %d", what);
   }
   if (!src) return fail(h, SMG_EINVAL, "level %d has no data %d", level, what);
@@ -928,6 +987,11 @@ static hipError_t op_presmooth_t(smg_handle_s* H, const Level& v, const void* f,
       e = sweep<typename PT::E, V>(H, v, +1, false, (const V*)f, (V*)u, nullptr, 0, nullptr, nullptr, st);
     return e;
   }
+  if (H->cfg.smoother == SMG_SMOOTH_LGS) {
+    e = launch_fill_bits<V>((V*)u, nv, sent, st);
+    if (e == hipSuccess) e = lgs_sweep<PT>(H, v, +1, (const V*)f, nullptr, (V*)u, nullptr, st);
+    return e;
+  }
   e = launch_fill_bits<V>((V*)v.h, nv, sent, st);
   if (e == hipSuccess) e = launch_fill_bits<V>((V*)u, nv, sent, st);
   if (e == hipSuccess)
@@ -960,6 +1024,15 @@ static hipError_t op_postsmooth_t(smg_handle_s* H, const Level& v, const void* f
     if (e == hipSuccess) e = launch_fill_bits<V>((V*)uout, nv, sent, st);
     if (e == hipSuccess) e = bsweep<typename PT::E, V>(H, v, -1, (const V*)v.h, (V*)uout, nullptr, 0, st);
     if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.ua, nv, sent, st);
+    return e;
+  }
+  if (H->cfg.smoother == SMG_SMOOTH_LGS) {
+    // u_old = u_in + P ec in the level's u_a buffer, then the backward line GS
+    // sweep, which gives u_a its sentinels back
+    e = hipMemcpyAsync(v.ua, uin, sizeof(V) * nv, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && ec != nullptr) e = launch_prolong_add<V>(v.g, v.cmask, 1, (const V*)ec, (V*)v.ua, st);
+    if (e == hipSuccess) e = launch_fill_bits<V>((V*)uout, nv, sent, st);
+    if (e == hipSuccess) e = lgs_sweep<PT>(H, v, -1, (const V*)f, (const V*)v.ua, (V*)uout, (V*)v.ua, st);
     return e;
   }
   if (H->cfg.smoother == SMG_SMOOTH_GS) {

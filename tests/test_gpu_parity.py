@@ -443,3 +443,73 @@ def test_small_level_sweeps_bitexact(shape, pat, prec):
     x = torch.zeros(b.size, dtype=torch.float64, device=DEV)
     res = mg.solve(T(b.ravel()), x, rtol=1e-9, maxit=200)
     assert res["status"] == 0 and res["rel_resid_true"] < 1e-9
+
+
+# line Gauss-Seidel: the five level shapes above plus columns longer than
+# one chunk (nz > 512: one column per chunk) and one-point columns
+LGS_CASES = CASES + [((16, 10, 520), 7, "full", 0), ((30, 20, 1), 19, "full", 0)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", LGS_CASES, ids=_ids)
+def test_lgs_bitexact(case, prec):
+    A, H, mg = _pair(case, smoother="lgs", prec=prec, sym=False)
+    g = workloads.rng(21)
+    for l in range(H.nlev - 1):
+        inf = H.level_info(l)
+        dims, S, cm = inf["dims"], inf["S"], inf["cmask"]
+        n = int(np.prod(dims))
+        off = workloads.offsets(S)
+        tr, tc = H.level_data(l, 7), H.level_data(l, 8)
+        for what, ref in ((7, tr), (8, tc)):
+            got = N(mg.export(l, what, torch.empty(ref.shape, dtype=torch.float64, device=DEV)))
+            assert np.array_equal(got, ref), f"Thomas factor {what} level {l}"
+        if prec == "fp64":
+            Al, dt, npt = H.level_data(l, 0), torch.float64, np.float64
+        else:
+            Al, dt, npt = H.level_data(l, 5), torch.float32, np.float32
+            tr, tc = tr.astype(np.float32), tc.astype(np.float32)
+        f = g.uniform(-1, 1, size=dims).astype(npt)
+        u = g.uniform(-1, 1, size=dims).astype(npt)
+        ec = g.uniform(-1, 1, size=oracle.coarse_dims(dims, cm)).astype(npt)
+        ug = N(mg.op_presmooth(l, T(f, dt), torch.empty(n, dtype=dt, device=DEV)))
+        ur = oracle.lgs_sweep(off, Al, tr, tc, f, np.zeros(dims, npt), 1, 1)
+        assert np.array_equal(ug, ur.ravel()), f"forward LGS level {l}: {np.abs(ug - ur.ravel()).max()}"
+        uo = N(mg.op_postsmooth(l, T(f, dt), T(u, dt), T(ec, dt), torch.empty(n, dtype=dt, device=DEV)))
+        ref = oracle.lgs_sweep(off, Al, tr, tc, f, oracle.prolong_add(u, ec, cm), -1, 0)
+        assert np.array_equal(uo, ref.ravel()), f"backward LGS level {l}: {np.abs(uo - ref.ravel()).max()}"
+
+
+@pytest.mark.parametrize("case", [CASES[1], CASES[3], CASES[5]], ids=_ids)
+def test_lgs_vcycle_and_repeat(case):
+    A, H, mg = _pair(case, smoother="lgs", sym=False)
+    dims = H.level_info(0)["dims"]
+    r = workloads.rng(9).uniform(-1, 1, size=dims)
+    zr = H.apply(r).ravel()
+    z = None
+    for _ in range(3):  # buffers and sentinels are reused across cycles
+        zi = N(mg.precondition(T(r.ravel()), torch.empty(r.size, dtype=torch.float64, device=DEV)))
+        assert np.abs(zi - zr).max() <= 1e-12 * np.abs(zr).max()
+        if z is None:
+            z = zi
+        assert np.array_equal(zi, z)
+
+
+def test_gmres_lgs_weather_like():
+    """Anisotropic weather-like 19-point operator: GMRES(30) with the line GS
+    V-cycle reaches 1e-9 in the oracle's iteration count (+-1)."""
+    shape = (48, 40, 24)
+    A, b = workloads.weather19(shape, seed=3)
+    b = b.reshape(shape)
+    H = oracle.Hierarchy(shape, 19, A, smoother="lgs", coarsen="semi_xy")
+    xr, st, itr, relr = H.gmres(b, 1e-9, 200, restart=30)
+    assert st == 0
+    for prec in ("fp64", "fp32"):
+        mg = smg.StructMG(T(A), shape, pattern=19, smoother="lgs", coarsen="semi_xy", prec=prec, gmres_restart=30,
+                          device=DEV)
+        x = torch.zeros(b.size, dtype=torch.float64, device=DEV)
+        res = mg.solve(T(b.ravel()), x, rtol=1e-9, maxit=200, krylov=30)
+        assert res["status"] == 0 and res["rel_resid_true"] < 1e-9, (prec, res)
+        if prec == "fp64":
+            assert abs(res["iters"] - itr) <= 1
+            assert np.abs(N(x) - xr.ravel()).max() / np.abs(xr).max() < 1e-6
