@@ -177,6 +177,21 @@ def extra_weather(args, smg, torch, np, dev):
                       "variants": res}), flush=True)
 
 
+def extra_weather_lgs(args, smg, torch, np, dev):
+    import workloads
+    shape = (512, 512, 64)
+    A, b = workloads.weather19(shape, seed=3)
+    W = dict(shape=shape, A=A, b=b)
+    res = _variants(args, smg, torch, np, dev, W, ("fp64", "fp32"), 1e-9, 30, pattern=19, smoother="lgs",
+                    coarsen="semi_xy", gmres_restart=30)
+    print(json.dumps({"metric": METRIC, "value": res["fp32"]["ms_per_step"], "unit": "ms", "n_gpus": 1,
+                      "steps": args.steps, "higher_is_better": False, "dtype": "f32 V-cycle / f64 GMRES",
+                      "data": "synthetic (seeded)",
+                      "config": {"workload": "weather-like 512x512x64, 19-pt, vertical 100x, GMRES(30) + line-GS "
+                                             "V-cycle (z-columns), xy-semi coarsening, tol 1e-9"},
+                      "variants": res}), flush=True)
+
+
 def extra_elasticity(args, smg, torch, np, dev):
     import workloads
     n = 128
@@ -245,7 +260,8 @@ def extra_batch(args, smg, torch, np, dev):
                       "variants": out}), flush=True)
 
 
-EXTRA = {"weather512": extra_weather, "elasticity128": extra_elasticity, "reservoir_batch256": extra_batch}
+EXTRA = {"weather512": extra_weather, "weather512_lgs": extra_weather_lgs, "elasticity128": extra_elasticity,
+         "reservoir_batch256": extra_batch}
 
 
 def main():

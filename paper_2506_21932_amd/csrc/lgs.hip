@@ -15,7 +15,8 @@
 // pattern (2d5 for 3d7, 2d9 for 3d19 / 3d27) those lie on earlier
 // hyperplanes cwx*x + y = t with cwx = 1 (3d7) or 2 (3d19, 3d27: the
 // neighbour (x-1, y+1) must come first).  Work unit: a chunk of K columns of
-// one hyperplane (K*nz <= 512 points), numbered hyperplane-major.  Persistent
+// one hyperplane (K*nz <= 256 points, one per thread, unless a column is
+// longer), numbered hyperplane-major.  Persistent
 // workgroups take chunks by atomic ticket, so every chunk's producers hold
 // smaller tickets and are already running: the grid always makes progress.
 // A workgroup
@@ -24,7 +25,8 @@
 //      sweep, plain loads); then the terms of columns of this sweep, whose
 //      values are read device-coherently from the output and awaited while
 //      they still hold the sentinel; each group in canonical order with fma.
-//      The Thomas factors of the chunk are staged in LDS with the sums;
+//      Every load of a point is issued before its first wait.  The Thomas
+//      factors of the chunk are staged in LDS with the sums;
 //   B. solves each column in one lane (forward elimination, back
 //      substitution), in the oracle's order of operations;
 //   C. stores the column device-coherently and, if asked, writes the sentinel
@@ -42,7 +44,7 @@ namespace smg {
 namespace {
 
 constexpr int LGS_NT = 256;                 // threads per workgroup
-constexpr int LGS_PTS = 512;                // points per chunk (K * nz), unless nz is larger
+constexpr int LGS_PTS = LGS_NT;             // points per chunk (K * nz), unless nz is larger
 constexpr unsigned LGS_SPIN_LIMIT = 1u << 21;
 
 __host__ __device__ constexpr int lgs_cwx(int pat) { return pat == 7 ? 1 : 2; }
@@ -89,30 +91,59 @@ __device__ inline V await_value(const V* p, V v, unsigned* err) {
   return v;
 }
 
-// Terms of one group (columns later in the order: OLD = true; columns of
-// this sweep: OLD = false) for slot S, in canonical order via the fold below.
-template <int PAT, int DIR, bool OLD, int S, class V>
-__device__ __forceinline__ void lgs_term(V& t, const V* __restrict__ A, const V* src, long N, long i, const Grid& g,
-                                         int X, int Y, int Z, unsigned* err) {
+// Loads of the term of slot S (off-column slots only), issued for all slots
+// before any wait: in-grid flag, coefficient, and the neighbour's value (from
+// before the sweep for a column later in the order, else device-coherently
+// from the output).  A neighbour outside the grid loads the row's own
+// position instead; its term is not used.
+template <int PAT, int DIR, bool ZG, int S, class V>
+__device__ __forceinline__ void lgs_load(bool (&in)[PAT], V (&av)[PAT], V (&uv)[PAT], const LgsArgs<V>& a, long N,
+                                         long i, int X, int Y, int Z) {
   constexpr int dx = pat_off(PAT, S, 0), dy = pat_off(PAT, S, 1), dz = pat_off(PAT, S, 2);
-  if constexpr (!(dx == 0 && dy == 0) && lgs_later(DIR, dx, dy) == OLD) {
-    if (in_grid(g, X + dx, Y + dy, Z + dz)) {
-      const long j = i + dx * ((long)g.ny * g.nz) + dy * (long)g.nz + dz;
-      V u;
-      if constexpr (OLD) {
-        u = src[j];
-      } else {
-        u = await_value(src + j, cload(src + j), err);
-      }
-      t = fma(-A[(long)S * N + i], u, t);
-    }
+  if constexpr (!(dx == 0 && dy == 0) && !(ZG && lgs_later(DIR, dx, dy))) {
+    in[S] = in_grid(a.g, X + dx, Y + dy, Z + dz);
+    const long j = in[S] ? i + dx * ((long)a.g.ny * a.g.nz) + dy * (long)a.g.nz + dz : i;
+    av[S] = a.A[(long)S * N + i];
+    if constexpr (lgs_later(DIR, dx, dy))
+      uv[S] = a.uold[j];
+    else
+      uv[S] = cload(a.x + j);
   }
 }
 
-template <int PAT, int DIR, bool OLD, class V, int... S>
-__device__ __forceinline__ void lgs_group(V& t, const V* __restrict__ A, const V* src, long N, long i, const Grid& g,
-                                          int X, int Y, int Z, unsigned* err, std::integer_sequence<int, S...>) {
-  (lgs_term<PAT, DIR, OLD, S, V>(t, A, src, N, i, g, X, Y, Z, err), ...);
+// Bounded wait for the value of a column of this sweep that is still the
+// sentinel.
+template <int PAT, int DIR, int S, class V>
+__device__ __forceinline__ void lgs_wait(const bool (&in)[PAT], V (&uv)[PAT], const LgsArgs<V>& a, long i) {
+  constexpr int dx = pat_off(PAT, S, 0), dy = pat_off(PAT, S, 1), dz = pat_off(PAT, S, 2);
+  if constexpr (!(dx == 0 && dy == 0) && !lgs_later(DIR, dx, dy)) {
+    if (in[S] && VBits<V>::bits(uv[S]) == VBits<V>::sent)
+      uv[S] = await_value(a.x + i + dx * ((long)a.g.ny * a.g.nz) + dy * (long)a.g.nz + dz, uv[S], a.err);
+  }
+}
+
+// t = fma(-a_s, u_nbr, t) for slot S if it belongs to the group (OLD: columns
+// later in the order) and its neighbour is in the grid.
+template <int PAT, int DIR, bool OLD, int S, class V>
+__device__ __forceinline__ void lgs_acc(V& t, const bool (&in)[PAT], const V (&av)[PAT], const V (&uv)[PAT]) {
+  constexpr int dx = pat_off(PAT, S, 0), dy = pat_off(PAT, S, 1);
+  if constexpr (!(dx == 0 && dy == 0) && lgs_later(DIR, dx, dy) == OLD) t = in[S] ? fma(-av[S], uv[S], t) : t;
+}
+
+// Right-hand side of point i: f_i, then the group of columns not yet visited
+// (omitted for the zero initial guess), then the columns of this sweep, each
+// in canonical order.
+template <int PAT, int DIR, bool ZG, class V, int... S>
+__device__ __forceinline__ V lgs_rhs(const LgsArgs<V>& a, long N, long i, int X, int Y, int Z,
+                                     std::integer_sequence<int, S...>) {
+  bool in[PAT];
+  V av[PAT], uv[PAT];
+  V t = a.f[i];
+  (lgs_load<PAT, DIR, ZG, S, V>(in, av, uv, a, N, i, X, Y, Z), ...);
+  if constexpr (!ZG) (lgs_acc<PAT, DIR, true, S, V>(t, in, av, uv), ...);
+  (lgs_wait<PAT, DIR, S, V>(in, uv, a, i), ...);
+  (lgs_acc<PAT, DIR, false, S, V>(t, in, av, uv), ...);
+  return t;
 }
 
 __device__ inline unsigned lgs_take_ticket(unsigned* ctr) {
@@ -156,35 +187,59 @@ __global__ __launch_bounds__(LGS_NT) void k_lgs(LgsArgs<V> a) {
     int x0, nxr;
     lgs_xrange(g, CWX, t, &x0, &nxr);
     const int ncol = nxr - j * K < K ? nxr - j * K : K;  // columns of this chunk (may be <= 0)
-    // A. right-hand sides and staged factors
+    // A. right-hand sides and staged factors (one point per thread unless
+    // the column is longer than a workgroup)
     for (int q = threadIdx.x; q < ncol * nz; q += LGS_NT) {
       const int c = q / nz, Z = q - c * nz;
       const int X = x0 + j * K + c, Y = t - CWX * X;
       const long i = ((long)X * g.ny + Y) * nz + Z;
-      V s = a.f[i];
-      if constexpr (!ZG)
-        lgs_group<PAT, DIR, true, V>(s, a.A, a.uold, N, i, g, X, Y, Z, a.err, std::make_integer_sequence<int, PAT>{});
-      lgs_group<PAT, DIR, false, V>(s, a.A, a.x, N, i, g, X, Y, Z, a.err, std::make_integer_sequence<int, PAT>{});
       const int o = c * LD + Z;
-      ld[o] = s;
       la[o] = Z > 0 ? a.A[(long)SLO * N + i] : V(0);
       lr[o] = a.rden[i];
       lc[o] = a.cp[i];
+      ld[o] = lgs_rhs<PAT, DIR, ZG, V>(a, N, i, X, Y, Z, std::make_integer_sequence<int, PAT>{});
     }
     __syncthreads();
-    // B. Thomas solve, one lane per column
+    // B. Thomas solve, one lane per column, in blocks of 8 points whose LDS
+    // reads are issued together.  d'_0 = t_0 * rden_0 comes out of the same
+    // formula: the stored coupling to z-1 at z = 0 is +0 and d' starts at +0,
+    // so fma(-0, +0, t_0) = t_0 exactly.
     if ((int)threadIdx.x < ncol) {
       const int b = (int)threadIdx.x * LD;
-      V dp = ld[b] * lr[b];
-      ld[b] = dp;
-      for (int Z = 1; Z < nz; ++Z) {
-        dp = fma(-la[b + Z], dp, ld[b + Z]) * lr[b + Z];
-        ld[b + Z] = dp;
+      V dp = V(0);
+      for (int z0 = 0; z0 < nz; z0 += 8) {
+        V a8[8], r8[8], d8[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int z = z0 + k < nz ? z0 + k : nz - 1;
+          a8[k] = la[b + z];
+          r8[k] = lr[b + z];
+          d8[k] = ld[b + z];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (z0 + k < nz) {
+            dp = fma(-a8[k], dp, d8[k]) * r8[k];
+            ld[b + z0 + k] = dp;
+          }
+        }
       }
       V xv = dp;
-      for (int Z = nz - 2; Z >= 0; --Z) {
-        xv = fma(-lc[b + Z], xv, ld[b + Z]);
-        ld[b + Z] = xv;
+      for (int z1 = nz - 2; z1 >= 0; z1 -= 8) {
+        V c8[8], d8[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int z = z1 - k >= 0 ? z1 - k : 0;
+          c8[k] = lc[b + z];
+          d8[k] = ld[b + z];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (z1 - k >= 0) {
+            xv = fma(-c8[k], xv, d8[k]);
+            ld[b + z1 - k] = xv;
+          }
+        }
       }
     }
     __syncthreads();
