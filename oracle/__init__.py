@@ -70,6 +70,8 @@ def _declare(L):
     L.orc_rap_chains.restype = _i
     L.orc_ilu0.argtypes = [_i, _i, _i, _i, _ip, _dp, _dp, _dp, _dp]
     L.orc_ilu0.restype = _i
+    L.orc_ilu0_mask.argtypes = [_i, _i, _i, _i, _ip, _dp, _i, _ip, _dp, _dp, _dp]
+    L.orc_ilu0_mask.restype = _i
     L.orc_tri_factor.argtypes = [_i, _i, _i, _i, _ip, _dp, _dp, _dp]
     L.orc_tri_factor.restype = _i
     L.orc_lu_factor.argtypes = [_i, _dp, _ip]
@@ -82,7 +84,7 @@ def _declare(L):
     L.orc_f32_to_f16.restype = C.c_uint16
     L.orc_f16_to_f32.argtypes = [C.c_uint16]
     L.orc_f16_to_f32.restype = C.c_float
-    L.orc_mg_create.argtypes = [_i, _i, _i, _i, _i, _dp, _i, _i, _i, _i, _i]
+    L.orc_mg_create.argtypes = [_i, _i, _i, _i, _i, _dp, _i, _i, _i, _i, _i, _i]
     L.orc_mg_create.restype = C.c_void_p
     L.orc_mg_destroy.argtypes = [C.c_void_p]
     L.orc_mg_nlev.argtypes = [C.c_void_p]
@@ -254,6 +256,21 @@ def ilu0(off, A, shape):
     return L, U, rU
 
 
+def ilu0_mask(off, A, offm, shape):
+    """ILU(0) of A (pattern off) on the mask offm: factors on offm's slots."""
+    off = _c(off, np.int32)
+    offm = _c(offm, np.int32)
+    Sm = offm.shape[0]
+    N = int(np.prod(shape))
+    L = np.zeros((Sm, N))
+    U = np.zeros((Sm, N))
+    rU = np.zeros(N)
+    if lib().orc_ilu0_mask(*_dims(shape), off.shape[0], off.ravel(), _c(A, np.float64).ravel(), Sm, offm.ravel(),
+                           L.ravel(), U.ravel(), rU):
+        raise ValueError("zero pivot")
+    return L, U, rU
+
+
 def dense(off, A, shape, bs=1):
     off = _c(off, np.int32)
     n = int(np.prod(shape)) * bs
@@ -289,13 +306,13 @@ class Hierarchy:
     """Oracle multigrid hierarchy built from the finest matrix (FP64 setup)."""
 
     def __init__(self, shape, pattern_pts, A0, block=1, smoother="gs", coarsen="full", semi_levels=0,
-                 prec="fp64", max_coarse=8192):
+                 prec="fp64", max_coarse=8192, ilu_mask=0):
         self.shape = tuple(int(v) for v in shape)
         self.bs = int(block)
         self._A0 = _c(A0, np.float64)
         h = lib().orc_mg_create(*self.shape, int(pattern_pts), self.bs, self._A0.ravel(),
                                 SMOOTHER[smoother], 1 if coarsen == "semi_xy" else 0, int(semi_levels),
-                                PREC[prec], int(max_coarse))
+                                PREC[prec], int(max_coarse), int(ilu_mask))
         if not h:
             raise ValueError("oracle hierarchy setup failed")
         self.h = C.c_void_p(h)
@@ -312,16 +329,18 @@ class Hierarchy:
         return lib().orc_mg_nlev(self.h)
 
     def level_info(self, l):
-        info = np.zeros(5, np.int32)
+        info = np.zeros(6, np.int32)
         lib().orc_mg_level_info(self.h, l, info)
-        return {"dims": tuple(int(v) for v in info[:3]), "S": int(info[3]), "cmask": int(info[4])}
+        return {"dims": tuple(int(v) for v in info[:3]), "S": int(info[3]), "cmask": int(info[4]),
+                "Sm": int(info[5])}
 
     def level_data(self, l, what):
         inf = self.level_info(l)
         N = int(np.prod(inf["dims"]))
         be = self.bs * self.bs
         S = inf["S"]
-        sizes = {0: (S * be, N), 1: ((9 if self.bs == 3 else 1), N), 2: (S, N), 3: (S, N), 4: (1, N),
+        Sm = inf["Sm"] or S
+        sizes = {0: (S * be, N), 1: ((9 if self.bs == 3 else 1), N), 2: (Sm, N), 3: (Sm, N), 4: (1, N),
                  5: (S * be, N), 6: ((9 if self.bs == 3 else 1), N), 7: (1, N), 8: (1, N)}
         dt = np.float32 if what in (5, 6) else np.float64
         out = np.zeros(sizes[what], dt)

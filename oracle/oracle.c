@@ -219,29 +219,34 @@ int orc_rap_chains(int S, const int* off, int cmask, int n_index, int* out, int 
 }
 
 /* ---- ILU(0) factorisation (Sec. 4.2.3 mask flexibility; Sec. 4.4 ILU) ---
- * Doolittle (unit lower factor), IKJ order, restricted to the pattern mask.
+ * Doolittle (unit lower factor), IKJ order, restricted to a mask (offsets
+ * off[0..S), which may differ from A's pattern offA[0..SA): entries of A
+ * outside the mask are dropped, fill inside the mask is kept).
  * Row i: w = row i of A on the mask; for each lower slot s in canonical
  * order (= ascending column k = i+off_s): w[s] = w[s] / U_c[k]; then for
  * each upper slot t of row k in canonical order with j = k+off_t in the grid
  * and off_s+off_t in the mask: w[slot] = fma(-w[s], U_t[k], w[slot]).
  * The lower slots of w go to L, centre and upper slots to U; rU = 1/U_c.
  * Returns 0, or -1 on a zero pivot. */
-int orc_ilu0(int nx, int ny, int nz, int S, const int* off, const double* A, double* L, double* U,
-             double* rU) {
+int orc_ilu0_mask(int nx, int ny, int nz, int SA, const int* offA, const double* A, int S, const int* off,
+                  double* L, double* U, double* rU) {
   long N = (long)nx * ny * nz;
-  int slot[27], c = -1;
-  for (int k = 0; k < 27; ++k) slot[k] = -1;
+  int slot[27], aslot[27], c = -1;
+  for (int k = 0; k < 27; ++k) slot[k] = aslot[k] = -1;
   for (int s = 0; s < S; ++s) {
     slot[(off[3 * s] + 1) * 9 + (off[3 * s + 1] + 1) * 3 + (off[3 * s + 2] + 1)] = s;
     if (off[3 * s] == 0 && off[3 * s + 1] == 0 && off[3 * s + 2] == 0) c = s;
   }
+  for (int s = 0; s < SA; ++s) aslot[(offA[3 * s] + 1) * 9 + (offA[3 * s + 1] + 1) * 3 + (offA[3 * s + 2] + 1)] = s;
   double w[27];
   for (long i = 0; i < N; ++i) {
     int X = (int)(i / ((long)ny * nz)), Y = (int)((i / nz) % ny), Z = (int)(i % nz);
     for (int s = 0; s < S; ++s) {
+      /* row i of A on the mask: zero where A's pattern has no such offset */
       int a = X + off[3 * s], b = Y + off[3 * s + 1], cc = Z + off[3 * s + 2];
       int in = !(a < 0 || a >= nx || b < 0 || b >= ny || cc < 0 || cc >= nz);
-      w[s] = in ? A[s * N + i] : 0.0;
+      int sa = aslot[(off[3 * s] + 1) * 9 + (off[3 * s + 1] + 1) * 3 + (off[3 * s + 2] + 1)];
+      w[s] = in && sa >= 0 ? A[sa * N + i] : 0.0;
     }
     for (int s = 0; s < c; ++s) {
       int a = X + off[3 * s], b = Y + off[3 * s + 1], cc = Z + off[3 * s + 2];
@@ -266,6 +271,12 @@ int orc_ilu0(int nx, int ny, int nz, int S, const int* off, const double* A, dou
     rU[i] = 1.0 / w[c];
   }
   return 0;
+}
+
+/* ILU(0) on the matrix's own pattern. */
+int orc_ilu0(int nx, int ny, int nz, int S, const int* off, const double* A, double* L, double* U,
+             double* rU) {
+  return orc_ilu0_mask(nx, ny, nz, S, off, A, S, off, L, U, rU);
 }
 
 /* ---- dense LU with partial pivoting (coarsest level) ------------------ */
@@ -398,6 +409,7 @@ typedef struct {
   int nx, ny, nz, S, cmask;
   long N;
   int off[81];
+  int Sm, offm[81]; /* ILU(0) mask (the level's own pattern unless chosen) */
   double *A, *rd, *L, *U, *rU;           /* FP64 level data */
   double *tr, *tc;                       /* Thomas factors rden, cp (line GS) */
   float *A32, *rd32, *L32, *U32, *rU32;  /* truncated level data */
@@ -469,12 +481,15 @@ void orc_mg_destroy(omg* mg);
  * pattern: 7/19/27 (level 0); coarse levels are 27-point.  bs: 1 or 3.
  * smoother: 0 = symmetric GS, 1 = ILU(0), 2 = symmetric line GS over
  * z-columns (scalar systems; FP64 and FP32).  prec: 0 FP64, 1 FP32,
- * 2 FP16 row-scaled.  A0 is copied; out-of-grid couplings are zeroed.
+ * 2 FP16 row-scaled.  ilu_mask: 0 = ILU(0) on each level's own pattern, or
+ * 7 / 19 / 27 = that mask for the finest matrix (coarse levels keep their
+ * own 27-point pattern).  A0 is copied; out-of-grid couplings are zeroed.
  * Returns NULL on error (zero pivot, coarsest level too large).
  */
 omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0, int smoother, int semi_mode,
-                   int semi_levels, int prec, int max_coarse) {
+                   int semi_levels, int prec, int max_coarse, int ilu_mask) {
   if (smoother == 2 && (bs != 1 || prec == 2)) return NULL;
+  if (ilu_mask != 0 && (smoother != 1 || (ilu_mask != 7 && ilu_mask != 19 && ilu_mask != 27))) return NULL;
   omg* mg = (omg*)calloc(1, sizeof(omg));
   mg->bs = bs;
   mg->smoother = smoother;
@@ -532,10 +547,14 @@ omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0
       v->rd = (double*)malloc(sizeof(double) * v->N);
       for (long i = 0; i < v->N; ++i) v->rd[i] = 1.0 / v->A[c * v->N + i];
       if (smoother == 1) {
-        v->L = (double*)malloc(sizeof(double) * v->S * v->N);
-        v->U = (double*)malloc(sizeof(double) * v->S * v->N);
+        v->Sm = ilu_mask && l == 0 ? orc_pattern(ilu_mask, v->offm) : orc_pattern(v->S, v->offm);
+        v->L = (double*)malloc(sizeof(double) * v->Sm * v->N);
+        v->U = (double*)malloc(sizeof(double) * v->Sm * v->N);
         v->rU = (double*)malloc(sizeof(double) * v->N);
-        if (orc_ilu0(v->nx, v->ny, v->nz, v->S, v->off, v->A, v->L, v->U, v->rU)) { orc_mg_destroy(mg); return NULL; }
+        if (orc_ilu0_mask(v->nx, v->ny, v->nz, v->S, v->off, v->A, v->Sm, v->offm, v->L, v->U, v->rU)) {
+          orc_mg_destroy(mg);
+          return NULL;
+        }
       }
       if (smoother == 2) {
         v->tr = (double*)malloc(sizeof(double) * v->N);
@@ -548,8 +567,8 @@ omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0
       v->A32 = prec == 2 ? to_f16_rowscaled(v->A, v->N, v->S, bs) : to_f32(v->A, na);
       v->rd32 = to_f32(v->rd, (bs == 3 ? 9 : 1) * v->N);
       if (smoother == 1 && bs == 1) {
-        v->L32 = to_f32(v->L, (long)v->S * v->N);
-        v->U32 = to_f32(v->U, (long)v->S * v->N);
+        v->L32 = to_f32(v->L, (long)v->Sm * v->N);
+        v->U32 = to_f32(v->U, (long)v->Sm * v->N);
         v->rU32 = to_f32(v->rU, v->N);
       }
       if (smoother == 2) {
@@ -597,10 +616,10 @@ void orc_mg_destroy(omg* mg) {
 
 int orc_mg_nlev(const omg* mg) { return mg->nlev; }
 
-/* dims[0..2], S, cmask of level l */
+/* dims[0..2], S, cmask, ILU mask points of level l */
 void orc_mg_level_info(const omg* mg, int l, int* info) {
   const olev* v = &mg->lev[l];
-  info[0] = v->nx; info[1] = v->ny; info[2] = v->nz; info[3] = v->S; info[4] = v->cmask;
+  info[0] = v->nx; info[1] = v->ny; info[2] = v->nz; info[3] = v->S; info[4] = v->cmask; info[5] = v->Sm;
 }
 
 /* Copies out level data: what = 0 A, 1 rd (or block Dinv), 2 L, 3 U, 4 rU,
@@ -611,8 +630,8 @@ void orc_mg_level_data(const omg* mg, int l, int what, void* out) {
   switch (what) {
     case 0: memcpy(out, v->A, sizeof(double) * v->S * be * v->N); break;
     case 1: memcpy(out, v->rd, sizeof(double) * (mg->bs == 3 ? 9 : 1) * v->N); break;
-    case 2: memcpy(out, v->L, sizeof(double) * v->S * v->N); break;
-    case 3: memcpy(out, v->U, sizeof(double) * v->S * v->N); break;
+    case 2: memcpy(out, v->L, sizeof(double) * v->Sm * v->N); break;
+    case 3: memcpy(out, v->U, sizeof(double) * v->Sm * v->N); break;
     case 4: memcpy(out, v->rU, sizeof(double) * v->N); break;
     case 5: memcpy(out, v->A32, sizeof(float) * v->S * be * v->N); break;
     case 6: memcpy(out, v->rd32, sizeof(float) * (mg->bs == 3 ? 9 : 1) * v->N); break;

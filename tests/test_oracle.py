@@ -187,6 +187,48 @@ def test_ilu0_property(npts, shape):
     assert np.allclose(LU @ z.ravel(), r.ravel(), rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("apat", [7, 19, 27])
+@pytest.mark.parametrize("mpat", [7, 19, 27])
+def test_ilu0_mask_property(apat, mpat):
+    """ILU(0) on a mask other than A's pattern (Sec. 4.2.3): (L U)_ij = a_ij
+    at every position of the mask, with a_ij = 0 where A has no such offset
+    (fill kept) and A's entries outside the mask dropped."""
+    shape = (4, 3, 5)
+    off = workloads.offsets(apat)
+    offm = workloads.offsets(mpat)
+    A = workloads.random_sgdia(shape, apat, seed=23, symmetric=False)
+    L, U, rU = oracle.ilu0_mask(off, A, offm, shape)
+    n = int(np.prod(shape))
+    Lm = helpers.dense_from_sgdia(L, offm, shape) + np.eye(n)
+    Um = helpers.dense_from_sgdia(U, offm, shape)
+    M = helpers.dense_from_sgdia(A, off, shape)
+    mask = helpers.dense_from_sgdia(np.ones((mpat, n)), offm, shape) != 0
+    LU = Lm @ Um
+    assert np.abs((LU - M)[mask]).max() <= 1e-14 * np.abs(M).max()
+    assert np.allclose(rU, 1.0 / np.diag(Um), rtol=0, atol=0)
+    r = workloads.rng(2).uniform(-1, 1, size=shape)
+    z = oracle.tri_solve(offm, U, rU, oracle.tri_solve(offm, L, None, r, 0), 1)
+    assert np.allclose(LU @ z.ravel(), r.ravel(), rtol=0, atol=1e-13)
+    if mpat == apat:
+        L0, U0, rU0 = oracle.ilu0(off, A, shape)
+        assert np.array_equal(L, L0) and np.array_equal(U, U0) and np.array_equal(rU, rU0)
+
+
+def test_ilu_mask_more_fill_fewer_iterations():
+    """A 3d7 operator smoothed with ILU(0) on its own mask, on 3d19 and on
+    3d27: more fill-in gives a stronger smoother (fewer PCG iterations)."""
+    shape = (24, 24, 24)
+    A, b = workloads.diffusion7(shape, seed=2, nspheres=2, rmin=3.0, rmax=6.0)
+    its = []
+    for m in (0, 19, 27):
+        H = oracle.Hierarchy(shape, 7, A, smoother="ilu0", ilu_mask=m)
+        assert H.level_info(0)["Sm"] == (m or 7) and H.level_info(1)["Sm"] == 27
+        x, st, it, rel = H.pcg(b.reshape(shape), 1e-9, 200)
+        assert st == 0 and rel < 1e-9
+        its.append(it)
+    assert its[0] > its[1] >= its[2], its
+
+
 def test_ilu0_exact_on_tridiagonal():
     """On a 1 x 1 x n grid the 3d7 operator is tridiagonal and ILU(0) = LU."""
     off = workloads.offsets(7)
