@@ -168,12 +168,13 @@ def extra_weather(args, smg, torch, np, dev):
     A, b = workloads.weather19(shape, seed=3)
     W = dict(shape=shape, A=A, b=b)
     res = _variants(args, smg, torch, np, dev, W, ("fp64", "fp32"), 1e-9, 30, pattern=19, smoother="ilu0",
-                    coarsen="semi_xy", gmres_restart=30)
+                    coarsen="semi_xy", gmres_restart=30, ilu_mask=args.ilu_mask)
+    mask = f" on a {args.ilu_mask}-point mask" if args.ilu_mask else ""
     print(json.dumps({"metric": METRIC, "value": res["fp32"]["ms_per_step"], "unit": "ms", "n_gpus": 1,
                       "steps": args.steps, "higher_is_better": False, "dtype": "f32 V-cycle / f64 GMRES",
                       "data": "synthetic (seeded)",
-                      "config": {"workload": "weather-like 512x512x64, 19-pt, vertical 100x, GMRES(30) + ILU(0) "
-                                             "V-cycle, xy-semi coarsening, tol 1e-9"},
+                      "config": {"workload": "weather-like 512x512x64, 19-pt, vertical 100x, GMRES(30) + ILU(0)"
+                                             f"{mask} V-cycle, xy-semi coarsening, tol 1e-9"},
                       "variants": res}), flush=True)
 
 
@@ -273,6 +274,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 / FP16 V-cycle variants")
     ap.add_argument("--breakdown", action="store_true", help="print per-kernel table to stderr")
+    ap.add_argument("--ilu-mask", type=int, default=0, choices=(0, 7, 19, 27),
+                    help="weather512: ILU(0) mask of the finest matrix (0: its own 19-point pattern)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))

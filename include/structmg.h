@@ -72,6 +72,10 @@ typedef struct {
                           and the coarsest solve stay FP64 */
   int max_coarse;      /* bound on the unknowns of the dense coarsest level (0: 4096) */
   int gmres_restart;   /* Krylov basis reserved in the workspace for GMRES (0: none) */
+  int ilu_mask;        /* ILU(0) only: positions kept by the factorisation of the finest
+                          matrix (Sec. 4.2.3 ILU masks): 0 = its own pattern, or the
+                          7 / 19 / 27-point mask (fewer or more fill-ins than the
+                          matrix pattern); coarse levels keep their 27-point pattern */
 } smg_config;
 
 typedef struct {
@@ -134,7 +138,8 @@ int smg_num_levels(smg_handle h);
 /* Copies level data into device memory dst (stream-ordered):
  * what = 0 matrix (FP64, S*block^2*N), 1 reciprocal diagonal (FP64, N) or
  * 3x3 diagonal-block inverses (FP64, 9*N), 2 ILU lower factor (FP64, S*N),
- * 3 ILU upper factor (FP64, S*N), 4 reciprocal of the ILU diagonal (FP64, N),
+ * 3 ILU upper factor (FP64, S*N; on the finest level S is the ILU mask's
+ * points when cfg.ilu_mask is set), 4 reciprocal of the ILU diagonal (FP64, N),
  * 5 V-cycle matrix (FP32; FP16 storage is expanded to scale*float(h)),
  * 6 V-cycle reciprocal diagonal / block inverses (FP32), 7 line GS Thomas
  * reciprocal pivots (FP64, N), 8 line GS Thomas c/pivot (FP64, N). */

@@ -210,7 +210,31 @@ __device__ __forceinline__ bool ilu_point(const Grid& g, int tau, int x0, int nx
   return Z >= 0 && Z < g.nz;
 }
 
-template <int PAT>
+// Row i of A on the factor mask PAT: A's coefficient of the same offset in
+// its own pattern PA where there is one and the neighbour is in the grid,
+// else 0 (a mask larger than A's pattern keeps fill there, a smaller one
+// drops A's other entries).
+template <int PAT, int PA, int S>
+__device__ __forceinline__ void ilu_init(double (&w)[PAT], const double* __restrict__ A, long N, long i,
+                                         const Grid& g, int X, int Y, int Z) {
+  constexpr int dx = pat_off(PAT, S, 0), dy = pat_off(PAT, S, 1), dz = pat_off(PAT, S, 2);
+  constexpr int sa = pat_slot(PA, dx, dy, dz);
+  if constexpr (sa >= 0) {
+    const double a = A[(long)sa * N + i];  // row i's own slot: always in bounds
+    w[S] = in_grid(g, X + dx, Y + dy, Z + dz) ? a : 0.0;
+  } else {
+    w[S] = 0.0;
+  }
+}
+
+template <int PAT, int PA, int... S>
+__device__ __forceinline__ void ilu_init_row(double (&w)[PAT], const double* __restrict__ A, long N, long i,
+                                             const Grid& g, int X, int Y, int Z, std::integer_sequence<int, S...>) {
+  (ilu_init<PAT, PA, S>(w, A, N, i, g, X, Y, Z), ...);
+}
+
+// PAT: the factor mask (its hyperplanes order the rows); PA: A's pattern.
+template <int PAT, int PA>
 __global__ __launch_bounds__(ILU_WG) void k_ilu0_plane(Grid g, int tau, int x0, int nxr,
                                                        const double* __restrict__ A, double* __restrict__ L,
                                                        double* __restrict__ U, double* __restrict__ rU,
@@ -222,12 +246,7 @@ __global__ __launch_bounds__(ILU_WG) void k_ilu0_plane(Grid g, int tau, int x0, 
   if (!ilu_point<WX, WY>(g, tau, x0, nxr, kb, (int)(blockIdx.x * (unsigned)ILU_WG + threadIdx.x), X, Y, Z)) return;
   const long i = ((long)X * g.ny + Y) * g.nz + Z;
   double w[PAT];
-#pragma unroll
-  for (int s = 0; s < PAT; ++s) {
-    const bool in = in_grid(g, X + pat_off(PAT, s, 0), Y + pat_off(PAT, s, 1), Z + pat_off(PAT, s, 2));
-    const double a = A[(long)s * N + i];  // row i's own slot: always in bounds
-    w[s] = in ? a : 0.0;
-  }
+  ilu_init_row<PAT, PA>(w, A, N, i, g, X, Y, Z, std::make_integer_sequence<int, PAT>{});
   ilu_rows<PAT>(w, g, X, Y, Z, i, U, std::make_integer_sequence<int, C>{});
 #pragma unroll
   for (int s = 0; s < PAT; ++s) {
@@ -238,33 +257,43 @@ __global__ __launch_bounds__(ILU_WG) void k_ilu0_plane(Grid g, int tau, int x0, 
   rU[i] = 1.0 / w[C];
 }
 
-hipError_t launch_ilu0_factor(int pat, const Grid& g, const double* A, double* L, double* U, double* rU,
-                              unsigned* err, hipStream_t st) {
-  if (pat != 7 && pat != 19 && pat != 27) return hipErrorInvalidValue;
-  const int wx = hp_wx(pat), wy = hp_wy(pat);
+template <int PAT, int PA>
+static hipError_t launch_ilu0_t(const Grid& g, const double* A, double* L, double* U, double* rU, unsigned* err,
+                                hipStream_t st) {
+  constexpr int wx = hp_wx(PAT), wy = hp_wy(PAT);
   const int D = wx * (g.nx - 1) + wy * (g.ny - 1) + g.nz;
   const long N = g.N();
-  hipError_t e0 = launch_fill_bits<double>(U + (long)pat * N, 1, 0.0, st);
-  if (e0 == hipSuccess) e0 = launch_fill_bits<double>(U + (long)pat * N + 1, 1, 1.0, st);
-  if (e0 != hipSuccess) return e0;
+  hipError_t e = launch_fill_bits<double>(U + (long)PAT * N, 1, 0.0, st);
+  if (e == hipSuccess) e = launch_fill_bits<double>(U + (long)PAT * N + 1, 1, 1.0, st);
+  if (e != hipSuccess) return e;
   const int kb = ilu_band(g.nz, wy);
   for (int tau = 0; tau < D; ++tau) {
     int x0, nxr;
     ilu_xrange(g, wx, wy, tau, &x0, &nxr);
     if (nxr <= 0) continue;
     const dim3 grid((unsigned)((nxr * kb + ILU_WG - 1) / ILU_WG)), blk(ILU_WG);
-    if (pat == 7)
-      hipLaunchKernelGGL((k_ilu0_plane<7>), grid, blk, 0, st, g, tau, x0, nxr, A, L, U, rU, err);
-    else if (pat == 19)
-      hipLaunchKernelGGL((k_ilu0_plane<19>), grid, blk, 0, st, g, tau, x0, nxr, A, L, U, rU, err);
-    else if (pat == 27)
-      hipLaunchKernelGGL((k_ilu0_plane<27>), grid, blk, 0, st, g, tau, x0, nxr, A, L, U, rU, err);
-    else
-      return hipErrorInvalidValue;
-    hipError_t e = hipGetLastError();
+    hipLaunchKernelGGL((k_ilu0_plane<PAT, PA>), grid, blk, 0, st, g, tau, x0, nxr, A, L, U, rU, err);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+template <int PAT>
+static hipError_t launch_ilu0_m(int pa, const Grid& g, const double* A, double* L, double* U, double* rU,
+                                unsigned* err, hipStream_t st) {
+  if (pa == 7) return launch_ilu0_t<PAT, 7>(g, A, L, U, rU, err, st);
+  if (pa == 19) return launch_ilu0_t<PAT, 19>(g, A, L, U, rU, err, st);
+  if (pa == 27) return launch_ilu0_t<PAT, 27>(g, A, L, U, rU, err, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_ilu0_factor(int pa, int pm, const Grid& g, const double* A, double* L, double* U, double* rU,
+                              unsigned* err, hipStream_t st) {
+  if (pm == 7) return launch_ilu0_m<7>(pa, g, A, L, U, rU, err, st);
+  if (pm == 19) return launch_ilu0_m<19>(pa, g, A, L, U, rU, err, st);
+  if (pm == 27) return launch_ilu0_m<27>(pa, g, A, L, U, rU, err, st);
+  return hipErrorInvalidValue;
 }
 
 __global__ __launch_bounds__(256) void k_to_f32(const double* __restrict__ s, float* __restrict__ d, long n) {

@@ -16,6 +16,7 @@ constexpr int MAXLEV = 40;
 struct Level {
   Grid g;
   int S = 0;      // pattern points
+  int Ssw = 0;    // pattern of the triangular sweeps and their data (ILU: the factor mask; else S)
   int cmask = 0;  // axes coarsened to reach the next level (0: coarsest)
   long N = 0;
   double *A64 = nullptr, *rd64 = nullptr, *L64 = nullptr, *U64 = nullptr, *rU64 = nullptr;

@@ -205,9 +205,10 @@ hipError_t launch_bwf_pack_h(const Grid& g, const WfTiling& tl, int dir, const _
 hipError_t launch_copy_masked(int pat, const Grid& g, int be, const double* src, double* dst, hipStream_t st);
 hipError_t launch_recip_diag(int pat, const Grid& g, const double* A, double* rd, unsigned* err, hipStream_t st);
 hipError_t launch_block_dinv(const Grid& g, const double* A, double* Dinv, unsigned* err, hipStream_t st);
-// ILU(0) factors; U holds pat*N + 2 doubles (the last two are set to {0, 1}
-// and read where a coupling or pivot is unused)
-hipError_t launch_ilu0_factor(int pat, const Grid& g, const double* A, double* L, double* U, double* rU,
+// ILU(0) factors on the mask pattern pm of A (pattern pa); L and U hold the
+// mask's slots, U holds pm*N + 2 doubles (the last two are set to {0, 1} and
+// read where a coupling or pivot is unused)
+hipError_t launch_ilu0_factor(int pa, int pm, const Grid& g, const double* A, double* L, double* U, double* rU,
                               unsigned* err, hipStream_t st);
 // Line Gauss-Seidel over z-columns (lgs.hip).  Chunks of K columns of one
 // hyperplane are the work units (M chunks per hyperplane, T hyperplanes);

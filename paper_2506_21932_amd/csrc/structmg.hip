@@ -104,6 +104,9 @@ const char* check_cfg(const smg_config* c) {
   if (c->semi_levels < 0) return "semi_levels must be >= 0";
   if (c->prec < SMG_FP64 || c->prec > SMG_FP16_ROWSCALE) return "unknown precision";
   if (c->max_coarse < 0 || c->gmres_restart < 0 || c->gmres_restart > 200) return "bad max_coarse / gmres_restart";
+  if (c->ilu_mask != 0 && c->ilu_mask != 7 && c->ilu_mask != 19 && c->ilu_mask != 27)
+    return "ilu_mask must be 0, 7, 19 or 27";
+  if (c->ilu_mask != 0 && c->smoother != SMG_SMOOTH_ILU0) return "ilu_mask applies to the ILU(0) smoother only";
   return nullptr;
 }
 
@@ -123,6 +126,7 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
     v.g = Grid{n[0], n[1], n[2]};
     v.N = v.g.N();
     v.S = nlev == 0 ? cfg.pattern : 27;
+    v.Ssw = cfg.smoother == SMG_SMOOTH_ILU0 && nlev == 0 && cfg.ilu_mask ? cfg.ilu_mask : v.S;
     v.cmask = next_cmask(nlev, n, cfg.coarsen == SMG_COARSEN_SEMI_XY, cfg.semi_levels);
     ++nlev;
     if (v.cmask == 0 || nlev == MAXLEV) {
@@ -149,8 +153,8 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
     vec(&v.h);
     v.rd64 = ar.take<double>((size_t)(bs == 3 ? 9 : 1) * N);
     if (cfg.smoother == SMG_SMOOTH_ILU0) {
-      v.L64 = ar.take<double>((size_t)v.S * N);
-      v.U64 = ar.take<double>((size_t)v.S * N + 2);  // + the factorisation's {0, 1}
+      v.L64 = ar.take<double>((size_t)v.Ssw * N);
+      v.U64 = ar.take<double>((size_t)v.Ssw * N + 2);  // + the factorisation's {0, 1}
       v.rU64 = ar.take<double>((size_t)N);
       vec(&v.y1);
       vec(&v.y2);
@@ -167,8 +171,8 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
         v.tc32 = ar.take<float>((size_t)N);
       }
     } else if (bs == 1) {
-      wf_tiling(v.g, v.S, &v.tl);
-      const size_t pbytes = (size_t)wf_pack_count(v.S, eb) * 16 * v.tl.nsk;
+      wf_tiling(v.g, v.Ssw, &v.tl);
+      const size_t pbytes = (size_t)wf_pack_count(v.Ssw, eb) * 16 * v.tl.nsk;
       v.pk[0] = ar.take<char>(pbytes);
       v.pk[1] = ar.take<char>(pbytes);
       if (cfg.prec == SMG_FP16_ROWSCALE) v.psd = ar.take<float>((size_t)2 * v.tl.nsk);
@@ -189,8 +193,8 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
       v.A32 = ar.take<float>((size_t)v.S * be * N);
       v.rd32 = ar.take<float>((size_t)(bs == 3 ? 9 : 1) * N);
       if (cfg.smoother == SMG_SMOOTH_ILU0) {
-        v.L32 = ar.take<float>((size_t)v.S * N);
-        v.U32 = ar.take<float>((size_t)v.S * N);
+        v.L32 = ar.take<float>((size_t)v.Ssw * N);
+        v.U32 = ar.take<float>((size_t)v.Ssw * N);
         v.rU32 = ar.take<float>((size_t)N);
       }
     } else if (cfg.prec == SMG_FP16_ROWSCALE) {
@@ -251,7 +255,7 @@ hipError_t sweep(smg_handle_s* H, const Level& L, int dir, bool unitd, const V* 
   a.addout = addout;
   a.ctr = H->ctr;
   a.err = H->err;
-  return launch_wavefront<E>(L.S, dir, unitd, addout != nullptr, a, st);
+  return launch_wavefront<E>(L.Ssw, dir, unitd, addout != nullptr, a, st);
 }
 
 template <class E, class V>
@@ -564,7 +568,8 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
       SCHK(launch_block_dinv(v.g, v.A64, v.rd64, H->err, st));
     else
       SCHK(launch_recip_diag(v.S, v.g, v.A64, v.rd64, H->err, st));
-    if (cfg->smoother == SMG_SMOOTH_ILU0) SCHK(launch_ilu0_factor(v.S, v.g, v.A64, v.L64, v.U64, v.rU64, H->err, st));
+    if (cfg->smoother == SMG_SMOOTH_ILU0)
+      SCHK(launch_ilu0_factor(v.S, v.Ssw, v.g, v.A64, v.L64, v.U64, v.rU64, H->err, st));
     if (cfg->smoother == SMG_SMOOTH_LGS) {
       SCHK(launch_tri_factor(v.S, v.g, v.A64, v.tr64, v.tc64, H->err, st));
       if (cfg->prec == SMG_FP32) {
@@ -577,8 +582,8 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
       SCHK(launch_to_f32(v.A64, v.A32, na, st));
       SCHK(launch_to_f32(v.rd64, v.rd32, (bs == 3 ? 9 : 1) * v.N, st));
       if (cfg->smoother == SMG_SMOOTH_ILU0) {
-        SCHK(launch_to_f32(v.L64, v.L32, (long)v.S * v.N, st));
-        SCHK(launch_to_f32(v.U64, v.U32, (long)v.S * v.N, st));
+        SCHK(launch_to_f32(v.L64, v.L32, (long)v.Ssw * v.N, st));
+        SCHK(launch_to_f32(v.U64, v.U32, (long)v.Ssw * v.N, st));
         SCHK(launch_to_f32(v.rU64, v.rU32, v.N, st));
       }
     } else if (cfg->prec == SMG_FP16_ROWSCALE) {
@@ -605,9 +610,9 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
       for (int d = 0; d < 2; ++d) {
         const int dir = d == 0 ? 1 : -1;
         if (cfg->prec == SMG_FP64)
-          SCHK(launch_wf_pack<double>(v.S, v.g, v.tl, dir, lo, dg, up, (double*)v.pk[d], st));
+          SCHK(launch_wf_pack<double>(v.Ssw, v.g, v.tl, dir, lo, dg, up, (double*)v.pk[d], st));
         else if (cfg->prec == SMG_FP32)
-          SCHK(launch_wf_pack<float>(v.S, v.g, v.tl, dir, lo, dg, up, (float*)v.pk[d], st));
+          SCHK(launch_wf_pack<float>(v.Ssw, v.g, v.tl, dir, lo, dg, up, (float*)v.pk[d], st));
         else
           SCHK(launch_wf_pack_h(v.S, v.g, v.tl, dir, v.A16, v.sc16, v.rd32, (__half*)v.pk[d], v.psd, st));
       }
@@ -925,8 +930,8 @@ smg_status smg_level_export(smg_handle h, int level, int what, void* dst, void* 
   switch (what) {
     case 0: src = v.A64; bytes = sizeof(double) * v.S * be * v.N; break;
     case 1: src = v.rd64; bytes = sizeof(double) * nd; break;
-    case 2: src = v.L64; bytes = sizeof(double) * v.S * v.N; break;
-    case 3: src = v.U64; bytes = sizeof(double) * v.S * v.N; break;
+    case 2: src = v.L64; bytes = sizeof(double) * v.Ssw * v.N; break;
+    case 3: src = v.U64; bytes = sizeof(double) * v.Ssw * v.N; break;
     case 4: src = v.rU64; bytes = sizeof(double) * v.N; break;
     case 5:
       if (last || h->cfg.prec == SMG_FP64) return fail(h, SMG_EINVAL, "no reduced-precision matrix on this level");

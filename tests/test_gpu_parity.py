@@ -513,3 +513,45 @@ def test_gmres_lgs_weather_like():
         if prec == "fp64":
             assert abs(res["iters"] - itr) <= 1
             assert np.abs(N(x) - xr.ravel()).max() / np.abs(xr).max() < 1e-6
+
+
+# ILU(0) of the finest matrix on a mask other than its pattern (fewer or more
+# fill-ins); coarse levels keep their own pattern
+ILU_MASK_CASES = [(CASES[1], 7), (CASES[1], 27), (CASES[0], 19), (CASES[0], 27), (CASES[5], 27), (CASES[3], 7)]
+
+
+@pytest.mark.parametrize("case,mask", ILU_MASK_CASES, ids=lambda v: str(v) if isinstance(v, int) else _ids(v))
+def test_ilu0_mask_bitexact(case, mask):
+    shape, pat, coarsen, semi = case
+    A = workloads.random_sgdia(shape, pat, seed=3, symmetric=False)
+    H = oracle.Hierarchy(shape, pat, A, smoother="ilu0", coarsen=coarsen, semi_levels=semi, ilu_mask=mask)
+    mg = smg.StructMG(T(A), shape, pattern=pat, smoother="ilu0", coarsen=coarsen, semi_levels=semi, ilu_mask=mask,
+                      device=DEV)
+    assert mg.nlev == H.nlev and H.level_info(0)["Sm"] == mask
+    g = workloads.rng(17)
+    for l in range(H.nlev - 1):
+        inf = H.level_info(l)
+        dims, cm = inf["dims"], inf["cmask"]
+        offm = workloads.offsets(inf["Sm"])
+        for what in (2, 3, 4):
+            ref = H.level_data(l, what)
+            got = N(mg.export(l, what, torch.empty(ref.shape, dtype=torch.float64, device=DEV)))
+            assert np.array_equal(got, ref), f"ILU factor {what} level {l}"
+        Lf, Uf, rU = H.level_data(l, 2), H.level_data(l, 3), H.level_data(l, 4).ravel()
+        f = g.uniform(-1, 1, size=dims)
+        u = g.uniform(-1, 1, size=dims)
+        ec = g.uniform(-1, 1, size=oracle.coarse_dims(dims, cm))
+        n = int(np.prod(dims))
+        ug = N(mg.op_presmooth(l, T(f), torch.empty(n, dtype=torch.float64, device=DEV)))
+        ref = oracle.tri_solve(offm, Uf, rU, oracle.tri_solve(offm, Lf, None, f, 0), 1)
+        assert np.array_equal(ug, ref.ravel()), f"ILU solve level {l}"
+        uo = N(mg.op_postsmooth(l, T(f), T(u), T(ec), torch.empty(n, dtype=torch.float64, device=DEV)))
+        uold = oracle.prolong_add(u, ec, cm)
+        r = oracle.residual(workloads.offsets(inf["S"]), H.level_data(l, 0), f, uold)
+        zc = oracle.tri_solve(offm, Uf, rU, oracle.tri_solve(offm, Lf, None, r, 0), 1)
+        assert np.array_equal(uo, (uold + zc).ravel()), f"ILU correction level {l}"
+    dims = H.level_info(0)["dims"]
+    rr = workloads.rng(9).uniform(-1, 1, size=dims)
+    zr = H.apply(rr).ravel()
+    z = N(mg.precondition(T(rr.ravel()), torch.empty(rr.size, dtype=torch.float64, device=DEV)))
+    assert np.abs(z - zr).max() <= 1e-12 * np.abs(zr).max()
