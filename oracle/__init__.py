@@ -63,11 +63,16 @@ def _declare(L):
         getattr(L, "orc_bresidual" + sfx).argtypes = [_i, _i, _i, _i, _ip, p, p, p, p]
         getattr(L, "orc_bgs_sweep" + sfx).argtypes = [_i, _i, _i, _i, _ip, p, p, p, p, _i, _i]
         getattr(L, "orc_lgs_sweep" + sfx).argtypes = [_i, _i, _i, _i, _ip, p, p, p, p, p, _i, _i, p]
+        getattr(L, "orc_restrict_cc" + sfx).argtypes = [_i, _i, _i, _i, _i, p, p]
+        getattr(L, "orc_prolong_add_cc" + sfx).argtypes = [_i, _i, _i, _i, _i, p, p]
     L.orc_pattern.argtypes = [_i, _ip]
     L.orc_pattern.restype = _i
     L.orc_rap.argtypes = [_i, _i, _i, _i, _ip, _i, _dp, _i, _dp]
     L.orc_rap_chains.argtypes = [_i, _ip, _i, _i, _ip, _i]
     L.orc_rap_chains.restype = _i
+    L.orc_rap_cc.argtypes = [_i, _i, _i, _i, _ip, _i, _dp, _i, _dp]
+    L.orc_rap_cc_chains.argtypes = [_i, _ip, _i]
+    L.orc_rap_cc_chains.restype = _i
     L.orc_ilu0.argtypes = [_i, _i, _i, _i, _ip, _dp, _dp, _dp, _dp]
     L.orc_ilu0.restype = _i
     L.orc_ilu0_mask.argtypes = [_i, _i, _i, _i, _ip, _dp, _i, _ip, _dp, _dp, _dp]
@@ -84,7 +89,7 @@ def _declare(L):
     L.orc_f32_to_f16.restype = C.c_uint16
     L.orc_f16_to_f32.argtypes = [C.c_uint16]
     L.orc_f16_to_f32.restype = C.c_float
-    L.orc_mg_create.argtypes = [_i, _i, _i, _i, _i, _dp, _i, _i, _i, _i, _i, _i]
+    L.orc_mg_create.argtypes = [_i, _i, _i, _i, _i, _dp, _i, _i, _i, _i, _i, _i, _i]
     L.orc_mg_create.restype = C.c_void_p
     L.orc_mg_destroy.argtypes = [C.c_void_p]
     L.orc_mg_nlev.argtypes = [C.c_void_p]
@@ -181,8 +186,36 @@ def tri_solve(off, F, rU, r, upper):
     return y
 
 
-def coarse_dims(shape, cmask):
-    return tuple(n // 2 if (cmask >> a) & 1 else n for a, n in enumerate(shape))
+def coarse_dims(shape, cmask, cell=False):
+    return tuple(((n + 1) // 2 if cell else n // 2) if (cmask >> a) & 1 else n for a, n in enumerate(shape))
+
+
+def restrict_cc(rf, cmask, bs=1):
+    shp = rf.shape[:3]
+    rc = np.zeros(coarse_dims(shp, cmask, True) + rf.shape[3:], rf.dtype)
+    getattr(lib(), "orc_restrict_cc" + _sfx(rf))(*_dims(shp), int(cmask), int(bs), _c(rf).ravel(), rc.ravel())
+    return rc
+
+
+def prolong_add_cc(uf, ec, cmask, bs=1):
+    shp = uf.shape[:3]
+    out = _c(uf).copy()
+    getattr(lib(), "orc_prolong_add_cc" + _sfx(uf))(*_dims(shp), int(cmask), int(bs), _c(ec).ravel(), out.ravel())
+    return out
+
+
+def rap_cc(off, Af, shape, cmask, bs=1):
+    off = _c(off, np.int32)
+    Nc = int(np.prod(coarse_dims(shape, cmask, True)))
+    Ac = np.zeros((off.shape[0] * bs * bs, Nc))
+    lib().orc_rap_cc(*_dims(shape), off.shape[0], off.ravel(), int(bs), _c(Af, np.float64).ravel(), int(cmask),
+                     Ac.ravel())
+    return Ac
+
+
+def rap_cc_chains(off, cmask):
+    off = _c(off, np.int32)
+    return lib().orc_rap_cc_chains(off.shape[0], off.ravel(), int(cmask))
 
 
 def restrict(rf, cmask, bs=1):
@@ -300,19 +333,20 @@ def f16_bits_to_f32(h):
 
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2}
 SMOOTHER = {"gs": 0, "ilu0": 1, "lgs": 2}
+INTERP = {"vertex": 0, "cell": 1}
 
 
 class Hierarchy:
     """Oracle multigrid hierarchy built from the finest matrix (FP64 setup)."""
 
     def __init__(self, shape, pattern_pts, A0, block=1, smoother="gs", coarsen="full", semi_levels=0,
-                 prec="fp64", max_coarse=8192, ilu_mask=0):
+                 prec="fp64", max_coarse=8192, ilu_mask=0, interp="vertex"):
         self.shape = tuple(int(v) for v in shape)
         self.bs = int(block)
         self._A0 = _c(A0, np.float64)
         h = lib().orc_mg_create(*self.shape, int(pattern_pts), self.bs, self._A0.ravel(),
                                 SMOOTHER[smoother], 1 if coarsen == "semi_xy" else 0, int(semi_levels),
-                                PREC[prec], int(max_coarse), int(ilu_mask))
+                                PREC[prec], int(max_coarse), int(ilu_mask), INTERP[interp])
         if not h:
             raise ValueError("oracle hierarchy setup failed")
         self.h = C.c_void_p(h)

@@ -373,6 +373,79 @@ int orc_block_dinv(int nx, int ny, int nz, int S, const int* off, const double* 
   return 0;
 }
 
+/* ---- stencil Galerkin product for the cell-centred pair (Cell_3d8
+ * restriction and interpolation; Table of R/A/P combinations, 3d8c columns)
+ * With piecewise-constant P and R = P^T, A_c(I, n) is the sum of A(f, s)
+ * over the children f of coarse cell I (lexicographic order of the child
+ * offset d) and the fine offsets s (canonical order) with f + s in the grid
+ * and parent(f + s) = I + n; plain additions from zero.  A coupling of the
+ * fine pattern can only reach coarse offsets of that pattern, so the coarse
+ * operator keeps the fine pattern (off, S); Ac holds S*bs*bs coarse
+ * diagonals. */
+void orc_rap_cc(int nxf, int nyf, int nzf, int S, const int* off, int bs, const double* Af, int cmask, double* Ac) {
+  int nf[3] = {nxf, nyf, nzf}, nc[3], cm[3];
+  for (int a = 0; a < 3; ++a) {
+    cm[a] = (cmask >> a) & 1;
+    nc[a] = cm[a] ? (nf[a] + 1) / 2 : nf[a];
+  }
+  long Nf = (long)nf[0] * nf[1] * nf[2], Nc = (long)nc[0] * nc[1] * nc[2];
+  int be = bs * bs;
+  for (int X = 0; X < nc[0]; ++X)
+    for (int Y = 0; Y < nc[1]; ++Y)
+      for (int Z = 0; Z < nc[2]; ++Z) {
+        int I[3] = {X, Y, Z};
+        long ic = ((long)X * nc[1] + Y) * nc[2] + Z;
+        for (int n = 0; n < S; ++n)
+          for (int e = 0; e < be; ++e) {
+            double acc = 0.0;
+            for (int dx = 0; dx <= cm[0]; ++dx)
+              for (int dy = 0; dy <= cm[1]; ++dy)
+                for (int dz = 0; dz <= cm[2]; ++dz) {
+                  int d[3] = {dx, dy, dz}, f[3], skip = 0;
+                  for (int a = 0; a < 3; ++a) {
+                    f[a] = cm[a] ? 2 * I[a] + d[a] : I[a];
+                    if (f[a] >= nf[a]) skip = 1;
+                  }
+                  if (skip) continue;
+                  long i = ((long)f[0] * nf[1] + f[1]) * nf[2] + f[2];
+                  for (int s = 0; s < S; ++s) {
+                    int g[3], hit = 1;
+                    for (int a = 0; a < 3; ++a) {
+                      g[a] = f[a] + off[3 * s + a];
+                      if (g[a] < 0 || g[a] >= nf[a]) hit = 0;
+                      else if ((cm[a] ? g[a] / 2 : g[a]) - I[a] != off[3 * n + a]) hit = 0;
+                    }
+                    if (hit) acc = acc + Af[((long)s * be + e) * Nf + i];
+                  }
+                }
+            Ac[((long)n * be + e) * Nc + ic] = acc;
+          }
+      }
+}
+
+/* Influence chains of the cell-centred product for an interior coarse cell
+ * and full coarsening: the (child, fine offset) pairs, each of which lands on
+ * exactly one coarse offset (Table of chain counts, 3d8c columns). */
+int orc_rap_cc_chains(int S, const int* off, int cmask) {
+  int cnt = 0, I[3] = {4, 4, 4}, cm[3];
+  for (int a = 0; a < 3; ++a) cm[a] = (cmask >> a) & 1;
+  for (int n = 0; n < S; ++n)
+    for (int dx = 0; dx <= cm[0]; ++dx)
+      for (int dy = 0; dy <= cm[1]; ++dy)
+        for (int dz = 0; dz <= cm[2]; ++dz) {
+          int d[3] = {dx, dy, dz};
+          for (int s = 0; s < S; ++s) {
+            int hit = 1;
+            for (int a = 0; a < 3; ++a) {
+              int f = cm[a] ? 2 * I[a] + d[a] : I[a], g = f + off[3 * s + a];
+              if ((cm[a] ? g / 2 : g) - I[a] != off[3 * n + a]) hit = 0;
+            }
+            cnt += hit;
+          }
+        }
+  return cnt;
+}
+
 /* ---- Thomas factorisation of the z-columns (Sec. 4.4, LGS paragraph) ---
  * For every column (x, y) the tridiagonal block of A on that column: a_z =
  * coupling to z-1, b_z = centre, c_z = coupling to z+1 (zero at the column
@@ -419,7 +492,7 @@ typedef struct {
 } olev;
 
 typedef struct {
-  int nlev, bs, smoother, prec;
+  int nlev, bs, smoother, prec, cell;
   olev lev[48];
   int nc;
   double *LU, *cw;
@@ -483,15 +556,19 @@ void orc_mg_destroy(omg* mg);
  * z-columns (scalar systems; FP64 and FP32).  prec: 0 FP64, 1 FP32,
  * 2 FP16 row-scaled.  ilu_mask: 0 = ILU(0) on each level's own pattern, or
  * 7 / 19 / 27 = that mask for the finest matrix (coarse levels keep their
- * own 27-point pattern).  A0 is copied; out-of-grid couplings are zeroed.
+ * own 27-point pattern).  cell = 0: vertex-centred trilinear P, R = P^T,
+ * coarse levels 27-point; cell = 1: cell-centred piecewise-constant P and
+ * R = P^T (Cell_3d8), every level keeps the finest pattern.  A0 is copied;
+ * out-of-grid couplings are zeroed.
  * Returns NULL on error (zero pivot, coarsest level too large).
  */
 omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0, int smoother, int semi_mode,
-                   int semi_levels, int prec, int max_coarse, int ilu_mask) {
+                   int semi_levels, int prec, int max_coarse, int ilu_mask, int cell) {
   if (smoother == 2 && (bs != 1 || prec == 2)) return NULL;
   if (ilu_mask != 0 && (smoother != 1 || (ilu_mask != 7 && ilu_mask != 19 && ilu_mask != 27))) return NULL;
   omg* mg = (omg*)calloc(1, sizeof(omg));
   mg->bs = bs;
+  mg->cell = cell;
   mg->smoother = smoother;
   mg->prec = prec;
   int be = bs * bs, l = 0;
@@ -500,7 +577,7 @@ omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0
     olev* v = &mg->lev[l];
     v->nx = n[0]; v->ny = n[1]; v->nz = n[2];
     v->N = (long)n[0] * n[1] * n[2];
-    v->S = orc_pattern(l == 0 ? pattern : 27, v->off);
+    v->S = orc_pattern(l == 0 || cell ? pattern : 27, v->off);
     v->A = (double*)malloc(sizeof(double) * v->S * be * v->N);
     if (l == 0) {
       for (int s = 0; s < v->S; ++s)
@@ -513,7 +590,10 @@ omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0
         }
     } else {
       olev* p = &mg->lev[l - 1];
-      orc_rap(p->nx, p->ny, p->nz, p->S, p->off, bs, p->A, p->cmask, v->A);
+      if (cell)
+        orc_rap_cc(p->nx, p->ny, p->nz, p->S, p->off, bs, p->A, p->cmask, v->A);
+      else
+        orc_rap(p->nx, p->ny, p->nz, p->S, p->off, bs, p->A, p->cmask, v->A);
     }
     long nvec = v->N * bs;
     v->f = (double*)calloc(nvec, sizeof(double));
@@ -533,7 +613,7 @@ omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0
       break;
     }
     for (int a = 0; a < 3; ++a)
-      if ((v->cmask >> a) & 1) n[a] /= 2;
+      if ((v->cmask >> a) & 1) n[a] = cell ? (n[a] + 1) / 2 : n[a] / 2;
     ++l;
   }
   /* smoother data on all but the coarsest level */

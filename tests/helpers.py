@@ -126,3 +126,18 @@ def line_gs(M, shape, b, u0, direction):
         rhs = b[r] - M[r, :] @ u + M[r, r] @ u[r]
         u[r] = np.linalg.solve(M[r, r], rhs)
     return u
+
+
+def cell_interp_matrix(shape, cmask):
+    """Explicit cell-centred piecewise-constant interpolation P (Nf x Nc):
+    fine cell f takes the value of its parent cell f // 2 on each coarsened
+    axis (identity on the others); n_c = ceil(n_f / 2)."""
+    cs = tuple((n + 1) // 2 if (cmask >> a) & 1 else n for a, n in enumerate(shape))
+    P = np.zeros((int(np.prod(shape)), int(np.prod(cs))))
+    for x in range(shape[0]):
+        for y in range(shape[1]):
+            for z in range(shape[2]):
+                f = (x, y, z)
+                J = tuple(f[a] // 2 if (cmask >> a) & 1 else f[a] for a in range(3))
+                P[lin(shape, *f), lin(cs, *J)] = 1.0
+    return P, cs

@@ -392,6 +392,72 @@ def test_chain_counts_table():
     assert tot7xy == 5 ** 2 + 4 * 4 * 5 + 2 * 5 ** 2 == 155
 
 
+@pytest.mark.parametrize("shape", [(6, 5, 7), (8, 8, 8), (5, 6, 4), (7, 3, 9)])
+@pytest.mark.parametrize("cmask", [7, 3, 1, 6])
+def test_cell_transfers_are_transposes(shape, cmask):
+    """Cell_3d8 pair: prolongation is piecewise constant, restriction its
+    transpose (sum over the children), n_c = ceil(n_f / 2)."""
+    P, cs = helpers.cell_interp_matrix(shape, cmask)
+    g = workloads.rng(8)
+    r = g.uniform(-1, 1, size=shape)
+    rc = oracle.restrict_cc(r, cmask)
+    assert rc.shape == cs
+    assert np.allclose(rc.ravel(), P.T @ r.ravel(), rtol=0, atol=1e-14)
+    u = g.uniform(-1, 1, size=shape)
+    e = g.uniform(-1, 1, size=cs)
+    assert np.array_equal(oracle.prolong_add_cc(u, e, cmask).ravel(), u.ravel() + P @ e.ravel())
+
+
+@pytest.mark.parametrize("npts", [7, 19, 27])
+@pytest.mark.parametrize("shape,cmask", [((6, 5, 7), 7), ((8, 6, 5), 3), ((5, 8, 6), 5), ((4, 7, 9), 6),
+                                         ((7, 7, 7), 7)])
+def test_rap_cc_matches_dense(npts, shape, cmask):
+    """Stencil product of the cell-centred pair = P^T A P assembled densely;
+    the coarse operator keeps the fine pattern (no entry outside it)."""
+    off = workloads.offsets(npts)
+    A = workloads.random_sgdia(shape, npts, seed=13, symmetric=False)
+    M = helpers.dense_from_sgdia(A, off, shape)
+    P, cs = helpers.cell_interp_matrix(shape, cmask)
+    Ac = oracle.rap_cc(off, A, shape, cmask)
+    assert np.allclose(helpers.dense_from_sgdia(Ac, off, cs), P.T @ M @ P, rtol=0, atol=1e-13 * np.abs(M).max())
+
+
+def test_rap_cc_chain_count_and_symmetry():
+    tab = _gold_tables()
+    assert oracle.rap_cc_chains(workloads.offsets(7), 7) == int(tab[("chains", "3d8c", "3d7", "3d8c")])
+    # every (child, fine offset) pair lands on one coarse offset
+    assert oracle.rap_cc_chains(workloads.offsets(27), 7) == 8 * 27
+    assert oracle.rap_cc_chains(workloads.offsets(19), 3) == 4 * 19
+    shape = (8, 7, 6)
+    for npts in (7, 19, 27):
+        off = workloads.offsets(npts)
+        A = workloads.random_sgdia(shape, npts, seed=5, symmetric=True)
+        cs = oracle.coarse_dims(shape, 7, cell=True)
+        Mc = helpers.dense_from_sgdia(oracle.rap_cc(off, A, shape, 7), off, cs)
+        assert np.allclose(Mc, Mc.T, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("npts", [7, 27])
+def test_cell_vcycle_symmetric_and_pcg(npts):
+    """Cell-centred hierarchy: every level keeps the fine pattern, the V(1,1)
+    symmetric GS cycle is symmetric and PCG converges on the 3d7 Laplacian."""
+    shape = (16, 12, 10)
+    A = workloads.random_sgdia(shape, npts, seed=17, symmetric=True)
+    H = oracle.Hierarchy(shape, npts, A, interp="cell")
+    assert H.nlev >= 2 and all(H.level_info(l)["S"] == npts for l in range(H.nlev))
+    assert H.level_info(1)["dims"] == (8, 6, 5)
+    g = workloads.rng(5)
+    x = g.uniform(-1, 1, size=shape)
+    y = g.uniform(-1, 1, size=shape)
+    a = np.dot(H.apply(x).ravel(), y.ravel())
+    b = np.dot(x.ravel(), H.apply(y).ravel())
+    assert abs(a - b) <= 1e-12 * max(abs(a), 1.0)
+    A7, b7 = workloads.poisson7(24)
+    Hc = oracle.Hierarchy((24, 24, 24), 7, A7, interp="cell")
+    _, st, it, rel = Hc.pcg(b7.reshape(24, 24, 24), 1e-9, 200)
+    assert st == 0 and rel < 1e-9
+
+
 def test_listing1_chain_set():
     """2D example: R = 2d9, A = 2d5, P = 2d9, coarse neighbour (-1, +1)."""
     exp = set()
