@@ -55,6 +55,7 @@ typedef enum {
 typedef enum { SMG_SMOOTH_GS = 0, SMG_SMOOTH_ILU0 = 1, SMG_SMOOTH_LGS = 2 } smg_smoother;
 typedef enum { SMG_COARSEN_FULL = 0, SMG_COARSEN_SEMI_XY = 1 } smg_coarsen;
 typedef enum { SMG_FP64 = 0, SMG_FP32 = 1, SMG_FP16_ROWSCALE = 2 } smg_prec;
+typedef enum { SMG_INTERP_VERTEX = 0, SMG_INTERP_CELL = 1 } smg_interp;
 
 typedef struct {
   int nx, ny, nz;      /* finest grid */
@@ -76,6 +77,13 @@ typedef struct {
                           matrix (Sec. 4.2.3 ILU masks): 0 = its own pattern, or the
                           7 / 19 / 27-point mask (fewer or more fill-ins than the
                           matrix pattern); coarse levels keep their 27-point pattern */
+  int interp;          /* smg_interp: vertex-centred trilinear P with R = P^T, coarse
+                          X <-> fine 2X+1, n_c = floor(n_f/2), 27-point coarse levels; or
+                          the cell-centred piecewise-constant pair (table of R/A/P
+                          combinations, Cell_3d8 interpolation and restriction): coarse
+                          cell I owns fine cells 2I, 2I+1 per coarsened axis,
+                          n_c = ceil(n_f/2), R = P^T, every level keeps the finest
+                          pattern (scalar systems) */
 } smg_config;
 
 typedef struct {

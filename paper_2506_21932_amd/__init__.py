@@ -17,6 +17,7 @@ STATUS_NAMES = {0: "SMG_OK", 1: "SMG_ENOTCONV", -1: "SMG_EINVAL", -2: "SMG_ENOME
                 -4: "SMG_EBREAKDOWN", -5: "SMG_EDEADLOCK"}
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2}
 SMOOTHER = {"gs": 0, "ilu0": 1, "lgs": 2}
+INTERP = {"vertex": 0, "cell": 1}
 COARSEN = {"full": 0, "semi_xy": 1}
 
 
@@ -29,7 +30,7 @@ class SmgError(RuntimeError):
 class Config(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("block", C.c_int), ("pattern", C.c_int),
                 ("smoother", C.c_int), ("coarsen", C.c_int), ("semi_levels", C.c_int), ("prec", C.c_int),
-                ("max_coarse", C.c_int), ("gmres_restart", C.c_int), ("ilu_mask", C.c_int)]
+                ("max_coarse", C.c_int), ("gmres_restart", C.c_int), ("ilu_mask", C.c_int), ("interp", C.c_int)]
 
 
 class Result(C.Structure):
@@ -112,10 +113,10 @@ def rap_chain_count(pattern, cmask):
 
 
 def make_config(shape, pattern=7, block=1, smoother="gs", coarsen="full", semi_levels=0, prec="fp64",
-                max_coarse=0, gmres_restart=0, ilu_mask=0):
+                max_coarse=0, gmres_restart=0, ilu_mask=0, interp="vertex"):
     nx, ny, nz = (int(v) for v in shape)
     return Config(nx, ny, nz, int(block), int(pattern), SMOOTHER[smoother], COARSEN[coarsen], int(semi_levels),
-                  PREC[prec], int(max_coarse), int(gmres_restart), int(ilu_mask))
+                  PREC[prec], int(max_coarse), int(gmres_restart), int(ilu_mask), INTERP[interp])
 
 
 def _ptr(t):
@@ -131,12 +132,12 @@ class StructMG:
     """Owns a libstructmg handle and its workspace (a torch uint8 tensor)."""
 
     def __init__(self, coeffs, shape, pattern=7, block=1, smoother="gs", coarsen="full", semi_levels=0, prec="fp64",
-                 max_coarse=0, gmres_restart=0, device="cuda", workspace=None, ilu_mask=0):
+                 max_coarse=0, gmres_restart=0, device="cuda", workspace=None, ilu_mask=0, interp="vertex"):
         import torch
         L = load()
         self.L = L
         self.cfg = make_config(shape, pattern, block, smoother, coarsen, semi_levels, prec, max_coarse, gmres_restart,
-                               ilu_mask)
+                               ilu_mask, interp)
         self.block = int(block)
         self.prec = prec
         nbytes = C.c_size_t(0)

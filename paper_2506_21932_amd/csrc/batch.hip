@@ -657,8 +657,9 @@ smg_status smg_batch_workspace_size(int nsys, const smg_config* cfgs, size_t* by
     const smg_config& c = cfgs[s];
     const char* why = config_error(&c);
     if (why) return bfail(nullptr, SMG_EINVAL, "system %d: %s", s, why);
-    if (c.block != 1 || c.smoother != SMG_SMOOTH_GS)
-      return bfail(nullptr, SMG_EINVAL, "system %d: batches take scalar systems with the GS smoother", s);
+    if (c.block != 1 || c.smoother != SMG_SMOOTH_GS || c.interp != SMG_INTERP_VERTEX)
+      return bfail(nullptr, SMG_EINVAL,
+                   "system %d: batches take scalar systems, the GS smoother and vertex-centred transfers", s);
     if (c.prec != cfgs[0].prec || c.pattern != cfgs[0].pattern)
       return bfail(nullptr, SMG_EINVAL, "system %d: every system of a batch has the same pattern and precision", s);
     sh[s].lev.resize(MAXLEV);

@@ -181,6 +181,16 @@ hipError_t launch_restrict(const Grid& g, int cmask, int bs, const V* rf, V* rc,
 template <class V>
 hipError_t launch_prolong_add(const Grid& g, int cmask, int bs, const V* ec, V* uf, hipStream_t st);
 
+// cell-centred piecewise-constant pair (cell.hip): coarse cell I owns fine
+// cells 2I + {0,1} on coarsened axes, n_c = ceil(n_f / 2); rc = P^T rf,
+// uout = uin + P ec (uout may be uin), A_c = R A P on the fine pattern
+template <class V>
+hipError_t launch_restrict_cc(const Grid& gf, int cmask, int bs, const V* rf, V* rc, hipStream_t st);
+template <class V>
+hipError_t launch_prolong_cc(const Grid& gf, int cmask, int bs, const V* ec, const V* uin, V* uout, hipStream_t st);
+hipError_t launch_rap_cc(int pat, int cmask, const Grid& gf, const double* A, long sA, double* Ac, long sAc,
+                         hipStream_t st);
+
 // ---- block (3x3) variants (block.hip) --------------------------------
 // y = A x or y = b - A x on 3x3 blocks (27-point pattern)
 template <class M>

@@ -107,6 +107,8 @@ const char* check_cfg(const smg_config* c) {
   if (c->ilu_mask != 0 && c->ilu_mask != 7 && c->ilu_mask != 19 && c->ilu_mask != 27)
     return "ilu_mask must be 0, 7, 19 or 27";
   if (c->ilu_mask != 0 && c->smoother != SMG_SMOOTH_ILU0) return "ilu_mask applies to the ILU(0) smoother only";
+  if (c->interp != SMG_INTERP_VERTEX && c->interp != SMG_INTERP_CELL) return "unknown interpolation";
+  if (c->interp == SMG_INTERP_CELL && c->block != 1) return "cell-centred transfers are implemented for scalar systems";
   return nullptr;
 }
 
@@ -125,7 +127,7 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
     Level& v = L[nlev];
     v.g = Grid{n[0], n[1], n[2]};
     v.N = v.g.N();
-    v.S = nlev == 0 ? cfg.pattern : 27;
+    v.S = nlev == 0 || cfg.interp == SMG_INTERP_CELL ? cfg.pattern : 27;
     v.Ssw = cfg.smoother == SMG_SMOOTH_ILU0 && nlev == 0 && cfg.ilu_mask ? cfg.ilu_mask : v.S;
     v.cmask = next_cmask(nlev, n, cfg.coarsen == SMG_COARSEN_SEMI_XY, cfg.semi_levels);
     ++nlev;
@@ -134,7 +136,7 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
       break;
     }
     for (int a = 0; a < 3; ++a)
-      if ((v.cmask >> a) & 1) n[a] /= 2;
+      if ((v.cmask >> a) & 1) n[a] = cfg.interp == SMG_INTERP_CELL ? (n[a] + 1) / 2 : n[a] / 2;
   }
   const long nc = L[nlev - 1].N * bs;
   if (nlev_out) *nlev_out = nlev;
@@ -348,6 +350,13 @@ hipError_t lgs_sweep(smg_handle_s* H, const Level& v, int dir, const typename PT
   return launch_lgs<V>(v.S, dir, uold == nullptr, a, st);
 }
 
+// uf += P ec with the handle's interpolation (bs components per point).
+template <class V>
+hipError_t prolong_in_place(const smg_handle_s* H, const Level& v, const V* ec, V* uf, hipStream_t st) {
+  if (H->cfg.interp == SMG_INTERP_CELL) return launch_prolong_cc<V>(v.g, v.cmask, H->bs, ec, uf, uf, st);
+  return launch_prolong_add<V>(v.g, v.cmask, H->bs, ec, uf, st);
+}
+
 // One V-cycle on internal or caller vectors: f0 = level-0 right-hand side,
 // z0 = level-0 output (its positions read across tiles are given sentinels by
 // the pre-smoothing sweep).
@@ -358,6 +367,7 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
   const int NL = H->nlev;
   const bool ilu = H->cfg.smoother == SMG_SMOOTH_ILU0;
   const bool lgs = H->cfg.smoother == SMG_SMOOTH_LGS;
+  const bool cell = H->cfg.interp == SMG_INTERP_CELL;
   auto F = [&](int l) -> const V* { return l == 0 ? f0 : (const V*)H->lev[l].f; };
   auto UB = [&](int l) -> V* { return l == 0 ? z0 : (V*)H->lev[l].ub; };
   hipError_t e;
@@ -383,7 +393,10 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
     if (e != hipSuccess) return e;
     {
       Timed t(H, l, 2, st);
-      if (split_rp(v)) {
+      if (cell) {
+        e = launch_spmv(v.S, v.g, A, (const V*)v.ua, F(l), (V*)v.h, true, st);
+        if (e == hipSuccess) e = launch_restrict_cc<V>(v.g, v.cmask, 1, (const V*)v.h, (V*)H->lev[l + 1].f, st);
+      } else if (split_rp(v)) {
         // residual into the level's h (free until the upward leg), then R
         e = launch_spmv(v.S, v.g, A, (const V*)v.ua, F(l), (V*)v.h, true, st);
         if (e == hipSuccess) e = launch_restrict<V>(v.g, v.cmask, 1, (const V*)v.h, (V*)H->lev[l + 1].f, st);
@@ -404,7 +417,8 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
     if (lgs) {
       {
         Timed t(H, l, 4, st);
-        e = launch_prolong_add<V>(v.g, v.cmask, 1, (const V*)UB(l + 1), (V*)v.ua, st);
+        e = cell ? launch_prolong_cc<V>(v.g, v.cmask, 1, (const V*)UB(l + 1), (const V*)v.ua, (V*)v.ua, st)
+                 : launch_prolong_add<V>(v.g, v.cmask, 1, (const V*)UB(l + 1), (V*)v.ua, st);
       }
       if (e != hipSuccess) return e;
       // backward line GS from u_a + P e_c; u_a gets its sentinels back
@@ -413,10 +427,11 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
     } else if (!ilu) {
       {
         Timed t(H, l, 4, st);
-        if (split_rp(v)) {
+        if (cell || split_rp(v)) {
           // u_old = u + P e_c in place (u_a is refilled by the sweep below),
           // then the backward sweep's old-value terms
-          e = launch_prolong_add<V>(v.g, v.cmask, 1, (const V*)UB(l + 1), (V*)v.ua, st);
+          e = cell ? launch_prolong_cc<V>(v.g, v.cmask, 1, (const V*)UB(l + 1), (const V*)v.ua, (V*)v.ua, st)
+                   : launch_prolong_add<V>(v.g, v.cmask, 1, (const V*)UB(l + 1), (V*)v.ua, st);
           if (e == hipSuccess) e = launch_lower(v.S, v.g, A, F(l), (const V*)v.ua, (V*)v.h, st);
         } else {
           e = launch_prolong_post(v.S, v.g, v.cmask, A, F(l), (const V*)v.ua, (const V*)UB(l + 1), (V*)v.h,
@@ -429,8 +444,14 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
     } else {
       {
         Timed t(H, l, 4, st);
-        e = launch_prolong_post(v.S, v.g, v.cmask, A, F(l), (const V*)v.ua, (const V*)UB(l + 1), (V*)v.h,
-                                (V*)v.uo, true, st);
+        if (cell) {
+          // u_old = u_a + P e_c into u_o, then h = f - A u_old
+          e = launch_prolong_cc<V>(v.g, v.cmask, 1, (const V*)UB(l + 1), (const V*)v.ua, (V*)v.uo, st);
+          if (e == hipSuccess) e = launch_spmv(v.S, v.g, A, (const V*)v.uo, F(l), (V*)v.h, true, st);
+        } else {
+          e = launch_prolong_post(v.S, v.g, v.cmask, A, F(l), (const V*)v.ua, (const V*)UB(l + 1), (V*)v.h,
+                                  (V*)v.uo, true, st);
+        }
       }
       if (e != hipSuccess) return e;
       {
@@ -557,9 +578,14 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
   for (int l = 0; l + 1 < H->nlev; ++l) {
     const Level& f = H->lev[l];
     Level& c = H->lev[l + 1];
-    for (int e = 0; e < be; ++e)
-      SCHK(launch_rap(f.S, f.cmask, f.g, f.A64 + (long)e * f.N, (long)be * f.N, c.A64 + (long)e * c.N,
-                      (long)be * c.N, st));
+    for (int e = 0; e < be; ++e) {
+      if (cfg->interp == SMG_INTERP_CELL)
+        SCHK(launch_rap_cc(f.S, f.cmask, f.g, f.A64 + (long)e * f.N, (long)be * f.N, c.A64 + (long)e * c.N,
+                           (long)be * c.N, st));
+      else
+        SCHK(launch_rap(f.S, f.cmask, f.g, f.A64 + (long)e * f.N, (long)be * f.N, c.A64 + (long)e * c.N,
+                        (long)be * c.N, st));
+    }
   }
   // smoother data, truncation, wavefront tiling and sentinel fills
   for (int l = 0; l + 1 < H->nlev; ++l) {
@@ -1035,7 +1061,7 @@ static hipError_t op_postsmooth_t(smg_handle_s* H, const Level& v, const void* f
     // u_old = u_in + P ec in the level's u_a buffer, then the backward line GS
     // sweep, which gives u_a its sentinels back
     e = hipMemcpyAsync(v.ua, uin, sizeof(V) * nv, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess && ec != nullptr) e = launch_prolong_add<V>(v.g, v.cmask, 1, (const V*)ec, (V*)v.ua, st);
+    if (e == hipSuccess && ec != nullptr) e = prolong_in_place<V>(H, v, (const V*)ec, (V*)v.ua, st);
     if (e == hipSuccess) e = launch_fill_bits<V>((V*)uout, nv, sent, st);
     if (e == hipSuccess) e = lgs_sweep<PT>(H, v, -1, (const V*)f, (const V*)v.ua, (V*)uout, (V*)v.ua, st);
     return e;
@@ -1044,9 +1070,9 @@ static hipError_t op_postsmooth_t(smg_handle_s* H, const Level& v, const void* f
     // the V-cycle's kernels for this level: h = f - lower(A) u_old with
     // u_old = u_in + P ec (large levels: formed in u_a, whose sentinels are
     // restored after)
-    if (split_rp(v)) {
+    if (split_rp(v) || H->cfg.interp == SMG_INTERP_CELL) {
       e = hipMemcpyAsync(v.ua, uin, sizeof(V) * nv, hipMemcpyDeviceToDevice, st);
-      if (e == hipSuccess && ec != nullptr) e = launch_prolong_add<V>(v.g, v.cmask, 1, (const V*)ec, (V*)v.ua, st);
+      if (e == hipSuccess && ec != nullptr) e = prolong_in_place<V>(H, v, (const V*)ec, (V*)v.ua, st);
       if (e == hipSuccess) e = launch_lower(v.S, v.g, A, (const V*)f, (const V*)v.ua, (V*)v.h, st);
       if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.ua, nv, sent, st);
     } else {
@@ -1060,8 +1086,14 @@ static hipError_t op_postsmooth_t(smg_handle_s* H, const Level& v, const void* f
   }
   // ILU correction: r = f - A u_old; u_out = u_old + U^-1 L^-1 r.  Scratch: the
   // level's y1/y2/zz buffers, whose sentinel state is restored afterwards.
-  e = launch_prolong_post(v.S, v.g, v.cmask, A, (const V*)f, (const V*)uin, (const V*)ec, (V*)v.h, (V*)v.uo, true,
-                          st);
+  if (H->cfg.interp == SMG_INTERP_CELL) {
+    e = ec ? launch_prolong_cc<V>(v.g, v.cmask, 1, (const V*)ec, (const V*)uin, (V*)v.uo, st)
+           : hipMemcpyAsync(v.uo, uin, sizeof(V) * nv, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = launch_spmv(v.S, v.g, A, (const V*)v.uo, (const V*)f, (V*)v.h, true, st);
+  } else {
+    e = launch_prolong_post(v.S, v.g, v.cmask, A, (const V*)f, (const V*)uin, (const V*)ec, (V*)v.h, (V*)v.uo,
+                            true, st);
+  }
   if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.y2, nv, sent, st);
   if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.zz, nv, sent, st);
   if (e == hipSuccess)
@@ -1121,9 +1153,13 @@ struct OpRR {
       if (e == hipSuccess) e = launch_restrict<V>(v.g, v.cmask, 3, (const V*)v.h, (V*)rc, st);
       return e;
     }
-    if (!split_rp(v)) return launch_resid_restrict(v.S, v.g, v.cmask, PT::A(v), (const V*)f, (const V*)u, (V*)rc, st);
+    const bool cell = H->cfg.interp == SMG_INTERP_CELL;
+    if (!split_rp(v) && !cell)
+      return launch_resid_restrict(v.S, v.g, v.cmask, PT::A(v), (const V*)f, (const V*)u, (V*)rc, st);
     hipError_t e = launch_spmv(v.S, v.g, PT::A(v), (const V*)u, (const V*)f, (V*)v.h, true, st);
-    if (e == hipSuccess) e = launch_restrict<V>(v.g, v.cmask, 1, (const V*)v.h, (V*)rc, st);
+    if (e == hipSuccess)
+      e = cell ? launch_restrict_cc<V>(v.g, v.cmask, 1, (const V*)v.h, (V*)rc, st)
+               : launch_restrict<V>(v.g, v.cmask, 1, (const V*)v.h, (V*)rc, st);
     return e;
   }
 };
@@ -1174,10 +1210,17 @@ smg_status smg_op_restrict(smg_handle h, int level, const void* rf, void* rc, vo
   if (level < 0 || level + 1 >= h->nlev) return fail(h, SMG_EINVAL, "level %d has no coarser level", level);
   if (!rf || !rc) return fail(h, SMG_EINVAL, "null vector");
   const Level& v = h->lev[level];
-  if (h->cfg.prec == SMG_FP64)
-    HIPCHK(h, launch_restrict<double>(v.g, v.cmask, h->bs, (const double*)rf, (double*)rc, (hipStream_t)stream));
-  else
-    HIPCHK(h, launch_restrict<float>(v.g, v.cmask, h->bs, (const float*)rf, (float*)rc, (hipStream_t)stream));
+  const hipStream_t st = (hipStream_t)stream;
+  if (h->cfg.interp == SMG_INTERP_CELL) {
+    if (h->cfg.prec == SMG_FP64)
+      HIPCHK(h, launch_restrict_cc<double>(v.g, v.cmask, h->bs, (const double*)rf, (double*)rc, st));
+    else
+      HIPCHK(h, launch_restrict_cc<float>(v.g, v.cmask, h->bs, (const float*)rf, (float*)rc, st));
+  } else if (h->cfg.prec == SMG_FP64) {
+    HIPCHK(h, launch_restrict<double>(v.g, v.cmask, h->bs, (const double*)rf, (double*)rc, st));
+  } else {
+    HIPCHK(h, launch_restrict<float>(v.g, v.cmask, h->bs, (const float*)rf, (float*)rc, st));
+  }
   return SMG_OK;
 }
 
@@ -1187,9 +1230,9 @@ smg_status smg_op_prolong_add(smg_handle h, int level, const void* ec, void* uf,
   if (!ec || !uf) return fail(h, SMG_EINVAL, "null vector");
   const Level& v = h->lev[level];
   if (h->cfg.prec == SMG_FP64)
-    HIPCHK(h, launch_prolong_add<double>(v.g, v.cmask, h->bs, (const double*)ec, (double*)uf, (hipStream_t)stream));
+    HIPCHK(h, prolong_in_place<double>(h, v, (const double*)ec, (double*)uf, (hipStream_t)stream));
   else
-    HIPCHK(h, launch_prolong_add<float>(v.g, v.cmask, h->bs, (const float*)ec, (float*)uf, (hipStream_t)stream));
+    HIPCHK(h, prolong_in_place<float>(h, v, (const float*)ec, (float*)uf, (hipStream_t)stream));
   return SMG_OK;
 }
 

@@ -555,3 +555,63 @@ def test_ilu0_mask_bitexact(case, mask):
     zr = H.apply(rr).ravel()
     z = N(mg.precondition(T(rr.ravel()), torch.empty(rr.size, dtype=torch.float64, device=DEV)))
     assert np.abs(z - zr).max() <= 1e-12 * np.abs(zr).max()
+
+
+# cell-centred piecewise-constant transfers (every level keeps the finest
+# pattern; odd sizes give coarse cells with a single child)
+CELL_CASES = [(CASES[0], "gs", "fp64"), (CASES[1], "gs", "fp64"), (CASES[2], "gs", "fp64"), (CASES[4], "gs", "fp64"),
+              (CASES[3], "ilu0", "fp64"), (CASES[1], "lgs", "fp64"), (CASES[0], "gs", "fp32"),
+              (CASES[6], "gs", "fp64")]
+
+
+@pytest.mark.parametrize("case,smoother,prec", CELL_CASES,
+                         ids=lambda v: v if isinstance(v, str) else _ids(v))
+def test_cell_centred_bitexact(case, smoother, prec):
+    shape, pat, coarsen, semi = case
+    A = workloads.random_sgdia(shape, pat, seed=3, symmetric=smoother != "ilu0")
+    H = oracle.Hierarchy(shape, pat, A, smoother=smoother, coarsen=coarsen, semi_levels=semi, prec=prec,
+                         interp="cell")
+    mg = smg.StructMG(T(A), shape, pattern=pat, smoother=smoother, coarsen=coarsen, semi_levels=semi, prec=prec,
+                      interp="cell", device=DEV)
+    assert mg.nlev == H.nlev
+    dt, npt = (torch.float64, np.float64) if prec == "fp64" else (torch.float32, np.float32)
+    g = workloads.rng(31)
+    for l in range(H.nlev):
+        inf = H.level_info(l)
+        assert mg.level_info(l)["dims"] == inf["dims"] and inf["S"] == pat
+        Ar = H.level_data(l, 0)
+        got = N(mg.export(l, 0, torch.empty(Ar.shape, dtype=torch.float64, device=DEV)))
+        assert np.array_equal(got, Ar), f"cell RAP level {l}"
+        if l == H.nlev - 1:
+            break
+        dims, cm = inf["dims"], inf["cmask"]
+        cdims = oracle.coarse_dims(dims, cm, cell=True)
+        Al = Ar if prec == "fp64" else H.level_data(l, 5)
+        off = workloads.offsets(pat)
+        f = g.uniform(-1, 1, size=dims).astype(npt)
+        u = g.uniform(-1, 1, size=dims).astype(npt)
+        ec = g.uniform(-1, 1, size=cdims).astype(npt)
+        rc = N(mg.op_resid_restrict(l, T(f, dt), T(u, dt), torch.empty(int(np.prod(cdims)), dtype=dt, device=DEV)))
+        assert np.array_equal(rc, oracle.restrict_cc(oracle.residual(off, Al, f, u), cm).ravel())
+        uf = T(u.copy(), dt)
+        mg.op_prolong_add(l, T(ec, dt), uf)
+        assert np.array_equal(N(uf).ravel(), oracle.prolong_add_cc(u, ec, cm).ravel())
+        if smoother == "gs":
+            rd = H.level_data(l, 1 if prec == "fp64" else 6).ravel()
+            uo = N(mg.op_postsmooth(l, T(f, dt), T(u, dt), T(ec, dt), torch.empty(int(np.prod(dims)), dtype=dt,
+                                                                                  device=DEV)))
+            ref = oracle.gs_sweep(off, Al, rd, f, oracle.prolong_add_cc(u, ec, cm), -1, 0)
+            assert np.array_equal(uo, ref.ravel()), f"cell post-smoothing level {l}"
+    dims = H.level_info(0)["dims"]
+    r = workloads.rng(9).uniform(-1, 1, size=dims)
+    z = N(mg.precondition(T(r.ravel()), torch.empty(r.size, dtype=torch.float64, device=DEV)))
+    zr = H.apply(r).ravel()  # the oracle's cycle in the hierarchy's precision
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert np.abs(z - zr).max() <= tol * np.abs(zr).max()
+    if smoother == "gs" and prec == "fp64":
+        b = workloads.rng(4).uniform(-1, 1, size=dims)
+        xr, st, itr, _ = H.pcg(b, 1e-9, 300)
+        x = torch.zeros(b.size, dtype=torch.float64, device=DEV)
+        res = mg.solve(T(b.ravel()), x, rtol=1e-9, maxit=300)
+        assert st == 0 and res["status"] == 0 and res["rel_resid_true"] < 1e-9
+        assert abs(res["iters"] - itr) <= 1
