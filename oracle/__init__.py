@@ -65,6 +65,7 @@ def _declare(L):
         getattr(L, "orc_lgs_sweep" + sfx).argtypes = [_i, _i, _i, _i, _ip, p, p, p, p, p, _i, _i, p]
         getattr(L, "orc_restrict_cc" + sfx).argtypes = [_i, _i, _i, _i, _i, p, p]
         getattr(L, "orc_prolong_add_cc" + sfx).argtypes = [_i, _i, _i, _i, _i, p, p]
+        getattr(L, "orc_prolong_add_c64" + sfx).argtypes = [_i, _i, _i, _i, _i, p, p]
     L.orc_pattern.argtypes = [_i, _ip]
     L.orc_pattern.restype = _i
     L.orc_rap.argtypes = [_i, _i, _i, _i, _ip, _i, _dp, _i, _dp]
@@ -73,6 +74,9 @@ def _declare(L):
     L.orc_rap_cc.argtypes = [_i, _i, _i, _i, _ip, _i, _dp, _i, _dp]
     L.orc_rap_cc_chains.argtypes = [_i, _ip, _i]
     L.orc_rap_cc_chains.restype = _i
+    L.orc_rap_c64.argtypes = [_i, _i, _i, _i, _ip, _i, _dp, _i, _dp]
+    L.orc_rap_c64_chains.argtypes = [_i, _ip, _i]
+    L.orc_rap_c64_chains.restype = _i
     L.orc_ilu0.argtypes = [_i, _i, _i, _i, _ip, _dp, _dp, _dp, _dp]
     L.orc_ilu0.restype = _i
     L.orc_ilu0_mask.argtypes = [_i, _i, _i, _i, _ip, _dp, _i, _ip, _dp, _dp, _dp]
@@ -213,6 +217,27 @@ def rap_cc(off, Af, shape, cmask, bs=1):
     return Ac
 
 
+def prolong_add_c64(uf, ec, cmask, bs=1):
+    shp = uf.shape[:3]
+    out = _c(uf).copy()
+    getattr(lib(), "orc_prolong_add_c64" + _sfx(uf))(*_dims(shp), int(cmask), int(bs), _c(ec).ravel(), out.ravel())
+    return out
+
+
+def rap_c64(off, Af, shape, cmask, bs=1):
+    off = _c(off, np.int32)
+    Nc = int(np.prod(coarse_dims(shape, cmask, True)))
+    Ac = np.zeros((27 * bs * bs, Nc))
+    lib().orc_rap_c64(*_dims(shape), off.shape[0], off.ravel(), int(bs), _c(Af, np.float64).ravel(), int(cmask),
+                      Ac.ravel())
+    return Ac
+
+
+def rap_c64_chains(off, cmask):
+    off = _c(off, np.int32)
+    return lib().orc_rap_c64_chains(off.shape[0], off.ravel(), int(cmask))
+
+
 def rap_cc_chains(off, cmask):
     off = _c(off, np.int32)
     return lib().orc_rap_cc_chains(off.shape[0], off.ravel(), int(cmask))
@@ -333,7 +358,7 @@ def f16_bits_to_f32(h):
 
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2}
 SMOOTHER = {"gs": 0, "ilu0": 1, "lgs": 2}
-INTERP = {"vertex": 0, "cell": 1}
+INTERP = {"vertex": 0, "cell": 1, "cell_trilinear": 2}
 
 
 class Hierarchy:

@@ -446,6 +446,101 @@ int orc_rap_cc_chains(int S, const int* off, int cmask) {
   return cnt;
 }
 
+/* ---- stencil Galerkin product of Cell_3d8 restriction and Cell_3d64
+ * interpolation (table of R/A/P combinations: R 3d8c, P 3d64c) ------------
+ * A_c(I, n) for the 27 coarse offsets n (canonical order): over the children
+ * f of I (lexicographic d), the fine offsets s (canonical) with g = f + s in
+ * the grid, and the interpolation contributors J of g (lexicographic, as in
+ * orc_prolong_add_c64) with J - I = n: acc = fma(A(f, s), w_J, acc) from
+ * zero.  Coarse operators are 27-point. */
+static int c64_parents(int g, int cm, int nc, int* par, double* wt) {
+  if (!cm) { par[0] = g; wt[0] = 1.0; return 1; }
+  int I = g / 2, J = (g & 1) ? I + 1 : I - 1, n = 0;
+  int lo = J < I ? J : I, hi = J < I ? I : J;
+  if (lo >= 0 && lo < nc) { par[n] = lo; wt[n] = lo == I ? 0.75 : 0.25; ++n; }
+  if (hi >= 0 && hi < nc) { par[n] = hi; wt[n] = hi == I ? 0.75 : 0.25; ++n; }
+  return n;
+}
+
+void orc_rap_c64(int nxf, int nyf, int nzf, int S, const int* off, int bs, const double* Af, int cmask, double* Ac) {
+  int nf[3] = {nxf, nyf, nzf}, nc[3], cm[3];
+  for (int a = 0; a < 3; ++a) {
+    cm[a] = (cmask >> a) & 1;
+    nc[a] = cm[a] ? (nf[a] + 1) / 2 : nf[a];
+  }
+  long Nf = (long)nf[0] * nf[1] * nf[2], Nc = (long)nc[0] * nc[1] * nc[2];
+  int be = bs * bs, off27[81];
+  orc_pattern(27, off27);
+  for (int X = 0; X < nc[0]; ++X)
+    for (int Y = 0; Y < nc[1]; ++Y)
+      for (int Z = 0; Z < nc[2]; ++Z) {
+        int I[3] = {X, Y, Z};
+        long ic = ((long)X * nc[1] + Y) * nc[2] + Z;
+        for (int n = 0; n < 27; ++n)
+          for (int e = 0; e < be; ++e) {
+            double acc = 0.0;
+            for (int dx = 0; dx <= cm[0]; ++dx)
+              for (int dy = 0; dy <= cm[1]; ++dy)
+                for (int dz = 0; dz <= cm[2]; ++dz) {
+                  int d[3] = {dx, dy, dz}, f[3], skip = 0;
+                  for (int a = 0; a < 3; ++a) {
+                    f[a] = cm[a] ? 2 * I[a] + d[a] : I[a];
+                    if (f[a] >= nf[a]) skip = 1;
+                  }
+                  if (skip) continue;
+                  long i = ((long)f[0] * nf[1] + f[1]) * nf[2] + f[2];
+                  for (int s = 0; s < S; ++s) {
+                    int g[3], par[3][2], np[3], out = 0;
+                    double wt[3][2];
+                    for (int a = 0; a < 3; ++a) {
+                      g[a] = f[a] + off[3 * s + a];
+                      if (g[a] < 0 || g[a] >= nf[a]) out = 1;
+                    }
+                    if (out) continue;
+                    for (int a = 0; a < 3; ++a) np[a] = c64_parents(g[a], cm[a], nc[a], par[a], wt[a]);
+                    double av = Af[((long)s * be + e) * Nf + i];
+                    for (int p = 0; p < np[0]; ++p)
+                      for (int q = 0; q < np[1]; ++q)
+                        for (int r = 0; r < np[2]; ++r)
+                          if (par[0][p] - X == off27[3 * n] && par[1][q] - Y == off27[3 * n + 1] &&
+                              par[2][r] - Z == off27[3 * n + 2])
+                            acc = fma(av, wt[0][p] * wt[1][q] * wt[2][r], acc);
+                  }
+                }
+            Ac[((long)n * be + e) * Nc + ic] = acc;
+          }
+      }
+}
+
+/* Influence chains of the (3d8c, A, 3d64c) product for an interior coarse
+ * cell: (child, fine offset, interpolation contributor) triples summed over
+ * the 27 coarse offsets (Table of chain counts). */
+int orc_rap_c64_chains(int S, const int* off, int cmask) {
+  int cnt = 0, I[3] = {4, 4, 4}, cm[3], off27[81];
+  orc_pattern(27, off27);
+  for (int a = 0; a < 3; ++a) cm[a] = (cmask >> a) & 1;
+  for (int n = 0; n < 27; ++n)
+    for (int dx = 0; dx <= cm[0]; ++dx)
+      for (int dy = 0; dy <= cm[1]; ++dy)
+        for (int dz = 0; dz <= cm[2]; ++dz) {
+          int d[3] = {dx, dy, dz};
+          for (int s = 0; s < S; ++s) {
+            int par[3][2], np[3];
+            double wt[3][2];
+            for (int a = 0; a < 3; ++a) {
+              int f = cm[a] ? 2 * I[a] + d[a] : I[a];
+              np[a] = c64_parents(f + off[3 * s + a], cm[a], 64, par[a], wt[a]);
+            }
+            for (int p = 0; p < np[0]; ++p)
+              for (int q = 0; q < np[1]; ++q)
+                for (int r = 0; r < np[2]; ++r)
+                  cnt += par[0][p] - I[0] == off27[3 * n] && par[1][q] - I[1] == off27[3 * n + 1] &&
+                         par[2][r] - I[2] == off27[3 * n + 2];
+          }
+        }
+  return cnt;
+}
+
 /* ---- Thomas factorisation of the z-columns (Sec. 4.4, LGS paragraph) ---
  * For every column (x, y) the tridiagonal block of A on that column: a_z =
  * coupling to z-1, b_z = centre, c_z = coupling to z+1 (zero at the column
@@ -558,7 +653,9 @@ void orc_mg_destroy(omg* mg);
  * 7 / 19 / 27 = that mask for the finest matrix (coarse levels keep their
  * own 27-point pattern).  cell = 0: vertex-centred trilinear P, R = P^T,
  * coarse levels 27-point; cell = 1: cell-centred piecewise-constant P and
- * R = P^T (Cell_3d8), every level keeps the finest pattern.  A0 is copied;
+ * R = P^T (Cell_3d8), every level keeps the finest pattern; cell = 2:
+ * Cell_3d8 restriction with cell-centred trilinear interpolation (3d64c),
+ * coarse levels 27-point.  A0 is copied;
  * out-of-grid couplings are zeroed.
  * Returns NULL on error (zero pivot, coarsest level too large).
  */
@@ -577,7 +674,7 @@ omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0
     olev* v = &mg->lev[l];
     v->nx = n[0]; v->ny = n[1]; v->nz = n[2];
     v->N = (long)n[0] * n[1] * n[2];
-    v->S = orc_pattern(l == 0 || cell ? pattern : 27, v->off);
+    v->S = orc_pattern(l == 0 || cell == 1 ? pattern : 27, v->off);
     v->A = (double*)malloc(sizeof(double) * v->S * be * v->N);
     if (l == 0) {
       for (int s = 0; s < v->S; ++s)
@@ -590,8 +687,10 @@ omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0
         }
     } else {
       olev* p = &mg->lev[l - 1];
-      if (cell)
+      if (cell == 1)
         orc_rap_cc(p->nx, p->ny, p->nz, p->S, p->off, bs, p->A, p->cmask, v->A);
+      else if (cell == 2)
+        orc_rap_c64(p->nx, p->ny, p->nz, p->S, p->off, bs, p->A, p->cmask, v->A);
       else
         orc_rap(p->nx, p->ny, p->nz, p->S, p->off, bs, p->A, p->cmask, v->A);
     }

@@ -141,3 +141,28 @@ def cell_interp_matrix(shape, cmask):
                 J = tuple(f[a] // 2 if (cmask >> a) & 1 else f[a] for a in range(3))
                 P[lin(shape, *f), lin(cs, *J)] = 1.0
     return P, cs
+
+
+def cell_trilinear_matrix(shape, cmask):
+    """Explicit cell-centred trilinear interpolation (Nf x Nc): on a coarsened
+    axis fine cell 2I + d takes weight 3/4 from I and 1/4 from I - 1 (d = 0)
+    or I + 1 (d = 1), contributors outside the coarse grid dropped; weights of
+    the axes multiply."""
+    cs = tuple((n + 1) // 2 if (cmask >> a) & 1 else n for a, n in enumerate(shape))
+    P = np.zeros((int(np.prod(shape)), int(np.prod(cs))))
+
+    def axis(f, a):
+        if not (cmask >> a) & 1:
+            return [(f, 1.0)]
+        I = f // 2
+        J = I + 1 if f % 2 else I - 1
+        return [(k, w) for k, w in ((I, 0.75), (J, 0.25)) if 0 <= k < cs[a]]
+
+    for x in range(shape[0]):
+        for y in range(shape[1]):
+            for z in range(shape[2]):
+                for jx, wx in axis(x, 0):
+                    for jy, wy in axis(y, 1):
+                        for jz, wz in axis(z, 2):
+                            P[lin(shape, x, y, z), lin(cs, jx, jy, jz)] += wx * wy * wz
+    return P, cs

@@ -437,6 +437,65 @@ def test_rap_cc_chain_count_and_symmetry():
         assert np.allclose(Mc, Mc.T, rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("shape", [(6, 5, 7), (8, 8, 8), (7, 3, 9)])
+@pytest.mark.parametrize("cmask", [7, 3, 6])
+def test_cell_trilinear_interpolation(shape, cmask):
+    """3d64c interpolation against its explicit matrix; interior rows sum to 1
+    (constants are interpolated exactly away from the boundary)."""
+    P, cs = helpers.cell_trilinear_matrix(shape, cmask)
+    g = workloads.rng(3)
+    u = g.uniform(-1, 1, size=shape)
+    e = g.uniform(-1, 1, size=cs)
+    assert np.allclose(oracle.prolong_add_c64(u, e, cmask).ravel(), u.ravel() + P @ e.ravel(), rtol=0, atol=1e-15)
+    one = oracle.prolong_add_c64(np.zeros(shape), np.ones(cs), cmask)
+    inner = tuple(slice(1, n - 1) if (cmask >> a) & 1 else slice(None) for a, n in enumerate(shape))
+    assert np.array_equal(one[inner], np.ones_like(one[inner]))
+
+
+@pytest.mark.parametrize("npts", [7, 19, 27])
+@pytest.mark.parametrize("shape,cmask", [((6, 5, 7), 7), ((8, 6, 5), 3), ((5, 8, 6), 5), ((7, 7, 7), 7)])
+def test_rap_c64_matches_dense(npts, shape, cmask):
+    """Stencil product of the Cell_3d8 restriction and the 3d64c
+    interpolation = R A P assembled densely (R = transpose of the
+    piecewise-constant interpolation); 27-point coarse operator."""
+    off = workloads.offsets(npts)
+    A = workloads.random_sgdia(shape, npts, seed=13, symmetric=False)
+    M = helpers.dense_from_sgdia(A, off, shape)
+    R, cs = helpers.cell_interp_matrix(shape, cmask)
+    P, _ = helpers.cell_trilinear_matrix(shape, cmask)
+    Ac = oracle.rap_c64(off, A, shape, cmask)
+    ref = R.T @ M @ P
+    assert np.allclose(helpers.dense_from_sgdia(Ac, workloads.offsets(27), cs), ref, rtol=0,
+                       atol=1e-13 * np.abs(M).max())
+
+
+def test_rap_c64_chain_counts():
+    tab = _gold_tables()
+    for npts in (19, 27):
+        assert oracle.rap_c64_chains(workloads.offsets(npts), 7) == int(tab[("chains", "3d8c", f"3d{npts}", "3d64c")])
+    assert oracle.rap_c64_chains(workloads.offsets(7), 7) == 8 * 7 * 8
+
+
+def test_cell_trilinear_hierarchy_converges():
+    """Cell_3d8 restriction with 3d64c interpolation (the paper's Laplace
+    setting): 27-point coarse levels, PCG on the Laplacian as fast as the
+    vertex-centred hierarchy; R != P^T makes the cycle non-symmetric, so the
+    high-contrast diffusion case is solved with GMRES."""
+    A, b = workloads.poisson7(24)
+    its = {}
+    for interp in ("vertex", "cell_trilinear"):
+        H = oracle.Hierarchy((24, 24, 24), 7, A, interp=interp)
+        _, st, its[interp], rel = H.pcg(b.reshape(24, 24, 24), 1e-9, 100)
+        assert st == 0 and rel < 1e-9
+    assert H.level_info(1)["S"] == 27 and H.level_info(1)["dims"] == (12, 12, 12)
+    assert its["cell_trilinear"] <= its["vertex"] + 1
+    shape = (24, 24, 24)
+    A, b = workloads.diffusion7(shape, seed=2, nspheres=3, rmin=3.0, rmax=8.0)
+    H = oracle.Hierarchy(shape, 7, A, interp="cell_trilinear")
+    _, st, it, rel = H.gmres(b.reshape(shape), 1e-9, 200)
+    assert st == 0 and rel < 1e-9
+
+
 @pytest.mark.parametrize("npts", [7, 27])
 def test_cell_vcycle_symmetric_and_pcg(npts):
     """Cell-centred hierarchy: every level keeps the fine pattern, the V(1,1)
