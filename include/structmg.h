@@ -55,7 +55,7 @@ typedef enum {
 typedef enum { SMG_SMOOTH_GS = 0, SMG_SMOOTH_ILU0 = 1, SMG_SMOOTH_LGS = 2 } smg_smoother;
 typedef enum { SMG_COARSEN_FULL = 0, SMG_COARSEN_SEMI_XY = 1 } smg_coarsen;
 typedef enum { SMG_FP64 = 0, SMG_FP32 = 1, SMG_FP16_ROWSCALE = 2 } smg_prec;
-typedef enum { SMG_INTERP_VERTEX = 0, SMG_INTERP_CELL = 1 } smg_interp;
+typedef enum { SMG_INTERP_VERTEX = 0, SMG_INTERP_CELL = 1, SMG_INTERP_CELL_TRILINEAR = 2 } smg_interp;
 
 typedef struct {
   int nx, ny, nz;      /* finest grid */
@@ -83,7 +83,11 @@ typedef struct {
                           combinations, Cell_3d8 interpolation and restriction): coarse
                           cell I owns fine cells 2I, 2I+1 per coarsened axis,
                           n_c = ceil(n_f/2), R = P^T, every level keeps the finest
-                          pattern (scalar systems) */
+                          pattern; or that restriction with cell-centred trilinear
+                          interpolation (Cell_3d64: 3/4 from the parent cell, 1/4 from
+                          the neighbour on the fine cell's side, per axis), 27-point
+                          coarse levels, R != P^T (use GMRES unless A is benign).
+                          Cell-centred transfers take scalar systems. */
 } smg_config;
 
 typedef struct {

@@ -190,6 +190,13 @@ template <class V>
 hipError_t launch_prolong_cc(const Grid& gf, int cmask, int bs, const V* ec, const V* uin, V* uout, hipStream_t st);
 hipError_t launch_rap_cc(int pat, int cmask, const Grid& gf, const double* A, long sA, double* Ac, long sAc,
                          hipStream_t st);
+// cell-centred trilinear interpolation (3d64c; same grid map): uout = uin + P ec,
+// and the 27-point product of the Cell_3d8 restriction, A and this P
+template <class V>
+hipError_t launch_prolong_c64(const Grid& gf, int cmask, int bs, const V* ec, const V* uin, V* uout,
+                              hipStream_t st);
+hipError_t launch_rap_c64(int pat, int cmask, const Grid& gf, const double* A, long sA, double* Ac, long sAc,
+                          hipStream_t st);
 
 // ---- block (3x3) variants (block.hip) --------------------------------
 // y = A x or y = b - A x on 3x3 blocks (27-point pattern)

@@ -107,8 +107,9 @@ const char* check_cfg(const smg_config* c) {
   if (c->ilu_mask != 0 && c->ilu_mask != 7 && c->ilu_mask != 19 && c->ilu_mask != 27)
     return "ilu_mask must be 0, 7, 19 or 27";
   if (c->ilu_mask != 0 && c->smoother != SMG_SMOOTH_ILU0) return "ilu_mask applies to the ILU(0) smoother only";
-  if (c->interp != SMG_INTERP_VERTEX && c->interp != SMG_INTERP_CELL) return "unknown interpolation";
-  if (c->interp == SMG_INTERP_CELL && c->block != 1) return "cell-centred transfers are implemented for scalar systems";
+  if (c->interp != SMG_INTERP_VERTEX && c->interp != SMG_INTERP_CELL && c->interp != SMG_INTERP_CELL_TRILINEAR)
+    return "unknown interpolation";
+  if (c->interp != SMG_INTERP_VERTEX && c->block != 1) return "cell-centred transfers are implemented for scalar systems";
   return nullptr;
 }
 
@@ -136,7 +137,7 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
       break;
     }
     for (int a = 0; a < 3; ++a)
-      if ((v.cmask >> a) & 1) n[a] = cfg.interp == SMG_INTERP_CELL ? (n[a] + 1) / 2 : n[a] / 2;
+      if ((v.cmask >> a) & 1) n[a] = cfg.interp != SMG_INTERP_VERTEX ? (n[a] + 1) / 2 : n[a] / 2;
   }
   const long nc = L[nlev - 1].N * bs;
   if (nlev_out) *nlev_out = nlev;
@@ -350,10 +351,17 @@ hipError_t lgs_sweep(smg_handle_s* H, const Level& v, int dir, const typename PT
   return launch_lgs<V>(v.S, dir, uold == nullptr, a, st);
 }
 
+// uout = uin + P ec for the cell-centred interpolations (uout may be uin).
+template <class V>
+hipError_t prolong_cell(const smg_handle_s* H, const Level& v, const V* ec, const V* uin, V* uout, hipStream_t st) {
+  if (H->cfg.interp == SMG_INTERP_CELL_TRILINEAR) return launch_prolong_c64<V>(v.g, v.cmask, H->bs, ec, uin, uout, st);
+  return launch_prolong_cc<V>(v.g, v.cmask, H->bs, ec, uin, uout, st);
+}
+
 // uf += P ec with the handle's interpolation (bs components per point).
 template <class V>
 hipError_t prolong_in_place(const smg_handle_s* H, const Level& v, const V* ec, V* uf, hipStream_t st) {
-  if (H->cfg.interp == SMG_INTERP_CELL) return launch_prolong_cc<V>(v.g, v.cmask, H->bs, ec, uf, uf, st);
+  if (H->cfg.interp != SMG_INTERP_VERTEX) return prolong_cell<V>(H, v, ec, uf, uf, st);
   return launch_prolong_add<V>(v.g, v.cmask, H->bs, ec, uf, st);
 }
 
@@ -367,7 +375,7 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
   const int NL = H->nlev;
   const bool ilu = H->cfg.smoother == SMG_SMOOTH_ILU0;
   const bool lgs = H->cfg.smoother == SMG_SMOOTH_LGS;
-  const bool cell = H->cfg.interp == SMG_INTERP_CELL;
+  const bool cell = H->cfg.interp != SMG_INTERP_VERTEX;
   auto F = [&](int l) -> const V* { return l == 0 ? f0 : (const V*)H->lev[l].f; };
   auto UB = [&](int l) -> V* { return l == 0 ? z0 : (V*)H->lev[l].ub; };
   hipError_t e;
@@ -417,8 +425,7 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
     if (lgs) {
       {
         Timed t(H, l, 4, st);
-        e = cell ? launch_prolong_cc<V>(v.g, v.cmask, 1, (const V*)UB(l + 1), (const V*)v.ua, (V*)v.ua, st)
-                 : launch_prolong_add<V>(v.g, v.cmask, 1, (const V*)UB(l + 1), (V*)v.ua, st);
+        e = prolong_in_place<V>(H, v, (const V*)UB(l + 1), (V*)v.ua, st);
       }
       if (e != hipSuccess) return e;
       // backward line GS from u_a + P e_c; u_a gets its sentinels back
@@ -430,8 +437,7 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
         if (cell || split_rp(v)) {
           // u_old = u + P e_c in place (u_a is refilled by the sweep below),
           // then the backward sweep's old-value terms
-          e = cell ? launch_prolong_cc<V>(v.g, v.cmask, 1, (const V*)UB(l + 1), (const V*)v.ua, (V*)v.ua, st)
-                   : launch_prolong_add<V>(v.g, v.cmask, 1, (const V*)UB(l + 1), (V*)v.ua, st);
+          e = prolong_in_place<V>(H, v, (const V*)UB(l + 1), (V*)v.ua, st);
           if (e == hipSuccess) e = launch_lower(v.S, v.g, A, F(l), (const V*)v.ua, (V*)v.h, st);
         } else {
           e = launch_prolong_post(v.S, v.g, v.cmask, A, F(l), (const V*)v.ua, (const V*)UB(l + 1), (V*)v.h,
@@ -446,7 +452,7 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
         Timed t(H, l, 4, st);
         if (cell) {
           // u_old = u_a + P e_c into u_o, then h = f - A u_old
-          e = launch_prolong_cc<V>(v.g, v.cmask, 1, (const V*)UB(l + 1), (const V*)v.ua, (V*)v.uo, st);
+          e = prolong_cell<V>(H, v, (const V*)UB(l + 1), (const V*)v.ua, (V*)v.uo, st);
           if (e == hipSuccess) e = launch_spmv(v.S, v.g, A, (const V*)v.uo, F(l), (V*)v.h, true, st);
         } else {
           e = launch_prolong_post(v.S, v.g, v.cmask, A, F(l), (const V*)v.ua, (const V*)UB(l + 1), (V*)v.h,
@@ -582,6 +588,9 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
       if (cfg->interp == SMG_INTERP_CELL)
         SCHK(launch_rap_cc(f.S, f.cmask, f.g, f.A64 + (long)e * f.N, (long)be * f.N, c.A64 + (long)e * c.N,
                            (long)be * c.N, st));
+      else if (cfg->interp == SMG_INTERP_CELL_TRILINEAR)
+        SCHK(launch_rap_c64(f.S, f.cmask, f.g, f.A64 + (long)e * f.N, (long)be * f.N, c.A64 + (long)e * c.N,
+                            (long)be * c.N, st));
       else
         SCHK(launch_rap(f.S, f.cmask, f.g, f.A64 + (long)e * f.N, (long)be * f.N, c.A64 + (long)e * c.N,
                         (long)be * c.N, st));
@@ -1070,7 +1079,7 @@ static hipError_t op_postsmooth_t(smg_handle_s* H, const Level& v, const void* f
     // the V-cycle's kernels for this level: h = f - lower(A) u_old with
     // u_old = u_in + P ec (large levels: formed in u_a, whose sentinels are
     // restored after)
-    if (split_rp(v) || H->cfg.interp == SMG_INTERP_CELL) {
+    if (split_rp(v) || H->cfg.interp != SMG_INTERP_VERTEX) {
       e = hipMemcpyAsync(v.ua, uin, sizeof(V) * nv, hipMemcpyDeviceToDevice, st);
       if (e == hipSuccess && ec != nullptr) e = prolong_in_place<V>(H, v, (const V*)ec, (V*)v.ua, st);
       if (e == hipSuccess) e = launch_lower(v.S, v.g, A, (const V*)f, (const V*)v.ua, (V*)v.h, st);
@@ -1086,8 +1095,8 @@ static hipError_t op_postsmooth_t(smg_handle_s* H, const Level& v, const void* f
   }
   // ILU correction: r = f - A u_old; u_out = u_old + U^-1 L^-1 r.  Scratch: the
   // level's y1/y2/zz buffers, whose sentinel state is restored afterwards.
-  if (H->cfg.interp == SMG_INTERP_CELL) {
-    e = ec ? launch_prolong_cc<V>(v.g, v.cmask, 1, (const V*)ec, (const V*)uin, (V*)v.uo, st)
+  if (H->cfg.interp != SMG_INTERP_VERTEX) {
+    e = ec ? prolong_cell<V>(H, v, (const V*)ec, (const V*)uin, (V*)v.uo, st)
            : hipMemcpyAsync(v.uo, uin, sizeof(V) * nv, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = launch_spmv(v.S, v.g, A, (const V*)v.uo, (const V*)f, (V*)v.h, true, st);
   } else {
@@ -1153,7 +1162,7 @@ struct OpRR {
       if (e == hipSuccess) e = launch_restrict<V>(v.g, v.cmask, 3, (const V*)v.h, (V*)rc, st);
       return e;
     }
-    const bool cell = H->cfg.interp == SMG_INTERP_CELL;
+    const bool cell = H->cfg.interp != SMG_INTERP_VERTEX;
     if (!split_rp(v) && !cell)
       return launch_resid_restrict(v.S, v.g, v.cmask, PT::A(v), (const V*)f, (const V*)u, (V*)rc, st);
     hipError_t e = launch_spmv(v.S, v.g, PT::A(v), (const V*)u, (const V*)f, (V*)v.h, true, st);
@@ -1211,7 +1220,7 @@ smg_status smg_op_restrict(smg_handle h, int level, const void* rf, void* rc, vo
   if (!rf || !rc) return fail(h, SMG_EINVAL, "null vector");
   const Level& v = h->lev[level];
   const hipStream_t st = (hipStream_t)stream;
-  if (h->cfg.interp == SMG_INTERP_CELL) {
+  if (h->cfg.interp != SMG_INTERP_VERTEX) {
     if (h->cfg.prec == SMG_FP64)
       HIPCHK(h, launch_restrict_cc<double>(v.g, v.cmask, h->bs, (const double*)rf, (double*)rc, st));
     else

@@ -559,26 +559,30 @@ def test_ilu0_mask_bitexact(case, mask):
 
 # cell-centred piecewise-constant transfers (every level keeps the finest
 # pattern; odd sizes give coarse cells with a single child)
-CELL_CASES = [(CASES[0], "gs", "fp64"), (CASES[1], "gs", "fp64"), (CASES[2], "gs", "fp64"), (CASES[4], "gs", "fp64"),
-              (CASES[3], "ilu0", "fp64"), (CASES[1], "lgs", "fp64"), (CASES[0], "gs", "fp32"),
-              (CASES[6], "gs", "fp64")]
+CELL_CASES = [(CASES[0], "gs", "fp64", "cell"), (CASES[1], "gs", "fp64", "cell"), (CASES[2], "gs", "fp64", "cell"),
+              (CASES[4], "gs", "fp64", "cell"), (CASES[3], "ilu0", "fp64", "cell"), (CASES[1], "lgs", "fp64", "cell"),
+              (CASES[0], "gs", "fp32", "cell"), (CASES[6], "gs", "fp64", "cell"),
+              (CASES[0], "gs", "fp64", "cell_trilinear"), (CASES[1], "gs", "fp64", "cell_trilinear"),
+              (CASES[2], "ilu0", "fp64", "cell_trilinear"), (CASES[4], "gs", "fp32", "cell_trilinear"),
+              (CASES[3], "lgs", "fp64", "cell_trilinear")]
 
 
-@pytest.mark.parametrize("case,smoother,prec", CELL_CASES,
+@pytest.mark.parametrize("case,smoother,prec,interp", CELL_CASES,
                          ids=lambda v: v if isinstance(v, str) else _ids(v))
-def test_cell_centred_bitexact(case, smoother, prec):
+def test_cell_centred_bitexact(case, smoother, prec, interp):
     shape, pat, coarsen, semi = case
     A = workloads.random_sgdia(shape, pat, seed=3, symmetric=smoother != "ilu0")
     H = oracle.Hierarchy(shape, pat, A, smoother=smoother, coarsen=coarsen, semi_levels=semi, prec=prec,
-                         interp="cell")
+                         interp=interp)
     mg = smg.StructMG(T(A), shape, pattern=pat, smoother=smoother, coarsen=coarsen, semi_levels=semi, prec=prec,
-                      interp="cell", device=DEV)
+                      interp=interp, gmres_restart=30, device=DEV)
     assert mg.nlev == H.nlev
+    prolong = oracle.prolong_add_cc if interp == "cell" else oracle.prolong_add_c64
     dt, npt = (torch.float64, np.float64) if prec == "fp64" else (torch.float32, np.float32)
     g = workloads.rng(31)
     for l in range(H.nlev):
         inf = H.level_info(l)
-        assert mg.level_info(l)["dims"] == inf["dims"] and inf["S"] == pat
+        assert mg.level_info(l)["dims"] == inf["dims"] and inf["S"] == (pat if interp == "cell" or l == 0 else 27)
         Ar = H.level_data(l, 0)
         got = N(mg.export(l, 0, torch.empty(Ar.shape, dtype=torch.float64, device=DEV)))
         assert np.array_equal(got, Ar), f"cell RAP level {l}"
@@ -587,7 +591,7 @@ def test_cell_centred_bitexact(case, smoother, prec):
         dims, cm = inf["dims"], inf["cmask"]
         cdims = oracle.coarse_dims(dims, cm, cell=True)
         Al = Ar if prec == "fp64" else H.level_data(l, 5)
-        off = workloads.offsets(pat)
+        off = workloads.offsets(inf["S"])
         f = g.uniform(-1, 1, size=dims).astype(npt)
         u = g.uniform(-1, 1, size=dims).astype(npt)
         ec = g.uniform(-1, 1, size=cdims).astype(npt)
@@ -595,12 +599,12 @@ def test_cell_centred_bitexact(case, smoother, prec):
         assert np.array_equal(rc, oracle.restrict_cc(oracle.residual(off, Al, f, u), cm).ravel())
         uf = T(u.copy(), dt)
         mg.op_prolong_add(l, T(ec, dt), uf)
-        assert np.array_equal(N(uf).ravel(), oracle.prolong_add_cc(u, ec, cm).ravel())
+        assert np.array_equal(N(uf).ravel(), prolong(u, ec, cm).ravel())
         if smoother == "gs":
             rd = H.level_data(l, 1 if prec == "fp64" else 6).ravel()
             uo = N(mg.op_postsmooth(l, T(f, dt), T(u, dt), T(ec, dt), torch.empty(int(np.prod(dims)), dtype=dt,
                                                                                   device=DEV)))
-            ref = oracle.gs_sweep(off, Al, rd, f, oracle.prolong_add_cc(u, ec, cm), -1, 0)
+            ref = oracle.gs_sweep(off, Al, rd, f, prolong(u, ec, cm), -1, 0)
             assert np.array_equal(uo, ref.ravel()), f"cell post-smoothing level {l}"
     dims = H.level_info(0)["dims"]
     r = workloads.rng(9).uniform(-1, 1, size=dims)
@@ -609,9 +613,11 @@ def test_cell_centred_bitexact(case, smoother, prec):
     tol = 1e-12 if prec == "fp64" else 1e-5
     assert np.abs(z - zr).max() <= tol * np.abs(zr).max()
     if smoother == "gs" and prec == "fp64":
+        # the trilinear interpolation with R != P^T gives a non-symmetric cycle: GMRES
+        kr = 0 if interp == "cell" else 30
         b = workloads.rng(4).uniform(-1, 1, size=dims)
-        xr, st, itr, _ = H.pcg(b, 1e-9, 300)
+        xr, st, itr, _ = H.pcg(b, 1e-9, 300) if kr == 0 else H.gmres(b, 1e-9, 300, restart=kr)
         x = torch.zeros(b.size, dtype=torch.float64, device=DEV)
-        res = mg.solve(T(b.ravel()), x, rtol=1e-9, maxit=300)
+        res = mg.solve(T(b.ravel()), x, rtol=1e-9, maxit=300, krylov=kr)
         assert st == 0 and res["status"] == 0 and res["rel_resid_true"] < 1e-9
         assert abs(res["iters"] - itr) <= 1
