@@ -193,6 +193,40 @@ def extra_weather_lgs(args, smg, torch, np, dev):
                       "variants": res}), flush=True)
 
 
+def extra_diffusion_interp(args, smg, torch, np, dev):
+    """The benchmark's diffusion workload with the three hierarchies: vertex
+    trilinear (PCG), cell-centred piecewise constant (PCG) and Cell_3d8
+    restriction with cell-centred trilinear interpolation (non-symmetric
+    cycle: GMRES(30))."""
+    W = make_workload("diffusion256")
+    A = torch.from_numpy(W["A"]).to(dev)
+    b = torch.from_numpy(W["b"].ravel().copy()).to(dev)
+    x = torch.zeros_like(b)
+    res = {}
+    for interp, kr in (("vertex", 0), ("cell", 0), ("cell_trilinear", 30)):
+        m = smg.StructMG(A, W["shape"], device=dev, pattern=7, interp=interp, gmres_restart=kr)
+
+        def step():
+            m.resetup(A)
+            x.zero_()
+            return m.solve(b, x, rtol=1e-9, maxit=500, krylov=kr)
+
+        r, ms = _timed(step, torch, args.steps)
+        res[interp] = {"ms_per_step": round(ms, 2), "iters": r["iters"], "rel_resid_true": r["rel_resid_true"],
+                       "converged": r["status"] == 0 and r["rel_resid_true"] < 1e-9, "solver": "GMRES(30)" if kr
+                       else "PCG", "t_setup_ms": round(r["t_setup_ms"], 2), "t_solve_ms": round(r["t_solve_ms"], 2),
+                       "levels": r["levels"], "op_complexity": round(r["op_complexity"], 4)}
+        print(f"[bench] {interp}: {res[interp]}", file=sys.stderr, flush=True)
+        m.close()
+        del m
+    for k in res:
+        res[k]["speedup_vs_vertex"] = round(res["vertex"]["ms_per_step"] / res[k]["ms_per_step"], 3)
+    print(json.dumps({"metric": METRIC, "value": res["cell"]["ms_per_step"], "unit": "ms", "n_gpus": 1,
+                      "steps": args.steps, "higher_is_better": False, "dtype": "f64", "data": "synthetic (seeded)",
+                      "config": {"workload": W["desc"] + "; vertex-centred vs cell-centred hierarchies"},
+                      "variants": res}), flush=True)
+
+
 def extra_elasticity(args, smg, torch, np, dev):
     import workloads
     n = 128
@@ -262,7 +296,7 @@ def extra_batch(args, smg, torch, np, dev):
 
 
 EXTRA = {"weather512": extra_weather, "weather512_lgs": extra_weather_lgs, "elasticity128": extra_elasticity,
-         "reservoir_batch256": extra_batch}
+         "reservoir_batch256": extra_batch, "diffusion256_interp": extra_diffusion_interp}
 
 
 def main():
