@@ -66,6 +66,8 @@ def _declare(L):
         getattr(L, "orc_restrict_cc" + sfx).argtypes = [_i, _i, _i, _i, _i, p, p]
         getattr(L, "orc_prolong_add_cc" + sfx).argtypes = [_i, _i, _i, _i, _i, p, p]
         getattr(L, "orc_prolong_add_c64" + sfx).argtypes = [_i, _i, _i, _i, _i, p, p]
+        getattr(L, "orc_restrict_od" + sfx).argtypes = [_i, _i, _i, _i, _i, p, p, p]
+        getattr(L, "orc_prolong_add_od" + sfx).argtypes = [_i, _i, _i, _i, _i, p, p, p]
     L.orc_pattern.argtypes = [_i, _ip]
     L.orc_pattern.restype = _i
     L.orc_rap.argtypes = [_i, _i, _i, _i, _ip, _i, _dp, _i, _dp]
@@ -77,6 +79,9 @@ def _declare(L):
     L.orc_rap_c64.argtypes = [_i, _i, _i, _i, _ip, _i, _dp, _i, _dp]
     L.orc_rap_c64_chains.argtypes = [_i, _ip, _i]
     L.orc_rap_c64_chains.restype = _i
+    L.orc_od_weights.argtypes = [_i, _i, _i, _i, _ip, _dp, _i, _dp]
+    L.orc_od_weights.restype = _i
+    L.orc_rap_od.argtypes = [_i, _i, _i, _i, _ip, _dp, _i, _dp, _dp]
     L.orc_ilu0.argtypes = [_i, _i, _i, _i, _ip, _dp, _dp, _dp, _dp]
     L.orc_ilu0.restype = _i
     L.orc_ilu0_mask.argtypes = [_i, _i, _i, _i, _ip, _dp, _i, _ip, _dp, _dp, _dp]
@@ -238,6 +243,40 @@ def rap_c64_chains(off, cmask):
     return lib().orc_rap_c64_chains(off.shape[0], off.ravel(), int(cmask))
 
 
+def od_weights(off, A, shape, cmask):
+    """Operator-dependent interpolation weights W (8, N) of a vertex level."""
+    off = _c(off, np.int32)
+    W = np.zeros((8, int(np.prod(shape))))
+    if lib().orc_od_weights(*_dims(shape), off.shape[0], off.ravel(), _c(A, np.float64).ravel(), int(cmask),
+                            W.ravel()):
+        raise ValueError("zero collapsed diagonal")
+    return W
+
+
+def restrict_od(rf, W, cmask):
+    shp = rf.shape[:3]
+    rc = np.zeros(coarse_dims(shp, cmask), rf.dtype)
+    getattr(lib(), "orc_restrict_od" + _sfx(rf))(*_dims(shp), int(cmask), 1, _c(W, rf.dtype).ravel(),
+                                                _c(rf).ravel(), rc.ravel())
+    return rc
+
+
+def prolong_add_od(uf, W, ec, cmask):
+    shp = uf.shape[:3]
+    out = _c(uf).copy()
+    getattr(lib(), "orc_prolong_add_od" + _sfx(uf))(*_dims(shp), int(cmask), 1, _c(W, uf.dtype).ravel(),
+                                                   _c(ec).ravel(), out.ravel())
+    return out
+
+
+def rap_od(off, Af, shape, cmask, W):
+    off = _c(off, np.int32)
+    Ac = np.zeros((27, int(np.prod(coarse_dims(shape, cmask)))))
+    lib().orc_rap_od(*_dims(shape), off.shape[0], off.ravel(), _c(Af, np.float64).ravel(), int(cmask),
+                     _c(W, np.float64).ravel(), Ac.ravel())
+    return Ac
+
+
 def rap_cc_chains(off, cmask):
     off = _c(off, np.int32)
     return lib().orc_rap_cc_chains(off.shape[0], off.ravel(), int(cmask))
@@ -358,7 +397,7 @@ def f16_bits_to_f32(h):
 
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2}
 SMOOTHER = {"gs": 0, "ilu0": 1, "lgs": 2}
-INTERP = {"vertex": 0, "cell": 1, "cell_trilinear": 2}
+INTERP = {"vertex": 0, "cell": 1, "cell_trilinear": 2, "operator": 3}
 
 
 class Hierarchy:
@@ -400,7 +439,7 @@ class Hierarchy:
         S = inf["S"]
         Sm = inf["Sm"] or S
         sizes = {0: (S * be, N), 1: ((9 if self.bs == 3 else 1), N), 2: (Sm, N), 3: (Sm, N), 4: (1, N),
-                 5: (S * be, N), 6: ((9 if self.bs == 3 else 1), N), 7: (1, N), 8: (1, N)}
+                 5: (S * be, N), 6: ((9 if self.bs == 3 else 1), N), 7: (1, N), 8: (1, N), 9: (8, N)}
         dt = np.float32 if what in (5, 6) else np.float64
         out = np.zeros(sizes[what], dt)
         lib().orc_mg_level_data(self.h, l, what, out.ctypes.data_as(C.c_void_p))

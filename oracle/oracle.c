@@ -541,6 +541,163 @@ int orc_rap_c64_chains(int S, const int* off, int cmask) {
   return cnt;
 }
 
+/* ---- operator-dependent vertex interpolation (Listing 1 caption: P and R
+ * vary from element to element; Dendy's black-box collapse) -------------
+ * Grid map of the vertex hierarchy (coarse X <-> fine 2X+1 on coarsened
+ * axes).  For fine point f let E(f) be the coarsened axes on which f is even
+ * (between two coarse points); its corners on such an axis are lo = f/2 - 1
+ * and hi = f/2, on the other axes the single parent.  W[c*N + f], c =
+ * (cx*2 + cy)*2 + cz in {0..7} with c_a = 0 for lo or the single parent, 1
+ * for hi: the weight of f's corner c.  Points with E(f) empty have W = 1 at
+ * c = 0.  Otherwise, in order of |E(f)| = 1, 2, 3, with the stencil collapsed
+ * onto the axes of E(f):
+ *   Abar(f, d) = sum over the offsets s (canonical) with s_a = d_a on the
+ *                axes a of E(f) of A(f, s)  (plain additions from zero),
+ *   W(f, c) = -( sum over d != 0 in the box of E(f) (lexicographic), with
+ *              g = f + d in the grid, of fma(Abar(f, d), W(g, c'), .) ) * r,
+ *   r = 1 / Abar(f, 0),
+ * where g contributes to c only if c_a = 1 when d_a = +1 and c_a = 0 when
+ * d_a = -1 (g sits on that corner's line), and c'_a = (d_a == 0 ? c_a : 0).
+ * Returns 0, or -1 on a zero collapsed diagonal. */
+static int od_nbits(int f, int cm) { return cm && !(f & 1); }
+
+int orc_od_weights(int nxf, int nyf, int nzf, int S, const int* off, const double* A, int cmask, double* W) {
+  int nf[3] = {nxf, nyf, nzf}, cm[3];
+  long N = (long)nxf * nyf * nzf;
+  for (int a = 0; a < 3; ++a) cm[a] = (cmask >> a) & 1;
+  for (int k = 0; k <= 3; ++k)
+    for (int X = 0; X < nf[0]; ++X)
+      for (int Y = 0; Y < nf[1]; ++Y)
+        for (int Z = 0; Z < nf[2]; ++Z) {
+          int f[3] = {X, Y, Z}, ev[3], ne = 0;
+          for (int a = 0; a < 3; ++a) ne += ev[a] = od_nbits(f[a], cm[a]);
+          if (ne != k) continue;
+          long i = ((long)X * nf[1] + Y) * nf[2] + Z;
+          if (k == 0) {
+            for (int c = 0; c < 8; ++c) W[(long)c * N + i] = c == 0 ? 1.0 : 0.0;
+            continue;
+          }
+          double Ab[27];
+          for (int d = 0; d < 27; ++d) {
+            int dd[3] = {d / 9 - 1, (d / 3) % 3 - 1, d % 3 - 1}, skip = 0;
+            for (int a = 0; a < 3; ++a)
+              if (!ev[a] && dd[a] != 0) skip = 1;
+            Ab[d] = 0.0;
+            if (skip) continue;
+            for (int s2 = 0; s2 < S; ++s2) {
+              int match = 1;
+              for (int a = 0; a < 3; ++a)
+                if (ev[a] && off[3 * s2 + a] != dd[a]) match = 0;
+              if (match) Ab[d] = Ab[d] + A[(long)s2 * N + i];
+            }
+          }
+          if (Ab[13] == 0.0) return -1;
+          double r = 1.0 / Ab[13];
+          for (int c = 0; c < 8; ++c) {
+            int cc[3] = {c / 4, (c / 2) % 2, c % 2}, used = 1;
+            for (int a = 0; a < 3; ++a)
+              if (!ev[a] && cc[a]) used = 0;
+            double acc = 0.0;
+            if (used)
+              for (int d = 0; d < 27; ++d) {
+                int dd[3] = {d / 9 - 1, (d / 3) % 3 - 1, d % 3 - 1}, g[3], ok = 1, cp = 0;
+                if (d == 13) continue;
+                for (int a = 0; a < 3; ++a) {
+                  if (!ev[a] && dd[a] != 0) ok = 0;
+                  if (dd[a] == 1 && cc[a] != 1) ok = 0;
+                  if (dd[a] == -1 && cc[a] != 0) ok = 0;
+                  g[a] = f[a] + dd[a];
+                  if (g[a] < 0 || g[a] >= nf[a]) ok = 0;
+                }
+                if (!ok) continue;
+                for (int a = 0; a < 3; ++a) cp = cp * 2 + (dd[a] == 0 ? cc[a] : 0);
+                long j = ((long)g[0] * nf[1] + g[1]) * nf[2] + g[2];
+                acc = fma(Ab[d], W[(long)cp * N + j], acc);
+              }
+            W[(long)c * N + i] = used ? -acc * r : 0.0;
+          }
+        }
+  return 0;
+}
+
+/* Corner c' of fine point g that is coarse point J (per axis: the single
+ * parent, or lo / hi of an even coordinate), or -1 if J is not a corner. */
+static int od_corner(const int* g, const int* cm, const int* J) {
+  int c = 0;
+  for (int a = 0; a < 3; ++a) {
+    int b;
+    if (!cm[a]) b = J[a] == g[a] ? 0 : -1;
+    else if (g[a] & 1) b = J[a] == (g[a] - 1) / 2 ? 0 : -1;
+    else b = J[a] == g[a] / 2 - 1 ? 0 : (J[a] == g[a] / 2 ? 1 : -1);
+    if (b < 0) return -1;
+    c = c * 2 + b;
+  }
+  return c;
+}
+
+/* Galerkin product with the operator-dependent P and R = P^T: for coarse I
+ * and the 27 coarse offsets n (J = I + n in the coarse grid), over the fine
+ * points u = fine(I) + rho (rho lexicographic over the box of the coarsened
+ * axes, u in the grid) of which I is a corner:
+ * t = sum over the canonical s with g = u + s in the grid and J a corner of g
+ * of fma(A(u, s), W(g, corner J), t) from zero; then
+ * acc = fma(W(u, corner I), t, acc) (the per-u partial sum times R(I, u), as
+ * in the grouping of Listing 1).  Coarse operators are 27-point. */
+void orc_rap_od(int nxf, int nyf, int nzf, int S, const int* off, const double* Af, int cmask, const double* W,
+                double* Ac) {
+  int nf[3] = {nxf, nyf, nzf}, nc[3], cm[3];
+  for (int a = 0; a < 3; ++a) {
+    cm[a] = (cmask >> a) & 1;
+    nc[a] = cm[a] ? nf[a] / 2 : nf[a];
+  }
+  long Nf = (long)nf[0] * nf[1] * nf[2], Nc = (long)nc[0] * nc[1] * nc[2];
+  int off27[81];
+  orc_pattern(27, off27);
+  for (int X = 0; X < nc[0]; ++X)
+    for (int Y = 0; Y < nc[1]; ++Y)
+      for (int Z = 0; Z < nc[2]; ++Z) {
+        int I[3] = {X, Y, Z}, fI[3];
+        for (int a = 0; a < 3; ++a) fI[a] = cm[a] ? 2 * I[a] + 1 : I[a];
+        long ic = ((long)X * nc[1] + Y) * nc[2] + Z;
+        for (int n = 0; n < 27; ++n) {
+          int J[3], inJ = 1;
+          for (int a = 0; a < 3; ++a) {
+            J[a] = I[a] + off27[3 * n + a];
+            if (J[a] < 0 || J[a] >= nc[a]) inJ = 0;
+          }
+          double acc = 0.0;
+          if (inJ)
+            for (int rho = 0; rho < 27; ++rho) {
+              int rr[3] = {rho / 9 - 1, (rho / 3) % 3 - 1, rho % 3 - 1}, u[3], ok = 1;
+              for (int a = 0; a < 3; ++a) {
+                if (!cm[a] && rr[a] != 0) ok = 0;
+                u[a] = fI[a] + rr[a];
+                if (u[a] < 0 || u[a] >= nf[a]) ok = 0;
+              }
+              if (!ok) continue;
+              int cu = od_corner(u, cm, I);
+              if (cu < 0) continue;
+              long iu = ((long)u[0] * nf[1] + u[1]) * nf[2] + u[2];
+              double t = 0.0;
+              for (int s2 = 0; s2 < S; ++s2) {
+                int g[3], in = 1;
+                for (int a = 0; a < 3; ++a) {
+                  g[a] = u[a] + off[3 * s2 + a];
+                  if (g[a] < 0 || g[a] >= nf[a]) in = 0;
+                }
+                if (!in) continue;
+                int cg = od_corner(g, cm, J);
+                if (cg < 0) continue;
+                long ig = ((long)g[0] * nf[1] + g[1]) * nf[2] + g[2];
+                t = fma(Af[(long)s2 * Nf + iu], W[(long)cg * Nf + ig], t);
+              }
+              acc = fma(W[(long)cu * Nf + iu], t, acc);
+            }
+          Ac[(long)n * Nc + ic] = acc;
+        }
+      }
+}
+
 /* ---- Thomas factorisation of the z-columns (Sec. 4.4, LGS paragraph) ---
  * For every column (x, y) the tridiagonal block of A on that column: a_z =
  * coupling to z-1, b_z = centre, c_z = coupling to z+1 (zero at the column
@@ -580,6 +737,8 @@ typedef struct {
   int Sm, offm[81]; /* ILU(0) mask (the level's own pattern unless chosen) */
   double *A, *rd, *L, *U, *rU;           /* FP64 level data */
   double *tr, *tc;                       /* Thomas factors rden, cp (line GS) */
+  double* W;                             /* operator-dependent interpolation weights (8 x N) */
+  float* W32;
   float *A32, *rd32, *L32, *U32, *rU32;  /* truncated level data */
   float *tr32, *tc32;
   double *f, *u, *r, *w, *d;             /* FP64 work vectors (d: one column) */
@@ -655,7 +814,8 @@ void orc_mg_destroy(omg* mg);
  * coarse levels 27-point; cell = 1: cell-centred piecewise-constant P and
  * R = P^T (Cell_3d8), every level keeps the finest pattern; cell = 2:
  * Cell_3d8 restriction with cell-centred trilinear interpolation (3d64c),
- * coarse levels 27-point.  A0 is copied;
+ * coarse levels 27-point; cell = 3: operator-dependent vertex interpolation
+ * (orc_od_weights) with R = P^T, coarse levels 27-point.  A0 is copied;
  * out-of-grid couplings are zeroed.
  * Returns NULL on error (zero pivot, coarsest level too large).
  */
@@ -663,6 +823,7 @@ omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0
                    int semi_levels, int prec, int max_coarse, int ilu_mask, int cell) {
   if (smoother == 2 && (bs != 1 || prec == 2)) return NULL;
   if (ilu_mask != 0 && (smoother != 1 || (ilu_mask != 7 && ilu_mask != 19 && ilu_mask != 27))) return NULL;
+  if (cell == 3 && bs != 1) return NULL;
   omg* mg = (omg*)calloc(1, sizeof(omg));
   mg->bs = bs;
   mg->cell = cell;
@@ -687,7 +848,9 @@ omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0
         }
     } else {
       olev* p = &mg->lev[l - 1];
-      if (cell == 1)
+      if (cell == 3)
+        orc_rap_od(p->nx, p->ny, p->nz, p->S, p->off, p->A, p->cmask, p->W, v->A);
+      else if (cell == 1)
         orc_rap_cc(p->nx, p->ny, p->nz, p->S, p->off, bs, p->A, p->cmask, v->A);
       else if (cell == 2)
         orc_rap_c64(p->nx, p->ny, p->nz, p->S, p->off, bs, p->A, p->cmask, v->A);
@@ -711,8 +874,15 @@ omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0
       v->cmask = 0;
       break;
     }
+    if (cell == 3) {
+      v->W = (double*)malloc(sizeof(double) * 8 * v->N);
+      if (orc_od_weights(v->nx, v->ny, v->nz, v->S, v->off, v->A, v->cmask, v->W)) {
+        orc_mg_destroy(mg);
+        return NULL;
+      }
+    }
     for (int a = 0; a < 3; ++a)
-      if ((v->cmask >> a) & 1) n[a] = cell ? (n[a] + 1) / 2 : n[a] / 2;
+      if ((v->cmask >> a) & 1) n[a] = cell == 1 || cell == 2 ? (n[a] + 1) / 2 : n[a] / 2;
     ++l;
   }
   /* smoother data on all but the coarsest level */
@@ -754,6 +924,7 @@ omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0
         v->tr32 = to_f32(v->tr, v->N);
         v->tc32 = to_f32(v->tc, v->N);
       }
+      if (cell == 3) v->W32 = to_f32(v->W, 8 * v->N);
     }
   }
   /* coarsest: dense FP64 LU */
@@ -783,7 +954,7 @@ void orc_mg_destroy(omg* mg) {
     olev* v = &mg->lev[l];
     free(v->A); free(v->rd); free(v->L); free(v->U); free(v->rU);
     free(v->A32); free(v->rd32); free(v->L32); free(v->U32); free(v->rU32);
-    free(v->tr); free(v->tc); free(v->tr32); free(v->tc32);
+    free(v->tr); free(v->tc); free(v->tr32); free(v->tc32); free(v->W); free(v->W32);
     free(v->f); free(v->u); free(v->r); free(v->w); free(v->d);
     free(v->f32); free(v->u32); free(v->r32); free(v->w32); free(v->d32);
   }
@@ -802,7 +973,8 @@ void orc_mg_level_info(const omg* mg, int l, int* info) {
 }
 
 /* Copies out level data: what = 0 A, 1 rd (or block Dinv), 2 L, 3 U, 4 rU,
- * 5 truncated A (as float), 6 truncated rd, 7 Thomas rden, 8 Thomas cp. */
+ * 5 truncated A (as float), 6 truncated rd, 7 Thomas rden, 8 Thomas cp,
+ * 9 operator-dependent interpolation weights (8 x N). */
 void orc_mg_level_data(const omg* mg, int l, int what, void* out) {
   const olev* v = &mg->lev[l];
   long be = (long)mg->bs * mg->bs;
@@ -816,6 +988,7 @@ void orc_mg_level_data(const omg* mg, int l, int what, void* out) {
     case 6: memcpy(out, v->rd32, sizeof(float) * (mg->bs == 3 ? 9 : 1) * v->N); break;
     case 7: memcpy(out, v->tr, sizeof(double) * v->N); break;
     case 8: memcpy(out, v->tc, sizeof(double) * v->N); break;
+    case 9: memcpy(out, v->W, sizeof(double) * 8 * v->N); break;
   }
 }
 
@@ -831,6 +1004,7 @@ void orc_mg_level_data(const omg* mg, int l, int what, void* out) {
 #define FTR tr
 #define FTC tc
 #define FD d
+#define FPW W
 #define REAL double
 #define SFX _f64
 #include "oracle_vcycle.inc"
@@ -848,6 +1022,7 @@ void orc_mg_level_data(const omg* mg, int l, int what, void* out) {
 #undef FTR
 #undef FTC
 #undef FD
+#undef FPW
 
 #define FF f32
 #define FU_ u32
@@ -861,6 +1036,7 @@ void orc_mg_level_data(const omg* mg, int l, int what, void* out) {
 #define FTR tr32
 #define FTC tc32
 #define FD d32
+#define FPW W32
 #define REAL float
 #define SFX _f32
 #include "oracle_vcycle.inc"

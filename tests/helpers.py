@@ -166,3 +166,30 @@ def cell_trilinear_matrix(shape, cmask):
                         for jz, wz in axis(z, 2):
                             P[lin(shape, x, y, z), lin(cs, jx, jy, jz)] += wx * wy * wz
     return P, cs
+
+
+def od_matrix(W, shape, cmask):
+    """Explicit interpolation matrix (Nf x Nc) of operator-dependent weights
+    W (8, Nf): weight c of fine point f belongs to its corner c, whose index on
+    a coarsened axis is (f-1)/2 for odd f (c_a = 0) or f/2 - 1 + c_a for even
+    f, and f itself on other axes; corners outside the coarse grid and c_a = 1
+    on a non-even axis carry nothing."""
+    cs = tuple(n // 2 if (cmask >> a) & 1 else n for a, n in enumerate(shape))
+    P = np.zeros((int(np.prod(shape)), int(np.prod(cs))))
+    for x in range(shape[0]):
+        for y in range(shape[1]):
+            for z in range(shape[2]):
+                f = (x, y, z)
+                i = lin(shape, *f)
+                for c in range(8):
+                    cc = (c // 4, (c // 2) % 2, c % 2)
+                    J = []
+                    for a in range(3):
+                        if not (cmask >> a) & 1 or f[a] % 2:
+                            j = (f[a] if not (cmask >> a) & 1 else (f[a] - 1) // 2) if cc[a] == 0 else -1
+                        else:
+                            j = f[a] // 2 - 1 + cc[a]
+                        J.append(j)
+                    if all(0 <= J[a] < cs[a] for a in range(3)):
+                        P[i, lin(cs, *J)] += W[c, i]
+    return P, cs

@@ -496,6 +496,85 @@ def test_cell_trilinear_hierarchy_converges():
     assert st == 0 and rel < 1e-9
 
 
+def test_od_interpolation_is_trilinear_for_the_laplacian():
+    """On the constant-coefficient 3d7 Laplacian the collapsed stencils give
+    weights 1/2, 1/4, 1/8: away from the boundary the operator-dependent
+    interpolation is the trilinear one, exactly."""
+    n = 16
+    A, _ = workloads.poisson7(n)
+    W = oracle.od_weights(workloads.offsets(7), A, (n, n, n), 7)
+    P, _ = helpers.od_matrix(W, (n, n, n), 7)
+    T, _ = helpers.interp_matrix((n, n, n), 7)
+    inner = [helpers.lin((n, n, n), x, y, z) for x in range(2, n - 2) for y in range(2, n - 2) for z in range(2, n - 2)]
+    assert np.array_equal(P[inner], T[inner])
+
+
+def test_od_interpolation_closed_forms():
+    """1D: weight -a_(i,i+-1) / a_ii; zero row sums: constants are
+    interpolated exactly (the weights of each fine point sum to 1)."""
+    shape = (1, 1, 13)
+    off = workloads.offsets(7)
+    A = workloads.random_sgdia(shape, 7, seed=3, symmetric=False)
+    W = oracle.od_weights(off, A, shape, 4)
+    for z in range(0, 13, 2):
+        if z > 0:
+            assert W[0, z] == -(A[2, z] * (1.0 / A[3, z]))
+        if z < 12:
+            assert W[1, z] == -(A[4, z] * (1.0 / A[3, z]))
+    shape = (9, 8, 7)
+    for npts in (7, 19, 27):
+        off = workloads.offsets(npts)
+        A = workloads.random_sgdia(shape, npts, seed=4, symmetric=False)
+        M = helpers.dense_from_sgdia(A, off, shape)
+        A[npts // 2] -= M.sum(axis=1)  # zero row sums (Neumann-like)
+        for cmask in (7, 3):
+            W = oracle.od_weights(off, A, shape, cmask)
+            P, _ = helpers.od_matrix(W, shape, cmask)
+            assert np.allclose(P.sum(axis=1), 1.0, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("npts", [7, 19, 27])
+@pytest.mark.parametrize("shape,cmask", [((7, 6, 9), 7), ((8, 6, 5), 3), ((9, 9, 9), 7), ((6, 7, 8), 6)])
+def test_od_transfers_and_rap_match_dense(npts, shape, cmask):
+    """Restriction = P^T, prolongation = P, and the stencil product equals
+    P^T A P assembled densely from the weights."""
+    off = workloads.offsets(npts)
+    A = workloads.random_sgdia(shape, npts, seed=19, symmetric=False)
+    W = oracle.od_weights(off, A, shape, cmask)
+    P, cs = helpers.od_matrix(W, shape, cmask)
+    M = helpers.dense_from_sgdia(A, off, shape)
+    g = workloads.rng(6)
+    r = g.uniform(-1, 1, size=shape)
+    e = g.uniform(-1, 1, size=cs)
+    assert np.allclose(oracle.restrict_od(r, W, cmask).ravel(), P.T @ r.ravel(), rtol=0, atol=1e-14)
+    assert np.allclose(oracle.prolong_add_od(r, W, e, cmask).ravel(), r.ravel() + P @ e.ravel(), rtol=0, atol=1e-14)
+    Ac = oracle.rap_od(off, A, shape, cmask, W)
+    assert np.allclose(helpers.dense_from_sgdia(Ac, workloads.offsets(27), cs), P.T @ M @ P, rtol=0,
+                       atol=1e-13 * np.abs(M).max())
+
+
+def test_od_hierarchy_symmetric_and_faster_on_high_contrast():
+    """R = P^T keeps the cycle symmetric; on the high-contrast diffusion
+    stand-in the operator-dependent interpolation needs fewer PCG iterations
+    than the trilinear one."""
+    shape = (16, 12, 10)
+    A = workloads.random_sgdia(shape, 7, seed=17, symmetric=True)
+    H = oracle.Hierarchy(shape, 7, A, interp="operator")
+    g = workloads.rng(5)
+    x = g.uniform(-1, 1, size=shape)
+    y = g.uniform(-1, 1, size=shape)
+    a = np.dot(H.apply(x).ravel(), y.ravel())
+    b = np.dot(x.ravel(), H.apply(y).ravel())
+    assert abs(a - b) <= 1e-12 * max(abs(a), 1.0)
+    shape = (32, 32, 32)
+    A, b = workloads.diffusion7(shape, seed=2, nspheres=3, rmin=3.0, rmax=8.0)
+    its = {}
+    for interp in ("vertex", "operator"):
+        _, st, its[interp], rel = oracle.Hierarchy(shape, 7, A, interp=interp).pcg(b.reshape(shape), 1e-9, 200)
+        assert st == 0 and rel < 1e-9
+    assert its["operator"] < its["vertex"], its
+
+
 @pytest.mark.parametrize("npts", [7, 27])
 def test_cell_vcycle_symmetric_and_pcg(npts):
     """Cell-centred hierarchy: every level keeps the fine pattern, the V(1,1)
