@@ -55,7 +55,12 @@ typedef enum {
 typedef enum { SMG_SMOOTH_GS = 0, SMG_SMOOTH_ILU0 = 1, SMG_SMOOTH_LGS = 2 } smg_smoother;
 typedef enum { SMG_COARSEN_FULL = 0, SMG_COARSEN_SEMI_XY = 1 } smg_coarsen;
 typedef enum { SMG_FP64 = 0, SMG_FP32 = 1, SMG_FP16_ROWSCALE = 2 } smg_prec;
-typedef enum { SMG_INTERP_VERTEX = 0, SMG_INTERP_CELL = 1, SMG_INTERP_CELL_TRILINEAR = 2 } smg_interp;
+typedef enum {
+  SMG_INTERP_VERTEX = 0,
+  SMG_INTERP_CELL = 1,
+  SMG_INTERP_CELL_TRILINEAR = 2,
+  SMG_INTERP_OPERATOR = 3
+} smg_interp;
 
 typedef struct {
   int nx, ny, nz;      /* finest grid */
@@ -86,8 +91,14 @@ typedef struct {
                           pattern; or that restriction with cell-centred trilinear
                           interpolation (Cell_3d64: 3/4 from the parent cell, 1/4 from
                           the neighbour on the fine cell's side, per axis), 27-point
-                          coarse levels, R != P^T (use GMRES unless A is benign).
-                          Cell-centred transfers take scalar systems. */
+                          coarse levels, R != P^T (use GMRES unless A is benign); or
+                          operator-dependent vertex interpolation (the weights of the
+                          generated triple product vary per point, after Dendy): the
+                          vertex grid map, each fine point between coarse points takes
+                          its weights from its stencil collapsed onto the directions
+                          it is not aligned with, R = P^T, 27-point coarse levels.
+                          Cell-centred and operator-dependent transfers take scalar
+                          systems. */
 } smg_config;
 
 typedef struct {
@@ -154,7 +165,9 @@ int smg_num_levels(smg_handle h);
  * points when cfg.ilu_mask is set), 4 reciprocal of the ILU diagonal (FP64, N),
  * 5 V-cycle matrix (FP32; FP16 storage is expanded to scale*float(h)),
  * 6 V-cycle reciprocal diagonal / block inverses (FP32), 7 line GS Thomas
- * reciprocal pivots (FP64, N), 8 line GS Thomas c/pivot (FP64, N). */
+ * reciprocal pivots (FP64, N), 8 line GS Thomas c/pivot (FP64, N),
+ * 9 operator-dependent interpolation weights to the next level (FP64, 8*N:
+ * weight c of fine point i at [c*N + i]). */
 smg_status smg_level_export(smg_handle h, int level, int what, void* dst, void* stream);
 
 /* Influence chains of the generated triple product for a (fine pattern,

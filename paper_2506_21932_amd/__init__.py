@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "SMG_OK", 1: "SMG_ENOTCONV", -1: "SMG_EINVAL", -2: "SMG_ENOME
                 -4: "SMG_EBREAKDOWN", -5: "SMG_EDEADLOCK"}
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2}
 SMOOTHER = {"gs": 0, "ilu0": 1, "lgs": 2}
-INTERP = {"vertex": 0, "cell": 1, "cell_trilinear": 2}
+INTERP = {"vertex": 0, "cell": 1, "cell_trilinear": 2, "operator": 3}
 COARSEN = {"full": 0, "semi_xy": 1}
 
 

@@ -24,7 +24,7 @@ CXXFLAGS = [
     "-Wno-unused-command-line-argument",
 ]
 SOURCES = ["structmg.hip", "wavefront.hip", "stencil.hip", "rap.hip", "setup.hip", "coarse.hip", "vec.hip",
-           "block.hip", "batch.hip", "hpsweep.hip", "lgs.hip", "cell.hip"]
+           "block.hip", "batch.hip", "hpsweep.hip", "lgs.hip", "cell.hip", "od.hip"]
 
 
 def _compile(src):

@@ -1,0 +1,261 @@
+// Operator-dependent vertex interpolation (P and R = P^T varying from point
+// to point, as in the caption of the generated-code listing, after Dendy's
+// black-box multigrid): weights from the level's own stencil, the transfers
+// that apply them, and the stencil Galerkin product A_c = P^T A P.
+//
+// Grid map of the vertex hierarchy: coarse X <-> fine 2X+1 on coarsened axes.
+// A fine point f that is even on the coarsened axes of E(f) lies between
+// coarse points; its corner on such an axis is lo = f/2 - 1 (c_a = 0) or
+// hi = f/2 (c_a = 1), elsewhere the single parent (c_a = 0).  W[c*N + f]
+// holds the weight of corner c = (cx*2 + cy)*2 + cz.  Points with E(f) empty
+// are coarse points (weight 1).  The others, in order of |E(f)| = 1, 2, 3
+// (one launch each), collapse their stencil onto the axes of E(f),
+//   Abar(d) = sum of A(f, s) over the canonical s with s_a = d_a on E(f),
+// and take W(f, c) = -r * sum over the neighbours g = f + d (d != 0 in the
+// box of E(f), lexicographic, g in the grid, on the line of corner c) of
+// fma(Abar(d), W(g, c'), .), r = 1 / Abar(0), c'_a = (d_a == 0 ? c_a : 0).
+#include "smg_kernels.h"
+
+namespace smg {
+
+namespace {
+
+__device__ inline bool od_even(int f, int cm) { return cm && !(f & 1); }
+
+// index on one axis of corner bit b of fine coordinate f (-1: none)
+__device__ inline int od_corner_index(int f, int cm, int b) {
+  if (!cm) return b ? -1 : f;
+  if (f & 1) return b ? -1 : (f - 1) / 2;
+  return f / 2 - 1 + b;
+}
+
+template <int PAT>
+__global__ __launch_bounds__(256) void k_od_weights(Grid g, int cmask, int k, const double* __restrict__ A,
+                                                    double* __restrict__ W, unsigned* err) {
+  const long N = g.N();
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  const int Z = (int)(i % g.nz), Y = (int)((i / g.nz) % g.ny), X = (int)(i / ((long)g.nz * g.ny));
+  const int f[3] = {X, Y, Z};
+  int ev[3], ne = 0;
+  for (int a = 0; a < 3; ++a) ne += ev[a] = od_even(f[a], (cmask >> a) & 1);
+  if (ne != k) return;
+  if (k == 0) {
+    for (int c = 0; c < 8; ++c) W[(long)c * N + i] = c == 0 ? 1.0 : 0.0;
+    return;
+  }
+  double Ab[27];
+  for (int d = 0; d < 27; ++d) {
+    const int dd[3] = {d / 9 - 1, (d / 3) % 3 - 1, d % 3 - 1};
+    bool box = true;
+    for (int a = 0; a < 3; ++a)
+      if (!ev[a] && dd[a] != 0) box = false;
+    double acc = 0.0;
+    if (box)
+#pragma unroll
+      for (int s = 0; s < PAT; ++s) {
+        const int o[3] = {pat_off(PAT, s, 0), pat_off(PAT, s, 1), pat_off(PAT, s, 2)};
+        bool match = true;
+        for (int a = 0; a < 3; ++a)
+          if (ev[a] && o[a] != dd[a]) match = false;
+        if (match) acc = acc + A[(long)s * N + i];
+      }
+    Ab[d] = acc;
+  }
+  if (Ab[13] == 0.0) {
+    atomicOr(err, 2u);
+    return;
+  }
+  const double r = 1.0 / Ab[13];
+  for (int c = 0; c < 8; ++c) {
+    const int cc[3] = {c / 4, (c / 2) % 2, c % 2};
+    bool used = true;
+    for (int a = 0; a < 3; ++a)
+      if (!ev[a] && cc[a]) used = false;
+    double acc = 0.0;
+    if (used)
+      for (int d = 0; d < 27; ++d) {
+        if (d == 13) continue;
+        const int dd[3] = {d / 9 - 1, (d / 3) % 3 - 1, d % 3 - 1};
+        bool ok = true;
+        int gg[3], cp = 0;
+        for (int a = 0; a < 3; ++a) {
+          if (!ev[a] && dd[a] != 0) ok = false;
+          if (dd[a] == 1 && cc[a] != 1) ok = false;
+          if (dd[a] == -1 && cc[a] != 0) ok = false;
+          gg[a] = f[a] + dd[a];
+        }
+        if (!ok || !in_grid(g, gg[0], gg[1], gg[2])) continue;
+        for (int a = 0; a < 3; ++a) cp = cp * 2 + (dd[a] == 0 ? cc[a] : 0);
+        const long j = ((long)gg[0] * g.ny + gg[1]) * g.nz + gg[2];
+        acc = fma(Ab[d], W[(long)cp * N + j], acc);
+      }
+    W[(long)c * N + i] = used ? -acc * r : 0.0;
+  }
+}
+
+// r_c[I] = sum over u = fine(I) + rho (rho lexicographic, u in the grid) of
+// fma(W(u, corner I), r_f[u], acc) from zero (R = P^T).
+template <class V>
+__global__ __launch_bounds__(256) void k_restrict_od(Grid gf, int cmask, const V* __restrict__ W,
+                                                     const V* __restrict__ rf, V* __restrict__ rc) {
+  const int cx = cmask & 1, cy = (cmask >> 1) & 1, cz = (cmask >> 2) & 1;
+  const Grid gc{cx ? gf.nx / 2 : gf.nx, cy ? gf.ny / 2 : gf.ny, cz ? gf.nz / 2 : gf.nz};
+  const long Nf = gf.N();
+  const long ic = (long)blockIdx.x * 256 + threadIdx.x;
+  if (ic >= gc.N()) return;
+  const int Z = (int)(ic % gc.nz), Y = (int)((ic / gc.nz) % gc.ny), X = (int)(ic / ((long)gc.nz * gc.ny));
+  const int fx = cx ? 2 * X + 1 : X, fy = cy ? 2 * Y + 1 : Y, fz = cz ? 2 * Z + 1 : Z;
+  V acc = V(0);
+  for (int dx = -cx; dx <= cx; ++dx)
+    for (int dy = -cy; dy <= cy; ++dy)
+      for (int dz = -cz; dz <= cz; ++dz) {
+        const int ux = fx + dx, uy = fy + dy, uz = fz + dz;
+        if (!in_grid(gf, ux, uy, uz)) continue;
+        // I is the hi corner of an even coordinate reached from below
+        const int c = ((dx < 0 ? 1 : 0) * 2 + (dy < 0 ? 1 : 0)) * 2 + (dz < 0 ? 1 : 0);
+        const long iu = ((long)ux * gf.ny + uy) * gf.nz + uz;
+        acc = fma(W[(long)c * Nf + iu], rf[iu], acc);
+      }
+  rc[ic] = acc;
+}
+
+// uout[f] = uin[f] + pe, pe = sum over the corners c in order of
+// fma(W(f, c), e_c[corner], pe) from zero (uout may be uin).
+template <class V>
+__global__ __launch_bounds__(256) void k_prolong_od(Grid gf, int cmask, const V* __restrict__ W,
+                                                    const V* __restrict__ ec, const V* uin, V* uout) {
+  const int cx = cmask & 1, cy = (cmask >> 1) & 1, cz = (cmask >> 2) & 1;
+  const Grid gc{cx ? gf.nx / 2 : gf.nx, cy ? gf.ny / 2 : gf.ny, cz ? gf.nz / 2 : gf.nz};
+  const long Nf = gf.N();
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= Nf) return;
+  const int Z = (int)(i % gf.nz), Y = (int)((i / gf.nz) % gf.ny), X = (int)(i / ((long)gf.nz * gf.ny));
+  V pe = V(0);
+  for (int c = 0; c < 8; ++c) {
+    const int jx = od_corner_index(X, cx, c / 4), jy = od_corner_index(Y, cy, (c / 2) % 2),
+              jz = od_corner_index(Z, cz, c % 2);
+    if (!in_grid(gc, jx, jy, jz)) continue;
+    pe = fma(W[(long)c * Nf + i], ec[((long)jx * gc.ny + jy) * gc.nz + jz], pe);
+  }
+  uout[i] = uin[i] + pe;
+}
+
+// corner index (0..7) of fine point g that is coarse point J, or -1
+__device__ inline int od_corner_of(int gx, int gy, int gz, int cx, int cy, int cz, int JX, int JY, int JZ) {
+  const int gv[3] = {gx, gy, gz}, cm[3] = {cx, cy, cz}, J[3] = {JX, JY, JZ};
+  int c = 0;
+  for (int a = 0; a < 3; ++a) {
+    int b = -1;
+    if (od_corner_index(gv[a], cm[a], 0) == J[a])
+      b = 0;
+    else if (od_corner_index(gv[a], cm[a], 1) == J[a])
+      b = 1;
+    if (b < 0) return -1;
+    c = c * 2 + b;
+  }
+  return c;
+}
+
+// A_c(I, n), n over the 27 coarse offsets: over u = fine(I) + rho
+// (lexicographic, in the grid, I a corner of u), t = sum over the canonical s
+// with g = u + s in the grid and J = I + n a corner of g of
+// fma(A(u, s), W(g, corner J), t); acc = fma(W(u, corner I), t, acc).
+template <int PAT>
+__global__ __launch_bounds__(256) void k_rap_od(Grid gf, int cmask, const double* __restrict__ A,
+                                                const double* __restrict__ W, double* __restrict__ Ac) {
+  const int cx = cmask & 1, cy = (cmask >> 1) & 1, cz = (cmask >> 2) & 1;
+  const Grid gc{cx ? gf.nx / 2 : gf.nx, cy ? gf.ny / 2 : gf.ny, cz ? gf.nz / 2 : gf.nz};
+  const long Nf = gf.N(), Nc = gc.N();
+  const long t0 = (long)blockIdx.x * 256 + threadIdx.x;
+  if (t0 >= Nc * 27) return;
+  const int n = (int)(t0 / Nc);
+  const long ic = t0 - (long)n * Nc;
+  const int Z = (int)(ic % gc.nz), Y = (int)((ic / gc.nz) % gc.ny), X = (int)(ic / ((long)gc.nz * gc.ny));
+  const int JX = X + pat_off(27, n, 0), JY = Y + pat_off(27, n, 1), JZ = Z + pat_off(27, n, 2);
+  double acc = 0.0;
+  if (in_grid(gc, JX, JY, JZ)) {
+    const int fx = cx ? 2 * X + 1 : X, fy = cy ? 2 * Y + 1 : Y, fz = cz ? 2 * Z + 1 : Z;
+    for (int dx = -cx; dx <= cx; ++dx)
+      for (int dy = -cy; dy <= cy; ++dy)
+        for (int dz = -cz; dz <= cz; ++dz) {
+          const int ux = fx + dx, uy = fy + dy, uz = fz + dz;
+          if (!in_grid(gf, ux, uy, uz)) continue;
+          const int cu = od_corner_of(ux, uy, uz, cx, cy, cz, X, Y, Z);
+          if (cu < 0) continue;
+          const long iu = ((long)ux * gf.ny + uy) * gf.nz + uz;
+          double t = 0.0;
+#pragma unroll
+          for (int s = 0; s < PAT; ++s) {
+            const int gx = ux + pat_off(PAT, s, 0), gy = uy + pat_off(PAT, s, 1), gz = uz + pat_off(PAT, s, 2);
+            if (!in_grid(gf, gx, gy, gz)) continue;
+            const int cg = od_corner_of(gx, gy, gz, cx, cy, cz, JX, JY, JZ);
+            if (cg < 0) continue;
+            t = fma(A[(long)s * Nf + iu], W[(long)cg * Nf + ((long)gx * gf.ny + gy) * gf.nz + gz], t);
+          }
+          acc = fma(W[(long)cu * Nf + iu], t, acc);
+        }
+  }
+  Ac[(long)n * Nc + ic] = acc;
+}
+
+}  // namespace
+
+hipError_t launch_od_weights(int pat, const Grid& g, int cmask, const double* A, double* W, unsigned* err,
+                             hipStream_t st) {
+  const dim3 grid((unsigned)((g.N() + 255) / 256)), blk(256);
+  for (int k = 0; k <= 3; ++k) {
+    if (pat == 7)
+      hipLaunchKernelGGL(k_od_weights<7>, grid, blk, 0, st, g, cmask, k, A, W, err);
+    else if (pat == 19)
+      hipLaunchKernelGGL(k_od_weights<19>, grid, blk, 0, st, g, cmask, k, A, W, err);
+    else if (pat == 27)
+      hipLaunchKernelGGL(k_od_weights<27>, grid, blk, 0, st, g, cmask, k, A, W, err);
+    else
+      return hipErrorInvalidValue;
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <class V>
+hipError_t launch_restrict_od(const Grid& gf, int cmask, const V* W, const V* rf, V* rc, hipStream_t st) {
+  const long n = (long)((cmask & 1) ? gf.nx / 2 : gf.nx) * ((cmask & 2) ? gf.ny / 2 : gf.ny) *
+                 ((cmask & 4) ? gf.nz / 2 : gf.nz);
+  hipLaunchKernelGGL(k_restrict_od<V>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gf, cmask, W, rf, rc);
+  return hipGetLastError();
+}
+
+template <class V>
+hipError_t launch_prolong_od(const Grid& gf, int cmask, const V* W, const V* ec, const V* uin, V* uout,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_prolong_od<V>, dim3((unsigned)((gf.N() + 255) / 256)), dim3(256), 0, st, gf, cmask, W, ec, uin,
+                     uout);
+  return hipGetLastError();
+}
+
+hipError_t launch_rap_od(int pat, int cmask, const Grid& gf, const double* A, const double* W, double* Ac,
+                         hipStream_t st) {
+  const long nc = (long)((cmask & 1) ? gf.nx / 2 : gf.nx) * ((cmask & 2) ? gf.ny / 2 : gf.ny) *
+                  ((cmask & 4) ? gf.nz / 2 : gf.nz);
+  const dim3 grid((unsigned)((nc * 27 + 255) / 256)), blk(256);
+  if (pat == 7)
+    hipLaunchKernelGGL(k_rap_od<7>, grid, blk, 0, st, gf, cmask, A, W, Ac);
+  else if (pat == 19)
+    hipLaunchKernelGGL(k_rap_od<19>, grid, blk, 0, st, gf, cmask, A, W, Ac);
+  else if (pat == 27)
+    hipLaunchKernelGGL(k_rap_od<27>, grid, blk, 0, st, gf, cmask, A, W, Ac);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template hipError_t launch_restrict_od<double>(const Grid&, int, const double*, const double*, double*, hipStream_t);
+template hipError_t launch_restrict_od<float>(const Grid&, int, const float*, const float*, float*, hipStream_t);
+template hipError_t launch_prolong_od<double>(const Grid&, int, const double*, const double*, const double*, double*,
+                                              hipStream_t);
+template hipError_t launch_prolong_od<float>(const Grid&, int, const float*, const float*, const float*, float*,
+                                             hipStream_t);
+
+}  // namespace smg

@@ -198,6 +198,19 @@ hipError_t launch_prolong_c64(const Grid& gf, int cmask, int bs, const V* ec, co
 hipError_t launch_rap_c64(int pat, int cmask, const Grid& gf, const double* A, long sA, double* Ac, long sAc,
                           hipStream_t st);
 
+// operator-dependent vertex interpolation (od.hip): weights W (8 per fine
+// point) from the level's stencil, rc = P^T rf, uout = uin + P ec (uout may
+// be uin), and the 27-point product P^T A P (scalar systems)
+hipError_t launch_od_weights(int pat, const Grid& g, int cmask, const double* A, double* W, unsigned* err,
+                             hipStream_t st);
+template <class V>
+hipError_t launch_restrict_od(const Grid& gf, int cmask, const V* W, const V* rf, V* rc, hipStream_t st);
+template <class V>
+hipError_t launch_prolong_od(const Grid& gf, int cmask, const V* W, const V* ec, const V* uin, V* uout,
+                             hipStream_t st);
+hipError_t launch_rap_od(int pat, int cmask, const Grid& gf, const double* A, const double* W, double* Ac,
+                         hipStream_t st);
+
 // ---- block (3x3) variants (block.hip) --------------------------------
 // y = A x or y = b - A x on 3x3 blocks (27-point pattern)
 template <class M>

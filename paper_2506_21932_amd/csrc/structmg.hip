@@ -82,6 +82,10 @@ int next_cmask(int lev, const int* n, int semi, int semi_levels) {
   return m;
 }
 
+bool cell_centred(const smg_config& c) {
+  return c.interp == SMG_INTERP_CELL || c.interp == SMG_INTERP_CELL_TRILINEAR;
+}
+
 const char* check_cfg(const smg_config* c) {
   if (!c) return "null config";
   if (c->nx < 1 || c->ny < 1 || c->nz < 1) return "grid dimensions must be >= 1";
@@ -107,9 +111,9 @@ const char* check_cfg(const smg_config* c) {
   if (c->ilu_mask != 0 && c->ilu_mask != 7 && c->ilu_mask != 19 && c->ilu_mask != 27)
     return "ilu_mask must be 0, 7, 19 or 27";
   if (c->ilu_mask != 0 && c->smoother != SMG_SMOOTH_ILU0) return "ilu_mask applies to the ILU(0) smoother only";
-  if (c->interp != SMG_INTERP_VERTEX && c->interp != SMG_INTERP_CELL && c->interp != SMG_INTERP_CELL_TRILINEAR)
-    return "unknown interpolation";
-  if (c->interp != SMG_INTERP_VERTEX && c->block != 1) return "cell-centred transfers are implemented for scalar systems";
+  if (c->interp < SMG_INTERP_VERTEX || c->interp > SMG_INTERP_OPERATOR) return "unknown interpolation";
+  if (c->interp != SMG_INTERP_VERTEX && c->block != 1)
+    return "cell-centred and operator-dependent transfers are implemented for scalar systems";
   return nullptr;
 }
 
@@ -137,7 +141,7 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
       break;
     }
     for (int a = 0; a < 3; ++a)
-      if ((v.cmask >> a) & 1) n[a] = cfg.interp != SMG_INTERP_VERTEX ? (n[a] + 1) / 2 : n[a] / 2;
+      if ((v.cmask >> a) & 1) n[a] = cell_centred(cfg) ? (n[a] + 1) / 2 : n[a] / 2;
   }
   const long nc = L[nlev - 1].N * bs;
   if (nlev_out) *nlev_out = nlev;
@@ -155,6 +159,10 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
     vec(&v.ua);
     vec(&v.h);
     v.rd64 = ar.take<double>((size_t)(bs == 3 ? 9 : 1) * N);
+    if (cfg.interp == SMG_INTERP_OPERATOR) {
+      v.W64 = ar.take<double>((size_t)8 * N);
+      if (cfg.prec != SMG_FP64) v.W32 = ar.take<float>((size_t)8 * N);
+    }
     if (cfg.smoother == SMG_SMOOTH_ILU0) {
       v.L64 = ar.take<double>((size_t)v.Ssw * N);
       v.U64 = ar.take<double>((size_t)v.Ssw * N + 2);  // + the factorisation's {0, 1}
@@ -351,11 +359,30 @@ hipError_t lgs_sweep(smg_handle_s* H, const Level& v, int dir, const typename PT
   return launch_lgs<V>(v.S, dir, uold == nullptr, a, st);
 }
 
-// uout = uin + P ec for the cell-centred interpolations (uout may be uin).
+// operator-dependent interpolation weights of level v in precision V
+template <class V>
+const V* od_weights(const Level& v) {
+  return sizeof(V) == 8 ? reinterpret_cast<const V*>(v.W64) : reinterpret_cast<const V*>(v.W32);
+}
+
+// uout = uin + P ec for the cell-centred and operator-dependent
+// interpolations (uout may be uin).
 template <class V>
 hipError_t prolong_cell(const smg_handle_s* H, const Level& v, const V* ec, const V* uin, V* uout, hipStream_t st) {
-  if (H->cfg.interp == SMG_INTERP_CELL_TRILINEAR) return launch_prolong_c64<V>(v.g, v.cmask, H->bs, ec, uin, uout, st);
+  if (H->cfg.interp == SMG_INTERP_OPERATOR)
+    return launch_prolong_od<V>(v.g, v.cmask, od_weights<V>(v), ec, uin, uout, st);
+  if (H->cfg.interp == SMG_INTERP_CELL_TRILINEAR)
+    return launch_prolong_c64<V>(v.g, v.cmask, H->bs, ec, uin, uout, st);
   return launch_prolong_cc<V>(v.g, v.cmask, H->bs, ec, uin, uout, st);
+}
+
+// rc = R rf with the handle's restriction (bs components per point).
+template <class V>
+hipError_t restrict_any(const smg_handle_s* H, const Level& v, const V* rf, V* rc, hipStream_t st) {
+  if (H->cfg.interp == SMG_INTERP_OPERATOR)
+    return launch_restrict_od<V>(v.g, v.cmask, od_weights<V>(v), rf, rc, st);
+  if (H->cfg.interp != SMG_INTERP_VERTEX) return launch_restrict_cc<V>(v.g, v.cmask, H->bs, rf, rc, st);
+  return launch_restrict<V>(v.g, v.cmask, H->bs, rf, rc, st);
 }
 
 // uf += P ec with the handle's interpolation (bs components per point).
@@ -375,7 +402,8 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
   const int NL = H->nlev;
   const bool ilu = H->cfg.smoother == SMG_SMOOTH_ILU0;
   const bool lgs = H->cfg.smoother == SMG_SMOOTH_LGS;
-  const bool cell = H->cfg.interp != SMG_INTERP_VERTEX;
+  // transfers other than the vertex trilinear ones run as separate passes
+  const bool sep = H->cfg.interp != SMG_INTERP_VERTEX;
   auto F = [&](int l) -> const V* { return l == 0 ? f0 : (const V*)H->lev[l].f; };
   auto UB = [&](int l) -> V* { return l == 0 ? z0 : (V*)H->lev[l].ub; };
   hipError_t e;
@@ -401,9 +429,9 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
     if (e != hipSuccess) return e;
     {
       Timed t(H, l, 2, st);
-      if (cell) {
+      if (sep) {
         e = launch_spmv(v.S, v.g, A, (const V*)v.ua, F(l), (V*)v.h, true, st);
-        if (e == hipSuccess) e = launch_restrict_cc<V>(v.g, v.cmask, 1, (const V*)v.h, (V*)H->lev[l + 1].f, st);
+        if (e == hipSuccess) e = restrict_any<V>(H, v, (const V*)v.h, (V*)H->lev[l + 1].f, st);
       } else if (split_rp(v)) {
         // residual into the level's h (free until the upward leg), then R
         e = launch_spmv(v.S, v.g, A, (const V*)v.ua, F(l), (V*)v.h, true, st);
@@ -434,7 +462,7 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
     } else if (!ilu) {
       {
         Timed t(H, l, 4, st);
-        if (cell || split_rp(v)) {
+        if (sep || split_rp(v)) {
           // u_old = u + P e_c in place (u_a is refilled by the sweep below),
           // then the backward sweep's old-value terms
           e = prolong_in_place<V>(H, v, (const V*)UB(l + 1), (V*)v.ua, st);
@@ -450,7 +478,7 @@ hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z
     } else {
       {
         Timed t(H, l, 4, st);
-        if (cell) {
+        if (sep) {
           // u_old = u_a + P e_c into u_o, then h = f - A u_old
           e = prolong_cell<V>(H, v, (const V*)UB(l + 1), (const V*)v.ua, (V*)v.uo, st);
           if (e == hipSuccess) e = launch_spmv(v.S, v.g, A, (const V*)v.uo, F(l), (V*)v.h, true, st);
@@ -591,6 +619,10 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
       else if (cfg->interp == SMG_INTERP_CELL_TRILINEAR)
         SCHK(launch_rap_c64(f.S, f.cmask, f.g, f.A64 + (long)e * f.N, (long)be * f.N, c.A64 + (long)e * c.N,
                             (long)be * c.N, st));
+      else if (cfg->interp == SMG_INTERP_OPERATOR) {
+        SCHK(launch_od_weights(f.S, f.g, f.cmask, f.A64, f.W64, H->err, st));
+        SCHK(launch_rap_od(f.S, f.cmask, f.g, f.A64, f.W64, c.A64, st));
+      }
       else
         SCHK(launch_rap(f.S, f.cmask, f.g, f.A64 + (long)e * f.N, (long)be * f.N, c.A64 + (long)e * c.N,
                         (long)be * c.N, st));
@@ -605,6 +637,7 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
       SCHK(launch_recip_diag(v.S, v.g, v.A64, v.rd64, H->err, st));
     if (cfg->smoother == SMG_SMOOTH_ILU0)
       SCHK(launch_ilu0_factor(v.S, v.Ssw, v.g, v.A64, v.L64, v.U64, v.rU64, H->err, st));
+    if (v.W32) SCHK(launch_to_f32(v.W64, v.W32, 8 * v.N, st));
     if (cfg->smoother == SMG_SMOOTH_LGS) {
       SCHK(launch_tri_factor(v.S, v.g, v.A64, v.tr64, v.tc64, H->err, st));
       if (cfg->prec == SMG_FP32) {
@@ -984,6 +1017,7 @@ smg_status smg_level_export(smg_handle h, int level, int what, void* dst, void* 
       break;
     case 7: src = v.tr64; bytes = sizeof(double) * v.N; break;
     case 8: src = v.tc64; bytes = sizeof(double) * v.N; break;
+    case 9: src = v.W64; bytes = sizeof(double) * 8 * v.N; break;
     default: return fail(h, SMG_EINVAL, "unknown export %d", what);
   }
   if (!src) return fail(h, SMG_EINVAL, "level %d has no data %d", level, what);
@@ -1162,13 +1196,11 @@ struct OpRR {
       if (e == hipSuccess) e = launch_restrict<V>(v.g, v.cmask, 3, (const V*)v.h, (V*)rc, st);
       return e;
     }
-    const bool cell = H->cfg.interp != SMG_INTERP_VERTEX;
-    if (!split_rp(v) && !cell)
+    if (!split_rp(v) && H->cfg.interp == SMG_INTERP_VERTEX)
       return launch_resid_restrict(v.S, v.g, v.cmask, PT::A(v), (const V*)f, (const V*)u, (V*)rc, st);
     hipError_t e = launch_spmv(v.S, v.g, PT::A(v), (const V*)u, (const V*)f, (V*)v.h, true, st);
     if (e == hipSuccess)
-      e = cell ? launch_restrict_cc<V>(v.g, v.cmask, 1, (const V*)v.h, (V*)rc, st)
-               : launch_restrict<V>(v.g, v.cmask, 1, (const V*)v.h, (V*)rc, st);
+      e = restrict_any<V>(H, v, (const V*)v.h, (V*)rc, st);
     return e;
   }
 };
@@ -1220,16 +1252,10 @@ smg_status smg_op_restrict(smg_handle h, int level, const void* rf, void* rc, vo
   if (!rf || !rc) return fail(h, SMG_EINVAL, "null vector");
   const Level& v = h->lev[level];
   const hipStream_t st = (hipStream_t)stream;
-  if (h->cfg.interp != SMG_INTERP_VERTEX) {
-    if (h->cfg.prec == SMG_FP64)
-      HIPCHK(h, launch_restrict_cc<double>(v.g, v.cmask, h->bs, (const double*)rf, (double*)rc, st));
-    else
-      HIPCHK(h, launch_restrict_cc<float>(v.g, v.cmask, h->bs, (const float*)rf, (float*)rc, st));
-  } else if (h->cfg.prec == SMG_FP64) {
-    HIPCHK(h, launch_restrict<double>(v.g, v.cmask, h->bs, (const double*)rf, (double*)rc, st));
-  } else {
-    HIPCHK(h, launch_restrict<float>(v.g, v.cmask, h->bs, (const float*)rf, (float*)rc, st));
-  }
+  if (h->cfg.prec == SMG_FP64)
+    HIPCHK(h, restrict_any<double>(h, v, (const double*)rf, (double*)rc, st));
+  else
+    HIPCHK(h, restrict_any<float>(h, v, (const float*)rf, (float*)rc, st));
   return SMG_OK;
 }
 

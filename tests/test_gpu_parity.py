@@ -621,3 +621,62 @@ def test_cell_centred_bitexact(case, smoother, prec, interp):
         res = mg.solve(T(b.ravel()), x, rtol=1e-9, maxit=300, krylov=kr)
         assert st == 0 and res["status"] == 0 and res["rel_resid_true"] < 1e-9
         assert abs(res["iters"] - itr) <= 1
+
+
+# operator-dependent vertex interpolation (weights from each level's stencil)
+OD_CASES = [(CASES[0], "gs", "fp64"), (CASES[1], "gs", "fp64"), (CASES[2], "gs", "fp64"), (CASES[4], "gs", "fp64"),
+            (CASES[3], "ilu0", "fp64"), (CASES[1], "lgs", "fp64"), (CASES[0], "gs", "fp32"), (CASES[6], "gs", "fp64")]
+
+
+@pytest.mark.parametrize("case,smoother,prec", OD_CASES, ids=lambda v: v if isinstance(v, str) else _ids(v))
+def test_operator_interp_bitexact(case, smoother, prec):
+    shape, pat, coarsen, semi = case
+    A = workloads.random_sgdia(shape, pat, seed=3, symmetric=smoother != "ilu0")
+    H = oracle.Hierarchy(shape, pat, A, smoother=smoother, coarsen=coarsen, semi_levels=semi, prec=prec,
+                         interp="operator")
+    mg = smg.StructMG(T(A), shape, pattern=pat, smoother=smoother, coarsen=coarsen, semi_levels=semi, prec=prec,
+                      interp="operator", device=DEV)
+    assert mg.nlev == H.nlev
+    dt, npt = (torch.float64, np.float64) if prec == "fp64" else (torch.float32, np.float32)
+    g = workloads.rng(37)
+    for l in range(H.nlev):
+        inf = H.level_info(l)
+        Ar = H.level_data(l, 0)
+        got = N(mg.export(l, 0, torch.empty(Ar.shape, dtype=torch.float64, device=DEV)))
+        assert np.array_equal(got, Ar), f"operator-dependent RAP level {l}"
+        if l == H.nlev - 1:
+            break
+        W = H.level_data(l, 9)
+        gw = N(mg.export(l, 9, torch.empty(W.shape, dtype=torch.float64, device=DEV)))
+        assert np.array_equal(gw, W), f"interpolation weights level {l}"
+        dims, cm = inf["dims"], inf["cmask"]
+        cdims = oracle.coarse_dims(dims, cm)
+        Al = Ar if prec == "fp64" else H.level_data(l, 5)
+        Wl = W.astype(npt)
+        off = workloads.offsets(inf["S"])
+        f = g.uniform(-1, 1, size=dims).astype(npt)
+        u = g.uniform(-1, 1, size=dims).astype(npt)
+        ec = g.uniform(-1, 1, size=cdims).astype(npt)
+        rc = N(mg.op_resid_restrict(l, T(f, dt), T(u, dt), torch.empty(int(np.prod(cdims)), dtype=dt, device=DEV)))
+        assert np.array_equal(rc, oracle.restrict_od(oracle.residual(off, Al, f, u), Wl, cm).ravel())
+        uf = T(u.copy(), dt)
+        mg.op_prolong_add(l, T(ec, dt), uf)
+        assert np.array_equal(N(uf).ravel(), oracle.prolong_add_od(u, Wl, ec, cm).ravel())
+        if smoother == "gs":
+            rd = H.level_data(l, 1 if prec == "fp64" else 6).ravel()
+            uo = N(mg.op_postsmooth(l, T(f, dt), T(u, dt), T(ec, dt), torch.empty(int(np.prod(dims)), dtype=dt,
+                                                                                  device=DEV)))
+            ref = oracle.gs_sweep(off, Al, rd, f, oracle.prolong_add_od(u, Wl, ec, cm), -1, 0)
+            assert np.array_equal(uo, ref.ravel()), f"post-smoothing level {l}"
+    dims = H.level_info(0)["dims"]
+    r = workloads.rng(9).uniform(-1, 1, size=dims)
+    z = N(mg.precondition(T(r.ravel()), torch.empty(r.size, dtype=torch.float64, device=DEV)))
+    zr = H.apply(r).ravel()
+    assert np.abs(z - zr).max() <= (1e-12 if prec == "fp64" else 1e-5) * np.abs(zr).max()
+    if smoother == "gs" and prec == "fp64":
+        b = workloads.rng(4).uniform(-1, 1, size=dims)
+        xr, st, itr, _ = H.pcg(b, 1e-9, 300)
+        x = torch.zeros(b.size, dtype=torch.float64, device=DEV)
+        res = mg.solve(T(b.ravel()), x, rtol=1e-9, maxit=300)
+        assert st == 0 and res["status"] == 0 and res["rel_resid_true"] < 1e-9
+        assert abs(res["iters"] - itr) <= 1
