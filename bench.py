@@ -36,10 +36,17 @@ KERNEL_OF_KIND = {"pre_sweep": "k_wavefront (forward)", "pre_sweep_u": "k_wavefr
                   "post_sweep_u": "k_wavefront (ILU upper, add)", "spmv_fp64": "k_spmv"}
 
 
-def kernel_bytes(kind, S, N, Nc, w, smoother="gs", ncoarse=0):
+def kernel_bytes(kind, S, N, Nc, w, smoother="gs", ncoarse=0, interp="vertex"):
     """Algorithmic HBM bytes of one launch: every stored coefficient and vector
-    entry the kernel needs is read once, every output written once."""
+    entry the kernel needs is read once, every output written once.  With the
+    operator-dependent interpolation the transfers run as separate passes and
+    read the weights in use (27/8 per fine point on average: 1, 2, 4 or 8 for
+    coarse, edge, face and interior points)."""
     SL = S // 2
+    if interp == "operator" and kind == "resid_restrict":
+        return (S + 2) * w * N + (1 + 27 / 8) * w * N + w * Nc
+    if interp == "operator" and kind == "prolong_post" and smoother == "gs":
+        return (2 + 27 / 8) * w * N + w * Nc + (SL + 2) * w * N
     if kind == "pre_sweep":
         return (SL + 3) * w * N if smoother == "gs" else (SL + 2) * w * N
     if kind == "pre_sweep_u":
@@ -90,19 +97,21 @@ def make_workload(name):
         shape = (256, 256, 256)
         A, b = workloads.diffusion7(shape, seed=2)
         return dict(shape=shape, A=A, b=b, pattern=7, smoother="gs", coarsen="full", semi_levels=0, krylov=0,
-                    desc="3D diffusion 256^3, 7-pt, log-normal sigma=2 + 32 inclusions, FP64 PCG + V(1,1) sym GS")
+                    interp="operator",
+                    desc="3D diffusion 256^3, 7-pt, log-normal sigma=2 + 32 inclusions, FP64 PCG + V(1,1) sym GS, "
+                         "operator-dependent interpolation")
     if name == "poisson32":
         shape = (32, 32, 32)
         A, b = workloads.poisson7(32)
         return dict(shape=shape, A=A, b=b, pattern=7, smoother="gs", coarsen="full", semi_levels=0, krylov=0,
-                    desc="3D Poisson 32^3, 7-pt, FP64 PCG + V(1,1) sym GS")
+                    interp="vertex", desc="3D Poisson 32^3, 7-pt, FP64 PCG + V(1,1) sym GS, trilinear P")
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(name, budget_s=30.0):
+def cpu_baseline(name, interp="vertex"):
     """The oracle (single-threaded C, as committed) on a bounded sample: the
-    same recipe at 1/8 of the unknowns (128^3 for the 256^3 workload), full
-    setup + PCG to 1e-9, scaled by the unknown-count ratio."""
+    same recipe and hierarchy at 1/8 of the unknowns (128^3 for the 256^3
+    workload), full setup + PCG to 1e-9, scaled by the unknown-count ratio."""
     import oracle
     import workloads
     if name == "diffusion256":
@@ -116,11 +125,12 @@ def cpu_baseline(name, budget_s=30.0):
         scale = 1.0
         sample = "full workload"
     t0 = time.perf_counter()
-    H = oracle.Hierarchy(shape, 7, A)
+    H = oracle.Hierarchy(shape, 7, A, interp=interp)
     x, st, it, rel = H.pcg(b, 1e-9, 200)
     t = time.perf_counter() - t0
     return {"value": round(t * 1e3 * scale, 1), "unit": "ms", "cores": 1, "kind": "oracle",
-            "sample": f"{sample}; measured {t:.1f}s, {it} iterations, rel resid {rel:.2e}"}
+            "sample": f"{sample}, {interp} interpolation; measured {t:.1f}s, {it} iterations, "
+                      f"rel resid {rel:.2e}"}
 
 
 # ---- supplementary workloads (opt-in; the default line is the 256^3 diffusion)
@@ -334,7 +344,8 @@ def main():
     A = torch.from_numpy(W["A"]).to(dev)
     b = torch.from_numpy(W["b"].ravel().copy()).to(dev)
     x = torch.zeros(n, dtype=torch.float64, device=dev)
-    kw = dict(pattern=W["pattern"], smoother=W["smoother"], coarsen=W["coarsen"], semi_levels=W["semi_levels"])
+    kw = dict(pattern=W["pattern"], smoother=W["smoother"], coarsen=W["coarsen"], semi_levels=W["semi_levels"],
+              interp=W["interp"])
     mg = smg.StructMG(A, shape, device=dev, **kw)
     levels = [mg.level_info(l) for l in range(mg.nlev)]
 
@@ -351,7 +362,7 @@ def main():
         N = int(np.prod(inf["dims"]))
         Nc = int(np.prod(levels[l + 1]["dims"])) if l + 1 < len(levels) else 0
         ncoarse = int(np.prod(levels[-1]["dims"]))
-        return kernel_bytes(kind, inf["S"], N, Nc, 8, W["smoother"], ncoarse)
+        return kernel_bytes(kind, inf["S"], N, Nc, 8, W["smoother"], ncoarse, W["interp"])
 
     ncycles = sum(c for (l, k), (ms, c) in rep.items() if l == 0 and k == "pre_sweep")
     vc_ms = sum(ms for (l, k), (ms, c) in rep.items() if k != "spmv_fp64")
@@ -438,6 +449,26 @@ def main():
             gtimes.append((time.perf_counter() - ts) * 1e3)
     line["graph"] = {"ms_per_step": round(float(np.mean(gtimes)), 2), "iters": rg["iters"],
                      "converged": rg["status"] == 0 and rg["rel_resid_true"] < 1e-9}
+    if W["interp"] != "vertex":
+        # the same steps with the plain trilinear interpolation, for reference
+        mg.set_timing(False)
+        mv = smg.StructMG(A, shape, device=dev, **dict(kw, interp="vertex"))
+        vtimes, rv = [], None
+        for k in range(1 + args.steps):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            mv.resetup(A)
+            x.zero_()
+            rv = mv.solve(b, x, rtol=1e-9, maxit=300, krylov=W["krylov"])
+            torch.cuda.synchronize()
+            if k > 0:
+                vtimes.append((time.perf_counter() - ts) * 1e3)
+        vms = float(np.mean(vtimes))
+        line["trilinear"] = {"ms_per_step": round(vms, 2), "iters": rv["iters"],
+                             "converged": rv["status"] == 0 and rv["rel_resid_true"] < 1e-9,
+                             "speedup_of_default": round(vms / ms_per_step, 3)}
+        mv.close()
+        del mv
     if not args.no_mixed:
         # the same workload with the V-cycle in FP32 and in FP16 (per-row
         # scaled) storage, inside the FP64 PCG: time-to-solution against FP64
@@ -465,7 +496,7 @@ def main():
         line["mixed"] = mixed
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(args.workload)
+        line["cpu_baseline"] = cpu_baseline(args.workload, W["interp"])
     print(json.dumps(line), flush=True)
 
 
