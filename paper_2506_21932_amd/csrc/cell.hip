@@ -63,10 +63,11 @@ __global__ __launch_bounds__(256) void k_rap_cc(Grid gf, int cmask, const double
                                                 double* __restrict__ Ac, long sAc) {
   const Grid gc = cc_coarse(gf, cmask);
   const long Nc = gc.N();
-  const long t = (long)blockIdx.x * 256 + threadIdx.x;
-  if (t >= Nc * PAT) return;
-  const int n = (int)(t / Nc);
-  const long ic = t - (long)n * Nc;
+  // block b: coarse points [256*(b/PAT), +256) for offset n = b % PAT (the
+  // PAT blocks of one tile run together and share their fine reads)
+  const int n = (int)(blockIdx.x % (unsigned)PAT);
+  const long ic = (long)(blockIdx.x / (unsigned)PAT) * 256 + threadIdx.x;
+  if (ic >= Nc) return;
   const int Z = (int)(ic % gc.nz), Y = (int)((ic / gc.nz) % gc.ny), X = (int)(ic / ((long)gc.nz * gc.ny));
   const int cx = cmask & 1, cy = (cmask >> 1) & 1, cz = (cmask >> 2) & 1;
   const int nx = pat_off(PAT, n, 0), ny = pat_off(PAT, n, 1), nz = pat_off(PAT, n, 2);
@@ -147,10 +148,10 @@ __global__ __launch_bounds__(256) void k_rap_c64(Grid gf, int cmask, const doubl
                                                  double* __restrict__ Ac, long sAc) {
   const Grid gc = cc_coarse(gf, cmask);
   const long Nc = gc.N();
-  const long t = (long)blockIdx.x * 256 + threadIdx.x;
-  if (t >= Nc * 27) return;
-  const int n = (int)(t / Nc);
-  const long ic = t - (long)n * Nc;
+  // block b: coarse points [256*(b/27), +256) for offset n = b % 27
+  const int n = (int)(blockIdx.x % 27u);
+  const long ic = (long)(blockIdx.x / 27u) * 256 + threadIdx.x;
+  if (ic >= Nc) return;
   const int Z = (int)(ic % gc.nz), Y = (int)((ic / gc.nz) % gc.ny), X = (int)(ic / ((long)gc.nz * gc.ny));
   const int cx = cmask & 1, cy = (cmask >> 1) & 1, cz = (cmask >> 2) & 1;
   const int JX = X + pat_off(27, n, 0), JY = Y + pat_off(27, n, 1), JZ = Z + pat_off(27, n, 2);
@@ -192,8 +193,8 @@ hipError_t launch_prolong_c64(const Grid& gf, int cmask, int bs, const V* ec, co
 
 hipError_t launch_rap_c64(int pat, int cmask, const Grid& gf, const double* A, long sA, double* Ac, long sAc,
                           hipStream_t st) {
-  const long n = cc_coarse(gf, cmask).N() * 27;
-  const dim3 grid((unsigned)((n + 255) / 256)), blk(256);
+  const long n = cc_coarse(gf, cmask).N();
+  const dim3 grid((unsigned)((n + 255) / 256 * 27)), blk(256);
   if (pat == 7)
     hipLaunchKernelGGL(k_rap_c64<7>, grid, blk, 0, st, gf, cmask, A, sA, Ac, sAc);
   else if (pat == 19)
@@ -222,8 +223,8 @@ hipError_t launch_prolong_cc(const Grid& gf, int cmask, int bs, const V* ec, con
 
 hipError_t launch_rap_cc(int pat, int cmask, const Grid& gf, const double* A, long sA, double* Ac, long sAc,
                          hipStream_t st) {
-  const long n = cc_coarse(gf, cmask).N() * pat;
-  const dim3 grid((unsigned)((n + 255) / 256)), blk(256);
+  const long n = cc_coarse(gf, cmask).N();
+  const dim3 grid((unsigned)((n + 255) / 256 * pat)), blk(256);
   if (pat == 7)
     hipLaunchKernelGGL(k_rap_cc<7>, grid, blk, 0, st, gf, cmask, A, sA, Ac, sAc);
   else if (pat == 19)

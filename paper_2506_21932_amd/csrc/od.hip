@@ -167,10 +167,12 @@ __global__ __launch_bounds__(256) void k_rap_od(Grid gf, int cmask, const double
   const int cx = cmask & 1, cy = (cmask >> 1) & 1, cz = (cmask >> 2) & 1;
   const Grid gc{cx ? gf.nx / 2 : gf.nx, cy ? gf.ny / 2 : gf.ny, cz ? gf.nz / 2 : gf.nz};
   const long Nf = gf.N(), Nc = gc.N();
-  const long t0 = (long)blockIdx.x * 256 + threadIdx.x;
-  if (t0 >= Nc * 27) return;
-  const int n = (int)(t0 / Nc);
-  const long ic = t0 - (long)n * Nc;
+  // block b covers coarse points [256*(b/27), +256) for offset n = b % 27:
+  // the 27 blocks of one tile of coarse points run together and read the
+  // same fine neighbourhood, which the caches then serve once
+  const int n = (int)(blockIdx.x % 27u);
+  const long ic = (long)(blockIdx.x / 27u) * 256 + threadIdx.x;
+  if (ic >= Nc) return;
   const int Z = (int)(ic % gc.nz), Y = (int)((ic / gc.nz) % gc.ny), X = (int)(ic / ((long)gc.nz * gc.ny));
   const int JX = X + pat_off(27, n, 0), JY = Y + pat_off(27, n, 1), JZ = Z + pat_off(27, n, 2);
   double acc = 0.0;
@@ -239,7 +241,7 @@ hipError_t launch_rap_od(int pat, int cmask, const Grid& gf, const double* A, co
                          hipStream_t st) {
   const long nc = (long)((cmask & 1) ? gf.nx / 2 : gf.nx) * ((cmask & 2) ? gf.ny / 2 : gf.ny) *
                   ((cmask & 4) ? gf.nz / 2 : gf.nz);
-  const dim3 grid((unsigned)((nc * 27 + 255) / 256)), blk(256);
+  const dim3 grid((unsigned)((nc + 255) / 256 * 27)), blk(256);
   if (pat == 7)
     hipLaunchKernelGGL(k_rap_od<7>, grid, blk, 0, st, gf, cmask, A, W, Ac);
   else if (pat == 19)
