@@ -101,3 +101,34 @@ def test_batch_validation_host_only():
     assert L.smg_batch_workspace_size(1, blk, C.byref(n)) == smg.SMG_EINVAL
     assert L.smg_batch_workspace_size(0, ilu, C.byref(n)) == smg.SMG_EINVAL
     assert L.smg_batch_workspace_size(4096, ilu, C.byref(n)) == smg.SMG_EINVAL
+
+
+def test_smoother_and_interpolation_options_host_only():
+    """Line GS, ILU masks and the interpolation options are validated and
+    sized on the host."""
+    base = _ws(shape=(32, 32, 32), pattern=19)[1]
+    st, n = _ws(shape=(32, 32, 32), pattern=19, smoother="lgs")
+    assert st == smg.SMG_OK and n > 0
+    assert _ws(shape=(32, 32, 32), pattern=19, smoother="lgs", prec="fp32")[0] == smg.SMG_OK
+    assert _ws(shape=(8, 8, 8), pattern=19, smoother="lgs", prec="fp16")[0] == smg.SMG_EINVAL
+    assert _ws(shape=(8, 8, 8), pattern=27, block=3, smoother="lgs")[0] == smg.SMG_EINVAL
+    assert _ws(shape=(4, 4, 2048), pattern=7, smoother="lgs", coarsen="semi_xy")[0] == smg.SMG_EINVAL
+    # ILU masks: fewer slots with the 3d7 mask, more with 3d27, only for ILU(0)
+    n19 = _ws(shape=(32, 32, 32), pattern=19, smoother="ilu0")[1]
+    n7 = _ws(shape=(32, 32, 32), pattern=19, smoother="ilu0", ilu_mask=7)[1]
+    n27 = _ws(shape=(32, 32, 32), pattern=19, smoother="ilu0", ilu_mask=27)[1]
+    assert n7 < n19 < n27
+    assert _ws(shape=(8, 8, 8), pattern=19, smoother="ilu0", ilu_mask=9)[0] == smg.SMG_EINVAL
+    assert _ws(shape=(8, 8, 8), pattern=19, ilu_mask=7)[0] == smg.SMG_EINVAL
+    # interpolation: cell-centred keeps the fine pattern (smaller coarse
+    # levels), operator-dependent adds 8 weights per fine point
+    assert _ws(shape=(32, 32, 32), pattern=7, interp="cell")[1] < _ws(shape=(32, 32, 32), pattern=7)[1]
+    assert _ws(shape=(32, 32, 32), pattern=19, interp="operator")[1] > base
+    assert _ws(shape=(32, 32, 32), pattern=7, interp="cell_trilinear")[0] == smg.SMG_OK
+    assert _ws(shape=(8, 8, 8), pattern=27, block=3, interp="operator")[0] == smg.SMG_EINVAL
+    cfg = smg.make_config((8, 8, 8), pattern=7)
+    cfg.interp = 4
+    n_ = C.c_size_t(0)
+    assert smg.load().smg_workspace_size(C.byref(cfg), C.byref(n_)) == smg.SMG_EINVAL
+    cells = (smg.Config * 1)(smg.make_config((8, 8, 8), 7, interp="cell"))
+    assert smg.load().smg_batch_workspace_size(1, cells, C.byref(n_)) == smg.SMG_EINVAL
