@@ -14,6 +14,8 @@
 // and take W(f, c) = -r * sum over the neighbours g = f + d (d != 0 in the
 // box of E(f), lexicographic, g in the grid, on the line of corner c) of
 // fma(Abar(d), W(g, c'), .), r = 1 / Abar(0), c'_a = (d_a == 0 ? c_a : 0).
+#include <utility>
+
 #include "smg_kernels.h"
 
 namespace smg {
@@ -141,64 +143,111 @@ __global__ __launch_bounds__(256) void k_prolong_od(Grid gf, int cmask, const V*
   uout[i] = uin[i] + pe;
 }
 
-// corner index (0..7) of fine point g that is coarse point J, or -1
-__device__ inline int od_corner_of(int gx, int gy, int gz, int cx, int cy, int cz, int JX, int JY, int JZ) {
-  const int gv[3] = {gx, gy, gz}, cm[3] = {cx, cy, cz}, J[3] = {JX, JY, JZ};
-  int c = 0;
-  for (int a = 0; a < 3; ++a) {
-    int b = -1;
-    if (od_corner_index(gv[a], cm[a], 0) == J[a])
-      b = 0;
-    else if (od_corner_index(gv[a], cm[a], 1) == J[a])
-      b = 1;
-    if (b < 0) return -1;
-    c = c * 2 + b;
-  }
-  return c;
+// A_c = P^T A P, 27-point: one thread per coarse point I computes all 27
+// coarse offsets n.  Over the fine points u = fine(I) + rho (rho
+// lexicographic, u in the grid; I is always a corner of u) the partial sums
+// t[n] collect fma(A(u, s), W(g, corner c), t[n]) over the canonical s with
+// g = u + s in the grid and the corners c of g, n = J_c - I; then
+// acc[n] = fma(W(u, corner I), t[n], acc[n]).  rho, s and c are unrolled at
+// compile time, so every coarse offset is a constant and the sums stay in
+// registers; offsets whose J lies outside the coarse grid are stored as 0.
+// CM: the coarsening mask.
+// offset component of corner bit c on one axis for q = rho_a + s_a (-1: none)
+__host__ __device__ constexpr int od_noff(bool cm, int rho, int s, int c) {
+  return !cm ? (c ? -9 : s)
+             : (((rho + s) % 2 == 0) ? (c ? -9 : (rho + s) / 2) : ((rho + s + 2 - 1) / 2 - 1 + c));
 }
 
-// A_c(I, n), n over the 27 coarse offsets: over u = fine(I) + rho
-// (lexicographic, in the grid, I a corner of u), t = sum over the canonical s
-// with g = u + s in the grid and J = I + n a corner of g of
-// fma(A(u, s), W(g, corner J), t); acc = fma(W(u, corner I), t, acc).
-template <int PAT>
-__global__ __launch_bounds__(256) void k_rap_od(Grid gf, int cmask, const double* __restrict__ A,
-                                                const double* __restrict__ W, double* __restrict__ Ac) {
-  const int cx = cmask & 1, cy = (cmask >> 1) & 1, cz = (cmask >> 2) & 1;
+template <int PAT, int CM, int RHO, int S>
+__device__ __forceinline__ void od_rap_s(double (&t)[27], const double* __restrict__ A, const double* __restrict__ W,
+                                         long Nf, long iu, const Grid& gf, int ux, int uy, int uz) {
+  constexpr int rx = RHO / 9 - 1, ry = (RHO / 3) % 3 - 1, rz = RHO % 3 - 1;
+  constexpr int sx = pat_off(PAT, S, 0), sy = pat_off(PAT, S, 1), sz = pat_off(PAT, S, 2);
+  const int gx = ux + sx, gy = uy + sy, gz = uz + sz;
+  if (!in_grid(gf, gx, gy, gz)) return;
+  const double a = A[(long)S * Nf + iu];
+  const long ig = ((long)gx * gf.ny + gy) * gf.nz + gz;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int nx = od_noff(CM & 1, rx, sx, c / 4), ny = od_noff((CM >> 1) & 1, ry, sy, (c / 2) % 2),
+              nz = od_noff((CM >> 2) & 1, rz, sz, c % 2);
+    if (nx < -1 || ny < -1 || nz < -1 || nx > 1 || ny > 1 || nz > 1) continue;
+    const int n = (nx + 1) * 9 + (ny + 1) * 3 + (nz + 1);
+    t[n] = fma(a, W[(long)c * Nf + ig], t[n]);
+  }
+}
+
+template <int PAT, int CM, int RHO, int... S>
+__device__ __forceinline__ void od_rap_rho(double (&acc)[27], const double* __restrict__ A,
+                                           const double* __restrict__ W, long Nf, const Grid& gf, int fx, int fy,
+                                           int fz, std::integer_sequence<int, S...>) {
+  constexpr int rx = RHO / 9 - 1, ry = (RHO / 3) % 3 - 1, rz = RHO % 3 - 1;
+  if constexpr ((rx != 0 && !(CM & 1)) || (ry != 0 && !(CM & 2)) || (rz != 0 && !(CM & 4))) {
+    return;
+  } else {
+    const int ux = fx + rx, uy = fy + ry, uz = fz + rz;
+    if (!in_grid(gf, ux, uy, uz)) return;
+    const long iu = ((long)ux * gf.ny + uy) * gf.nz + uz;
+    // corner of u that is I: hi (1) where u is even below fine(I), else 0
+    constexpr int cu = ((rx < 0 ? 1 : 0) * 2 + (ry < 0 ? 1 : 0)) * 2 + (rz < 0 ? 1 : 0);
+    double t[27];
+#pragma unroll
+    for (int n = 0; n < 27; ++n) t[n] = 0.0;
+    (od_rap_s<PAT, CM, RHO, S>(t, A, W, Nf, iu, gf, ux, uy, uz), ...);
+    const double wu = W[(long)cu * Nf + iu];
+#pragma unroll
+    for (int n = 0; n < 27; ++n) acc[n] = fma(wu, t[n], acc[n]);
+  }
+}
+
+template <int PAT, int CM, int... RHO>
+__device__ __forceinline__ void od_rap_all(double (&acc)[27], const double* __restrict__ A,
+                                           const double* __restrict__ W, long Nf, const Grid& gf, int fx, int fy,
+                                           int fz, std::integer_sequence<int, RHO...>) {
+  (od_rap_rho<PAT, CM, RHO>(acc, A, W, Nf, gf, fx, fy, fz, std::make_integer_sequence<int, PAT>{}), ...);
+}
+
+template <int PAT, int CM>
+__global__ __launch_bounds__(256) void k_rap_od_all(Grid gf, const double* __restrict__ A,
+                                                    const double* __restrict__ W, double* __restrict__ Ac) {
+  constexpr int cx = CM & 1, cy = (CM >> 1) & 1, cz = (CM >> 2) & 1;
   const Grid gc{cx ? gf.nx / 2 : gf.nx, cy ? gf.ny / 2 : gf.ny, cz ? gf.nz / 2 : gf.nz};
   const long Nf = gf.N(), Nc = gc.N();
-  // block b covers coarse points [256*(b/27), +256) for offset n = b % 27:
-  // the 27 blocks of one tile of coarse points run together and read the
-  // same fine neighbourhood, which the caches then serve once
-  const int n = (int)(blockIdx.x % 27u);
-  const long ic = (long)(blockIdx.x / 27u) * 256 + threadIdx.x;
+  const long ic = (long)blockIdx.x * 256 + threadIdx.x;
   if (ic >= Nc) return;
   const int Z = (int)(ic % gc.nz), Y = (int)((ic / gc.nz) % gc.ny), X = (int)(ic / ((long)gc.nz * gc.ny));
-  const int JX = X + pat_off(27, n, 0), JY = Y + pat_off(27, n, 1), JZ = Z + pat_off(27, n, 2);
-  double acc = 0.0;
-  if (in_grid(gc, JX, JY, JZ)) {
-    const int fx = cx ? 2 * X + 1 : X, fy = cy ? 2 * Y + 1 : Y, fz = cz ? 2 * Z + 1 : Z;
-    for (int dx = -cx; dx <= cx; ++dx)
-      for (int dy = -cy; dy <= cy; ++dy)
-        for (int dz = -cz; dz <= cz; ++dz) {
-          const int ux = fx + dx, uy = fy + dy, uz = fz + dz;
-          if (!in_grid(gf, ux, uy, uz)) continue;
-          const int cu = od_corner_of(ux, uy, uz, cx, cy, cz, X, Y, Z);
-          if (cu < 0) continue;
-          const long iu = ((long)ux * gf.ny + uy) * gf.nz + uz;
-          double t = 0.0;
+  double acc[27];
 #pragma unroll
-          for (int s = 0; s < PAT; ++s) {
-            const int gx = ux + pat_off(PAT, s, 0), gy = uy + pat_off(PAT, s, 1), gz = uz + pat_off(PAT, s, 2);
-            if (!in_grid(gf, gx, gy, gz)) continue;
-            const int cg = od_corner_of(gx, gy, gz, cx, cy, cz, JX, JY, JZ);
-            if (cg < 0) continue;
-            t = fma(A[(long)s * Nf + iu], W[(long)cg * Nf + ((long)gx * gf.ny + gy) * gf.nz + gz], t);
-          }
-          acc = fma(W[(long)cu * Nf + iu], t, acc);
-        }
+  for (int n = 0; n < 27; ++n) acc[n] = 0.0;
+  od_rap_all<PAT, CM>(acc, A, W, Nf, gf, cx ? 2 * X + 1 : X, cy ? 2 * Y + 1 : Y, cz ? 2 * Z + 1 : Z,
+                      std::make_integer_sequence<int, 27>{});
+#pragma unroll
+  for (int n = 0; n < 27; ++n) {
+    const bool inJ = in_grid(gc, X + n / 9 - 1, Y + (n / 3) % 3 - 1, Z + n % 3 - 1);
+    Ac[(long)n * Nc + ic] = inJ ? acc[n] : 0.0;
   }
-  Ac[(long)n * Nc + ic] = acc;
+}
+
+template <int PAT, int CM>
+hipError_t launch_rap_od_all_t(const Grid& gf, const double* A, const double* W, double* Ac, hipStream_t st) {
+  const long nc = (long)((CM & 1) ? gf.nx / 2 : gf.nx) * ((CM & 2) ? gf.ny / 2 : gf.ny) * ((CM & 4) ? gf.nz / 2 : gf.nz);
+  hipLaunchKernelGGL((k_rap_od_all<PAT, CM>), dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, gf, A, W, Ac);
+  return hipGetLastError();
+}
+
+template <int PAT>
+hipError_t launch_rap_od_all_p(int cmask, const Grid& gf, const double* A, const double* W, double* Ac,
+                               hipStream_t st) {
+  switch (cmask) {
+    case 1: return launch_rap_od_all_t<PAT, 1>(gf, A, W, Ac, st);
+    case 2: return launch_rap_od_all_t<PAT, 2>(gf, A, W, Ac, st);
+    case 3: return launch_rap_od_all_t<PAT, 3>(gf, A, W, Ac, st);
+    case 4: return launch_rap_od_all_t<PAT, 4>(gf, A, W, Ac, st);
+    case 5: return launch_rap_od_all_t<PAT, 5>(gf, A, W, Ac, st);
+    case 6: return launch_rap_od_all_t<PAT, 6>(gf, A, W, Ac, st);
+    case 7: return launch_rap_od_all_t<PAT, 7>(gf, A, W, Ac, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
@@ -239,18 +288,10 @@ hipError_t launch_prolong_od(const Grid& gf, int cmask, const V* W, const V* ec,
 
 hipError_t launch_rap_od(int pat, int cmask, const Grid& gf, const double* A, const double* W, double* Ac,
                          hipStream_t st) {
-  const long nc = (long)((cmask & 1) ? gf.nx / 2 : gf.nx) * ((cmask & 2) ? gf.ny / 2 : gf.ny) *
-                  ((cmask & 4) ? gf.nz / 2 : gf.nz);
-  const dim3 grid((unsigned)((nc + 255) / 256 * 27)), blk(256);
-  if (pat == 7)
-    hipLaunchKernelGGL(k_rap_od<7>, grid, blk, 0, st, gf, cmask, A, W, Ac);
-  else if (pat == 19)
-    hipLaunchKernelGGL(k_rap_od<19>, grid, blk, 0, st, gf, cmask, A, W, Ac);
-  else if (pat == 27)
-    hipLaunchKernelGGL(k_rap_od<27>, grid, blk, 0, st, gf, cmask, A, W, Ac);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  if (pat == 7) return launch_rap_od_all_p<7>(cmask, gf, A, W, Ac, st);
+  if (pat == 19) return launch_rap_od_all_p<19>(cmask, gf, A, W, Ac, st);
+  if (pat == 27) return launch_rap_od_all_p<27>(cmask, gf, A, W, Ac, st);
+  return hipErrorInvalidValue;
 }
 
 template hipError_t launch_restrict_od<double>(const Grid&, int, const double*, const double*, double*, hipStream_t);
