@@ -11,22 +11,29 @@
 // rden_z = 1/p_z, cp_z = c_z * rden_z.
 //
 // Sweep (k_lgs): a column depends only on columns whose (x, y) come earlier
-// in the visiting order and are stencil neighbours; in the projected 2D
-// pattern (2d5 for 3d7, 2d9 for 3d19 / 3d27) those lie on earlier
-// hyperplanes cwx*x + y = t with cwx = 1 (3d7) or 2 (3d19, 3d27: the
-// neighbour (x-1, y+1) must come first).  Work unit: a chunk of K columns of
-// one hyperplane (K*nz <= 256 points, one per thread, unless a column is
-// longer), numbered hyperplane-major.  Persistent
-// workgroups take chunks by atomic ticket, so every chunk's producers hold
-// smaller tickets and are already running: the grid always makes progress.
-// A workgroup
-//   A. assembles the right-hand side of its K columns, one point per thread:
+// in the visiting order and are stencil neighbours (the projected 2D pattern:
+// 2d5 for 3d7, 2d9 for 3d19 / 3d27).  In the sheared coordinates
+// (x, y' = y + sh*x), sh = 0 for 3d7 and 1 otherwise (the neighbour
+// (x-1, y+1) must come first), every such neighbour lies at (dx, dy') with
+// dx <= 0, dy' <= 0 and dx + dy' <= -1.  The columns are cut into K x K tiles
+// in (x, y'); a tile depends only on the tiles (bx-1, by'), (bx-1, by'-1) and
+// (bx, by'-1), so tiles listed by diagonal bx + by' (setup-time table, empty
+// tiles left out) are in dependence order.  Persistent workgroups take tiles
+// by atomic ticket (every tile's producers hold smaller tickets and are
+// already running: the grid always makes progress) and walk a tile's local
+// hyperplanes lx + ly' = k, at most K columns each (K*nz <= 256 points, one
+// per thread, unless a column is longer); every column of this sweep is read
+// back device-coherently, a column of another tile after its sentinel has
+// gone.  The backward sweep takes the table and the local
+// hyperplanes in reverse.
+// For each local hyperplane a workgroup
+//   A. assembles the right-hand side of its columns, one point per thread:
 //      t = f_i; the terms of columns not yet visited (values from before the
 //      sweep, plain loads); then the terms of columns of this sweep, whose
 //      values are read device-coherently from the output and awaited while
 //      they still hold the sentinel; each group in canonical order with fma.
 //      Every load of a point is issued before its first wait.  The Thomas
-//      factors of the chunk are staged in LDS with the sums;
+//      factors of the columns are staged in LDS with the sums;
 //   B. solves each column in one lane (forward elimination, back
 //      substitution), in the oracle's order of operations;
 //   C. stores the column device-coherently and, if asked, writes the sentinel
@@ -36,6 +43,7 @@
 // Waits are bounded: after LGS_SPIN_LIMIT polls, bit 0 of err is set and
 // every waiting lane gives up.
 #include <utility>
+#include <vector>
 
 #include "smg_kernels.h"
 
@@ -53,14 +61,6 @@ __host__ __device__ constexpr int lgs_cwx(int pat) { return pat == 7 ? 1 : 2; }
 // visiting order of direction DIR?
 __host__ __device__ constexpr bool lgs_later(int dir, int dx, int dy) {
   return dir > 0 ? (dx > 0 || (dx == 0 && dy > 0)) : (dx < 0 || (dx == 0 && dy < 0));
-}
-
-// x range [x0, x0 + nxr) of the columns on hyperplane cwx*x + y = t
-__host__ __device__ inline void lgs_xrange(const Grid& g, int cwx, int t, int* x0, int* nxr) {
-  const int lo = t - (g.ny - 1);
-  *x0 = lo <= 0 ? 0 : (lo + cwx - 1) / cwx;
-  const int x1 = t / cwx < g.nx - 1 ? t / cwx : g.nx - 1;
-  *nxr = x1 - *x0 + 1;
 }
 
 template <class V>
@@ -178,78 +178,92 @@ __global__ __launch_bounds__(LGS_NT) void k_lgs(LgsArgs<V> a) {
   V* la = ld + K * LD;                      // coupling to z-1
   V* lr = la + K * LD;                      // 1 / pivot
   V* lc = lr + K * LD;                      // c / pivot
-  const unsigned total = (unsigned)a.T * (unsigned)a.M;
+  const int SH = CWX - 1;
+  const int nsteps = 2 * K - 1;
   for (;;) {
     const unsigned ticket = lgs_take_ticket(a.ctr);
-    if (ticket >= total) break;
-    const int p = (int)(ticket / (unsigned)a.M), j = (int)(ticket % (unsigned)a.M);
-    const int t = DIR > 0 ? p : a.T - 1 - p;
-    int x0, nxr;
-    lgs_xrange(g, CWX, t, &x0, &nxr);
-    const int ncol = nxr - j * K < K ? nxr - j * K : K;  // columns of this chunk (may be <= 0)
-    // A. right-hand sides and staged factors (one point per thread unless
-    // the column is longer than a workgroup)
-    for (int q = threadIdx.x; q < ncol * nz; q += LGS_NT) {
-      const int c = q / nz, Z = q - c * nz;
-      const int X = x0 + j * K + c, Y = t - CWX * X;
-      const long i = ((long)X * g.ny + Y) * nz + Z;
-      const int o = c * LD + Z;
-      la[o] = Z > 0 ? a.A[(long)SLO * N + i] : V(0);
-      lr[o] = a.rden[i];
-      lc[o] = a.cp[i];
-      ld[o] = lgs_rhs<PAT, DIR, ZG, V>(a, N, i, X, Y, Z, std::make_integer_sequence<int, PAT>{});
-    }
-    __syncthreads();
-    // B. Thomas solve, one lane per column, in blocks of 8 points whose LDS
-    // reads are issued together.  d'_0 = t_0 * rden_0 comes out of the same
-    // formula: the stored coupling to z-1 at z = 0 is +0 and d' starts at +0,
-    // so fma(-0, +0, t_0) = t_0 exactly.
-    if ((int)threadIdx.x < ncol) {
-      const int b = (int)threadIdx.x * LD;
-      V dp = V(0);
-      for (int z0 = 0; z0 < nz; z0 += 8) {
-        V a8[8], r8[8], d8[8];
+    if (ticket >= (unsigned)a.ntile) break;
+    const int e = a.tmap[DIR > 0 ? (int)ticket : a.ntile - 1 - (int)ticket];
+    const int bx = e >> 16, by = e & 0xffff;
+    for (int st = 0; st < nsteps; ++st) {
+      const int kh = DIR > 0 ? st : nsteps - 1 - st;  // local hyperplane lx + ly' = kh
+      const int lx0 = kh - (K - 1) > 0 ? kh - (K - 1) : 0;
+      const int ncol = (kh < K - 1 ? kh : K - 1) - lx0 + 1;  // columns of this hyperplane in the tile
+      // column c of the hyperplane: (lx, ly') = (lx0 + c, kh - lx0 - c); it
+      // exists if it falls inside the grid
+      auto column = [&](int c, int& X, int& Y) {
+        X = bx * K + lx0 + c;
+        Y = by * K + (kh - lx0 - c) - SH * X;
+        return X < g.nx && Y >= 0 && Y < g.ny;
+      };
+      // A. right-hand sides and staged factors (one point per thread unless
+      // the column is longer than a workgroup)
+      for (int q = threadIdx.x; q < ncol * nz; q += LGS_NT) {
+        const int c = q / nz, Z = q - c * nz;
+        int X, Y;
+        if (!column(c, X, Y)) continue;
+        const long i = ((long)X * g.ny + Y) * nz + Z;
+        const int o = c * LD + Z;
+        la[o] = Z > 0 ? a.A[(long)SLO * N + i] : V(0);
+        lr[o] = a.rden[i];
+        lc[o] = a.cp[i];
+        ld[o] = lgs_rhs<PAT, DIR, ZG, V>(a, N, i, X, Y, Z, std::make_integer_sequence<int, PAT>{});
+      }
+      __syncthreads();
+      // B. Thomas solve, one lane per column, in blocks of 8 points whose LDS
+      // reads are issued together.  d'_0 = t_0 * rden_0 comes out of the same
+      // formula: the stored coupling to z-1 at z = 0 is +0 and d' starts at +0,
+      // so fma(-0, +0, t_0) = t_0 exactly.
+      int cX, cY;
+      if ((int)threadIdx.x < ncol && column((int)threadIdx.x, cX, cY)) {
+        const int b = (int)threadIdx.x * LD;
+        V dp = V(0);
+        for (int z0 = 0; z0 < nz; z0 += 8) {
+          V a8[8], r8[8], d8[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const int z = z0 + k < nz ? z0 + k : nz - 1;
-          a8[k] = la[b + z];
-          r8[k] = lr[b + z];
-          d8[k] = ld[b + z];
+          for (int k = 0; k < 8; ++k) {
+            const int z = z0 + k < nz ? z0 + k : nz - 1;
+            a8[k] = la[b + z];
+            r8[k] = lr[b + z];
+            d8[k] = ld[b + z];
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            if (z0 + k < nz) {
+              dp = fma(-a8[k], dp, d8[k]) * r8[k];
+              ld[b + z0 + k] = dp;
+            }
+          }
         }
+        V xv = dp;
+        for (int z1 = nz - 2; z1 >= 0; z1 -= 8) {
+          V c8[8], d8[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          if (z0 + k < nz) {
-            dp = fma(-a8[k], dp, d8[k]) * r8[k];
-            ld[b + z0 + k] = dp;
+          for (int k = 0; k < 8; ++k) {
+            const int z = z1 - k >= 0 ? z1 - k : 0;
+            c8[k] = lc[b + z];
+            d8[k] = ld[b + z];
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            if (z1 - k >= 0) {
+              xv = fma(-c8[k], xv, d8[k]);
+              ld[b + z1 - k] = xv;
+            }
           }
         }
       }
-      V xv = dp;
-      for (int z1 = nz - 2; z1 >= 0; z1 -= 8) {
-        V c8[8], d8[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const int z = z1 - k >= 0 ? z1 - k : 0;
-          c8[k] = lc[b + z];
-          d8[k] = ld[b + z];
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          if (z1 - k >= 0) {
-            xv = fma(-c8[k], xv, d8[k]);
-            ld[b + z1 - k] = xv;
-          }
-        }
+      __syncthreads();
+      // C. results out, sentinels for the next sweep
+      for (int q = threadIdx.x; q < ncol * nz; q += LGS_NT) {
+        const int c = q / nz, Z = q - c * nz;
+        int X, Y;
+        if (!column(c, X, Y)) continue;
+        const long i = ((long)X * g.ny + Y) * nz + Z;
+        cstore(a.x + i, ld[c * LD + Z]);
+        if (a.next) a.next[i] = VBits<V>::val(VBits<V>::sent);
       }
-    }
-    __syncthreads();
-    // C. results out, sentinels for the next sweep
-    for (int q = threadIdx.x; q < ncol * nz; q += LGS_NT) {
-      const int c = q / nz, Z = q - c * nz;
-      const int X = x0 + j * K + c, Y = t - CWX * X;
-      const long i = ((long)X * g.ny + Y) * nz + Z;
-      cstore(a.x + i, ld[c * LD + Z]);
-      if (a.next) a.next[i] = VBits<V>::val(VBits<V>::sent);
+      __syncthreads();  // LDS is refilled by the next local hyperplane
     }
   }
   lgs_retire(a.ctr);
@@ -279,9 +293,9 @@ __global__ __launch_bounds__(256) void k_tri_factor(Grid g, int slo, int sc, int
 
 template <int PAT, int DIR, class V, bool ZG>
 hipError_t launch_lgs_t(const LgsArgs<V>& a, hipStream_t st) {
-  const unsigned total = (unsigned)a.T * (unsigned)a.M;
+  const unsigned total = (unsigned)a.ntile;
   const unsigned grid = total < (unsigned)LGS_MAX_GRID ? total : (unsigned)LGS_MAX_GRID;
-  const size_t lds = (size_t)4 * a.K * (a.g.nz + 1) * sizeof(V);
+  const size_t lds = lgs_lds_bytes(a.g, a.K, (int)sizeof(V));
   hipLaunchKernelGGL((k_lgs<PAT, DIR, V, ZG>), dim3(grid), dim3(LGS_NT), lds, st, a);
   return hipGetLastError();
 }
@@ -295,17 +309,27 @@ hipError_t launch_lgs_p(int dir, bool zg, const LgsArgs<V>& a, hipStream_t st) {
 
 }  // namespace
 
-void lgs_plan(const Grid& g, int pat, int* K, int* M, int* T) {
-  const int cwx = lgs_cwx(pat);
-  *K = g.nz >= LGS_PTS ? 1 : (LGS_PTS / g.nz < 64 ? LGS_PTS / g.nz : 64);
-  *T = cwx * (g.nx - 1) + (g.ny - 1) + 1;
-  int mx = 0;
-  for (int t = 0; t < *T; ++t) {
-    int x0, nxr;
-    lgs_xrange(g, cwx, t, &x0, &nxr);
-    mx = nxr > mx ? nxr : mx;
-  }
-  *M = (mx + *K - 1) / *K;
+int lgs_plan(const Grid& g, int pat, int* K, std::vector<int>* tmap) {
+  const int k = g.nz >= LGS_PTS ? 1 : (LGS_PTS / g.nz < 8 ? LGS_PTS / g.nz : 8);
+  const int sh = lgs_cwx(pat) - 1;
+  const int ntx = (g.nx + k - 1) / k, nty = (g.ny + sh * (g.nx - 1) + k - 1) / k;
+  *K = k;
+  int n = 0;
+  for (int d = 0; d < ntx + nty - 1; ++d)
+    for (int bx = 0; bx < ntx; ++bx) {
+      const int by = d - bx;
+      if (by < 0 || by >= nty) continue;
+      // the tile holds a column if some x of it has y = y' - sh*x in [0, ny)
+      bool any = false;
+      for (int x = bx * k; x < bx * k + k && x < g.nx && !any; ++x) {
+        const int y0 = by * k - sh * x, y1 = y0 + k - 1;
+        any = y1 >= 0 && y0 < g.ny;
+      }
+      if (!any) continue;
+      if (tmap) tmap->push_back((bx << 16) | by);
+      ++n;
+    }
+  return n;
 }
 
 size_t lgs_lds_bytes(const Grid& g, int K, int vbytes) { return (size_t)4 * K * (g.nz + 1) * vbytes; }
@@ -322,7 +346,7 @@ hipError_t launch_tri_factor(int pat, const Grid& g, const double* A, double* rd
 
 template <class V>
 hipError_t launch_lgs(int pat, int dir, bool zero_guess, const LgsArgs<V>& a, hipStream_t st) {
-  if (a.K < 1 || a.M < 1 || a.T < 1 || a.g.nz > LGS_MAX_NZ || lgs_lds_bytes(a.g, a.K, (int)sizeof(V)) > 65536 ||
+  if (a.K < 1 || a.ntile < 1 || !a.tmap || a.g.nz > LGS_MAX_NZ || lgs_lds_bytes(a.g, a.K, (int)sizeof(V)) > 65536 ||
       (!zero_guess && a.uold == nullptr))
     return hipErrorInvalidValue;
   if (pat == 7) return launch_lgs_p<7, V>(dir, zero_guess, a, st);

@@ -33,7 +33,8 @@ struct Level {
   void* hp_cf[2] = {nullptr, nullptr};  // its step-ordered coefficients, forward / backward
   double *tr64 = nullptr, *tc64 = nullptr;  // line GS: Thomas 1/pivot and c/pivot per point
   float *tr32 = nullptr, *tc32 = nullptr;
-  int lg_K = 0, lg_M = 0, lg_T = 0;         // line GS chunking (columns per chunk, chunks, hyperplanes)
+  int lg_K = 0, lg_nt = 0;                  // line GS tiles: side (columns) and number
+  int* lg_map = nullptr;                    // their dependence order (bx << 16 | by')
   double* W64 = nullptr;                    // operator-dependent interpolation weights to the next level (8 x N)
   float* W32 = nullptr;                     // their FP32 copy for reduced-precision V-cycles
 };

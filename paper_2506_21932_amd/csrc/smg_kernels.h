@@ -240,10 +240,11 @@ hipError_t launch_block_dinv(const Grid& g, const double* A, double* Dinv, unsig
 // read where a coupling or pivot is unused)
 hipError_t launch_ilu0_factor(int pa, int pm, const Grid& g, const double* A, double* L, double* U, double* rU,
                               unsigned* err, hipStream_t st);
-// Line Gauss-Seidel over z-columns (lgs.hip).  Chunks of K columns of one
-// hyperplane are the work units (M chunks per hyperplane, T hyperplanes);
-// x holds the sentinel until written; uold: values before the sweep (null for
-// the zero-guess forward sweep); next: buffer given the sentinel (or null).
+// Line Gauss-Seidel over z-columns (lgs.hip).  Tiles of K x K columns in
+// sheared (x, y + sh*x) coordinates are the work units, taken in the order of
+// tmap (ntile entries bx << 16 | by'); x holds the sentinel until written;
+// uold: values before the sweep (null for the zero-guess forward sweep);
+// next: buffer given the sentinel (or null).
 constexpr int LGS_MAX_GRID = 512;
 constexpr int LGS_MAX_NZ = 2047;
 template <class V>
@@ -256,11 +257,14 @@ struct LgsArgs {
   const V* uold;
   V* x;
   V* next;
-  int K, M, T;
+  int K, ntile;
+  const int* tmap;
   unsigned* ctr;
   unsigned* err;
 };
-void lgs_plan(const Grid& g, int pat, int* K, int* M, int* T);
+// tile side K and the tiles holding columns in dependence order (tmap may
+// be null: count only); returns their number
+int lgs_plan(const Grid& g, int pat, int* K, std::vector<int>* tmap);
 size_t lgs_lds_bytes(const Grid& g, int K, int vbytes);
 hipError_t launch_tri_factor(int pat, const Grid& g, const double* A, double* rden, double* cp, unsigned* err,
                              hipStream_t st);

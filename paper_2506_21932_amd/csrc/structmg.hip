@@ -174,7 +174,8 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
     }
     const int eb = cfg.prec == SMG_FP16_ROWSCALE ? 2 : (int)vsz;
     if (cfg.smoother == SMG_SMOOTH_LGS) {
-      lgs_plan(v.g, v.S, &v.lg_K, &v.lg_M, &v.lg_T);
+      v.lg_nt = lgs_plan(v.g, v.S, &v.lg_K, nullptr);
+      v.lg_map = ar.take<int>((size_t)v.lg_nt);
       v.tr64 = ar.take<double>((size_t)N);
       v.tc64 = ar.take<double>((size_t)N);
       if (cfg.prec == SMG_FP32) {
@@ -352,8 +353,8 @@ hipError_t lgs_sweep(smg_handle_s* H, const Level& v, int dir, const typename PT
   a.x = x;
   a.next = next;
   a.K = v.lg_K;
-  a.M = v.lg_M;
-  a.T = v.lg_T;
+  a.ntile = v.lg_nt;
+  a.tmap = v.lg_map;
   a.ctr = H->ctr;
   a.err = H->err;
   return launch_lgs<V>(v.S, dir, uold == nullptr, a, st);
@@ -639,6 +640,10 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
       SCHK(launch_ilu0_factor(v.S, v.Ssw, v.g, v.A64, v.L64, v.U64, v.rU64, H->err, st));
     if (v.W32) SCHK(launch_to_f32(v.W64, v.W32, 8 * v.N, st));
     if (cfg->smoother == SMG_SMOOTH_LGS) {
+      std::vector<int> tiles;
+      int kside = 0;
+      lgs_plan(v.g, v.S, &kside, &tiles);
+      SCHK(hipMemcpy(v.lg_map, tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice));
       SCHK(launch_tri_factor(v.S, v.g, v.A64, v.tr64, v.tc64, H->err, st));
       if (cfg->prec == SMG_FP32) {
         SCHK(launch_to_f32(v.tr64, v.tr32, v.N, st));
