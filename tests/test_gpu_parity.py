@@ -385,14 +385,24 @@ def test_single_level_hierarchy():
     assert res["status"] == 0 and res["rel_resid_true"] < 1e-9 and abs(res["iters"] - itr) <= 1
 
 
-@pytest.mark.parametrize("kind", ["gs_fp64", "gs_fp32", "block_fp16"])
+@pytest.mark.parametrize("kind", ["gs_fp64", "gs_fp32", "block_fp16", "lgs_fp64", "operator_fp64", "cell_fp32",
+                                  "ilu27_fp64"])
 def test_graph_replay_identical(kind):
     """PCG with the V-cycle replayed from a captured graph gives the same bits
-    as launching its kernels one by one, also across repeated solves."""
+    as launching its kernels one by one, also across repeated solves (line
+    GS, operator-dependent and cell-centred transfers and ILU masks
+    included)."""
     if kind == "block_fp16":
         shape = (12, 12, 12)
         A, b = workloads.elasticity27(12, seed=4)
         mg = smg.StructMG(T(A), shape, pattern=27, block=3, prec="fp16", device=DEV)
+    elif kind != "gs_fp64" and kind != "gs_fp32":
+        shape = (33, 17, 20)
+        A = workloads.random_sgdia(shape, 19, seed=5)
+        b = workloads.rng(6).uniform(-1, 1, size=shape)
+        opts = {"lgs_fp64": dict(smoother="lgs"), "operator_fp64": dict(interp="operator"),
+                "cell_fp32": dict(interp="cell", prec="fp32"), "ilu27_fp64": dict(smoother="ilu0", ilu_mask=27)}
+        mg = smg.StructMG(T(A), shape, pattern=19, device=DEV, **opts[kind])
     else:
         shape = (33, 17, 20)
         A = workloads.random_sgdia(shape, 7, seed=5)
