@@ -213,24 +213,27 @@ __device__ __forceinline__ bool ilu_point(const Grid& g, int tau, int x0, int nx
 // Row i of A on the factor mask PAT: A's coefficient of the same offset in
 // its own pattern PA where there is one and the neighbour is in the grid,
 // else 0 (a mask larger than A's pattern keeps fill there, a smaller one
-// drops A's other entries).
+// drops A's other entries).  Outside the grid the slot reads the stored zero
+// z0 = U[PAT*N] through a selected address: a select of the loaded value
+// instead lets the compiler move each load into a branch that waits for it
+// alone, one memory round trip per slot.
 template <int PAT, int PA, int S>
-__device__ __forceinline__ void ilu_init(double (&w)[PAT], const double* __restrict__ A, long N, long i,
-                                         const Grid& g, int X, int Y, int Z) {
+__device__ __forceinline__ void ilu_init(double (&w)[PAT], const double* __restrict__ A, const double* z0, long N,
+                                         long i, const Grid& g, int X, int Y, int Z) {
   constexpr int dx = pat_off(PAT, S, 0), dy = pat_off(PAT, S, 1), dz = pat_off(PAT, S, 2);
   constexpr int sa = pat_slot(PA, dx, dy, dz);
   if constexpr (sa >= 0) {
-    const double a = A[(long)sa * N + i];  // row i's own slot: always in bounds
-    w[S] = in_grid(g, X + dx, Y + dy, Z + dz) ? a : 0.0;
+    w[S] = *(in_grid(g, X + dx, Y + dy, Z + dz) ? A + (long)sa * N + i : z0);
   } else {
     w[S] = 0.0;
   }
 }
 
 template <int PAT, int PA, int... S>
-__device__ __forceinline__ void ilu_init_row(double (&w)[PAT], const double* __restrict__ A, long N, long i,
-                                             const Grid& g, int X, int Y, int Z, std::integer_sequence<int, S...>) {
-  (ilu_init<PAT, PA, S>(w, A, N, i, g, X, Y, Z), ...);
+__device__ __forceinline__ void ilu_init_row(double (&w)[PAT], const double* __restrict__ A, const double* z0,
+                                             long N, long i, const Grid& g, int X, int Y, int Z,
+                                             std::integer_sequence<int, S...>) {
+  (ilu_init<PAT, PA, S>(w, A, z0, N, i, g, X, Y, Z), ...);
 }
 
 // PAT: the factor mask (its hyperplanes order the rows); PA: A's pattern.
@@ -246,7 +249,7 @@ __global__ __launch_bounds__(ILU_WG) void k_ilu0_plane(Grid g, int tau, int x0, 
   if (!ilu_point<WX, WY>(g, tau, x0, nxr, kb, (int)(blockIdx.x * (unsigned)ILU_WG + threadIdx.x), X, Y, Z)) return;
   const long i = ((long)X * g.ny + Y) * g.nz + Z;
   double w[PAT];
-  ilu_init_row<PAT, PA>(w, A, N, i, g, X, Y, Z, std::make_integer_sequence<int, PAT>{});
+  ilu_init_row<PAT, PA>(w, A, U + (long)PAT * N, N, i, g, X, Y, Z, std::make_integer_sequence<int, PAT>{});
   ilu_rows<PAT>(w, g, X, Y, Z, i, U, std::make_integer_sequence<int, C>{});
 #pragma unroll
   for (int s = 0; s < PAT; ++s) {
