@@ -123,53 +123,111 @@ hipError_t launch_block_dinv(const Grid& g, const double* A, double* Dinv, unsig
   return hipGetLastError();
 }
 
+// Which of a point's 26 neighbours lie in the grid: every offset that the
+// elimination of one row touches (its own slots, the rows of its lower
+// neighbours and the fill kept on the mask) lies within one step of the point
+// on each axis, so six comparisons per point decide them all.
+struct IluNb {
+  bool xl, xh, yl, yh, zl, zh;  // neighbour at -1 / +1 on x, y, z in the grid
+};
+
+template <int DX, int DY, int DZ>
+__device__ __forceinline__ bool ilu_nb(const IluNb& b) {
+  static_assert(DX >= -1 && DX <= 1 && DY >= -1 && DY <= 1 && DZ >= -1 && DZ <= 1, "offset beyond one step");
+  bool r = true;
+  if constexpr (DX < 0) r = r & b.xl;
+  if constexpr (DX > 0) r = r & b.xh;
+  if constexpr (DY < 0) r = r & b.yl;
+  if constexpr (DY > 0) r = r & b.yh;
+  if constexpr (DZ < 0) r = r & b.zl;
+  if constexpr (DZ > 0) r = r & b.zh;
+  return r;
+}
+
+// Flat index offset of the neighbour at (dx, dy, dz).
+__device__ __forceinline__ long ilu_flat(const Grid& g, int dx, int dy, int dz) {
+  return ((long)dx * g.ny + dy) * g.nz + dz;
+}
+
 // Compile-time unrolled elimination of one ILU(0) row (all slot indices are
 // constants): for lower slot S (canonical order) of the row, with the row k
 // of that neighbour: w[S] /= U_C[k], then for each upper slot T of row k in
 // canonical order whose combined offset lies in the mask and in the grid,
 // w[slot] = fma(-w[S], U_T[k], w[slot]).
-// Branch-free: every update is performed, with the pivot 1 and the coupling 0
-// where the neighbour row is outside the grid or the fill is out of the mask.
-// Those constants are read from U[PAT*N] = 0 and U[PAT*N+1] = 1 through a
-// selected index, so their values stay unknown to the compiler: it keeps every
-// load of the row unconditional and in flight together instead of splitting
-// the row into branches that each wait for their own load.
+// The elimination runs in two phases: every pivot and coupling it uses is
+// loaded first (ilu_load), then the arithmetic runs on registers (ilu_elim),
+// so all loads of the row are in flight together.  Every update is performed,
+// with the pivot 1 and the coupling 0 where the neighbour row is outside the
+// grid or the fill is out of the mask; those constants are read from
+// one = U[PAT*N+1] and zero = U[PAT*N] through a selected address (a select
+// of a loaded value instead lets the compiler move the load into a branch
+// that waits for it alone).  An address is a per-launch constant
+// (U + T*N + the neighbour's flat offset) plus the point's index i.
+template <int PAT>
+struct IluRowVals {
+  double ud[PAT / 2];               // pivot U_C of lower neighbour S
+  double uf[PAT / 2][PAT / 2];      // coupling U_T of lower neighbour S, T = C + 1 + t
+};
+
+// combined offset of lower slot S and upper slot T: its slot in the mask, or
+// -1 if the fill is dropped
 template <int PAT, int S, int T>
-__device__ __forceinline__ void ilu_fill(double (&w)[PAT], const double* __restrict__ U, long N, long k, bool vs,
-                                         const Grid& g, int ax, int ay, int az) {
+__host__ __device__ constexpr int ilu_fill_slot() {
   constexpr int dx = pat_off(PAT, S, 0) + pat_off(PAT, T, 0), dy = pat_off(PAT, S, 1) + pat_off(PAT, T, 1),
                 dz = pat_off(PAT, S, 2) + pat_off(PAT, T, 2);
-  if constexpr (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) {
-    constexpr int sl = pat_slot(PAT, dx, dy, dz);
-    if constexpr (sl >= 0) {
-      const bool in = vs & in_grid(g, ax + pat_off(PAT, T, 0), ay + pat_off(PAT, T, 1), az + pat_off(PAT, T, 2));
-      // unused couplings read the stored zero U[PAT*N]: w + (-w_S * 0) = w
-      // up to the sign of a zero result
-      const double u = U[in ? (long)T * N + k : (long)PAT * N];
-      w[sl] = fma(-w[S], u, w[sl]);
-    }
+  if constexpr (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1)
+    return pat_slot(PAT, dx, dy, dz);
+  else
+    return -1;
+}
+
+template <int PAT, int S, int T>
+__device__ __forceinline__ void ilu_load_fill(IluRowVals<PAT>& v, const double* __restrict__ U, const double* zero,
+                                              long N, long koff, long i, bool vs, const IluNb& nb) {
+  constexpr int sl = ilu_fill_slot<PAT, S, T>();
+  if constexpr (sl >= 0) {
+    constexpr int dx = pat_off(PAT, sl, 0), dy = pat_off(PAT, sl, 1), dz = pat_off(PAT, sl, 2);
+    const bool in = vs & ilu_nb<dx, dy, dz>(nb);
+    v.uf[S][T - PAT / 2 - 1] = *(in ? U + ((long)T * N + koff) + i : zero);
   }
 }
 
 template <int PAT, int S, int... T>
-__device__ __forceinline__ void ilu_row(double (&w)[PAT], const Grid& g, int X, int Y, int Z, long i,
-                                        const double* __restrict__ U, std::integer_sequence<int, T...>) {
+__device__ __forceinline__ void ilu_load(IluRowVals<PAT>& v, const Grid& g, long i, const IluNb& nb,
+                                         const double* __restrict__ U, const double* zero,
+                                         std::integer_sequence<int, T...>) {
   constexpr int C = PAT / 2;
+  constexpr int ox = pat_off(PAT, S, 0), oy = pat_off(PAT, S, 1), oz = pat_off(PAT, S, 2);
   const long N = g.N();
-  const int ax = X + pat_off(PAT, S, 0), ay = Y + pat_off(PAT, S, 1), az = Z + pat_off(PAT, S, 2);
-  const bool vs = in_grid(g, ax, ay, az);
-  const long k =
-      vs ? i + pat_off(PAT, S, 0) * ((long)g.ny * g.nz) + pat_off(PAT, S, 1) * (long)g.nz + pat_off(PAT, S, 2) : i;
-  // the stored 1 outside the grid
-  const double ud = U[vs ? (long)C * N + k : (long)PAT * N + 1];
-  w[S] = w[S] / ud;
-  (ilu_fill<PAT, S, C + 1 + T>(w, U, N, k, vs, g, ax, ay, az), ...);
+  const bool vs = ilu_nb<ox, oy, oz>(nb);
+  const long koff = ilu_flat(g, ox, oy, oz);
+  v.ud[S] = *(vs ? U + ((long)C * N + koff) + i : zero + 1);  // the stored 1 outside the grid
+  (ilu_load_fill<PAT, S, C + 1 + T>(v, U, zero, N, koff, i, vs, nb), ...);
+}
+
+template <int PAT, int S, int T>
+__device__ __forceinline__ void ilu_elim_fill(double (&w)[PAT], const IluRowVals<PAT>& v) {
+  constexpr int sl = ilu_fill_slot<PAT, S, T>();
+  // unused couplings are the stored zero: w + (-w_S * 0) = w up to the sign
+  // of a zero result
+  if constexpr (sl >= 0) w[sl] = fma(-w[S], v.uf[S][T - PAT / 2 - 1], w[sl]);
+}
+
+template <int PAT, int S, int... T>
+__device__ __forceinline__ void ilu_elim(double (&w)[PAT], const IluRowVals<PAT>& v,
+                                         std::integer_sequence<int, T...>) {
+  w[S] = w[S] / v.ud[S];
+  (ilu_elim_fill<PAT, S, PAT / 2 + 1 + T>(w, v), ...);
 }
 
 template <int PAT, int... S>
-__device__ __forceinline__ void ilu_rows(double (&w)[PAT], const Grid& g, int X, int Y, int Z, long i,
-                                         const double* __restrict__ U, std::integer_sequence<int, S...>) {
-  (ilu_row<PAT, S>(w, g, X, Y, Z, i, U, std::make_integer_sequence<int, PAT - PAT / 2 - 1>{}), ...);
+__device__ __forceinline__ void ilu_rows(double (&w)[PAT], const Grid& g, long i, const IluNb& nb,
+                                         const double* __restrict__ U, const double* zero,
+                                         std::integer_sequence<int, S...>) {
+  using Up = std::make_integer_sequence<int, PAT - PAT / 2 - 1>;
+  IluRowVals<PAT> v;
+  (ilu_load<PAT, S>(v, g, i, nb, U, zero, Up{}), ...);
+  (ilu_elim<PAT, S>(w, v, Up{}), ...);
 }
 
 // ILU(0) rows on one hyperplane wx*x + wy*y + z = tau (all their lower
@@ -214,31 +272,30 @@ __device__ __forceinline__ bool ilu_point(const Grid& g, int tau, int x0, int nx
 // its own pattern PA where there is one and the neighbour is in the grid,
 // else 0 (a mask larger than A's pattern keeps fill there, a smaller one
 // drops A's other entries).  Outside the grid the slot reads the stored zero
-// z0 = U[PAT*N] through a selected address: a select of the loaded value
-// instead lets the compiler move each load into a branch that waits for it
-// alone, one memory round trip per slot.
+// through a selected address: a select of the loaded value instead lets the
+// compiler move each load into a branch that waits for it alone, one memory
+// round trip per slot.
 template <int PAT, int PA, int S>
-__device__ __forceinline__ void ilu_init(double (&w)[PAT], const double* __restrict__ A, const double* z0, long N,
-                                         long i, const Grid& g, int X, int Y, int Z) {
+__device__ __forceinline__ void ilu_init(double (&w)[PAT], const double* __restrict__ A, const double* zero, long N,
+                                         long i, const IluNb& nb) {
   constexpr int dx = pat_off(PAT, S, 0), dy = pat_off(PAT, S, 1), dz = pat_off(PAT, S, 2);
   constexpr int sa = pat_slot(PA, dx, dy, dz);
   if constexpr (sa >= 0) {
-    w[S] = *(in_grid(g, X + dx, Y + dy, Z + dz) ? A + (long)sa * N + i : z0);
+    w[S] = *(ilu_nb<dx, dy, dz>(nb) ? A + (long)sa * N + i : zero);
   } else {
     w[S] = 0.0;
   }
 }
 
 template <int PAT, int PA, int... S>
-__device__ __forceinline__ void ilu_init_row(double (&w)[PAT], const double* __restrict__ A, const double* z0,
-                                             long N, long i, const Grid& g, int X, int Y, int Z,
-                                             std::integer_sequence<int, S...>) {
-  (ilu_init<PAT, PA, S>(w, A, z0, N, i, g, X, Y, Z), ...);
+__device__ __forceinline__ void ilu_init_row(double (&w)[PAT], const double* __restrict__ A, const double* zero,
+                                             long N, long i, const IluNb& nb, std::integer_sequence<int, S...>) {
+  (ilu_init<PAT, PA, S>(w, A, zero, N, i, nb), ...);
 }
 
 // PAT: the factor mask (its hyperplanes order the rows); PA: A's pattern.
 template <int PAT, int PA>
-__global__ __launch_bounds__(ILU_WG) void k_ilu0_plane(Grid g, int tau, int x0, int nxr,
+__global__ __launch_bounds__(ILU_WG) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_ilu0_plane(Grid g, int tau, int x0, int nxr,
                                                        const double* __restrict__ A, double* __restrict__ L,
                                                        double* __restrict__ U, double* __restrict__ rU,
                                                        unsigned* err) {
@@ -248,9 +305,11 @@ __global__ __launch_bounds__(ILU_WG) void k_ilu0_plane(Grid g, int tau, int x0, 
   int X, Y, Z;
   if (!ilu_point<WX, WY>(g, tau, x0, nxr, kb, (int)(blockIdx.x * (unsigned)ILU_WG + threadIdx.x), X, Y, Z)) return;
   const long i = ((long)X * g.ny + Y) * g.nz + Z;
+  const IluNb nb{X > 0, X < g.nx - 1, Y > 0, Y < g.ny - 1, Z > 0, Z < g.nz - 1};
+  const double* zero = U + (long)PAT * N;  // U[PAT*N] = 0, U[PAT*N+1] = 1
   double w[PAT];
-  ilu_init_row<PAT, PA>(w, A, U + (long)PAT * N, N, i, g, X, Y, Z, std::make_integer_sequence<int, PAT>{});
-  ilu_rows<PAT>(w, g, X, Y, Z, i, U, std::make_integer_sequence<int, C>{});
+  ilu_init_row<PAT, PA>(w, A, zero, N, i, nb, std::make_integer_sequence<int, PAT>{});
+  ilu_rows<PAT>(w, g, i, nb, U, zero, std::make_integer_sequence<int, C>{});
 #pragma unroll
   for (int s = 0; s < PAT; ++s) {
     L[(long)s * N + i] = s < C ? w[s] : 0.0;
