@@ -612,20 +612,23 @@ __global__ __launch_bounds__(256) void k_wf_pack(Grid g, WfTiling tl, int dir, c
   const long N = g.N();
   const long row = q / WF_NL;
   const int lane = (int)(q % WF_NL);
+  // positions without a point read point 0 and store zeros: every load is
+  // unconditional and all of them come before the first store, so a
+  // thread's loads are in flight together
+  const long ic = i >= 0 ? i : 0;
+  E v[NPK * K];
+#pragma unroll
+  for (int m = 0; m < NPK * K; ++m) {
+    double x = 0.0;
+    if (m < NT) x = (dir > 0 ? lo + (long)m * N : up + (long)(C + 1 + m) * N)[ic];
+    if (m == NT) x = dg[ic];
+    v[m] = to_e<E>(i >= 0 ? x : 0.0);
+  }
 #pragma unroll
   for (int p = 0; p < NPK; ++p) {
-    E v[K];
-#pragma unroll
-    for (int e = 0; e < K; ++e) {
-      const int m = p * K + e;
-      double x = 0.0;
-      if (i >= 0 && m < NT) x = (dir > 0 ? lo[(long)m * N + i] : up[(long)(C + 1 + m) * N + i]);
-      if (i >= 0 && m == NT) x = dg[i];
-      v[e] = to_e<E>(x);
-    }
     E* o = out + ((row * NPK + p) * WF_NL + lane) * K;
 #pragma unroll
-    for (int e = 0; e < K; ++e) o[e] = v[e];
+    for (int e = 0; e < K; ++e) o[e] = v[p * K + e];
   }
 }
 
@@ -642,18 +645,26 @@ __global__ __launch_bounds__(256) void k_wf_pack_h(Grid g, WfTiling tl, int dir,
   const long N = g.N();
   const long row = q / WF_NL;
   const int lane = (int)(q % WF_NL);
+  // unconditional loads (point 0 for positions without a point), all before
+  // the first store
+  const long ic = i >= 0 ? i : 0;
+  __half v[NPK * K];
+#pragma unroll
+  for (int m = 0; m < NPK * K; ++m) {
+    __half x = __float2half_rn(0.0f);
+    if (m < NT) x = (a16 + (long)(dir > 0 ? m : C + 1 + m) * N)[ic];
+    v[m] = i >= 0 ? x : __float2half_rn(0.0f);
+  }
+  const float s0 = sc[ic], s1 = rd[ic];
 #pragma unroll
   for (int p = 0; p < NPK; ++p) {
     __half* o = out + ((row * NPK + p) * WF_NL + lane) * K;
 #pragma unroll
-    for (int e = 0; e < K; ++e) {
-      const int m = p * K + e;
-      o[e] = (i >= 0 && m < NT) ? a16[(long)(dir > 0 ? m : C + 1 + m) * N + i] : __float2half_rn(0.0f);
-    }
+    for (int e = 0; e < K; ++e) o[e] = v[p * K + e];
   }
   if (dir > 0) {
-    sd[2 * q] = i >= 0 ? sc[i] : 0.0f;
-    sd[2 * q + 1] = i >= 0 ? rd[i] : 0.0f;
+    sd[2 * q] = i >= 0 ? s0 : 0.0f;
+    sd[2 * q + 1] = i >= 0 ? s1 : 0.0f;
   }
 }
 
