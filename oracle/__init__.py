@@ -48,6 +48,7 @@ def lib():
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _fp = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
 _ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_lp = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 _i = C.c_int
 
 
@@ -82,6 +83,7 @@ def _declare(L):
     L.orc_od_weights.argtypes = [_i, _i, _i, _i, _ip, _dp, _i, _dp]
     L.orc_od_weights.restype = _i
     L.orc_rap_od.argtypes = [_i, _i, _i, _i, _ip, _dp, _i, _dp, _dp]
+    L.orc_rap_od_points.argtypes = [_i, _i, _i, _i, _ip, _dp, _i, _dp, _i, _lp, _dp]
     L.orc_ilu0.argtypes = [_i, _i, _i, _i, _ip, _dp, _dp, _dp, _dp]
     L.orc_ilu0.restype = _i
     L.orc_ilu0_mask.argtypes = [_i, _i, _i, _i, _ip, _dp, _i, _ip, _dp, _dp, _dp]
@@ -274,6 +276,16 @@ def rap_od(off, Af, shape, cmask, W):
     Ac = np.zeros((27, int(np.prod(coarse_dims(shape, cmask)))))
     lib().orc_rap_od(*_dims(shape), off.shape[0], off.ravel(), _c(Af, np.float64).ravel(), int(cmask),
                      _c(W, np.float64).ravel(), Ac.ravel())
+    return Ac
+
+
+def rap_od_points(off, Af, shape, cmask, W, pts):
+    """Rows (27, len(pts)) of rap_od at the flat coarse indices pts."""
+    off = _c(off, np.int32)
+    pts = _c(np.asarray(pts), np.int64)
+    Ac = np.zeros((27, pts.size))
+    lib().orc_rap_od_points(*_dims(shape), off.shape[0], off.ravel(), _c(Af, np.float64).ravel(), int(cmask),
+                            _c(W, np.float64).ravel(), int(pts.size), pts.ravel(), Ac.ravel())
     return Ac
 
 

@@ -643,6 +643,51 @@ static int od_corner(const int* g, const int* cm, const int* J) {
  * of fma(A(u, s), W(g, corner J), t) from zero; then
  * acc = fma(W(u, corner I), t, acc) (the per-u partial sum times R(I, u), as
  * in the grouping of Listing 1).  Coarse operators are 27-point. */
+/* The 27 entries of coarse row I (coarse grid nc, 27-point offsets off27),
+ * written to Ac[n * ldc] for n = 0..26. */
+static void od_rap_row(const int* nf, const int* nc, const int* cm, int S, const int* off, const int* off27,
+                       const double* Af, const double* W, const int* I, double* Ac, long ldc) {
+  long Nf = (long)nf[0] * nf[1] * nf[2];
+  int fI[3];
+  for (int a = 0; a < 3; ++a) fI[a] = cm[a] ? 2 * I[a] + 1 : I[a];
+  for (int n = 0; n < 27; ++n) {
+    int J[3], inJ = 1;
+    for (int a = 0; a < 3; ++a) {
+      J[a] = I[a] + off27[3 * n + a];
+      if (J[a] < 0 || J[a] >= nc[a]) inJ = 0;
+    }
+    double acc = 0.0;
+    if (inJ)
+      for (int rho = 0; rho < 27; ++rho) {
+        int rr[3] = {rho / 9 - 1, (rho / 3) % 3 - 1, rho % 3 - 1}, u[3], ok = 1;
+        for (int a = 0; a < 3; ++a) {
+          if (!cm[a] && rr[a] != 0) ok = 0;
+          u[a] = fI[a] + rr[a];
+          if (u[a] < 0 || u[a] >= nf[a]) ok = 0;
+        }
+        if (!ok) continue;
+        int cu = od_corner(u, cm, I);
+        if (cu < 0) continue;
+        long iu = ((long)u[0] * nf[1] + u[1]) * nf[2] + u[2];
+        double t = 0.0;
+        for (int s2 = 0; s2 < S; ++s2) {
+          int g[3], in = 1;
+          for (int a = 0; a < 3; ++a) {
+            g[a] = u[a] + off[3 * s2 + a];
+            if (g[a] < 0 || g[a] >= nf[a]) in = 0;
+          }
+          if (!in) continue;
+          int cg = od_corner(g, cm, J);
+          if (cg < 0) continue;
+          long ig = ((long)g[0] * nf[1] + g[1]) * nf[2] + g[2];
+          t = fma(Af[(long)s2 * Nf + iu], W[(long)cg * Nf + ig], t);
+        }
+        acc = fma(W[(long)cu * Nf + iu], t, acc);
+      }
+    Ac[(long)n * ldc] = acc;
+  }
+}
+
 void orc_rap_od(int nxf, int nyf, int nzf, int S, const int* off, const double* Af, int cmask, const double* W,
                 double* Ac) {
   int nf[3] = {nxf, nyf, nzf}, nc[3], cm[3];
@@ -650,52 +695,35 @@ void orc_rap_od(int nxf, int nyf, int nzf, int S, const int* off, const double* 
     cm[a] = (cmask >> a) & 1;
     nc[a] = cm[a] ? nf[a] / 2 : nf[a];
   }
-  long Nf = (long)nf[0] * nf[1] * nf[2], Nc = (long)nc[0] * nc[1] * nc[2];
+  long Nc = (long)nc[0] * nc[1] * nc[2];
   int off27[81];
   orc_pattern(27, off27);
   for (int X = 0; X < nc[0]; ++X)
     for (int Y = 0; Y < nc[1]; ++Y)
       for (int Z = 0; Z < nc[2]; ++Z) {
-        int I[3] = {X, Y, Z}, fI[3];
-        for (int a = 0; a < 3; ++a) fI[a] = cm[a] ? 2 * I[a] + 1 : I[a];
+        int I[3] = {X, Y, Z};
         long ic = ((long)X * nc[1] + Y) * nc[2] + Z;
-        for (int n = 0; n < 27; ++n) {
-          int J[3], inJ = 1;
-          for (int a = 0; a < 3; ++a) {
-            J[a] = I[a] + off27[3 * n + a];
-            if (J[a] < 0 || J[a] >= nc[a]) inJ = 0;
-          }
-          double acc = 0.0;
-          if (inJ)
-            for (int rho = 0; rho < 27; ++rho) {
-              int rr[3] = {rho / 9 - 1, (rho / 3) % 3 - 1, rho % 3 - 1}, u[3], ok = 1;
-              for (int a = 0; a < 3; ++a) {
-                if (!cm[a] && rr[a] != 0) ok = 0;
-                u[a] = fI[a] + rr[a];
-                if (u[a] < 0 || u[a] >= nf[a]) ok = 0;
-              }
-              if (!ok) continue;
-              int cu = od_corner(u, cm, I);
-              if (cu < 0) continue;
-              long iu = ((long)u[0] * nf[1] + u[1]) * nf[2] + u[2];
-              double t = 0.0;
-              for (int s2 = 0; s2 < S; ++s2) {
-                int g[3], in = 1;
-                for (int a = 0; a < 3; ++a) {
-                  g[a] = u[a] + off[3 * s2 + a];
-                  if (g[a] < 0 || g[a] >= nf[a]) in = 0;
-                }
-                if (!in) continue;
-                int cg = od_corner(g, cm, J);
-                if (cg < 0) continue;
-                long ig = ((long)g[0] * nf[1] + g[1]) * nf[2] + g[2];
-                t = fma(Af[(long)s2 * Nf + iu], W[(long)cg * Nf + ig], t);
-              }
-              acc = fma(W[(long)cu * Nf + iu], t, acc);
-            }
-          Ac[(long)n * Nc + ic] = acc;
-        }
+        od_rap_row(nf, nc, cm, S, off, off27, Af, W, I, Ac + ic, Nc);
       }
+}
+
+/* The same rows at npts listed coarse points (flat coarse indices pts[k]):
+ * Ac[n * npts + k].  For checks of a large grid's product at sampled points
+ * without forming the whole coarse operator. */
+void orc_rap_od_points(int nxf, int nyf, int nzf, int S, const int* off, const double* Af, int cmask,
+                       const double* W, int npts, const long* pts, double* Ac) {
+  int nf[3] = {nxf, nyf, nzf}, nc[3], cm[3];
+  for (int a = 0; a < 3; ++a) {
+    cm[a] = (cmask >> a) & 1;
+    nc[a] = cm[a] ? nf[a] / 2 : nf[a];
+  }
+  int off27[81];
+  orc_pattern(27, off27);
+  for (int k = 0; k < npts; ++k) {
+    long ic = pts[k];
+    int I[3] = {(int)(ic / ((long)nc[1] * nc[2])), (int)((ic / nc[2]) % nc[1]), (int)(ic % nc[2])};
+    od_rap_row(nf, nc, cm, S, off, off27, Af, W, I, Ac + k, npts);
+  }
 }
 
 /* ---- Thomas factorisation of the z-columns (Sec. 4.4, LGS paragraph) ---

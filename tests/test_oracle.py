@@ -553,6 +553,25 @@ def test_od_transfers_and_rap_match_dense(npts, shape, cmask):
                        atol=1e-13 * np.abs(M).max())
 
 
+@pytest.mark.parametrize("shape,cmask", [((9, 8, 7), 7), ((8, 6, 5), 3), ((6, 7, 8), 6)])
+def test_od_rap_points_match_dense(shape, cmask):
+    """Rows of the stencil product at listed coarse points (in a shuffled
+    order, with repeats) equal the whole product's rows and the rows of
+    P^T A P assembled densely from the weights."""
+    off = workloads.offsets(7)
+    A = workloads.random_sgdia(shape, 7, seed=23, symmetric=False)
+    W = oracle.od_weights(off, A, shape, cmask)
+    P, cs = helpers.od_matrix(W, shape, cmask)
+    nc = int(np.prod(cs))
+    pts = workloads.rng(8).permutation(np.concatenate([np.arange(nc), [0, nc - 1]]))
+    Ap = oracle.rap_od_points(off, A, shape, cmask, W, pts)
+    Ac = oracle.rap_od(off, A, shape, cmask, W)
+    assert np.array_equal(Ap, Ac[:, pts])
+    D = P.T @ helpers.dense_from_sgdia(A, off, shape) @ P
+    rows = helpers.dense_from_sgdia(Ac, workloads.offsets(27), cs)
+    assert np.allclose(rows[pts], D[pts], rtol=0, atol=1e-13 * np.abs(A).max())
+
+
 def test_od_hierarchy_symmetric_and_faster_on_high_contrast():
     """R = P^T keeps the cycle symmetric; on the high-contrast diffusion
     stand-in the operator-dependent interpolation needs fewer PCG iterations
