@@ -72,6 +72,7 @@ def _declare(L):
     L.orc_pattern.argtypes = [_i, _ip]
     L.orc_pattern.restype = _i
     L.orc_rap.argtypes = [_i, _i, _i, _i, _ip, _i, _dp, _i, _dp]
+    L.orc_rap_points.argtypes = [_i, _i, _i, _i, _ip, _i, _dp, _i, _i, _lp, _dp]
     L.orc_rap_chains.argtypes = [_i, _ip, _i, _i, _ip, _i]
     L.orc_rap_chains.restype = _i
     L.orc_rap_cc.argtypes = [_i, _i, _i, _i, _ip, _i, _dp, _i, _dp]
@@ -343,6 +344,16 @@ def rap(off, Af, shape, cmask, bs=1):
     Ac = np.zeros((27 * bs * bs, Nc))
     lib().orc_rap(*_dims(shape), off.shape[0], off.ravel(), int(bs), _c(Af, np.float64).ravel(), int(cmask),
                   Ac.ravel())
+    return Ac
+
+
+def rap_points(off, Af, shape, cmask, pts, bs=1):
+    """Rows (27 * bs^2, len(pts)) of rap at the flat coarse indices pts."""
+    off = _c(off, np.int32)
+    pts = _c(np.asarray(pts), np.int64)
+    Ac = np.zeros((27 * bs * bs, pts.size))
+    lib().orc_rap_points(*_dims(shape), off.shape[0], off.ravel(), int(bs), _c(Af, np.float64).ravel(), int(cmask),
+                         int(pts.size), pts.ravel(), Ac.ravel())
     return Ac
 
 

@@ -131,61 +131,82 @@ static int rap_chain_ok(const int* rho, const int* a, const int* n, int cmask, d
  * the 9 block entries as an independent scalar field (P, R act per unknown).
  * Output Ac[(n*bs*bs + e)*Nc + I], with Nc the coarse grid size.
  */
-void orc_rap(int nxf, int nyf, int nzf, int S, const int* off, int bs, const double* Af, int cmask,
-             double* Ac) {
-  int nf[3] = {nxf, nyf, nzf}, nc[3], cm[3];
+/* The 27 * bs^2 entries of coarse row I, written to Ac[(n * be + e) * ldc]. */
+static void rap_row(const int* nf, const int* nc, int S, const int* off, int bs, const double* Af, int cmask,
+                    const int* I, double* Ac, long ldc) {
+  int cm[3], fI[3];
+  long Nf = (long)nf[0] * nf[1] * nf[2];
+  int be = bs * bs;
   for (int a = 0; a < 3; ++a) {
     cm[a] = (cmask >> a) & 1;
-    nc[a] = cm[a] ? nf[a] / 2 : nf[a];
+    fI[a] = cm[a] ? 2 * I[a] + 1 : I[a];
   }
-  long Nf = (long)nf[0] * nf[1] * nf[2], Nc = (long)nc[0] * nc[1] * nc[2];
-  int be = bs * bs;
+  int ni = 0;
+  for (int nx_ = -1; nx_ <= 1; ++nx_)
+    for (int ny_ = -1; ny_ <= 1; ++ny_)
+      for (int nz_ = -1; nz_ <= 1; ++nz_, ++ni) {
+        int n[3] = {nx_, ny_, nz_}, J[3], inJ = 1;
+        for (int a = 0; a < 3; ++a) {
+          J[a] = I[a] + n[a];
+          if (J[a] < 0 || J[a] >= nc[a]) inJ = 0;
+        }
+        for (int e = 0; e < be; ++e) {
+          double res = 0.0;
+          if (inJ) {
+            for (int rx = -1; rx <= 1; ++rx)
+              for (int ry = -1; ry <= 1; ++ry)
+                for (int rz = -1; rz <= 1; ++rz) {
+                  int rho[3] = {rx, ry, rz}, u[3], inU = 1;
+                  for (int a = 0; a < 3; ++a) {
+                    u[a] = fI[a] + rho[a];
+                    if (u[a] < 0 || u[a] >= nf[a]) inU = 0;
+                  }
+                  if (!inU) continue;
+                  int anyc = 0;
+                  double wR = 1.0, tmp = 0.0;
+                  long iu = ((long)u[0] * nf[1] + u[1]) * nf[2] + u[2];
+                  for (int s = 0; s < S; ++s) {
+                    double wr, wp;
+                    if (!rap_chain_ok(rho, &off[3 * s], n, cmask, &wr, &wp)) continue;
+                    int v0 = u[0] + off[3 * s], v1 = u[1] + off[3 * s + 1], v2 = u[2] + off[3 * s + 2];
+                    if (v0 < 0 || v0 >= nf[0] || v1 < 0 || v1 >= nf[1] || v2 < 0 || v2 >= nf[2]) continue;
+                    wR = wr;
+                    anyc = 1;
+                    tmp = fma(Af[((long)s * be + e) * Nf + iu], wp, tmp);
+                  }
+                  if (anyc) res = fma(tmp, wR, res);
+                }
+          }
+          Ac[((long)ni * be + e) * ldc] = res;
+        }
+      }
+}
+
+void orc_rap(int nxf, int nyf, int nzf, int S, const int* off, int bs, const double* Af, int cmask,
+             double* Ac) {
+  int nf[3] = {nxf, nyf, nzf}, nc[3];
+  for (int a = 0; a < 3; ++a) nc[a] = (cmask >> a) & 1 ? nf[a] / 2 : nf[a];
+  long Nc = (long)nc[0] * nc[1] * nc[2];
   for (int X = 0; X < nc[0]; ++X)
     for (int Y = 0; Y < nc[1]; ++Y)
       for (int Z = 0; Z < nc[2]; ++Z) {
-        int I[3] = {X, Y, Z}, fI[3];
-        for (int a = 0; a < 3; ++a) fI[a] = cm[a] ? 2 * I[a] + 1 : I[a];
+        int I[3] = {X, Y, Z};
         long ic = ((long)X * nc[1] + Y) * nc[2] + Z;
-        int ni = 0;
-        for (int nx_ = -1; nx_ <= 1; ++nx_)
-          for (int ny_ = -1; ny_ <= 1; ++ny_)
-            for (int nz_ = -1; nz_ <= 1; ++nz_, ++ni) {
-              int n[3] = {nx_, ny_, nz_}, J[3], inJ = 1;
-              for (int a = 0; a < 3; ++a) {
-                J[a] = I[a] + n[a];
-                if (J[a] < 0 || J[a] >= nc[a]) inJ = 0;
-              }
-              for (int e = 0; e < be; ++e) {
-                double res = 0.0;
-                if (inJ) {
-                  for (int rx = -1; rx <= 1; ++rx)
-                    for (int ry = -1; ry <= 1; ++ry)
-                      for (int rz = -1; rz <= 1; ++rz) {
-                        int rho[3] = {rx, ry, rz}, u[3], inU = 1;
-                        for (int a = 0; a < 3; ++a) {
-                          u[a] = fI[a] + rho[a];
-                          if (u[a] < 0 || u[a] >= nf[a]) inU = 0;
-                        }
-                        if (!inU) continue;
-                        int anyc = 0;
-                        double wR = 1.0, tmp = 0.0;
-                        long iu = ((long)u[0] * nf[1] + u[1]) * nf[2] + u[2];
-                        for (int s = 0; s < S; ++s) {
-                          double wr, wp;
-                          if (!rap_chain_ok(rho, &off[3 * s], n, cmask, &wr, &wp)) continue;
-                          int v0 = u[0] + off[3 * s], v1 = u[1] + off[3 * s + 1], v2 = u[2] + off[3 * s + 2];
-                          if (v0 < 0 || v0 >= nf[0] || v1 < 0 || v1 >= nf[1] || v2 < 0 || v2 >= nf[2]) continue;
-                          wR = wr;
-                          anyc = 1;
-                          tmp = fma(Af[((long)s * be + e) * Nf + iu], wp, tmp);
-                        }
-                        if (anyc) res = fma(tmp, wR, res);
-                      }
-                }
-                Ac[((long)ni * be + e) * Nc + ic] = res;
-              }
-            }
+        rap_row(nf, nc, S, off, bs, Af, cmask, I, Ac + ic, Nc);
       }
+}
+
+/* The same rows at npts listed coarse points (flat coarse indices pts[k]):
+ * Ac[(n * be + e) * npts + k]. */
+void orc_rap_points(int nxf, int nyf, int nzf, int S, const int* off, int bs, const double* Af, int cmask,
+                    int npts, const long* pts, double* Ac) {
+  int nf[3] = {nxf, nyf, nzf}, nc[3];
+  for (int a = 0; a < 3; ++a) nc[a] = (cmask >> a) & 1 ? nf[a] / 2 : nf[a];
+  for (int k = 0; k < npts; ++k) {
+    long ic = pts[k];
+    int I[3] = {(int)(ic / ((long)nc[1] * nc[2])), (int)((ic / nc[2]) % nc[1]), (int)(ic % nc[2])};
+    rap_row(nf, nc, S, off, bs, Af, cmask, I, Ac + k, npts);
+  }
 }
 
 /*

@@ -295,6 +295,25 @@ def test_rap_block_matches_brute_force():
     assert np.abs(Ac - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("npts,shape,cmask,bs", [(19, (8, 6, 5), 3, 1), (7, (6, 5, 7), 7, 1), (27, (5, 6, 4), 7, 3)])
+def test_rap_points_match_whole_and_brute_force(npts, shape, cmask, bs):
+    """Rows of the stencil product at listed coarse points (shuffled, with
+    repeats) equal the whole product's rows and the brute-force P^T A P."""
+    off = workloads.offsets(npts)
+    A = workloads.random_sgdia(shape, npts, seed=37, block=bs)
+    Ac = oracle.rap(off, A, shape, cmask, bs=bs)
+    cs = oracle.coarse_dims(shape, cmask)
+    nc = int(np.prod(cs))
+    pts = workloads.rng(12).permutation(np.concatenate([np.arange(nc), [0, nc - 1]]))
+    Ap = oracle.rap_points(off, A, shape, cmask, pts, bs=bs)
+    assert np.array_equal(Ap, Ac[:, pts])
+    M = helpers.dense_from_sgdia(A, off, shape, bs=bs)
+    P, _ = helpers.interp_matrix(shape, cmask)
+    P = np.kron(P, np.eye(bs))
+    ref = helpers.sgdia_from_dense27(P.T @ M @ P, cs, bs=bs, tol=1e-12)
+    assert np.abs(Ap - ref[:, pts]).max() <= 1e-13 * np.abs(ref).max()
+
+
 def _tridiag(n, c, d):
     T = np.diag(np.full(n, d)) + np.diag(np.full(n - 1, c), 1) + np.diag(np.full(n - 1, c), -1)
     return T
