@@ -193,3 +193,34 @@ def od_matrix(W, shape, cmask):
                     if all(0 <= J[a] < cs[a] for a in range(3)):
                         P[i, lin(cs, *J)] += W[c, i]
     return P, cs
+
+
+def masked_sgdia(A, off, shape, be=1):
+    """SG-DIA matrix (len(off) * be, N) with the couplings of slot s zeroed
+    where the neighbour i + off[s] lies outside the grid (the finest level's
+    Dirichlet masking); be entries per slot (9 for 3x3 blocks)."""
+    Am = np.array(A, dtype=np.float64).reshape(len(off), be, *shape)
+    for s, o in enumerate(off):
+        for a in range(3):
+            if o[a] != 0:
+                sl = [slice(None)] * 3
+                sl[a] = slice(0, 1) if o[a] < 0 else slice(shape[a] - 1, shape[a])
+                Am[(s, slice(None), *sl)] = 0.0
+    return Am.reshape(len(off) * be, -1)
+
+
+def coarse_sample_points(cdims, n, seed):
+    """Sorted distinct flat indices of about 2n coarse points: n uniform in the
+    grid, n on its faces, and its 8 corners."""
+    g = np.random.default_rng(seed)
+    X, Y, Z = (g.integers(0, d, size=n) for d in cdims)
+    face, side = g.integers(0, 3, size=n), g.integers(0, 2, size=n)
+    B = [X.copy(), Y.copy(), Z.copy()]
+    for a in range(3):
+        B[a] = np.where(face == a, side * (cdims[a] - 1), B[a])
+    corners = np.array([(x, y, z) for x in (0, cdims[0] - 1) for y in (0, cdims[1] - 1) for z in (0, cdims[2] - 1)])
+
+    def flat(x, y, z):
+        return (np.asarray(x, np.int64) * cdims[1] + np.asarray(y)) * cdims[2] + np.asarray(z)
+
+    return np.unique(np.concatenate([flat(X, Y, Z), flat(*B), flat(*corners.T)])).astype(np.int64)

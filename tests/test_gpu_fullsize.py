@@ -15,6 +15,8 @@ import pytest
 import oracle
 import workloads
 
+from tests import helpers
+
 torch = pytest.importorskip("torch")
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
 
@@ -41,19 +43,6 @@ def _say(msg):
     print(f"[fullsize] {msg}", flush=True)
 
 
-def _masked(A, off, shape):
-    """Coupling s of point i kept where the neighbour i + off[s] is in the
-    grid, zero elsewhere (the finest level's Dirichlet masking)."""
-    Am = A.reshape(len(off), *shape).copy()
-    for s, o in enumerate(off):
-        for a in range(3):
-            if o[a] != 0:
-                sl = [slice(None)] * 3
-                sl[a] = slice(0, 1) if o[a] < 0 else slice(shape[a] - 1, shape[a])
-                Am[(s, *sl)] = 0.0
-    return Am.reshape(len(off), -1)
-
-
 @pytest.fixture(scope="module")
 def full():
     _say("generating the 256^3 diffusion workload")
@@ -62,7 +51,7 @@ def full():
     _say("GPU hierarchy")
     mg = smg.StructMG(T(A), SHAPE, pattern=7, smoother="gs", coarsen="full", semi_levels=0, interp="operator",
                       device=DEV)
-    Am = _masked(A, off, SHAPE)
+    Am = helpers.masked_sgdia(A, off, SHAPE)
     _say("oracle interpolation weights")
     W = oracle.od_weights(off, Am, SHAPE, CMASK)
     return dict(A=A, b=b, off=off, mg=mg, Am=Am, W=W)
@@ -111,17 +100,7 @@ def test_fullsize_level1_product_sampled(full):
     mg, Am, W, off = full["mg"], full["Am"], full["W"], full["off"]
     cdims = oracle.coarse_dims(SHAPE, CMASK)
     nc = int(np.prod(cdims))
-    g = workloads.rng(43)
-    # random interior and boundary rows, the corners of the coarse grid
-    X, Y, Z = (g.integers(0, d, size=6000) for d in cdims)
-    face = g.integers(0, 3, size=6000)
-    side = g.integers(0, 2, size=6000)
-    B = [X.copy(), Y.copy(), Z.copy()]
-    for a in range(3):
-        B[a] = np.where(face == a, side * (cdims[a] - 1), B[a])
-    corners = [(x, y, z) for x in (0, cdims[0] - 1) for y in (0, cdims[1] - 1) for z in (0, cdims[2] - 1)]
-    flat = lambda x, y, z: (np.asarray(x) * cdims[1] + np.asarray(y)) * cdims[2] + np.asarray(z)  # noqa: E731
-    pts = np.unique(np.concatenate([flat(X, Y, Z), flat(*B), [flat(*c) for c in corners]]).astype(np.int64))
+    pts = helpers.coarse_sample_points(cdims, 6000, 43)
     _say(f"level-1 product at {pts.size} coarse points")
     A1 = N(mg.export(1, 0, torch.empty((27, nc), dtype=torch.float64, device=DEV)))
     assert np.array_equal(A1[:, pts], oracle.rap_od_points(off, Am, SHAPE, CMASK, W, pts))
