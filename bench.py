@@ -128,9 +128,29 @@ def cpu_baseline(name, interp="vertex"):
     H = oracle.Hierarchy(shape, 7, A, interp=interp)
     x, st, it, rel = H.pcg(b, 1e-9, 200)
     t = time.perf_counter() - t0
-    return {"value": round(t * 1e3 * scale, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+    info = {"value": round(t * 1e3 * scale, 1), "unit": "ms", "cores": 1, "kind": "oracle",
             "sample": f"{sample}, {interp} interpolation; measured {t:.1f}s, {it} iterations, "
                       f"rel resid {rel:.2e}"}
+    return info, dict(shape=shape, A=A, b=b, x=x, desc=sample)
+
+
+def oracle_errors(smg, torch, np, dev, sample, kw, krylov):
+    """Each V-cycle precision's PCG solution on the oracle's sample against
+    the FP64 oracle solution: relative 2-norm error and true residual."""
+    A = torch.from_numpy(sample["A"]).to(dev)
+    b = torch.from_numpy(sample["b"].ravel().copy()).to(dev)
+    xo = sample["x"].ravel()
+    out = {"sample": sample["desc"]}
+    for prec in ("fp64", "fp32", "fp16"):
+        m = smg.StructMG(A, sample["shape"], device=dev, prec=prec, **kw)
+        x = torch.zeros_like(b)
+        r = m.solve(b, x, rtol=1e-9, maxit=300, krylov=krylov)
+        torch.cuda.synchronize()
+        xg = x.cpu().numpy()
+        out[prec] = {"rel_err_vs_oracle": float(np.linalg.norm(xg - xo) / np.linalg.norm(xo)),
+                     "rel_resid_true": r["rel_resid_true"], "iters": r["iters"]}
+        m.close()
+    return out
 
 
 # ---- supplementary workloads (opt-in; the default line is the 256^3 diffusion)
@@ -496,7 +516,8 @@ def main():
         line["mixed"] = mixed
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(args.workload, W["interp"])
+        line["cpu_baseline"], sample = cpu_baseline(args.workload, W["interp"])
+        line["oracle_error"] = oracle_errors(smg, torch, np, dev, sample, kw, W["krylov"])
     print(json.dumps(line), flush=True)
 
 
