@@ -134,17 +134,17 @@ def cpu_baseline(name, interp="vertex"):
     return info, dict(shape=shape, A=A, b=b, x=x, desc=sample)
 
 
-def oracle_errors(smg, torch, np, dev, sample, kw, krylov):
-    """Each V-cycle precision's PCG solution on the oracle's sample against
+def oracle_errors(smg, torch, np, dev, sample, kw, krylov, precs=("fp64", "fp32", "fp16"), tol=1e-9):
+    """Each V-cycle precision's Krylov solution on the oracle's sample against
     the FP64 oracle solution: relative 2-norm error and true residual."""
     A = torch.from_numpy(sample["A"]).to(dev)
     b = torch.from_numpy(sample["b"].ravel().copy()).to(dev)
     xo = sample["x"].ravel()
     out = {"sample": sample["desc"]}
-    for prec in ("fp64", "fp32", "fp16"):
+    for prec in precs:
         m = smg.StructMG(A, sample["shape"], device=dev, prec=prec, **kw)
         x = torch.zeros_like(b)
-        r = m.solve(b, x, rtol=1e-9, maxit=300, krylov=krylov)
+        r = m.solve(b, x, rtol=tol, maxit=500, krylov=krylov)
         torch.cuda.synchronize()
         xg = x.cpu().numpy()
         out[prec] = {"rel_err_vs_oracle": float(np.linalg.norm(xg - xo) / np.linalg.norm(xo)),
@@ -197,15 +197,32 @@ def extra_weather(args, smg, torch, np, dev):
     shape = (512, 512, 64)
     A, b = workloads.weather19(shape, seed=3)
     W = dict(shape=shape, A=A, b=b)
-    res = _variants(args, smg, torch, np, dev, W, ("fp64", "fp32"), 1e-9, 30, pattern=19, smoother="ilu0",
-                    coarsen="semi_xy", gmres_restart=30, ilu_mask=args.ilu_mask)
+    kw = dict(pattern=19, smoother="ilu0", coarsen="semi_xy", gmres_restart=30, ilu_mask=args.ilu_mask)
+    res = _variants(args, smg, torch, np, dev, W, ("fp64", "fp32"), 1e-9, 30, **kw)
     mask = f" on a {args.ilu_mask}-point mask" if args.ilu_mask else ""
-    print(json.dumps({"metric": METRIC, "value": res["fp32"]["ms_per_step"], "unit": "ms", "n_gpus": 1,
-                      "steps": args.steps, "higher_is_better": False, "dtype": "f32 V-cycle / f64 GMRES",
-                      "data": "synthetic (seeded)",
-                      "config": {"workload": "weather-like 512x512x64, 19-pt, vertical 100x, GMRES(30) + ILU(0)"
-                                             f"{mask} V-cycle, xy-semi coarsening, tol 1e-9"},
-                      "variants": res}), flush=True)
+    line = {"metric": METRIC, "value": res["fp32"]["ms_per_step"], "unit": "ms", "n_gpus": 1,
+            "steps": args.steps, "higher_is_better": False, "dtype": "f32 V-cycle / f64 GMRES",
+            "data": "synthetic (seeded)",
+            "config": {"workload": "weather-like 512x512x64, 19-pt, vertical 100x, GMRES(30) + ILU(0)"
+                                   f"{mask} V-cycle, xy-semi coarsening, tol 1e-9"},
+            "variants": res}
+    if not args.no_cpu_baseline:
+        line["oracle_error"] = oracle_errors(smg, torch, np, dev, weather_sample(args.ilu_mask), kw, 30,
+                                             precs=("fp64", "fp32"))
+    print(json.dumps(line), flush=True)
+
+
+def weather_sample(ilu_mask):
+    """The weather recipe at 128 x 128 x 64 solved by the oracle (GMRES(30),
+    same V-cycle) for the solution-error check."""
+    import oracle
+    import workloads
+    shape = (128, 128, 64)
+    A, b = workloads.weather19(shape, seed=3)
+    H = oracle.Hierarchy(shape, 19, A, smoother="ilu0", coarsen="semi_xy", ilu_mask=ilu_mask)
+    x, st, it, rel = H.gmres(b, 1e-9, 500, restart=30)
+    return dict(shape=shape, A=A, b=b, x=x,
+                desc=f"same recipe at 128x128x64, oracle GMRES(30): {it} iterations, rel resid {rel:.2e}")
 
 
 def extra_weather_lgs(args, smg, torch, np, dev):
@@ -264,12 +281,29 @@ def extra_elasticity(args, smg, torch, np, dev):
     A, b = workloads.elasticity27(n, seed=4)
     W = dict(shape=(n, n, n), A=A, b=b)
     res = _variants(args, smg, torch, np, dev, W, ("fp64", "fp32", "fp16"), 1e-8, 0, pattern=27, block=3)
-    print(json.dumps({"metric": METRIC, "value": res["fp16"]["ms_per_step"], "unit": "ms", "n_gpus": 1,
-                      "steps": args.steps, "higher_is_better": False, "dtype": "f16 V-cycle / f64 PCG",
-                      "data": "synthetic (seeded)",
-                      "config": {"workload": "elasticity-like 128^3 x 3, 27-pt 3x3 blocks, Q1 FEM, log-normal "
-                                             "moduli (sigma 1), nu 0.3, PCG + block-GS V-cycle, tol 1e-8"},
-                      "variants": res}), flush=True)
+    line = {"metric": METRIC, "value": res["fp16"]["ms_per_step"], "unit": "ms", "n_gpus": 1,
+            "steps": args.steps, "higher_is_better": False, "dtype": "f16 V-cycle / f64 PCG",
+            "data": "synthetic (seeded)",
+            "config": {"workload": "elasticity-like 128^3 x 3, 27-pt 3x3 blocks, Q1 FEM, log-normal "
+                                   "moduli (sigma 1), nu 0.3, PCG + block-GS V-cycle, tol 1e-8"},
+            "variants": res}
+    if not args.no_cpu_baseline:
+        line["oracle_error"] = oracle_errors(smg, torch, np, dev, elasticity_sample(), dict(pattern=27, block=3), 0,
+                                             tol=1e-8)
+    print(json.dumps(line), flush=True)
+
+
+def elasticity_sample():
+    """The elasticity recipe at 32^3 nodes solved by the oracle (PCG, same
+    block V-cycle) for the solution-error check."""
+    import oracle
+    import workloads
+    n = 32
+    A, b = workloads.elasticity27(n, seed=4)
+    H = oracle.Hierarchy((n, n, n), 27, A, block=3)
+    x, st, it, rel = H.pcg(b, 1e-8, 500)
+    return dict(shape=(n, n, n), A=A, b=b, x=x,
+                desc=f"same recipe at 32^3 x 3, oracle PCG: {it} iterations, rel resid {rel:.2e}")
 
 
 def extra_batch(args, smg, torch, np, dev):
