@@ -108,17 +108,27 @@ __global__ __launch_bounds__(256) void k_restrict_od(Grid gf, int cmask, const V
   if (ic >= gc.N()) return;
   const int Z = (int)(ic % gc.nz), Y = (int)((ic / gc.nz) % gc.ny), X = (int)(ic / ((long)gc.nz * gc.ny));
   const int fx = cx ? 2 * X + 1 : X, fy = cy ? 2 * Y + 1 : Y, fz = cz ? 2 * Z + 1 : Z;
+  // all 27 candidate fine points, lexicographic; the loads are
+  // unconditional (a point outside the grid or on an uncoarsened axis offset
+  // reads the centre point fine(I), c = 0) so a thread's loads are in flight
+  // together, and such points leave the sum unchanged
+  const long i0 = ((long)fx * gf.ny + fy) * gf.nz + fz;
+  V w[27], r[27];
+  bool ok[27];
+#pragma unroll
+  for (int d = 0; d < 27; ++d) {
+    const int dx = d / 9 - 1, dy = (d / 3) % 3 - 1, dz = d % 3 - 1;
+    const int ux = fx + dx, uy = fy + dy, uz = fz + dz;
+    ok[d] = (cx || dx == 0) && (cy || dy == 0) && (cz || dz == 0) && in_grid(gf, ux, uy, uz);
+    // I is the hi corner of an even coordinate reached from below
+    const int c = ((dx < 0 ? 1 : 0) * 2 + (dy < 0 ? 1 : 0)) * 2 + (dz < 0 ? 1 : 0);
+    const long iu = ok[d] ? ((long)ux * gf.ny + uy) * gf.nz + uz : i0;
+    w[d] = W[(ok[d] ? (long)c * Nf : 0L) + iu];
+    r[d] = rf[iu];
+  }
   V acc = V(0);
-  for (int dx = -cx; dx <= cx; ++dx)
-    for (int dy = -cy; dy <= cy; ++dy)
-      for (int dz = -cz; dz <= cz; ++dz) {
-        const int ux = fx + dx, uy = fy + dy, uz = fz + dz;
-        if (!in_grid(gf, ux, uy, uz)) continue;
-        // I is the hi corner of an even coordinate reached from below
-        const int c = ((dx < 0 ? 1 : 0) * 2 + (dy < 0 ? 1 : 0)) * 2 + (dz < 0 ? 1 : 0);
-        const long iu = ((long)ux * gf.ny + uy) * gf.nz + uz;
-        acc = fma(W[(long)c * Nf + iu], rf[iu], acc);
-      }
+#pragma unroll
+  for (int d = 0; d < 27; ++d) acc = ok[d] ? fma(w[d], r[d], acc) : acc;
   rc[ic] = acc;
 }
 
@@ -133,13 +143,23 @@ __global__ __launch_bounds__(256) void k_prolong_od(Grid gf, int cmask, const V*
   const long i = (long)blockIdx.x * 256 + threadIdx.x;
   if (i >= Nf) return;
   const int Z = (int)(i % gf.nz), Y = (int)((i / gf.nz) % gf.ny), X = (int)(i / ((long)gf.nz * gf.ny));
-  V pe = V(0);
+  // every load is unconditional so that a thread's loads are in flight
+  // together: a corner the point does not have reads the point's corner-0
+  // weight (a line the thread reads anyway) and coarse entry 0, and leaves
+  // the sum unchanged
+  V w[8], e[8];
+  bool ok[8];
+#pragma unroll
   for (int c = 0; c < 8; ++c) {
     const int jx = od_corner_index(X, cx, c / 4), jy = od_corner_index(Y, cy, (c / 2) % 2),
               jz = od_corner_index(Z, cz, c % 2);
-    if (!in_grid(gc, jx, jy, jz)) continue;
-    pe = fma(W[(long)c * Nf + i], ec[((long)jx * gc.ny + jy) * gc.nz + jz], pe);
+    ok[c] = in_grid(gc, jx, jy, jz);
+    w[c] = W[(ok[c] ? (long)c * Nf : 0L) + i];
+    e[c] = ec[ok[c] ? ((long)jx * gc.ny + jy) * gc.nz + jz : 0L];
   }
+  V pe = V(0);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) pe = ok[c] ? fma(w[c], e[c], pe) : pe;
   uout[i] = uin[i] + pe;
 }
 
