@@ -156,9 +156,10 @@ __device__ __forceinline__ long ilu_flat(const Grid& g, int dx, int dy, int dz) 
 // w[slot] = fma(-w[S], U_T[k], w[slot]).
 // The elimination runs in two phases: every pivot and coupling it uses is
 // loaded first (ilu_load), then the arithmetic runs on registers (ilu_elim),
-// so all loads of the row are in flight together.  Every update is performed,
-// with the pivot 1 and the coupling 0 where the neighbour row is outside the
-// grid or the fill is out of the mask; those constants are read from
+// so all loads of the row are in flight together.  Fill outside the mask is
+// dropped at compile time; every other update is performed, with the pivot 1
+// and the coupling 0 where the neighbour row or the coupled point lies
+// outside the grid; those constants are read from
 // one = U[PAT*N+1] and zero = U[PAT*N] through a selected address (a select
 // of a loaded value instead lets the compiler move the load into a branch
 // that waits for it alone).  An address is a per-launch constant
