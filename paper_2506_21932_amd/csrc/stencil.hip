@@ -378,12 +378,20 @@ struct PPOp {
     if (!in_grid(gf, fx, fy, fz)) continue;
     const long i = ((long)fx * gf.ny + fy) * gf.nz + fz;
     const int c = ((lx + 1) * HY + (ly + 1)) * HZ + (lz + 1);
+    // the row's coefficients are loaded unconditionally (row i's own slots)
+    // before the sums, so a thread's loads are in flight together; terms of
+    // neighbours outside the grid leave the sums unchanged
+    constexpr int NS = FULL ? PAT : PAT / 2;
+    V a[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) a[s] = m(s, i);
     if (!FULL) {
       V t = f[i];
 #pragma unroll
       for (int s = 0; s < PAT / 2; ++s) {
         const int dx = pat_off(PAT, s, 0), dy = pat_off(PAT, s, 1), dz = pat_off(PAT, s, 2);
-        if (in_grid(gf, fx + dx, fy + dy, fz + dz)) t = fma(-m(s, i), us[c + (dx * HY + dy) * HZ + dz], t);
+        const V un = us[c + (dx * HY + dy) * HZ + dz];
+        t = in_grid(gf, fx + dx, fy + dy, fz + dz) ? fma(-a[s], un, t) : t;
       }
       h[i] = t;
     } else {
@@ -391,7 +399,8 @@ struct PPOp {
 #pragma unroll
       for (int s = 0; s < PAT; ++s) {
         const int dx = pat_off(PAT, s, 0), dy = pat_off(PAT, s, 1), dz = pat_off(PAT, s, 2);
-        if (in_grid(gf, fx + dx, fy + dy, fz + dz)) acc = fma(m(s, i), us[c + (dx * HY + dy) * HZ + dz], acc);
+        const V un = us[c + (dx * HY + dy) * HZ + dz];
+        acc = in_grid(gf, fx + dx, fy + dy, fz + dz) ? fma(a[s], un, acc) : acc;
       }
       h[i] = f[i] - acc;
       uo[i] = us[c];
