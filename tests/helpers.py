@@ -107,6 +107,37 @@ def csr_gs(M, b, u, direction, zero_guess):
     return u
 
 
+def block_gs(M, Dinv, b, u, direction, zero_guess):
+    """Sequential point-block GS on an explicit (3N x 3N) matrix: nodes in
+    ascending (direction=+1) or descending order.  Node update: t = b_i (three
+    rows); then the nodes holding values from before the sweep, then the nodes
+    already updated in this sweep, each group in ascending node order, and per
+    neighbour node j: for row r, for column c, t_r = fma(-M[3i+r, 3j+c],
+    u[3j+c], t_r).  Then u_i = Dinv_i t row by row: Dinv_r0 * t_0, then
+    fma(Dinv_r1, t_1, .), fma(Dinv_r2, t_2, .).  Dinv has shape (N, 3, 3)."""
+    n = len(b) // 3
+    u = np.array(u, dtype=np.float64).copy()
+    fma = np.fma if hasattr(np, "fma") else _fma
+    nodes = range(n) if direction > 0 else range(n - 1, -1, -1)
+    for i in nodes:
+        t = [float(b[3 * i + r]) for r in range(3)]
+        nz = np.nonzero(np.abs(M[3 * i:3 * i + 3]).sum(axis=0))[0]
+        nbrs = sorted({int(c) // 3 for c in nz} - {i})
+        old = [j for j in nbrs if (j > i if direction > 0 else j < i)]
+        new = [j for j in nbrs if (j < i if direction > 0 else j > i)]
+        for grp in ([new] if zero_guess else [old, new]):
+            for j in grp:
+                for r in range(3):
+                    for c in range(3):
+                        t[r] = float(fma(-M[3 * i + r, 3 * j + c], u[3 * j + c], t[r]))
+        for r in range(3):
+            acc = Dinv[i, r, 0] * t[0]
+            acc = float(fma(Dinv[i, r, 1], t[1], acc))
+            acc = float(fma(Dinv[i, r, 2], t[2], acc))
+            u[3 * i + r] = acc
+    return u
+
+
 def _fma(a, b, c):
     """Correctly rounded a*b+c via exact rational arithmetic."""
     from fractions import Fraction

@@ -761,6 +761,70 @@ def test_block_gs_exact_without_coupling():
     assert np.allclose(oracle.bspmv(off, A, u).ravel(), M @ u.ravel(), rtol=0, atol=1e-14)
 
 
+def _coupled_block_system(shape, seed):
+    """27-point 3x3-block operator with every off-centre block nonzero and
+    non-symmetric (neither A_ij = A_ji^T nor symmetric blocks), plus the
+    inverses of its diagonal blocks computed by numpy."""
+    off = workloads.offsets(27)
+    A = workloads.random_sgdia(shape, 27, seed=seed, block=3, symmetric=False)
+    N = int(np.prod(shape))
+    A = A.reshape(27 * 9, N)
+    g = workloads.rng(seed + 100)
+    # perturb the diagonal blocks so that they are not symmetric either
+    A[13 * 9:14 * 9] *= g.uniform(0.9, 1.1, size=(9, N))
+    D = np.linalg.inv(A[13 * 9:14 * 9].T.reshape(N, 3, 3))
+    Dl = np.ascontiguousarray(D.reshape(N, 9).T)  # oracle layout Dinv[(r*3+c)*N + i]
+    return off, A, D, Dl
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 5), (2, 3, 7), (4, 2, 3)])
+def test_block_spmv_full_coupling_matches_dense(shape):
+    """Block SpMV with all 27 blocks nonzero against the explicit matrix
+    assembled entry by entry: a wrong neighbour index, block transpose or
+    skipped block fails."""
+    off, A, _, _ = _coupled_block_system(shape, 11)
+    M = helpers.dense_from_sgdia(A, off, shape, bs=3)
+    assert np.abs(M - M.T).max() > 0.1
+    x = workloads.rng(12).uniform(-1, 1, size=tuple(shape) + (3,))
+    y = oracle.bspmv(off, A, x).ravel()
+    ref = M @ x.ravel()
+    assert np.abs(y - ref).max() <= 1e-14 * np.abs(M).sum(axis=1).max()
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 5), (2, 3, 7), (4, 2, 3)])
+@pytest.mark.parametrize("direction,zero_guess", [(1, 1), (1, 0), (-1, 0)])
+def test_block_gs_full_coupling_bitexact_vs_dense(shape, direction, zero_guess):
+    """Point-block GS with all 27 blocks nonzero and non-symmetric against a
+    sequential block GS on the explicit matrix (old-value blocks, then
+    new-value blocks, then the diagonal-block inverse row by row), bit for
+    bit; and against the matrix form of one sweep, u = (D+L)^-1 (b - U u0)
+    forward and (D+U)^-1 (b - L u0) backward."""
+    off, A, D, Dl = _coupled_block_system(shape, 21)
+    M = helpers.dense_from_sgdia(A, off, shape, bs=3)
+    g = workloads.rng(22)
+    b = g.uniform(-1, 1, size=tuple(shape) + (3,))
+    u0 = np.zeros_like(b) if zero_guess else g.uniform(-1, 1, size=b.shape)
+    u = oracle.bgs_sweep(off, A, Dl, b, u0, direction, zero_guess).ravel()
+    ref = helpers.block_gs(M, D, b.ravel(), u0.ravel(), direction, zero_guess)
+    assert np.array_equal(u, ref)
+    # matrix form (node blocks: lower = j < i, upper = j > i)
+    n3 = M.shape[0]
+    node = np.arange(n3) // 3
+    low = node[:, None] > node[None, :]
+    upp = node[:, None] < node[None, :]
+    if direction > 0:
+        K, rhs = np.where(~upp, M, 0.0), b.ravel() - np.where(upp, M, 0.0) @ u0.ravel()
+    else:
+        K, rhs = np.where(~low, M, 0.0), b.ravel() - np.where(low, M, 0.0) @ u0.ravel()
+    assert np.allclose(u, np.linalg.solve(K, rhs), rtol=0, atol=1e-12)
+
+
+def test_block_dinv_matches_numpy_inverse():
+    off, A, D, Dl = _coupled_block_system((3, 3, 4), 31)
+    got = oracle.block_dinv(off, A, (3, 3, 4))
+    assert np.allclose(got.reshape(9, -1), Dl.reshape(9, -1), rtol=1e-13, atol=1e-15)
+
+
 def test_vcycle_single_level_is_exact_and_pcg_one_iteration():
     """A grid too small to coarsen gives a one-level hierarchy: M = A^-1, so
     PCG converges in one iteration."""
