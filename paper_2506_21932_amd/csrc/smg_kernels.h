@@ -7,9 +7,9 @@
 namespace smg {
 
 // ---- wavefront triangular sweep --------------------------------------
-// Persistent grid of at most WF_MAX_GRID workgroups (256 CUs, up to three
-// resident sweep workgroups each).
-constexpr int WF_MAX_GRID = 768;
+// Persistent grid of at most WF_MAX_GRID workgroups (one resident sweep
+// workgroup per CU: its LDS ring and chunk buffers take most of the CU's LDS).
+constexpr int WF_MAX_GRID = 256;
 
 template <class E>
 struct WfVal {

@@ -11,67 +11,78 @@
 // GPU design (replaces the CPU design of the paper, which projects the grid
 // onto x-y columns, runs level-scheduled column tasks and synchronises
 // threads point-to-point through a shared counter array):
-//  * The z-column is the unit.  A workgroup owns a TX x TY tile of columns,
-//    one column per lane: tile (X, Y) holds x in [X*TX, X*TX+TX) and
-//    y + sh*(x - X*TX) in [Y*TY, Y*TY+TY) (sheared so that no dependence
-//    points from a tile to a later one).
-//  * Lane (lx, ly) handles point z at step s = z + skew(lx, ly), with
-//    skew = (wx - sh*wy)*lx + wy*ly + KB and the hyperplane weights
+//  * The z-column is the unit.  A workgroup owns a TX x TY tile of columns:
+//    tile (X, Y) holds x in [X*TX, X*TX+TX) and y + sh*(x - X*TX) in
+//    [Y*TY, Y*TY+TY) (sheared so that no dependence points from a tile to a
+//    later one).
+//  * Column (lx, ly) of the tile handles point z at step s = z + skew(lx, ly),
+//    skew = (wx - sh*wy)*lx + wy*ly + KB with the hyperplane weights
 //    (wx, wy, 1) of the pattern; a neighbour at offset (dx, dy, dz) is then
-//    handled exactly wx*dx + wy*dy + dz steps away, the same for every lane,
-//    which is earlier for every lower neighbour.  A backward sweep runs the
-//    same tiles and steps in reverse order, which orders upper neighbours
-//    first.  KB pads both ends of the step range so that values of
-//    neighbouring tiles referenced at the first and last steps have a step.
-//  * The coefficients and the diagonal scaling are read from a copy stored
-//    in this schedule order, one copy per direction, packed 16 bytes per lane
-//    ([tile][step][pack][lane]): each step loads them with a few wide,
-//    fully coalesced loads.
-//  * Values are exchanged through an LDS ring of 16 steps holding the tile's
-//    columns plus a halo of neighbouring tiles' columns, with one workgroup
-//    barrier per step.  Because step distances do not depend on the lane,
-//    every neighbour read is one LDS load at a compile-time row.
-//  * Halo values are fetched by a few loader lanes from the output vector,
-//    which holds a signalling-NaN sentinel at every position read by another
-//    tile until that tile writes it; a value is ready when it is no longer
-//    the sentinel.  These accesses are device-coherent (agent scope), so no
-//    fences or flag counters are needed.  The sentinels for the next sweep on
-//    the same level are written by this sweep into that sweep's output.
-//  * Halo values are prefetched PH = 4 steps ahead: enough to cover a
-//    device-coherent load (about a microsecond), while a tile must run only
-//    that far behind its producer for the prefetch to find them written.
-//    A loader lane that finds a value not yet written first waits for the
-//    value WF_AHEAD steps further along the same column and then refetches
-//    its other prefetched halo values: the tile then runs far enough behind
-//    its producer that later prefetches find their values written, instead
-//    of paying one coherent round trip per step.
-//  * The right-hand side is staged through LDS in chunks of 16 steps, loaded
-//    one chunk ahead as runs of 16 consecutive z per column (two runs per
-//    step in the first half of a chunk, each placed in LDS four steps after
-//    its load); each lane writes its result over the right-hand-side slot it
-//    has just used, and the chunk's results leave the same way, two runs per
-//    step in the first half of the following chunk (before their slots are
-//    refilled), together with the sentinels for the next sweep.  Per-step accesses to the natural-order vectors would touch one
-//    element of a different cache line per lane and keep hundreds of lines
-//    per tile alive in the L2 cache; spreading the runs over the steps keeps
-//    them from holding up the in-order completion of the coefficient loads.
-//    Only columns read by other tiles are also stored at once,
-//    device-coherently.
+//    handled exactly wx*dx + wy*dy + dz steps away, the same for every
+//    column, which is earlier for every lower neighbour.  A backward sweep
+//    runs the same tiles and steps in reverse order.  KB pads both ends of
+//    the step range so that values referenced at the first and last steps
+//    have a step.
+//  * A step costs the time a wave needs to issue its instructions (one per
+//    four cycles at best) plus one exchange of values through LDS, so the
+//    workgroup splits the work by role, each role in waves of its own, and
+//    all waves meet at one workgroup barrier per step:
+//      - four compute waves, one column per lane: per step they read the
+//        right-hand side and the neighbours' values from LDS, run the chain
+//        of fmas, write the result to LDS, and prefetch the step's packed
+//        coefficients (a schedule-ordered copy, 16-byte coalesced loads,
+//        P steps ahead) -- about twenty instructions, no global stores and
+//        no waits on memory other than their own coefficient loads;
+//      - a halo wave: fetches the values of neighbouring tiles' columns
+//        (device-coherent loads PH steps ahead, checked against the
+//        sentinel) into the LDS ring;
+//      - a load wave: streams the right-hand side into LDS as runs of 16
+//        consecutive z per column, two chunks of 16 steps ahead;
+//      - a store wave: stores the tile's own columns that other tiles read
+//        (device-coherent, one step after they are computed), and streams
+//        the results out of LDS as runs one chunk behind, together with the
+//        sentinels for the next sweep on the level.
+//    Loads and stores never share a wave: a wave's vector memory operations
+//    retire in issue order, so a wave that waits for a load would also wait
+//    for every store issued before it, whose acknowledgement is slow.
+//    Values that cross waves move through an LDS ring of 16 steps (the tile's
+//    columns plus a halo of neighbouring tiles' columns) and three chunk
+//    buffers (one filled, one computed, one drained).
+//  * Inactive positions (a column outside the grid, or z outside [0, nz) at
+//    that step) have zero coefficients, scaling and right-hand side, so
+//    their result is zero without a test: the LDS is zeroed once per launch
+//    and every value in it stays finite.
+//  * Every position read by another tile holds a signalling-NaN sentinel
+//    until it is written; a value is ready when it is no longer the
+//    sentinel.  The sentinels for the next sweep on the same level are
+//    written by this sweep into that sweep's output.
+//  * A halo wave that finds a value not yet written first waits for the value
+//    WF_AHEAD steps further along the same column and then refetches its
+//    other prefetched halo values: the tile then runs far enough behind its
+//    producer that later prefetches find their values written, instead of
+//    paying one coherent round trip per step.
 //  * Tiles are handed out by an atomic ticket in dependence order, so a
 //    persistent grid of any size always makes progress.  Waits are bounded
 //    by a watchdog that raises an error flag instead of hanging.
-//  * All per-point accesses use buffer instructions; lanes without a point
-//    at a step use an offset outside the buffer, for which loads return zero
-//    and stores are dropped.  Tile inputs are prefetched P steps ahead.
+//  * All per-point accesses use buffer instructions; positions without a
+//    point use an offset outside the buffer, for which loads return zero
+//    and stores are dropped.
 #include "smg_common.h"
 #include "smg_kernels.h"
 
 namespace smg {
 
-constexpr int WF_HIST = 16;                // LDS ring rows (steps)
-constexpr int WF_CH = 16;                  // steps per chunk of right-hand side / results
-constexpr int WF_NL = WF_TX * WF_TY;       // lanes (columns) per tile
-constexpr int WF_NH = 104;                 // halo slots around a tile
+constexpr int WF_HIST = 16;                  // LDS ring rows (steps)
+constexpr int WF_CH = 16;                    // steps per chunk of right-hand side / results
+constexpr int WF_NL = WF_TX * WF_TY;         // compute lanes (columns) per tile
+constexpr int WF_NH = 104;                   // halo slots around a tile
+constexpr int WF_NB = 3;                     // chunk buffers: filled, computed, drained
+constexpr int WF_NW = 7;                     // waves: 4 compute, halo, load, store
+constexpr int WF_THREADS = 64 * WF_NW;
+constexpr int WF_GRP = WF_NL * WF_CH / 64;   // column-run groups per chunk (4 columns x 16 steps)
+constexpr int WF_GPS = WF_GRP / WF_CH;       // groups moved per step
+constexpr int WF_RW = WF_NL + WF_NH + 1;     // ring row length (padded)
+constexpr int WF_HRW = WF_NL + 1;            // chunk buffer row length (padded)
 constexpr unsigned WF_SPIN_LIMIT = 1u << 21;
 #ifndef WF_LAG_EXTRA
 #define WF_LAG_EXTRA 2
@@ -79,8 +90,8 @@ constexpr unsigned WF_SPIN_LIMIT = 1u << 21;
 #ifndef WF_PH
 #define WF_PH 4
 #endif
-constexpr unsigned WF_OOB = 0x80000000u;   // buffer offset outside every range
-constexpr int WF_SC1 = 16;                 // cache policy of device-coherent accesses
+constexpr unsigned WF_OOB = 0x80000000u;     // buffer offset outside every range
+constexpr int WF_SC1 = 16;                   // cache policy of device-coherent accesses
 
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
@@ -116,7 +127,11 @@ __host__ __device__ constexpr int wf_npk(int pat, int ebytes) {
 }
 
 void wf_tiling(const Grid& g, int pat, WfTiling* t) {
-  t->sh = g.ny <= WF_TY ? 0 : 1;
+  // Tiles are sheared (y + x offset) when a lower neighbour column lies at
+  // (x-1, y+1) (19- and 27-point patterns); otherwise, and when a single
+  // tile row covers y, plain rectangles keep every dependence pointing to
+  // an earlier tile with fewer tile hand-offs on the critical path.
+  t->sh = (pat == 7 || g.ny <= WF_TY) ? 0 : 1;
   t->ntx = (g.nx + WF_TX - 1) / WF_TX;
   t->nty = (g.ny + t->sh * (WF_TX - 1) + WF_TY - 1) / WF_TY;
   const int kb = wf_kb(pat);
@@ -164,18 +179,6 @@ __device__ inline bool wf_halo_used(int pat, int dir, int sh, int qx, int qy) {
     const int cx = dir * col_dx(c), cy = dir * col_dy(c);
     const int lx = qx - cx, ly = qy - cy - sh * cx;
     if (lx >= 0 && lx < WF_TX && ly >= 0 && ly < WF_TY) return true;
-  }
-  return false;
-}
-
-// Is lane (lx, ly)'s column read by a lane of another tile in a sweep of
-// direction dir?
-__device__ inline bool wf_exported(int pat, int dir, int lx, int ly, int sh) {
-  for (int c = 0; c < 4; ++c) {
-    if (!col_used(pat, c)) continue;
-    const int cx = dir * col_dx(c), cy = dir * col_dy(c);
-    const int qx = lx - cx, qy = ly - cy - sh * cx;
-    if (qx < 0 || qx >= WF_TX || qy < 0 || qy >= WF_TY) return true;
   }
   return false;
 }
@@ -243,279 +246,507 @@ struct WfE<__half> {
   }
 };
 
-// One tile of a sweep (tile numbers in forward dependence order).  err
-// receives the watchdog flag.
-template <int PAT, int DIR, int P, class E, bool UNITD, bool ADD>
-__device__ __forceinline__ void wf_tile(const WfArgs<typename WfVal<E>::V>& a, unsigned tile, unsigned* err) {
+// Columns of a tile that no lane of another tile reads in a sweep of
+// direction dir: the lanes whose consumers (lane - neighbour-column offset,
+// sheared) all lie inside the tile, an intersection of shifted copies of the
+// tile, hence a rectangle [xl, xh) x [yl, yh).
+struct WfRect {
+  int xl, xh, yl, yh;
+};
+__host__ __device__ constexpr WfRect wf_inner(int pat, int dir, int sh) {
+  WfRect r{0, WF_TX, 0, WF_TY};
+  for (int c = 0; c < 4; ++c) {
+    if (!col_used(pat, c)) continue;
+    const int cx = dir * col_dx(c), cy = dir * col_dy(c) + sh * dir * col_dx(c);
+    r.xl = r.xl > cx ? r.xl : cx;
+    r.xh = r.xh < WF_TX + cx ? r.xh : WF_TX + cx;
+    r.yl = r.yl > cy ? r.yl : cy;
+    r.yh = r.yh < WF_TY + cy ? r.yh : WF_TY + cy;
+  }
+  return r;
+}
+__host__ __device__ constexpr int wf_exported_count(const WfRect& r) {
+  return WF_NL - (r.xh - r.xl) * (r.yh - r.yl);
+}
+// Lane (lx*TY + ly) of the e-th column outside the rectangle, in lane order.
+__device__ inline int wf_exported_lane(const WfRect& r, int e) {
+  const int nm = WF_TY - (r.yh - r.yl);  // outside columns per row inside [xl, xh)
+  int lx, ly;
+  if (e < WF_TY * r.xl) {
+    lx = e / WF_TY;
+    ly = e % WF_TY;
+  } else if (e < WF_TY * r.xl + nm * (r.xh - r.xl)) {
+    const int q = e - WF_TY * r.xl;
+    lx = r.xl + q / nm;
+    const int w = q % nm;
+    ly = w < r.yl ? w : r.yh + (w - r.yl);
+  } else {
+    const int q = e - WF_TY * r.xl - nm * (r.xh - r.xl);
+    lx = r.xh + q / WF_TY;
+    ly = q % WF_TY;
+  }
+  return lx * WF_TY + ly;
+}
+
+// Geometry of one tile shared by all roles.
+struct WfGeo {
+  int X, Y, sh, NS, nsteps;
+  int p0;             // first x plane of the vector buffers
+  unsigned vbytes;    // bytes of the vector buffers (planes p0 .. p1-1)
+  long vb;            // element offset of plane p0
+};
+
+template <class V>
+__device__ inline WfGeo wf_geo(const WfArgs<V>& a, unsigned tile) {
+  WfGeo q;
+  q.X = (int)(tile / (unsigned)a.t.nty);
+  q.Y = (int)(tile % (unsigned)a.t.nty);
+  q.sh = a.t.sh;
+  q.NS = a.t.ns;
+  q.nsteps = (q.NS + WF_CH - 1) / WF_CH * WF_CH;
+  q.p0 = q.X * WF_TX > 0 ? q.X * WF_TX - 1 : 0;
+  const int p1 = q.X * WF_TX + WF_TX + 1 < a.g.nx ? q.X * WF_TX + WF_TX + 1 : a.g.nx;
+  const long pl = (long)a.g.ny * a.g.nz;
+  q.vbytes = (unsigned)((p1 - q.p0) * pl * (long)sizeof(V));
+  q.vb = q.p0 * pl;
+  return q;
+}
+
+template <int DIR>
+__device__ inline int wf_step(int NS, int k) {
+  return DIR > 0 ? k : NS - 1 - k;
+}
+
+// ---- compute role (waves 0-3) ----------------------------------------------
+template <int PAT, int DIR, int P, class E, bool UNITD>
+__device__ __forceinline__ void wf_compute(const WfArgs<typename WfVal<E>::V>& a, const WfGeo& q, unsigned tile,
+                                           typename WfVal<E>::V* ring, typename WfVal<E>::V* hbuf) {
   using T = WfE<E>;
   using V = typename T::V;
-  using B = VBits<V>;
   constexpr int C = PAT / 2;
   constexpr int NT = PAT / 2;
   constexpr int WX = hp_wx(PAT), WY = hp_wy(PAT);
-  constexpr int KB = wf_kb(PAT);
   constexpr int NPK = wf_npk(PAT, sizeof(E));
-  constexpr int RW = WF_NL + WF_NH + 1;  // ring row length (padded: column runs hit distinct banks)
-  constexpr int HRW = WF_NL + 1;         // right-hand-side chunk row length (padded likewise)
   constexpr unsigned PACKB = WF_NL * 16u;
-  constexpr int PH = WF_PH;                    // prefetch distance of halo values
-  constexpr int WF_AHEAD = PH + WF_LAG_EXTRA;  // steps a stalled tile falls back behind its producer
-  static_assert(WF_HIST % P == 0 && WF_HIST % PH == 0 && PH >= 2 && WF_HIST > KB + 1, "ring too short");
-  __shared__ V ring[WF_HIST * RW];
-  __shared__ V hbuf[2 * WF_CH * HRW];  // right-hand side then results, two chunks of 16 steps
-
+  static_assert(WF_HIST % P == 0 && WF_HIST > wf_kb(PAT) + 1, "ring too short");
   const int tid = threadIdx.x;
   const int lx = tid / WF_TY, ly = tid % WF_TY;
-  const int sh = a.t.sh;
-  const int skew = (WX - sh * WY) * lx + WY * ly + KB;
-  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-  const int NS = a.t.ns;
-  const bool exported = wf_exported(PAT, DIR, lx, ly, sh);
+  const int NS = q.NS;
 
-  // LDS index of each neighbour column (its offsets mirrored for a backward
-  // sweep): a lane of this tile or a halo slot
+  // LDS index of each neighbour column within a ring row (offsets mirrored
+  // for a backward sweep): a lane of this tile or a halo slot
   int nidx[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int cx = DIR * col_dx(c), cy = DIR * col_dy(c);
-    const int qx = lx + cx, qy = ly + cy + sh * cx;
+    const int qx = lx + cx, qy = ly + cy + q.sh * cx;
     const bool in = qx >= 0 && qx < WF_TX && qy >= 0 && qy < WF_TY;
     nidx[c] = !col_used(PAT, c) ? 0 : (in ? qx * WF_TY + qy : WF_NL + wf_halo_slot(qx, qy));
   }
-  // halo loader role: slot hs, spread over the four waves
-  const int hs = (tid % 64) * 4 + tid / 64;
-  int hqx = 0, hqy = 0;
-  bool hrole = false;
-  if (hs < WF_NH) {
-    wf_halo_pos(hs, &hqx, &hqy);
-    hrole = wf_halo_used(PAT, DIR, sh, hqx, hqy);
-  }
-  const int hskew = (WX - sh * WY) * hqx + WY * hqy + KB;
-  // column runs: in chunk transfers this thread moves step (tid % 16) of the
-  // columns of lanes (lx = i, ly = tid / 16), i = 0..15
-  const int cy = tid / WF_CH;
-  const int cr = tid % WF_CH;
-  unsigned cexp = 0, cnext = 0;  // bit i: that column is read by other tiles in this / the next sweep
+  const unsigned tbytes = (unsigned)NS * NPK * PACKB;
+  const auto rp = wf_rsrc((const char*)a.pk + (size_t)tile * tbytes, tbytes);
+  const unsigned sdbytes = T::HALF ? (unsigned)NS * WF_NL * 8u : 0u;
+  const auto rs = wf_rsrc(T::HALF ? (const char*)a.sd + (size_t)tile * sdbytes : (const char*)a.pk, sdbytes);
+
+  u32x4 cf[P][NPK];
+  u32x2 sdv[P];
+  auto prefetch = [&](int k, int j) {
+    const int s = wf_step<DIR>(NS, k);
+    const bool sin = s >= 0 && s < NS;
+    const unsigned so = sin ? (unsigned)s * (NPK * PACKB) : WF_OOB;
 #pragma unroll
-  for (int i = 0; i < WF_TX; ++i) {
-    cexp |= wf_exported(PAT, DIR, i, cy, sh) ? 1u << i : 0u;
-    cnext |= (a.next != nullptr && wf_exported(PAT, a.next_dir, i, cy, sh)) ? 1u << i : 0u;
-  }
-
-  {
-    const int X = (int)(tile / (unsigned)a.t.nty), Y = (int)(tile % (unsigned)a.t.nty);
-    const int xt = X * WF_TX + lx;
-    const int yt = Y * WF_TY + ly - sh * lx;
-    const bool colv = xt < nx && yt >= 0 && yt < ny;
-
-    // buffers over the planes x in [X*TX - 1, X*TX + TX + 1) of the vectors
-    const int p0 = X * WF_TX > 0 ? X * WF_TX - 1 : 0;
-    const int p1 = X * WF_TX + WF_TX + 1 < nx ? X * WF_TX + WF_TX + 1 : nx;
-    const long pl = (long)ny * nz;
-    const unsigned vbytes = (unsigned)((p1 - p0) * pl * (long)sizeof(V));
-    const long vb = p0 * pl;
-    const auto rh = wf_rsrc(a.h + vb, vbytes);
-    const auto rx = wf_rsrc(a.x + vb, vbytes);
-    const auto rn = wf_rsrc((a.next != nullptr ? a.next : a.x) + vb, a.next != nullptr ? vbytes : 0u);
-    const auto rav = wf_rsrc((ADD ? a.addv : a.h) + vb, ADD ? vbytes : 0u);
-    const auto rao = wf_rsrc((ADD ? a.addout : a.x) + vb, ADD ? vbytes : 0u);
-    const unsigned vo = colv ? (unsigned)(((xt - p0) * (long)ny + yt) * nz) : 0u;
-    const int gx = X * WF_TX + hqx, gy = Y * WF_TY + hqy - sh * hqx;
-    const bool hcolv = hrole && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-    const unsigned hvo = hcolv ? (unsigned)(((gx - p0) * (long)ny + gy) * nz) : 0u;
-    const unsigned tbytes = (unsigned)NS * NPK * PACKB;
-    const auto rp = wf_rsrc((const char*)a.pk + (size_t)tile * tbytes, tbytes);
-    const unsigned sdbytes = T::HALF ? (unsigned)NS * WF_NL * 8u : 0u;
-    const auto rs = wf_rsrc(T::HALF ? (const char*)a.sd + (size_t)tile * sdbytes : (const char*)a.pk, sdbytes);
-
-    const int nsteps = (NS + WF_HIST - 1) / WF_HIST * WF_HIST;
-    u32x4 cf[P][NPK];
-    u32x2 sdv[P];
-    V hb[PH], hc[WF_TX / 2];
-    V own_prev = V(0);
-
-    auto step_of = [&](int k) { return DIR > 0 ? k : NS - 1 - k; };
-    auto prefetch = [&](int k, int j) {
-      const int s = step_of(k);
-      const bool sin = s >= 0 && s < NS;
-      const unsigned so = sin ? (unsigned)s * (NPK * PACKB) : WF_OOB;
+    for (int p = 0; p < NPK; ++p)
+      cf[j][p] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rp, tid * 16u, so + p * PACKB, 0));
+    if (T::HALF)
+      sdv[j] = __builtin_amdgcn_raw_buffer_load_b64(rs, tid * 8u, sin ? (unsigned)s * (WF_NL * 8u) : WF_OOB, 0);
+  };
 #pragma unroll
-      for (int p = 0; p < NPK; ++p)
-        cf[j][p] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rp, tid * 16u, so + p * PACKB, 0));
-      if (T::HALF)
-        sdv[j] = __builtin_amdgcn_raw_buffer_load_b64(rs, tid * 8u, sin ? (unsigned)s * (WF_NL * 8u) : WF_OOB, 0);
-    };
-    // byte offset of step s of the column of lane (i, cy), or WF_OOB.  The
-    // column's element offset and skew are linear in i; which columns lie in
-    // the grid is fixed per tile (bit i of rmask).
-    const unsigned rb0 = (unsigned)(((X * WF_TX - p0) * (long)ny + (Y * WF_TY + cy)) * nz);
-    const unsigned rdi = (unsigned)((long)ny * nz - (long)sh * nz);
-    const int rsk0 = WY * cy + KB;
-    unsigned rmask = 0;
+  for (int j = 0; j < P; ++j) prefetch(j, j);
+  V own_prev = V(0);
+  __syncthreads();  // prologue: the first chunk is in LDS
+
+  for (int k0 = 0; k0 < q.nsteps; k0 += WF_HIST) {
+    V* hb = hbuf + ((k0 / WF_CH) % WF_NB) * (WF_CH * WF_HRW) + tid;
 #pragma unroll
-    for (int i = 0; i < WF_TX; ++i) {
-      const int xx = X * WF_TX + i, yy = Y * WF_TY + cy - sh * i;
-      rmask |= (xx < nx && yy >= 0 && yy < ny) ? 1u << i : 0u;
+    for (int j = 0; j < WF_HIST; ++j) {
+      const int jp = j % P;
+      const V sc = T::HALF ? __uint_as_float(sdv[jp].x) : V(1);
+      V t = hb[j * WF_HRW];
+      // all neighbour values first (one wait), then the chain of fmas in
+      // canonical order of the triangle's offsets
+      V val[NT];
+#pragma unroll
+      for (int m = 0; m < NT; ++m) {
+        const int so = DIR > 0 ? m : C + 1 + m;
+        const int dx = pat_off(PAT, so, 0), dy = pat_off(PAT, so, 1), dz = pat_off(PAT, so, 2);
+        if (dx == 0 && dy == 0) {
+          val[m] = own_prev;
+        } else {
+          const int c = col_of(DIR * dx, DIR * dy);
+          const int back = DIR * (WX * dx + WY * dy + dz);  // in [-KB, -1]
+          val[m] = ring[((j + back + WF_HIST) % WF_HIST) * WF_RW + nidx[c]];
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < NT; ++m) {
+        const V cm = T::HALF ? sc * T::get(cf[jp], m) : T::get(cf[jp], m);
+        t = fma(-cm, val[m], t);
+      }
+      const V dv = T::HALF ? __uint_as_float(sdv[jp].y) : T::get(cf[jp], NT);
+      const V xv = UNITD ? t : t * dv;
+      own_prev = xv;
+      ring[j * WF_RW + tid] = xv;
+      hb[j * WF_HRW] = xv;
+      prefetch(k0 + j + P, jp);
+      __syncthreads();
     }
-    auto run_off = [&](int i, int s) {
-      const int z = s - rsk0 - (WX - sh * WY) * i;
-      // branch-free: both tests as bits
-      const unsigned ok = ((rmask >> i) & 1u) & (unsigned)((unsigned)z < (unsigned)nz);
-      return ok ? (rb0 + (unsigned)i * rdi + (unsigned)z) * (unsigned)sizeof(V) : WF_OOB;
-    };
-    // right-hand side of chunk c: column runs i loaded into hc[i], then
-    // placed in LDS
-    auto hrun_load = [&](int c, int i) { hc[i % (WF_TX / 2)] = bld<V, 0>(rh, run_off(i, step_of(c * WF_CH + cr))); };
-    auto hrun_put = [&](int c, int i) { hbuf[((c & 1) * WF_CH + cr) * HRW + i * WF_TY + cy] = hc[i % (WF_TX / 2)]; };
-    // results of chunk c (in its hbuf half): column run i out, with the
-    // sentinels of the next sweep
-    auto xrun_out = [&](int c, int i) {
-      const unsigned off = run_off(i, step_of(c * WF_CH + cr));
-      const V xo = hbuf[((c & 1) * WF_CH + cr) * HRW + i * WF_TY + cy];
-      bst<0>(xo, rx, (cexp >> i) & 1u ? WF_OOB : off);
-      bst<0>(B::val(B::sent), rn, (cnext >> i) & 1u ? off : WF_OOB);
-    };
-    // ADD: addout = addv + x for all runs of chunk c
-    auto add_out = [&](int c) {
-      V av[WF_TX];
-      unsigned off[WF_TX];
-#pragma unroll
-      for (int i = 0; i < WF_TX; ++i) {
-        off[i] = run_off(i, step_of(c * WF_CH + cr));
-        av[i] = bld<V, 0>(rav, off[i]);
-      }
-#pragma unroll
-      for (int i = 0; i < WF_TX; ++i) bst<0>(av[i] + hbuf[((c & 1) * WF_CH + cr) * HRW + i * WF_TY + cy], rao, off[i]);
-    };
-    auto halo_fetch = [&](int k, int j) {
-      const int s = step_of(k);
-      const int hz = s - hskew;
-      const bool hok = s >= 0 && s < NS && hcolv && hz >= 0 && hz < nz;
-      hb[j] = bld<V, WF_SC1>(rx, hok ? (hvo + (unsigned)hz) * (unsigned)sizeof(V) : WF_OOB);
-    };
-    // Bounded wait until the halo value at byte offset off is no longer the
-    // sentinel (v: its last loaded value).
-    auto wait_value = [&](unsigned off, V v) {
-      unsigned spins = 0;
-      while (B::bits(v) == B::sent && spins < WF_SPIN_LIMIT) {
-        __builtin_amdgcn_s_sleep(1);
-        v = bld<V, WF_SC1>(rx, off);
-        ++spins;
-        // once any wait has timed out, stop waiting anywhere
-        if ((spins & 1023u) == 1023u && (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u))
-          spins = WF_SPIN_LIMIT;
-      }
-      if (spins >= WF_SPIN_LIMIT) atomicOr(err, 1u);
-      return v;
-    };
-    // halo value of iteration k (held in slot j): wait for it if it is still
-    // the sentinel, then publish it in the ring
-    auto halo_put = [&](int k, int j) {
-      const int s = step_of(k);
-      const int hz = s - hskew;
-      const bool hok = s >= 0 && s < NS && hcolv && hz >= 0 && hz < nz;
-      V v = hb[j];
-      if (hok && B::bits(v) == B::sent) {
-        // fall back behind the producer: wait for the value WF_AHEAD steps on
-        // (clamped to the column), then for this one
-        int zf = hz + DIR * WF_AHEAD;
-        zf = zf < 0 ? 0 : (zf >= nz ? nz - 1 : zf);
-        const unsigned offf = (hvo + (unsigned)zf) * (unsigned)sizeof(V);
-        wait_value(offf, bld<V, WF_SC1>(rx, offf));
-        v = wait_value((hvo + (unsigned)hz) * (unsigned)sizeof(V), v);
-        // the other prefetched halo values were fetched too early: fetch again
-#pragma unroll
-        for (int d = 1; d < PH - 1; ++d) halo_fetch(k + d, (j + d) % PH);
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the refetched values are in
-      }
-      if (hrole) ring[(k % WF_HIST) * RW + WF_NL + hs] = hok ? v : V(0);
-    };
+  }
+  __syncthreads();  // tail: the last chunk is drained and the last step exported
+  __syncthreads();
+}
 
+// ---- halo role (wave 4) ------------------------------------------------------
+template <int PAT, int DIR, class V>
+__device__ __forceinline__ void wf_halo(const WfArgs<V>& a, const WfGeo& q, V* ring, unsigned* err) {
+  using B = VBits<V>;
+  constexpr int WX = hp_wx(PAT), WY = hp_wy(PAT);
+  constexpr int KB = wf_kb(PAT);
+  constexpr int PH = WF_PH;
+  constexpr int WF_AHEAD = PH + WF_LAG_EXTRA;  // steps a stalled tile falls back behind its producer
+  static_assert(WF_HIST % PH == 0 && PH >= 2, "halo prefetch distance");
+  const int t = threadIdx.x - 4 * 64;
+  const int NS = q.NS, nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  const long vb = q.vb;
+  const auto rx = wf_rsrc(a.x + vb, q.vbytes);
+
+  // halo slots t and 64 + t
+  bool hrole[2];
+  int hs[2], hskew[2];
+  unsigned hvo[2];
+  bool hcolv[2];
 #pragma unroll
-    for (int j = 0; j < P; ++j) prefetch(j, j);
-#pragma unroll
-    for (int j = 0; j < PH; ++j) halo_fetch(j, j);
-#pragma unroll
-    for (int i = 0; i < WF_TX; ++i) {
-      hrun_load(0, i);
-      hrun_put(0, i);
+  for (int i = 0; i < 2; ++i) {
+    hs[i] = t + 64 * i;
+    int hqx = 0, hqy = 0;
+    hrole[i] = false;
+    if (hs[i] < WF_NH) {
+      wf_halo_pos(hs[i], &hqx, &hqy);
+      hrole[i] = wf_halo_used(PAT, DIR, q.sh, hqx, hqy);
     }
-    halo_put(0, 0);
-    __syncthreads();
+    hskew[i] = (WX - q.sh * WY) * hqx + WY * hqy + KB;
+    const int gx = q.X * WF_TX + hqx, gy = q.Y * WF_TY + hqy - q.sh * hqx;
+    hcolv[i] = hrole[i] && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    hvo[i] = hcolv[i] ? (unsigned)(((gx - q.p0) * (long)ny + gy) * nz) : 0u;
+  }
+  V hb[2][PH];
+  auto halo_off = [&](int i, int k) {
+    const int s = wf_step<DIR>(NS, k);
+    const int hz = s - hskew[i];
+    const bool ok = s >= 0 && s < NS && hcolv[i] && hz >= 0 && hz < nz;
+    return ok ? (hvo[i] + (unsigned)hz) * (unsigned)sizeof(V) : WF_OOB;
+  };
+  auto halo_fetch = [&](int k, int j) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) hb[i][j] = bld<V, WF_SC1>(rx, halo_off(i, k));
+  };
+  // Bounded wait until the value at byte offset off is no longer the
+  // sentinel (v: its last loaded value).
+  auto wait_value = [&](unsigned off, V v) {
+    unsigned spins = 0;
+    while (B::bits(v) == B::sent && spins < WF_SPIN_LIMIT) {
+      __builtin_amdgcn_s_sleep(1);
+      v = bld<V, WF_SC1>(rx, off);
+      ++spins;
+      // once any wait has timed out, stop waiting anywhere
+      if ((spins & 1023u) == 1023u && (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u))
+        spins = WF_SPIN_LIMIT;
+    }
+    if (spins >= WF_SPIN_LIMIT) atomicOr(err, 1u);
+    return v;
+  };
+  // halo values of step k (slot j): wait for any that is still the sentinel,
+  // then publish them in ring row k
+  auto halo_put = [&](int k, int j) {
+    bool miss = false;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) miss |= B::bits(hb[i][j]) == B::sent;
+    if (__builtin_amdgcn_ballot_w64(miss) != 0) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        if (B::bits(hb[i][j]) == B::sent) {
+          // fall back behind the producer: wait for the value WF_AHEAD steps
+          // on (clamped to the column), then for this one
+          const int s = wf_step<DIR>(NS, k);
+          const int hz = s - hskew[i];
+          int zf = hz + DIR * WF_AHEAD;
+          zf = zf < 0 ? 0 : (zf >= nz ? nz - 1 : zf);
+          const unsigned offf = (hvo[i] + (unsigned)zf) * (unsigned)sizeof(V);
+          wait_value(offf, bld<V, WF_SC1>(rx, offf));
+          hb[i][j] = wait_value(halo_off(i, k), hb[i][j]);
+        }
+      }
+      // the other prefetched halo values were fetched too early: fetch again
+#pragma unroll
+      for (int d = 1; d < PH; ++d) halo_fetch(k + d, (j + d) % PH);
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the refetched values are in
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      if (hrole[i]) ring[(k % WF_HIST) * WF_RW + WF_NL + hs[i]] = hb[i][j];
+  };
+#pragma unroll
+  for (int j = 0; j < PH; ++j) halo_fetch(j, j);
+  __syncthreads();  // prologue
 
-    for (int k0 = 0; k0 < nsteps; k0 += WF_HIST) {
+  for (int k0 = 0; k0 < q.nsteps; k0 += WF_HIST) {
 #pragma unroll
-      for (int j = 0; j < WF_HIST; ++j) {
-        const int k = k0 + j;
-        const int jp = j % P;
-        const int jj = j % WF_CH;
-        const int ch = k / WF_CH;
-        // the previous chunk's results, runs 2jj and 2jj+1 (a chunk before the
-        // first maps every run outside the buffers), out before their slots
-        // are refilled below
-        if (jj < WF_CH / 2) {
-          if (ADD && jj == 0) add_out(ch - 1);
-          xrun_out(ch - 1, 2 * jj);
-          xrun_out(ch - 1, 2 * jj + 1);
-        }
-        // the next chunk's right-hand side: runs 2(jj-4), 2(jj-4)+1 into LDS,
-        // then runs 2jj, 2jj+1 from HBM (their registers were just freed)
-        if (jj >= 4 && jj < WF_CH / 2 + 4) {
-          hrun_put(ch + 1, 2 * (jj - 4));
-          hrun_put(ch + 1, 2 * (jj - 4) + 1);
-        }
-        if (jj < WF_CH / 2) {
-          hrun_load(ch + 1, 2 * jj);
-          hrun_load(ch + 1, 2 * jj + 1);
-        }
-        const int s = step_of(k);
-        const int z = s - skew;
-        const bool act = colv && z >= 0 && z < nz;
-        // the row update, in canonical order of the triangle's offsets
-        const V sc = T::HALF ? __uint_as_float(sdv[jp].x) : V(1);
-        V& hslot = hbuf[((ch & 1) * WF_CH + jj) * HRW + tid];
-        V t = hslot;
-        // all neighbour values first (one wait), then the chain of fmas
-        V val[NT];
+    for (int j = 0; j < WF_HIST; ++j) {
+      const int k = k0 + j;
+      halo_put(k, j % PH);
+      halo_fetch(k + PH, j % PH);
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  __syncthreads();
+}
+
+// ---- column runs (load and store roles) --------------------------------------
+// Group r of a chunk moves columns 4r + cq (cq = lane / 16), steps m = lane %
+// 16 of the chunk: each column's 16 consecutive z values are one coalesced run.
+// Per chunk a lane forms its base offsets once, per step the step's bases; a
+// group then adds a uniform term.  The bases pass through wf_keep, which the
+// compiler may not move across the step's memory operations, so that it does
+// not compute every step's offsets ahead (they would hold dozens of
+// registers for the whole chunk or sweep).
+__device__ inline int wf_keep(int v) {
+  asm volatile("" : "+v"(v) : : "memory");
+  return v;
+}
+__device__ inline int wf_keep_s(int v) {
+  asm volatile("" : "+s"(v) : : "memory");
+  return v;
+}
+
+template <int PAT, int DIR, class V>
+struct WfRuns {
+  static constexpr int WX = hp_wx(PAT), WY = hp_wy(PAT), KB = wf_kb(PAT);
+  int cq, m;
+  int lds;        // LDS index of (step m, column cq) within a chunk buffer
+  int a0;         // element offset of column cq of group 0 minus its skew
+  int y0;         // y of column cq of group 0
+  int skq;        // skew of column cq of group 0
+  int gx, gy;     // element offset steps per group row (r / 4) and per group (r % 4)
+  int sx;         // skew step per group row
+  int nx;
+  __device__ void init(const WfArgs<V>& a, const WfGeo& q, int lane) {
+    nx = a.g.nx;
+    cq = lane / 16;
+    m = lane % 16;
+    lds = m * WF_HRW + cq;
+    const int ny = a.g.ny, nz = a.g.nz;
+    skq = WY * cq + KB;
+    y0 = q.Y * WF_TY + cq;
+    a0 = ((q.X * WF_TX - q.p0) * ny + y0) * nz - skq;
+    sx = WX - q.sh * WY;
+    gx = (ny - q.sh) * nz - sx;
+    gy = 4 * (nz - WY);
+  }
+  // Per-chunk bases of this lane's step s of the chunk.
+  struct Base {
+    int e;    // element offset of group 0
+    int z;    // z of group 0
+    int gx, gy, sx;
+  };
+  __device__ Base base(int s) const { return Base{wf_keep(a0 + s), wf_keep(s - skq), wf_keep_s(gx), wf_keep_s(gy),
+                                                  wf_keep_s(sx)}; }
+  // Per-step bases: the four groups 4j .. 4j+3 moved at step j of a chunk
+  // share the column row lx = j.
+  struct Step {
+    int e, z, y, lx;
+  };
+  __device__ Step step(const Base& b, const WfGeo& q, int j) const {
+    // a column row beyond the grid in x takes y = -1 - 16 (outside for every group)
+    const int y = q.X * WF_TX + j < nx ? y0 - q.sh * j : -WF_TY - 1;
+    return Step{wf_keep(b.e + j * b.gx), wf_keep(b.z - j * b.sx), wf_keep(y), j};
+  }
+  // byte offset of group 4*lx + g with every position in the grid
+  __device__ static unsigned off_in(const Base& b, const Step& t, int g) {
+    return (unsigned)(t.e + g * b.gy) * (unsigned)sizeof(V);
+  }
+  // byte offset of group 4*lx + g, or WF_OOB where the position is outside the grid
+  __device__ static unsigned off_any(const WfArgs<V>& a, const WfGeo& q, const Base& b, const Step& t, int g) {
+    const int yt = t.y + 4 * g;
+    const int z = t.z - 4 * WY * g;
+    const bool ok = (unsigned)yt < (unsigned)a.g.ny && (unsigned)z < (unsigned)a.g.nz;
+    return ok ? off_in(b, t, g) : WF_OOB;
+  }
+};
+
+// ---- load role (wave 5): right-hand side, two chunks ahead --------------------
+template <int PAT, int DIR, class V>
+__device__ __forceinline__ void wf_load(const WfArgs<V>& a, const WfGeo& q, V* hbuf) {
+  using RU = WfRuns<PAT, DIR, V>;
+  const int lane = threadIdx.x - 5 * 64;
+  RU R;
+  R.init(a, q, lane);
+  const auto rh = wf_rsrc(a.h + q.vb, q.vbytes);
+  V reg[WF_GRP];
+  // Per step j of a chunk: the registers of groups 4j .. 4j+3 (a chunk's
+  // runs) go to the chunk buffer hb, then take the runs of the chunk with
+  // bases b.
+  auto advance = [&](V* hb, const typename RU::Base& b, bool sync) {
 #pragma unroll
-        for (int m = 0; m < NT; ++m) {
-          const int so = DIR > 0 ? m : C + 1 + m;
-          const int dx = pat_off(PAT, so, 0), dy = pat_off(PAT, so, 1), dz = pat_off(PAT, so, 2);
-          if (dx == 0 && dy == 0) {
-            val[m] = own_prev;
-          } else {
-            const int c = col_of(DIR * dx, DIR * dy);
-            const int back = DIR * (WX * dx + WY * dy + dz);  // in [-KB, -1]
-            val[m] = ring[((j + back + WF_HIST) % WF_HIST) * RW + nidx[c]];
-          }
-        }
+    for (int j = 0; j < WF_HIST; ++j) {
 #pragma unroll
-        for (int m = 0; m < NT; ++m) {
-          const V cm = T::HALF ? sc * T::get(cf[jp], m) : T::get(cf[jp], m);
-          t = fma(-cm, val[m], t);
-        }
-        const V dv = T::HALF ? __uint_as_float(sdv[jp].y) : T::get(cf[jp], NT);
-        const V xv = UNITD ? t : t * dv;
-        const V xr = act ? xv : V(0);
-        own_prev = xr;
-        ring[j * RW + tid] = xr;
-        hslot = xr;
-        // columns read by other tiles leave at once, device-coherently
-        bst<WF_SC1>(xv, rx, exported && act ? (vo + (unsigned)z) * (unsigned)sizeof(V) : WF_OOB);
-        halo_put(k + 1, (j + 1) % PH);
-        halo_fetch(k + PH, j % PH);
-        prefetch(k + P, jp);
+      for (int g = 0; g < WF_GPS; ++g) hb[4 * (j * WF_GPS + g)] = reg[j * WF_GPS + g];
+      const typename RU::Step t = R.step(b, q, j);
+#pragma unroll
+      for (int g = 0; g < WF_GPS; ++g) reg[j * WF_GPS + g] = bld<V, 0>(rh, RU::off_any(a, q, b, t, g));
+      if (sync)
         __syncthreads();
-      }
+      else
+        __builtin_amdgcn_sched_barrier(0);  // keep the refill behind this step's LDS writes
     }
-    // the last chunk's results
-    {
-      const int cl = nsteps / WF_CH - 1;
+  };
+  auto bases = [&](int c) { return R.base(wf_step<DIR>(q.NS, c * WF_CH + R.m)); };
+  // prologue: chunk 0 into buffer 0, chunk 1 into the registers
+  {
+    const typename RU::Base b = bases(0);
 #pragma unroll
-      for (int i = 0; i < WF_TX; ++i) xrun_out(cl, i);
-      if (ADD) add_out(cl);
+    for (int j = 0; j < WF_HIST; ++j) {
+      const typename RU::Step t = R.step(b, q, j);
+#pragma unroll
+      for (int g = 0; g < WF_GPS; ++g) reg[j * WF_GPS + g] = bld<V, 0>(rh, RU::off_any(a, q, b, t, g));
     }
   }
+  advance(hbuf + R.lds, bases(1), false);
+  __syncthreads();
+
+  for (int k0 = 0; k0 < q.nsteps; k0 += WF_HIST) {
+    const int c = k0 / WF_CH;
+    // chunk c+1's groups into LDS, then chunk c+2's into the registers freed
+    advance(hbuf + ((c + 1) % WF_NB) * (WF_CH * WF_HRW) + R.lds, bases(c + 2), true);
+  }
+  __syncthreads();
+  __syncthreads();
+}
+
+// ---- store role (wave 6): exports, results one chunk behind, sentinels -------
+template <int PAT, int DIR, class V>
+__device__ __forceinline__ void wf_store(const WfArgs<V>& a, const WfGeo& q, const V* ring, V* hbuf) {
+  using B = VBits<V>;
+  using RU = WfRuns<PAT, DIR, V>;
+  constexpr int WX = hp_wx(PAT), WY = hp_wy(PAT), KB = wf_kb(PAT);
+  const int lane = threadIdx.x - 6 * 64;
+  const int NS = q.NS, nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  RU R;
+  R.init(a, q, lane);
+  const auto rx = wf_rsrc(a.x + q.vb, q.vbytes);
+  const auto rn = wf_rsrc((a.next != nullptr ? a.next : a.x) + q.vb, a.next != nullptr ? q.vbytes : 0u);
+  // Columns read by other tiles in this sweep (exported below) and in the
+  // next sweep (given the sentinel) lie outside the inner rectangles.  Bit r
+  // of xm / nm: is column 4r + cq outside (its run store dropped / its
+  // sentinel written)?  A set bit 31 puts an offset outside the buffer.
+  const WfRect ix = wf_inner(PAT, DIR, q.sh);
+  const WfRect inx = wf_inner(PAT, a.next_dir, q.sh);
+  unsigned long long xm = 0, nm = 0;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int ly = 4 * g + R.cq;
+    xm |= (ly < ix.yl || ly >= ix.yh) ? 0x1111111111111111ull << g : 0ull;
+    nm |= (ly < inx.yl || ly >= inx.yh) ? 0x1111111111111111ull << g : 0ull;
+  }
+#pragma unroll
+  for (int lx = 0; lx < WF_TX; ++lx) {
+    xm |= (lx < ix.xl || lx >= ix.xh) ? 0xFull << (4 * lx) : 0ull;
+    nm |= (lx < inx.xl || lx >= inx.xh) ? 0xFull << (4 * lx) : 0ull;
+  }
+  const unsigned xm0 = (unsigned)xm, xm1 = (unsigned)(xm >> 32);
+  const unsigned nm0 = ~(unsigned)nm, nm1 = ~(unsigned)(nm >> 32);  // set: no sentinel
+  // does group r hold a column that gets the sentinel (the same for all lanes)?
+  auto gsent = [&](int r) {
+    const int lx = r / 4, g = r % 4;
+    return lx < inx.xl || lx >= inx.xh || 4 * g < inx.yl || 4 * g + 3 >= inx.yh;
+  };
+  auto bit31 = [](unsigned w, int r) { return ((w >> (r % 32)) & 1u) << 31; };
+  auto put = [&](unsigned off, int r, const V* hb, bool nxt) {
+    const V v = hb[4 * r];
+    bst<0>(v, rx, off | bit31(r < 32 ? xm0 : xm1, r));
+    if (nxt && gsent(r)) bst<0>(B::val(B::sent), rn, off | bit31(r < 32 ? nm0 : nm1, r));
+  };
+  // exported column `lane` (in lane order) of the tile
+  const bool erole = lane < wf_exported_count(ix);
+  const int el = erole ? wf_exported_lane(ix, lane) : 0;
+  const int elx = el / WF_TY, ely = el % WF_TY;
+  const int exx = q.X * WF_TX + elx, eyy = q.Y * WF_TY + ely - q.sh * elx;
+  const bool ecolv = erole && exx < nx && eyy >= 0 && eyy < ny;
+  const unsigned evo = ecolv ? (unsigned)(((exx - q.p0) * (long)ny + eyy) * nz) : 0u;
+  const int eskew = (WX - q.sh * WY) * elx + WY * ely + KB;
+  // the exported columns' values of step k (ring row j = k mod 16), device-coherently
+  auto export_step = [&](int k, int j) {
+    const int s = wf_step<DIR>(NS, k);
+    const int z = s - eskew;
+    const bool ok = ecolv && k >= 0 && s >= 0 && s < NS && z >= 0 && z < nz;
+    const V v = ring[((j + WF_HIST) % WF_HIST) * WF_RW + el];
+    bst<WF_SC1>(v, rx, ok ? (evo + (unsigned)z) * (unsigned)sizeof(V) : WF_OOB);
+  };
+  auto chunk = [&](int k0, const typename RU::Base& b, int mode, const V* hb) {
+#pragma unroll
+    for (int j = 0; j < WF_HIST; ++j) {
+      export_step(k0 + j - 1, j - 1);
+      if (mode > 0) {
+        const typename RU::Step t = R.step(b, q, j);
+#pragma unroll
+        for (int g = 0; g < WF_GPS; ++g) put(RU::off_any(a, q, b, t, g), j * WF_GPS + g, hb, mode == 2);
+      }
+      __syncthreads();
+    }
+  };
+  __syncthreads();  // prologue
+
+  for (int k0 = 0; k0 < q.nsteps; k0 += WF_HIST) {
+    const int c = k0 / WF_CH;
+    const V* hb = hbuf + ((c + WF_NB - 1) % WF_NB) * (WF_CH * WF_HRW) + R.lds;
+    const typename RU::Base b = R.base(wf_step<DIR>(q.NS, (c - 1) * WF_CH + R.m));
+    if (c == 0)
+      chunk(k0, b, 0, hb);
+    else if (a.next != nullptr)
+      chunk(k0, b, 2, hb);
+    else
+      chunk(k0, b, 1, hb);
+  }
+  __syncthreads();
+  export_step(q.nsteps - 1, WF_HIST - 1);
+  {
+    const int c = q.nsteps / WF_CH - 1;
+    const V* hb = hbuf + (c % WF_NB) * (WF_CH * WF_HRW) + R.lds;
+    const typename RU::Base b = R.base(wf_step<DIR>(q.NS, c * WF_CH + R.m));
+#pragma unroll 4
+    for (int r = 0; r < WF_GRP; ++r) {
+      const unsigned off = RU::off_any(a, q, b, R.step(b, q, r / 4), r % 4);
+      const V v = hb[4 * r];
+      const unsigned xw = r < 32 ? xm0 : xm1, nw = r < 32 ? nm0 : nm1;
+      bst<0>(v, rx, off | (((xw >> (r % 32)) & 1u) << 31));
+      if (a.next != nullptr) bst<0>(B::val(B::sent), rn, off | (((nw >> (r % 32)) & 1u) << 31));
+    }
+  }
+  __syncthreads();
+}
+
+// The LDS of a sweep workgroup: the value ring and the chunk buffers, zeroed
+// once per launch (inactive positions then compute zeros from zeros).
+template <class V>
+struct WfLds {
+  V ring[WF_HIST * WF_RW];
+  V hbuf[WF_NB * WF_CH * WF_HRW];
+};
+template <class V>
+__device__ inline void wf_zero_lds(WfLds<V>* L) {
+  constexpr int n = (int)(sizeof(WfLds<V>) / 4);
+  unsigned* p = reinterpret_cast<unsigned*>(L);
+  for (int i = threadIdx.x; i < n; i += WF_THREADS) p[i] = 0u;
+  __syncthreads();
 }
 
 // The last workgroup to finish resets the ticket counters for the next launch.
@@ -538,15 +769,41 @@ __device__ inline unsigned wf_take_ticket(unsigned* ctr) {
   return __builtin_amdgcn_readfirstlane(t);
 }
 
-// One sweep over one grid: persistent workgroups take tiles by ticket.
-template <int PAT, int DIR, int P, class E, bool UNITD, bool ADD>
-__global__ __launch_bounds__(WF_NL) void k_wavefront(WfArgs<typename WfVal<E>::V> a) {
-  const unsigned ntiles = (unsigned)(a.t.ntx * a.t.nty);
-  for (;;) {
-    const unsigned ticket = wf_take_ticket(a.ctr);
-    if (ticket >= ntiles) break;
-    wf_tile<PAT, DIR, P, E, UNITD, ADD>(a, DIR > 0 ? ticket : ntiles - 1u - ticket, a.err);
+// Every role of a sweep workgroup runs its own loop over the workgroup's
+// tiles (values a role keeps across tiles then stay out of the other roles'
+// code); next(&a, &tile) takes the next ticket, the same for all waves.
+template <int PAT, int DIR, int P, class E, bool UNITD, class Next>
+__device__ __forceinline__ void wf_roles(Next next, unsigned* err, WfLds<typename WfVal<E>::V>* L) {
+  using V = typename WfVal<E>::V;
+  WfArgs<V> a;
+  unsigned tile;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64);
+  if (wave < 4) {
+    while (next(&a, &tile)) wf_compute<PAT, DIR, P, E, UNITD>(a, wf_geo(a, tile), tile, L->ring, L->hbuf);
+  } else if (wave == 4) {
+    while (next(&a, &tile)) wf_halo<PAT, DIR, V>(a, wf_geo(a, tile), L->ring, err);
+  } else if (wave == 5) {
+    while (next(&a, &tile)) wf_load<PAT, DIR, V>(a, wf_geo(a, tile), L->hbuf);
+  } else {
+    while (next(&a, &tile)) wf_store<PAT, DIR, V>(a, wf_geo(a, tile), L->ring, L->hbuf);
   }
+}
+
+// One sweep over one grid: persistent workgroups take tiles by ticket.
+template <int PAT, int DIR, int P, class E, bool UNITD>
+__global__ __launch_bounds__(WF_THREADS) void k_wavefront(WfArgs<typename WfVal<E>::V> a) {
+  using V = typename WfVal<E>::V;
+  __shared__ WfLds<V> L;
+  wf_zero_lds(&L);
+  const unsigned ntiles = (unsigned)(a.t.ntx * a.t.nty);
+  auto next = [&](WfArgs<V>* pa, unsigned* tile) {
+    const unsigned ticket = wf_take_ticket(a.ctr);
+    if (ticket >= ntiles) return false;
+    *pa = a;
+    *tile = DIR > 0 ? ticket : ntiles - 1u - ticket;
+    return true;
+  };
+  wf_roles<PAT, DIR, P, E, UNITD>(next, a.err, &L);
   wf_retire(a.ctr);
 }
 
@@ -554,21 +811,36 @@ __global__ __launch_bounds__(WF_NL) void k_wavefront(WfArgs<typename WfVal<E>::V
 // one launch.  Ticket k names entry tmap[k] = (segment << 20) | r: the r-th
 // tile of segment seg in that segment's own dependence order, so every
 // tile's producers hold smaller tickets whatever the merge of the segments.
-template <int PAT, int DIR, int P, class E, bool UNITD, bool ADD>
-__global__ __launch_bounds__(WF_NL) void k_wavefront_group(const WfArgs<typename WfVal<E>::V>* __restrict__ segs,
-                                                           const unsigned* __restrict__ tmap, unsigned total,
-                                                           const int* __restrict__ live, unsigned* ctr,
-                                                           unsigned* err) {
-  for (;;) {
-    const unsigned ticket = wf_take_ticket(ctr);
-    if (ticket >= total) break;
-    const unsigned e = __builtin_amdgcn_readfirstlane(tmap[ticket]);
-    const WfArgs<typename WfVal<E>::V> a = segs[e >> 20];
-    if (live != nullptr && live[a.sys] == 0) continue;
-    const unsigned r = e & 0xFFFFFu, nt = (unsigned)(a.t.ntx * a.t.nty);
-    wf_tile<PAT, DIR, P, E, UNITD, ADD>(a, DIR > 0 ? r : nt - 1u - r, err);
-  }
+template <int PAT, int DIR, int P, class E>
+__global__ __launch_bounds__(WF_THREADS) void k_wavefront_group(const WfArgs<typename WfVal<E>::V>* __restrict__ segs,
+                                                                const unsigned* __restrict__ tmap, unsigned total,
+                                                                const int* __restrict__ live, unsigned* ctr,
+                                                                unsigned* err) {
+  using V = typename WfVal<E>::V;
+  __shared__ WfLds<V> L;
+  wf_zero_lds(&L);
+  auto next = [&](WfArgs<V>* pa, unsigned* tile) {
+    for (;;) {
+      const unsigned ticket = wf_take_ticket(ctr);
+      if (ticket >= total) return false;
+      const unsigned e = __builtin_amdgcn_readfirstlane(tmap[ticket]);
+      *pa = segs[e >> 20];
+      if (live != nullptr && live[pa->sys] == 0) continue;
+      const unsigned r = e & 0xFFFFFu, nt = (unsigned)(pa->t.ntx * pa->t.nty);
+      *tile = DIR > 0 ? r : nt - 1u - r;
+      return true;
+    }
+  };
+  wf_roles<PAT, DIR, P, E, false>(next, err, &L);
   wf_retire(ctr);
+}
+
+// addout = addv + x (the correction step after an ILU(0) upper sweep)
+template <class V>
+__global__ __launch_bounds__(256) void k_wf_add(const V* __restrict__ addv, const V* __restrict__ x,
+                                                V* __restrict__ addout, long n) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) addout[i] = addv[i] + x[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -702,20 +974,27 @@ hipError_t launch_wf_pack_h(int pat, const Grid& g, const WfTiling& tl, int dir,
 }
 
 // ---------------------------------------------------------------------------
-template <int PAT, int DIR, int P, class E, bool UNITD, bool ADD>
+template <int PAT, int DIR, int P, class E, bool UNITD>
 static hipError_t launch_wf_t(const WfArgs<typename WfVal<E>::V>& a, hipStream_t st) {
   const unsigned ntiles = (unsigned)(a.t.ntx * a.t.nty);
   const unsigned grid = ntiles < (unsigned)WF_MAX_GRID ? ntiles : (unsigned)WF_MAX_GRID;
-  hipLaunchKernelGGL((k_wavefront<PAT, DIR, P, E, UNITD, ADD>), dim3(grid), dim3(WF_NL), 0, st, a);
+  hipLaunchKernelGGL((k_wavefront<PAT, DIR, P, E, UNITD>), dim3(grid), dim3(WF_THREADS), 0, st, a);
   return hipGetLastError();
 }
 
-template <int PAT, int DIR, int P, class E, bool UNITD, bool ADD>
+template <int PAT, int DIR, int P, class E>
 static hipError_t launch_wfg_t(const WfArgs<typename WfVal<E>::V>* segs, const unsigned* tmap, unsigned total,
                                unsigned grid, const int* live, unsigned* ctr, unsigned* err, hipStream_t st) {
-  hipLaunchKernelGGL((k_wavefront_group<PAT, DIR, P, E, UNITD, ADD>), dim3(grid), dim3(WF_NL), 0, st, segs, tmap,
-                     total, live, ctr, err);
+  hipLaunchKernelGGL((k_wavefront_group<PAT, DIR, P, E>), dim3(grid), dim3(WF_THREADS), 0, st, segs, tmap, total,
+                     live, ctr, err);
   return hipGetLastError();
+}
+
+// Coefficient prefetch distance (steps) per pattern and storage type: as deep
+// as the compute waves' registers allow (NPK 16-byte packs per step).
+template <int PAT, class E>
+constexpr int wf_prefetch() {
+  return wf_npk(PAT, sizeof(E)) * 4 * 16 <= 160 ? 16 : (wf_npk(PAT, sizeof(E)) * 4 * 8 <= 160 ? 8 : 4);
 }
 
 template <class E>
@@ -724,12 +1003,16 @@ hipError_t launch_wavefront_group(int pat, int dir, const WfArgs<typename WfVal<
                                   hipStream_t st) {
   if (total == 0) return hipSuccess;
   if (grid == 0 || grid > total) grid = total;
-  if (pat == 7 && dir > 0) return launch_wfg_t<7, 1, 8, E, false, false>(segs, tmap, total, grid, live, ctr, err, st);
-  if (pat == 7 && dir < 0) return launch_wfg_t<7, -1, 8, E, false, false>(segs, tmap, total, grid, live, ctr, err, st);
-  if (pat == 19 && dir > 0) return launch_wfg_t<19, 1, 4, E, false, false>(segs, tmap, total, grid, live, ctr, err, st);
-  if (pat == 19 && dir < 0) return launch_wfg_t<19, -1, 4, E, false, false>(segs, tmap, total, grid, live, ctr, err, st);
-  if (pat == 27 && dir > 0) return launch_wfg_t<27, 1, 4, E, false, false>(segs, tmap, total, grid, live, ctr, err, st);
-  if (pat == 27 && dir < 0) return launch_wfg_t<27, -1, 4, E, false, false>(segs, tmap, total, grid, live, ctr, err, st);
+  if (grid > (unsigned)WF_MAX_GRID) grid = WF_MAX_GRID;
+#define SMG_WFG_CASE(PATV)                                                                                       \
+  if (pat == PATV && dir > 0)                                                                                    \
+    return launch_wfg_t<PATV, 1, wf_prefetch<PATV, E>(), E>(segs, tmap, total, grid, live, ctr, err, st);         \
+  if (pat == PATV && dir < 0)                                                                                    \
+    return launch_wfg_t<PATV, -1, wf_prefetch<PATV, E>(), E>(segs, tmap, total, grid, live, ctr, err, st);
+  SMG_WFG_CASE(7)
+  SMG_WFG_CASE(19)
+  SMG_WFG_CASE(27)
+#undef SMG_WFG_CASE
   return hipErrorInvalidValue;
 }
 template hipError_t launch_wavefront_group<double>(int, int, const WfArgs<double>*, const unsigned*, unsigned,
@@ -742,18 +1025,25 @@ template hipError_t launch_wavefront_group<__half>(int, int, const WfArgs<float>
 template <class E>
 hipError_t launch_wavefront(int pat, int dir, bool unitd, bool add, const WfArgs<typename WfVal<E>::V>& a,
                             hipStream_t st) {
-#define SMG_WF_CASE(PATV, PV)                                                                  \
-  if (pat == PATV) {                                                                           \
-    if (dir > 0 && !unitd && !add) return launch_wf_t<PATV, 1, PV, E, false, false>(a, st);    \
-    if (dir < 0 && !unitd && !add) return launch_wf_t<PATV, -1, PV, E, false, false>(a, st);   \
-    if (dir > 0 && unitd && !add) return launch_wf_t<PATV, 1, PV, E, true, false>(a, st);      \
-    if (dir < 0 && !unitd && add) return launch_wf_t<PATV, -1, PV, E, false, true>(a, st);     \
+  using V = typename WfVal<E>::V;
+  hipError_t e = hipErrorInvalidValue;
+#define SMG_WF_CASE(PATV)                                                                           \
+  if (pat == PATV) {                                                                                \
+    constexpr int PV = wf_prefetch<PATV, E>();                                                      \
+    if (dir > 0 && !unitd) e = launch_wf_t<PATV, 1, PV, E, false>(a, st);                           \
+    if (dir < 0 && !unitd) e = launch_wf_t<PATV, -1, PV, E, false>(a, st);                          \
+    if (dir > 0 && unitd) e = launch_wf_t<PATV, 1, PV, E, true>(a, st);                             \
   }
-  SMG_WF_CASE(7, 8)
-  SMG_WF_CASE(19, 4)
-  SMG_WF_CASE(27, 4)
+  SMG_WF_CASE(7)
+  SMG_WF_CASE(19)
+  SMG_WF_CASE(27)
 #undef SMG_WF_CASE
-  return hipErrorInvalidValue;
+  if (e != hipSuccess || !add) return e;
+  // addout = addv + x once the sweep has finished
+  const long n = a.g.N();
+  hipLaunchKernelGGL((k_wf_add<V>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a.addv,
+                     (const V*)a.x, a.addout, n);
+  return hipGetLastError();
 }
 
 template hipError_t launch_wavefront<double>(int, int, bool, bool, const WfArgs<double>&, hipStream_t);

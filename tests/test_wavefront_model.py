@@ -4,23 +4,27 @@ The GPU kernel runs tiles concurrently; any order in which each tile runs
 after every tile it depends on is one of its possible executions.  This model
 replays the kernel's exact index arithmetic -- lane -> column mapping with
 shear, per-lane skew with the KB padding, the LDS ring rows and halo slots,
-the halo loader lanes, the buffer windows of the vectors, the sentinel
+the roles of the waves (compute lanes, halo loader, right-hand-side loader,
+result / export store), the three chunk buffers, the column-run groups and
+their offset arithmetic, the buffer windows of the vectors, the sentinel
 prefill for the next sweep, the packed coefficient positions -- with the
 tiles run one after another in ticket order, and checks that
 
   * the result equals the sequential lexicographic sweep of the oracle,
   * every LDS ring read of a lane that has a point finds the value written
     for exactly that neighbour point in the same tile (or zero where the
-    neighbour lies outside the grid),
+    neighbour lies outside the grid), and lanes without a point compute
+    zero from finite values,
   * every value fetched from another tile's column held the sentinel when the
-    sweep started (so a concurrent reader would have waited for it),
-  * the right-hand side reaches each lane through the LDS chunk buffer
-    (loaded as column runs) and results leave through the ring as column
-    runs every 16 steps; only columns read by other tiles are written at
-    once, so a fetch of any other position would find the sentinel,
+    sweep started (so a concurrent reader would have waited for it) and was
+    written by that tile's export path,
+  * the right-hand side reaches each lane through the chunk buffer filled by
+    the load role (column runs) and results leave as column runs one chunk
+    behind; the roles' LDS accesses within a step never touch the same slot,
   * every buffer offset stays inside the planes the kernel's buffer covers,
-    every halo slot index is inside the frame and every used slot has a
-    loader lane,
+    the run groups' offsets equal the points' indices, every used halo slot
+    is inside the frame and has a loader lane, and the exported columns
+    enumerated by the store role are exactly the columns other tiles read,
   * the prefill of a sweep marks every position the next sweep fetches, and
   * the packed-data position of every point is unique and inverted by the
     setup kernel's mapping.
@@ -36,6 +40,9 @@ NL = TX * TY
 NH = 104
 HIST = 16    # LDS ring rows
 CH = 16      # steps per chunk of right-hand side / results
+NB = 3       # chunk buffers
+GRP = NL * CH // 64   # column-run groups per chunk
+GPS = GRP // CH       # groups moved per step
 
 
 def pat_has(pat, d):
@@ -111,11 +118,39 @@ def exported(pat, lx, ly, sh, direction):
 def tiling(g, pat):
     nx, ny, nz = g
     WX, WY = hp(pat)
-    sh = 0 if ny <= TY else 1
+    sh = 0 if (pat == 7 or ny <= TY) else 1
     ntx = (nx + TX - 1) // TX
     nty = (ny + sh * (TX - 1) + TY - 1) // TY
     ns = nz + (WX - sh * WY) * (TX - 1) + WY * (TY - 1) + 2 * kb_of(pat)
     return sh, ntx, nty, ns
+
+
+def inner_rect(pat, direction, sh):
+    """Lanes whose column no other tile reads: the kernel's wf_inner."""
+    xl, xh, yl, yh = 0, TX, 0, TY
+    for c in range(4):
+        if not col_used(pat, c):
+            continue
+        cx0, cy0 = col_d(c)
+        cx, cy = direction * cx0, direction * cy0 + sh * direction * cx0
+        xl, xh, yl, yh = max(xl, cx), min(xh, TX + cx), max(yl, cy), min(yh, TY + cy)
+    return xl, xh, yl, yh
+
+
+def exported_lane(rect, e):
+    """The kernel's wf_exported_lane: e-th lane outside the rectangle."""
+    xl, xh, yl, yh = rect
+    nm = TY - (yh - yl)
+    if e < TY * xl:
+        lx, ly = divmod(e, TY)
+    elif e < TY * xl + nm * (xh - xl):
+        q = e - TY * xl
+        lx, w = xl + q // nm, q % nm
+        ly = w if w < yl else yh + (w - yl)
+    else:
+        q = e - TY * xl - nm * (xh - xl)
+        lx, ly = xh + q // TY, q % TY
+    return lx * TY + ly
 
 
 def wf_point(g, pat, q):
@@ -133,10 +168,11 @@ def wf_point(g, pat, q):
     return (x * ny + y) * nz + z if ok else -1
 
 
-def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf):
+def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf, lds=None):
     """Replays one kernel launch in ticket order.  x_init: output buffer at
-    launch (nan marks a sentinel).  Returns (x, prefill mask, packed index of
-    every point)."""
+    launch (nan marks a sentinel).  lds: the workgroup's LDS (ring, chunk
+    buffers) carried from tile to tile, zero at launch.  Returns (x, prefill
+    mask, packed index of every point)."""
     nx, ny, nz = g
     N = nx * ny * nz
     WX, WY = hp(pat)
@@ -146,19 +182,25 @@ def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf):
     T = list(range(C)) if direction > 0 else list(range(C + 1, pat))
     sh, ntx, nty, NS = tiling(g, pat)
     nsteps = -(-NS // HIST) * HIST
+    NC = nsteps // CH
     RW = NL + NH + 1
     HRW = NL + 1
     x = x_init.copy()
     done = np.full(N, np.nan)   # every value as soon as it is computed (model bookkeeping only)
     sent_at_start = np.isnan(x_init)
+    exported_at = set()         # positions written by an export
     pref = np.zeros(N, bool)
     lanes = np.arange(NL)
     lx, ly = lanes // TY, lanes % TY
     skew = (WX - sh * WY) * lx + WY * ly + KB
-    exp_now = np.array([exported(pat, a, b, sh, direction) for a, b in zip(lx, ly)])
-    exp_next = np.array([exported(pat, a, b, sh, nxt_dir) for a, b in zip(lx, ly)]) if nxt_buf is not None \
-        else np.zeros(NL, bool)
-    run_y, run_r = lanes // CH, lanes % CH   # column-run roles of the threads
+    # exported columns: the store role's rectangle enumeration equals the
+    # columns other tiles read, in lane order
+    rect = inner_rect(pat, direction, sh)
+    ne = NL - (rect[1] - rect[0]) * (rect[3] - rect[2])
+    assert ne <= 64, "more exported columns than lanes of the store wave"
+    elanes = [exported_lane(rect, e) for e in range(ne)]
+    assert elanes == [l for l in range(NL) if exported(pat, l // TY, l % TY, sh, direction)]
+    rectn = inner_rect(pat, nxt_dir, sh) if nxt_buf is not None else None
     # neighbour column LDS indices
     nidx = {}
     for c in range(4):
@@ -176,17 +218,14 @@ def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf):
                 assert 0 <= hs < NH and halo_pos(hs) == (qx[l], qy[l])
                 idx[l] = NL + hs
         nidx[c] = idx
-    # halo loader lanes
-    hs_of = (lanes % 64) * 4 + lanes // 64
-    loaders = {}
-    for l in range(NL):
-        hs = int(hs_of[l])
-        if hs < NH:
-            assert halo_slot(*halo_pos(hs)) == hs
-            if halo_used(pat, direction, sh, *halo_pos(hs)):
-                loaders[hs] = l
+    # halo loader: lane t of the halo wave handles slots t and 64 + t
+    loaders = [hs for hs in range(NH) if halo_used(pat, direction, sh, *halo_pos(hs))]
+    assert all(hs < 128 for hs in loaders)
     used_slots = {int(v) - NL for c in nidx for v in nidx[c] if v >= NL}
     assert used_slots <= set(loaders), "a used halo slot has no loader lane"
+    if lds is None:
+        lds = {"ring": np.zeros((HIST, RW)), "hbuf": np.zeros((NB, CH, HRW))}
+    ring, hbuf = lds["ring"], lds["hbuf"]
     pkidx = np.full(N, -1, np.int64)
     ntiles = ntx * nty
     pl = ny * nz
@@ -200,97 +239,142 @@ def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf):
         yt = Y * TY + ly - sh * lx
         colv = (xt < nx) & (yt >= 0) & (yt < ny)
         cb = (xt * ny + yt) * nz
-        ring = np.full((HIST, RW), np.nan)
         ring_pt = np.full((HIST, RW), -2, np.int64)    # point index, or -1 for "zero"
         ring_it = np.full((HIST, RW), -10 ** 9, np.int64)
-        hbuf = np.full(2 * CH * HRW, np.nan)
-        hbuf_pt = np.full(2 * CH * HRW, -2, np.int64)   # point whose result a slot holds (-1: none)
+        hbuf_pt = np.full((NB, CH, HRW), -2, np.int64)  # point a slot holds (-1: none)
+        touched = {}                                    # LDS slots used in the current step, by role
         own_prev = np.zeros(NL)
 
         def step_of(k):
             return k if direction > 0 else NS - 1 - k
 
-        def run_off(i, cyy, s):
-            xx, yy = X * TX + i, Y * TY + cyy - sh * i
-            z = s - ((WX - sh * WY) * i + WY * cyy + KB)
-            if xx < nx and 0 <= yy < ny and 0 <= z < nz:
-                gi = (xx * ny + yy) * nz + z
+        def touch(key, role, write):
+            # two roles may read one slot in a step; a write excludes any other role
+            for r2, w2 in touched.setdefault(key, set()):
+                assert r2 == role or not (write or w2), f"{role} and {r2} race on LDS slot {key}"
+            touched[key].add((role, write))
+
+        def run_point(c, r, tl):
+            """Group r of chunk c, lane tl of a run wave: (step row m, column,
+            point index or -1), with the kernel's offset arithmetic checked."""
+            cq, m = tl // 16, tl % 16
+            col = 4 * r + cq
+            s = step_of(c * CH + m)
+            # the kernel's bases
+            skq = WY * cq + KB
+            y0 = Y * TY + cq
+            a0 = ((X * TX - p0) * ny + y0) * nz - skq
+            sx = WX - sh * WY
+            gx, gy = (ny - sh) * nz - sx, 4 * (nz - WY)
+            jj, gg = r // 4, r % 4
+            e = a0 + s + jj * gx + gg * gy
+            zz = s - skq - jj * sx - 4 * WY * gg
+            yy = (y0 - sh * jj) if X * TX + jj < nx else -TY - 1
+            yy += 4 * gg
+            ok = 0 <= yy < ny and 0 <= zz < nz
+            # the point directly
+            cl, cyy = col // TY, col % TY
+            xx, yd = X * TX + cl, Y * TY + cyy - sh * cl
+            z = s - ((WX - sh * WY) * cl + WY * cyy + KB)
+            valid = xx < nx and 0 <= yd < ny and 0 <= z < nz
+            assert ok == valid, "run group validity differs from the point's"
+            gi = (xx * ny + yd) * nz + z if valid else -1
+            if valid:
+                assert e + p0 * pl == gi, "run group offset differs from the point index"
                 assert lo_i <= gi < hi_i, "column-run offset outside the buffer window"
-                return gi
-            return -1
+            return m, col, gi
 
-        def hrun_put(c, i):
-            for t in range(NL):
-                s = step_of(c * CH + run_r[t])
-                gi = run_off(i, run_y[t], s)
-                li = ((c & 1) * CH + run_r[t]) * HRW + i * TY + run_y[t]
-                assert 0 <= li < 2 * CH * HRW
-                hbuf[li] = h[gi] if gi >= 0 else 0.0
-                hbuf_pt[li] = -3   # holds a right-hand side now
+        def load_group(c, r):
+            for tl in range(64):
+                m, col, gi = run_point(c, r, tl)
+                touch(("hbuf", c % NB, m, col), "load", True)
+                hbuf[c % NB, m, col] = h[gi] if gi >= 0 else 0.0
+                hbuf_pt[c % NB, m, col] = -3   # holds a right-hand side now
 
-        def xrun_out(c, i):
-            # results of chunk c, run i, from the hbuf slots the lanes wrote
-            for t in range(NL):
-                s = step_of(c * CH + run_r[t])
-                li = ((c & 1) * CH + run_r[t]) * HRW + i * TY + run_y[t]
-                gi = run_off(i, run_y[t], s)
-                lane = i * TY + run_y[t]
+        def drain_group(c, r):
+            for tl in range(64):
+                m, col, gi = run_point(c, r, tl)
+                touch(("hbuf", c % NB, m, col), "store", False)
                 if gi < 0:
                     continue
-                assert hbuf_pt[li] == gi, "result slot holds another point"
-                if not exp_now[lane]:
-                    assert np.isnan(x[gi]) or x[gi] == 0.0 or not sent_at_start[gi]
-                    x[gi] = hbuf[li]
+                assert hbuf_pt[c % NB, m, col] == gi, "result slot holds another point"
+                if not exported(pat, col // TY, col % TY, sh, direction):
+                    assert np.isnan(x[gi]) or not sent_at_start[gi]
+                    x[gi] = hbuf[c % NB, m, col]
                 else:
-                    assert x[gi] == hbuf[li]
-                if nxt_buf is not None and exported(pat, i, run_y[t], sh, nxt_dir):
+                    assert x[gi] == hbuf[c % NB, m, col]   # exported earlier, same value
+                if nxt_buf is not None and exported(pat, col // TY, col % TY, sh, nxt_dir):
+                    xl, xh, yl, yh = rectn
+                    lxr, g4 = r // 4, r % 4
+                    assert lxr < xl or lxr >= xh or 4 * g4 < yl or 4 * g4 + 3 >= yh, \
+                        "sentinel store of a group skipped"
                     pref[gi] = True
-                    if exported(pat, i, run_y[t], sh, nxt_dir) and nxt_buf is not None:
-                        pref[gi] = True
+
+        def export_step(k):
+            if k < 0:
+                return
+            s = step_of(k)
+            r = k % HIST
+            for el in elanes:
+                z = s - skew[el]
+                touch(("ring", r, el), "store", False)
+                if 0 <= s < NS and colv[el] and 0 <= z < nz:
+                    gi = cb[el] + z
+                    assert lo_i <= gi < hi_i, "export offset outside the buffer window"
+                    assert ring_pt[r, el] == gi, "exported ring slot holds another point"
+                    x[gi] = ring[r, el]
+                    exported_at.add(int(gi))
 
         def halo_put(k):
             s = step_of(k)
-            for hs, l in loaders.items():
+            r = k % HIST
+            for hs in loaders:
                 qx, qy = halo_pos(hs)
                 hskew = (WX - sh * WY) * qx + WY * qy + KB
                 gx, gy = X * TX + qx, Y * TY + qy - sh * qx
                 hz = s - hskew
                 ok = 0 <= s < NS and 0 <= gx < nx and 0 <= gy < ny and 0 <= hz < nz
-                r = k % HIST
+                touch(("ring", r, NL + hs), "halo", True)
                 if ok:
                     gi = (gx * ny + gy) * nz + hz
                     assert lo_i <= gi < hi_i, "halo offset outside the buffer window"
                     assert sent_at_start[gi], "fetched a position that was not a sentinel at launch"
                     assert not np.isnan(x[gi]), "fetched a value its producer has not written"
+                    assert int(gi) in exported_at, "fetched a value not written by an export"
                     ring[r, NL + hs], ring_pt[r, NL + hs] = x[gi], gi
                 else:
                     ring[r, NL + hs], ring_pt[r, NL + hs] = 0.0, -1
                 ring_it[r, NL + hs] = k
 
-        for i in range(TX):
-            hrun_put(0, i)
-        halo_put(0)
+        # prologue: chunk 0 into buffer 0 (chunk 1 is in the load role's registers)
+        for r in range(GRP):
+            load_group(0, r)
         for k in range(nsteps):
-            j = k % HIST
-            jj, ch = k % CH, k // CH
-            if jj < CH // 2:                      # the previous chunk's results, two runs per step
-                xrun_out(ch - 1, 2 * jj)
-                xrun_out(ch - 1, 2 * jj + 1)
-            if 4 <= jj < CH // 2 + 4:             # next chunk's right-hand side, four steps after its load
-                hrun_put(ch + 1, 2 * (jj - 4))
-                hrun_put(ch + 1, 2 * (jj - 4) + 1)
+            touched.clear()
+            j, c = k % HIST, k // CH
+            halo_put(k)
             s = step_of(k)
             z = s - skew
             act = colv & (z >= 0) & (z < nz)
             xr = np.zeros(NL)
-            for l in np.nonzero(act)[0]:
+            for l in range(NL):
+                slot = (c % NB, k % CH, l)
+                touch(("hbuf",) + slot, "compute", True)
+                tv = hbuf[slot]
+                if not act[l]:
+                    # no point: zero right-hand side, zero coefficients, finite values
+                    assert tv == 0.0
+                    for so in T:
+                        dx, dy, dz = (int(v) for v in off[so])
+                        if not (dx == 0 and dy == 0):
+                            c4 = col_of(direction * dx, direction * dy)
+                            back = direction * (WX * dx + WY * dy + dz)
+                            assert np.isfinite(ring[(j + back) % HIST, nidx[c4][l]])
+                    continue
                 i = cb[l] + z[l]
                 assert lo_i <= i < hi_i, "point offset outside the buffer window"
                 pkidx[i] = (t * NS + s) * NL + l
-                slot = ((k // CH) & 1) * CH * HRW + (k % CH) * HRW + l
-                tv = hbuf[slot]
                 assert tv == h[i] and hbuf_pt[slot] == -3, "right-hand side chunk holds another point"
-                
                 for so in T:
                     dx, dy, dz = (int(v) for v in off[so])
                     xn, yn, zn = xt[l] + dx, yt[l] + dy, z[l] + dz
@@ -300,11 +384,12 @@ def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf):
                         val = own_prev[l]
                         assert (val == done[gi]) if inb else val == 0.0
                     else:
-                        c = col_of(direction * dx, direction * dy)
+                        c4 = col_of(direction * dx, direction * dy)
                         back = direction * (WX * dx + WY * dy + dz)
                         assert -KB <= back <= -1
                         r = (j + back) % HIST
-                        idx = nidx[c][l]
+                        idx = nidx[c4][l]
+                        touch(("ring", r, int(idx)), "compute", False)
                         assert ring_it[r, idx] == k + back, "ring row not written in this tile at that step"
                         val = ring[r, idx]
                         if inb:
@@ -314,19 +399,27 @@ def run_sweep(g, pat, direction, A, rd, h, x_init, nxt_dir, nxt_buf):
                     tv = _fma(-A[so, i], val, tv)
                 xr[l] = tv * rd[i]
                 done[i] = xr[l]
-                if exp_now[l]:
-                    x[i] = xr[l]   # read by other tiles: written at once
             own_prev = xr
+            for l in range(NL):
+                touch(("ring", j, l), "compute", True)
             ring[j, :NL] = xr
-            for l in range(NL):   # each lane's result over its right-hand-side slot
-                slot = (ch & 1) * CH * HRW + jj * HRW + l
-                hbuf[slot] = xr[l]
-                hbuf_pt[slot] = (cb[l] + z[l]) if act[l] else -1
             ring_pt[j, :NL] = np.where(act, cb + z, -1)
             ring_it[j, :NL] = k
-            halo_put(k + 1)
-        for i in range(TX):
-            xrun_out(nsteps // CH - 1, i)
+            for l in range(NL):   # each lane's result over its right-hand-side slot
+                slot = (c % NB, k % CH, l)
+                hbuf[slot] = xr[l]
+                hbuf_pt[slot] = (cb[l] + z[l]) if act[l] else -1
+            # store role: the previous step's exports, then the previous
+            # chunk's groups of this step; load role: the next chunk's groups
+            export_step(k - 1)
+            for gq in range(GPS):
+                if c > 0:
+                    drain_group(c - 1, j * GPS + gq)
+                load_group(c + 1, j * GPS + gq)
+        touched.clear()
+        export_step(nsteps - 1)
+        for r in range(GRP):
+            drain_group(NC - 1, r)
     return x, pref, pkidx
 
 
