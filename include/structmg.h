@@ -123,6 +123,20 @@ smg_status smg_workspace_size(const smg_config* cfg, size_t* bytes);
 smg_status smg_setup(const smg_config* cfg, const double* coeffs, void* workspace, size_t bytes, void* stream,
                      smg_handle* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): smg_setup with
+ * the hierarchy placed in a static device array of SMG_SCRATCH_BYTES that the
+ * library holds on every GPU it runs on until the process ends, instead of a
+ * caller workspace.  Calls no hipMalloc / hipFree.  SMG_ENOMEM (nothing
+ * touched on the device) when smg_workspace_size(cfg) exceeds the array
+ * (7-point scalar grids beyond about 40^3).  Every call on one device
+ * builds its hierarchy in that device's one array: a call invalidates the
+ * handles of earlier smg_setup_noalloc calls on the same device (destroy them
+ * with smg_destroy), and calls or uses of such handles that overlap in time
+ * race.  Synchronises `stream`. */
+#define SMG_SCRATCH_BYTES ((size_t)64 << 20)
+smg_status smg_setup_noalloc(const smg_config* cfg, const double* coeffs, void* stream, smg_handle* out);
+
 /* Rebuilds the hierarchy of an existing handle for new finest-level
  * coefficients with the same grid, pattern and settings (same workspace).
  * Synchronises `stream`.  A failure leaves the handle unusable until the next

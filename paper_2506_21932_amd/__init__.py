@@ -45,7 +45,7 @@ EXPORTS = ["smg_workspace_size", "smg_setup", "smg_precondition", "smg_solve", "
            "smg_op_prolong_add", "smg_op_coarse_solve", "smg_set_timing", "smg_timing_report", "smg_resetup",
            "smg_batch_workspace_size", "smg_batch_setup", "smg_batch_precondition", "smg_batch_solve",
            "smg_batch_set_schedule", "smg_batch_tune", "smg_batch_set_graph", "smg_batch_num_systems",
-           "smg_batch_system", "smg_batch_destroy", "smg_batch_last_error", "smg_set_graph"]
+           "smg_batch_system", "smg_batch_destroy", "smg_batch_last_error", "smg_set_graph", "smg_setup_noalloc"]
 
 TIMING_KINDS = ["pre_sweep", "pre_sweep_u", "resid_restrict", "coarse_solve", "prolong_post", "post_sweep",
                 "post_sweep_u", "spmv_fp64"]
@@ -64,6 +64,7 @@ def load():
     vp, i, d = C.c_void_p, C.c_int, C.c_double
     L.smg_workspace_size.argtypes = [C.POINTER(Config), C.POINTER(C.c_size_t)]
     L.smg_setup.argtypes = [C.POINTER(Config), vp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.smg_setup_noalloc.argtypes = [C.POINTER(Config), vp, vp, C.POINTER(vp)]
     L.smg_precondition.argtypes = [vp, vp, vp, vp]
     L.smg_solve.argtypes = [vp, vp, vp, d, i, i, C.POINTER(Result), vp]
     L.smg_destroy.argtypes = [vp]

@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include <chrono>
+#include <mutex>
 
 #include "smg_handle.h"
 
@@ -781,6 +782,54 @@ smg_status smg_setup(const smg_config* cfg, const double* coeffs, void* workspac
   H->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = H;
   return SMG_OK;
+}
+
+// ---- setup into a static device array (callers that cannot allocate) ----
+// The hierarchy of smg_setup_noalloc lives in `scratch`, a file-scope device
+// array (each GPU the library runs on holds its own copy until the process
+// ends).  Host code never passes the array's name to a kernel or copy: its
+// device address is taken once per device with hipGetSymbolAddress and kept
+// in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[SMG_SCRATCH_BYTES];
+constexpr int SMG_SCRATCH_DEVICES = 64;
+static void* g_scratch_ptr[SMG_SCRATCH_DEVICES];
+static std::mutex g_scratch_mu;
+
+static smg_status scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(nullptr, SMG_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= SMG_SCRATCH_DEVICES)
+    return fail(nullptr, SMG_EDEVICE, "device %d beyond the %d devices the scratch table holds", dev,
+                SMG_SCRATCH_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return fail(nullptr, SMG_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SMG_OK;
+}
+
+smg_status smg_setup_noalloc(const smg_config* cfg, const double* coeffs, void* stream, smg_handle* out) {
+  if (!out) return fail(nullptr, SMG_EINVAL, "null output handle");
+  *out = nullptr;
+  const char* why = check_cfg(cfg);
+  if (why) return fail(nullptr, SMG_EINVAL, "%s", why);
+  int nlev = 0, nc = 0;
+  const size_t need = plan(*cfg, nullptr, nullptr, &nlev, &nc);
+  if (need == 0) return fail(nullptr, SMG_EINVAL, "coarsest level has %d unknowns (> max_coarse)", nc);
+  if (need > SMG_SCRATCH_BYTES)
+    return fail(nullptr, SMG_ENOMEM,
+                "hierarchy needs %zu bytes; the static scratch array holds %zu (use smg_setup with a workspace)", need,
+                (size_t)SMG_SCRATCH_BYTES);
+  void* p = nullptr;
+  const smg_status s = scratch_address(&p);
+  if (s != SMG_OK) return s;
+  return smg_setup(cfg, coeffs, p, SMG_SCRATCH_BYTES, stream, out);
 }
 
 smg_status smg_resetup(smg_handle h, const double* coeffs, void* stream) {

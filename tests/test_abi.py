@@ -132,3 +132,18 @@ def test_smoother_and_interpolation_options_host_only():
     assert smg.load().smg_workspace_size(C.byref(cfg), C.byref(n_)) == smg.SMG_EINVAL
     cells = (smg.Config * 1)(smg.make_config((8, 8, 8), 7, interp="cell"))
     assert smg.load().smg_batch_workspace_size(1, cells, C.byref(n_)) == smg.SMG_EINVAL
+
+
+def test_setup_noalloc_rejects_hierarchies_beyond_its_array():
+    """The static-array setup refuses, before any device call, a hierarchy
+    larger than its array (so this runs without a GPU)."""
+    cfg = smg.make_config(shape=(128, 128, 128), pattern=7)
+    need = C.c_size_t(0)
+    assert smg.load().smg_workspace_size(C.byref(cfg), C.byref(need)) == smg.SMG_OK
+    assert need.value > 64 << 20
+    h = C.c_void_p()
+    st = smg.load().smg_setup_noalloc(C.byref(cfg), C.c_void_p(1), None, C.byref(h))
+    assert st == smg.SMG_ENOMEM and not h.value
+    msg = smg.load().smg_last_error(None).decode()
+    assert "static scratch array" in msg
+    assert smg.load().smg_setup_noalloc(C.byref(cfg), C.c_void_p(1), None, None) == smg.SMG_EINVAL
