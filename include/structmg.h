@@ -148,7 +148,11 @@ smg_status smg_resetup(smg_handle h, const double* coeffs, void* stream);
 smg_status smg_precondition(smg_handle h, const double* r, double* z, void* stream);
 
 /* Solves A x = b with preconditioned CG (krylov = 0) or right-preconditioned
- * restarted GMRES(krylov) (krylov <= cfg.gmres_restart).  x holds the initial
+ * restarted GMRES(krylov) (krylov <= cfg.gmres_restart) in its flexible form
+ * (the preconditioned basis vectors are kept and combined into the update;
+ * for an exactly linear V-cycle this is plain right-preconditioned GMRES, and
+ * with an FP32 / FP16 V-cycle the recurrence residual stays the true one).
+ * x holds the initial
  * guess on entry.  Stops when ||r||_2 / ||b||_2 < rtol for the true residual
  * (settings table: relative tolerance).  Synchronises `stream`.
  * SMG_ENOTCONV when maxit is reached (res still filled in). */

@@ -52,6 +52,7 @@ struct smg_handle_s {
   double *dpart = nullptr, *dout = nullptr;
   double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr, *kt = nullptr, *kw = nullptr;
   double* kV = nullptr;
+  double* kZ = nullptr;  // flexible GMRES: preconditioned basis vectors
   int kV_m = 0;
   double t_setup_ms = 0.0;
   char msg[512] = {0};

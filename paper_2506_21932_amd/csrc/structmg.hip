@@ -230,6 +230,7 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
   double* kt = ar.take<double>(n0);
   double* kw = ar.take<double>(n0);
   double* kV = cfg.gmres_restart > 0 ? ar.take<double>((size_t)n0 * (cfg.gmres_restart + 1)) : nullptr;
+  double* kZ = cfg.gmres_restart > 0 ? ar.take<double>((size_t)n0 * cfg.gmres_restart) : nullptr;
   if (H) {
     H->aug = aug;
     H->ctr = ctr;
@@ -244,6 +245,7 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
     H->kt = kt;
     H->kw = kw;
     H->kV = kV;
+    H->kZ = kZ;
     H->kV_m = cfg.gmres_restart;
   }
   return ar.off + 256;
@@ -915,9 +917,14 @@ smg_status smg_solve(smg_handle H, const double* b, double* x, double rtol, int 
       KCHK(launch_xpby(n, z, beta, p, st));
     }
   } else if (status != SMG_OK) {
-    // right-preconditioned GMRES(m), modified Gram-Schmidt, Givens rotations
+    // right-preconditioned GMRES(m) in its flexible form: the preconditioned
+    // basis vectors z_j = M v_j are kept (Z) and the update is x += Z y, so
+    // no further V-cycle runs per cycle and the recurrence residual stays
+    // the true one when M is not exactly linear (V-cycle in FP32 / FP16);
+    // modified Gram-Schmidt, Givens rotations
     const int m = krylov;
     double* V = H->kV;
+    double* Z = H->kZ;
     double *w = H->kw, *t = H->kt;
     double Hm[201 * 200];
     double cs[200], sn[200], g[201], y[200];
@@ -930,8 +937,9 @@ smg_status smg_solve(smg_handle H, const double* b, double* x, double rtol, int 
       for (int j = 0; j < m && it < maxit; ++j) {
         double* vj = V + (long)j * n;
         double* vn = V + (long)(j + 1) * n;
-        KCHK(vcycle(H, vj, z, st));
-        KCHK(spmv64(H, z, nullptr, w, false, st));
+        double* zj = Z + (long)j * n;
+        KCHK(vcycle(H, vj, zj, st));
+        KCHK(spmv64(H, zj, nullptr, w, false, st));
         for (int i = 0; i <= j; ++i) {
           double* vi = V + (long)i * n;
           const double hij = KDOT(w, vi);
@@ -965,10 +973,7 @@ smg_status smg_solve(smg_handle H, const double* b, double* x, double rtol, int 
         for (int k = i + 1; k < jdone; ++k) s -= Hm[i * m + k] * y[k];
         y[i] = s / Hm[i * m + i];
       }
-      KCHK(launch_scale(n, y[0], V, t, st));
-      for (int i = 1; i < jdone; ++i) KCHK(launch_axpy(n, y[i], V + (long)i * n, t, st));
-      KCHK(vcycle(H, t, z, st));
-      KCHK(launch_axpy(n, 1.0, z, x, st));
+      for (int i = 0; i < jdone; ++i) KCHK(launch_axpy(n, y[i], Z + (long)i * n, x, st));
       KCHK(spmv64(H, x, b, r, true, st));
       beta = sqrt(KDOT(r, r));
       KCHK(e);

@@ -520,9 +520,36 @@ def test_gmres_lgs_weather_like():
         x = torch.zeros(b.size, dtype=torch.float64, device=DEV)
         res = mg.solve(T(b.ravel()), x, rtol=1e-9, maxit=200, krylov=30)
         assert res["status"] == 0 and res["rel_resid_true"] < 1e-9, (prec, res)
+        assert abs(res["iters"] - itr) <= 1, (prec, res["iters"], itr)
+        if prec == "fp64":
+            assert np.abs(N(x) - xr.ravel()).max() / np.abs(xr).max() < 1e-6
+
+
+def test_fgmres_reduced_precision_cycle_keeps_iterations():
+    """Weather-like operator with the ILU(0) V-cycle: flexible GMRES(30) with
+    the V-cycle in FP32 storage needs as many iterations as with the FP64
+    V-cycle (+-1), which needs the oracle's count (+-1); every run's true FP64
+    residual meets the tolerance and the FP64 run's solution matches the
+    oracle's."""
+    shape = (64, 48, 24)
+    A, b = workloads.weather19(shape, seed=3)
+    b = b.reshape(shape)
+    H = oracle.Hierarchy(shape, 19, A, smoother="ilu0", coarsen="semi_xy")
+    xr, st, itr, relr = H.gmres(b, 1e-9, 200, restart=30)
+    assert st == 0
+    its = {}
+    for prec in ("fp64", "fp32"):
+        mg = smg.StructMG(T(A), shape, pattern=19, smoother="ilu0", coarsen="semi_xy", prec=prec, gmres_restart=30,
+                          device=DEV)
+        x = torch.zeros(b.size, dtype=torch.float64, device=DEV)
+        res = mg.solve(T(b.ravel()), x, rtol=1e-9, maxit=200, krylov=30)
+        assert res["status"] == 0 and res["rel_resid_true"] < 1e-9, (prec, res)
+        its[prec] = res["iters"]
         if prec == "fp64":
             assert abs(res["iters"] - itr) <= 1
             assert np.abs(N(x) - xr.ravel()).max() / np.abs(xr).max() < 1e-6
+        mg.close()
+    assert abs(its["fp32"] - its["fp64"]) <= 1, its
 
 
 # ILU(0) of the finest matrix on a mask other than its pattern (fewer or more
