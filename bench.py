@@ -136,17 +136,39 @@ def vcycle_roofline(smg, torch, dev, A, b, shape, kw, krylov, tol, w=8):
             "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
-def cpu_baseline(name, interp="vertex"):
-    """The oracle (single-threaded C, as committed) on a bounded sample: the
-    same recipe and hierarchy at 1/8 of the unknowns (128^3 for the 256^3
-    workload), full setup + PCG to 1e-9, scaled by the unknown-count ratio."""
+def host_cpu():
+    """CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count()
+    return model, ncpu
+
+
+def cpu_baseline(name, interp="vertex", gpu_iters=None):
+    """The oracle (single-threaded C, as committed) on a bounded sample of the
+    workload: the same recipe at 1/8 of the unknowns (128^3 for the 256^3
+    diffusion, with the inclusion radii halved so that the 32 inclusions
+    cover the same volume fraction), full setup + PCG to 1e-9.  The setup time
+    is scaled by the unknown-count ratio and the solve time by that ratio
+    times the full problem's iteration count over the sample's."""
     import oracle
     import workloads
     if name == "diffusion256":
         shape = (128, 128, 128)
-        A, b = workloads.diffusion7(shape, seed=2, nspheres=4, rmin=4.0, rmax=16.0)
+        A, b = workloads.diffusion7(shape, seed=2, nspheres=32, rmin=4.0, rmax=16.0)
         scale = 8.0
-        sample = "same recipe at 128^3 (4 inclusions, radii 4-16), oracle setup + PCG to 1e-9, x8 unknowns"
+        sample = ("same recipe at 128^3 (32 inclusions, radii 4-16 cells: the inclusion volume fraction of the "
+                  "256^3 input), oracle setup + PCG to 1e-9")
     else:
         shape = (32, 32, 32)
         A, b = workloads.poisson7(32)
@@ -154,11 +176,17 @@ def cpu_baseline(name, interp="vertex"):
         sample = "full workload"
     t0 = time.perf_counter()
     H = oracle.Hierarchy(shape, 7, A, interp=interp)
+    t1 = time.perf_counter()
     x, st, it, rel = H.pcg(b, 1e-9, 200)
-    t = time.perf_counter() - t0
-    info = {"value": round(t * 1e3 * scale, 1), "unit": "ms", "cores": 1, "kind": "oracle",
-            "sample": f"{sample}, {interp} interpolation; measured {t:.1f}s, {it} iterations, "
-                      f"rel resid {rel:.2e}"}
+    t2 = time.perf_counter()
+    full_iters = gpu_iters if gpu_iters else it
+    ms = ((t1 - t0) * scale + (t2 - t1) * scale * full_iters / max(it, 1)) * 1e3
+    model, ncpu = host_cpu()
+    info = {"value": round(ms, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": f"{sample}, {interp} interpolation; measured setup {t1 - t0:.1f}s + solve {t2 - t1:.1f}s "
+                      f"({it} iterations, rel resid {rel:.2e}); value = setup x{scale:g} + solve x{scale:g} x "
+                      f"{full_iters}/{it} iterations",
+            "cpu_model": model, "host_cpus": ncpu}
     return info, dict(shape=shape, A=A, b=b, x=x, desc=sample)
 
 
@@ -194,7 +222,9 @@ def _timed(fn, torch, reps):
     return out, sum(times) / len(times)
 
 
-def _variants(args, smg, torch, np, dev, W, precs, tol, krylov, **kw):
+def _variants(args, smg, torch, np, dev, W, precs, tol, krylov, xref=None, steps=None, **kw):
+    """Time-to-solution (setup + solve, inputs resident) of each V-cycle
+    precision; xref: a reference solution for the relative error."""
     A = torch.from_numpy(W["A"]).to(dev)
     b = torch.from_numpy(W["b"].ravel().copy()).to(dev)
     x = torch.zeros_like(b)
@@ -207,11 +237,14 @@ def _variants(args, smg, torch, np, dev, W, precs, tol, krylov, **kw):
             x.zero_()
             return m.solve(b, x, rtol=tol, maxit=500, krylov=krylov)
 
-        r, ms = _timed(step, torch, args.steps)
+        r, ms = _timed(step, torch, args.steps if steps is None else steps)
         res[prec] = {"ms_per_step": round(ms, 2), "iters": r["iters"], "rel_resid_true": r["rel_resid_true"],
                      "converged": r["status"] == 0 and r["rel_resid_true"] < tol,
                      "t_setup_ms": round(r["t_setup_ms"], 2), "t_solve_ms": round(r["t_solve_ms"], 2),
                      "levels": r["levels"]}
+        if xref is not None:
+            xg = x.cpu().numpy()
+            res[prec]["rel_err_vs_oracle"] = float(np.linalg.norm(xg - xref) / np.linalg.norm(xref))
         print(f"[bench] {prec}: {res[prec]}", file=sys.stderr, flush=True)
         m.close()
         del m
@@ -391,6 +424,109 @@ def extra_batch(args, smg, torch, np, dev):
                       "variants": out}), flush=True)
 
 
+# ---- the other configurations, as sub-objects of the default line ----------
+def run_poisson32(args, smg, torch, np, dev, steps):
+    """3D Poisson 32^3 (the parity configuration, cache resident): FP64, FP32
+    and FP16 V-cycles in FP64 PCG, each solution against the oracle's."""
+    import oracle
+    import workloads
+    shape = (32, 32, 32)
+    A, b = workloads.poisson7(32)
+    H = oracle.Hierarchy(shape, 7, A)
+    xo, st, it, rel = H.pcg(b.reshape(shape), 1e-9, 200)
+    W = dict(shape=shape, A=A, b=b)
+    res = _variants(args, smg, torch, np, dev, W, ("fp64", "fp32", "fp16"), 1e-9, 0, xref=xo.ravel(), steps=steps,
+                    pattern=7)
+    return {"workload": "3D Poisson 32^3, 7-pt, PCG + V(1,1) sym GS, trilinear P, tol 1e-9", "variants": res,
+            "oracle": {"iters": it, "rel_resid_true": rel}}
+
+
+def run_weather(args, smg, torch, np, dev, steps):
+    """Weather-like 512x512x64, 19-point, GMRES(30) with the ILU(0) V-cycle
+    in FP64 and in FP32, and the FP64 V-cycle's algorithmic bandwidth."""
+    import workloads
+    shape = (512, 512, 64)
+    A, b = workloads.weather19(shape, seed=3)
+    W = dict(shape=shape, A=A, b=b)
+    kw = dict(pattern=19, smoother="ilu0", coarsen="semi_xy", gmres_restart=30)
+    res = _variants(args, smg, torch, np, dev, W, ("fp64", "fp32"), 1e-9, 30, steps=steps, **kw)
+    At = torch.from_numpy(A).to(dev)
+    bt = torch.from_numpy(b.ravel().copy()).to(dev)
+    vc = vcycle_roofline(smg, torch, dev, At, bt, shape, kw, 30, 1e-9)
+    return {"workload": "weather-like 512x512x64, 19-pt, vertical 100x, GMRES(30) + ILU(0) V-cycle, xy-semi "
+                        "coarsening, tol 1e-9", "variants": res, "vcycle_fp64": vc}
+
+
+def run_elasticity(args, smg, torch, np, dev, steps):
+    """Elasticity-like 128^3 x 3 (3x3 blocks, 27-point): PCG with FP64, FP32
+    and FP16 (row-scaled) block-GS V-cycles, tol 1e-8."""
+    import workloads
+    n = 128
+    A, b = workloads.elasticity27(n, seed=4)
+    W = dict(shape=(n, n, n), A=A, b=b)
+    res = _variants(args, smg, torch, np, dev, W, ("fp64", "fp32", "fp16"), 1e-8, 0, steps=steps, pattern=27,
+                    block=3)
+    return {"workload": "elasticity-like 128^3 x 3, 27-pt 3x3 blocks, Q1 FEM, log-normal moduli (sigma 1), "
+                        "nu 0.3, PCG + block-GS V-cycle, tol 1e-8", "variants": res}
+
+
+def run_batch(args, smg, torch, np, dev, steps):
+    """256 reservoir-like systems of uneven sizes solved together (FP32 and
+    FP64 V-cycles, FP64 PCG) against the FP64 single-system solver run on
+    one system after another."""
+    import workloads
+    dims = workloads.reservoir_batch(256, seed=5)
+    systems = [workloads.reservoir7(d, seed=1000 + k) for k, d in enumerate(dims)]
+    kw = dict(pattern=7, coarsen="full", semi_levels=3, max_coarse=512)
+    As = [torch.from_numpy(A).to(dev) for A, _ in systems]
+    bs = [torch.from_numpy(b.ravel().copy()).to(dev) for _, b in systems]
+    ncells = sum(int(np.prod(d)) for d in dims)
+    out = {}
+    for prec in ("fp32", "fp64"):
+        B = smg.StructMGBatch(As, dims, prec=prec, **kw)
+        tune = B.tune()
+        xs = [torch.zeros_like(b) for b in bs]
+
+        def solve():
+            for x in xs:
+                x.zero_()
+            return B.solve(bs, xs, rtol=1e-9, maxit=300)
+
+        (st, res), ms = _timed(solve, torch, steps)
+        out[f"batched_{prec}"] = {"ms": round(ms, 2), "systems_per_s": round(256 / (ms * 1e-3), 2),
+                                  "all_converged": st == 0 and all(r["rel_resid_true"] < 1e-9 for r in res),
+                                  "max_iters": max(r["iters"] for r in res),
+                                  "mean_iters": round(float(np.mean([r["iters"] for r in res])), 2),
+                                  "max_rel_resid_true": max(r["rel_resid_true"] for r in res),
+                                  "t_setup_ms": round(res[0]["t_setup_ms"], 1), "schedule": tune}
+        print(f"[bench] C5 batched {prec}: {out[f'batched_{prec}']}", file=sys.stderr, flush=True)
+        B.close()
+        del B
+    hs = [smg.StructMG(A, d, device=dev, prec="fp64", **kw) for A, d in zip(As, dims)]
+    xs = [torch.zeros_like(b) for b in bs]
+
+    def seq():
+        rs = []
+        for m, b, x in zip(hs, bs, xs):
+            x.zero_()
+            rs.append(m.solve(b, x, rtol=1e-9, maxit=300))
+        return rs
+
+    rs, ms = _timed(seq, torch, steps)
+    out["sequential_fp64"] = {"ms": round(ms, 2), "systems_per_s": round(256 / (ms * 1e-3), 2),
+                              "all_converged": all(r["status"] == 0 for r in rs)}
+    for k in ("batched_fp32", "batched_fp64"):
+        out[k]["speedup_vs_sequential_fp64"] = round(out["sequential_fp64"]["ms"] / out[k]["ms"], 2)
+    for m in hs:
+        m.close()
+    return {"workload": f"256 reservoir-like 7-pt systems, dims uniform in [16,96]^3 ({ncells} cells), kz/kx = "
+                        f"0.01, xy-semi x3 then full, tol 1e-9", "unit": "systems/s", "variants": out}
+
+
+CONFIG_RUNNERS = {"C1_poisson32": run_poisson32, "C3_weather512": run_weather, "C4_elasticity128": run_elasticity,
+                  "C5_batch256": run_batch}
+
+
 EXTRA = {"weather512": extra_weather, "weather512_lgs": extra_weather_lgs, "elasticity128": extra_elasticity,
          "reservoir_batch256": extra_batch, "diffusion256_interp": extra_diffusion_interp}
 
@@ -404,6 +540,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 / FP16 V-cycle variants")
     ap.add_argument("--breakdown", action="store_true", help="print per-kernel table to stderr")
+    ap.add_argument("--configs", default="C1,C3,C4,C5",
+                    help="other configurations reported as sub-objects of the default line (comma list of "
+                         "C1,C3,C4,C5, or none)")
     ap.add_argument("--ilu-mask", type=int, default=0, choices=(0, 7, 19, 27),
                     help="weather512: ILU(0) mask of the finest matrix (0: its own 19-point pattern)")
     args = ap.parse_args()
@@ -487,6 +626,16 @@ def main():
     achieved = d_bytes / (d_avg * 1e-3) / 1e9
     kernel_key = f"L{dom[0]}:{dom[1]}"
     traffic = load_traffic(kernel_key)
+    # a Gauss-Seidel / ILU sweep is a chain of dependent hyperplanes
+    # wx*x + wy*y + z = const (weights of the level's pattern): its length and
+    # the time per hyperplane
+    chain = None
+    if dom[1] in ("pre_sweep", "post_sweep", "pre_sweep_u", "post_sweep_u"):
+        S = levels[dom[0]]["S"]
+        wx, wy = {7: (1, 1), 19: (3, 2), 27: (4, 2)}[S]
+        nx_, ny_, nz_ = levels[dom[0]]["dims"]
+        hyper = wx * (nx_ - 1) + wy * (ny_ - 1) + (nz_ - 1) + 1
+        chain = {"hyperplanes": hyper, "us_per_hyperplane": round(d_avg * 1e3 / hyper, 3)}
     ok = all(r["status"] == 0 and r["rel_resid_true"] < 1e-9 for r in results)
     line = {
         "metric": METRIC,
@@ -507,7 +656,7 @@ def main():
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_launch": d_bytes, "avg_launch_ms": round(d_avg, 4),
-                     "launches": d_cnt},
+                     "launches": d_cnt, "dependence_chain": chain},
         "converged": ok,
         "iters": results[-1]["iters"],
         "rel_resid_true": results[-1]["rel_resid_true"],
@@ -579,9 +728,25 @@ def main():
             m2.close()
             del m2
         line["mixed"] = mixed
+    mg.close()
+    del mg, A, b, x
+    torch.cuda.empty_cache()
+    # the other configurations of the metric, each as a sub-object
+    wanted = [c.strip() for c in args.configs.split(",") if c.strip() and c.strip().lower() != "none"]
+    if wanted:
+        line["configs"] = {}
+        for key, fn in CONFIG_RUNNERS.items():
+            if key.split("_")[0] not in wanted:
+                continue
+            ts = time.perf_counter()
+            print(f"[bench] configuration {key}", file=sys.stderr, flush=True)
+            line["configs"][key] = fn(args, smg, torch, np, dev, min(args.steps, 3))
+            line["configs"][key]["bench_wall_s"] = round(time.perf_counter() - ts, 1)
+            print(f"[bench] {key} done in {time.perf_counter() - ts:.1f}s", file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"], sample = cpu_baseline(args.workload, W["interp"])
+        line["cpu_baseline"], sample = cpu_baseline(args.workload, W["interp"], gpu_iters=line["iters"])
         line["oracle_error"] = oracle_errors(smg, torch, np, dev, sample, kw, W["krylov"])
     print(json.dumps(line), flush=True)
 
