@@ -348,17 +348,26 @@ __device__ __forceinline__ void wf_compute(const WfArgs<typename WfVal<E>::V>& a
   const unsigned sdbytes = T::HALF ? (unsigned)NS * WF_NL * 8u : 0u;
   const auto rs = wf_rsrc(T::HALF ? (const char*)a.sd + (size_t)tile * sdbytes : (const char*)a.pk, sdbytes);
 
+  // Positions without a point (z outside [0, nz) or the column outside the
+  // grid) take an offset outside the buffer: their coefficients read as zero
+  // without a memory access, so the copy's padding costs no traffic.
+  const int skew = (WX - q.sh * WY) * lx + WY * ly + wf_kb(PAT);
+  const int xt = q.X * WF_TX + lx, yt = q.Y * WF_TY + ly - q.sh * lx;
+  const unsigned zlim = xt < a.g.nx && yt >= 0 && yt < a.g.ny ? (unsigned)a.g.nz : 0u;
   u32x4 cf[P][NPK];
   u32x2 sdv[P];
   auto prefetch = [&](int k, int j) {
     const int s = wf_step<DIR>(NS, k);
     const bool sin = s >= 0 && s < NS;
     const unsigned so = sin ? (unsigned)s * (NPK * PACKB) : WF_OOB;
+    const bool pt = (unsigned)(s - skew) < zlim;
+    const unsigned vo = pt ? tid * 16u : WF_OOB;
 #pragma unroll
     for (int p = 0; p < NPK; ++p)
-      cf[j][p] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rp, tid * 16u, so + p * PACKB, 0));
+      cf[j][p] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rp, vo, so + p * PACKB, 0));
     if (T::HALF)
-      sdv[j] = __builtin_amdgcn_raw_buffer_load_b64(rs, tid * 8u, sin ? (unsigned)s * (WF_NL * 8u) : WF_OOB, 0);
+      sdv[j] = __builtin_amdgcn_raw_buffer_load_b64(rs, pt ? tid * 8u : WF_OOB,
+                                                    sin ? (unsigned)s * (WF_NL * 8u) : WF_OOB, 0);
   };
 #pragma unroll
   for (int j = 0; j < P; ++j) prefetch(j, j);
