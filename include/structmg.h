@@ -232,7 +232,9 @@ smg_status smg_timing_report(smg_handle h, double* ms, int* counts, int max_leve
  * own hierarchy, built exactly as by smg_setup, and all systems advance in
  * lockstep through preconditioned CG, every step being one launch over all
  * systems; a system stops at its own convergence (per-system tolerance test
- * as in smg_solve).  One lockstep iteration runs as a captured HIP graph.
+ * as in smg_solve).  Four lockstep iterations run as one captured HIP graph,
+ * and the host reads the systems' flags once per graph; a system stops on the
+ * device at its convergence or at maxit.
  * Pointer arrays are host arrays of nsys device pointers.  At most 4095
  * systems. */
 typedef struct smg_batch_s* smg_batch;
@@ -257,14 +259,15 @@ smg_status smg_batch_solve(smg_batch b, const double* const* bv, double* const* 
                            smg_result* results, int* status, void* stream);
 
 /* Sweep schedule: merge order of the systems' tiles (0: system after system,
- * 1: round robin) and persistent grid of the batched sweeps (0: default). */
+ * 1: round robin) and persistent grid of the batched sweeps (workgroups, one
+ * per CU at most: larger values act as 256; 0: 256). */
 smg_status smg_batch_set_schedule(smg_batch b, int order, int grid);
 /* Times batched V-cycles for every (order, grid) candidate and keeps the
  * fastest; returns it and its time per V-cycle (ms).  Overwrites the
  * internal residual vectors (not the caller's). */
 smg_status smg_batch_tune(smg_batch b, void* stream, int* order, int* grid, double* ms_per_vcycle);
-/* Replays a captured graph per lockstep iteration (1, default) or launches
- * the iteration's kernels one by one (0). */
+/* Replays a captured graph of four lockstep iterations (1, default) or
+ * launches the iterations' kernels one by one (0). */
 smg_status smg_batch_set_graph(smg_batch b, int enable);
 int smg_batch_num_systems(smg_batch b);
 /* The hierarchy of system k (owned by the batch; for introspection and the

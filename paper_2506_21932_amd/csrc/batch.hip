@@ -15,8 +15,9 @@
 //    "still iterating" / "convergence claimed" live in device memory; a
 //    finished system is skipped by every later launch.  Dot products are
 //    deterministic: fixed blocks of 2048 elements, then a fixed-order sum.
-//  * One lockstep iteration is captured into a HIP graph once and replayed;
-//    the host reads the flags once per iteration.
+//  * BATCH_K lockstep iterations are captured into one HIP graph once and
+//    replayed; the host reads the flags once per replay, and each system
+//    stops on the device at its convergence or its iteration limit.
 //  * The merge order of the systems' sweep tiles (system after system, or
 //    round robin) and the size of the persistent sweep grid are chosen by
 //    timing whole batched V-cycles (smg_batch_tune).
@@ -100,7 +101,7 @@ enum { S_BN, S_REL0, S_RHO, S_ALPHA, S_REL, S_CLAIM, S_BETA, S_FINAL };
 template <int OP>
 __global__ __launch_bounds__(64) void k_bscal(const SysVec* __restrict__ sv, const double* __restrict__ part,
                                               Scal* __restrict__ sc, int* __restrict__ live, int* __restrict__ claim,
-                                              const double* __restrict__ rtol) {
+                                              const double* __restrict__ prm) {
   const int s = blockIdx.x;
   const bool need = (OP == S_BN || OP == S_REL0 || OP == S_FINAL) ? true
                                                                     : (OP == S_CLAIM ? claim[s] != 0 : live[s] != 0);
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(64) void k_bscal(const SysVec* __restrict__ sv, con
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (threadIdx.x != 0) return;
   Scal& c = sc[s];
-  const double tol = *rtol;
+  const double tol = prm[0];
   switch (OP) {
     case S_BN:
       c.bn = sqrt(acc);
@@ -156,6 +157,9 @@ __global__ __launch_bounds__(64) void k_bscal(const SysVec* __restrict__ sv, con
     case S_BETA:
       c.beta = acc / c.rho;
       c.rho = acc;
+      // the iteration limit: the system stops here, as the single-system
+      // solver's loop does after maxit iterations
+      if (c.iters >= (int)prm[1]) live[s] = 0;
       break;
     case S_FINAL:
       c.rel = sqrt(acc) / c.bn;
@@ -255,7 +259,7 @@ struct smg_batch_s {
   SysVec* sv = nullptr;
   Scal* sc = nullptr;
   int *live = nullptr, *claim = nullptr;
-  double *part = nullptr, *rtol = nullptr;
+  double *part = nullptr, *prm = nullptr;  // prm: {rtol, maxit} of the running solve
   unsigned *ctr = nullptr, *err = nullptr;
   unsigned* vbmap = nullptr;
   unsigned vblocks = 0;
@@ -264,7 +268,8 @@ struct smg_batch_s {
   // sweep schedule (smg_batch_tune)
   int order = 1;
   unsigned grid = WF_MAX_GRID;
-  // graph of one lockstep CG iteration
+  double prm_host[2] = {0.0, 0.0};
+  // graph of BATCH_K lockstep CG iterations
   bool use_graph = true;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -306,7 +311,7 @@ size_t layout(smg_batch_s* B, const std::vector<Shape>& sh, char* base) {
   B->sc = ar.take<Scal>(ns);
   B->live = ar.take<int>(ns);
   B->claim = ar.take<int>(ns);
-  B->rtol = ar.take<double>(1);
+  B->prm = ar.take<double>(2);
   B->ctr = ar.take<unsigned>(2);
   B->err = ar.take<unsigned>(1);
   long vb = 0, sb = 0;
@@ -583,7 +588,7 @@ hipError_t dot(smg_batch_s* B, const int* gate, hipStream_t st) {
 template <int OP>
 hipError_t scal(smg_batch_s* B, hipStream_t st) {
   hipLaunchKernelGGL((k_bscal<OP>), dim3(B->nsys), dim3(64), 0, st, B->sv, B->part, B->sc, B->live, B->claim,
-                     B->rtol);
+                     B->prm);
   return hipGetLastError();
 }
 template <int OP>
@@ -626,11 +631,17 @@ void drop_graph(smg_batch_s* B) {
   B->graph = nullptr;
 }
 
+// Lockstep iterations per graph launch: the host reads the systems' flags
+// once per launch.  A system that converges (or reaches maxit, or breaks
+// down) inside a launch is skipped by the rest of its kernels.
+constexpr int BATCH_K = 4;
+
 hipError_t ensure_graph(smg_batch_s* B) {
   if (B->exec) return hipSuccess;
   hipError_t e = hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
-  hipError_t ei = iteration(B, B->cap);
+  hipError_t ei = hipSuccess;
+  for (int k = 0; k < BATCH_K && ei == hipSuccess; ++k) ei = iteration(B, B->cap);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(B->cap, &g);
   if (ei != hipSuccess) e = ei;
@@ -781,7 +792,8 @@ smg_status smg_batch_tune(smg_batch B, void* stream, int* order_out, int* grid_o
   if (!B) return bfail(nullptr, SMG_EINVAL, "null batch");
   hipStream_t st = (hipStream_t)stream;
   for (int s = 0; s < B->nsys; ++s) BCHK(B, hipMemsetAsync(B->h[s]->kr, 0, sizeof(double) * B->sv_host[s].n, st));
-  const unsigned grids[] = {256, 512, 768, 1024, 1536};
+  // persistent sweep grids (one sweep workgroup fits a CU: at most WF_MAX_GRID)
+  const unsigned grids[] = {128, 192, WF_MAX_GRID};
   hipEvent_t e0, e1;
   BCHK(B, hipEventCreate(&e0));
   BCHK(B, hipEventCreate(&e1));
@@ -839,7 +851,9 @@ smg_status smg_batch_solve(smg_batch B, const double* const* b, double* const* x
   }
   BCHK(B, hipMemcpyAsync(B->sv, B->sv_host.data(), sizeof(SysVec) * ns, hipMemcpyHostToDevice, st));
   BCHK(B, hipMemcpyAsync(B->spmv_res.segs, res.data(), sizeof(SpmvArgs<MatD>) * ns, hipMemcpyHostToDevice, st));
-  BCHK(B, hipMemcpyAsync(B->rtol, &rtol, sizeof(double), hipMemcpyHostToDevice, st));
+  B->prm_host[0] = rtol;
+  B->prm_host[1] = (double)maxit;
+  BCHK(B, hipMemcpyAsync(B->prm, B->prm_host, sizeof B->prm_host, hipMemcpyHostToDevice, st));
   // start: |b|, r = b - A x, first residual, z = M r, p = z, rho = r.z
   BCHK(B, dot<D_BB>(B, nullptr, st));
   BCHK(B, scal<S_BN>(B, st));
@@ -851,18 +865,21 @@ smg_status smg_batch_solve(smg_batch B, const double* const* b, double* const* x
   BCHK(B, dot<D_RZ>(B, B->live, st));
   BCHK(B, scal<S_RHO>(B, st));
   if (B->use_graph) BCHK(B, ensure_graph(B));
+  // BATCH_K iterations per host check of the flags (one graph launch, or
+  // the same launches one by one); every system stops at its own
+  // convergence or at maxit on the device
   std::vector<int> live(ns);
-  int it = 0;
-  for (; it < maxit; ++it) {
+  for (int it = 0; it < maxit; it += BATCH_K) {
     BCHK(B, hipMemcpyAsync(live.data(), B->live, sizeof(int) * ns, hipMemcpyDeviceToHost, st));
     BCHK(B, hipStreamSynchronize(st));
     int nl = 0;
     for (int v : live) nl += v != 0;
     if (nl == 0) break;
-    if (B->use_graph)
+    if (B->use_graph) {
       BCHK(B, hipGraphLaunch(B->exec, st));
-    else
-      BCHK(B, iteration(B, st));
+    } else {
+      for (int k = 0; k < BATCH_K; ++k) BCHK(B, iteration(B, st));
+    }
   }
   // final true residuals
   BCHK(B, spmv(B, B->spmv_res, true, nullptr, st));

@@ -113,6 +113,12 @@ def test_batch_graph_and_restart():
     st, res = B.solve(bs, xs, rtol=1e-9, maxit=2)
     assert st == smg.SMG_ENOTCONV
     assert all(r["status"] == smg.SMG_ENOTCONV and r["iters"] == 2 for r in res)
+    # a limit that is not a multiple of the iterations per graph launch stops
+    # every system on the device at exactly that count
+    xs = [torch.zeros_like(b) for b in bs]
+    st, res = B.solve(bs, xs, rtol=1e-9, maxit=5)
+    assert st == smg.SMG_ENOTCONV
+    assert all(r["status"] == smg.SMG_ENOTCONV and r["iters"] == 5 for r in res)
 
 
 def test_batch_tune_keeps_results():
