@@ -53,7 +53,7 @@ typedef enum {
 } smg_status;
 
 typedef enum { SMG_SMOOTH_GS = 0, SMG_SMOOTH_ILU0 = 1, SMG_SMOOTH_LGS = 2 } smg_smoother;
-typedef enum { SMG_COARSEN_FULL = 0, SMG_COARSEN_SEMI_XY = 1 } smg_coarsen;
+typedef enum { SMG_COARSEN_FULL = 0, SMG_COARSEN_SEMI_XY = 1, SMG_COARSEN_AUTO = 2 } smg_coarsen;
 typedef enum { SMG_FP64 = 0, SMG_FP32 = 1, SMG_FP16_ROWSCALE = 2 } smg_prec;
 typedef enum {
   SMG_INTERP_VERTEX = 0,
@@ -71,7 +71,15 @@ typedef struct {
                           symmetric line GS over z-columns (Sec. 4.4: column right-hand
                           side from the neighbouring columns, Thomas solve per column;
                           scalar systems, FP64 or FP32, nz <= 2047) */
-  int coarsen;         /* smg_coarsen: coarsen x,y,z (full) or only x,y (semi) */
+  int coarsen;         /* smg_coarsen: coarsen x,y,z (full), only x,y (semi), or x,y while
+                          the level's z coupling stays weak (auto, Sec. 4.1 P2 fixed-stride
+                          coarsening chosen per level): with rho the ratio of the finest
+                          matrix's summed |z-face couplings| to the mean of its summed
+                          |x-face| and |y-face| couplings, level l coarsens x,y only while
+                          rho * 4^l < 1/4 (x,y coarsening by 2 scales the relative z
+                          coupling by 4), then x,y,z; scalar systems.  smg_workspace_size
+                          then returns the largest size over the possible choices, and
+                          smg_resetup keeps the coarsening chosen at setup */
   int semi_levels;     /* with SMG_COARSEN_FULL: the first semi_levels levels coarsen x,y only */
   int prec;            /* smg_prec of the V-cycle matrices and vectors; the outer
                           Krylov method, its operator, dot products, true residuals
@@ -99,12 +107,34 @@ typedef struct {
                           it is not aligned with, R = P^T, 27-point coarse levels.
                           Cell-centred and operator-dependent transfers take scalar
                           systems. */
+  /* Smoothing settings (Sec. 4.4 GS / ILU formulas; settings table: ZeroGuess,
+   * relax weight 1.0).  Zero in any of these fields selects the default. */
+  int pre_sweeps;      /* smoothing steps before the coarse correction, 1..8 (0: 1); GS
+                          directions alternate forward, backward, ... */
+  int post_sweeps;     /* after it, 1..8 (0: 1); GS directions alternate starting opposite
+                          to the last pre-sweep, so pre_sweeps == post_sweeps gives a
+                          symmetric V-cycle */
+  double relax_weight; /* weight w of the point GS sweeps, 0 < w < 2 (0: 1.0):
+                          u += w (D + w L)^-1 (b - A u) forward, (D + w U)^-1 backward.
+                          Computed as a GS sweep with diagonal factor w / a_ii on the
+                          right-hand side b + ((1 - w) / w) a_ii u_old (the same update in
+                          exact arithmetic).  Point GS only (scalar systems); ILU(0) has
+                          no weight, line GS and 3x3 blocks take w = 1 */
+  int zero_guess;      /* 0 or 1 (default): the first pre-smoothing step starts from u = 0
+                          and reads only the lower triangle and diagonal (ZeroGuess);
+                          -1: that step applies the full stencil to u = 0 (same values up
+                          to the sign of zero, more traffic) */
+  int min_coarse;      /* an axis of n points is coarsened while n >= 2 * min_coarse,
+                          2..4096 (0: 4) */
 } smg_config;
 
 typedef struct {
   int iters;               /* preconditioner applications in the Krylov loop */
   int levels;              /* multigrid levels */
   double rel_resid_true;   /* ||b - A x||_2 / ||b||_2 recomputed in FP64 at the end */
+  double rel_resid_recur;  /* the Krylov method's own residual estimate at exit, over ||b||_2:
+                              the recursively updated PCG residual, or |g_{j+1}| of the last
+                              GMRES step (batched solves: the recursive PCG residual) */
   double grid_complexity;  /* sum n_l / n_0          (Sec. 2, complexity equation) */
   double op_complexity;    /* sum S_l n_l / (S_0 n_0): stored structured entries */
   double t_setup_ms;
@@ -198,7 +228,9 @@ int smg_rap_chain_count(int pattern, int cmask);
  * size (times block).  Output arrays must not overlap inputs. */
 smg_status smg_op_spmv(smg_handle h, int level, const void* x, void* y, void* stream);          /* y = A_l x */
 smg_status smg_op_spmv_fp64(smg_handle h, const double* x, double* y, void* stream);           /* finest, FP64 */
-/* u = S_pre(f): forward GS or line GS sweep from u = 0, or the ILU(0) solve. */
+/* One smoothing step with the handle's weight, whatever pre_sweeps and
+ * post_sweeps hold.
+ * u = S_pre(f): forward GS or line GS sweep from u = 0, or the ILU(0) solve. */
 smg_status smg_op_presmooth(smg_handle h, int level, const void* f, void* u, void* stream);
 /* u_out = S_post(f, u_in + P e_c): backward GS or line GS sweep, or the
  * ILU(0) correction, after prolongation of the coarse correction e_c (level

@@ -57,6 +57,7 @@ def _declare(L):
         getattr(L, "orc_spmv" + sfx).argtypes = [_i, _i, _i, _i, _ip, p, p, p]
         getattr(L, "orc_residual" + sfx).argtypes = [_i, _i, _i, _i, _ip, p, p, p, p]
         getattr(L, "orc_gs_sweep" + sfx).argtypes = [_i, _i, _i, _i, _ip, p, p, p, p, _i, _i]
+        getattr(L, "orc_gs_sweep_w" + sfx).argtypes = [_i, _i, _i, _i, _ip, p, p, C.c_void_p, p, p, _i, _i]
         getattr(L, "orc_tri_solve" + sfx).argtypes = [_i, _i, _i, _i, _ip, p, C.c_void_p, p, p, _i]
         getattr(L, "orc_restrict" + sfx).argtypes = [_i, _i, _i, _i, _i, p, p]
         getattr(L, "orc_prolong_add" + sfx).argtypes = [_i, _i, _i, _i, _i, p, p]
@@ -103,6 +104,10 @@ def _declare(L):
     L.orc_f16_to_f32.restype = C.c_float
     L.orc_mg_create.argtypes = [_i, _i, _i, _i, _i, _dp, _i, _i, _i, _i, _i, _i, _i]
     L.orc_mg_create.restype = C.c_void_p
+    L.orc_mg_create_ex.argtypes = [_i, _i, _i, _i, _i, _dp, _i, _i, _i, _i, _i, _i, _i, _i, _i, C.c_double, _i, _i]
+    L.orc_mg_create_ex.restype = C.c_void_p
+    L.orc_auto_semi_levels.argtypes = [_i, _i, _i, _i, _ip, _dp]
+    L.orc_auto_semi_levels.restype = _i
     L.orc_mg_destroy.argtypes = [C.c_void_p]
     L.orc_mg_nlev.argtypes = [C.c_void_p]
     L.orc_mg_nlev.restype = _i
@@ -160,6 +165,23 @@ def gs_sweep(off, A, rd, b, u, direction, zero_guess):
     getattr(lib(), "orc_gs_sweep" + _sfx(b))(nx, ny, nz, off.shape[0], off.ravel(), _c(A).ravel(), _c(rd).ravel(),
                                             _c(b).ravel(), u.ravel(), int(direction), int(zero_guess))
     return u
+
+
+def gs_sweep_w(off, A, rd, qa, b, u, direction, zero_guess):
+    """Weighted GS sweep: rd = w / a_ii, qa = ((1 - w) / w) a_ii (None: w = 1); returns u."""
+    off = _c(off, np.int32)
+    nx, ny, nz = _dims(b.shape)
+    u = _c(u).copy()
+    qp = None if qa is None else _c(qa, b.dtype).ravel().ctypes.data_as(C.c_void_p)
+    getattr(lib(), "orc_gs_sweep_w" + _sfx(b))(nx, ny, nz, off.shape[0], off.ravel(), _c(A).ravel(), _c(rd).ravel(),
+                                              qp, _c(b).ravel(), u.ravel(), int(direction), int(zero_guess))
+    return u
+
+
+def auto_semi_levels(off, A, shape):
+    """x,y-only levels of the automatic coarsening for the (S, N) matrix A."""
+    off = _c(off, np.int32)
+    return lib().orc_auto_semi_levels(*(int(v) for v in shape), off.shape[0], off.ravel(), _c(A, np.float64).ravel())
 
 
 def lgs_sweep(off, A, rden, cp, b, u, direction, zero_guess):
@@ -427,13 +449,16 @@ class Hierarchy:
     """Oracle multigrid hierarchy built from the finest matrix (FP64 setup)."""
 
     def __init__(self, shape, pattern_pts, A0, block=1, smoother="gs", coarsen="full", semi_levels=0,
-                 prec="fp64", max_coarse=8192, ilu_mask=0, interp="vertex"):
+                 prec="fp64", max_coarse=8192, ilu_mask=0, interp="vertex", pre_sweeps=1, post_sweeps=1,
+                 relax_weight=1.0, zero_guess=True, min_coarse=4):
         self.shape = tuple(int(v) for v in shape)
         self.bs = int(block)
         self._A0 = _c(A0, np.float64)
-        h = lib().orc_mg_create(*self.shape, int(pattern_pts), self.bs, self._A0.ravel(),
-                                SMOOTHER[smoother], 1 if coarsen == "semi_xy" else 0, int(semi_levels),
-                                PREC[prec], int(max_coarse), int(ilu_mask), INTERP[interp])
+        mode = {"full": 0, "semi_xy": 1, "auto": 2}[coarsen]
+        h = lib().orc_mg_create_ex(*self.shape, int(pattern_pts), self.bs, self._A0.ravel(),
+                                   SMOOTHER[smoother], mode, int(semi_levels), PREC[prec], int(max_coarse),
+                                   int(ilu_mask), INTERP[interp], int(pre_sweeps), int(post_sweeps),
+                                   float(relax_weight), int(bool(zero_guess)), int(min_coarse))
         if not h:
             raise ValueError("oracle hierarchy setup failed")
         self.h = C.c_void_p(h)

@@ -787,6 +787,8 @@ typedef struct {
   double *A, *rd, *L, *U, *rU;           /* FP64 level data */
   double *tr, *tc;                       /* Thomas factors rden, cp (line GS) */
   double* W;                             /* operator-dependent interpolation weights (8 x N) */
+  double* qa;                            /* weighted GS: ((1 - w) / w) a_ii (NULL for w = 1) */
+  float* qa32;
   float* W32;
   float *A32, *rd32, *L32, *U32, *rU32;  /* truncated level data */
   float *tr32, *tc32;
@@ -796,6 +798,8 @@ typedef struct {
 
 typedef struct {
   int nlev, bs, smoother, prec, cell;
+  int npre, npost, zero_guess; /* smoothing steps per level; ZeroGuess on the first */
+  double w;                    /* GS weight */
   olev lev[48];
   int nc;
   double *LU, *cw;
@@ -805,19 +809,49 @@ typedef struct {
 } omg;
 
 /* Axes coarsened to go from level `lev` with dims n[] to the next level:
- * every allowed axis whose size is at least 8 (coarse size >= 4).  Allowed
- * axes are x and y on the first `semi_levels` levels (or always, for the
- * semi mode), all three otherwise.  A level of the first `semi_levels` whose
- * x and y can no longer be coarsened takes all three axes instead (the
- * switch to full coarsening comes early rather than the hierarchy ending). */
-static int orc_next_cmask(int lev, const int* n, int semi_mode, int semi_levels) {
+ * every allowed axis whose size is at least nmin = 2 * min_coarse (8 by
+ * default: coarse size >= 4).  Allowed axes are x and y on the first
+ * `semi_levels` levels (or always, for the semi mode), all three otherwise.
+ * A level of the first `semi_levels` whose x and y can no longer be coarsened
+ * takes all three axes instead (the switch to full coarsening comes early
+ * rather than the hierarchy ending). */
+static int orc_next_cmask(int lev, const int* n, int semi_mode, int semi_levels, int nmin) {
   int allowed = (semi_mode || lev < semi_levels) ? 3 : 7, m = 0;
   for (int a = 0; a < 3; ++a)
-    if (((allowed >> a) & 1) && n[a] >= 8) m |= 1 << a;
+    if (((allowed >> a) & 1) && n[a] >= nmin) m |= 1 << a;
   if (m == 0 && !semi_mode && allowed == 3)
     for (int a = 0; a < 3; ++a)
-      if (n[a] >= 8) m |= 1 << a;
+      if (n[a] >= nmin) m |= 1 << a;
   return m;
+}
+
+/* Automatic choice of the x,y-only levels (fixed-stride coarsening per
+ * level, Sec. 4.1 P2): rho = (sum over points of |a| of the two z-face
+ * couplings) / (mean of the same sums along x and along y), in-grid
+ * neighbours only.  Coarsening x and y by 2 makes the z coupling of the next
+ * level relatively 4 times stronger, so level l coarsens x,y only while
+ * rho * 4^l < 1/4. */
+int orc_auto_semi_levels(int nx, int ny, int nz, int S, const int* off, const double* A) {
+  long N = (long)nx * ny * nz;
+  double sum[3] = {0.0, 0.0, 0.0};
+  for (int s = 0; s < S; ++s) {
+    int d[3] = {off[3 * s], off[3 * s + 1], off[3 * s + 2]};
+    int axis = -1;
+    for (int a = 0; a < 3; ++a)
+      if (abs(d[a]) == 1 && d[(a + 1) % 3] == 0 && d[(a + 2) % 3] == 0) axis = a;
+    if (axis < 0) continue;
+    for (long i = 0; i < N; ++i) {
+      int X = (int)(i / ((long)ny * nz)), Y = (int)((i / nz) % ny), Z = (int)(i % nz);
+      int a = X + d[0], b = Y + d[1], c = Z + d[2];
+      if (a < 0 || a >= nx || b < 0 || b >= ny || c < 0 || c >= nz) continue;
+      sum[axis] += fabs(A[(long)s * N + i]);
+    }
+  }
+  double sxy = 0.5 * (sum[0] + sum[1]);
+  int lev = 0;
+  if (sxy > 0.0)
+    for (double r = sum[2] / sxy; lev < 40 && r < 0.25; r *= 4.0) ++lev;
+  return lev;
 }
 
 static float* to_f32(const double* a, long n) {
@@ -865,19 +899,33 @@ void orc_mg_destroy(omg* mg);
  * Cell_3d8 restriction with cell-centred trilinear interpolation (3d64c),
  * coarse levels 27-point; cell = 3: operator-dependent vertex interpolation
  * (orc_od_weights) with R = P^T, coarse levels 27-point.  A0 is copied;
- * out-of-grid couplings are zeroed.
+ * out-of-grid couplings are zeroed.  semi_mode: 0 = full coarsening after
+ * semi_levels x,y-only levels, 1 = x,y only, 2 = the automatic choice of
+ * orc_auto_semi_levels.  npre / npost: smoothing steps before / after the
+ * coarse correction (GS directions alternate, post-steps starting opposite
+ * to the last pre-step); w: GS weight (point GS, scalar systems);
+ * zero_guess: the first pre-step uses ZeroGuess (else it runs on u = 0 in
+ * full); an axis of n points is coarsened while n >= 2 * min_coarse.
  * Returns NULL on error (zero pivot, coarsest level too large).
  */
-omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0, int smoother, int semi_mode,
-                   int semi_levels, int prec, int max_coarse, int ilu_mask, int cell) {
+omg* orc_mg_create_ex(int nx, int ny, int nz, int pattern, int bs, const double* A0, int smoother, int semi_mode,
+                      int semi_levels, int prec, int max_coarse, int ilu_mask, int cell, int npre, int npost,
+                      double w, int zero_guess, int min_coarse) {
   if (smoother == 2 && (bs != 1 || prec == 2)) return NULL;
   if (ilu_mask != 0 && (smoother != 1 || (ilu_mask != 7 && ilu_mask != 19 && ilu_mask != 27))) return NULL;
   if (cell == 3 && bs != 1) return NULL;
+  if (npre < 1 || npost < 1 || !(w > 0.0 && w < 2.0) || min_coarse < 2) return NULL;
+  if (w != 1.0 && (smoother != 0 || bs != 1)) return NULL;
+  if (semi_mode == 2 && bs != 1) return NULL;
   omg* mg = (omg*)calloc(1, sizeof(omg));
   mg->bs = bs;
   mg->cell = cell;
   mg->smoother = smoother;
   mg->prec = prec;
+  mg->npre = npre;
+  mg->npost = npost;
+  mg->w = w;
+  mg->zero_guess = zero_guess;
   int be = bs * bs, l = 0;
   int n[3] = {nx, ny, nz};
   for (;;) {
@@ -918,7 +966,11 @@ omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0
     v->d = (double*)calloc(n[2], sizeof(double));
     v->d32 = (float*)calloc(n[2], sizeof(float));
     mg->nlev = l + 1;
-    v->cmask = orc_next_cmask(l, n, semi_mode, semi_levels);
+    if (l == 0 && semi_mode == 2) {
+      semi_levels = orc_auto_semi_levels(nx, ny, nz, v->S, v->off, v->A);
+      semi_mode = 0;
+    }
+    v->cmask = orc_next_cmask(l, n, semi_mode, semi_levels, 2 * min_coarse);
     if (v->cmask == 0 || l == 47) {
       v->cmask = 0;
       break;
@@ -943,7 +995,12 @@ omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0
       if (orc_block_dinv(v->nx, v->ny, v->nz, v->S, v->off, v->A, v->rd)) { orc_mg_destroy(mg); return NULL; }
     } else {
       v->rd = (double*)malloc(sizeof(double) * v->N);
-      for (long i = 0; i < v->N; ++i) v->rd[i] = 1.0 / v->A[c * v->N + i];
+      for (long i = 0; i < v->N; ++i) v->rd[i] = w / v->A[c * v->N + i];
+      if (w != 1.0) {
+        double q = (1.0 - w) / w;
+        v->qa = (double*)malloc(sizeof(double) * v->N);
+        for (long i = 0; i < v->N; ++i) v->qa[i] = q * v->A[c * v->N + i];
+      }
       if (smoother == 1) {
         v->Sm = ilu_mask && l == 0 ? orc_pattern(ilu_mask, v->offm) : orc_pattern(v->S, v->offm);
         v->L = (double*)malloc(sizeof(double) * v->Sm * v->N);
@@ -974,6 +1031,7 @@ omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0
         v->tc32 = to_f32(v->tc, v->N);
       }
       if (cell == 3) v->W32 = to_f32(v->W, 8 * v->N);
+      if (v->qa) v->qa32 = to_f32(v->qa, v->N);
     }
   }
   /* coarsest: dense FP64 LU */
@@ -997,10 +1055,17 @@ omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0
   return mg;
 }
 
+omg* orc_mg_create(int nx, int ny, int nz, int pattern, int bs, const double* A0, int smoother, int semi_mode,
+                   int semi_levels, int prec, int max_coarse, int ilu_mask, int cell) {
+  return orc_mg_create_ex(nx, ny, nz, pattern, bs, A0, smoother, semi_mode, semi_levels, prec, max_coarse, ilu_mask,
+                          cell, 1, 1, 1.0, 1, 4);
+}
+
 void orc_mg_destroy(omg* mg) {
   if (!mg) return;
   for (int l = 0; l < mg->nlev; ++l) {
     olev* v = &mg->lev[l];
+    free(v->qa); free(v->qa32);
     free(v->A); free(v->rd); free(v->L); free(v->U); free(v->rU);
     free(v->A32); free(v->rd32); free(v->L32); free(v->U32); free(v->rU32);
     free(v->tr); free(v->tc); free(v->tr32); free(v->tc32); free(v->W); free(v->W32);
@@ -1054,6 +1119,7 @@ void orc_mg_level_data(const omg* mg, int l, int what, void* out) {
 #define FTC tc
 #define FD d
 #define FPW W
+#define FQA qa
 #define REAL double
 #define SFX _f64
 #include "oracle_vcycle.inc"
@@ -1072,6 +1138,7 @@ void orc_mg_level_data(const omg* mg, int l, int what, void* out) {
 #undef FTC
 #undef FD
 #undef FPW
+#undef FQA
 
 #define FF f32
 #define FU_ u32
@@ -1086,6 +1153,7 @@ void orc_mg_level_data(const omg* mg, int l, int what, void* out) {
 #define FTC tc32
 #define FD d32
 #define FPW W32
+#define FQA qa32
 #define REAL float
 #define SFX _f32
 #include "oracle_vcycle.inc"

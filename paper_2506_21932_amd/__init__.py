@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "SMG_OK", 1: "SMG_ENOTCONV", -1: "SMG_EINVAL", -2: "SMG_ENOME
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2}
 SMOOTHER = {"gs": 0, "ilu0": 1, "lgs": 2}
 INTERP = {"vertex": 0, "cell": 1, "cell_trilinear": 2, "operator": 3}
-COARSEN = {"full": 0, "semi_xy": 1}
+COARSEN = {"full": 0, "semi_xy": 1, "auto": 2}
 
 
 class SmgError(RuntimeError):
@@ -30,12 +30,14 @@ class SmgError(RuntimeError):
 class Config(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("block", C.c_int), ("pattern", C.c_int),
                 ("smoother", C.c_int), ("coarsen", C.c_int), ("semi_levels", C.c_int), ("prec", C.c_int),
-                ("max_coarse", C.c_int), ("gmres_restart", C.c_int), ("ilu_mask", C.c_int), ("interp", C.c_int)]
+                ("max_coarse", C.c_int), ("gmres_restart", C.c_int), ("ilu_mask", C.c_int), ("interp", C.c_int),
+                ("pre_sweeps", C.c_int), ("post_sweeps", C.c_int), ("relax_weight", C.c_double),
+                ("zero_guess", C.c_int), ("min_coarse", C.c_int)]
 
 
 class Result(C.Structure):
     _fields_ = [("iters", C.c_int), ("levels", C.c_int), ("rel_resid_true", C.c_double),
-                ("grid_complexity", C.c_double), ("op_complexity", C.c_double), ("t_setup_ms", C.c_double),
+                ("rel_resid_recur", C.c_double), ("grid_complexity", C.c_double), ("op_complexity", C.c_double), ("t_setup_ms", C.c_double),
                 ("t_solve_ms", C.c_double)]
 
 
@@ -114,10 +116,14 @@ def rap_chain_count(pattern, cmask):
 
 
 def make_config(shape, pattern=7, block=1, smoother="gs", coarsen="full", semi_levels=0, prec="fp64",
-                max_coarse=0, gmres_restart=0, ilu_mask=0, interp="vertex"):
+                max_coarse=0, gmres_restart=0, ilu_mask=0, interp="vertex", pre_sweeps=0, post_sweeps=0,
+                relax_weight=0.0, zero_guess=0, min_coarse=0):
+    """smg_config; zero smoothing fields select the defaults (one step before and
+    after the coarse correction, weight 1, ZeroGuess, min_coarse 4)."""
     nx, ny, nz = (int(v) for v in shape)
     return Config(nx, ny, nz, int(block), int(pattern), SMOOTHER[smoother], COARSEN[coarsen], int(semi_levels),
-                  PREC[prec], int(max_coarse), int(gmres_restart), int(ilu_mask), INTERP[interp])
+                  PREC[prec], int(max_coarse), int(gmres_restart), int(ilu_mask), INTERP[interp], int(pre_sweeps),
+                  int(post_sweeps), float(relax_weight), int(zero_guess), int(min_coarse))
 
 
 def _ptr(t):
@@ -133,12 +139,13 @@ class StructMG:
     """Owns a libstructmg handle and its workspace (a torch uint8 tensor)."""
 
     def __init__(self, coeffs, shape, pattern=7, block=1, smoother="gs", coarsen="full", semi_levels=0, prec="fp64",
-                 max_coarse=0, gmres_restart=0, device="cuda", workspace=None, ilu_mask=0, interp="vertex"):
+                 max_coarse=0, gmres_restart=0, device="cuda", workspace=None, ilu_mask=0, interp="vertex",
+                 pre_sweeps=0, post_sweeps=0, relax_weight=0.0, zero_guess=0, min_coarse=0):
         import torch
         L = load()
         self.L = L
         self.cfg = make_config(shape, pattern, block, smoother, coarsen, semi_levels, prec, max_coarse, gmres_restart,
-                               ilu_mask, interp)
+                               ilu_mask, interp, pre_sweeps, post_sweeps, relax_weight, zero_guess, min_coarse)
         self.block = int(block)
         self.prec = prec
         nbytes = C.c_size_t(0)
@@ -193,6 +200,7 @@ class StructMG:
         if st not in (SMG_OK, SMG_ENOTCONV):
             self._check(st, self.h)
         return {"status": st, "iters": res.iters, "levels": res.levels, "rel_resid_true": res.rel_resid_true,
+                "rel_resid_recur": res.rel_resid_recur,
                 "grid_complexity": res.grid_complexity, "op_complexity": res.op_complexity,
                 "t_setup_ms": res.t_setup_ms, "t_solve_ms": res.t_solve_ms}
 
@@ -319,7 +327,8 @@ class StructMGBatch:
         if st not in (SMG_OK, SMG_ENOTCONV, SMG_EBREAKDOWN):
             self._check(st, self.b)
         return st, [{"status": stt[k], "iters": res[k].iters, "levels": res[k].levels,
-                     "rel_resid_true": res[k].rel_resid_true, "t_setup_ms": res[k].t_setup_ms,
+                     "rel_resid_true": res[k].rel_resid_true, "rel_resid_recur": res[k].rel_resid_recur,
+                     "t_setup_ms": res[k].t_setup_ms,
                      "t_solve_ms": res[k].t_solve_ms} for k in range(self.n)]
 
     def set_schedule(self, order, grid=0):

@@ -58,6 +58,7 @@ struct SysVec {
 
 struct Scal {
   double bn, rho, alpha, beta, rel;
+  double recur;  // recursively updated residual norm / ||b|| of the last iteration
   int iters, status;
 };
 
@@ -120,6 +121,7 @@ __global__ __launch_bounds__(64) void k_bscal(const SysVec* __restrict__ sv, con
       break;
     case S_REL0:
       c.rel = sqrt(acc) / c.bn;
+      c.recur = c.rel;
       c.iters = 0;
       claim[s] = 0;
       if (c.rel < tol) {
@@ -144,6 +146,7 @@ __global__ __launch_bounds__(64) void k_bscal(const SysVec* __restrict__ sv, con
     case S_REL:
       c.iters += 1;
       c.rel = sqrt(acc) / c.bn;
+      c.recur = c.rel;
       claim[s] = c.rel < tol ? 1 : 0;
       break;
     case S_CLAIM:
@@ -671,6 +674,10 @@ smg_status smg_batch_workspace_size(int nsys, const smg_config* cfgs, size_t* by
     if (c.block != 1 || c.smoother != SMG_SMOOTH_GS || c.interp != SMG_INTERP_VERTEX)
       return bfail(nullptr, SMG_EINVAL,
                    "system %d: batches take scalar systems, the GS smoother and vertex-centred transfers", s);
+    if (!cfg_default_smoothing(c) || c.coarsen == SMG_COARSEN_AUTO)
+      return bfail(nullptr, SMG_EINVAL,
+                   "system %d: batches take one ZeroGuess GS step before and after the coarse correction "
+                   "(weight 1) and a fixed coarsening", s);
     if (c.prec != cfgs[0].prec || c.pattern != cfgs[0].pattern)
       return bfail(nullptr, SMG_EINVAL, "system %d: every system of a batch has the same pattern and precision", s);
     sh[s].lev.resize(MAXLEV);
@@ -904,6 +911,7 @@ smg_status smg_batch_solve(smg_batch B, const double* const* b, double* const* x
       r.iters = sc[s].iters;
       r.levels = H->nlev;
       r.rel_resid_true = sc[s].rel;
+      r.rel_resid_recur = sc[s].recur;
       double sn = 0, so = 0;
       for (int l = 0; l < H->nlev; ++l) {
         sn += (double)H->lev[l].N;

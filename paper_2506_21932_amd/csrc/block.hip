@@ -61,12 +61,13 @@ hipError_t launch_bspmv(const Grid& g, const M& m, const typename M::V* x, const
   return hipGetLastError();
 }
 
-// h = f - sum over lower neighbour blocks of A_ij u_j (old values): the
-// terms a backward sweep takes from before the sweep, in the order the
-// sequential sweep applies them (first group of the row update).
-template <class M>
-__global__ __launch_bounds__(256) void k_blower(Grid g, M m, const typename M::V* __restrict__ f,
-                                                const typename M::V* __restrict__ u, typename M::V* __restrict__ h) {
+// h = f - sum over lower (UP = false) or upper (UP = true) neighbour blocks
+// of A_ij u_j (old values): the terms a backward or forward sweep takes from
+// before the sweep, in the order the sequential sweep applies them (first
+// group of the row update).
+template <class M, bool UP>
+__global__ __launch_bounds__(256) void k_btri(Grid g, M m, const typename M::V* __restrict__ f,
+                                              const typename M::V* __restrict__ u, typename M::V* __restrict__ h) {
   using V = typename M::V;
   const long N = g.N();
   const long i = (long)blockIdx.x * 256 + threadIdx.x;
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(256) void k_blower(Grid g, M m, const typename M::V
   for (int r = 0; r < 3; ++r) {
     V t = f[i * 3 + r];
 #pragma unroll
-    for (int s = 0; s < 13; ++s) {
+    for (int s = UP ? 14 : 0; s < (UP ? 27 : 13); ++s) {
       const int dx = pat_off(27, s, 0), dy = pat_off(27, s, 1), dz = pat_off(27, s, 2);
       if (!in_grid(g, X + dx, Y + dy, Z + dz)) continue;
       const long j = i + dx * nyz + dy * g.nz + dz;
@@ -91,13 +92,21 @@ __global__ __launch_bounds__(256) void k_blower(Grid g, M m, const typename M::V
 template <class M>
 hipError_t launch_blower(const Grid& g, const M& m, const typename M::V* f, const typename M::V* u,
                          typename M::V* h, hipStream_t st) {
-  hipLaunchKernelGGL((k_blower<M>), dim3((unsigned)((g.N() + 255) / 256)), dim3(256), 0, st, g, m, f, u, h);
+  hipLaunchKernelGGL((k_btri<M, false>), dim3((unsigned)((g.N() + 255) / 256)), dim3(256), 0, st, g, m, f, u, h);
+  return hipGetLastError();
+}
+
+template <class M>
+hipError_t launch_bupper(const Grid& g, const M& m, const typename M::V* f, const typename M::V* u,
+                         typename M::V* h, hipStream_t st) {
+  hipLaunchKernelGGL((k_btri<M, true>), dim3((unsigned)((g.N() + 255) / 256)), dim3(256), 0, st, g, m, f, u, h);
   return hipGetLastError();
 }
 
 #define SMG_BINST(M)                                                                                           \
   template hipError_t launch_bspmv<M>(const Grid&, const M&, const M::V*, const M::V*, M::V*, bool, hipStream_t); \
-  template hipError_t launch_blower<M>(const Grid&, const M&, const M::V*, const M::V*, M::V*, hipStream_t);
+  template hipError_t launch_blower<M>(const Grid&, const M&, const M::V*, const M::V*, M::V*, hipStream_t); \
+  template hipError_t launch_bupper<M>(const Grid&, const M&, const M::V*, const M::V*, M::V*, hipStream_t);
 SMG_BINST(BMatD)
 SMG_BINST(BMatF)
 SMG_BINST(BMatH)

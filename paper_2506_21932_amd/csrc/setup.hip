@@ -50,19 +50,76 @@ hipError_t launch_copy_masked(int pat, const Grid& g, int be, const double* src,
 }
 
 // rd_i = 1 / a_ii (IEEE division); a zero diagonal raises err bit 1.
-__global__ __launch_bounds__(256) void k_recip_diag(long N, const double* __restrict__ ac, double* __restrict__ rd,
-                                                    unsigned* err) {
+__global__ __launch_bounds__(256) void k_recip_diag(long N, const double* __restrict__ ac, double w,
+                                                    double* __restrict__ rd, unsigned* err) {
   const long i = (long)blockIdx.x * 256 + threadIdx.x;
   if (i >= N) return;
   const double a = ac[i];
   if (a == 0.0) atomicOr(err, 2u);
-  rd[i] = 1.0 / a;
+  rd[i] = w / a;
 }
 
-hipError_t launch_recip_diag(int pat, const Grid& g, const double* A, double* rd, unsigned* err, hipStream_t st) {
+hipError_t launch_recip_diag(int pat, const Grid& g, const double* A, double w, double* rd, unsigned* err,
+                             hipStream_t st) {
   const long N = g.N();
   hipLaunchKernelGGL(k_recip_diag, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, A + (long)(pat / 2) * N,
-                     rd, err);
+                     w, rd, err);
+  return hipGetLastError();
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_centre_scaled(long N, const double* __restrict__ ac, double q,
+                                                       V* __restrict__ qa) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < N) qa[i] = (V)(q * ac[i]);
+}
+
+template <class V>
+hipError_t launch_centre_scaled(int pat, const Grid& g, const double* A, double q, V* qa, hipStream_t st) {
+  const long N = g.N();
+  hipLaunchKernelGGL((k_centre_scaled<V>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N,
+                     A + (long)(pat / 2) * N, q, qa);
+  return hipGetLastError();
+}
+template hipError_t launch_centre_scaled<double>(int, const Grid&, const double*, double, double*, hipStream_t);
+template hipError_t launch_centre_scaled<float>(int, const Grid&, const double*, double, float*, hipStream_t);
+
+// Coupling strength per axis: sums of |a| over the two face offsets of x, y
+// and z whose neighbour lies in the grid.  Workgroup b of the fixed grid
+// takes every AXIS_BLOCKS-th chunk of 256 points; lane sums are combined in
+// a fixed order, so the result does not depend on timing.
+__global__ __launch_bounds__(256) void k_axis_coupling(Grid g, const double* __restrict__ A, int sxm, int sxp,
+                                                       int sym, int syp, int szm, int szp, double* __restrict__ part) {
+  const long N = g.N();
+  const long nyz = (long)g.ny * g.nz;
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < N; i += (long)AXIS_BLOCKS * 256) {
+    const int X = (int)(i / nyz), Y = (int)((i / g.nz) % g.ny), Z = (int)(i % g.nz);
+    if (X > 0) sx += fabs(A[(long)sxm * N + i]);
+    if (X + 1 < g.nx) sx += fabs(A[(long)sxp * N + i]);
+    if (Y > 0) sy += fabs(A[(long)sym * N + i]);
+    if (Y + 1 < g.ny) sy += fabs(A[(long)syp * N + i]);
+    if (Z > 0) sz += fabs(A[(long)szm * N + i]);
+    if (Z + 1 < g.nz) sz += fabs(A[(long)szp * N + i]);
+  }
+  __shared__ double red[3][256];
+  red[0][threadIdx.x] = sx;
+  red[1][threadIdx.x] = sy;
+  red[2][threadIdx.x] = sz;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) part[3 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+hipError_t launch_axis_coupling(int pat, const Grid& g, const double* A, double* part, hipStream_t st) {
+  const int sxm = pat_slot(pat, -1, 0, 0), sxp = pat_slot(pat, 1, 0, 0), sym = pat_slot(pat, 0, -1, 0),
+            syp = pat_slot(pat, 0, 1, 0), szm = pat_slot(pat, 0, 0, -1), szp = pat_slot(pat, 0, 0, 1);
+  if (sxm < 0 || sxp < 0 || sym < 0 || syp < 0 || szm < 0 || szp < 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_axis_coupling, dim3(AXIS_BLOCKS), dim3(256), 0, st, g, A, sxm, sxp, sym, syp, szm, szp, part);
   return hipGetLastError();
 }
 

@@ -37,7 +37,23 @@ struct Level {
   int* lg_map = nullptr;                    // their dependence order (bx << 16 | by')
   double* W64 = nullptr;                    // operator-dependent interpolation weights to the next level (8 x N)
   float* W32 = nullptr;                     // their FP32 copy for reduced-precision V-cycles
+  // non-default smoothing settings only
+  void* ux = nullptr;  // third sweep output when a cycle has an odd number of sweeps per level
+  void* uz = nullptr;  // zeros: the old values of the first step without ZeroGuess
+  void* qa = nullptr;  // weighted GS: ((1 - w) / w) a_ii, the old-centre term of a full sweep
 };
+
+// Smoothing settings of a configuration with the defaults of zero fields
+// filled in.
+inline int cfg_pre(const smg_config& c) { return c.pre_sweeps > 0 ? c.pre_sweeps : 1; }
+inline int cfg_post(const smg_config& c) { return c.post_sweeps > 0 ? c.post_sweeps : 1; }
+inline double cfg_weight(const smg_config& c) { return c.relax_weight != 0.0 ? c.relax_weight : 1.0; }
+inline bool cfg_zero_guess(const smg_config& c) { return c.zero_guess >= 0; }
+inline int cfg_min_coarse(const smg_config& c) { return c.min_coarse > 0 ? c.min_coarse : 4; }
+// one ZeroGuess step before and one step after the coarse correction, w = 1
+inline bool cfg_default_smoothing(const smg_config& c) {
+  return cfg_pre(c) == 1 && cfg_post(c) == 1 && cfg_weight(c) == 1.0 && cfg_zero_guess(c);
+}
 
 }  // namespace smg
 

@@ -174,6 +174,10 @@ hipError_t launch_prolong_post(int pat, const Grid& g, int cmask, const M& m, co
 template <class M>
 hipError_t launch_lower(int pat, const Grid& g, const M& m, const typename M::V* f, const typename M::V* u,
                         typename M::V* h, hipStream_t st);
+// h = f - sum_{upper s} a_s u[nbr]: the input of a forward sweep from old values u
+template <class M>
+hipError_t launch_upper(int pat, const Grid& g, const M& m, const typename M::V* f, const typename M::V* u,
+                        typename M::V* h, hipStream_t st);
 
 // plain restriction / prolongation (kernel-level entry points)
 template <class V>
@@ -220,6 +224,10 @@ hipError_t launch_bspmv(const Grid& g, const M& m, const typename M::V* x, const
 template <class M>
 hipError_t launch_blower(const Grid& g, const M& m, const typename M::V* f, const typename M::V* u,
                          typename M::V* h, hipStream_t st);
+// h = f - sum over upper neighbour blocks (input of a forward block sweep from old values u)
+template <class M>
+hipError_t launch_bupper(const Grid& g, const M& m, const typename M::V* f, const typename M::V* u,
+                         typename M::V* h, hipStream_t st);
 // point-block Gauss-Seidel sweep on 8 x 8-column tiles (WfArgs.pk: launch_bwf_pack data of this direction)
 void bwf_tiling(const Grid& g, WfTiling* t);
 int bwf_pack_count(int ebytes);
@@ -233,7 +241,17 @@ hipError_t launch_bwf_pack_h(const Grid& g, const WfTiling& tl, int dir, const _
 
 // ---- setup (setup.hip) ------------------------------------------------
 hipError_t launch_copy_masked(int pat, const Grid& g, int be, const double* src, double* dst, hipStream_t st);
-hipError_t launch_recip_diag(int pat, const Grid& g, const double* A, double* rd, unsigned* err, hipStream_t st);
+// rd_i = w / a_ii (the diagonal factor of the GS sweeps with weight w)
+hipError_t launch_recip_diag(int pat, const Grid& g, const double* A, double w, double* rd, unsigned* err,
+                             hipStream_t st);
+// qa_i = (V)(q * a_ii): the old-centre coefficient q = (1 - w) / w of a weighted sweep
+template <class V>
+hipError_t launch_centre_scaled(int pat, const Grid& g, const double* A, double q, V* qa, hipStream_t st);
+// Sums of |a| over the couplings along x, y and z (the two face offsets of
+// each axis, in-grid neighbours only): one triple per workgroup of a fixed
+// grid of AXIS_BLOCKS, part[3 * b + axis]
+constexpr int AXIS_BLOCKS = 256;
+hipError_t launch_axis_coupling(int pat, const Grid& g, const double* A, double* part, hipStream_t st);
 hipError_t launch_block_dinv(const Grid& g, const double* A, double* Dinv, unsigned* err, hipStream_t st);
 // ILU(0) factors on the mask pattern pm of A (pattern pa); L and U hold the
 // mask's slots, U holds pm*N + 2 doubles (the last two are set to {0, 1} and
@@ -298,6 +316,8 @@ hipError_t launch_dot(long n, const double* x, const double* y, double* partial,
 hipError_t launch_cast_d2f(long n, const double* x, float* y, hipStream_t st);
 hipError_t launch_cast_f2d(long n, const float* x, double* y, hipStream_t st);
 hipError_t launch_add(long n, const double* a, const double* b, double* y, hipStream_t st);
+template <class V>
+hipError_t launch_vfma(long n, const V* a, const V* x, V* y, hipStream_t st);  // y_i = fma(a_i, x_i, y_i)
 constexpr int DOT_BLOCKS = 1024;
 
 }  // namespace smg

@@ -89,11 +89,12 @@ hipError_t launch_spmv_group(int pat, bool res, const SpmvArgs<M>* segs, const u
   return hipErrorInvalidValue;
 }
 
-// ------------------------------------------ lower-triangle residual
-// h = f - sum over the lower offsets s (canonical order) of a_s u[nbr]: the
-// old-value terms of a backward Gauss-Seidel row (t = f; t = fma(-a, u, t)).
-template <int PAT, class M>
-struct LowerOp {
+// ------------------------------------------ one-triangle residual
+// h = f - sum over the lower (UP = false) or upper (UP = true) offsets s, in
+// canonical order, of a_s u[nbr]: the old-value terms of a backward or a
+// forward Gauss-Seidel row (t = f; t = fma(-a, u, t)).
+template <int PAT, class M, bool UP>
+struct TriOp {
   using Args = SpmvArgs<M>;  // x = u, b = f, y = h
   __device__ static void run(const Args& a, unsigned bid) {
     using V = typename M::V;
@@ -106,7 +107,7 @@ struct LowerOp {
     const long nyz = (long)g.ny * g.nz;
     V t = a.b[i];
 #pragma unroll
-    for (int s = 0; s < PAT / 2; ++s) {
+    for (int s = UP ? PAT / 2 + 1 : 0; s < (UP ? PAT : PAT / 2); ++s) {
       const int dx = pat_off(PAT, s, 0), dy = pat_off(PAT, s, 1), dz = pat_off(PAT, s, 2);
       if (in_grid(g, X + dx, Y + dy, Z + dz)) t = fma(-m(s, i), a.x[(long)i + dx * nyz + dy * g.nz + dz], t);
     }
@@ -114,20 +115,32 @@ struct LowerOp {
   }
 };
 
-template <class M>
-hipError_t launch_lower(int pat, const Grid& g, const M& m, const typename M::V* f, const typename M::V* u,
-                        typename M::V* h, hipStream_t st) {
+template <class M, bool UP>
+static hipError_t launch_tri(int pat, const Grid& g, const M& m, const typename M::V* f, const typename M::V* u,
+                             typename M::V* h, hipStream_t st) {
   const SpmvArgs<M> a{g, m, u, f, h, 0};
   const dim3 grid(spmv_blocks(g)), blk(256);
   if (pat == 7)
-    hipLaunchKernelGGL((k_one<LowerOp<7, M>>), grid, blk, 0, st, a);
+    hipLaunchKernelGGL((k_one<TriOp<7, M, UP>>), grid, blk, 0, st, a);
   else if (pat == 19)
-    hipLaunchKernelGGL((k_one<LowerOp<19, M>>), grid, blk, 0, st, a);
+    hipLaunchKernelGGL((k_one<TriOp<19, M, UP>>), grid, blk, 0, st, a);
   else if (pat == 27)
-    hipLaunchKernelGGL((k_one<LowerOp<27, M>>), grid, blk, 0, st, a);
+    hipLaunchKernelGGL((k_one<TriOp<27, M, UP>>), grid, blk, 0, st, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+template <class M>
+hipError_t launch_lower(int pat, const Grid& g, const M& m, const typename M::V* f, const typename M::V* u,
+                        typename M::V* h, hipStream_t st) {
+  return launch_tri<M, false>(pat, g, m, f, u, h, st);
+}
+
+template <class M>
+hipError_t launch_upper(int pat, const Grid& g, const M& m, const typename M::V* f, const typename M::V* u,
+                        typename M::V* h, hipStream_t st) {
+  return launch_tri<M, true>(pat, g, m, f, u, h, st);
 }
 
 // ------------------------------------------------ residual + restriction
@@ -559,6 +572,10 @@ template hipError_t launch_lower<MatD>(int, const Grid&, const MatD&, const doub
                                        hipStream_t);
 template hipError_t launch_lower<MatF>(int, const Grid&, const MatF&, const float*, const float*, float*, hipStream_t);
 template hipError_t launch_lower<MatH>(int, const Grid&, const MatH&, const float*, const float*, float*, hipStream_t);
+template hipError_t launch_upper<MatD>(int, const Grid&, const MatD&, const double*, const double*, double*,
+                                       hipStream_t);
+template hipError_t launch_upper<MatF>(int, const Grid&, const MatF&, const float*, const float*, float*, hipStream_t);
+template hipError_t launch_upper<MatH>(int, const Grid&, const MatH&, const float*, const float*, float*, hipStream_t);
 template hipError_t launch_restrict<double>(const Grid&, int, int, const double*, double*, hipStream_t);
 template hipError_t launch_restrict<float>(const Grid&, int, int, const float*, float*, hipStream_t);
 template hipError_t launch_prolong_add<double>(const Grid&, int, int, const double*, double*, hipStream_t);

@@ -15,6 +15,7 @@
 
 #include <chrono>
 #include <mutex>
+#include <vector>
 
 #include "smg_handle.h"
 
@@ -70,16 +71,17 @@ struct Arena {
   }
 };
 
-// Axes coarsened from level lev (dims n): the allowed axes with >= 8 points;
-// x,y only on the first semi_levels levels (or always in semi mode), where a
-// level whose x and y cannot be coarsened any more switches to all axes.
-int next_cmask(int lev, const int* n, int semi, int semi_levels) {
+// Axes coarsened from level lev (dims n): the allowed axes with at least
+// nmin points; x,y only on the first semi_levels levels (or always in semi
+// mode), where a level whose x and y cannot be coarsened any more switches to
+// all axes.
+int next_cmask(int lev, const int* n, int semi, int semi_levels, int nmin) {
   int allowed = (semi || lev < semi_levels) ? 3 : 7, m = 0;
   for (int a = 0; a < 3; ++a)
-    if (((allowed >> a) & 1) && n[a] >= 8) m |= 1 << a;
+    if (((allowed >> a) & 1) && n[a] >= nmin) m |= 1 << a;
   if (m == 0 && !semi && allowed == 3)
     for (int a = 0; a < 3; ++a)
-      if (n[a] >= 8) m |= 1 << a;
+      if (n[a] >= nmin) m |= 1 << a;
   return m;
 }
 
@@ -105,7 +107,9 @@ const char* check_cfg(const smg_config* c) {
   if (c->smoother == SMG_SMOOTH_LGS && c->nz > LGS_MAX_NZ) return "line GS: nz too large (limit 2047)";
   if (c->smoother == SMG_SMOOTH_ILU0 && c->block != 1) return "ILU(0) is implemented for scalar systems";
   if (c->smoother == SMG_SMOOTH_ILU0 && c->prec == SMG_FP16_ROWSCALE) return "ILU(0) supports FP64 and FP32";
-  if (c->coarsen != SMG_COARSEN_FULL && c->coarsen != SMG_COARSEN_SEMI_XY) return "unknown coarsening";
+  if (c->coarsen != SMG_COARSEN_FULL && c->coarsen != SMG_COARSEN_SEMI_XY && c->coarsen != SMG_COARSEN_AUTO)
+    return "unknown coarsening";
+  if (c->coarsen == SMG_COARSEN_AUTO && c->block != 1) return "automatic coarsening takes scalar systems";
   if (c->semi_levels < 0) return "semi_levels must be >= 0";
   if (c->prec < SMG_FP64 || c->prec > SMG_FP16_ROWSCALE) return "unknown precision";
   if (c->max_coarse < 0 || c->gmres_restart < 0 || c->gmres_restart > 200) return "bad max_coarse / gmres_restart";
@@ -115,6 +119,14 @@ const char* check_cfg(const smg_config* c) {
   if (c->interp < SMG_INTERP_VERTEX || c->interp > SMG_INTERP_OPERATOR) return "unknown interpolation";
   if (c->interp != SMG_INTERP_VERTEX && c->block != 1)
     return "cell-centred and operator-dependent transfers are implemented for scalar systems";
+  if (c->pre_sweeps < 0 || c->pre_sweeps > 8 || c->post_sweeps < 0 || c->post_sweeps > 8)
+    return "pre_sweeps / post_sweeps must be 0..8 (0: 1)";
+  if (!(c->relax_weight == 0.0 || (c->relax_weight > 0.0 && c->relax_weight < 2.0)))
+    return "relax_weight must lie in (0, 2) (0: 1.0)";
+  if (cfg_weight(*c) != 1.0 && (c->smoother != SMG_SMOOTH_GS || c->block != 1))
+    return "relax_weight other than 1 applies to point GS on scalar systems";
+  if (c->zero_guess < -1 || c->zero_guess > 1) return "zero_guess must be -1, 0 or 1";
+  if (c->min_coarse != 0 && (c->min_coarse < 2 || c->min_coarse > 4096)) return "min_coarse must be 2..4096 (0: 4)";
   return nullptr;
 }
 
@@ -135,7 +147,7 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
     v.N = v.g.N();
     v.S = nlev == 0 || cfg.interp == SMG_INTERP_CELL ? cfg.pattern : 27;
     v.Ssw = cfg.smoother == SMG_SMOOTH_ILU0 && nlev == 0 && cfg.ilu_mask ? cfg.ilu_mask : v.S;
-    v.cmask = next_cmask(nlev, n, cfg.coarsen == SMG_COARSEN_SEMI_XY, cfg.semi_levels);
+    v.cmask = next_cmask(nlev, n, cfg.coarsen == SMG_COARSEN_SEMI_XY, cfg.semi_levels, 2 * cfg_min_coarse(cfg));
     ++nlev;
     if (v.cmask == 0 || nlev == MAXLEV) {
       v.cmask = 0;
@@ -159,6 +171,9 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
     if (last) continue;
     vec(&v.ua);
     vec(&v.h);
+    if ((cfg_pre(cfg) + cfg_post(cfg)) % 2 == 1 && cfg.smoother != SMG_SMOOTH_ILU0) vec(&v.ux);
+    if (!cfg_zero_guess(cfg)) vec(&v.uz);
+    if (cfg_weight(cfg) != 1.0) v.qa = ar.take<char>((size_t)N * vsz);
     v.rd64 = ar.take<double>((size_t)(bs == 3 ? 9 : 1) * N);
     if (cfg.interp == SMG_INTERP_OPERATOR) {
       v.W64 = ar.take<double>((size_t)8 * N);
@@ -396,12 +411,184 @@ hipError_t prolong_in_place(const smg_handle_s* H, const Level& v, const V* ec, 
   return launch_prolong_add<V>(v.g, v.cmask, H->bs, ec, uf, st);
 }
 
+// h = f minus the terms a GS sweep in direction dir takes from the values u
+// of before the sweep (upper neighbours forward, lower backward), plus, for
+// weight w != 1, the old-centre term ((1 - w) / w) a_ii u_i: with the
+// diagonal factor w / a_ii of the packed sweep data this makes the sweep the
+// weighted one of the GS formulas (Sec. 4.4).
+template <class PT>
+hipError_t old_terms(smg_handle_s* H, const Level& v, int dir, const typename PT::V* f, const typename PT::V* u,
+                     typename PT::V* h, hipStream_t st) {
+  using V = typename PT::V;
+  hipError_t e;
+  if (H->bs == 3)
+    e = dir > 0 ? launch_bupper(v.g, PT::BA(v), f, u, h, st) : launch_blower(v.g, PT::BA(v), f, u, h, st);
+  else
+    e = dir > 0 ? launch_upper(v.S, v.g, PT::A(v), f, u, h, st) : launch_lower(v.S, v.g, PT::A(v), f, u, h, st);
+  if (e == hipSuccess && v.qa) e = launch_vfma<V>(v.N, (const V*)v.qa, u, h, st);
+  return e;
+}
+
+// V-cycle with the smoothing settings of the configuration (pre_sweeps and
+// post_sweeps steps per level, GS weight, ZeroGuess on or off), from plain
+// passes: every GS step is "old-value terms, then the triangular sweep";
+// every ILU(0) step is "residual, L solve, U solve, add".  The default
+// settings take vcycle_t's fused forms instead; both apply the same
+// operations to each value.
+//
+// GS step k of a level (0 <= k < T = pre + post) runs in direction D(k) and
+// writes X(k); the step before it left the sentinels of direction D(k) in
+// X(k) (the last step of a cycle prepares X(0) of the next cycle, setup
+// prepares every buffer once).  X alternates between u_a and the level's
+// output, so X(k + 1) = X(k - 1): that buffer's old values were consumed by
+// the old-value pass (GS) or are read only by columns this sweep waits for
+// (line GS) before it receives sentinels.  With T odd, X(0) is a third
+// buffer u_x so that the last step still ends in the level's output.
+template <class PT>
+hipError_t vcycle_gen_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z0, hipStream_t st) {
+  using V = typename PT::V;
+  using E = typename PT::E;
+  const int NL = H->nlev, bs = H->bs;
+  const int m = cfg_pre(H->cfg), T = m + cfg_post(H->cfg);
+  const bool zg = cfg_zero_guess(H->cfg);
+  const bool ilu = H->cfg.smoother == SMG_SMOOTH_ILU0;
+  const bool lgs = H->cfg.smoother == SMG_SMOOTH_LGS;
+  auto F = [&](int l) -> const V* { return l == 0 ? f0 : (const V*)H->lev[l].f; };
+  auto UB = [&](int l) -> V* { return l == 0 ? z0 : (V*)H->lev[l].ub; };
+  auto X = [&](int l, int k) -> V* {
+    const Level& v = H->lev[l];
+    if (T % 2 == 1 && k == 0) return (V*)v.ux;
+    return (k % 2 == 0) == (T % 2 == 0) ? (V*)v.ua : UB(l);
+  };
+  // pre-steps alternate forward, backward, ...; post-steps start opposite to the last pre-step
+  auto D = [&](int k) {
+    if (k < m) return k % 2 == 0 ? 1 : -1;
+    const int last = (m - 1) % 2 == 0 ? 1 : -1;
+    return (k - m) % 2 == 0 ? -last : last;
+  };
+  // GS / line GS step k of level l
+  auto gs_step = [&](int l, int k) -> hipError_t {
+    const Level& v = H->lev[l];
+    const int kn = (k + 1) % T;
+    V* x = X(l, k);
+    V* nx = X(l, kn);
+    const bool first_zg = k == 0 && zg;
+    const V* uold = k == 0 ? (zg ? nullptr : (const V*)v.uz) : X(l, k - 1);
+    Timed t(H, l, k < m ? 0 : 5, st);
+    if (lgs) return lgs_sweep<PT>(H, v, D(k), F(l), uold, x, nx, st);
+    const V* hin = F(l);
+    if (!first_zg) {
+      hipError_t e = old_terms<PT>(H, v, D(k), F(l), uold, (V*)v.h, st);
+      if (e != hipSuccess) return e;
+      hin = (const V*)v.h;
+    }
+    if (bs == 3) return bsweep<E, V>(H, v, D(k), hin, x, nx, D(kn), st);
+    return sweep<E, V>(H, v, D(k), false, hin, x, nx, D(kn), nullptr, nullptr, st);
+  };
+  // ILU(0) step k: out = u + U^-1 L^-1 (f - A u) (u null: the ZeroGuess
+  // solve into u_a).  The L solve of step k writes LB(k), alternately y1 and
+  // y2, whose sentinels the U solve of step k - 1 (which reads the other one)
+  // has written; the U solve writes zz (sentinels from the L solve) or u_a.
+  // With T odd the last step would have to prepare the buffer it reads, so
+  // the cycle refills y1 before its first step instead.
+  auto LB = [&](const Level& v, int k) -> V* { return k % 2 == 0 ? (V*)v.y1 : (V*)v.y2; };
+  auto ilu_step = [&](int l, int k, const V* u, V* out, int kind) -> hipError_t {
+    const Level& v = H->lev[l];
+    const auto A = PT::A(v);
+    V* nxt = k + 1 < T ? LB(v, k + 1) : (T % 2 == 0 ? LB(v, 0) : nullptr);
+    hipError_t e;
+    Timed t(H, l, kind, st);
+    if (!u) {
+      e = sweep<E, V>(H, v, +1, true, F(l), LB(v, k), (V*)v.ua, -1, nullptr, nullptr, st);
+      if (e == hipSuccess) e = sweep<E, V>(H, v, -1, false, (const V*)LB(v, k), (V*)v.ua, nxt, +1, nullptr, nullptr, st);
+      return e;
+    }
+    e = launch_spmv(v.S, v.g, A, u, F(l), (V*)v.h, true, st);
+    if (e == hipSuccess) e = sweep<E, V>(H, v, +1, true, (const V*)v.h, LB(v, k), (V*)v.zz, -1, nullptr, nullptr, st);
+    if (e == hipSuccess) e = sweep<E, V>(H, v, -1, false, (const V*)LB(v, k), (V*)v.zz, nxt, +1, u, out, st);
+    return e;
+  };
+  V sent;
+  if (sizeof(V) == 8) {
+    uint64_t b = SENT64;
+    memcpy(&sent, &b, 8);
+  } else {
+    uint32_t b = SENT32;
+    memcpy(&sent, &b, 4);
+  }
+  hipError_t e;
+  std::vector<V*> upre(NL);  // each level's pre-smoothed values
+  for (int l = 0; l < NL - 1; ++l) {
+    const Level& v = H->lev[l];
+    if (ilu) {
+      if (T % 2 == 1) {
+        e = launch_fill_bits<V>((V*)v.y1, v.N, sent, st);
+        if (e != hipSuccess) return e;
+      }
+      V* u = nullptr;
+      for (int k = 0; k < m; ++k) {
+        V* out = (u == (V*)v.ua) ? (V*)v.uo : (V*)v.ua;
+        e = ilu_step(l, k, k == 0 ? (zg ? nullptr : (const V*)v.uz) : u, out, 0);
+        if (e != hipSuccess) return e;
+        u = (k == 0 && zg) ? (V*)v.ua : out;
+      }
+      upre[l] = u;
+    } else {
+      for (int k = 0; k < m; ++k) {
+        e = gs_step(l, k);
+        if (e != hipSuccess) return e;
+      }
+      upre[l] = X(l, m - 1);
+    }
+    Timed t(H, l, 2, st);
+    if (bs == 3) {
+      e = launch_bspmv(v.g, PT::BA(v), (const V*)upre[l], F(l), (V*)v.h, true, st);
+      if (e == hipSuccess) e = launch_restrict<V>(v.g, v.cmask, 3, (const V*)v.h, (V*)H->lev[l + 1].f, st);
+    } else {
+      e = launch_spmv(v.S, v.g, PT::A(v), (const V*)upre[l], F(l), (V*)v.h, true, st);
+      if (e == hipSuccess) e = restrict_any<V>(H, v, (const V*)v.h, (V*)H->lev[l + 1].f, st);
+    }
+    if (e != hipSuccess) return e;
+  }
+  {
+    Timed t(H, NL - 1, 3, st);
+    e = launch_coarse_gemv<V>(H->nc, H->aug + H->nc, 2 * H->nc, F(NL - 1), UB(NL - 1), st);
+  }
+  if (e != hipSuccess) return e;
+  for (int l = NL - 2; l >= 0; --l) {
+    const Level& v = H->lev[l];
+    {
+      Timed t(H, l, 4, st);
+      e = bs == 3 ? launch_prolong_add<V>(v.g, v.cmask, 3, (const V*)UB(l + 1), upre[l], st)
+                  : prolong_in_place<V>(H, v, (const V*)UB(l + 1), upre[l], st);
+    }
+    if (e != hipSuccess) return e;
+    if (ilu) {
+      const int p = T - m;
+      V* u = upre[l];
+      for (int k = 0; k < p; ++k) {
+        V* out = k == p - 1 ? UB(l) : (u == (V*)v.ua ? (V*)v.uo : (V*)v.ua);
+        e = ilu_step(l, m + k, u, out, 5);
+        if (e != hipSuccess) return e;
+        u = out;
+      }
+    } else {
+      for (int k = m; k < T; ++k) {
+        e = gs_step(l, k);
+        if (e != hipSuccess) return e;
+      }
+    }
+  }
+  return hipSuccess;
+}
+
 // One V-cycle on internal or caller vectors: f0 = level-0 right-hand side,
 // z0 = level-0 output (its positions read across tiles are given sentinels by
 // the pre-smoothing sweep).
 template <class PT>
 hipError_t vcycle_t(smg_handle_s* H, const typename PT::V* f0, typename PT::V* z0, hipStream_t st) {
   using V = typename PT::V;
+  if (!cfg_default_smoothing(H->cfg)) return vcycle_gen_t<PT>(H, f0, z0, st);
   if (H->bs == 3) return bvcycle_t<PT>(H, f0, z0, st);
   const int NL = H->nlev;
   const bool ilu = H->cfg.smoother == SMG_SMOOTH_ILU0;
@@ -638,7 +825,20 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
     if (bs == 3)
       SCHK(launch_block_dinv(v.g, v.A64, v.rd64, H->err, st));
     else
-      SCHK(launch_recip_diag(v.S, v.g, v.A64, v.rd64, H->err, st));
+      SCHK(launch_recip_diag(v.S, v.g, v.A64, cfg_weight(*cfg), v.rd64, H->err, st));
+    if (v.qa) {
+      const double w = cfg_weight(*cfg), q = (1.0 - w) / w;
+      if (cfg->prec == SMG_FP64)
+        SCHK(launch_centre_scaled<double>(v.S, v.g, v.A64, q, (double*)v.qa, st));
+      else
+        SCHK(launch_centre_scaled<float>(v.S, v.g, v.A64, q, (float*)v.qa, st));
+    }
+    if (v.uz) {
+      if (cfg->prec == SMG_FP64)
+        SCHK(launch_fill_bits<double>((double*)v.uz, v.N * bs, 0.0, st));
+      else
+        SCHK(launch_fill_bits<float>((float*)v.uz, v.N * bs, 0.0f, st));
+    }
     if (cfg->smoother == SMG_SMOOTH_ILU0)
       SCHK(launch_ilu0_factor(v.S, v.Ssw, v.g, v.A64, v.L64, v.U64, v.rU64, H->err, st));
     if (v.W32) SCHK(launch_to_f32(v.W64, v.W32, 8 * v.N, st));
@@ -703,7 +903,7 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
       }
     }
     const long nv = v.N * bs;
-    void* bufs[] = {v.ua, v.ub, v.y1, v.y2, v.zz};
+    void* bufs[] = {v.ua, v.ub, v.y1, v.y2, v.zz, v.ux};
     for (void* p : bufs) {
       if (!p) continue;
       if (cfg->prec == SMG_FP64) {
@@ -741,12 +941,57 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
 
 extern "C" {
 
+// Workspace bytes of cfg; with automatic coarsening the largest over the
+// possible numbers of leading x,y-only levels.
+size_t plan_bytes(const smg_config& cfg, int* nlev, int* nc) {
+  if (cfg.coarsen != SMG_COARSEN_AUTO) return plan(cfg, nullptr, nullptr, nlev, nc);
+  size_t best = 0;
+  for (int s = MAXLEV; s >= 0; --s) {
+    smg_config e = cfg;
+    e.coarsen = SMG_COARSEN_FULL;
+    e.semi_levels = s;
+    int nl = 0, ncc = 0;
+    const size_t b = plan(e, nullptr, nullptr, &nl, &ncc);
+    if (b > best || s == MAXLEV) {
+      *nlev = nl;
+      *nc = ncc;
+    }
+    if (b > best) best = b;
+  }
+  return best;
+}
+
+// Leading x,y-only levels of the automatic coarsening for the finest
+// coefficients: rho = sum |z couplings| / mean(sum |x couplings|, sum |y
+// couplings|); level l coarsens x,y only while rho * 4^l < 1/4.  part holds
+// 3 * AXIS_BLOCKS doubles of device scratch.  Synchronises st.
+hipError_t auto_semi_levels(const smg_config& cfg, const double* coeffs, double* part, hipStream_t st, int* out) {
+  const Grid g{cfg.nx, cfg.ny, cfg.nz};
+  hipError_t e = launch_axis_coupling(cfg.pattern, g, coeffs, part, st);
+  std::vector<double> h(3 * AXIS_BLOCKS);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  for (int b = 0; b < AXIS_BLOCKS; ++b) {
+    sx += h[3 * b];
+    sy += h[3 * b + 1];
+    sz += h[3 * b + 2];
+  }
+  const double sxy = 0.5 * (sx + sy);
+  int s = 0;
+  if (sxy > 0.0)
+    for (double r = sz / sxy; s < MAXLEV && r < 0.25; r *= 4.0) ++s;
+  *out = s;
+  return hipSuccess;
+}
+
 smg_status smg_workspace_size(const smg_config* cfg, size_t* bytes) {
   const char* why = check_cfg(cfg);
   if (why) return fail(nullptr, SMG_EINVAL, "%s", why);
   if (!bytes) return fail(nullptr, SMG_EINVAL, "null bytes pointer");
   int nlev = 0, nc = 0;
-  size_t b = plan(*cfg, nullptr, nullptr, &nlev, &nc);
+  size_t b = plan_bytes(*cfg, &nlev, &nc);
   if (b == 0) return fail(nullptr, SMG_EINVAL, "coarsest level has %d unknowns (> max_coarse)", nc);
   *bytes = b;
   return SMG_OK;
@@ -760,16 +1005,28 @@ smg_status smg_setup(const smg_config* cfg, const double* coeffs, void* workspac
   if (why) return fail(nullptr, SMG_EINVAL, "%s", why);
   if (!coeffs || !workspace) return fail(nullptr, SMG_EINVAL, "null coefficient or workspace pointer");
   int nlev = 0, nc = 0;
-  const size_t need = plan(*cfg, nullptr, nullptr, &nlev, &nc);
+  const size_t need = plan_bytes(*cfg, &nlev, &nc);
   if (need == 0) return fail(nullptr, SMG_EINVAL, "coarsest level has %d unknowns (> max_coarse)", nc);
   if (bytes < need) return fail(nullptr, SMG_ENOMEM, "workspace of %zu bytes, %zu needed", bytes, need);
   hipStream_t st = (hipStream_t)stream;
   auto t0 = std::chrono::steady_clock::now();
-  smg_handle_s* H = new smg_handle_s();
-  H->cfg = *cfg;
-  H->bs = cfg->block;
   char* base = (char*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
-  plan(*cfg, H, base, &H->nlev, &H->nc);
+  smg_config eff = *cfg;
+  if (cfg->coarsen == SMG_COARSEN_AUTO) {
+    // the rule needs the coefficients: the workspace serves as scratch first
+    int s = 0;
+    const hipError_t e = auto_semi_levels(*cfg, coeffs, (double*)base, st, &s);
+    if (e != hipSuccess) return fail(nullptr, SMG_EDEVICE, "automatic coarsening: %s", hipGetErrorString(e));
+    eff.coarsen = SMG_COARSEN_FULL;
+    eff.semi_levels = s;
+    if (plan(eff, nullptr, nullptr, &nlev, &nc) == 0)
+      return fail(nullptr, SMG_EINVAL, "automatic coarsening (%d x,y levels): coarsest level has %d unknowns "
+                  "(> max_coarse)", s, nc);
+  }
+  smg_handle_s* H = new smg_handle_s();
+  H->cfg = eff;
+  H->bs = cfg->block;
+  plan(eff, H, base, &H->nlev, &H->nc);
   auto bail = [&](smg_status s) {
     if (s != SMG_OK) {
       snprintf(g_setup_msg, sizeof g_setup_msg, "%s", H->msg);
@@ -822,7 +1079,7 @@ smg_status smg_setup_noalloc(const smg_config* cfg, const double* coeffs, void* 
   const char* why = check_cfg(cfg);
   if (why) return fail(nullptr, SMG_EINVAL, "%s", why);
   int nlev = 0, nc = 0;
-  const size_t need = plan(*cfg, nullptr, nullptr, &nlev, &nc);
+  const size_t need = plan_bytes(*cfg, &nlev, &nc);
   if (need == 0) return fail(nullptr, SMG_EINVAL, "coarsest level has %d unknowns (> max_coarse)", nc);
   if (need > SMG_SCRATCH_BYTES)
     return fail(nullptr, SMG_ENOMEM,
@@ -878,6 +1135,7 @@ smg_status smg_solve(smg_handle H, const double* b, double* x, double rtol, int 
   double rel = sqrt(KDOT(r, r)) / bn;
   KCHK(e);
   int it = 0;
+  double recur = rel;  // the method's own residual estimate
   smg_status status = SMG_ENOTCONV;
   if (rel < rtol) status = SMG_OK;
   if (krylov == 0 && status != SMG_OK) {
@@ -900,6 +1158,7 @@ smg_status smg_solve(smg_handle H, const double* b, double* x, double rtol, int 
       ++it;
       rel = sqrt(KDOT(r, r)) / bn;
       KCHK(e);
+      recur = rel;
       if (rel < rtol) {
         KCHK(spmv64(H, x, b, r, true, st));
         rel = sqrt(KDOT(r, r)) / bn;
@@ -966,7 +1225,8 @@ smg_status smg_solve(smg_handle H, const double* b, double* x, double rtol, int 
         g[j] = cs[j] * g[j];
         ++it;
         jdone = j + 1;
-        if (fabs(g[j + 1]) / bn < rtol || hn == 0.0) break;
+        recur = fabs(g[j + 1]) / bn;
+        if (recur < rtol || hn == 0.0) break;
       }
       for (int i = jdone - 1; i >= 0; --i) {
         double s = g[i];
@@ -993,6 +1253,7 @@ smg_status smg_solve(smg_handle H, const double* b, double* x, double rtol, int 
     res->iters = it;
     res->levels = H->nlev;
     res->rel_resid_true = rel;
+    res->rel_resid_recur = recur;
     double sn0 = 0, sn = 0, so0 = 0, so = 0;
     for (int l = 0; l < H->nlev; ++l) {
       sn += (double)H->lev[l].N;
@@ -1172,10 +1433,10 @@ static hipError_t op_postsmooth_t(smg_handle_s* H, const Level& v, const void* f
     // the V-cycle's kernels for this level: h = f - lower(A) u_old with
     // u_old = u_in + P ec (large levels: formed in u_a, whose sentinels are
     // restored after)
-    if (split_rp(v) || H->cfg.interp != SMG_INTERP_VERTEX) {
+    if (split_rp(v) || H->cfg.interp != SMG_INTERP_VERTEX || v.qa) {
       e = hipMemcpyAsync(v.ua, uin, sizeof(V) * nv, hipMemcpyDeviceToDevice, st);
       if (e == hipSuccess && ec != nullptr) e = prolong_in_place<V>(H, v, (const V*)ec, (V*)v.ua, st);
-      if (e == hipSuccess) e = launch_lower(v.S, v.g, A, (const V*)f, (const V*)v.ua, (V*)v.h, st);
+      if (e == hipSuccess) e = old_terms<PT>(H, v, -1, (const V*)f, (const V*)v.ua, (V*)v.h, st);
       if (e == hipSuccess) e = launch_fill_bits<V>((V*)v.ua, nv, sent, st);
     } else {
       e = launch_prolong_post(v.S, v.g, v.cmask, A, (const V*)f, (const V*)uin, (const V*)ec, (V*)v.h,

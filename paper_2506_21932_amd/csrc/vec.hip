@@ -90,4 +90,18 @@ hipError_t launch_add(long n, const double* a, const double* b, double* y, hipSt
   return hipGetLastError();
 }
 
+template <class V>
+__global__ __launch_bounds__(256) void k_vfma(long n, const V* __restrict__ a, const V* __restrict__ x,
+                                              V* __restrict__ y) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = fma(a[i], x[i], y[i]);
+}
+template <class V>
+hipError_t launch_vfma(long n, const V* a, const V* x, V* y, hipStream_t st) {
+  hipLaunchKernelGGL((k_vfma<V>), g1(n), dim3(256), 0, st, n, a, x, y);
+  return hipGetLastError();
+}
+template hipError_t launch_vfma<double>(long, const double*, const double*, double*, hipStream_t);
+template hipError_t launch_vfma<float>(long, const float*, const float*, float*, hipStream_t);
+
 }  // namespace smg

@@ -147,3 +147,67 @@ def test_setup_noalloc_rejects_hierarchies_beyond_its_array():
     msg = smg.load().smg_last_error(None).decode()
     assert "static scratch array" in msg
     assert smg.load().smg_setup_noalloc(C.byref(cfg), C.c_void_p(1), None, None) == smg.SMG_EINVAL
+
+
+def _struct_fields(name):
+    src = open(os.path.join(ROOT, "include", "structmg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r";", src).group(1)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        m = re.match(r"(int|double)\s+(.*)", decl)
+        names += [v.strip() for v in m.group(2).split(",")]
+    return names
+
+
+def test_binding_structs_match_header():
+    assert [f[0] for f in smg.Config._fields_] == _struct_fields("smg_config")
+    assert [f[0] for f in smg.Result._fields_] == _struct_fields("smg_result")
+
+
+@pytest.mark.parametrize("bad", [dict(pre_sweeps=-1), dict(pre_sweeps=9), dict(post_sweeps=9),
+                                 dict(relax_weight=-0.5), dict(relax_weight=2.0), dict(relax_weight=float("nan")),
+                                 dict(relax_weight=1.2, smoother="ilu0"), dict(relax_weight=1.2, smoother="lgs"),
+                                 dict(relax_weight=1.2, pattern=27, block=3), dict(zero_guess=2),
+                                 dict(zero_guess=-2), dict(min_coarse=1), dict(min_coarse=5000),
+                                 dict(coarsen="auto", pattern=27, block=3)])
+def test_smoothing_and_coarsening_fields_validated(bad):
+    kw = dict(shape=(16, 16, 16), pattern=7)
+    kw.update(bad)
+    assert _ws(**kw)[0] == smg.SMG_EINVAL
+    assert smg.load().smg_last_error(None).decode() != "no error"
+
+
+def test_smoothing_fields_size_their_buffers():
+    base = _ws(shape=(32, 32, 32), pattern=7)[1]
+    # defaults spelled out are the defaults
+    assert _ws(shape=(32, 32, 32), pattern=7, pre_sweeps=1, post_sweeps=1, relax_weight=1.0, zero_guess=1,
+               min_coarse=4)[1] == base
+    assert _ws(shape=(32, 32, 32), pattern=7, pre_sweeps=2, post_sweeps=2)[1] == base
+    # an odd number of steps per level needs a third sweep buffer; the weight
+    # its old-centre terms; ZeroGuess off a vector of zeros
+    for kw in (dict(pre_sweeps=2), dict(relax_weight=1.3), dict(zero_guess=-1)):
+        assert _ws(shape=(32, 32, 32), pattern=7, **kw)[1] > base, kw
+    # min_coarse 2 adds the 2^3 level below 4^3
+    assert _ws(shape=(32, 32, 32), pattern=7, min_coarse=2)[1] > base
+
+
+def test_auto_coarsening_sizes_for_every_choice():
+    L = smg.load()
+    auto = _ws(shape=(64, 64, 48), pattern=7, coarsen="auto")
+    assert auto[0] == smg.SMG_OK
+    sizes = [_ws(shape=(64, 64, 48), pattern=7, coarsen="full", semi_levels=s)[1] for s in range(0, 8)]
+    assert auto[1] == max(sizes)
+    assert L is not None
+
+
+def test_batch_rejects_non_default_smoothing():
+    L = smg.load()
+    n = C.c_size_t(0)
+    for kw in (dict(pre_sweeps=2), dict(relax_weight=1.1), dict(zero_guess=-1), dict(coarsen="auto")):
+        cfgs = (smg.Config * 1)(smg.make_config((8, 8, 8), 7, **kw))
+        assert L.smg_batch_workspace_size(1, cfgs, C.byref(n)) == smg.SMG_EINVAL, kw
+        assert "batches" in L.smg_batch_last_error(None).decode()
