@@ -377,6 +377,45 @@ __global__ __launch_bounds__(ILU_WG) __attribute__((amdgpu_waves_per_eu(1, 1))) 
   rU[i] = 1.0 / w[C];
 }
 
+// The factorisation of a small level in one workgroup: hyperplane after
+// hyperplane, its band slots dealt to the workgroup's threads, one barrier
+// between hyperplanes (which makes the rows just stored visible to every
+// thread of the workgroup).  Each row takes the operations of k_ilu0_plane
+// in the same order.
+constexpr int ILU_WG1 = 256;
+
+template <int PAT, int PA>
+__global__ __launch_bounds__(ILU_WG1) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_ilu0_small(
+    Grid g, const double* __restrict__ A, double* __restrict__ L, double* __restrict__ U, double* __restrict__ rU,
+    unsigned* err) {
+  constexpr int C = PAT / 2, WX = hp_wx(PAT), WY = hp_wy(PAT);
+  const long N = g.N();
+  const int kb = ilu_band(g.nz, WY);
+  const int D = WX * (g.nx - 1) + WY * (g.ny - 1) + g.nz;
+  const double* zero = U + (long)PAT * N;
+  for (int tau = 0; tau < D; ++tau) {
+    int x0, nxr;
+    ilu_xrange(g, WX, WY, tau, &x0, &nxr);
+    for (int slot = threadIdx.x; slot < nxr * kb; slot += ILU_WG1) {
+      int X, Y, Z;
+      if (!ilu_point<WX, WY>(g, tau, x0, nxr, kb, slot, X, Y, Z)) continue;
+      const long i = ((long)X * g.ny + Y) * g.nz + Z;
+      const IluNb nb{X > 0, X < g.nx - 1, Y > 0, Y < g.ny - 1, Z > 0, Z < g.nz - 1};
+      double w[PAT];
+      ilu_init_row<PAT, PA>(w, A, zero, N, i, nb, std::make_integer_sequence<int, PAT>{});
+      ilu_rows<PAT>(w, g, i, nb, U, zero, std::make_integer_sequence<int, C>{});
+#pragma unroll
+      for (int s = 0; s < PAT; ++s) {
+        L[(long)s * N + i] = s < C ? w[s] : 0.0;
+        U[(long)s * N + i] = s >= C ? w[s] : 0.0;
+      }
+      if (w[C] == 0.0) atomicOr(err, 2u);
+      rU[i] = 1.0 / w[C];
+    }
+    __syncthreads();
+  }
+}
+
 template <int PAT, int PA>
 static hipError_t launch_ilu0_t(const Grid& g, const double* A, double* L, double* U, double* rU, unsigned* err,
                                 hipStream_t st) {
@@ -386,6 +425,10 @@ static hipError_t launch_ilu0_t(const Grid& g, const double* A, double* L, doubl
   hipError_t e = launch_fill_bits<double>(U + (long)PAT * N, 1, 0.0, st);
   if (e == hipSuccess) e = launch_fill_bits<double>(U + (long)PAT * N + 1, 1, 1.0, st);
   if (e != hipSuccess) return e;
+  if (N <= ILU_SMALL_POINTS) {
+    hipLaunchKernelGGL((k_ilu0_small<PAT, PA>), dim3(1), dim3(ILU_WG1), 0, st, g, A, L, U, rU, err);
+    return hipGetLastError();
+  }
   const int kb = ilu_band(g.nz, wy);
   for (int tau = 0; tau < D; ++tau) {
     int x0, nxr;

@@ -75,6 +75,7 @@ struct smg_handle_s {
   // kernel timing (profiling aid): event pairs per (level, kind)
   // captured graph of the V-cycle on the solver's own vectors (kr -> kz)
   bool use_graph = true;
+  bool side_ok = true;  // setup may run per-level work on the library's side streams
   bool hp_on = true;  // small levels use the one-workgroup sweep (off inside batches)
   hipStream_t cap = nullptr;
   hipGraph_t vgraph = nullptr;

@@ -256,6 +256,10 @@ hipError_t launch_block_dinv(const Grid& g, const double* A, double* Dinv, unsig
 // ILU(0) factors on the mask pattern pm of A (pattern pa); L and U hold the
 // mask's slots, U holds pm*N + 2 doubles (the last two are set to {0, 1} and
 // read where a coupling or pivot is unused)
+// Levels of at most ILU_SMALL_POINTS points are factored in one
+// workgroup (one launch), larger ones with one launch per hyperplane; both
+// give the same bits.
+constexpr long ILU_SMALL_POINTS = 4096;
 hipError_t launch_ilu0_factor(int pa, int pm, const Grid& g, const double* A, double* L, double* U, double* rU,
                               unsigned* err, hipStream_t st);
 // Line Gauss-Seidel over z-columns (lgs.hip).  Tiles of K x K columns in

@@ -784,9 +784,54 @@ size_t plan_shapes(const smg_config& cfg, Level* L, int* nlev, int* nc) {
 
 namespace {
 
+// Streams for the setup work of different levels, which is independent once
+// the triple products are done (the ILU(0) factorisation in particular is
+// bound by the latency of one hyperplane after another and occupies few
+// compute units).  One pool per device for the life of the process, at the
+// default priority.
+constexpr int SETUP_SIDE = 3;
+constexpr int SETUP_DEVICES = 64;
+static hipStream_t g_side[SETUP_DEVICES][SETUP_SIDE];
+static std::mutex g_side_mu;
+
+static hipError_t side_streams(hipStream_t* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= SETUP_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  for (int k = 0; k < SETUP_SIDE; ++k) {
+    if (!g_side[dev][k]) {
+      e = hipStreamCreateWithFlags(&g_side[dev][k], hipStreamNonBlocking);
+      if (e != hipSuccess) return e;
+    }
+    out[k] = g_side[dev][k];
+  }
+  return hipSuccess;
+}
+
+constexpr long SETUP_SIDE_POINTS = 1L << 21;  // finest levels from this size use the side streams
+
+// Events that join the side streams back into the caller's stream; on an
+// early return the side streams are drained before the events go.
+struct SideJoin {
+  hipEvent_t ev[SETUP_SIDE + 1] = {};
+  hipStream_t* side = nullptr;
+  bool joined = false;
+  ~SideJoin() {
+    if (side && !joined)
+      for (int k = 0; k < SETUP_SIDE; ++k) (void)hipStreamSynchronize(side[k]);
+    for (hipEvent_t& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
 // Setup pipeline on an already planned handle (used by smg_setup and
 // smg_resetup): level-0 copy, triple products, smoother data, truncation,
-// sentinel fills, coarsest inverse.
+// sentinel fills, coarsest inverse.  Large hierarchies build the smoother
+// data of level 0, level 1 and the remaining levels on three side streams
+// that start after the triple products and join the caller's stream before
+// the final synchronisation.
 smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st) {
   const smg_config* cfg = &H->cfg;
   const int bs = H->bs, be = bs * bs;
@@ -820,8 +865,23 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
     }
   }
   // smoother data, truncation, wavefront tiling and sentinel fills
+  hipStream_t side[SETUP_SIDE] = {st, st, st};
+  SideJoin join;
+  const bool par = H->side_ok && H->nlev >= 3 && H->lev[0].N >= SETUP_SIDE_POINTS;
+  if (par) {
+    SCHK(side_streams(side));
+    join.side = side;
+    SCHK(hipEventCreateWithFlags(&join.ev[SETUP_SIDE], hipEventDisableTiming));
+    SCHK(hipEventRecord(join.ev[SETUP_SIDE], st));
+    for (int k = 0; k < SETUP_SIDE; ++k) {
+      SCHK(hipEventCreateWithFlags(&join.ev[k], hipEventDisableTiming));
+      SCHK(hipStreamWaitEvent(side[k], join.ev[SETUP_SIDE], 0));
+    }
+  }
+  const hipStream_t st0 = st;
   for (int l = 0; l + 1 < H->nlev; ++l) {
     Level& v = H->lev[l];
+    const hipStream_t st = side[l < SETUP_SIDE ? l : SETUP_SIDE - 1];
     if (bs == 3)
       SCHK(launch_block_dinv(v.g, v.A64, v.rd64, H->err, st));
     else
@@ -922,9 +982,16 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
   // coarsest: dense FP64 inverse
   {
     const Level& c = H->lev[H->nlev - 1];
-    SCHK(launch_aug_init(H->nc, H->aug, st));
-    SCHK(launch_dense_assemble(c.g, c.S, bs, c.A64, H->aug, 2 * H->nc, st));
-    SCHK(coarse_invert(H->nc, H->aug, H->info, st));
+    SCHK(launch_aug_init(H->nc, H->aug, st0));
+    SCHK(launch_dense_assemble(c.g, c.S, bs, c.A64, H->aug, 2 * H->nc, st0));
+    SCHK(coarse_invert(H->nc, H->aug, H->info, st0));
+  }
+  if (par) {
+    for (int k = 0; k < SETUP_SIDE; ++k) {
+      SCHK(hipEventRecord(join.ev[k], side[k]));
+      SCHK(hipStreamWaitEvent(st0, join.ev[k], 0));
+    }
+    join.joined = true;
   }
   SCHK(hipStreamSynchronize(st));
   unsigned errv = 0;
@@ -997,8 +1064,18 @@ smg_status smg_workspace_size(const smg_config* cfg, size_t* bytes) {
   return SMG_OK;
 }
 
+static smg_status setup_impl(const smg_config* cfg, const double* coeffs, void* workspace, size_t bytes,
+                             void* stream, smg_handle* out, bool side_ok);
+
 smg_status smg_setup(const smg_config* cfg, const double* coeffs, void* workspace, size_t bytes, void* stream,
                      smg_handle* out) {
+  return setup_impl(cfg, coeffs, workspace, bytes, stream, out, true);
+}
+
+// side_ok: the setup may use the library's side streams (not for callers
+// that cannot allocate)
+static smg_status setup_impl(const smg_config* cfg, const double* coeffs, void* workspace, size_t bytes,
+                             void* stream, smg_handle* out, bool side_ok) {
   if (!out) return fail(nullptr, SMG_EINVAL, "null output handle");
   *out = nullptr;
   const char* why = check_cfg(cfg);
@@ -1026,6 +1103,7 @@ smg_status smg_setup(const smg_config* cfg, const double* coeffs, void* workspac
   smg_handle_s* H = new smg_handle_s();
   H->cfg = eff;
   H->bs = cfg->block;
+  H->side_ok = side_ok;
   plan(eff, H, base, &H->nlev, &H->nc);
   auto bail = [&](smg_status s) {
     if (s != SMG_OK) {
@@ -1088,7 +1166,7 @@ smg_status smg_setup_noalloc(const smg_config* cfg, const double* coeffs, void* 
   void* p = nullptr;
   const smg_status s = scratch_address(&p);
   if (s != SMG_OK) return s;
-  return smg_setup(cfg, coeffs, p, SMG_SCRATCH_BYTES, stream, out);
+  return setup_impl(cfg, coeffs, p, SMG_SCRATCH_BYTES, stream, out, false);
 }
 
 smg_status smg_resetup(smg_handle h, const double* coeffs, void* stream) {
