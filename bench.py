@@ -659,6 +659,7 @@ def main():
                      "launches": d_cnt, "dependence_chain": chain},
         "converged": ok,
         "iters": results[-1]["iters"],
+        "host_waits": results[-1]["host_waits"],
         "rel_resid_true": results[-1]["rel_resid_true"],
         "t_setup_ms": round(float(np.mean([r["t_setup_ms"] for r in results])), 2),
         "t_solve_ms": round(float(np.mean([r["t_solve_ms"] for r in results])), 2),

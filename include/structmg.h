@@ -139,6 +139,10 @@ typedef struct {
   double op_complexity;    /* sum S_l n_l / (S_0 n_0): stored structured entries */
   double t_setup_ms;
   double t_solve_ms;
+  int host_waits;          /* times the solve waited for the device: PCG keeps its scalars on
+                              the device and reads its state once per batch of iterations
+                              (one per iteration only near convergence); GMRES once per
+                              inner product */
 } smg_result;
 
 /* Workspace bytes needed for cfg.  Returns SMG_EINVAL for an unsupported cfg. */
@@ -182,7 +186,10 @@ smg_status smg_precondition(smg_handle h, const double* r, double* z, void* stre
  * (the preconditioned basis vectors are kept and combined into the update;
  * for an exactly linear V-cycle this is plain right-preconditioned GMRES, and
  * with an FP32 / FP16 V-cycle the recurrence residual stays the true one).
- * x holds the initial
+ * PCG forms its scalars (rho, alpha, beta) and its convergence tests on the
+ * device with the same arithmetic as a host loop, so the iterates do not
+ * depend on how many iterations the host enqueues between reads of the
+ * state.  x holds the initial
  * guess on entry.  Stops when ||r||_2 / ||b||_2 < rtol for the true residual
  * (settings table: relative tolerance).  Synchronises `stream`.
  * SMG_ENOTCONV when maxit is reached (res still filled in). */

@@ -38,7 +38,7 @@ class Config(C.Structure):
 class Result(C.Structure):
     _fields_ = [("iters", C.c_int), ("levels", C.c_int), ("rel_resid_true", C.c_double),
                 ("rel_resid_recur", C.c_double), ("grid_complexity", C.c_double), ("op_complexity", C.c_double), ("t_setup_ms", C.c_double),
-                ("t_solve_ms", C.c_double)]
+                ("t_solve_ms", C.c_double), ("host_waits", C.c_int)]
 
 
 EXPORTS = ["smg_workspace_size", "smg_setup", "smg_precondition", "smg_solve", "smg_destroy", "smg_last_error",
@@ -202,7 +202,7 @@ class StructMG:
         return {"status": st, "iters": res.iters, "levels": res.levels, "rel_resid_true": res.rel_resid_true,
                 "rel_resid_recur": res.rel_resid_recur,
                 "grid_complexity": res.grid_complexity, "op_complexity": res.op_complexity,
-                "t_setup_ms": res.t_setup_ms, "t_solve_ms": res.t_solve_ms}
+                "t_setup_ms": res.t_setup_ms, "t_solve_ms": res.t_solve_ms, "host_waits": res.host_waits}
 
     # single V-cycle steps (same kernels as the cycle)
     def op_spmv(self, l, x, y):

@@ -876,9 +876,11 @@ smg_status smg_batch_solve(smg_batch B, const double* const* b, double* const* x
   // the same launches one by one); every system stops at its own
   // convergence or at maxit on the device
   std::vector<int> live(ns);
+  int waits = 0;
   for (int it = 0; it < maxit; it += BATCH_K) {
     BCHK(B, hipMemcpyAsync(live.data(), B->live, sizeof(int) * ns, hipMemcpyDeviceToHost, st));
     BCHK(B, hipStreamSynchronize(st));
+    ++waits;
     int nl = 0;
     for (int v : live) nl += v != 0;
     if (nl == 0) break;
@@ -897,6 +899,7 @@ smg_status smg_batch_solve(smg_batch B, const double* const* b, double* const* x
   BCHK(B, hipMemcpyAsync(sc.data(), B->sc, sizeof(Scal) * ns, hipMemcpyDeviceToHost, st));
   BCHK(B, hipMemcpyAsync(&ef, B->err, sizeof ef, hipMemcpyDeviceToHost, st));
   BCHK(B, hipStreamSynchronize(st));
+  ++waits;
   if (ef & 1u) return bfail(B, SMG_EDEADLOCK, "wavefront watchdog fired");
   const double tsolve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   smg_status worst = SMG_OK;
@@ -921,6 +924,7 @@ smg_status smg_batch_solve(smg_batch B, const double* const* b, double* const* x
       r.op_complexity = so / ((double)H->lev[0].N * H->lev[0].S);
       r.t_setup_ms = B->t_setup_ms;
       r.t_solve_ms = tsolve;
+      r.host_waits = waits;
     }
   }
   if (worst == SMG_ENOTCONV) bfail(B, worst, "some systems did not converge in %d iterations", maxit);

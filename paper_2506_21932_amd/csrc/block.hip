@@ -28,8 +28,10 @@ namespace smg {
 // ------------------------------------------------------------ SpMV / residual
 template <class M, bool RES>
 __global__ __launch_bounds__(256) void k_bspmv(Grid g, M m, const typename M::V* __restrict__ x,
-                                               const typename M::V* __restrict__ b, typename M::V* __restrict__ y) {
+                                               const typename M::V* __restrict__ b, typename M::V* __restrict__ y,
+                                               const double* gate) {
   using V = typename M::V;
+  if (gate != nullptr && *gate == 0.0) return;
   const long N = g.N();
   const long i = (long)blockIdx.x * 256 + threadIdx.x;
   if (i >= N) return;
@@ -55,9 +57,16 @@ hipError_t launch_bspmv(const Grid& g, const M& m, const typename M::V* x, const
                         typename M::V* y, bool res, hipStream_t st) {
   const dim3 grid((unsigned)((g.N() + 255) / 256)), blk(256);
   if (res)
-    hipLaunchKernelGGL((k_bspmv<M, true>), grid, blk, 0, st, g, m, x, b, y);
+    hipLaunchKernelGGL((k_bspmv<M, true>), grid, blk, 0, st, g, m, x, b, y, (const double*)nullptr);
   else
-    hipLaunchKernelGGL((k_bspmv<M, false>), grid, blk, 0, st, g, m, x, b, y);
+    hipLaunchKernelGGL((k_bspmv<M, false>), grid, blk, 0, st, g, m, x, b, y, (const double*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_bspmv_res_gated(const Grid& g, const BMatD& m, const double* x, const double* b, double* y,
+                                  const double* gate, hipStream_t st) {
+  const dim3 grid((unsigned)((g.N() + 255) / 256)), blk(256);
+  hipLaunchKernelGGL((k_bspmv<BMatD, true>), grid, blk, 0, st, g, m, x, b, y, gate);
   return hipGetLastError();
 }
 

@@ -324,4 +324,33 @@ template <class V>
 hipError_t launch_vfma(long n, const V* a, const V* x, V* y, hipStream_t st);  // y_i = fma(a_i, x_i, y_i)
 constexpr int DOT_BLOCKS = 1024;
 
+// ---- device-resident PCG (vec.hip) ------------------------------------
+// The scalars of preconditioned CG (Sec. 5.2) live in a small device block
+// s[] so that an iteration needs no host round trip: alpha, beta and the
+// convergence tests are formed on the device with the host loop's formulas,
+// and the vector kernels below skip their work unless s[PS_STATE] == 0.
+// States: iterating, recurrence residual below tolerance (the true residual
+// is checked next), converged, iteration limit, breakdown (p.Ap <= 0).
+enum PcgSlot {
+  PS_RHO = 8, PS_PQ, PS_RR, PS_RZ, PS_BN, PS_ALPHA, PS_NALPHA, PS_BETA, PS_RECUR, PS_REL, PS_STATE, PS_IT,
+  PS_MAXIT, PS_RTOL, PS_GATE, PS_END
+};
+constexpr double PCG_ITERATING = 0.0, PCG_CHECK = 1.0, PCG_DONE = 2.0, PCG_LIMIT = 3.0, PCG_BREAKDOWN = 4.0;
+hipError_t launch_pcg_start(double* s, double bn, int it, int maxit, double rtol, hipStream_t st);
+hipError_t launch_pcg_alpha(double* s, hipStream_t st);        // limit and breakdown tests, alpha = rho / p.q
+hipError_t launch_pcg_recur(double* s, hipStream_t st);        // it += 1, recurrence residual test
+hipError_t launch_pcg_true(double* s, hipStream_t st);         // true residual test after the check
+hipError_t launch_pcg_beta(double* s, hipStream_t st);         // beta = r.z / rho, rho = r.z
+// y = fma(*a, x, y) / y = fma(*b, y, x) where *state == 0
+hipError_t launch_axpy_dev(long n, const double* a, const double* state, const double* x, double* y, hipStream_t st);
+hipError_t launch_xpby_dev(long n, const double* x, const double* b, const double* state, double* y, hipStream_t st);
+// launch_dot where *gate != 0 (out unchanged otherwise)
+hipError_t launch_dot_gated(long n, const double* x, const double* y, double* partial, double* out,
+                            const double* gate, hipStream_t st);
+// residual y = b - A x of the finest level where *gate != 0 (y unchanged otherwise)
+hipError_t launch_spmv_res_gated(int pat, const Grid& g, const MatD& m, const double* x, const double* b, double* y,
+                                 const double* gate, hipStream_t st);
+hipError_t launch_bspmv_res_gated(const Grid& g, const BMatD& m, const double* x, const double* b, double* y,
+                                  const double* gate, hipStream_t st);
+
 }  // namespace smg

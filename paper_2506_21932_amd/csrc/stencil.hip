@@ -69,6 +69,28 @@ hipError_t launch_spmv(int pat, const Grid& g, const M& m, const typename M::V* 
   return hipErrorInvalidValue;
 }
 
+// The residual of the true-residual check of the device-resident PCG: runs
+// only where *gate != 0 (the same operations as SpmvOp otherwise).
+template <class OP>
+__global__ __launch_bounds__(256) void k_one_gated(const typename OP::Args a, const double* gate) {
+  if (*gate == 0.0) return;
+  OP::run(a, blockIdx.x);
+}
+hipError_t launch_spmv_res_gated(int pat, const Grid& g, const MatD& m, const double* x, const double* b, double* y,
+                                 const double* gate, hipStream_t st) {
+  const SpmvArgs<MatD> a{g, m, x, b, y, 0};
+  const dim3 grid(spmv_blocks(g)), blk(256);
+  if (pat == 7)
+    hipLaunchKernelGGL((k_one_gated<SpmvOp<7, MatD, true>>), grid, blk, 0, st, a, gate);
+  else if (pat == 19)
+    hipLaunchKernelGGL((k_one_gated<SpmvOp<19, MatD, true>>), grid, blk, 0, st, a, gate);
+  else if (pat == 27)
+    hipLaunchKernelGGL((k_one_gated<SpmvOp<27, MatD, true>>), grid, blk, 0, st, a, gate);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 template <class M>
 hipError_t launch_spmv_group(int pat, bool res, const SpmvArgs<M>* segs, const unsigned* bmap, unsigned nblocks,
                              const int* live, hipStream_t st) {

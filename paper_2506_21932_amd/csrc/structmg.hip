@@ -1204,7 +1204,8 @@ smg_status smg_solve(smg_handle H, const double* b, double* x, double rtol, int 
     e = (expr);                                                                          \
     if (e != hipSuccess) return fail(H, SMG_EDEVICE, "%s: %s", #expr, hipGetErrorString(e)); \
   } while (0)
-#define KDOT(a, b_) dot(H, a, b_, n, st, &e)
+  int waits = 0;  // host waits for the device (reported in the result)
+#define KDOT(a, b_) (++waits, dot(H, a, b_, n, st, &e))
   double *r = H->kr, *z = H->kz, *p = H->kp, *q = H->kq;
   double bn = sqrt(KDOT(b, b));
   KCHK(e);
@@ -1217,41 +1218,85 @@ smg_status smg_solve(smg_handle H, const double* b, double* x, double rtol, int 
   smg_status status = SMG_ENOTCONV;
   if (rel < rtol) status = SMG_OK;
   if (krylov == 0 && status != SMG_OK) {
+    // PCG with its scalars on the device (rho, p.q, r.r, r.z, alpha, beta and
+    // the convergence tests of the host formulation, in the same order and
+    // arithmetic, so the iterates are the same).  The host enqueues several
+    // iterations between reads of the state: as many as the recurrence
+    // residual's recent rate predicts before convergence (one at a time near
+    // it); an iteration enqueued after convergence changes nothing (its
+    // vector updates are skipped on the device).
+    double* sc = H->dout;
     KCHK(vcycle_solver(H, st));
     KCHK(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-    double rho = KDOT(r, z);
-    KCHK(e);
-    while (it < maxit) {
-      KCHK(spmv64(H, p, nullptr, q, false, st));
-      const double pq = KDOT(p, q);
-      KCHK(e);
-      if (!(pq > 0.0)) {
-        status = SMG_EBREAKDOWN;
-        fail(H, SMG_EBREAKDOWN, "p.Ap = %g <= 0", pq);
+    KCHK(launch_dot(n, r, z, H->dpart, sc + PS_RHO, st));
+    KCHK(launch_pcg_start(sc, bn, it, maxit, rtol, st));
+    double hs[PS_END];
+    double rel_prev = rel;
+    int it_prev = it, batch = 1;
+    // first half of an iteration: q = A p, alpha, the updates of x and r and
+    // the convergence tests; second half: the V-cycle, beta and p
+    auto first_half = [&]() -> hipError_t {
+      hipError_t e2 = spmv64(H, p, nullptr, q, false, st);
+      if (e2 == hipSuccess) e2 = launch_dot(n, p, q, H->dpart, sc + PS_PQ, st);
+      if (e2 == hipSuccess) e2 = launch_pcg_alpha(sc, st);
+      if (e2 == hipSuccess) e2 = launch_axpy_dev(n, sc + PS_ALPHA, sc + PS_STATE, p, x, st);
+      if (e2 == hipSuccess) e2 = launch_axpy_dev(n, sc + PS_NALPHA, sc + PS_STATE, q, r, st);
+      if (e2 == hipSuccess) e2 = launch_dot(n, r, r, H->dpart, sc + PS_RR, st);
+      if (e2 == hipSuccess) e2 = launch_pcg_recur(sc, st);
+      // the true residual where the recurrence residual is below tolerance
+      const Level& l0 = H->lev[0];
+      if (e2 == hipSuccess)
+        e2 = H->bs == 3 ? launch_bspmv_res_gated(l0.g, BMatD{l0.A64, l0.N}, x, b, r, sc + PS_GATE, st)
+                        : launch_spmv_res_gated(l0.S, l0.g, MatD{l0.A64, l0.N}, x, b, r, sc + PS_GATE, st);
+      if (e2 == hipSuccess) e2 = launch_dot_gated(n, r, r, H->dpart, sc + PS_RR, sc + PS_GATE, st);
+      if (e2 == hipSuccess) e2 = launch_pcg_true(sc, st);
+      return e2;
+    };
+    auto second_half = [&]() -> hipError_t {
+      hipError_t e2 = vcycle_solver(H, st);
+      if (e2 == hipSuccess) e2 = launch_dot(n, r, z, H->dpart, sc + PS_RZ, st);
+      if (e2 == hipSuccess) e2 = launch_pcg_beta(sc, st);
+      if (e2 == hipSuccess) e2 = launch_xpby_dev(n, z, sc + PS_BETA, sc + PS_STATE, p, st);
+      return e2;
+    };
+    for (;;) {
+      // the state is read after the last iteration's tests, before its
+      // V-cycle, so no V-cycle runs after convergence is seen
+      for (int k = 0; k < batch; ++k) {
+        KCHK(first_half());
+        if (k + 1 < batch) KCHK(second_half());
+      }
+      KCHK(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+      KCHK(hipStreamSynchronize(st));
+      ++waits;
+      it = (int)hs[PS_IT];
+      if (it > it_prev) {
+        recur = hs[PS_RECUR];
+        rel = hs[PS_REL];
+      }
+      const double state = hs[PS_STATE];
+      if (state == PCG_DONE) {
+        status = SMG_OK;
         break;
       }
-      const double alpha = rho / pq;
-      KCHK(launch_axpy(n, alpha, p, x, st));
-      KCHK(launch_axpy(n, -alpha, q, r, st));
-      ++it;
-      rel = sqrt(KDOT(r, r)) / bn;
-      KCHK(e);
-      recur = rel;
-      if (rel < rtol) {
-        KCHK(spmv64(H, x, b, r, true, st));
-        rel = sqrt(KDOT(r, r)) / bn;
-        KCHK(e);
-        if (rel < rtol) {
-          status = SMG_OK;
-          break;
-        }
+      if (state == PCG_BREAKDOWN) {
+        status = SMG_EBREAKDOWN;
+        fail(H, SMG_EBREAKDOWN, "p.Ap = %g <= 0", hs[PS_PQ]);
+        break;
       }
-      KCHK(vcycle_solver(H, st));
-      const double rho1 = KDOT(r, z);
-      KCHK(e);
-      const double beta = rho1 / rho;
-      rho = rho1;
-      KCHK(launch_xpby(n, z, beta, p, st));
+      if (state == PCG_LIMIT || it >= maxit) break;
+      KCHK(second_half());
+      // iterations to enqueue next: one fewer than the recurrence's rate
+      // over the last batch predicts to reach the tolerance, 1 to 8
+      batch = 1;
+      if (it > it_prev && recur < rel_prev && recur > 0.0) {
+        const double rate = log(recur / rel_prev) / (it - it_prev);
+        const double need = log(rtol / recur) / rate;
+        if (need > 2.0) batch = need > 9.0 ? 8 : (int)need - 1;
+      }
+      if (batch > maxit - it) batch = maxit - it;
+      rel_prev = recur;
+      it_prev = it;
     }
   } else if (status != SMG_OK) {
     // right-preconditioned GMRES(m) in its flexible form: the preconditioned
@@ -1324,6 +1369,7 @@ smg_status smg_solve(smg_handle H, const double* b, double* x, double rtol, int 
   rel = sqrt(KDOT(r, r)) / bn;
   KCHK(e);
   smg_status es = check_err(H, st);
+  ++waits;
   if (es != SMG_OK) return es;
 #undef KDOT
 #undef KCHK
@@ -1332,6 +1378,7 @@ smg_status smg_solve(smg_handle H, const double* b, double* x, double rtol, int 
     res->levels = H->nlev;
     res->rel_resid_true = rel;
     res->rel_resid_recur = recur;
+    res->host_waits = waits;
     double sn0 = 0, sn = 0, so0 = 0, so = 0;
     for (int l = 0; l < H->nlev; ++l) {
       sn += (double)H->lev[l].N;

@@ -43,7 +43,9 @@ __device__ inline double block_sum(double v) {
 }
 
 __global__ __launch_bounds__(256) void k_dot_partial(long n, const double* __restrict__ x,
-                                                     const double* __restrict__ y, double* __restrict__ part) {
+                                                     const double* __restrict__ y, double* __restrict__ part,
+                                                     const double* gate) {
+  if (gate != nullptr && *gate == 0.0) return;
   const long chunk = (n + DOT_BLOCKS - 1) / DOT_BLOCKS;
   const long lo = (long)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
   double acc = 0.0;
@@ -51,7 +53,9 @@ __global__ __launch_bounds__(256) void k_dot_partial(long n, const double* __res
   const double s = block_sum(acc);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
-__global__ __launch_bounds__(256) void k_dot_final(const double* __restrict__ part, double* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_dot_final(const double* __restrict__ part, double* __restrict__ out,
+                                                   const double* gate) {
+  if (gate != nullptr && *gate == 0.0) return;
   double acc = 0.0;
   for (int i = threadIdx.x; i < DOT_BLOCKS; i += 256) acc += part[i];
   const double s = block_sum(acc);
@@ -72,9 +76,103 @@ hipError_t launch_scale(long n, double s, const double* x, double* y, hipStream_
   hipLaunchKernelGGL(k_scale, g1(n), dim3(256), 0, st, n, s, x, y);
   return hipGetLastError();
 }
+hipError_t launch_dot_gated(long n, const double* x, const double* y, double* partial, double* out,
+                            const double* gate, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS), dim3(256), 0, st, n, x, y, partial, gate);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, st, (const double*)partial, out, gate);
+  return hipGetLastError();
+}
 hipError_t launch_dot(long n, const double* x, const double* y, double* partial, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS), dim3(256), 0, st, n, x, y, partial);
-  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, st, (const double*)partial, out);
+  return launch_dot_gated(n, x, y, partial, out, nullptr, st);
+}
+
+// ---- device-resident PCG scalars: one thread each, the host loop's formulas
+__global__ void k_pcg_start(double* s, double bn, int it, int maxit, double rtol) {
+  s[PS_BN] = bn;
+  s[PS_IT] = it;
+  s[PS_MAXIT] = maxit;
+  s[PS_RTOL] = rtol;
+  s[PS_STATE] = PCG_ITERATING;
+  s[PS_GATE] = 0.0;
+}
+__global__ void k_pcg_alpha(double* s) {
+  if (s[PS_STATE] != PCG_ITERATING) return;
+  if (s[PS_IT] >= s[PS_MAXIT]) {
+    s[PS_STATE] = PCG_LIMIT;
+    return;
+  }
+  const double pq = s[PS_PQ];
+  if (!(pq > 0.0)) {
+    s[PS_STATE] = PCG_BREAKDOWN;
+    return;
+  }
+  const double alpha = s[PS_RHO] / pq;
+  s[PS_ALPHA] = alpha;
+  s[PS_NALPHA] = -alpha;
+}
+__global__ void k_pcg_recur(double* s) {
+  if (s[PS_STATE] != PCG_ITERATING) return;
+  s[PS_IT] = s[PS_IT] + 1.0;
+  const double rel = sqrt(s[PS_RR]) / s[PS_BN];
+  s[PS_RECUR] = rel;
+  s[PS_REL] = rel;
+  if (rel < s[PS_RTOL]) {
+    s[PS_STATE] = PCG_CHECK;
+    s[PS_GATE] = 1.0;
+  }
+}
+__global__ void k_pcg_true(double* s) {
+  if (s[PS_STATE] != PCG_CHECK) return;
+  const double rel = sqrt(s[PS_RR]) / s[PS_BN];
+  s[PS_REL] = rel;
+  s[PS_STATE] = rel < s[PS_RTOL] ? PCG_DONE : PCG_ITERATING;
+  s[PS_GATE] = 0.0;
+}
+__global__ void k_pcg_beta(double* s) {
+  if (s[PS_STATE] != PCG_ITERATING) return;
+  const double rho1 = s[PS_RZ];
+  s[PS_BETA] = rho1 / s[PS_RHO];
+  s[PS_RHO] = rho1;
+}
+__global__ __launch_bounds__(256) void k_axpy_dev(long n, const double* __restrict__ a, const double* __restrict__ state,
+                                                  const double* __restrict__ x, double* __restrict__ y) {
+  if (*state != PCG_ITERATING) return;
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = fma(*a, x[i], y[i]);
+}
+__global__ __launch_bounds__(256) void k_xpby_dev(long n, const double* __restrict__ x, const double* __restrict__ b,
+                                                  const double* __restrict__ state, double* __restrict__ y) {
+  if (*state != PCG_ITERATING) return;
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = fma(*b, y[i], x[i]);
+}
+
+hipError_t launch_pcg_start(double* s, double bn, int it, int maxit, double rtol, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_start, dim3(1), dim3(1), 0, st, s, bn, it, maxit, rtol);
+  return hipGetLastError();
+}
+hipError_t launch_pcg_alpha(double* s, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(1), 0, st, s);
+  return hipGetLastError();
+}
+hipError_t launch_pcg_recur(double* s, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_recur, dim3(1), dim3(1), 0, st, s);
+  return hipGetLastError();
+}
+hipError_t launch_pcg_true(double* s, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_true, dim3(1), dim3(1), 0, st, s);
+  return hipGetLastError();
+}
+hipError_t launch_pcg_beta(double* s, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(1), 0, st, s);
+  return hipGetLastError();
+}
+hipError_t launch_axpy_dev(long n, const double* a, const double* state, const double* x, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy_dev, g1(n), dim3(256), 0, st, n, a, state, x, y);
+  return hipGetLastError();
+}
+hipError_t launch_xpby_dev(long n, const double* x, const double* b, const double* state, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_xpby_dev, g1(n), dim3(256), 0, st, n, x, b, state, y);
   return hipGetLastError();
 }
 hipError_t launch_cast_d2f(long n, const double* x, float* y, hipStream_t st) {
