@@ -203,6 +203,20 @@ smg_status smg_destroy(smg_handle h);
  * launches the V-cycle's kernels one by one (0).  Results are identical. */
 smg_status smg_set_graph(smg_handle h, int enable);
 
+/* Tile shape of the wavefront sweep of one level (the columns a workgroup
+ * owns): 1 sheared (y offset by x, the default for 19/27-point levels with
+ * more than one tile row), 2 rectangular 16 x 16 (the default otherwise), 0
+ * the default rule.  The sweep's results do not depend on it (every shape
+ * runs the sequential lexicographic order; Sec. 4.4), only its time.
+ * Rectangles of a 19/27-point sweep with more than one tile row are refused
+ * (tiles of one tile column would wait on each other).  Re-packs the level's
+ * sweep data and resets its sentinels; synchronises `stream`.  SMG_EINVAL for
+ * the coarsest level, 3x3 block systems, line GS, a shape outside 0..2 or
+ * that refused case. */
+smg_status smg_set_tile_shape(smg_handle h, int level, int shape, void* stream);
+/* Current tile shape of a level (1 or 2), 0 where the level has no tiled sweep. */
+int smg_tile_shape(smg_handle h, int level);
+
 /* Message of the last failed call on h (or of the last failed setup when h is
  * NULL).  Never NULL. */
 const char* smg_last_error(smg_handle h);
@@ -302,9 +316,16 @@ smg_status smg_batch_solve(smg_batch b, const double* const* bv, double* const* 
  * per CU at most: larger values act as 256; 0: 256). */
 smg_status smg_batch_set_schedule(smg_batch b, int order, int grid);
 /* Times batched V-cycles for every (order, grid) candidate and keeps the
- * fastest; returns it and its time per V-cycle (ms).  Overwrites the
- * internal residual vectors (not the caller's). */
+ * fastest, then, level by level, the faster tile shape of the level's sweeps
+ * (sheared or rectangular; smg_batch_tile_shape reports the choice); returns
+ * the order, grid and time per V-cycle (ms) of the final choice.  Results
+ * do not depend on any of these choices.  Overwrites the internal residual
+ * vectors (not the caller's). */
 smg_status smg_batch_tune(smg_batch b, void* stream, int* order, int* grid, double* ms_per_vcycle);
+/* Tile shape of the sweeps of one level in every system (as
+ * smg_set_tile_shape); synchronises `stream`. */
+smg_status smg_batch_set_tile_shape(smg_batch b, int level, int shape, void* stream);
+int smg_batch_tile_shape(smg_batch b, int level);
 /* Replays a captured graph of four lockstep iterations (1, default) or
  * launches the iterations' kernels one by one (0). */
 smg_status smg_batch_set_graph(smg_batch b, int enable);

@@ -47,7 +47,8 @@ EXPORTS = ["smg_workspace_size", "smg_setup", "smg_precondition", "smg_solve", "
            "smg_op_prolong_add", "smg_op_coarse_solve", "smg_set_timing", "smg_timing_report", "smg_resetup",
            "smg_batch_workspace_size", "smg_batch_setup", "smg_batch_precondition", "smg_batch_solve",
            "smg_batch_set_schedule", "smg_batch_tune", "smg_batch_set_graph", "smg_batch_num_systems",
-           "smg_batch_system", "smg_batch_destroy", "smg_batch_last_error", "smg_set_graph", "smg_setup_noalloc"]
+           "smg_batch_system", "smg_batch_destroy", "smg_batch_last_error", "smg_set_graph", "smg_setup_noalloc",
+           "smg_set_tile_shape", "smg_tile_shape", "smg_batch_set_tile_shape", "smg_batch_tile_shape"]
 
 TIMING_KINDS = ["pre_sweep", "pre_sweep_u", "resid_restrict", "coarse_solve", "prolong_post", "post_sweep",
                 "post_sweep_u", "spmv_fp64"]
@@ -90,6 +91,10 @@ def load():
     L.smg_resetup.argtypes = [vp, vp, vp]
     L.smg_timing_report.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int), i, C.POINTER(C.c_int)]
     L.smg_set_graph.argtypes = [vp, i]
+    L.smg_set_tile_shape.argtypes = [vp, i, i, vp]
+    L.smg_tile_shape.argtypes = [vp, i]
+    L.smg_batch_set_tile_shape.argtypes = [vp, i, i, vp]
+    L.smg_batch_tile_shape.argtypes = [vp, i]
     L.smg_batch_workspace_size.argtypes = [i, C.POINTER(Config), C.POINTER(C.c_size_t)]
     L.smg_batch_setup.argtypes = [i, C.POINTER(Config), C.POINTER(vp), vp, C.c_size_t, vp, C.POINTER(vp)]
     L.smg_batch_precondition.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
@@ -266,6 +271,13 @@ class StructMG:
     def set_graph(self, enable):
         self._check(self.L.smg_set_graph(self.h, int(bool(enable))), self.h)
 
+    def set_tile_shape(self, l, shape):
+        """Tile shape of level l's sweeps: 0 default, 1 sheared, 2 rectangular."""
+        self._check(self.L.smg_set_tile_shape(self.h, int(l), int(shape), _stream()), self.h)
+
+    def tile_shape(self, l):
+        return self.L.smg_tile_shape(self.h, int(l))
+
     def op_coarse_solve(self, f, u):
         self._check(self.L.smg_op_coarse_solve(self.h, _ptr(f), _ptr(u), _stream()), self.h)
         return u
@@ -340,4 +352,12 @@ class StructMGBatch:
     def tune(self):
         o, g, ms = C.c_int(0), C.c_int(0), C.c_double(0)
         self._check(self.L.smg_batch_tune(self.b, _stream(), C.byref(o), C.byref(g), C.byref(ms)), self.b)
-        return {"order": o.value, "grid": g.value, "ms_per_vcycle": ms.value}
+        nl = max(self.levels(k) for k in range(self.n))
+        return {"order": o.value, "grid": g.value, "ms_per_vcycle": ms.value,
+                "tile_shapes": [self.tile_shape(l) for l in range(nl - 1)]}
+
+    def set_tile_shape(self, l, shape):
+        self._check(self.L.smg_batch_set_tile_shape(self.b, int(l), int(shape), _stream()), self.b)
+
+    def tile_shape(self, l):
+        return self.L.smg_batch_tile_shape(self.b, int(l))

@@ -336,7 +336,11 @@ size_t layout(smg_batch_s* B, const std::vector<Shape>& sh, char* base) {
       if (l + 1 >= sh[s].nlev) continue;
       const Level& v = sh[s].lev[l];
       L.sys.push_back(s);
-      tiles += (long)v.tl.ntx * v.tl.nty;
+      // room in the tile maps for either tile shape (smg_batch_set_tile_shape)
+      WfTiling t1, t2;
+      wf_tiling(v.g, v.Ssw, &t1, 1);
+      wf_tiling(v.g, v.Ssw, &t2, 2);
+      tiles += std::max((long)t1.ntx * t1.nty, (long)t2.ntx * t2.nty);
       rrb += rr_blocks(v.g, v.cmask, false);
       ppb += pp_blocks(v.g, false);
       L.pre.pat = L.post.pat = L.rr.pat = L.pp.pat = v.S;
@@ -357,7 +361,6 @@ size_t layout(smg_batch_s* B, const std::vector<Shape>& sh, char* base) {
     L.post.segs = ar.take<char>(k * SEGB);
     L.pre.tmap = ar.take<unsigned>(tiles);
     L.post.tmap = ar.take<unsigned>(tiles);
-    L.pre.total = L.post.total = (unsigned)tiles;
     L.rr.segs = ar.take<char>(k * SEGB);
     L.rr.bmap = ar.take<unsigned>(rrb);
     L.rr.nblocks = (unsigned)rrb;
@@ -506,6 +509,9 @@ hipError_t fill_tables(smg_batch_s* B) {
       ppb.push_back(pp_blocks(v.g, L.pp.small));
     }
     L.post.nt = L.pre.nt;
+    unsigned tiles = 0;
+    for (int t : L.pre.nt) tiles += (unsigned)t;
+    L.pre.total = L.post.total = tiles;
     if ((e = upload_typed(L.pre.segs, pre)) != hipSuccess) return e;
     if ((e = upload_typed(L.post.segs, post)) != hipSuccess) return e;
     if ((e = upload_typed(L.rr.segs, rr)) != hipSuccess) return e;
@@ -536,6 +542,14 @@ hipError_t fill_tables(smg_batch_s* B) {
   }
   if ((e = upload_typed(B->spmv_ap.segs, ap)) != hipSuccess) return e;
   return upload(B->spmv_ap.bmap, block_map(apb));
+}
+
+hipError_t fill_tables_any(smg_batch_s* B) {
+  switch (B->prec) {
+    case SMG_FP64: return fill_tables<P64>(B);
+    case SMG_FP32: return fill_tables<P32>(B);
+    default: return fill_tables<P16>(B);
+  }
 }
 
 // One batched V-cycle z = M r on the systems with gate[s] != 0 (null: all),
@@ -742,13 +756,11 @@ smg_status smg_batch_setup(int nsys, const smg_config* cfgs, const double* const
     B->h.push_back(H);
     off += (b + 255) & ~(size_t)255;
   }
-  hipError_t e;
-  switch (B->prec) {
-    case SMG_FP64: e = fill_tables<P64>(B); break;
-    case SMG_FP32: e = fill_tables<P32>(B); break;
-    default: e = fill_tables<P16>(B); break;
-  }
-  if (e == hipSuccess) e = hipMemsetAsync(B->ctr, 0, 3 * sizeof(unsigned), st);
+  hipError_t e = fill_tables_any(B);
+  // ticket counters and the watchdog flag start at zero (the workspace is
+  // the caller's memory, not cleared; a stale flag read as a fired watchdog)
+  if (e == hipSuccess) e = hipMemsetAsync(B->ctr, 0, 2 * sizeof(unsigned), st);
+  if (e == hipSuccess) e = hipMemsetAsync(B->err, 0, sizeof(unsigned), st);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
@@ -757,6 +769,22 @@ smg_status smg_batch_setup(int nsys, const smg_config* cfgs, const double* const
   }
   B->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = B;
+  return SMG_OK;
+}
+
+// Tile shape of level l in every system that sweeps there, and the batch's
+// tables that depend on the tilings.
+smg_status set_tile_shape(smg_batch_s* B, int l, int shape, hipStream_t st) {
+  if (l < 0 || l + 1 >= B->maxlev) return bfail(B, SMG_EINVAL, "level %d has no smoothing sweep", l);
+  for (int s : B->lv[l].sys) {
+    const char* why = nullptr;
+    const hipError_t e = retile_level(B->h[s], l, shape, st, &why);
+    if (why) return bfail(B, SMG_EINVAL, "system %d level %d: %s", s, l, why);
+    BCHK(B, e);
+  }
+  BCHK(B, hipStreamSynchronize(st));
+  drop_graph(B);
+  BCHK(B, fill_tables_any(B));
   return SMG_OK;
 }
 
@@ -826,10 +854,47 @@ smg_status smg_batch_tune(smg_batch B, void* stream, int* order_out, int* grid_o
       }
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   smg_status s = smg_batch_set_schedule(B, bo, (int)bg);
   if (s != SMG_OK) return s;
+  // then the tile shape of each level's sweeps (sheared / rectangular),
+  // level by level with the others fixed
+  auto time_cycles = [&](double* ms_out) -> smg_status {
+    BCHK(B, vcycle_any(B, nullptr, st));
+    BCHK(B, hipEventRecord(e0, st));
+    for (int k = 0; k < 3; ++k) BCHK(B, vcycle_any(B, nullptr, st));
+    BCHK(B, hipEventRecord(e1, st));
+    BCHK(B, hipEventSynchronize(e1));
+    float ms = 0.f;
+    BCHK(B, hipEventElapsedTime(&ms, e0, e1));
+    *ms_out = ms / 3.0;
+    return SMG_OK;
+  };
+  for (int l = 0; l + 1 < B->maxlev; ++l) {
+    if (B->lv[l].sys.empty()) continue;
+    // rectangles only where every system's level allows them
+    bool rect_ok = true;
+    for (int sy : B->lv[l].sys) {
+      const Level& v = B->h[sy]->lev[l];
+      WfTiling t;
+      wf_tiling(v.g, v.Ssw, &t, 2);
+      rect_ok = rect_ok && (v.Ssw == 7 || t.nty == 1);
+    }
+    int bshape = 0;
+    double bms = 1e300;
+    for (int shape = 1; shape <= (rect_ok ? 2 : 1); ++shape) {
+      if ((s = set_tile_shape(B, l, shape, st)) != SMG_OK) return s;
+      double ms = 0.0;
+      if ((s = time_cycles(&ms)) != SMG_OK) return s;
+      if (ms < bms) {
+        bms = ms;
+        bshape = shape;
+      }
+    }
+    if ((s = set_tile_shape(B, l, bshape, st)) != SMG_OK) return s;
+    best = bms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   unsigned ef = 0;
   BCHK(B, hipMemcpy(&ef, B->err, sizeof ef, hipMemcpyDeviceToHost));
   if (ef & 1u) return bfail(B, SMG_EDEADLOCK, "wavefront watchdog fired");
@@ -930,6 +995,16 @@ smg_status smg_batch_solve(smg_batch B, const double* const* b, double* const* x
   if (worst == SMG_ENOTCONV) bfail(B, worst, "some systems did not converge in %d iterations", maxit);
   if (worst == SMG_EBREAKDOWN) bfail(B, worst, "breakdown (p.Ap <= 0) in some system");
   return worst;
+}
+
+smg_status smg_batch_set_tile_shape(smg_batch B, int level, int shape, void* stream) {
+  if (!B) return bfail(nullptr, SMG_EINVAL, "null batch");
+  return set_tile_shape(B, level, shape, (hipStream_t)stream);
+}
+
+int smg_batch_tile_shape(smg_batch B, int level) {
+  if (!B || level < 0 || level + 1 >= B->maxlev || B->lv[level].sys.empty()) return 0;
+  return smg_tile_shape(B->h[B->lv[level].sys[0]], level);
 }
 
 int smg_batch_num_systems(smg_batch B) { return B ? B->nsys : 0; }

@@ -26,6 +26,7 @@ struct Level {
   void *f = nullptr, *ua = nullptr, *ub = nullptr, *h = nullptr;
   void *y1 = nullptr, *y2 = nullptr, *zz = nullptr, *uo = nullptr;
   WfTiling tl{};                    // wavefront tiling
+  long nsk_cap = 0;                 // schedule positions the packed sweep data has room for (either tile shape)
   void* pk[2] = {nullptr, nullptr};  // packed sweep data, forward / backward (V-cycle precision; FP16: halves)
   float* psd = nullptr;             // FP16: {row scale, diagonal scaling} per schedule position
   int hp_steps = 0;                 // small level: hyperplanes of the one-workgroup sweep (0: tiled sweep)
@@ -147,5 +148,10 @@ struct P16 {
 // too large; L holds MAXLEV entries.
 const char* config_error(const smg_config* cfg);
 size_t plan_shapes(const smg_config& cfg, Level* L, int* nlev, int* nc);
+
+// Re-tiles the sweep of level l (shape 0 default, 1 sheared, 2 rectangular):
+// new schedule-ordered sweep data and sentinel state for the level; *why is
+// set when the request is refused (hipErrorInvalidValue).
+hipError_t retile_level(smg_handle_s* H, int l, int shape, hipStream_t st, const char** why);
 
 }  // namespace smg

@@ -37,7 +37,9 @@ struct WfArgs {
   int sys;                   // grouped sweeps: system of this grid
 };
 
-void wf_tiling(const Grid& g, int pat, WfTiling* t);
+// shape: 0 default (sheared for 19/27 points with more than one tile row),
+// 1 sheared, 2 rectangular
+void wf_tiling(const Grid& g, int pat, WfTiling* t, int shape = 0);
 // 16-byte packs per schedule position and direction for storage elements of
 // ebytes bytes; offsets within a tile must stay below 2^31 bytes.
 int wf_pack_count(int pat, int ebytes);

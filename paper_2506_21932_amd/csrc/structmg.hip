@@ -199,11 +199,16 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
         v.tc32 = ar.take<float>((size_t)N);
       }
     } else if (bs == 1) {
+      // room for the sweep data of either tile shape (smg_set_tile_shape)
+      WfTiling t1, t2;
+      wf_tiling(v.g, v.Ssw, &t1, 1);
+      wf_tiling(v.g, v.Ssw, &t2, 2);
       wf_tiling(v.g, v.Ssw, &v.tl);
-      const size_t pbytes = (size_t)wf_pack_count(v.Ssw, eb) * 16 * v.tl.nsk;
+      v.nsk_cap = std::max(t1.nsk, t2.nsk);
+      const size_t pbytes = (size_t)wf_pack_count(v.Ssw, eb) * 16 * v.nsk_cap;
       v.pk[0] = ar.take<char>(pbytes);
       v.pk[1] = ar.take<char>(pbytes);
-      if (cfg.prec == SMG_FP16_ROWSCALE) v.psd = ar.take<float>((size_t)2 * v.tl.nsk);
+      if (cfg.prec == SMG_FP16_ROWSCALE) v.psd = ar.take<float>((size_t)2 * v.nsk_cap);
       v.hp_steps = cfg.smoother == SMG_SMOOTH_GS ? hp_plan(v.g, v.S, (int)vsz, nullptr) : 0;
       if (v.hp_steps > 0) {
         v.hp_pts = ar.take<int>((size_t)v.hp_steps * 256);
@@ -826,6 +831,53 @@ struct SideJoin {
   }
 };
 
+// Scalar point-smoother levels: the sweep data of both directions in the
+// schedule order of the level's current tiling.
+hipError_t pack_sweep_data(smg_handle_s* H, Level& v, hipStream_t st) {
+  const smg_config* cfg = &H->cfg;
+  const bool ilu = cfg->smoother == SMG_SMOOTH_ILU0;
+  const double* lo = ilu ? v.L64 : v.A64;
+  const double* up = ilu ? v.U64 : v.A64;
+  const double* dg = ilu ? v.rU64 : v.rd64;
+  for (int d = 0; d < 2; ++d) {
+    const int dir = d == 0 ? 1 : -1;
+    hipError_t e;
+    if (cfg->prec == SMG_FP64)
+      e = launch_wf_pack<double>(v.Ssw, v.g, v.tl, dir, lo, dg, up, (double*)v.pk[d], st);
+    else if (cfg->prec == SMG_FP32)
+      e = launch_wf_pack<float>(v.Ssw, v.g, v.tl, dir, lo, dg, up, (float*)v.pk[d], st);
+    else
+      e = launch_wf_pack_h(v.S, v.g, v.tl, dir, v.A16, v.sc16, v.rd32, (__half*)v.pk[d], v.psd, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Every smoothing buffer of a level filled with the sentinel: the state the
+// first sweep of a cycle expects whatever the tiling (each sweep then hands
+// the next one its sentinels).
+hipError_t fill_sentinels(smg_handle_s* H, Level& v, hipStream_t st) {
+  const long nv = v.N * H->bs;
+  void* bufs[] = {v.ua, v.ub, v.y1, v.y2, v.zz, v.ux};
+  for (void* p : bufs) {
+    if (!p) continue;
+    hipError_t e;
+    if (H->cfg.prec == SMG_FP64) {
+      double s;
+      uint64_t b = SENT64;
+      memcpy(&s, &b, 8);
+      e = launch_fill_bits<double>((double*)p, nv, s, st);
+    } else {
+      float s;
+      uint32_t b = SENT32;
+      memcpy(&s, &b, 4);
+      e = launch_fill_bits<float>((float*)p, nv, s, st);
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // Setup pipeline on an already planned handle (used by smg_setup and
 // smg_resetup): level-0 copy, triple products, smoother data, truncation,
 // sentinel fills, coarsest inverse.  Large hierarchies build the smoother
@@ -939,19 +991,7 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
       }
     }
     if (bs == 1 && cfg->smoother != SMG_SMOOTH_LGS) {
-      const bool ilu = cfg->smoother == SMG_SMOOTH_ILU0;
-      const double* lo = ilu ? v.L64 : v.A64;
-      const double* up = ilu ? v.U64 : v.A64;
-      const double* dg = ilu ? v.rU64 : v.rd64;
-      for (int d = 0; d < 2; ++d) {
-        const int dir = d == 0 ? 1 : -1;
-        if (cfg->prec == SMG_FP64)
-          SCHK(launch_wf_pack<double>(v.Ssw, v.g, v.tl, dir, lo, dg, up, (double*)v.pk[d], st));
-        else if (cfg->prec == SMG_FP32)
-          SCHK(launch_wf_pack<float>(v.Ssw, v.g, v.tl, dir, lo, dg, up, (float*)v.pk[d], st));
-        else
-          SCHK(launch_wf_pack_h(v.S, v.g, v.tl, dir, v.A16, v.sc16, v.rd32, (__half*)v.pk[d], v.psd, st));
-      }
+      SCHK(pack_sweep_data(H, v, st));
       if (v.hp_steps > 0) {
         std::vector<int> pts;
         hp_plan(v.g, v.S, cfg->prec == SMG_FP64 ? 8 : 4, &pts);
@@ -962,22 +1002,7 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
                               v.rd32, v.hp_cf[d], st));
       }
     }
-    const long nv = v.N * bs;
-    void* bufs[] = {v.ua, v.ub, v.y1, v.y2, v.zz, v.ux};
-    for (void* p : bufs) {
-      if (!p) continue;
-      if (cfg->prec == SMG_FP64) {
-        double s;
-        uint64_t b = SENT64;
-        memcpy(&s, &b, 8);
-        SCHK(launch_fill_bits<double>((double*)p, nv, s, st));
-      } else {
-        float s;
-        uint32_t b = SENT32;
-        memcpy(&s, &b, 4);
-        SCHK(launch_fill_bits<float>((float*)p, nv, s, st));
-      }
-    }
+    SCHK(fill_sentinels(H, v, st));
   }
   // coarsest: dense FP64 inverse
   {
@@ -1003,6 +1028,51 @@ smg_status build_hierarchy(smg_handle_s* H, const double* coeffs, hipStream_t st
 #undef SCHK
   return SMG_OK;
 }
+
+}  // namespace
+
+namespace smg {
+// Re-tiles level l of a handle (shape 0 default, 1 sheared, 2 rectangular)
+// and rebuilds what depends on the tiling: the packed sweep data of both
+// directions and the sentinel state of the level's buffers.  The captured
+// V-cycle graph is dropped (its launches carry the old tiling).  *why names
+// the reason of a refusal.
+hipError_t retile_level(smg_handle_s* H, int l, int shape, hipStream_t st, const char** why) {
+  *why = nullptr;
+  if (l < 0 || l >= H->nlev - 1) {
+    *why = "the level has no smoothing sweep";
+    return hipErrorInvalidValue;
+  }
+  if (shape < 0 || shape > 2) {
+    *why = "tile shape must be 0 (default), 1 (sheared) or 2 (rectangular)";
+    return hipErrorInvalidValue;
+  }
+  if (H->bs != 1 || H->cfg.smoother == SMG_SMOOTH_LGS) {
+    *why = "tile shapes apply to the point GS and ILU(0) sweeps of scalar systems";
+    return hipErrorInvalidValue;
+  }
+  Level& v = H->lev[l];
+  WfTiling t;
+  wf_tiling(v.g, v.Ssw, &t, shape);
+  if (t.sh == 0 && v.Ssw != 7 && t.nty > 1) {
+    *why = "rectangular tiles of a 19/27-point sweep need a single tile row (ny <= 16)";
+    return hipErrorInvalidValue;
+  }
+  const int vb = H->cfg.prec == SMG_FP64 ? 8 : 4, eb = H->cfg.prec == SMG_FP16_ROWSCALE ? 2 : vb;
+  if (t.nsk > v.nsk_cap || !wf_ranges_ok(v.g, t, v.Ssw, vb, eb)) {
+    *why = "the tiling does not fit the level's sweep buffers";
+    return hipErrorInvalidValue;
+  }
+  if (t.sh == v.tl.sh) return hipSuccess;
+  v.tl = t;
+  hipError_t e = pack_sweep_data(H, v, st);
+  if (e == hipSuccess) e = fill_sentinels(H, v, st);
+  drop_vgraph(H);
+  return e;
+}
+}  // namespace smg
+
+namespace {
 
 }  // namespace
 
@@ -1412,6 +1482,21 @@ smg_status smg_set_graph(smg_handle h, int enable) {
   h->use_graph = enable != 0;
   drop_vgraph(h);
   return SMG_OK;
+}
+
+smg_status smg_set_tile_shape(smg_handle h, int level, int shape, void* stream) {
+  if (!h) return fail(nullptr, SMG_EINVAL, "null handle");
+  const char* why = nullptr;
+  const hipError_t e = retile_level(h, level, shape, (hipStream_t)stream, &why);
+  if (why) return fail(h, SMG_EINVAL, "level %d: %s", level, why);
+  HIPCHK(h, e);
+  HIPCHK(h, hipStreamSynchronize((hipStream_t)stream));
+  return SMG_OK;
+}
+
+int smg_tile_shape(smg_handle h, int level) {
+  if (!h || level < 0 || level >= h->nlev - 1 || h->bs != 1 || h->cfg.smoother == SMG_SMOOTH_LGS) return 0;
+  return h->lev[level].tl.sh ? 1 : 2;
 }
 
 const char* smg_last_error(smg_handle h) { return h ? h->msg : g_setup_msg; }

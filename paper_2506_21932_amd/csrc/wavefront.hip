@@ -126,12 +126,19 @@ __host__ __device__ constexpr int wf_npk(int pat, int ebytes) {
   return (pat / 2 + (ebytes == 2 ? 0 : 1) + 16 / ebytes - 1) / (16 / ebytes);
 }
 
-void wf_tiling(const Grid& g, int pat, WfTiling* t) {
-  // Tiles are sheared (y + x offset) when a lower neighbour column lies at
-  // (x-1, y+1) (19- and 27-point patterns); otherwise, and when a single
-  // tile row covers y, plain rectangles keep every dependence pointing to
-  // an earlier tile with fewer tile hand-offs on the critical path.
-  t->sh = (pat == 7 || g.ny <= WF_TY) ? 0 : 1;
+void wf_tiling(const Grid& g, int pat, WfTiling* t, int shape) {
+  // Default: tiles are sheared (y + x offset) when a lower neighbour column
+  // lies at (x-1, y+1) (19- and 27-point patterns), so that every dependence
+  // points to an earlier tile in x and y; otherwise, and when a single tile
+  // row covers y, plain rectangles, which give fewer tile hand-offs on the
+  // critical path.  Shears are valid for every pattern (a point's step is its
+  // hyperplane index minus a per-tile offset either way).  Rectangles are not
+  // for 19/27-point sweeps with more than one tile row: column (x, y) of a
+  // tile's top row then reads (x-1, y+1) in the tile above, which reads the
+  // tile below through (x, y-1), and two tiles waiting on each other stall
+  // (retile_level refuses that case).  shape 1 / 2 forces sheared /
+  // rectangular tiles.
+  t->sh = shape == 1 ? 1 : (shape == 2 ? 0 : ((pat == 7 || g.ny <= WF_TY) ? 0 : 1));
   t->ntx = (g.nx + WF_TX - 1) / WF_TX;
   t->nty = (g.ny + t->sh * (WF_TX - 1) + WF_TY - 1) / WF_TY;
   const int kb = wf_kb(pat);

@@ -129,8 +129,38 @@ def test_batch_tune_keeps_results():
     B.solve(bs, xs0, rtol=1e-9, maxit=200)
     choice = B.tune()
     assert choice["order"] in (0, 1) and choice["grid"] > 0 and choice["ms_per_vcycle"] > 0
+    assert all(s in (0, 1, 2) for s in choice["tile_shapes"]) and choice["tile_shapes"][0] in (1, 2)
     xs1 = [torch.zeros_like(b) for b in bs]
     st, res = B.solve(bs, xs1, rtol=1e-9, maxit=200)
     assert st == smg.SMG_OK
     for a, b in zip(xs0, xs1):
         assert np.array_equal(N(a), N(b))
+
+
+def test_batch_tile_shapes_bitexact():
+    """Each level's sweeps in either tile shape give the batched V-cycle's
+    bits (the schedule is the sequential order whatever the shape)."""
+    sysl = _systems(SHAPES, seed0=95)
+    B = smg.StructMGBatch([T(A) for _, A, _ in sysl], [s for s, _, _ in sysl], pattern=7, prec="fp64", **KW)
+    g = workloads.rng(96)
+    rs = [T(g.standard_normal(int(np.prod(s)))) for s, _, _ in sysl]
+    zs0 = [torch.empty_like(r) for r in rs]
+    B.precondition(rs, zs0)
+    ref = [N(z) for z in zs0]
+    nl = max(B.levels(k) for k in range(B.n))
+    # level 0 (7 points): both shapes; coarser levels (27 points): sheared,
+    # and rectangles only where every system has a single tile row there
+    for shape in (1, 2):
+        B.set_tile_shape(0, shape)
+        assert B.tile_shape(0) == shape
+        for l in range(1, nl - 1):
+            B.set_tile_shape(l, 1)
+        zs = [torch.empty_like(r) for r in rs]
+        B.precondition(rs, zs)
+        B.precondition(rs, zs)
+        for a, z in zip(ref, zs):
+            assert np.array_equal(a, N(z)), f"shape {shape}"
+    bs = [T(b.ravel()) for _, _, b in sysl]
+    xs = [torch.zeros_like(b) for b in bs]
+    st, res = B.solve(bs, xs, rtol=1e-9, maxit=200)
+    assert st == smg.SMG_OK
