@@ -99,8 +99,227 @@ __global__ __launch_bounds__(256) void k_gj_elim(int n, double* __restrict__ aug
   aug[(long)r * ld + j] = fma(-fac[r], pk, aug[(long)r * ld + j]);
 }
 
+// Blocked form of the same steps, B pivot steps per pair of launches.
+// k_gj_panel: one workgroup holds the panel's columns k0..k0+B-1 of every row
+// in LDS and runs its B steps on them (pivot search, row swap, division of
+// the pivot row by the pivot, elimination), keeping each step's pivot row,
+// pivot and column of multipliers (column k after the swap).  The panel's
+// columns are not read after the panel.  k_gj_trail: column tiles of the
+// remaining columns (the rest of the left half and all of the right half),
+// held in LDS, go through the same B steps: swap, division of the pivot
+// row's entry by the pivot, then a_rj = fma(-m_r, a_kj, a_rj) for the other
+// rows, skipped where a_kj is zero.  Every element meets the operations of
+// the one-step-per-launch form in the same order, so the inverse has the
+// same bits.  A singular pivot sets *info and ends the remaining launches.
+// Thread t owns rows t + GJ_THREADS * i, i < R (n <= R * GJ_THREADS).
+constexpr int GJ_THREADS = 1024;
+constexpr int GJ_BMAX = 32;
+constexpr int GJ_TCMAX = 8;
+constexpr long GJ_LDS_BYTES = 128 * 1024;
+constexpr int GJ_NMAX = 2 * GJ_THREADS;  // larger inverses take one step per pair of launches
+                                         // (their panels would be narrower than 8 columns)
+
+template <int R>
+__global__ __launch_bounds__(GJ_THREADS) void k_gj_panel(int n, const double* __restrict__ aug, int k0, int B,
+                                                         double* __restrict__ F, double* __restrict__ piv,
+                                                         int* __restrict__ perm, int* info) {
+  extern __shared__ double P[];  // P[c * n + r]: panel column k0 + c of row r
+  __shared__ double wv[GJ_THREADS / 64];
+  __shared__ int wi[GJ_THREADS / 64];
+  __shared__ double qrow[GJ_BMAX], krow[GJ_BMAX];  // the step's scaled pivot row; row k before the swap
+  if (*info) return;
+  const int ld = 2 * n, tid = threadIdx.x;
+  for (long e = tid; e < (long)n * B; e += GJ_THREADS) {
+    const int r = (int)(e / B), c = (int)(e % B);
+    P[(long)c * n + r] = aug[(long)r * ld + k0 + c];
+  }
+  __syncthreads();
+  for (int c = 0; c < B; ++c) {
+    const int k = k0 + c;
+    const double* col = P + (long)c * n;
+    // largest |a_rk| over rows r >= k, the first of equal ones
+    double best = -1.0;
+    int bidx = n;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int r = tid + GJ_THREADS * i;
+      if (r >= k && r < n) {
+        const double v = fabs(col[r]);
+        if (v > best || (v == best && r < bidx)) {
+          best = v;
+          bidx = r;
+        }
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o);
+      const int oi = __shfl_xor(bidx, o);
+      if (ov > best || (ov == best && oi < bidx)) {
+        best = ov;
+        bidx = oi;
+      }
+    }
+    if ((tid & 63) == 0) {
+      wv[tid >> 6] = best;
+      wi[tid >> 6] = bidx;
+    }
+    __syncthreads();
+    // every thread reduces the wave results (read only until the next barrier)
+    best = wv[0];
+    bidx = wi[0];
+    for (int w = 1; w < GJ_THREADS / 64; ++w)
+      if (wv[w] > best || (wv[w] == best && wi[w] < bidx)) {
+        best = wv[w];
+        bidx = wi[w];
+      }
+    if (best == 0.0 || bidx >= n) {
+      if (tid == 0) atomicOr(info, 1);
+      return;
+    }
+    const int p = bidx;
+    const double pv = col[p];  // the pivot: row p's entry, row k after the swap
+    if (tid == 0) {
+      perm[c] = p;
+      piv[c] = pv;
+    }
+    // multipliers: column k after the swap
+    double m[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int r = tid + GJ_THREADS * i;
+      m[i] = r < n ? (r == k ? pv : (r == p ? col[k] : col[r])) : 0.0;
+      if (r < n) F[(long)c * n + r] = m[i];
+    }
+    if (tid >= c + 1 && tid < B) {
+      krow[tid] = P[(long)tid * n + k];
+      qrow[tid] = P[(long)tid * n + p] / pv;
+    }
+    __syncthreads();
+    // row k takes the scaled pivot row, row p the old row k, and every row
+    // other than k is eliminated (columns after c; column c is not read again)
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int r = tid + GJ_THREADS * i;
+      if (r >= n) continue;
+      if (r == k) {
+        for (int cc = c + 1; cc < B; ++cc) P[(long)cc * n + k] = qrow[cc];
+        continue;
+      }
+      for (int cc = c + 1; cc < B; ++cc) {
+        const double q = qrow[cc];
+        const double a = r == p ? krow[cc] : P[(long)cc * n + r];
+        P[(long)cc * n + r] = q != 0.0 ? fma(-m[i], q, a) : a;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(GJ_THREADS) void k_gj_trail(int n, double* __restrict__ aug, int k0, int B, int j0,
+                                                         int tc_max, const double* __restrict__ F,
+                                                         const double* __restrict__ piv,
+                                                         const int* __restrict__ perm, const int* info) {
+  extern __shared__ double T[];  // T[cc * (n + 1) + r]: tile column cc of row r
+  __shared__ double pk[GJ_TCMAX], spiv[GJ_BMAX];
+  __shared__ int sperm[GJ_BMAX];
+  if (*info) return;
+  const int ld = 2 * n, tid = threadIdx.x, np = n + 1;
+  const int ja = j0 + (int)blockIdx.x * tc_max;
+  const int tc = ld - ja < tc_max ? ld - ja : tc_max;
+  if (tid < B) {
+    spiv[tid] = piv[tid];
+    sperm[tid] = perm[tid];
+  }
+  for (long e = tid; e < (long)n * tc; e += GJ_THREADS) {
+    const int r = (int)(e / tc), cc = (int)(e % tc);
+    T[(long)cc * np + r] = aug[(long)r * ld + ja + cc];
+  }
+  double m[R];  // the multipliers of the current step for the owned rows
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int r = tid + GJ_THREADS * i;
+    m[i] = r < n ? F[r] : 0.0;
+  }
+  __syncthreads();
+  for (int c = 0; c < B; ++c) {
+    const int k = k0 + c;
+    if (tid < tc) {
+      const int p = sperm[c];
+      double a = T[(long)tid * np + k];
+      if (p != k) {
+        const double b = T[(long)tid * np + p];
+        T[(long)tid * np + p] = a;
+        a = b;
+      }
+      a = a / spiv[c];
+      T[(long)tid * np + k] = a;
+      pk[tid] = a;
+    }
+    // the next step's multipliers load while this step computes
+    double mn[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int r = tid + GJ_THREADS * i;
+      mn[i] = (r < n && c + 1 < B) ? F[(long)(c + 1) * n + r] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int r = tid + GJ_THREADS * i;
+      if (r >= n || r == k) continue;
+      for (int cc = 0; cc < tc; ++cc) {
+        const double q = pk[cc];
+        if (q != 0.0) T[(long)cc * np + r] = fma(-m[i], q, T[(long)cc * np + r]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) m[i] = mn[i];
+    __syncthreads();
+  }
+  for (long e = tid; e < (long)n * tc; e += GJ_THREADS) {
+    const int r = (int)(e / tc), cc = (int)(e % tc);
+    aug[(long)r * ld + ja + cc] = T[(long)cc * np + r];
+  }
+}
+
+template <int R>
+static hipError_t gj_blocked(int n, double* aug, int* info_dev, hipStream_t st) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gj_panel<R>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)GJ_LDS_BYTES);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gj_trail<R>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)GJ_LDS_BYTES);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const long bl = GJ_LDS_BYTES / 8 / n, tl = GJ_LDS_BYTES / 8 / (n + 1);
+  const int B = (int)(bl < GJ_BMAX ? bl : GJ_BMAX), TC = (int)(tl < GJ_TCMAX ? tl : GJ_TCMAX);
+  double* F = aug + (long)n * 2 * n;
+  double* piv = F + (long)n * GJ_BMAX;
+  int* perm = reinterpret_cast<int*>(piv + GJ_BMAX);
+  for (int k0 = 0; k0 < n; k0 += B) {
+    const int Bp = n - k0 < B ? n - k0 : B;
+    hipLaunchKernelGGL(k_gj_panel<R>, dim3(1), dim3(GJ_THREADS), (size_t)n * Bp * 8, st, n, (const double*)aug, k0,
+                       Bp, F, piv, perm, info_dev);
+    const int j0 = k0 + Bp, tiles = (2 * n - j0 + TC - 1) / TC;
+    hipLaunchKernelGGL(k_gj_trail<R>, dim3((unsigned)tiles), dim3(GJ_THREADS), (size_t)TC * (n + 1) * 8, st, n, aug,
+                       k0, Bp, j0, TC, (const double*)F, (const double*)piv, (const int*)perm,
+                       (const int*)info_dev);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+long coarse_invert_extra(int n) { return (long)n * GJ_BMAX + 2L * GJ_BMAX; }
+
 hipError_t coarse_invert(int n, double* aug, int* info_dev, hipStream_t st) {
-  double* fac = aug + (long)n * 2 * n;  // n extra doubles after the augmented matrix
+  if (n <= GJ_THREADS) return gj_blocked<1>(n, aug, info_dev, st);
+  if (n <= GJ_NMAX) return gj_blocked<2>(n, aug, info_dev, st);
+  double* fac = aug + (long)n * 2 * n;
   for (int k = 0; k < n; ++k) {
     hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, st, n, aug, k, fac, info_dev);
     const long work = (long)n * (2 * n - k);

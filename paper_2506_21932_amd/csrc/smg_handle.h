@@ -62,7 +62,7 @@ struct smg_handle_s {
   smg_config cfg{};
   int bs = 1, nlev = 0, nc = 0;
   smg::Level lev[smg::MAXLEV];
-  double* aug = nullptr;  // coarsest [.. | A^-1] (n x 2n) + n spare
+  double* aug = nullptr;  // coarsest [.. | A^-1] (n x 2n) + the inversion's work space
   unsigned* ctr = nullptr;
   unsigned* err = nullptr;
   int* info = nullptr;

@@ -310,7 +310,10 @@ int rap_chain_count(int pat, int cmask);
 hipError_t launch_dense_assemble(const Grid& g, int pat, int bs, const double* A, double* M, int ld,
                                  hipStream_t st);
 hipError_t launch_aug_init(int n, double* aug, hipStream_t st);
-hipError_t coarse_invert(int n, double* aug, int* info_dev, hipStream_t st);  // aug: n x 2n, inverse in right half
+// aug: n x 2n [A | I] followed by coarse_invert_extra(n) doubles of work
+// space; the inverse ends in the right half (Gauss-Jordan, partial pivoting)
+long coarse_invert_extra(int n);
+hipError_t coarse_invert(int n, double* aug, int* info_dev, hipStream_t st);
 template <class V>
 hipError_t launch_coarse_gemv(int n, const double* Ainv, int ld, const V* f, V* u, hipStream_t st);
 

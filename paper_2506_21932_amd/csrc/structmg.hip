@@ -236,7 +236,7 @@ size_t plan(const smg_config& cfg, smg_handle_s* H, char* base, int* nlev_out, i
       v.rd32 = ar.take<float>((size_t)(bs == 3 ? 9 : 1) * N);
     }
   }
-  double* aug = ar.take<double>((size_t)nc * 2 * nc + nc);
+  double* aug = ar.take<double>((size_t)nc * 2 * nc + coarse_invert_extra(nc));
   unsigned* ctr = ar.take<unsigned>(64);
   unsigned* err = ar.take<unsigned>(64);
   int* info = ar.take<int>(64);

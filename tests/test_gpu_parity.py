@@ -385,6 +385,25 @@ def test_single_level_hierarchy():
     assert res["status"] == 0 and res["rel_resid_true"] < 1e-9 and abs(res["iters"] - itr) <= 1
 
 
+# dense coarsest inverses of every size class: blocked panels of 32 and 16
+# columns with one row per thread, 9-column panels with two rows per thread,
+# and one pivot step per pair of launches beyond 2048 unknowns
+@pytest.mark.parametrize("shape,pat", [((5, 6, 7), 7), ((10, 10, 10), 27), ((12, 12, 12), 7), ((13, 13, 13), 27)],
+                         ids=["210", "1000", "1728", "2197"])
+def test_dense_coarsest_sizes(shape, pat):
+    if pat == 7:
+        A, _ = workloads.reservoir7(shape, seed=57)
+    else:
+        A = workloads.random_sgdia(shape, pat, seed=58, symmetric=False)
+    mg = smg.StructMG(T(A), shape, pattern=pat, max_coarse=4096, min_coarse=64, device=DEV)  # one level
+    assert mg.nlev == 1
+    f = workloads.rng(8).uniform(-1, 1, size=int(np.prod(shape)))
+    u = N(mg.op_coarse_solve(T(f), torch.empty(f.size, dtype=torch.float64, device=DEV)))
+    M = oracle.dense(workloads.offsets(pat), A, shape)
+    ref = np.linalg.solve(M, f)
+    assert np.abs(u - ref).max() <= 1e-13 * np.abs(ref).max() * max(1.0, np.linalg.cond(M) / 1e3)
+
+
 @pytest.mark.parametrize("kind", ["gs_fp64", "gs_fp32", "block_fp16", "lgs_fp64", "operator_fp64", "cell_fp32",
                                   "ilu27_fp64"])
 def test_graph_replay_identical(kind):
