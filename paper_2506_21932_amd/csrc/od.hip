@@ -16,6 +16,7 @@
 // fma(Abar(d), W(g, c'), .), r = 1 / Abar(0), c'_a = (d_a == 0 ? c_a : 0).
 #include <utility>
 
+#include "smg_group.h"
 #include "smg_kernels.h"
 
 namespace smg {
@@ -233,7 +234,9 @@ __global__ __launch_bounds__(256) void k_rap_od_all(Grid gf, const double* __res
   constexpr int cx = CM & 1, cy = (CM >> 1) & 1, cz = (CM >> 2) & 1;
   const Grid gc{cx ? gf.nx / 2 : gf.nx, cy ? gf.ny / 2 : gf.ny, cz ? gf.nz / 2 : gf.nz};
   const long Nf = gf.N(), Nc = gc.N();
-  const long ic = (long)blockIdx.x * 256 + threadIdx.x;
+  // contiguous coarse lines per XCD: neighbouring lines share most of their
+  // fine neighbourhood, which then stays in one L2
+  const long ic = (long)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   if (ic >= Nc) return;
   const int Z = (int)(ic % gc.nz), Y = (int)((ic / gc.nz) % gc.ny), X = (int)(ic / ((long)gc.nz * gc.ny));
   double acc[27];
