@@ -251,6 +251,18 @@ struct WfE<__half> {
     const unsigned w = pk[m / 8][(m % 8) / 2];
     return __half2float(__ushort_as_half((unsigned short)(m % 2 == 0 ? (w & 0xffffu) : (w >> 16))));
   }
+  // the row-scaled coefficient float(h_m) * sc in one instruction: a mixed
+  // fma of the packed half (exact conversion) and sc with addend -0, which
+  // rounds once, like the product, and keeps its sign of zero
+  __device__ static float scaled(const u32x4* pk, int m, float sc) {
+    const unsigned w = pk[m / 8][(m % 8) / 2];
+    float r;
+    if (m % 2 == 0)
+      asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(sc), "v"(-0.0f));
+    else
+      asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(sc), "v"(-0.0f));
+    return r;
+  }
 };
 
 // Columns of a tile that no lane of another tile reads in a sweep of
@@ -405,7 +417,11 @@ __device__ __forceinline__ void wf_compute(const WfArgs<typename WfVal<E>::V>& a
       }
 #pragma unroll
       for (int m = 0; m < NT; ++m) {
-        const V cm = T::HALF ? sc * T::get(cf[jp], m) : T::get(cf[jp], m);
+        V cm;
+        if constexpr (T::HALF)
+          cm = T::scaled(cf[jp], m, sc);
+        else
+          cm = T::get(cf[jp], m);
         t = fma(-cm, val[m], t);
       }
       const V dv = T::HALF ? __uint_as_float(sdv[jp].y) : T::get(cf[jp], NT);
