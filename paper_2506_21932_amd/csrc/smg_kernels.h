@@ -328,6 +328,17 @@ hipError_t launch_add(long n, const double* a, const double* b, double* y, hipSt
 template <class V>
 hipError_t launch_vfma(long n, const V* a, const V* x, V* y, hipStream_t st);  // y_i = fma(a_i, x_i, y_i)
 constexpr int DOT_BLOCKS = 1024;
+// Sum over a 256-thread workgroup in a fixed order (wavefront shuffles, then
+// the four wave sums pairwise); the result is valid in thread 0.
+__device__ inline double block_sum(double v) {
+  __shared__ double red[4];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) s = (red[0] + red[1]) + (red[2] + red[3]);
+  return s;
+}
 
 // ---- device-resident PCG (vec.hip) ------------------------------------
 // The scalars of preconditioned CG (Sec. 5.2) live in a small device block
@@ -347,7 +358,11 @@ hipError_t launch_pcg_recur(double* s, hipStream_t st);        // it += 1, recur
 hipError_t launch_pcg_true(double* s, hipStream_t st);         // true residual test after the check
 hipError_t launch_pcg_beta(double* s, hipStream_t st);         // beta = r.z / rho, rho = r.z
 // y = fma(*a, x, y) / y = fma(*b, y, x) where *state == 0
-hipError_t launch_axpy_dev(long n, const double* a, const double* state, const double* x, double* y, hipStream_t st);
+// x += alpha p, r -= alpha q (while iterating) and rr = r.r, with s the PCG
+// slots (PS_ALPHA, PS_NALPHA, PS_STATE); the dot's bits equal launch_dot's
+hipError_t launch_pcg_update(long n, const double* s, const double* p, const double* q, double* x, double* r,
+                             double* partial, double* rr, hipStream_t st);
+
 hipError_t launch_xpby_dev(long n, const double* x, const double* b, const double* state, double* y, hipStream_t st);
 // launch_dot where *gate != 0 (out unchanged otherwise)
 hipError_t launch_dot_gated(long n, const double* x, const double* y, double* partial, double* out,

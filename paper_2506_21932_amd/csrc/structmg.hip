@@ -1309,9 +1309,7 @@ smg_status smg_solve(smg_handle H, const double* b, double* x, double rtol, int 
       hipError_t e2 = spmv64(H, p, nullptr, q, false, st);
       if (e2 == hipSuccess) e2 = launch_dot(n, p, q, H->dpart, sc + PS_PQ, st);
       if (e2 == hipSuccess) e2 = launch_pcg_alpha(sc, st);
-      if (e2 == hipSuccess) e2 = launch_axpy_dev(n, sc + PS_ALPHA, sc + PS_STATE, p, x, st);
-      if (e2 == hipSuccess) e2 = launch_axpy_dev(n, sc + PS_NALPHA, sc + PS_STATE, q, r, st);
-      if (e2 == hipSuccess) e2 = launch_dot(n, r, r, H->dpart, sc + PS_RR, st);
+      if (e2 == hipSuccess) e2 = launch_pcg_update(n, sc, p, q, x, r, H->dpart, sc + PS_RR, st);
       if (e2 == hipSuccess) e2 = launch_pcg_recur(sc, st);
       // the true residual where the recurrence residual is below tolerance
       const Level& l0 = H->lev[0];

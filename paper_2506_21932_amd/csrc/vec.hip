@@ -32,16 +32,6 @@ __global__ __launch_bounds__(256) void k_f2d(long n, const float* __restrict__ x
   if (i < n) y[i] = (double)x[i];
 }
 
-__device__ inline double block_sum(double v) {
-  __shared__ double red[4];
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0) s = (red[0] + red[1]) + (red[2] + red[3]);
-  return s;
-}
-
 __global__ __launch_bounds__(256) void k_dot_partial(long n, const double* __restrict__ x,
                                                      const double* __restrict__ y, double* __restrict__ part,
                                                      const double* gate) {
@@ -134,17 +124,43 @@ __global__ void k_pcg_beta(double* s) {
   s[PS_BETA] = rho1 / s[PS_RHO];
   s[PS_RHO] = rho1;
 }
-__global__ __launch_bounds__(256) void k_axpy_dev(long n, const double* __restrict__ a, const double* __restrict__ state,
-                                                  const double* __restrict__ x, double* __restrict__ y) {
-  if (*state != PCG_ITERATING) return;
-  const long i = (long)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) y[i] = fma(*a, x[i], y[i]);
-}
 __global__ __launch_bounds__(256) void k_xpby_dev(long n, const double* __restrict__ x, const double* __restrict__ b,
                                                   const double* __restrict__ state, double* __restrict__ y) {
   if (*state != PCG_ITERATING) return;
   const long i = (long)blockIdx.x * 256 + threadIdx.x;
   if (i < n) y[i] = fma(*b, y[i], x[i]);
+}
+
+// x += alpha p, r -= alpha q (skipped unless the state is ITERATING) and the
+// partial sums of r.r in one pass: the element-to-thread mapping and the
+// order of the fmas are those of k_dot_partial, so r.r has the same bits as a
+// separate dot after the two updates.
+__global__ __launch_bounds__(256) void k_pcg_update(long n, const double* __restrict__ s, const double* __restrict__ p,
+                                                    const double* __restrict__ q, double* __restrict__ x,
+                                                    double* __restrict__ r, double* __restrict__ part) {
+  const bool upd = s[PS_STATE] == PCG_ITERATING;
+  const double a = s[PS_ALPHA], na = s[PS_NALPHA];
+  const long chunk = (n + DOT_BLOCKS - 1) / DOT_BLOCKS;
+  const long lo = (long)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  double acc = 0.0;
+  for (long i = lo + threadIdx.x; i < hi; i += 256) {
+    double ri = r[i];
+    if (upd) {
+      x[i] = fma(a, p[i], x[i]);
+      ri = fma(na, q[i], ri);
+      r[i] = ri;
+    }
+    acc = fma(ri, ri, acc);
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+hipError_t launch_pcg_update(long n, const double* s, const double* p, const double* q, double* x, double* r,
+                             double* partial, double* rr, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_update, dim3(DOT_BLOCKS), dim3(256), 0, st, n, s, p, q, x, r, partial);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, st, (const double*)partial, rr, (const double*)nullptr);
+  return hipGetLastError();
 }
 
 hipError_t launch_pcg_start(double* s, double bn, int it, int maxit, double rtol, hipStream_t st) {
@@ -165,10 +181,6 @@ hipError_t launch_pcg_true(double* s, hipStream_t st) {
 }
 hipError_t launch_pcg_beta(double* s, hipStream_t st) {
   hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(1), 0, st, s);
-  return hipGetLastError();
-}
-hipError_t launch_axpy_dev(long n, const double* a, const double* state, const double* x, double* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_axpy_dev, g1(n), dim3(256), 0, st, n, a, state, x, y);
   return hipGetLastError();
 }
 hipError_t launch_xpby_dev(long n, const double* x, const double* b, const double* state, double* y, hipStream_t st) {
