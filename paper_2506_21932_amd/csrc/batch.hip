@@ -170,28 +170,35 @@ __global__ __launch_bounds__(64) void k_bscal(const SysVec* __restrict__ sv, con
   }
 }
 
-enum { U_AXPY2, U_XPBY, U_COPYZP, U_IN, U_OUT, U_D2F, U_F2D };
+enum { U_AXPY2, U_XPBY, U_COPYZP, U_IN, U_OUT, U_D2F, U_F2D, U_AXPY2RR };
 
 // Vector updates of one block of BV elements per workgroup (same arithmetic
 // as the single-system vector kernels).
 template <int OP, class V>
+// U_AXPY2RR: U_AXPY2 with the partial sums of r.r over the same elements in
+// the same order as k_bdot<D_RR>, written where k_bdot writes them (the same
+// bits as the update followed by that dot).
 __global__ __launch_bounds__(256) void k_bvec(const SysVec* __restrict__ sv, const unsigned* __restrict__ bmap,
-                                              const int* __restrict__ gate, const Scal* __restrict__ sc) {
+                                              const int* __restrict__ gate, const Scal* __restrict__ sc,
+                                              double* __restrict__ part) {
   const unsigned e = bmap[blockIdx.x];
   const int s = (int)(e >> 20);
   const long blk = e & 0xFFFFFu;
   if (gate != nullptr && gate[s] == 0) return;
   const SysVec& v = sv[s];
-  const double alpha = OP == U_AXPY2 ? sc[s].alpha : 0.0;
+  const double alpha = (OP == U_AXPY2 || OP == U_AXPY2RR) ? sc[s].alpha : 0.0;
   const double beta = OP == U_XPBY ? sc[s].beta : 0.0;
   const long i0 = blk * BV + threadIdx.x;
+  double acc = 0.0;
 #pragma unroll
   for (int k = 0; k < BV / 256; ++k) {
     const long i = i0 + k * 256;
     if (i >= v.n) break;
-    if (OP == U_AXPY2) {
+    if (OP == U_AXPY2 || OP == U_AXPY2RR) {
       v.x[i] = fma(alpha, v.p[i], v.x[i]);
-      v.r[i] = fma(-alpha, v.q[i], v.r[i]);
+      const double ri = fma(-alpha, v.q[i], v.r[i]);
+      v.r[i] = ri;
+      if (OP == U_AXPY2RR) acc = fma(ri, ri, acc);
     } else if (OP == U_XPBY) {
       v.p[i] = fma(beta, v.p[i], v.z[i]);
     } else if (OP == U_COPYZP) {
@@ -205,6 +212,10 @@ __global__ __launch_bounds__(256) void k_bvec(const SysVec* __restrict__ sv, con
     } else {
       v.z[i] = (double)((const V*)v.vout)[i];
     }
+  }
+  if (OP == U_AXPY2RR) {
+    const double t = bsum256(acc);
+    if (threadIdx.x == 0) part[v.pbase + blk] = t;
   }
 }
 
@@ -562,7 +573,7 @@ hipError_t bvcycle(smg_batch_s* B, const int* gate, hipStream_t st) {
   hipError_t e = hipSuccess;
   const dim3 vg(B->vblocks), vb(256);
   if (B->prec != SMG_FP64) {
-    hipLaunchKernelGGL((k_bvec<U_D2F, float>), vg, vb, 0, st, B->sv, B->vbmap, gate, B->sc);
+    hipLaunchKernelGGL((k_bvec<U_D2F, float>), vg, vb, 0, st, B->sv, B->vbmap, gate, B->sc, (double*)nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   for (int l = 0; l + 1 < B->maxlev; ++l) {
@@ -583,7 +594,7 @@ hipError_t bvcycle(smg_batch_s* B, const int* gate, hipStream_t st) {
     if (e != hipSuccess) return e;
   }
   if (B->prec != SMG_FP64) {
-    hipLaunchKernelGGL((k_bvec<U_F2D, float>), vg, vb, 0, st, B->sv, B->vbmap, gate, B->sc);
+    hipLaunchKernelGGL((k_bvec<U_F2D, float>), vg, vb, 0, st, B->sv, B->vbmap, gate, B->sc, (double*)nullptr);
     e = hipGetLastError();
   }
   return e;
@@ -610,7 +621,7 @@ hipError_t scal(smg_batch_s* B, hipStream_t st) {
 }
 template <int OP>
 hipError_t vec(smg_batch_s* B, const int* gate, hipStream_t st) {
-  hipLaunchKernelGGL((k_bvec<OP, float>), dim3(B->vblocks), dim3(256), 0, st, B->sv, B->vbmap, gate, B->sc);
+  hipLaunchKernelGGL((k_bvec<OP, float>), dim3(B->vblocks), dim3(256), 0, st, B->sv, B->vbmap, gate, B->sc, B->part);
   return hipGetLastError();
 }
 hipError_t spmv(smg_batch_s* B, const Grp& g, bool res, const int* gate, hipStream_t st) {
@@ -627,8 +638,7 @@ hipError_t iteration(smg_batch_s* B, hipStream_t st) {
   ICHK(spmv(B, B->spmv_ap, false, B->live, st));
   ICHK(dot<D_PQ>(B, B->live, st));
   ICHK(scal<S_ALPHA>(B, st));
-  ICHK(vec<U_AXPY2>(B, B->live, st));
-  ICHK(dot<D_RR>(B, B->live, st));
+  ICHK(vec<U_AXPY2RR>(B, B->live, st));
   ICHK(scal<S_REL>(B, st));
   ICHK(spmv(B, B->spmv_res, true, B->claim, st));
   ICHK(dot<D_RR>(B, B->claim, st));
