@@ -229,9 +229,10 @@ __device__ inline float bw_row<float>(const bu32x4* p, int e) {
 template <>
 __device__ inline float bw_row<__half>(const bu32x4* p, int e) {
   if (e >= 39) return __uint_as_float(p[(84 + 4 * (e - 39)) / 16][((84 + 4 * (e - 39)) % 16) / 4]);
+  // row scale (byte 80) times the half, rounded once
   const unsigned w = p[e / 8][(e % 8) / 2];
-  const float h = __half2float(__ushort_as_half((unsigned short)(e % 2 == 0 ? (w & 0xffffu) : (w >> 16))));
-  return __uint_as_float(p[5][0]) * h;  // row scale (byte 80) times the half
+  const float sc = __uint_as_float(p[5][0]);
+  return e % 2 == 0 ? half_times<0>(w, sc) : half_times<1>(w, sc);
 }
 
 constexpr int BW_NT = 3 * BW_NL;  // threads: one wave per scalar row

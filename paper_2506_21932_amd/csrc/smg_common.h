@@ -109,6 +109,20 @@ struct BMatF {
   using V = float;
   __device__ float operator()(int e, int r, long i) const { return a[(long)e * n + i]; }
 };
+// float(half m of the packed pair w) * sc rounded once, as the product of the
+// converted half and sc: a mixed-precision fma (the half operand converted
+// exactly) with addend -0, which keeps the product's sign of zero.  M = 0:
+// low half, 1: high half.
+template <int M>
+__device__ __forceinline__ float half_times(unsigned w, float sc) {
+  float r;
+  if constexpr (M == 0)
+    asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(sc), "v"(-0.0f));
+  else
+    asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(sc), "v"(-0.0f));
+  return r;
+}
+
 struct BMatH {
   const __half* a;
   const float* sc;

@@ -251,17 +251,10 @@ struct WfE<__half> {
     const unsigned w = pk[m / 8][(m % 8) / 2];
     return __half2float(__ushort_as_half((unsigned short)(m % 2 == 0 ? (w & 0xffffu) : (w >> 16))));
   }
-  // the row-scaled coefficient float(h_m) * sc in one instruction: a mixed
-  // fma of the packed half (exact conversion) and sc with addend -0, which
-  // rounds once, like the product, and keeps its sign of zero
+  // the row-scaled coefficient float(h_m) * sc in one instruction
   __device__ static float scaled(const u32x4* pk, int m, float sc) {
     const unsigned w = pk[m / 8][(m % 8) / 2];
-    float r;
-    if (m % 2 == 0)
-      asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(sc), "v"(-0.0f));
-    else
-      asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(sc), "v"(-0.0f));
-    return r;
+    return m % 2 == 0 ? half_times<0>(w, sc) : half_times<1>(w, sc);
   }
 };
 
