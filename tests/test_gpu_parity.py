@@ -265,6 +265,22 @@ def test_error_paths():
     assert e.value.status == smg.SMG_EBREAKDOWN
 
 
+def test_singular_coarsest():
+    """A one-level system whose dense operator is [[1, 1], [1, 1]] (1x1x2
+    grid, unit diagonal and z couplings): the coarsest inverse meets an exact
+    zero pivot and the setup reports a breakdown."""
+    shape = (1, 1, 2)
+    off = [tuple(int(v) for v in o) for o in workloads.offsets(7)]
+    A = np.zeros((7, 2))
+    A[off.index((0, 0, 0))] = 1.0
+    A[off.index((0, 0, 1)), 0] = 1.0
+    A[off.index((0, 0, -1)), 1] = 1.0
+    assert np.array_equal(oracle.dense(workloads.offsets(7), A, shape), np.ones((2, 2)))
+    with pytest.raises(smg.SmgError) as e:
+        smg.StructMG(T(A), shape, pattern=7, device=DEV)
+    assert e.value.status == smg.SMG_EBREAKDOWN
+
+
 # ---------------------------------------------------------------- 3x3 blocks
 BCASES = [(12, 10, 9), (17, 16, 8)]
 OFF27 = workloads.offsets(27)
