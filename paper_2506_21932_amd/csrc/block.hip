@@ -21,6 +21,7 @@
 // in the oracle's order, the three sums meet in LDS, and each wavefront
 // applies its row of the inverse diagonal block.
 #include "smg_common.h"
+#include "smg_group.h"
 #include "smg_kernels.h"
 
 namespace smg {
@@ -445,7 +446,9 @@ template <class E>
 __global__ __launch_bounds__(256) void k_bwf_pack(Grid g, WfTiling tl, int dir, const double* __restrict__ A,
                                                   const double* __restrict__ Dinv, E* __restrict__ out) {
   constexpr int K = 16 / (int)sizeof(E), NPR = bwf_npr(sizeof(E));
-  const long q = (long)blockIdx.x * 256 + threadIdx.x;
+  // consecutive steps of a tile read the same column lines: keep them on one
+  // XCD's L2 (contiguous block ranges per XCD)
+  const long q = (long)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   if (q >= tl.nsk) return;
   const long i = bwf_point(g, tl, q);
   const long N = g.N();
@@ -473,7 +476,9 @@ __global__ __launch_bounds__(256) void k_bwf_pack_h(Grid g, WfTiling tl, int dir
                                                     const float* __restrict__ sc, const float* __restrict__ rd,
                                                     unsigned char* __restrict__ out) {
   constexpr int NPR = bwf_npr(2);
-  const long q = (long)blockIdx.x * 256 + threadIdx.x;
+  // consecutive steps of a tile read the same column lines: keep them on one
+  // XCD's L2 (contiguous block ranges per XCD)
+  const long q = (long)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   if (q >= tl.nsk) return;
   const long i = bwf_point(g, tl, q);
   const long N = g.N();

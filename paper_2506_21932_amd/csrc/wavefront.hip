@@ -68,6 +68,7 @@
 //    point use an offset outside the buffer, for which loads return zero
 //    and stores are dropped.
 #include "smg_common.h"
+#include "smg_group.h"
 #include "smg_kernels.h"
 
 namespace smg {
@@ -903,7 +904,9 @@ __global__ __launch_bounds__(256) void k_wf_pack(Grid g, WfTiling tl, int dir, c
                                                  const double* __restrict__ dg, const double* __restrict__ up,
                                                  E* __restrict__ out) {
   constexpr int C = PAT / 2, NT = PAT / 2, K = 16 / (int)sizeof(E), NPK = wf_npk(PAT, sizeof(E));
-  const long q = (long)blockIdx.x * 256 + threadIdx.x;
+  // consecutive steps of a tile read the same column lines: keep them on one
+  // XCD's L2 (contiguous block ranges per XCD)
+  const long q = (long)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   if (q >= tl.nsk) return;
   const long i = wf_point(g, tl, PAT, q);
   const long N = g.N();
@@ -936,7 +939,9 @@ __global__ __launch_bounds__(256) void k_wf_pack_h(Grid g, WfTiling tl, int dir,
                                                    const float* __restrict__ sc, const float* __restrict__ rd,
                                                    __half* __restrict__ out, float* __restrict__ sd) {
   constexpr int C = PAT / 2, NT = PAT / 2, K = 8, NPK = wf_npk(PAT, 2);
-  const long q = (long)blockIdx.x * 256 + threadIdx.x;
+  // consecutive steps of a tile read the same column lines: keep them on one
+  // XCD's L2 (contiguous block ranges per XCD)
+  const long q = (long)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   if (q >= tl.nsk) return;
   const long i = wf_point(g, tl, PAT, q);
   const long N = g.N();
