@@ -96,7 +96,9 @@ def emit_kernel(npts, cmask):
     L.append("                                                double* __restrict__ Ac, long sAc) {")
     L.append(f"  const Grid gc{{{'gf.nx / 2' if cm[0] else 'gf.nx'}, {'gf.ny / 2' if cm[1] else 'gf.ny'}, "
              f"{'gf.nz / 2' if cm[2] else 'gf.nz'}}};")
-    L.append("  const unsigned k = blockIdx.x * 256u + threadIdx.x;")
+    L.append("  // contiguous coarse lines per XCD: neighbouring lines share most of")
+    L.append("  // their fine neighbourhood, which then stays in one L2")
+    L.append("  const unsigned k = xcd_block(blockIdx.x, gridDim.x) * 256u + threadIdx.x;")
     L.append("  if (k >= (unsigned)gc.N()) return;")
     L.append("  const unsigned nyz = (unsigned)gc.ny * (unsigned)gc.nz;")
     L.append("  const int X = (int)(k / nyz), Y = (int)((k / (unsigned)gc.nz) % (unsigned)gc.ny), "

@@ -3,6 +3,7 @@
 // from the enumerated influence chains.  R = P^T with vertex-centred
 // trilinear interpolation; coarse operators are 27-point.  Block systems run
 // the same kernel once per block entry (P and R act on each unknown alike).
+#include "smg_group.h"
 #include "smg_kernels.h"
 
 namespace smg {
