@@ -4,6 +4,7 @@
 // truncation of FP64 level data to FP32 or FP16 with a per-row FP32 scale.
 #include <utility>
 
+#include "smg_group.h"
 #include "smg_kernels.h"
 
 namespace smg {
@@ -361,7 +362,9 @@ __global__ __launch_bounds__(ILU_WG) __attribute__((amdgpu_waves_per_eu(1, 1))) 
   const long N = g.N();
   const int kb = ilu_band(g.nz, WY);
   int X, Y, Z;
-  if (!ilu_point<WX, WY>(g, tau, x0, nxr, kb, (int)(blockIdx.x * (unsigned)ILU_WG + threadIdx.x), X, Y, Z)) return;
+  // neighbouring band slots read overlapping U lines: keep them on one XCD
+  const unsigned slot = xcd_block(blockIdx.x, gridDim.x) * (unsigned)ILU_WG + threadIdx.x;
+  if (!ilu_point<WX, WY>(g, tau, x0, nxr, kb, (int)slot, X, Y, Z)) return;
   const long i = ((long)X * g.ny + Y) * g.nz + Z;
   const IluNb nb{X > 0, X < g.nx - 1, Y > 0, Y < g.ny - 1, Z > 0, Z < g.nz - 1};
   const double* zero = U + (long)PAT * N;  // U[PAT*N] = 0, U[PAT*N+1] = 1
