@@ -126,6 +126,11 @@ __host__ __device__ constexpr int wf_kb(int pat) {
 __host__ __device__ constexpr int wf_npk(int pat, int ebytes) {
   return (pat / 2 + (ebytes == 2 ? 0 : 1) + 16 / ebytes - 1) / (16 / ebytes);
 }
+// FP16 storage: do the position's FP32 {row scale, diagonal scaling} fit in
+// the last two words of its packs (after the pattern's lower halves)?  Then a
+// step loads them with the coefficients (7- and 19-point: one load per step
+// instead of two); otherwise (27-point) they come from a separate array.
+__host__ __device__ constexpr bool wf_sd_in_pack(int pat) { return pat / 2 + 4 <= 8 * wf_npk(pat, 2); }
 
 void wf_tiling(const Grid& g, int pat, WfTiling* t, int shape) {
   // Default: tiles are sheared (y + x offset) when a lower neighbour column
@@ -378,7 +383,7 @@ __device__ __forceinline__ void wf_compute(const WfArgs<typename WfVal<E>::V>& a
 #pragma unroll
     for (int p = 0; p < NPK; ++p)
       cf[j][p] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rp, vo, so + p * PACKB, 0));
-    if (T::HALF)
+    if (T::HALF && !wf_sd_in_pack(PAT))
       sdv[j] = __builtin_amdgcn_raw_buffer_load_b64(rs, pt ? tid * 8u : WF_OOB,
                                                     sin ? (unsigned)s * (WF_NL * 8u) : WF_OOB, 0);
   };
@@ -392,7 +397,8 @@ __device__ __forceinline__ void wf_compute(const WfArgs<typename WfVal<E>::V>& a
 #pragma unroll
     for (int j = 0; j < WF_HIST; ++j) {
       const int jp = j % P;
-      const V sc = T::HALF ? __uint_as_float(sdv[jp].x) : V(1);
+      constexpr bool SDP = T::HALF && wf_sd_in_pack(PAT);
+      const V sc = T::HALF ? __uint_as_float(SDP ? cf[jp][NPK - 1][2] : sdv[jp].x) : V(1);
       V t = hb[j * WF_HRW];
       // all neighbour values first (one wait), then the chain of fmas in
       // canonical order of the triangle's offsets
@@ -418,7 +424,7 @@ __device__ __forceinline__ void wf_compute(const WfArgs<typename WfVal<E>::V>& a
           cm = T::get(cf[jp], m);
         t = fma(-cm, val[m], t);
       }
-      const V dv = T::HALF ? __uint_as_float(sdv[jp].y) : T::get(cf[jp], NT);
+      const V dv = T::HALF ? __uint_as_float(SDP ? cf[jp][NPK - 1][3] : sdv[jp].y) : T::get(cf[jp], NT);
       const V xv = UNITD ? t : t * dv;
       own_prev = xv;
       ring[j * WF_RW + tid] = xv;
@@ -958,15 +964,23 @@ __global__ __launch_bounds__(256) void k_wf_pack_h(Grid g, WfTiling tl, int dir,
     v[m] = i >= 0 ? x : __float2half_rn(0.0f);
   }
   const float s0 = sc[ic], s1 = rd[ic];
+  const unsigned b0 = i >= 0 ? __float_as_uint(s0) : 0u, b1 = i >= 0 ? __float_as_uint(s1) : 0u;
+  if constexpr (wf_sd_in_pack(PAT)) {
+    // the scalars take the last two words: halves NPK*K-4 .. NPK*K-1
+    v[NPK * K - 4] = __ushort_as_half((unsigned short)(b0 & 0xffffu));
+    v[NPK * K - 3] = __ushort_as_half((unsigned short)(b0 >> 16));
+    v[NPK * K - 2] = __ushort_as_half((unsigned short)(b1 & 0xffffu));
+    v[NPK * K - 1] = __ushort_as_half((unsigned short)(b1 >> 16));
+  }
 #pragma unroll
   for (int p = 0; p < NPK; ++p) {
     __half* o = out + ((row * NPK + p) * WF_NL + lane) * K;
 #pragma unroll
     for (int e = 0; e < K; ++e) o[e] = v[p * K + e];
   }
-  if (dir > 0) {
-    sd[2 * q] = i >= 0 ? s0 : 0.0f;
-    sd[2 * q + 1] = i >= 0 ? s1 : 0.0f;
+  if (!wf_sd_in_pack(PAT) && dir > 0) {
+    sd[2 * q] = __uint_as_float(b0);
+    sd[2 * q + 1] = __uint_as_float(b1);
   }
 }
 
